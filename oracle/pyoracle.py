@@ -1,0 +1,253 @@
+"""ctypes marshalling for the FP64 oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3}
+_JNT = {"free": 0, "hinge": 1}
+_ACT = {"position": 0, "motor": 1}
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+
+
+class _Desc(C.Structure):
+    _fields_ = [("nbody", C.c_int32), ("njnt", C.c_int32), ("ngeom", C.c_int32), ("nu", C.c_int32),
+                ("body_parent", _i32p),
+                ("body_pos", _f64p), ("body_quat", _f64p), ("body_ipos", _f64p), ("body_iquat", _f64p),
+                ("body_mass", _f64p), ("body_inertia", _f64p),
+                ("jnt_type", _i32p), ("jnt_body", _i32p),
+                ("jnt_pos", _f64p), ("jnt_axis", _f64p), ("jnt_armature", _f64p),
+                ("geom_type", _i32p), ("geom_body", _i32p), ("geom_contype", _i32p), ("geom_conaffinity", _i32p),
+                ("geom_pos", _f64p), ("geom_quat", _f64p), ("geom_size", _f64p), ("geom_friction", _f64p),
+                ("geom_margin", _f64p),
+                ("act_type", _i32p), ("act_joint", _i32p),
+                ("act_kp", _f64p), ("act_kd", _f64p), ("act_gear", _f64p),
+                ("timestep", C.c_double), ("nsubsteps", C.c_int32), ("gravity", C.c_double * 3),
+                ("iterations", C.c_int32), ("tolerance", C.c_double), ("solref", C.c_double * 2),
+                ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("nq", C.c_int32), ("nv", C.c_int32), ("nu", C.c_int32), ("nbody", C.c_int32),
+                ("ngeom", C.c_int32), ("maxcon", C.c_int32), ("maxrows", C.c_int32), ("npair", C.c_int32),
+                ("meaninertia", C.c_double)]
+
+
+class _Contacts(C.Structure):
+    _fields_ = [("ncon", _i32p), ("geom", _i32p), ("feature", _i32p), ("dist", _f64p), ("pos", _f64p),
+                ("frame", _f64p), ("force", _f64p)]
+
+
+_TAP_FIELDS = [("xpos", "f", "nb3"), ("xquat", "f", "nb4"), ("xmat", "f", "nb9"), ("com", "f", "nb3"),
+               ("gpos", "f", "ng3"), ("gmat", "f", "ng9"),
+               ("M", "f", "nvnv"), ("bias", "f", "nv"), ("tau", "f", "nv"), ("a0", "f", "nv"),
+               ("ncon", "i", "1"), ("geom", "i", "mc2"), ("feature", "i", "mc"),
+               ("dist", "f", "mc"), ("pos", "f", "mc3"), ("frame", "f", "mc9"), ("mu", "f", "mc"),
+               ("J", "f", "mrnv"), ("aref", "f", "mr"), ("D", "f", "mr"), ("Ahat", "f", "mr"),
+               ("efc_force", "f", "mr"), ("qacc", "f", "nv"), ("cforce", "f", "mc3"),
+               ("niter", "i", "1"), ("cost", "f", "1")]
+
+
+class _Taps(C.Structure):
+    _fields_ = [(n, _f64p if t == "f" else _i32p) for n, t, _ in _TAP_FIELDS]
+
+
+_lib = None
+
+
+def build_if_missing() -> None:
+    if not os.path.exists(_build.LIB):
+        _build.build()
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build_if_missing()
+        L = C.CDLL(_build.LIB)
+        L.rbo_last_error.restype = C.c_char_p
+        L.rbo_model_create.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_void_p)]
+        L.rbo_model_destroy.argtypes = [C.c_void_p]
+        L.rbo_model_info.argtypes = [C.c_void_p, C.POINTER(_Info)]
+        L.rbo_set_mode.argtypes = [C.c_void_p, C.c_int32]
+        L.rbo_forward.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, C.POINTER(_Taps)]
+        L.rbo_step.argtypes = [C.c_void_p, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                               C.POINTER(C.c_uint32), C.POINTER(_Contacts), C.c_int32]
+        L.rbo_energy.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p]
+        L.rbo_jacobian.argtypes = [C.c_void_p, _f64p, C.c_int32, _f64p, _f64p, _f64p]
+        L.rbo_integrate.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p]
+        _lib = L
+    return _lib
+
+
+def _f(a):
+    return None if a is None else a.ctypes.data_as(_f64p)
+
+
+def _d(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    return a if n is None else a.reshape(n)
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError("oracle: " + lib().rbo_last_error().decode())
+
+
+class Oracle:
+    """FP64 reference for one model description (see ``workloads.robots``)."""
+
+    def __init__(self, model: dict):
+        L = lib()
+        B, Jt, G, A = model["bodies"], model["joints"], model["geoms"], model["actuators"]
+        keep = []
+
+        def i32(x):
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(-1))
+            keep.append(a)
+            return a.ctypes.data_as(_i32p)
+
+        def f64(x):
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+            keep.append(a)
+            return a.ctypes.data_as(_f64p)
+
+        d = _Desc()
+        d.nbody, d.njnt, d.ngeom, d.nu = len(B), len(Jt), len(G), len(A)
+        d.body_parent = i32([b["parent"] for b in B])
+        d.body_pos = f64([b["pos"] for b in B]); d.body_quat = f64([b["quat"] for b in B])
+        d.body_ipos = f64([b["ipos"] for b in B]); d.body_iquat = f64([b["iquat"] for b in B])
+        d.body_mass = f64([b["mass"] for b in B]); d.body_inertia = f64([b["inertia"] for b in B])
+        d.jnt_type = i32([_JNT[j["type"]] for j in Jt] or [0]); d.jnt_body = i32([j["body"] for j in Jt] or [0])
+        d.jnt_pos = f64([j["pos"] for j in Jt] or [0.0]); d.jnt_axis = f64([j["axis"] for j in Jt] or [0.0])
+        d.jnt_armature = f64([j["armature"] for j in Jt] or [0.0])
+        d.geom_type = i32([_GEOM[g["type"]] for g in G] or [0]); d.geom_body = i32([g["body"] for g in G] or [0])
+        d.geom_contype = i32([g["contype"] for g in G] or [0])
+        d.geom_conaffinity = i32([g["conaffinity"] for g in G] or [0])
+        d.geom_pos = f64([g["pos"] for g in G] or [0.0]); d.geom_quat = f64([g["quat"] for g in G] or [0.0])
+        d.geom_size = f64([g["size"] for g in G] or [0.0]); d.geom_friction = f64([g["friction"] for g in G] or [0.0])
+        d.geom_margin = f64([g["margin"] for g in G] or [0.0])
+        d.act_type = i32([_ACT[a["type"]] for a in A] or [0]); d.act_joint = i32([a["joint"] for a in A] or [0])
+        d.act_kp = f64([a["kp"] for a in A] or [0.0]); d.act_kd = f64([a["kd"] for a in A] or [0.0])
+        d.act_gear = f64([a["gear"] for a in A] or [0.0])
+        o = model["opt"]
+        d.timestep = o["timestep"]; d.nsubsteps = o["nsubsteps"]
+        d.gravity = (C.c_double * 3)(*o["gravity"])
+        d.iterations = o["iterations"]; d.tolerance = o["tolerance"]
+        d.solref = (C.c_double * 2)(*o["solref"]); d.solimp = (C.c_double * 5)(*o["solimp"])
+        d.friction_per_world = int(bool(model["per_world"].get("friction")))
+        d.mass_scale_per_world = int(bool(model["per_world"].get("mass_scale")))
+        h = C.c_void_p()
+        _check(L.rbo_model_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.model = model
+        info = _Info()
+        _check(L.rbo_model_info(h, C.byref(info)))
+        self.nq, self.nv, self.nu, self.nbody = info.nq, info.nv, info.nu, info.nbody
+        self.ngeom, self.maxcon, self.maxrows, self.npair = info.ngeom, info.maxcon, info.maxrows, info.npair
+        self.meaninertia = info.meaninertia
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().rbo_model_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def set_mode(self, mode: str) -> None:
+        _check(lib().rbo_set_mode(self._h, {"mirror": 0, "converged": 1}[mode]))
+
+    # ------------------------------------------------------------------------------
+    def forward(self, qpos, qvel, ctrl=None, qacc_ws=None, friction=None, mass_scale=None) -> dict:
+        """Stage taps of one substep (no integration) for one world."""
+        nv, nb, ng, mc, mr = self.nv, self.nbody, self.ngeom, self.maxcon, self.maxrows
+        sizes = {"nb3": nb * 3, "nb4": nb * 4, "nb9": nb * 9, "ng3": ng * 3, "ng9": ng * 9, "nvnv": nv * nv,
+                 "nv": nv, "1": 1, "mc": mc, "mc2": mc * 2, "mc3": mc * 3, "mc9": mc * 9, "mr": mr,
+                 "mrnv": mr * nv}
+        bufs, taps = {}, _Taps()
+        for n, t, s in _TAP_FIELDS:
+            a = np.zeros(max(1, sizes[s]), np.float64 if t == "f" else np.int32)
+            bufs[n] = a
+            setattr(taps, n, a.ctypes.data_as(_f64p if t == "f" else _i32p))
+        q, v = _d(qpos, self.nq), _d(qvel, nv)
+        u = _d(ctrl if ctrl is not None else np.zeros(self.nu), self.nu) if self.nu else None
+        ws = _d(qacc_ws, nv) if qacc_ws is not None else None
+        fr = _d([friction]) if friction is not None else None
+        ms = _d(mass_scale, nb) if mass_scale is not None else None
+        _check(lib().rbo_forward(self._h, _f(q), _f(v), _f(u), _f(ws), _f(fr), _f(ms), C.byref(taps)))
+        nc = int(bufs["ncon"][0])
+        nr = 4 * nc
+        out = dict(xpos=bufs["xpos"].reshape(nb, 3), xquat=bufs["xquat"].reshape(nb, 4),
+                   xmat=bufs["xmat"].reshape(nb, 3, 3), com=bufs["com"].reshape(nb, 3),
+                   gpos=bufs["gpos"][:ng * 3].reshape(ng, 3), gmat=bufs["gmat"][:ng * 9].reshape(ng, 3, 3),
+                   M=bufs["M"][:nv * nv].reshape(nv, nv), bias=bufs["bias"][:nv], tau=bufs["tau"][:nv],
+                   a0=bufs["a0"][:nv], ncon=nc, geom=bufs["geom"][:2 * nc].reshape(nc, 2),
+                   feature=bufs["feature"][:nc], dist=bufs["dist"][:nc], pos=bufs["pos"][:3 * nc].reshape(nc, 3),
+                   frame=bufs["frame"][:9 * nc].reshape(nc, 3, 3), mu=bufs["mu"][:nc],
+                   J=bufs["J"][:nr * nv].reshape(nr, nv), aref=bufs["aref"][:nr], D=bufs["D"][:nr],
+                   Ahat=bufs["Ahat"][:nr], efc_force=bufs["efc_force"][:nr], qacc=bufs["qacc"][:nv],
+                   cforce=bufs["cforce"][:3 * nc].reshape(nc, 3), niter=int(bufs["niter"][0]),
+                   cost=float(bufs["cost"][0]))
+        return out
+
+    def step(self, ctrl, qpos, qvel, qacc_ws, friction=None, mass_scale=None, status=None, contacts=False,
+             nthreads=0):
+        """One env step (K substeps) for n worlds, in place on float64 arrays; returns (status, contacts)."""
+        n = qpos.shape[0]
+        for a in (qpos, qvel, qacc_ws):
+            assert a.dtype == np.float64 and a.flags.c_contiguous
+        u = _d(ctrl, (n, self.nu)) if self.nu else None
+        fr = _d(friction, n) if friction is not None else None
+        ms = _d(mass_scale, (n, self.nbody)) if mass_scale is not None else None
+        st = np.zeros(n, np.uint32) if status is None else status
+        cs = None
+        out = None
+        if contacts:
+            mc = max(1, self.maxcon)
+            out = dict(ncon=np.zeros(n, np.int32), geom=np.zeros((n, mc, 2), np.int32),
+                       feature=np.zeros((n, mc), np.int32), dist=np.zeros((n, mc)), pos=np.zeros((n, mc, 3)),
+                       frame=np.zeros((n, mc, 3, 3)), force=np.zeros((n, mc, 3)))
+            cs = _Contacts()
+            for k, v in out.items():
+                setattr(cs, k, v.ctypes.data_as(_i32p if v.dtype == np.int32 else _f64p))
+        _check(lib().rbo_step(self._h, n, _f(u), _f(qpos), _f(qvel), _f(qacc_ws), _f(fr), _f(ms),
+                              st.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(cs) if cs is not None else None,
+                              int(nthreads)))
+        return st, out
+
+    def energy(self, qpos, qvel, mass_scale=None):
+        T, V = C.c_double(), C.c_double()
+        ms = _d(mass_scale, self.nbody) if mass_scale is not None else None
+        _check(lib().rbo_energy(self._h, _f(_d(qpos, self.nq)), _f(_d(qvel, self.nv)), _f(ms), C.byref(T),
+                                C.byref(V)))
+        return T.value, V.value
+
+    def jacobian(self, qpos, body, point):
+        jp = np.zeros((3, self.nv)); jr = np.zeros((3, self.nv))
+        _check(lib().rbo_jacobian(self._h, _f(_d(qpos, self.nq)), int(body), _f(_d(point, 3)), _f(jp), _f(jr)))
+        return jp, jr
+
+    def integrate(self, qpos, qvel, qacc):
+        qo = np.zeros(self.nq); vo = np.zeros(self.nv)
+        _check(lib().rbo_integrate(self._h, _f(_d(qpos, self.nq)), _f(_d(qvel, self.nv)), _f(_d(qacc, self.nv)),
+                                   _f(qo), _f(vo)))
+        return qo, vo
+
+    def rollout(self, qpos, qvel, ctrl=None, nsteps=1, qacc_ws=None, friction=None, mass_scale=None, nthreads=0):
+        """Run ``nsteps`` env steps from float arrays [n, ...]; returns (qpos, qvel, qacc_ws, status) float64."""
+        q = np.array(qpos, np.float64, order="C", ndmin=2)
+        v = np.array(qvel, np.float64, order="C", ndmin=2)
+        n = q.shape[0]
+        ws = np.zeros((n, self.nv)) if qacc_ws is None else np.array(qacc_ws, np.float64, order="C", ndmin=2)
+        st = np.zeros(n, np.uint32)
+        u = np.zeros((n, self.nu)) if ctrl is None else ctrl
+        for _ in range(nsteps):
+            self.step(u, q, v, ws, friction, mass_scale, st, nthreads=nthreads)
+        return q, v, ws, st

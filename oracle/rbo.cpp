@@ -1,0 +1,1029 @@
+/*
+ * FP64 CPU oracle for the batched rigid-body step -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously-correct definitions of what one physics substep computes.  The
+ * paper specifies the physics only by its interface (section "Architecture": static model,
+ * time-varying per-world state with a leading world dimension, per-world field expansion;
+ * section "Manager-Based API", pipeline step "Simulate": d physics substeps per env step
+ * with controls held).  The contents of a substep follow MuJoCo's published formulation,
+ * written from the mathematics:
+ *   - forward kinematics of a tree of bodies with free and hinge joints;
+ *   - joint-space inertia M as the sum over bodies of m Jp'Jp + Jr' I Jr (definition of
+ *     kinetic energy), plus joint armature;
+ *   - bias forces c(q, v) (Coriolis, centrifugal, gravity) as the Jacobian-transpose sum of
+ *     each body's Newton-Euler bias wrench (Featherstone 2008, ch. 5, with gravity applied
+ *     as a base acceleration);
+ *   - brute-force primitive collision against planes;
+ *   - soft contact constraints with a pyramidal friction cone, impedance and reference
+ *     acceleration (Todorov 2014; MuJoCo "Computation" chapter);
+ *   - the primal Newton method with exact line search on the convex constraint cost;
+ *   - semi-implicit Euler integration with exponential-map quaternion update.
+ * Every stage uses dense matrices and Cholesky factorisations; nothing is blocked, fused
+ * or reordered beyond these definitions.
+ */
+#include "rbo.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+thread_local std::string g_err;
+int fail(const std::string& s) {
+    g_err = s;
+    return -1;
+}
+
+// ------------------------------------------------------------------------------------
+// small 3-D helpers (row-major 3x3 matrices, quaternions (w, x, y, z), Hamilton product)
+// ------------------------------------------------------------------------------------
+inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+inline void cross3(const double* a, const double* b, double* o) {
+    double t[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    o[0] = t[0]; o[1] = t[1]; o[2] = t[2];
+}
+inline void matvec3(const double* R, const double* v, double* o) {
+    double t[3];
+    for (int i = 0; i < 3; i++) t[i] = R[3 * i] * v[0] + R[3 * i + 1] * v[1] + R[3 * i + 2] * v[2];
+    o[0] = t[0]; o[1] = t[1]; o[2] = t[2];
+}
+inline void matmul3(const double* A, const double* B, double* O) {
+    double t[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) t[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+    std::memcpy(O, t, sizeof t);
+}
+inline void quatmul(const double* a, const double* b, double* o) {
+    double t[4] = {a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3],
+                   a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2],
+                   a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1],
+                   a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0]};
+    o[0] = t[0]; o[1] = t[1]; o[2] = t[2]; o[3] = t[3];
+}
+inline void quatnormalize(double* q) {
+    double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int i = 0; i < 4; i++) q[i] /= n;
+}
+inline void quat2mat(const double* q, double* R) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+inline void axisangle2quat(const double* u, double theta, double* q) {
+    double s = std::sin(theta / 2);
+    q[0] = std::cos(theta / 2); q[1] = s * u[0]; q[2] = s * u[1]; q[3] = s * u[2];
+}
+
+// ------------------------------------------------------------------------------------
+// model and per-world data
+// ------------------------------------------------------------------------------------
+struct Model {
+    int nbody = 0, njnt = 0, ngeom = 0, nu = 0, nq = 0, nv = 0;
+    std::vector<int> parent, body_jnt;
+    std::vector<double> bpos, bquat, ipos, iquat, mass, inertia;
+    std::vector<int> jtype, jbody, jqadr, jdadr;
+    std::vector<double> jpos, jaxis, jarm;
+    std::vector<int> gtype, gbody, gcontype, gconaff;
+    std::vector<double> gpos, gquat, gsize, gfric, gmargin;
+    std::vector<int> atype, ajoint;
+    std::vector<double> akp, akd, agear;
+    std::vector<int> movable;  // body has a joint on its path to the world
+    double dt = 0.005;
+    int K = 1;
+    double grav[3] = {0, 0, -9.81};
+    int iters = 4;
+    double tol = 1e-8;
+    double solref[2] = {0.02, 1.0};
+    double solimp[5] = {0.9, 0.95, 0.001, 0.5, 2.0};
+    bool fr_pw = false, ms_pw = false;
+    int maxcon = 0, npair = 0;
+    double meaninertia = 1.0;
+    int mode = 0;
+};
+
+struct Contact {
+    int g1, g2, feature, b1, b2;
+    double dist, pos[3], frame[9], mu;
+};
+
+struct Data {
+    const Model* m;
+    std::vector<double> q, v, ctrl, aws;
+    double fr = 1.0;
+    std::vector<double> ms;  // mass scale per body
+    // kinematics
+    std::vector<double> xpos, xquat, xmat, com, Iw, mb, janchor, jaxw, gx, gR;
+    // dynamics
+    std::vector<double> M, c, tau, a0;
+    // constraints
+    std::vector<Contact> con;
+    int nrows = 0;
+    std::vector<double> J, aref, D, Ahat, efc_force, a, cforce;
+    int niter = 0;
+    double cost = 0;
+
+    explicit Data(const Model* mm) : m(mm) {
+        int nb = m->nbody, nv = m->nv, nj = m->njnt, ng = m->ngeom;
+        q.assign(m->nq, 0); v.assign(nv, 0); ctrl.assign(m->nu, 0); aws.assign(nv, 0);
+        ms.assign(nb, 1.0);
+        xpos.assign(3 * nb, 0); xquat.assign(4 * nb, 0); xmat.assign(9 * nb, 0); com.assign(3 * nb, 0);
+        Iw.assign(9 * nb, 0); mb.assign(nb, 0);
+        janchor.assign(3 * nj, 0); jaxw.assign(3 * nj, 0);
+        gx.assign(3 * ng, 0); gR.assign(9 * ng, 0);
+        M.assign(nv * nv, 0); c.assign(nv, 0); tau.assign(nv, 0); a0.assign(nv, 0); a.assign(nv, 0);
+    }
+};
+
+// ------------------------------------------------------------------------------------
+// forward kinematics: body frames, centres of mass, world inertias, joint axes, geom poses
+// ------------------------------------------------------------------------------------
+void kinematics(const Model& m, Data& d) {
+    for (int i = 0; i < 3; i++) d.xpos[i] = 0;
+    double qid[4] = {1, 0, 0, 0};
+    std::memcpy(&d.xquat[0], qid, sizeof qid);
+    quat2mat(qid, &d.xmat[0]);
+    for (int b = 1; b < m.nbody; b++) {
+        int p = m.parent[b];
+        double x0[3], q0[4], R0[9];
+        matvec3(&d.xmat[9 * p], &m.bpos[3 * b], x0);
+        for (int i = 0; i < 3; i++) x0[i] += d.xpos[3 * p + i];
+        quatmul(&d.xquat[4 * p], &m.bquat[4 * b], q0);
+        int j = m.body_jnt[b];
+        double* xb = &d.xpos[3 * b];
+        double* qb = &d.xquat[4 * b];
+        if (j < 0) {
+            std::memcpy(xb, x0, 3 * sizeof(double));
+            std::memcpy(qb, q0, 4 * sizeof(double));
+        } else if (m.jtype[j] == RBO_JNT_FREE) {
+            int a = m.jqadr[j];
+            for (int i = 0; i < 3; i++) xb[i] = d.q[a + i];
+            for (int i = 0; i < 4; i++) qb[i] = d.q[a + 3 + i];
+            quatnormalize(qb);
+            std::memcpy(&d.janchor[3 * j], xb, 3 * sizeof(double));
+        } else {
+            quat2mat(q0, R0);
+            double o[3], u[3], qr[4], Rb[9], off[3];
+            matvec3(R0, &m.jpos[3 * j], o);
+            for (int i = 0; i < 3; i++) o[i] += x0[i];
+            matvec3(R0, &m.jaxis[3 * j], u);
+            axisangle2quat(u, d.q[m.jqadr[j]], qr);
+            quatmul(qr, q0, qb);
+            quat2mat(qb, Rb);
+            matvec3(Rb, &m.jpos[3 * j], off);
+            for (int i = 0; i < 3; i++) xb[i] = o[i] - off[i];
+            std::memcpy(&d.janchor[3 * j], o, sizeof o);
+            std::memcpy(&d.jaxw[3 * j], u, sizeof u);
+        }
+        quat2mat(qb, &d.xmat[9 * b]);
+    }
+    // centres of mass, masses and world-frame rotational inertias about the COM
+    for (int b = 0; b < m.nbody; b++) {
+        const double* R = &d.xmat[9 * b];
+        double off[3];
+        matvec3(R, &m.ipos[3 * b], off);
+        for (int i = 0; i < 3; i++) d.com[3 * b + i] = d.xpos[3 * b + i] + off[i];
+        double s = d.ms[b];
+        d.mb[b] = s * m.mass[b];
+        double Ri[9], RR[9];
+        quat2mat(&m.iquat[4 * b], Ri);
+        matmul3(R, Ri, RR);
+        // I = RR diag(s*inertia) RR'
+        for (int i = 0; i < 3; i++)
+            for (int k = 0; k < 3; k++) {
+                double acc = 0;
+                for (int l = 0; l < 3; l++) acc += RR[3 * i + l] * s * m.inertia[3 * b + l] * RR[3 * k + l];
+                d.Iw[9 * b + 3 * i + k] = acc;
+            }
+    }
+    for (int g = 0; g < m.ngeom; g++) {
+        int b = m.gbody[g];
+        double off[3], Rg[9];
+        matvec3(&d.xmat[9 * b], &m.gpos[3 * g], off);
+        for (int i = 0; i < 3; i++) d.gx[3 * g + i] = d.xpos[3 * b + i] + off[i];
+        quat2mat(&m.gquat[4 * g], Rg);
+        matmul3(&d.xmat[9 * b], Rg, &d.gR[9 * g]);
+    }
+}
+
+// Point Jacobians of world point p attached to body b: jacp, jacr are [3, nv] row-major.
+void jacobian(const Model& m, const Data& d, int b, const double* p, double* jacp, double* jacr) {
+    int nv = m.nv;
+    std::fill(jacp, jacp + 3 * nv, 0.0);
+    std::fill(jacr, jacr + 3 * nv, 0.0);
+    for (int bb = b; bb > 0; bb = m.parent[bb]) {
+        int j = m.body_jnt[bb];
+        if (j < 0) continue;
+        int k = m.jdadr[j];
+        if (m.jtype[j] == RBO_JNT_HINGE) {
+            const double* u = &d.jaxw[3 * j];
+            double r[3], w[3];
+            for (int i = 0; i < 3; i++) r[i] = p[i] - d.janchor[3 * j + i];
+            cross3(u, r, w);
+            for (int i = 0; i < 3; i++) {
+                jacr[i * nv + k] = u[i];
+                jacp[i * nv + k] = w[i];
+            }
+        } else {
+            const double* R = &d.xmat[9 * bb];
+            double r[3];
+            for (int i = 0; i < 3; i++) r[i] = p[i] - d.xpos[3 * bb + i];
+            for (int a = 0; a < 3; a++) {
+                jacp[a * nv + k + a] = 1.0;
+                double e[3] = {R[a], R[3 + a], R[6 + a]};  // body axis a in world
+                double w[3];
+                cross3(e, r, w);
+                for (int i = 0; i < 3; i++) {
+                    jacr[i * nv + k + 3 + a] = e[i];
+                    jacp[i * nv + k + 3 + a] = w[i];
+                }
+            }
+        }
+    }
+}
+
+// M = sum_b m_b Jp(b, com_b)' Jp(b, com_b) + Jr(b)' I_b Jr(b) + diag(armature)
+void mass_matrix(const Model& m, Data& d) {
+    int nv = m.nv;
+    std::fill(d.M.begin(), d.M.end(), 0.0);
+    std::vector<double> jp(3 * nv), jr(3 * nv), IJ(3 * nv);
+    for (int b = 1; b < m.nbody; b++) {
+        jacobian(m, d, b, &d.com[3 * b], jp.data(), jr.data());
+        const double* I = &d.Iw[9 * b];
+        for (int i = 0; i < 3; i++)
+            for (int k = 0; k < nv; k++) IJ[i * nv + k] = I[3 * i] * jr[k] + I[3 * i + 1] * jr[nv + k] + I[3 * i + 2] * jr[2 * nv + k];
+        for (int r = 0; r < nv; r++)
+            for (int s = 0; s < nv; s++) {
+                double acc = 0;
+                for (int i = 0; i < 3; i++) acc += d.mb[b] * jp[i * nv + r] * jp[i * nv + s] + jr[i * nv + r] * IJ[i * nv + s];
+                d.M[r * nv + s] += acc;
+            }
+    }
+    for (int j = 0; j < m.njnt; j++)
+        if (m.jtype[j] == RBO_JNT_HINGE) d.M[m.jdadr[j] * (nv + 1)] += m.jarm[j];
+}
+
+// c(q, v): bias accelerations of every body with qacc = 0 and the world accelerating
+// upward at -gravity, turned into bias wrenches and projected with Jacobian transposes.
+void bias_forces(const Model& m, Data& d) {
+    int nv = m.nv, nb = m.nbody;
+    std::vector<double> w(3 * nb, 0.0), al(3 * nb, 0.0), ac(3 * nb, 0.0);
+    for (int i = 0; i < 3; i++) ac[i] = -m.grav[i];
+    std::fill(d.c.begin(), d.c.end(), 0.0);
+    std::vector<double> jp(3 * nv), jr(3 * nv);
+    for (int b = 1; b < nb; b++) {
+        int p = m.parent[b], j = m.body_jnt[b];
+        double* wb = &w[3 * b];
+        double* ab = &al[3 * b];
+        double* acb = &ac[3 * b];
+        const double* cb = &d.com[3 * b];
+        const double* cp = &d.com[3 * p];
+        if (j >= 0 && m.jtype[j] == RBO_JNT_FREE) {
+            double wl[3] = {d.v[m.jdadr[j] + 3], d.v[m.jdadr[j] + 4], d.v[m.jdadr[j] + 5]};
+            matvec3(&d.xmat[9 * b], wl, wb);
+            ab[0] = ab[1] = ab[2] = 0;
+            double r[3], t[3], t2[3];
+            for (int i = 0; i < 3; i++) r[i] = cb[i] - d.xpos[3 * b + i];
+            cross3(wb, r, t);
+            cross3(wb, t, t2);
+            for (int i = 0; i < 3; i++) acb[i] = -m.grav[i] + t2[i];
+        } else {
+            const double* wp = &w[3 * p];
+            const double* ap = &al[3 * p];
+            // the point o about which the body moves relative to its parent
+            double o[3];
+            double qd = 0, u[3] = {0, 0, 0};
+            if (j >= 0) {
+                std::memcpy(o, &d.janchor[3 * j], sizeof o);
+                std::memcpy(u, &d.jaxw[3 * j], sizeof u);
+                qd = d.v[m.jdadr[j]];
+            } else {
+                std::memcpy(o, cb, sizeof o);
+            }
+            double uq[3] = {u[0] * qd, u[1] * qd, u[2] * qd}, t[3];
+            for (int i = 0; i < 3; i++) wb[i] = wp[i] + uq[i];
+            cross3(wp, uq, t);
+            for (int i = 0; i < 3; i++) ab[i] = ap[i] + t[i];
+            // acceleration of o as a point of the parent
+            double r[3], t1[3], t2[3], t3[3], ao[3];
+            for (int i = 0; i < 3; i++) r[i] = o[i] - cp[i];
+            cross3(ap, r, t1);
+            cross3(wp, r, t2);
+            cross3(wp, t2, t3);
+            for (int i = 0; i < 3; i++) ao[i] = ac[3 * p + i] + t1[i] + t3[i];
+            // acceleration of this body's COM
+            for (int i = 0; i < 3; i++) r[i] = cb[i] - o[i];
+            cross3(ab, r, t1);
+            cross3(wb, r, t2);
+            cross3(wb, t2, t3);
+            for (int i = 0; i < 3; i++) acb[i] = ao[i] + t1[i] + t3[i];
+        }
+        // bias wrench of the body and its projection
+        double f[3], n[3], Iw[3], Ia[3], wIw[3];
+        for (int i = 0; i < 3; i++) f[i] = d.mb[b] * acb[i];
+        matvec3(&d.Iw[9 * b], wb, Iw);
+        matvec3(&d.Iw[9 * b], ab, Ia);
+        cross3(wb, Iw, wIw);
+        for (int i = 0; i < 3; i++) n[i] = Ia[i] + wIw[i];
+        jacobian(m, d, b, cb, jp.data(), jr.data());
+        for (int k = 0; k < nv; k++)
+            for (int i = 0; i < 3; i++) d.c[k] += jp[i * nv + k] * f[i] + jr[i * nv + k] * n[i];
+    }
+}
+
+void actuation(const Model& m, Data& d) {
+    std::fill(d.tau.begin(), d.tau.end(), 0.0);
+    for (int u = 0; u < m.nu; u++) {
+        int j = m.ajoint[u];
+        int k = m.jdadr[j], a = m.jqadr[j];
+        if (m.atype[u] == RBO_ACT_POSITION)
+            d.tau[k] += m.akp[u] * (d.ctrl[u] - d.q[a]) - m.akd[u] * d.v[k];
+        else
+            d.tau[k] += m.agear[u] * d.ctrl[u];
+    }
+}
+
+// dense Cholesky A = L L' (lower); returns false if not positive definite
+bool cholesky(const std::vector<double>& A, int n, std::vector<double>& L) {
+    L.assign(n * n, 0.0);
+    for (int j = 0; j < n; j++) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; k++) s -= L[j * n + k] * L[j * n + k];
+        if (!(s > 0)) return false;
+        L[j * n + j] = std::sqrt(s);
+        for (int i = j + 1; i < n; i++) {
+            double t = A[i * n + j];
+            for (int k = 0; k < j; k++) t -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = t / L[j * n + j];
+        }
+    }
+    return true;
+}
+void chol_solve(const std::vector<double>& L, int n, const double* b, double* x) {
+    std::vector<double> y(n);
+    for (int i = 0; i < n; i++) {
+        double s = b[i];
+        for (int k = 0; k < i; k++) s -= L[i * n + k] * y[k];
+        y[i] = s / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; i--) {
+        double s = y[i];
+        for (int k = i + 1; k < n; k++) s -= L[k * n + i] * x[k];
+        x[i] = s / L[i * n + i];
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// collision: brute force over geom pairs
+// ------------------------------------------------------------------------------------
+bool pair_allowed(const Model& m, int g1, int g2) {
+    int b1 = m.gbody[g1], b2 = m.gbody[g2];
+    if (b1 == b2) return false;
+    if ((m.parent[b1] == b2 && b2 != 0) || (m.parent[b2] == b1 && b1 != 0)) return false;
+    if (((m.gcontype[g1] & m.gconaff[g2]) | (m.gcontype[g2] & m.gconaff[g1])) == 0) return false;
+    if (!m.movable[b1] && !m.movable[b2]) return false;
+    return true;
+}
+
+int pair_capacity(int t1, int t2) {
+    if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_SPHERE) return 1;
+    if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_CAPSULE) return 2;
+    if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_BOX) return 8;
+    return -1;
+}
+
+// tangent frame: t1 = normalise(e_k - (e_k.n) n), k = argmin |n_k| (lowest on ties); t2 = n x t1
+void contact_frame(const double* n, double* frame) {
+    int k = 0;
+    for (int i = 1; i < 3; i++)
+        if (std::fabs(n[i]) < std::fabs(n[k])) k = i;
+    double t1[3] = {0, 0, 0};
+    t1[k] = 1.0;
+    double dn = t1[k] * n[k];
+    for (int i = 0; i < 3; i++) t1[i] -= dn * n[i];
+    double l = std::sqrt(dot3(t1, t1));
+    for (int i = 0; i < 3; i++) t1[i] /= l;
+    double t2[3];
+    cross3(n, t1, t2);
+    for (int i = 0; i < 3; i++) {
+        frame[i] = n[i];
+        frame[3 + i] = t1[i];
+        frame[6 + i] = t2[i];
+    }
+}
+
+void add_contact(const Model& m, Data& d, int g1, int g2, int feature, double dist, const double* pos,
+                 const double* n) {
+    Contact c;
+    c.g1 = g1; c.g2 = g2; c.feature = feature; c.dist = dist;
+    c.b1 = m.gbody[g1]; c.b2 = m.gbody[g2];
+    std::memcpy(c.pos, pos, 3 * sizeof(double));
+    contact_frame(n, c.frame);
+    c.mu = m.fr_pw ? d.fr : std::max(m.gfric[g1], m.gfric[g2]);
+    d.con.push_back(c);
+}
+
+void collide(const Model& m, Data& d) {
+    d.con.clear();
+    for (int ga = 0; ga < m.ngeom; ga++)
+        for (int gb = ga + 1; gb < m.ngeom; gb++) {
+            if (!pair_allowed(m, ga, gb)) continue;
+            int g1 = ga, g2 = gb;
+            if (m.gtype[g2] < m.gtype[g1]) std::swap(g1, g2);
+            int t1 = m.gtype[g1], t2 = m.gtype[g2];
+            double margin = std::max(m.gmargin[g1], m.gmargin[g2]);
+            if (t1 != RBO_GEOM_PLANE) continue;  // pairs without a plane were rejected at creation
+            const double* Rp = &d.gR[9 * g1];
+            double n[3] = {Rp[2], Rp[5], Rp[8]};  // plane normal = plane's local +z
+            const double* p0 = &d.gx[3 * g1];
+            const double* x = &d.gx[3 * g2];
+            const double* R = &d.gR[9 * g2];
+            const double* sz = &m.gsize[3 * g2];
+            if (t2 == RBO_GEOM_SPHERE) {
+                double r[3] = {x[0] - p0[0], x[1] - p0[1], x[2] - p0[2]};
+                double dist = dot3(n, r) - sz[0];
+                if (dist < margin) {
+                    double pos[3];
+                    for (int i = 0; i < 3; i++) pos[i] = x[i] - n[i] * (sz[0] + dist / 2);
+                    add_contact(m, d, g1, g2, 0, dist, pos, n);
+                }
+            } else if (t2 == RBO_GEOM_CAPSULE) {
+                for (int f = 0; f < 2; f++) {
+                    double sgn = f == 0 ? -1.0 : 1.0, e[3], r[3];
+                    for (int i = 0; i < 3; i++) e[i] = x[i] + sgn * sz[1] * R[3 * i + 2];
+                    for (int i = 0; i < 3; i++) r[i] = e[i] - p0[i];
+                    double dist = dot3(n, r) - sz[0];
+                    if (dist < margin) {
+                        double pos[3];
+                        for (int i = 0; i < 3; i++) pos[i] = e[i] - n[i] * (sz[0] + dist / 2);
+                        add_contact(m, d, g1, g2, f, dist, pos, n);
+                    }
+                }
+            } else if (t2 == RBO_GEOM_BOX) {
+                for (int k = 0; k < 8; k++) {
+                    double loc[3] = {(k & 4) ? sz[0] : -sz[0], (k & 2) ? sz[1] : -sz[1], (k & 1) ? sz[2] : -sz[2]};
+                    double vk[3], r[3];
+                    matvec3(R, loc, vk);
+                    for (int i = 0; i < 3; i++) vk[i] += x[i];
+                    for (int i = 0; i < 3; i++) r[i] = vk[i] - p0[i];
+                    double dist = dot3(n, r);
+                    if (dist < margin) {
+                        double pos[3];
+                        for (int i = 0; i < 3; i++) pos[i] = vk[i] - n[i] * dist / 2;
+                        add_contact(m, d, g1, g2, k, dist, pos, n);
+                    }
+                }
+            }
+        }
+    std::sort(d.con.begin(), d.con.end(), [](const Contact& a, const Contact& b) {
+        if (a.g1 != b.g1) return a.g1 < b.g1;
+        if (a.g2 != b.g2) return a.g2 < b.g2;
+        return a.feature < b.feature;
+    });
+}
+
+// ------------------------------------------------------------------------------------
+// soft constraints: pyramidal rows, impedance, reference acceleration, regulariser
+// ------------------------------------------------------------------------------------
+double impedance(const Model& m, double r) {
+    double dmin = m.solimp[0], dmax = m.solimp[1], width = m.solimp[2], mid = m.solimp[3], p = m.solimp[4];
+    double x = std::min(std::fabs(r) / width, 1.0);
+    double y;
+    if (x <= mid)
+        y = std::pow(x, p) / std::pow(mid, p - 1);
+    else
+        y = 1 - std::pow(1 - x, p) / std::pow(1 - mid, p - 1);
+    double imp = dmin + y * (dmax - dmin);
+    return std::min(std::max(imp, 1e-4), 0.9999);
+}
+
+void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
+    int nv = m.nv, nc = (int)d.con.size();
+    d.nrows = 4 * nc;
+    d.J.assign((size_t)d.nrows * nv, 0.0);
+    d.aref.assign(d.nrows, 0.0);
+    d.D.assign(d.nrows, 0.0);
+    d.Ahat.assign(d.nrows, 0.0);
+    double dmax = std::min(std::max(m.solimp[1], 1e-4), 0.9999);
+    double tc = std::max(m.solref[0], 2 * m.dt), zeta = m.solref[1];
+    double bcoef = 2.0 / (dmax * tc);
+    double kcoef = 1.0 / (dmax * dmax * tc * tc * zeta * zeta);
+    std::vector<double> jp1(3 * nv), jr1(3 * nv), jp2(3 * nv), jr2(3 * nv), Jc(3 * nv), x(nv);
+    for (int ci = 0; ci < nc; ci++) {
+        const Contact& c = d.con[ci];
+        jacobian(m, d, c.b2, c.pos, jp2.data(), jr2.data());
+        jacobian(m, d, c.b1, c.pos, jp1.data(), jr1.data());
+        for (int r = 0; r < 3; r++)
+            for (int k = 0; k < nv; k++) {
+                double acc = 0;
+                for (int i = 0; i < 3; i++) acc += c.frame[3 * r + i] * (jp2[i * nv + k] - jp1[i * nv + k]);
+                Jc[r * nv + k] = acc;
+            }
+        double rdist = c.dist - std::max(m.gmargin[c.g1], m.gmargin[c.g2]);
+        double imp = impedance(m, rdist);
+        for (int e = 0; e < 4; e++) {
+            int row = 4 * ci + e;
+            int t = 1 + e / 2;
+            double sgn = (e % 2 == 0) ? 1.0 : -1.0;
+            double* Je = &d.J[(size_t)row * nv];
+            for (int k = 0; k < nv; k++) Je[k] = Jc[k] + sgn * c.mu * Jc[t * nv + k];
+            double vel = 0;
+            for (int k = 0; k < nv; k++) vel += Je[k] * d.v[k];
+            chol_solve(LM, nv, Je, x.data());
+            double A = 0;
+            for (int k = 0; k < nv; k++) A += Je[k] * x[k];
+            d.Ahat[row] = A;
+            d.aref[row] = -bcoef * vel - kcoef * imp * rdist;
+            double R = std::max(1e-15, (1 - imp) / imp * A);
+            d.D[row] = 1.0 / R;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// primal Newton solver on f(a) = 0.5 (a-a0)'M(a-a0) + sum_e 0.5 D_e min(J_e a - aref_e, 0)^2
+// ------------------------------------------------------------------------------------
+double cost(const Model& m, const Data& d, const double* a) {
+    int nv = m.nv;
+    double f = 0;
+    for (int r = 0; r < nv; r++)
+        for (int s = 0; s < nv; s++) f += 0.5 * (a[r] - d.a0[r]) * d.M[r * nv + s] * (a[s] - d.a0[s]);
+    for (int e = 0; e < d.nrows; e++) {
+        double jar = -d.aref[e];
+        for (int k = 0; k < nv; k++) jar += d.J[(size_t)e * nv + k] * a[k];
+        if (jar < 0) f += 0.5 * d.D[e] * jar * jar;
+    }
+    return f;
+}
+
+// exact minimiser over alpha >= 0 of the convex piecewise quadratic phi(alpha) = f(a + alpha p)
+double line_search(const Model& m, const Data& d, const std::vector<double>& jar, const std::vector<double>& p) {
+    int nv = m.nv, nr = d.nrows;
+    bool any = false;
+    for (int k = 0; k < nv; k++) any |= (p[k] != 0);
+    if (!any) return 0.0;
+    std::vector<double> s(nr, 0.0), Mp(nv, 0.0);
+    for (int e = 0; e < nr; e++)
+        for (int k = 0; k < nv; k++) s[e] += d.J[(size_t)e * nv + k] * p[k];
+    for (int r = 0; r < nv; r++)
+        for (int k = 0; k < nv; k++) Mp[r] += d.M[r * nv + k] * p[k];
+    double A0 = 0, B0 = 0;
+    for (int k = 0; k < nv; k++) {
+        A0 += p[k] * Mp[k];
+        B0 += (d.a[k] - d.a0[k]) * Mp[k];
+    }
+    // breakpoints where a row switches on or off, in ascending order
+    std::vector<std::pair<double, int>> bp;
+    for (int e = 0; e < nr; e++)
+        if (s[e] != 0) {
+            double al = -jar[e] / s[e];
+            if (al > 0) bp.push_back({al, e});
+        }
+    std::sort(bp.begin(), bp.end());
+    // rows active just to the right of alpha = 0
+    std::vector<char> act(nr);
+    for (int e = 0; e < nr; e++) act[e] = (jar[e] < 0) || (jar[e] == 0 && s[e] < 0);
+    size_t i = 0;
+    while (true) {
+        double A = A0, B = B0;
+        for (int e = 0; e < nr; e++)
+            if (act[e]) {
+                A += d.D[e] * s[e] * s[e];
+                B += d.D[e] * s[e] * jar[e];
+            }
+        double root = -B / A;
+        if (i == bp.size() || root <= bp[i].first) return std::max(root, 0.0);
+        double here = bp[i].first;
+        while (i < bp.size() && bp[i].first == here) {
+            act[bp[i].second] = s[bp[i].second] < 0;  // s < 0: switches on; s > 0: switches off
+            i++;
+        }
+    }
+}
+
+void newton(const Model& m, Data& d) {
+    int nv = m.nv, nr = d.nrows;
+    int maxiter = m.mode == 1 ? 100 : m.iters;
+    double tol = m.mode == 1 ? 1e-12 : m.tol;
+    double scale = m.meaninertia * nv;
+    d.niter = 0;
+    d.a = d.a0;
+    if (nr == 0) {
+        d.efc_force.assign(0, 0.0);
+        d.cost = 0;
+        return;
+    }
+    if (cost(m, d, d.aws.data()) < cost(m, d, d.a0.data())) d.a = d.aws;
+    std::vector<double> jar(nr), g(nv), H(nv * nv), LH, p(nv), anew(nv);
+    for (int it = 0; it < maxiter; it++) {
+        for (int e = 0; e < nr; e++) {
+            double t = -d.aref[e];
+            for (int k = 0; k < nv; k++) t += d.J[(size_t)e * nv + k] * d.a[k];
+            jar[e] = t;
+        }
+        for (int r = 0; r < nv; r++) {
+            double t = 0;
+            for (int k = 0; k < nv; k++) t += d.M[r * nv + k] * (d.a[k] - d.a0[k]);
+            g[r] = t;
+        }
+        H = d.M;
+        for (int e = 0; e < nr; e++) {
+            if (!(jar[e] < 0)) continue;
+            const double* Je = &d.J[(size_t)e * nv];
+            for (int r = 0; r < nv; r++) {
+                g[r] += d.D[e] * jar[e] * Je[r];
+                for (int k = 0; k < nv; k++) H[r * nv + k] += d.D[e] * Je[r] * Je[k];
+            }
+        }
+        double gn = 0;
+        for (int k = 0; k < nv; k++) gn += g[k] * g[k];
+        if (std::sqrt(gn) / scale < tol) break;
+        if (!cholesky(H, nv, LH)) break;
+        std::vector<double> ng(nv);
+        for (int k = 0; k < nv; k++) ng[k] = -g[k];
+        chol_solve(LH, nv, ng.data(), p.data());
+        double alpha = line_search(m, d, jar, p);
+        double fold = cost(m, d, d.a.data());
+        for (int k = 0; k < nv; k++) anew[k] = d.a[k] + alpha * p[k];
+        double fnew = cost(m, d, anew.data());
+        d.a = anew;
+        d.niter = it + 1;
+        if ((fold - fnew) / scale < tol) break;
+    }
+    d.cost = cost(m, d, d.a.data());
+    d.efc_force.assign(nr, 0.0);
+    for (int e = 0; e < nr; e++) {
+        double t = -d.aref[e];
+        for (int k = 0; k < nv; k++) t += d.J[(size_t)e * nv + k] * d.a[k];
+        d.efc_force[e] = -d.D[e] * std::min(t, 0.0);
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// one substep without integration: actuation, kinematics, dynamics, collision, solve
+// ------------------------------------------------------------------------------------
+void forward(const Model& m, Data& d) {
+    actuation(m, d);
+    kinematics(m, d);
+    mass_matrix(m, d);
+    bias_forces(m, d);
+    std::vector<double> LM;
+    if (!cholesky(d.M, m.nv, LM)) {
+        std::fill(d.a0.begin(), d.a0.end(), NAN);
+        d.a = d.a0;
+        d.con.clear();
+        d.nrows = 0;
+        return;
+    }
+    std::vector<double> rhs(m.nv);
+    for (int k = 0; k < m.nv; k++) rhs[k] = d.tau[k] - d.c[k];
+    chol_solve(LM, m.nv, rhs.data(), d.a0.data());
+    collide(m, d);
+    make_rows(m, d, LM);
+    newton(m, d);
+    d.cforce.assign(3 * d.con.size(), 0.0);
+    for (size_t ci = 0; ci < d.con.size(); ci++) {
+        const double* f = &d.efc_force[4 * ci];
+        double mu = d.con[ci].mu;
+        d.cforce[3 * ci] = f[0] + f[1] + f[2] + f[3];
+        d.cforce[3 * ci + 1] = mu * (f[0] - f[1]);
+        d.cforce[3 * ci + 2] = mu * (f[2] - f[3]);
+    }
+}
+
+// semi-implicit Euler: v' = v + dt a; hinge q' = q + dt v'; free pos += dt v'_lin,
+// quat' = normalise(quat * exp(dt w'_local / 2))
+void integrate(const Model& m, const double* q, const double* v, const double* a, double* qo, double* vo) {
+    double dt = m.dt;
+    for (int k = 0; k < m.nv; k++) vo[k] = v[k] + dt * a[k];
+    for (int j = 0; j < m.njnt; j++) {
+        int qa = m.jqadr[j], da = m.jdadr[j];
+        if (m.jtype[j] == RBO_JNT_HINGE) {
+            qo[qa] = q[qa] + dt * vo[da];
+        } else {
+            for (int i = 0; i < 3; i++) qo[qa + i] = q[qa + i] + dt * vo[da + i];
+            double th[3] = {dt * vo[da + 3], dt * vo[da + 4], dt * vo[da + 5]};
+            double ang = std::sqrt(dot3(th, th));
+            double dq[4] = {1, 0, 0, 0};
+            if (ang > 0) {
+                double u[3] = {th[0] / ang, th[1] / ang, th[2] / ang};
+                axisangle2quat(u, ang, dq);
+            }
+            double qq[4];
+            quatmul(&q[qa + 3], dq, qq);
+            quatnormalize(qq);
+            for (int i = 0; i < 4; i++) qo[qa + 3 + i] = qq[i];
+        }
+    }
+}
+
+bool all_finite(const double* x, int n) {
+    for (int i = 0; i < n; i++)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+void load_world(const Model& m, Data& d, const double* q, const double* v, const double* ctrl, const double* aws,
+                const double* fr, const double* ms) {
+    std::copy(q, q + m.nq, d.q.begin());
+    std::copy(v, v + m.nv, d.v.begin());
+    if (m.nu) std::copy(ctrl, ctrl + m.nu, d.ctrl.begin());
+    if (aws)
+        std::copy(aws, aws + m.nv, d.aws.begin());
+    else
+        std::fill(d.aws.begin(), d.aws.end(), 0.0);
+    d.fr = fr ? *fr : 1.0;
+    if (ms && m.ms_pw)
+        std::copy(ms, ms + m.nbody, d.ms.begin());
+    else
+        std::fill(d.ms.begin(), d.ms.end(), 1.0);
+}
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+extern "C" {
+
+const char* rbo_last_error(void) { return g_err.c_str(); }
+
+int rbo_model_create(const rbo_desc* dsc, void** out) {
+    if (!dsc || !out) return fail("null argument");
+    Model* m = new Model();
+    Model& M = *m;
+    M.nbody = dsc->nbody; M.njnt = dsc->njnt; M.ngeom = dsc->ngeom; M.nu = dsc->nu;
+    int nb = M.nbody, nj = M.njnt, ng = M.ngeom, nu = M.nu;
+    auto bad = [&](const std::string& s) { delete m; return fail(s); };
+    if (nb < 1 || nj < 0 || ng < 0 || nu < 0) return bad("bad sizes");
+    M.parent.assign(dsc->body_parent, dsc->body_parent + nb);
+    M.bpos.assign(dsc->body_pos, dsc->body_pos + 3 * nb);
+    M.bquat.assign(dsc->body_quat, dsc->body_quat + 4 * nb);
+    M.ipos.assign(dsc->body_ipos, dsc->body_ipos + 3 * nb);
+    M.iquat.assign(dsc->body_iquat, dsc->body_iquat + 4 * nb);
+    M.mass.assign(dsc->body_mass, dsc->body_mass + nb);
+    M.inertia.assign(dsc->body_inertia, dsc->body_inertia + 3 * nb);
+    for (int b = 1; b < nb; b++)
+        if (M.parent[b] < 0 || M.parent[b] >= b) return bad("body parent must precede the body");
+    M.body_jnt.assign(nb, -1);
+    if (nj) {
+        M.jtype.assign(dsc->jnt_type, dsc->jnt_type + nj);
+        M.jbody.assign(dsc->jnt_body, dsc->jnt_body + nj);
+        M.jpos.assign(dsc->jnt_pos, dsc->jnt_pos + 3 * nj);
+        M.jaxis.assign(dsc->jnt_axis, dsc->jnt_axis + 3 * nj);
+        M.jarm.assign(dsc->jnt_armature, dsc->jnt_armature + nj);
+    }
+    M.jqadr.assign(nj, 0); M.jdadr.assign(nj, 0);
+    // joints must be listed in body order so dof order follows body order
+    int qa = 0, da = 0, lastb = 0;
+    for (int j = 0; j < nj; j++) {
+        int b = M.jbody[j];
+        if (b <= 0 || b >= nb) return bad("joint on invalid body");
+        if (M.body_jnt[b] >= 0) return bad("more than one joint on a body");
+        if (b < lastb) return bad("joints must be listed in body order");
+        lastb = b;
+        M.body_jnt[b] = j;
+        M.jqadr[j] = qa; M.jdadr[j] = da;
+        if (M.jtype[j] == RBO_JNT_FREE) {
+            if (M.parent[b] != 0) return bad("free joint must be on a child of the world");
+            qa += 7; da += 6;
+        } else if (M.jtype[j] == RBO_JNT_HINGE) {
+            qa += 1; da += 1;
+            double* ax = &M.jaxis[3 * j];
+            double n = std::sqrt(dot3(ax, ax));
+            if (!(n > 0)) return bad("zero hinge axis");
+            for (int i = 0; i < 3; i++) ax[i] /= n;
+        } else {
+            return bad("unknown joint type");
+        }
+    }
+    M.nq = qa; M.nv = da;
+    for (int b = 0; b < nb; b++) {
+        double* q = &M.bquat[4 * b];
+        double nrm = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        if (std::fabs(nrm - 1) > 1e-6) return bad("body quaternion not unit");
+        if (b > 0 && !(M.mass[b] > 0)) return bad("non-positive body mass");
+        const double* I = &M.inertia[3 * b];
+        if (b > 0 && (I[0] + I[1] < I[2] * (1 - 1e-12) || I[1] + I[2] < I[0] * (1 - 1e-12) || I[0] + I[2] < I[1] * (1 - 1e-12) ||
+                      !(I[0] > 0 && I[1] > 0 && I[2] > 0)))
+            return bad("inertia violates the triangle inequality");
+    }
+    M.movable.assign(nb, 0);
+    for (int b = 1; b < nb; b++) M.movable[b] = M.movable[M.parent[b]] || M.body_jnt[b] >= 0;
+    if (ng) {
+        M.gtype.assign(dsc->geom_type, dsc->geom_type + ng);
+        M.gbody.assign(dsc->geom_body, dsc->geom_body + ng);
+        M.gcontype.assign(dsc->geom_contype, dsc->geom_contype + ng);
+        M.gconaff.assign(dsc->geom_conaffinity, dsc->geom_conaffinity + ng);
+        M.gpos.assign(dsc->geom_pos, dsc->geom_pos + 3 * ng);
+        M.gquat.assign(dsc->geom_quat, dsc->geom_quat + 4 * ng);
+        M.gsize.assign(dsc->geom_size, dsc->geom_size + 3 * ng);
+        M.gfric.assign(dsc->geom_friction, dsc->geom_friction + ng);
+        M.gmargin.assign(dsc->geom_margin, dsc->geom_margin + ng);
+    }
+    for (int g = 0; g < ng; g++) {
+        if (M.gtype[g] < 0 || M.gtype[g] > 3) return bad("unknown geom type");
+        if (M.gbody[g] < 0 || M.gbody[g] >= nb) return bad("geom on invalid body");
+        if (M.gtype[g] == RBO_GEOM_PLANE && M.movable[M.gbody[g]]) return bad("planes must be static");
+    }
+    M.maxcon = 0; M.npair = 0;
+    for (int a = 0; a < ng; a++)
+        for (int b = a + 1; b < ng; b++) {
+            if (!pair_allowed(M, a, b)) continue;
+            int t1 = std::min(M.gtype[a], M.gtype[b]), t2 = std::max(M.gtype[a], M.gtype[b]);
+            int cap = pair_capacity(t1, t2);
+            if (cap < 0) return bad("unsupported collision pair type");
+            M.maxcon += cap;
+            M.npair++;
+        }
+    if (nu) {
+        M.atype.assign(dsc->act_type, dsc->act_type + nu);
+        M.ajoint.assign(dsc->act_joint, dsc->act_joint + nu);
+        M.akp.assign(dsc->act_kp, dsc->act_kp + nu);
+        M.akd.assign(dsc->act_kd, dsc->act_kd + nu);
+        M.agear.assign(dsc->act_gear, dsc->act_gear + nu);
+    }
+    for (int u = 0; u < nu; u++) {
+        if (M.ajoint[u] < 0 || M.ajoint[u] >= nj) return bad("actuator on invalid joint");
+        if (M.jtype[M.ajoint[u]] != RBO_JNT_HINGE) return bad("actuators drive hinge joints only");
+        if (M.atype[u] != RBO_ACT_POSITION && M.atype[u] != RBO_ACT_MOTOR) return bad("unknown actuator type");
+    }
+    M.dt = dsc->timestep; M.K = dsc->nsubsteps;
+    for (int i = 0; i < 3; i++) M.grav[i] = dsc->gravity[i];
+    M.iters = dsc->iterations; M.tol = dsc->tolerance;
+    for (int i = 0; i < 2; i++) M.solref[i] = dsc->solref[i];
+    for (int i = 0; i < 5; i++) M.solimp[i] = dsc->solimp[i];
+    M.fr_pw = dsc->friction_per_world != 0;
+    M.ms_pw = dsc->mass_scale_per_world != 0;
+    if (!(M.dt > 0) || M.K < 1 || M.iters < 0) return bad("bad options");
+    // mean diagonal inertia at the reference configuration (free joints at their body pose)
+    if (M.nv > 0) {
+        Data d(&M);
+        for (int j = 0; j < nj; j++) {
+            if (M.jtype[j] == RBO_JNT_FREE) {
+                int b = M.jbody[j];
+                for (int i = 0; i < 3; i++) d.q[M.jqadr[j] + i] = M.bpos[3 * b + i];
+                for (int i = 0; i < 4; i++) d.q[M.jqadr[j] + 3 + i] = M.bquat[4 * b + i];
+            }
+        }
+        kinematics(M, d);
+        mass_matrix(M, d);
+        double tr = 0;
+        for (int k = 0; k < M.nv; k++) tr += d.M[k * (M.nv + 1)];
+        M.meaninertia = tr / M.nv;
+    }
+    *out = m;
+    return 0;
+}
+
+void rbo_model_destroy(void* m) { delete static_cast<Model*>(m); }
+
+int rbo_model_info(const void* mp, rbo_info* out) {
+    if (!mp || !out) return fail("null argument");
+    const Model& m = *static_cast<const Model*>(mp);
+    out->nq = m.nq; out->nv = m.nv; out->nu = m.nu; out->nbody = m.nbody; out->ngeom = m.ngeom;
+    out->maxcon = m.maxcon; out->maxrows = 4 * m.maxcon; out->npair = m.npair;
+    out->meaninertia = m.meaninertia;
+    return 0;
+}
+
+int rbo_set_mode(void* mp, int32_t mode) {
+    if (!mp || (mode != 0 && mode != 1)) return fail("bad mode");
+    static_cast<Model*>(mp)->mode = mode;
+    return 0;
+}
+
+int rbo_forward(const void* mp, const double* qpos, const double* qvel, const double* ctrl, const double* qacc_ws,
+                const double* friction, const double* mass_scale, rbo_taps* t) {
+    if (!mp || !qpos || !qvel) return fail("null argument");
+    const Model& m = *static_cast<const Model*>(mp);
+    Data d(&m);
+    std::vector<double> zero(m.nu, 0.0);
+    load_world(m, d, qpos, qvel, ctrl ? ctrl : zero.data(), qacc_ws, friction, mass_scale);
+    forward(m, d);
+    if (!t) return 0;
+    int nv = m.nv, nb = m.nbody, ng = m.ngeom, nc = (int)d.con.size();
+    auto put = [](double* dst, const std::vector<double>& src) {
+        if (dst) std::copy(src.begin(), src.end(), dst);
+    };
+    put(t->xpos, d.xpos); put(t->xquat, d.xquat); put(t->xmat, d.xmat); put(t->com, d.com);
+    put(t->gpos, d.gx); put(t->gmat, d.gR);
+    put(t->M, d.M); put(t->bias, d.c); put(t->tau, d.tau); put(t->a0, d.a0);
+    put(t->qacc, d.a);
+    (void)nb; (void)ng;
+    if (t->ncon) *t->ncon = nc;
+    for (int ci = 0; ci < nc; ci++) {
+        const Contact& c = d.con[ci];
+        if (t->geom) { t->geom[2 * ci] = c.g1; t->geom[2 * ci + 1] = c.g2; }
+        if (t->feature) t->feature[ci] = c.feature;
+        if (t->dist) t->dist[ci] = c.dist;
+        if (t->pos) std::copy(c.pos, c.pos + 3, t->pos + 3 * ci);
+        if (t->frame) std::copy(c.frame, c.frame + 9, t->frame + 9 * ci);
+        if (t->mu) t->mu[ci] = c.mu;
+        if (t->cforce) std::copy(&d.cforce[3 * ci], &d.cforce[3 * ci] + 3, t->cforce + 3 * ci);
+    }
+    put(t->J, d.J); put(t->aref, d.aref); put(t->D, d.D); put(t->Ahat, d.Ahat); put(t->efc_force, d.efc_force);
+    if (t->niter) *t->niter = d.niter;
+    if (t->cost) *t->cost = d.cost;
+    return 0;
+}
+
+int rbo_step(const void* mp, int32_t n, const double* ctrl, double* qpos, double* qvel, double* qacc_ws,
+             const double* friction, const double* mass_scale, uint32_t* status, rbo_contacts* out, int32_t nthreads) {
+    if (!mp || n < 0 || !qpos || !qvel || !qacc_ws || !status) return fail("null argument");
+    const Model& m = *static_cast<const Model*>(mp);
+    if (m.nu && !ctrl) return fail("ctrl required");
+#ifdef _OPENMP
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        Data d(&m);
+        std::vector<double> q1(m.nq), v1(m.nv);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+        for (int w = 0; w < n; w++) {
+            double* q = qpos + (size_t)w * m.nq;
+            double* v = qvel + (size_t)w * m.nv;
+            double* aws = qacc_ws + (size_t)w * m.nv;
+            const double* u = m.nu ? ctrl + (size_t)w * m.nu : nullptr;
+            const double* fr = friction ? friction + w : nullptr;
+            const double* ms = mass_scale ? mass_scale + (size_t)w * m.nbody : nullptr;
+            int ncon = 0;
+            if (!(status[w] & 1u)) {
+                for (int k = 0; k < m.K; k++) {
+                    load_world(m, d, q, v, u, aws, fr, ms);
+                    forward(m, d);
+                    integrate(m, q, v, d.a.data(), q1.data(), v1.data());
+                    if (!all_finite(q1.data(), m.nq) || !all_finite(v1.data(), m.nv) || !all_finite(d.a.data(), m.nv)) {
+                        status[w] |= 1u;
+                        ncon = 0;
+                        break;
+                    }
+                    std::copy(q1.begin(), q1.end(), q);
+                    std::copy(v1.begin(), v1.end(), v);
+                    std::copy(d.a.begin(), d.a.end(), aws);
+                    ncon = (int)d.con.size();
+                }
+            }
+            if (out) {
+                if (out->ncon) out->ncon[w] = ncon;
+                size_t base = (size_t)w * m.maxcon;
+                for (int ci = 0; ci < ncon; ci++) {
+                    const Contact& c = d.con[ci];
+                    if (out->geom) { out->geom[2 * (base + ci)] = c.g1; out->geom[2 * (base + ci) + 1] = c.g2; }
+                    if (out->feature) out->feature[base + ci] = c.feature;
+                    if (out->dist) out->dist[base + ci] = c.dist;
+                    if (out->pos) std::copy(c.pos, c.pos + 3, out->pos + 3 * (base + ci));
+                    if (out->frame) std::copy(c.frame, c.frame + 9, out->frame + 9 * (base + ci));
+                    if (out->force) std::copy(&d.cforce[3 * ci], &d.cforce[3 * ci] + 3, out->force + 3 * (base + ci));
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+int rbo_energy(const void* mp, const double* qpos, const double* qvel, const double* mass_scale, double* kin,
+               double* pot) {
+    if (!mp || !qpos || !qvel) return fail("null argument");
+    const Model& m = *static_cast<const Model*>(mp);
+    Data d(&m);
+    std::vector<double> zero(m.nu, 0.0);
+    load_world(m, d, qpos, qvel, zero.data(), nullptr, nullptr, mass_scale);
+    kinematics(m, d);
+    mass_matrix(m, d);
+    double T = 0, V = 0;
+    for (int r = 0; r < m.nv; r++)
+        for (int s = 0; s < m.nv; s++) T += 0.5 * d.v[r] * d.M[r * m.nv + s] * d.v[s];
+    for (int b = 1; b < m.nbody; b++) V -= d.mb[b] * dot3(m.grav, &d.com[3 * b]);
+    if (kin) *kin = T;
+    if (pot) *pot = V;
+    return 0;
+}
+
+int rbo_jacobian(const void* mp, const double* qpos, int32_t body, const double* p, double* jacp, double* jacr) {
+    if (!mp || !qpos || !p || !jacp || !jacr) return fail("null argument");
+    const Model& m = *static_cast<const Model*>(mp);
+    if (body < 0 || body >= m.nbody) return fail("bad body");
+    Data d(&m);
+    std::copy(qpos, qpos + m.nq, d.q.begin());
+    kinematics(m, d);
+    jacobian(m, d, body, p, jacp, jacr);
+    return 0;
+}
+
+int rbo_integrate(const void* mp, const double* qpos, const double* qvel, const double* qacc, double* qo, double* vo) {
+    if (!mp || !qpos || !qvel || !qacc || !qo || !vo) return fail("null argument");
+    integrate(*static_cast<const Model*>(mp), qpos, qvel, qacc, qo, vo);
+    return 0;
+}
+
+}  // extern "C"

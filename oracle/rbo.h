@@ -1,0 +1,123 @@
+/*
+ * FP64 CPU oracle for the batched rigid-body physics step -- TEST INFRASTRUCTURE ONLY.
+ *
+ * This library is the plain, slow, obviously-correct reference that the HIP path is
+ * checked against.  Only the tests, the smoke check and the benchmark's CPU-baseline leg
+ * may load it; the product path never calls it.  It shares no code with the HIP library.
+ *
+ * The paper (section "Architecture", paragraph on the GPU physics backend) describes the
+ * physics only through its interface: a static model, a per-world time-varying state with
+ * a leading world dimension, model fields shared or expanded per world, and a step that
+ * advances every world (decimated into physics substeps, section "Manager-Based API",
+ * pipeline step "Simulate").  Everything inside the step follows the published MuJoCo
+ * formulation written from the mathematics (rigid-body kinematics and dynamics after
+ * Featherstone 2008; soft constraints and the Newton solver after Todorov 2014).
+ *
+ * Plain definitions, not fast algorithms: M is the Jacobian sum, c the Jacobian-transpose
+ * Newton-Euler sum, all solves dense Cholesky, collision brute force over geom pairs.
+ *
+ * All arrays are host memory, row-major, float64, owned by the caller.
+ * Functions return 0 on success, negative on error (message via rbo_last_error()).
+ */
+#ifndef RBO_H
+#define RBO_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { RBO_GEOM_PLANE = 0, RBO_GEOM_SPHERE = 1, RBO_GEOM_CAPSULE = 2, RBO_GEOM_BOX = 3 };
+enum { RBO_JNT_FREE = 0, RBO_JNT_HINGE = 1 };
+enum { RBO_ACT_POSITION = 0, RBO_ACT_MOTOR = 1 };
+
+typedef struct rbo_desc {
+    int32_t nbody, njnt, ngeom, nu;
+    /* bodies [nbody]; body 0 is the world */
+    const int32_t* body_parent;
+    const double *body_pos, *body_quat, *body_ipos, *body_iquat, *body_mass, *body_inertia;
+    /* joints [njnt] */
+    const int32_t *jnt_type, *jnt_body;
+    const double *jnt_pos, *jnt_axis, *jnt_armature;
+    /* geoms [ngeom] */
+    const int32_t *geom_type, *geom_body, *geom_contype, *geom_conaffinity;
+    const double *geom_pos, *geom_quat, *geom_size, *geom_friction, *geom_margin;
+    /* actuators [nu] */
+    const int32_t *act_type, *act_joint;
+    const double *act_kp, *act_kd, *act_gear;
+    /* options */
+    double timestep;
+    int32_t nsubsteps;
+    double gravity[3];
+    int32_t iterations;
+    double tolerance;
+    double solref[2];
+    double solimp[5];
+    int32_t friction_per_world, mass_scale_per_world;
+} rbo_desc;
+
+typedef struct rbo_info {
+    int32_t nq, nv, nu, nbody, ngeom, maxcon, maxrows, npair;
+    double meaninertia;
+} rbo_info;
+
+/* Contact list of one world, capacity maxcon (any pointer may be NULL). */
+typedef struct rbo_contacts {
+    int32_t* ncon;        /* [n] */
+    int32_t* geom;        /* [n, maxcon, 2] */
+    int32_t* feature;     /* [n, maxcon] */
+    double* dist;         /* [n, maxcon] */
+    double* pos;          /* [n, maxcon, 3] */
+    double* frame;        /* [n, maxcon, 9] rows: normal, t1, t2 */
+    double* force;        /* [n, maxcon, 3] (f_n, f_t1, f_t2) */
+} rbo_contacts;
+
+/* Stage taps of one substep for one world (any pointer may be NULL). */
+typedef struct rbo_taps {
+    double *xpos, *xquat, *xmat, *com;          /* [nbody,3] [nbody,4] [nbody,9] [nbody,3] */
+    double *gpos, *gmat;                        /* [ngeom,3] [ngeom,9] */
+    double *M, *bias, *tau, *a0;                /* [nv,nv] [nv] [nv] [nv] */
+    int32_t* ncon;                              /* [1] */
+    int32_t *geom, *feature;                    /* [maxcon,2] [maxcon] */
+    double *dist, *pos, *frame, *mu;            /* [maxcon] [maxcon,3] [maxcon,9] [maxcon] */
+    double *J, *aref, *D, *Ahat, *efc_force;    /* [maxrows,nv] [maxrows] x4 */
+    double *qacc, *cforce;                      /* [nv] [maxcon,3] */
+    int32_t* niter;                             /* [1] Newton iterations run */
+    double* cost;                               /* [1] final cost f(qacc) */
+} rbo_taps;
+
+const char* rbo_last_error(void);
+int rbo_model_create(const rbo_desc* d, void** out);
+void rbo_model_destroy(void* m);
+int rbo_model_info(const void* m, rbo_info* out);
+
+/* mode: 0 = mirror (model iterations/tolerance), 1 = converged (100 iterations, tol 1e-12). */
+int rbo_set_mode(void* m, int32_t mode);
+
+/* One substep for one world from (qpos, qvel, ctrl, qacc_ws); fills taps; does not integrate. */
+int rbo_forward(const void* m, const double* qpos, const double* qvel, const double* ctrl,
+                const double* qacc_ws, const double* friction, const double* mass_scale, rbo_taps* taps);
+
+/* n env steps of K substeps each (OpenMP over worlds, nthreads <= 0 -> all cores).
+ * qpos [n,nq], qvel [n,nv], qacc_ws [n,nv] in/out; ctrl [n,nu]; friction [n] / mass_scale
+ * [n,nbody] may be NULL; status [n] in/out (bit 0 = non-finite, world frozen);
+ * contacts may be NULL and receive the last substep's contacts. */
+int rbo_step(const void* m, int32_t n, const double* ctrl, double* qpos, double* qvel,
+             double* qacc_ws, const double* friction, const double* mass_scale, uint32_t* status,
+             rbo_contacts* contacts, int32_t nthreads);
+
+/* Energies of one world: kinetic 0.5 v'Mv and gravitational potential -sum m g.com. */
+int rbo_energy(const void* m, const double* qpos, const double* qvel, const double* mass_scale,
+               double* kinetic, double* potential);
+
+/* Point Jacobians of a body point p (world): jacp [3,nv], jacr [3,nv]. */
+int rbo_jacobian(const void* m, const double* qpos, int32_t body, const double* p, double* jacp,
+                 double* jacr);
+
+/* Integrate one semi-implicit Euler substep from a given acceleration (no dynamics). */
+int rbo_integrate(const void* m, const double* qpos, const double* qvel, const double* qacc,
+                  double* qpos_out, double* qvel_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

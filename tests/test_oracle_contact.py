@@ -1,0 +1,332 @@
+"""Pins of the oracle's collision, soft-constraint and Newton stages (CPU)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq, minimize
+
+from helpers import q_plus, quat_mul, rot
+from workloads import robots
+
+K_REF = 1.0 / (0.95 ** 2 * 0.02 ** 2)      # stiffness of the default solref/solimp, 1/s^2
+B_REF = 2.0 / (0.95 * 0.02)                 # damping, 1/s
+
+
+def imp_ref(r, dmin=0.9, dmax=0.95, width=0.001, mid=0.5, p=2.0):
+    x = min(abs(r) / width, 1.0)
+    y = x ** p / mid ** (p - 1) if x <= mid else 1 - (1 - x) ** p / (1 - mid) ** (p - 1)
+    return dmin + y * (dmax - dmin)
+
+
+def test_reference_coefficients():
+    assert abs(K_REF - 2770.083) < 1e-3 and abs(B_REF - 105.263) < 1e-3
+
+
+# ---------------------------------------------------------------- collision
+def test_sphere_plane(oracle_mod):
+    m = robots.free_body("sphere", size=(0.05,), ground_quat=robots.quat_axis_angle((1, 0, 0), 0.3))
+    o = oracle_mod.Oracle(m)
+    n = rot(m["geoms"][0]["quat"])[:, 2]
+    for h in (0.06, 0.05, 0.049, 0.03):
+        c = n * h + np.array([0.0, 0.0, 0.0])
+        c = c + np.cross(n, [1, 0, 0]) * 0.7       # slide along the plane: distance unchanged
+        q = np.concatenate([c, [1, 0, 0, 0]])
+        t = o.forward(q, np.zeros(6))
+        d = h - 0.05
+        if d < 0:
+            assert t["ncon"] == 1
+            assert abs(t["dist"][0] - d) < 1e-15
+            np.testing.assert_allclose(t["pos"][0], c - n * (0.05 + d / 2), atol=1e-15)
+            np.testing.assert_allclose(t["frame"][0][0], n, atol=1e-15)
+            F = t["frame"][0]
+            np.testing.assert_allclose(F @ F.T, np.eye(3), atol=1e-15)
+            assert abs(np.linalg.det(F) - 1) < 1e-14
+            assert tuple(t["geom"][0]) == (0, 1) and t["feature"][0] == 0
+        else:
+            assert t["ncon"] == 0   # d == 0 is not a contact (strict inequality)
+
+
+def test_tangent_frame_rule(oracle_mod):
+    m = robots.free_body("sphere", size=(0.05,))
+    o = oracle_mod.Oracle(m)
+    t = o.forward(np.array([0, 0, 0.04, 1, 0, 0, 0]), np.zeros(6))
+    # rows (n, t1, t2): n = z -> t1 = x, t2 = y
+    np.testing.assert_allclose(t["frame"][0], [[0, 0, 1], [1, 0, 0], [0, 1, 0]], atol=1e-15)
+    # tilted plane: t1 = normalise(e_k - (e_k . n) n) with k = argmin |n_k|
+    qg = robots.quat_axis_angle((0.3, 1.0, 0.2), 0.7)
+    m = robots.free_body("sphere", size=(0.05,), ground_quat=qg)
+    o = oracle_mod.Oracle(m)
+    n = rot(qg)[:, 2]
+    t = o.forward(np.concatenate([n * 0.04, [1, 0, 0, 0]]), np.zeros(6))
+    k = int(np.argmin(np.abs(n)))
+    e = np.eye(3)[k]
+    t1 = e - e.dot(n) * n
+    t1 /= np.linalg.norm(t1)
+    np.testing.assert_allclose(t["frame"][0], np.stack([n, t1, np.cross(n, t1)]), atol=1e-15)
+
+
+def test_capsule_plane_ends(oracle_mod):
+    qc = robots.quat_axis_angle((1, 0, 0), 0.4)
+    m = robots.free_body("capsule", size=(0.03, 0.2), ground=True)
+    o = oracle_mod.Oracle(m)
+    R = rot(qc)
+    x = np.array([0.1, -0.2, 0.09])
+    t = o.forward(np.concatenate([x, qc]), np.zeros(6))
+    ends = [x - 0.2 * R[:, 2], x + 0.2 * R[:, 2]]
+    exp = [(f, e[2] - 0.03) for f, e in enumerate(ends) if e[2] - 0.03 < 0]
+    assert t["ncon"] == len(exp) == 1
+    for i, (f, d) in enumerate(exp):
+        assert t["feature"][i] == f
+        assert abs(t["dist"][i] - d) < 1e-15
+        np.testing.assert_allclose(t["pos"][i], ends[f] - np.array([0, 0, 1]) * (0.03 + d / 2), atol=1e-15)
+
+
+def test_box_plane_vertices(oracle_mod):
+    m = robots.free_body("box", size=(0.1, 0.2, 0.3))
+    o = oracle_mod.Oracle(m)
+    rng = np.random.default_rng(10)
+    for _ in range(20):
+        qb = rng.normal(size=4); qb /= np.linalg.norm(qb)
+        R = rot(qb)
+        x = np.array([0.0, 0.0, rng.uniform(0.0, 0.3)])
+        t = o.forward(np.concatenate([x, qb]), np.zeros(6))
+        exp = []
+        for k in range(8):
+            s = np.array([0.1 if k & 4 else -0.1, 0.2 if k & 2 else -0.2, 0.3 if k & 1 else -0.3])
+            vk = x + R @ s
+            if vk[2] < 0:
+                exp.append((k, vk[2], vk - np.array([0, 0, vk[2] / 2])))
+        assert t["ncon"] == len(exp)
+        for i, (k, d, p) in enumerate(exp):
+            assert t["feature"][i] == k
+            assert abs(t["dist"][i] - d) < 1e-15
+            np.testing.assert_allclose(t["pos"][i], p, atol=1e-15)
+
+
+def test_pair_filters(oracle_mod):
+    mb = robots.ModelBuilder("filters", timestep=0.005, nsubsteps=1)
+    mb.geom(0, "plane", [0, 0, 0], contype=1, conaffinity=1)
+    a = mb.body("a", 0, (0, 0, 0.5), 1.0, robots.sphere_inertia(1.0, 0.1))
+    mb.joint(a, "free")
+    mb.geom(a, "sphere", [0.1], contype=1, conaffinity=1)
+    b = mb.body("b", a, (0, 0, 0), 1.0, robots.sphere_inertia(1.0, 0.1))
+    mb.joint(b, "hinge", (0, 1, 0))
+    mb.geom(b, "sphere", [0.1], contype=2, conaffinity=2)      # (2 & 1) | (1 & 2) = 0 with the plane
+    m = mb.build()
+    o = oracle_mod.Oracle(m)
+    assert o.npair == 1 and o.maxcon == 1        # plane-a only: a-b is parent-child, plane-b masked
+    t = o.forward(np.array([0, 0, 0.05, 1, 0, 0, 0, 0.0]), np.zeros(7))
+    assert t["ncon"] == 1 and tuple(t["geom"][0]) == (0, 1)
+
+
+def test_humanoid_contacts_sorted_and_bounded(oracle_mod):
+    m = robots.humanoid()
+    o = oracle_mod.Oracle(m)
+    assert o.maxcon == 32 * 2 + 8 * 8 and o.npair == 40
+    q = robots.qpos0(m)
+    q[2] = 0.05                                   # pelvis dropped into the floor
+    t = o.forward(q, np.zeros(o.nv))
+    keys = [(g[0], g[1], f) for g, f in zip(t["geom"], t["feature"])]
+    assert keys == sorted(keys) and len(set(keys)) == len(keys)
+    assert np.all(t["dist"] < 0)
+
+
+# ---------------------------------------------------------------- constraint rows
+def test_jacobian_rows_are_point_velocities(oracle_mod):
+    """J_c v equals the contact frame times the velocity of the body point at the contact."""
+    m = robots.free_body("box", size=(0.1, 0.1, 0.1))
+    o = oracle_mod.Oracle(m)
+    qb = robots.quat_axis_angle((1, 2, 3), 0.3)
+    q = np.concatenate([[0, 0, 0.05], qb])
+    rng = np.random.default_rng(11)
+    v = rng.normal(size=6)
+    t = o.forward(q, v)
+    eps = 1e-6
+    tp = o.forward(q_plus(m, q, eps * v), np.zeros(6))
+    tm = o.forward(q_plus(m, q, -eps * v), np.zeros(6))
+    for ci in range(t["ncon"]):
+        p = t["pos"][ci]
+        local = t["xmat"][1].T @ (p - t["xpos"][1])
+        vel = ((tp["xpos"][1] + tp["xmat"][1] @ local) - (tm["xpos"][1] + tm["xmat"][1] @ local)) / (2 * eps)
+        F, mu = t["frame"][ci], t["mu"][ci]
+        Jc_v = F @ vel
+        rows = t["J"][4 * ci:4 * ci + 4] @ v
+        exp = [Jc_v[0] + mu * Jc_v[1], Jc_v[0] - mu * Jc_v[1], Jc_v[0] + mu * Jc_v[2], Jc_v[0] - mu * Jc_v[2]]
+        np.testing.assert_allclose(rows, exp, rtol=1e-7, atol=1e-8)
+
+
+def test_impedance_reference_and_regulariser(oracle_mod):
+    m = robots.free_body("sphere", size=(0.05,), friction=0.7)
+    o = oracle_mod.Oracle(m)
+    for depth, vz in ((2e-4, -0.3), (8e-4, 0.1), (3e-3, 0.0)):
+        q = np.array([0, 0, 0.05 - depth, 1, 0, 0, 0.0])
+        v = np.array([0.2, 0, vz, 0, 0.5, 0])
+        t = o.forward(q, v)
+        r = t["dist"][0]
+        imp = imp_ref(r)
+        Minv = np.linalg.inv(t["M"])
+        for e in range(4):
+            J = t["J"][e]
+            A = J @ Minv @ J
+            assert abs(t["Ahat"][e] - A) < 1e-13 * A
+            np.testing.assert_allclose(t["aref"][e], -B_REF * (J @ v) - K_REF * imp * r, rtol=1e-12)
+            np.testing.assert_allclose(t["D"][e], imp / ((1 - imp) * A), rtol=1e-12)
+
+
+def test_single_row_closed_form(oracle_mod):
+    """Frictionless contact: the four pyramid rows coincide, so the solve reduces to one row
+    with regulariser R/4: a = a0 + M^-1 Jn' f, f = max(0, (aref - Jn a0) / (A + R/4))."""
+    m = robots.free_body("sphere", size=(0.05,), friction=0.0, iterations=4)
+    o = oracle_mod.Oracle(m)
+    q = np.array([0, 0, 0.0496, 1, 0, 0, 0.0])
+    for vz in (-0.5, -0.05, 0.0, 0.3):
+        v = np.array([0, 0, vz, 0, 0, 0.0])
+        t = o.forward(q, v)
+        Jn = t["J"][0]
+        Minv = np.linalg.inv(t["M"])
+        A = Jn @ Minv @ Jn
+        R = 1.0 / t["D"][0]
+        f = max(0.0, (t["aref"][0] - Jn @ t["a0"]) / (A + R / 4))
+        np.testing.assert_allclose(t["qacc"], t["a0"] + Minv @ Jn * f, rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(t["efc_force"].sum(), f, rtol=1e-10, atol=1e-12)
+
+
+def _settle(o, m, q, steps, friction=None):
+    q = np.array(q, float)[None].copy()
+    v = np.zeros((1, o.nv)); ws = np.zeros((1, o.nv))
+    fr = None if friction is None else np.array([friction])
+    for _ in range(steps):
+        o.step(np.zeros((1, o.nu)), q, v, ws, friction=fr)
+    return q[0], v[0], ws[0]
+
+
+def test_resting_sphere_penetration_closed_form(oracle_mod):
+    """Steady state: 4 imp^2 k |r| / ((1 - imp) A) = m g, A = 1/m + mu^2 (1/m + rho^2 / I),
+    rho = radius + dist/2 the lever arm of the mid-surface contact point."""
+    m = robots.free_body("sphere", size=(0.05,), mass=1.0, pos=(0, 0, 0.05))
+    o = oracle_mod.Oracle(m)
+    q, v, ws = _settle(o, m, robots.qpos0(m), 400)
+    I = 0.4 * 1.0 * 0.05 ** 2
+
+    def resid(r):
+        imp = imp_ref(r)
+        A = 1.0 + (1.0 + (0.05 - r / 2) ** 2 / I)
+        return 4 * imp ** 2 * K_REF * r / ((1 - imp) * A) - 9.81
+
+    r_star = brentq(resid, 1e-6, 9e-4, xtol=1e-18)
+    assert abs(r_star - 3.98e-4) < 1e-6
+    assert abs((0.05 - q[2]) / r_star - 1) < 1e-6
+    assert np.abs(v).max() < 1e-9
+
+
+def test_resting_box_forces(oracle_mod):
+    m = robots.free_body("box", size=(0.1, 0.1, 0.1), mass=1.0, pos=(0, 0, 0.1))
+    o = oracle_mod.Oracle(m)
+    q, v, ws = _settle(o, m, robots.qpos0(m), 400)
+    t = o.forward(q, v, qacc_ws=ws)
+    assert t["ncon"] == 4
+    fn = t["cforce"][:, 0]
+    assert abs(fn.sum() / 9.81 - 1) < 1e-6
+    np.testing.assert_allclose(fn, fn.mean(), rtol=1e-6)
+    # tangential forces cancel (they need not vanish per corner: each pyramid edge row has its own A)
+    ft_world = sum(t["cforce"][i, 1] * t["frame"][i][1] + t["cforce"][i, 2] * t["frame"][i][2] for i in range(4))
+    assert np.linalg.norm(ft_world) < 1e-6
+    assert np.abs(v).max() < 1e-9
+
+
+@pytest.mark.parametrize("theta,mu,slides,h", [(math.radians(30), 1.0, False, 0.05),
+                                               (math.radians(30), 0.3, True, 0.005)])
+def test_inclined_plane_friction(oracle_mod, theta, mu, slides, h):
+    """Sticking cube (tan theta < mu) and sliding thin plate (tan theta > mu; thin so that the
+    friction torque about the centre of mass cannot rock it): a = g (sin theta - mu cos theta)."""
+    qg = robots.quat_axis_angle((1, 0, 0), theta)
+    n = rot(qg)[:, 2]
+    m = robots.free_body("box", size=(0.05 if not slides else 0.1, 0.05 if not slides else 0.1, h), mass=1.0,
+                         ground_quat=qg, friction=mu)
+    o = oracle_mod.Oracle(m)
+    x = n * (h - 2e-4)
+    q0 = np.concatenate([x, qg])
+    q, v, ws = _settle(o, m, q0, 100)
+    down = np.cross(n, np.cross([0, 0, -1.0], n))
+    down /= np.linalg.norm(down)
+    s0, v0 = q[:3] @ down, v[:3] @ down
+    dt = m["opt"]["timestep"]
+    q, v, ws = q[None].copy(), v[None].copy(), ws[None].copy()
+    for _ in range(100):
+        o.step(np.zeros((1, 0)), q, v, ws)
+    v1 = v[0, :3] @ down
+    if slides:
+        acc = (v1 - v0) / (100 * dt)
+        exp = 9.81 * (math.sin(theta) - mu * math.cos(theta))
+        assert abs(acc / exp - 1) < 0.02
+    else:
+        # the soft friction rows act through aref = -b v, so a sticking box creeps at a small
+        # constant speed while the contact forces exactly balance gravity
+        assert abs(v1 - v0) < 1e-7 and 0 <= v1 < 1e-2
+        t = o.forward(q[0], v[0], qacc_ws=ws[0])
+        F = sum(t["cforce"][i] @ t["frame"][i] for i in range(t["ncon"]))
+        np.testing.assert_allclose(F, [0, 0, 9.81], atol=1e-6 * 9.81)
+
+
+# ---------------------------------------------------------------- Newton solver
+def _problem(t):
+    M, a0, J, aref, D = t["M"], t["a0"], t["J"], t["aref"], t["D"]
+
+    def f(a):
+        jar = J @ a - aref
+        return 0.5 * (a - a0) @ M @ (a - a0) + 0.5 * np.sum(D * np.minimum(jar, 0) ** 2)
+
+    def g(a):
+        jar = J @ a - aref
+        return M @ (a - a0) + J.T @ (D * np.minimum(jar, 0))
+
+    return f, g
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_newton_converged_matches_scipy(oracle_mod, seed):
+    rng = np.random.default_rng(100 + seed)
+    m = robots.free_body("box", size=(0.1, 0.07, 0.05), mass=1.3, friction=0.8)
+    o = oracle_mod.Oracle(m)
+    o.set_mode("converged")
+    qb = rng.normal(size=4); qb /= np.linalg.norm(qb)
+    q = np.concatenate([[0, 0, 0.05], qb])
+    v = rng.normal(0, 0.5, 6)
+    t = o.forward(q, v)
+    assert t["ncon"] >= 1
+    f, g = _problem(t)
+    res = minimize(f, t["a0"], jac=g, method="BFGS", options={"gtol": 1e-12, "maxiter": 10000})
+    scale = np.abs(res.x).max() + 1
+    np.testing.assert_allclose(t["qacc"], res.x, atol=1e-6 * scale)
+    assert f(t["qacc"]) <= f(res.x) + 1e-9 * abs(f(res.x))
+    assert np.linalg.norm(g(t["qacc"])) < 1e-8 * o.meaninertia * o.nv * 10
+    assert np.all(t["efc_force"] >= 0)
+    # mirror mode with at most 4 iterations never does worse than its starting point
+    o.set_mode("mirror")
+    t4 = o.forward(q, v)
+    assert t4["niter"] <= 4 and f(t4["qacc"]) <= f(t4["a0"]) + 1e-12
+
+
+def test_warm_start_at_optimum_is_kept(oracle_mod):
+    m = robots.free_body("box", size=(0.1, 0.07, 0.05), mass=1.3, friction=0.8)
+    o = oracle_mod.Oracle(m)
+    o.set_mode("converged")
+    q = np.concatenate([[0, 0, 0.04], robots.quat_axis_angle((1, 1, 0), 0.2)])
+    v = np.array([0.1, 0, -0.2, 0, 0.3, 0])
+    t = o.forward(q, v)
+    o.set_mode("mirror")
+    t2 = o.forward(q, v, qacc_ws=t["qacc"])
+    assert t2["niter"] == 0
+    np.testing.assert_allclose(t2["qacc"], t["qacc"], rtol=0, atol=0)
+
+
+def test_no_contact_means_smooth_acceleration(oracle_mod):
+    m = robots.quadruped()
+    o = oracle_mod.Oracle(m)
+    q = robots.qpos0(m); q[2] = 2.0
+    t = o.forward(q, np.ones(18) * 0.1, ctrl=np.full(12, 0.3))
+    assert t["ncon"] == 0
+    np.testing.assert_array_equal(t["qacc"], t["a0"])
+    np.testing.assert_allclose(t["M"] @ t["a0"], t["tau"] - t["bias"], rtol=1e-12, atol=1e-12)
+    # position actuators: tau = kp (ctrl - q) - kd v on each driven hinge
+    np.testing.assert_allclose(t["tau"][6:], 20 * (0.3 - q[7:]) - 0.5 * 0.1, rtol=1e-15)

@@ -1,0 +1,103 @@
+"""Seeded synthetic inputs: initial states, control tables and per-world parameters.
+
+World ``w`` of workload ``c`` draws from ``numpy.random.Generator(PCG64(SeedSequence([c, w, s])))``
+with stream ``s`` = 0 for the initial state, 1 for controls, 2 for per-world
+parameters, so a world's inputs never depend on how many worlds run beside it.
+Values are drawn in float64 and rounded to float32; both the oracle and the HIP
+path consume the same float32 values (the oracle widens them to float64).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import robots
+
+WORKLOAD_IDS = {"chain3": 1, "quadruped": 2, "humanoid": 3, "arm_box": 4}
+CTRL_PERIOD = 20          # env steps between control resamples
+CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3}
+
+
+def rng(workload_id: int, world: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(workload_id), int(world), int(stream)])))
+
+
+def _hinge_qadr(model: dict) -> list[int]:
+    out, adr = [], 0
+    for j in model["joints"]:
+        if j["type"] == "hinge":
+            out.append(adr)
+            adr += 1
+        else:
+            adr += 7
+    return out
+
+
+def initial_state(model: dict, name: str, worlds, workload_id: int | None = None):
+    """(qpos[n, nq], qvel[n, nv]) float32 for the given world ids."""
+    wid = WORKLOAD_IDS.get(name, 0) if workload_id is None else workload_id
+    d = robots.dims(model)
+    q0 = robots.qpos0(model)
+    hq = _hinge_qadr(model)
+    worlds = list(worlds)
+    qpos = np.zeros((len(worlds), d["nq"]), np.float64)
+    qvel = np.zeros((len(worlds), d["nv"]), np.float64)
+    for i, w in enumerate(worlds):
+        g = rng(wid, w, 0)
+        qpos[i] = q0
+        if name == "chain3":
+            qpos[i, :] = g.uniform(-math.pi, math.pi, d["nq"])
+            qvel[i, :] = g.normal(0.0, 0.5, d["nv"])
+        elif name == "quadruped":
+            qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))
+        elif name == "humanoid":
+            qpos[i, hq] = g.uniform(-0.05, 0.05, len(hq))
+        elif name == "arm_box":
+            qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))
+        else:
+            raise KeyError(name)
+    return qpos.astype(np.float32), qvel.astype(np.float32)
+
+
+def ctrl_table(model: dict, name: str, worlds, nseg: int, workload_id: int | None = None) -> np.ndarray:
+    """Control targets [nseg, n, nu] float32; segment k is held for env steps [k*20, (k+1)*20)."""
+    wid = WORKLOAD_IDS.get(name, 0) if workload_id is None else workload_id
+    nu = len(model["actuators"])
+    worlds = list(worlds)
+    out = np.zeros((nseg, len(worlds), nu), np.float64)
+    std = CTRL_STD.get(name, 0.0)
+    if nu and std > 0:
+        for i, w in enumerate(worlds):
+            out[:, i, :] = rng(wid, w, 1).normal(0.0, std, (nseg, nu))
+    return out.astype(np.float32)
+
+
+def world_params(model: dict, name: str, worlds, workload_id: int | None = None):
+    """Per-world (friction[n], mass_scale[n, nbody]) float32, or None where the model shares the field."""
+    wid = WORKLOAD_IDS.get(name, 0) if workload_id is None else workload_id
+    nb = len(model["bodies"])
+    worlds = list(worlds)
+    fr = ms = None
+    if model["per_world"].get("friction") or model["per_world"].get("mass_scale"):
+        fr = np.zeros(len(worlds), np.float64)
+        ms = np.ones((len(worlds), nb), np.float64)
+        for i, w in enumerate(worlds):
+            g = rng(wid, w, 2)
+            fr[i] = g.uniform(0.3, 1.2)
+            ms[i, 1:] = g.uniform(0.8, 1.2, nb - 1)
+        fr = fr.astype(np.float32) if model["per_world"].get("friction") else None
+        ms = ms.astype(np.float32) if model["per_world"].get("mass_scale") else None
+    return fr, ms
+
+
+def workload(name: str, nworlds: int, nsteps: int, first_world: int = 0):
+    """Everything one benchmark workload needs: model, initial state, control table, per-world params."""
+    model = robots.by_name(name)
+    worlds = range(first_world, first_world + nworlds)
+    qpos, qvel = initial_state(model, name, worlds)
+    nseg = max(1, -(-nsteps // CTRL_PERIOD))
+    ctrl = ctrl_table(model, name, worlds, nseg)
+    fr, ms = world_params(model, name, worlds)
+    return dict(model=model, name=name, qpos=qpos, qvel=qvel, ctrl=ctrl, friction=fr, mass_scale=ms,
+                nsteps=nsteps, worlds=list(worlds))
