@@ -1,0 +1,156 @@
+/*
+ * rbstep -- batched rigid-body physics step for MI355X (gfx950).
+ *
+ * The operation: advance N independent worlds of one robot model by one environment step,
+ * i.e. K physics substeps with the controls held (paper, section "Manager-Based API",
+ * pipeline step "Simulate": d decimation substeps per env step).  The model is static and
+ * shared by all worlds; the state has a leading world dimension; selected model fields
+ * (friction, body mass scale) can be expanded to one value per world (paper, section
+ * "Architecture", paragraph on the GPU physics backend).  A substep performs forward
+ * kinematics, the joint-space inertia and its factorisation, bias forces, plane collision,
+ * the soft-contact Newton solve and semi-implicit Euler integration.
+ *
+ * Conventions
+ *   - Units SI; quaternions (w, x, y, z); body 0 is the world; parent[b] < b.
+ *   - Free joint qpos = [pos(3, world), quat(4)], qvel = [linear velocity of the body
+ *     origin (world, 3), angular velocity (body frame, 3)].  Hinge qpos is the angle.
+ *   - Every device array is row-major with the world index leading, float32 unless noted,
+ *     and belongs to the caller (e.g. a torch tensor); the library never frees it.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the default stream).  Every
+ *     function that takes a stream only enqueues work on it and returns; the caller
+ *     synchronises (e.g. through torch).  Buffers must stay valid until that work ends.
+ *
+ * Errors
+ *   Functions return RB_OK (0) or a negative code; rb_last_error() then returns a message
+ *   (thread-local).  Argument and model validation errors are reported synchronously;
+ *   an asynchronous device fault surfaces as RB_EHIP on a later call.  Numerical trouble is
+ *   data, not an error: it is reported per world in the status word (RB_STATUS_*).
+ */
+#ifndef RBSTEP_H
+#define RBSTEP_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RB_OK 0
+#define RB_EINVAL (-1)   /* invalid argument or model */
+#define RB_ENOMEM (-2)   /* device allocation failed */
+#define RB_EHIP (-3)     /* HIP runtime error (including earlier asynchronous faults) */
+#define RB_EBUDGET (-4)  /* request exceeds the configured device-memory budget */
+#define RB_ESTATE (-5)   /* object used in a state that does not allow the call */
+
+/* per-world status bits */
+#define RB_STATUS_NONFINITE 1u   /* non-finite qpos/qvel/qacc: the world is frozen until reset */
+#define RB_STATUS_ITERCAP 2u     /* the Newton solve ran its full iteration budget (informational) */
+#define RB_STATUS_CONOVERFLOW 4u /* more contacts than the per-world capacity; the extra ones
+                                    (last in pair order) were dropped for this substep */
+
+enum { RB_GEOM_PLANE = 0, RB_GEOM_SPHERE = 1, RB_GEOM_CAPSULE = 2, RB_GEOM_BOX = 3 };
+enum { RB_JNT_FREE = 0, RB_JNT_HINGE = 1 };
+enum { RB_ACT_POSITION = 0, RB_ACT_MOTOR = 1 };
+enum { RB_PARAM_FRICTION = 0, RB_PARAM_MASS_SCALE = 1 };
+
+/* Host-side model description, float64, owned by the caller (copied by rb_model_create).
+ * Bodies [nbody] (body 0 = world), joints [njnt] (listed in body order, at most one per
+ * body, free joints only on children of the world), geoms [ngeom], actuators [nu]
+ * (hinge joints only).  Sizes: sphere (r), capsule (r, half-length along local z), box
+ * (half-sizes); a plane's normal is its local +z and it must sit on a static body. */
+typedef struct rb_model_desc {
+    int32_t nbody, njnt, ngeom, nu;
+    const int32_t* body_parent;
+    const double *body_pos, *body_quat, *body_ipos, *body_iquat, *body_mass, *body_inertia;
+    const int32_t *jnt_type, *jnt_body;
+    const double *jnt_pos, *jnt_axis, *jnt_armature;
+    const int32_t *geom_type, *geom_body, *geom_contype, *geom_conaffinity;
+    const double *geom_pos, *geom_quat, *geom_size, *geom_friction, *geom_margin;
+    const int32_t *act_type, *act_joint;
+    const double *act_kp, *act_kd, *act_gear;
+    double timestep;        /* physics substep, s */
+    int32_t nsubsteps;      /* K substeps per env step, controls held */
+    double gravity[3];
+    int32_t iterations;     /* Newton iteration budget */
+    double tolerance;       /* Newton tolerance on the scaled gradient and improvement */
+    double solref[2];       /* (time constant, damping ratio) */
+    double solimp[5];       /* (dmin, dmax, width, midpoint, power) */
+    int32_t friction_per_world, mass_scale_per_world;
+} rb_model_desc;
+
+typedef struct rb_model rb_model;
+typedef struct rb_batch rb_batch;
+
+typedef struct rb_model_info {
+    int32_t nq, nv, nu, nbody, ngeom, npair;
+    int32_t maxcon;          /* static per-world contact bound of the model */
+    int32_t max_depth;       /* longest chain of dofs from the root */
+    int32_t lds_bytes;       /* on-chip memory one world uses during a step */
+    double meaninertia;
+} rb_model_info;
+
+/* Contact output of the last substep, struct of device arrays with `cap` slots per world
+ * (cap = the batch's contact capacity, rb_batch_contact_capacity()).  Any pointer may be
+ * NULL to skip that field.  Contacts appear in collision-pair order; slots >= ncon are
+ * left untouched. */
+typedef struct rb_contacts {
+    int32_t* ncon;     /* [n] */
+    int32_t* geom;     /* [n, cap, 2]  (g1, g2), normal points from g1 to g2 */
+    int32_t* feature;  /* [n, cap]     0 sphere; 0/1 capsule -z/+z end; 0..7 box vertex */
+    float* dist;       /* [n, cap]     signed distance, < 0 when penetrating */
+    float* pos;        /* [n, cap, 3]  contact point (midway between the surfaces) */
+    float* frame;      /* [n, cap, 9]  rows: normal, tangent 1, tangent 2 */
+    float* force;      /* [n, cap, 3]  (normal, tangent 1, tangent 2) contact force */
+} rb_contacts;
+
+const char* rb_last_error(void);
+
+/* Validate and compile a model; uploads its constants to the current HIP device.
+ * Rejects (RB_EINVAL): parent >= child, non-positive mass or inertia violating the
+ * triangle inequality, non-unit quaternions, misplaced joints, unknown types,
+ * collision pairs other than plane-{sphere, capsule, box}, pairs whose bodies can both
+ * move, more than 64 dofs, 64 collision pairs or a dof chain deeper than 32. */
+int rb_model_create(const rb_model_desc* desc, rb_model** out);
+void rb_model_destroy(rb_model* model);
+int rb_model_info_get(const rb_model* model, rb_model_info* out);
+
+/* A batch of `capacity` world slots of one model: owns each world's warm start (qacc of
+ * the previous substep), status word, per-world parameters and contact capacity.
+ * contact_capacity <= 0 selects min(model maxcon, 64); at most 64.  Worlds start with a
+ * zero warm start, status 0, friction = model friction and mass scale 1. */
+int rb_batch_create(const rb_model* model, int32_t capacity, int32_t contact_capacity, rb_batch** out);
+void rb_batch_destroy(rb_batch* batch);
+int32_t rb_batch_contact_capacity(const rb_batch* batch);
+
+/* Per-world parameters for slots [0, n): RB_PARAM_FRICTION takes [n] floats (friction of
+ * every contact in the world; the model must have friction_per_world), RB_PARAM_MASS_SCALE
+ * [n, nbody] floats (scales each body's mass and rotational inertia; the model must have
+ * mass_scale_per_world).  Device pointer; copied on the stream. */
+int rb_batch_set_params(rb_batch* batch, int32_t field, int32_t n, const float* dev_vals, void* hip_stream);
+
+/* Reset n worlds named by dev_ids [n] (int32, device): clear their status and set their
+ * warm start from dev_qacc_ws [n, nv] (device; NULL = zero). */
+int rb_world_reset(rb_batch* batch, const int32_t* dev_ids, int32_t n, const float* dev_qacc_ws, void* hip_stream);
+
+/* Copy the warm start [n, nv] and status [n] of slots [0, n) out (either may be NULL). */
+int rb_get_state(const rb_batch* batch, int32_t n, float* dev_qacc_ws, uint32_t* dev_status, void* hip_stream);
+
+/* One env step (K substeps) of slots [0, n).  dev_qpos [n, nq] and dev_qvel [n, nv] are
+ * read and overwritten in place; dev_ctrl [n, nu] is held for the K substeps (NULL when
+ * nu = 0).  contacts (nullable) receives the last substep's contacts; dev_status [n]
+ * (nullable) receives each world's status word.  A world with RB_STATUS_NONFINITE set is
+ * not advanced. */
+int rb_step(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
+            const rb_contacts* contacts, uint32_t* dev_status, void* hip_stream);
+
+/* Diagnostic taps of the first substep of one step of slots [0, n), for parity checks:
+ * the same computation as rb_step (and it advances the state the same way), plus per world
+ * dev_M [n, nv, nv] joint-space inertia, dev_bias [n, nv] bias forces c(q, v),
+ * dev_a0 [n, nv] smooth acceleration, dev_qacc [n, nv] constrained acceleration of the
+ * first substep, dev_efc [n, cap, 4, 3] per pyramid row (aref, D, A-hat).  Any may be NULL. */
+int rb_step_taps(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
+                 const rb_contacts* contacts, uint32_t* dev_status, float* dev_M, float* dev_bias,
+                 float* dev_a0, float* dev_qacc, float* dev_efc, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

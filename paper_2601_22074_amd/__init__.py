@@ -1,0 +1,6 @@
+"""Batched rigid-body physics step for MI355X (gfx950): HIP kernels behind a C ABI.
+
+``rbstep`` is the ctypes binding of ``librbstep.so`` (see ``include/rbstep.h``).
+"""
+from .rbstep import (Batch, Contacts, Model, RbError, PARAM_FRICTION, PARAM_MASS_SCALE,  # noqa: F401
+                     STATUS_CONOVERFLOW, STATUS_ITERCAP, STATUS_NONFINITE, lib)

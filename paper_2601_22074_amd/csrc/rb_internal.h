@@ -1,0 +1,114 @@
+// Internal layout shared by the host runtime and the gfx950 step kernel.
+//
+// A compiled model is one device blob of 4-byte words holding the tables below; the kernel
+// receives a DevModel by value with pointers into that blob.  Per-world working state lives
+// in LDS (one wavefront per world); its layout (offsets in floats) is part of DevModel.
+#pragma once
+#include <stdint.h>
+
+#define RB_WAVE 64
+#define RB_MAX_DOF 64
+#define RB_MAX_PAIR 64
+#define RB_MAX_CON 64
+
+struct DevModel {
+    // sizes
+    int nbody, nv, nq, nu, njnt, npair, ncap, maxd;
+    int nblevel;   // body levels 1..nblevel (level 0 = world)
+    int ndlevel;   // dof depth levels 1..ndlevel
+    int K, maxiter;
+    int fr_pw, ms_pw;
+    int nM;        // packed tree-sparse matrix entries
+    // options (float32)
+    float dt, grav[3];
+    float tol_scale;          // tolerance * meaninertia * nv
+    float kref, bref;         // reference-acceleration stiffness and damping
+    float dmin, dmax, width, mid, power;
+    // bodies [nbody]
+    const int* body_parent;
+    const int* body_jtype;     // -1 none, RB_JNT_FREE, RB_JNT_HINGE
+    const int* body_qadr;
+    const int* body_dadr;
+    const int* body_lastdof;   // deepest dof of the body's chain, -1 if the body cannot move
+    const int* body_depth;     // number of dofs on the chain (0 if static)
+    const int* body_level;
+    const float* body_pos;     // [3]
+    const float* body_quat;    // [4]
+    const float* body_ipos;    // [3]
+    const float* body_iquat;   // [4]
+    const float* body_mass;
+    const float* body_inertia; // [3]
+    const float* body_jpos;    // [3] joint anchor in the body frame
+    const float* body_jaxis;   // [3] unit hinge axis in the body frame
+    const uint64_t* body_chainmask;  // bit i set iff dof i lies on the body's chain
+    const int* level_start;    // [nblevel + 2] CSR into level_body, levels 0..nblevel
+    const int* level_body;
+    const int* child_start;    // [nbody + 1] CSR into child_list
+    const int* child_list;
+    // dofs [nv]
+    const int* dof_body;
+    const int* dof_depth;      // chain length including the dof itself
+    const int* dof_rowadr;     // start of the dof's row in the packed matrices
+    const int* dof_anc;        // [nv * maxd] dof at chain position t (root first), -1 padded
+    const int* desc_start;     // [nv + 1] CSR of strict descendants
+    const int* desc_list;
+    const int* dlevel_start;   // [ndlevel + 2] CSR of dofs by depth, depths 1..ndlevel
+    const int* dlevel_dof;
+    const float* dof_armature;
+    const int* act_start;      // [nv + 1] CSR of actuators driving each dof
+    const int* act_list;
+    const int* act_type;
+    const int* act_qadr;
+    const float* act_kp;
+    const float* act_kd;
+    const float* act_gear;
+    // joints [njnt]
+    const int* jnt_type;
+    const int* jnt_qadr;
+    const int* jnt_dadr;
+    // collision pairs [npair], in (g1, g2) order; g1 is the plane
+    const int* pair_g1;
+    const int* pair_g2;
+    const int* pair_type;      // geom type of g2
+    const int* pair_body;      // the body that can move
+    const int* pair_cap;       // contacts the pair can produce
+    const float* pair_sigma;   // +1 if the moving body carries g2, -1 if it carries g1
+    const float* pair_mu;      // friction when it is not per world
+    const float* pair_margin;
+    const int* geom_body;
+    const float* geom_pos;     // [3]
+    const float* geom_quat;    // [4]
+    const float* geom_size;    // [3]
+    // LDS layout (offsets in floats from the world's base)
+    int o_q, o_v, o_ctrl, o_aws, o_mscale;
+    int o_xpos, o_xquat, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
+    int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp;
+    int o_M, o_H, o_misc;
+    int lds_floats;
+};
+
+// Per-world resident state owned by a batch.
+struct DevWorlds {
+    float* qacc_ws;         // [cap, nv]
+    uint32_t* status;       // [cap]
+    float* friction;        // [cap]
+    float* mass_scale;      // [cap, nbody]
+};
+
+struct DevContactsOut {
+    int32_t* ncon;
+    int32_t* geom;
+    int32_t* feature;
+    float* dist;
+    float* pos;
+    float* frame;
+    float* force;
+};
+
+struct DevTaps {
+    float* M;
+    float* bias;
+    float* a0;
+    float* qacc;
+    float* efc;
+};

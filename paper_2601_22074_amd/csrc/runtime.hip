@@ -1,0 +1,638 @@
+// Host runtime of librbstep: model validation and compilation into device tables, batches of
+// world slots, and the C ABI declared in include/rbstep.h.
+//
+// The model pipeline mirrors the paper's scene path (section "Architecture", paragraph on
+// the scene pipeline: a description is compiled on the CPU and transferred to the GPU): a
+// host description is validated, flattened into structure-of-arrays tables (dof chains,
+// tree levels, collision pairs, LDS layout) and uploaded once; every world shares them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rb_internal.h"
+#include "rbstep.h"
+
+hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
+                          const DevContactsOut* co, uint32_t* status_out, const DevTaps* taps, hipStream_t stream);
+hipError_t rb_launch_reset(int nv, const int32_t* ids, int n, const float* qacc_ws, DevWorlds W, int capacity,
+                           hipStream_t stream);
+hipError_t rb_launch_fill(float* dst, float value, size_t count, hipStream_t stream);
+
+namespace {
+
+thread_local std::string g_err;
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return RB_EHIP;
+}
+
+// ------------------------------------------------------------------ host-side double math
+void qmul_d(const double* a, const double* b, double* o) {
+    double t[4] = {a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3],
+                   a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2],
+                   a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1],
+                   a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0]};
+    std::memcpy(o, t, sizeof t);
+}
+void qmat_d(const double* q, double* R) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+void mv_d(const double* R, const double* v, double* o) {
+    double t[3];
+    for (int i = 0; i < 3; i++) t[i] = R[3 * i] * v[0] + R[3 * i + 1] * v[1] + R[3 * i + 2] * v[2];
+    std::memcpy(o, t, sizeof t);
+}
+void cross_d(const double* a, const double* b, double* o) {
+    double t[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    std::memcpy(o, t, sizeof t);
+}
+
+// blob builder: 4-byte words, 8-byte aligned sections
+struct Blob {
+    std::vector<uint32_t> words;
+    size_t add_i(const std::vector<int>& v) {
+        align();
+        size_t off = words.size();
+        for (int x : v) words.push_back((uint32_t)x);
+        if (v.empty()) words.push_back(0);
+        return off;
+    }
+    size_t add_f(const std::vector<double>& v) {
+        align();
+        size_t off = words.size();
+        for (double x : v) {
+            float f = (float)x;
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            words.push_back(u);
+        }
+        if (v.empty()) words.push_back(0);
+        return off;
+    }
+    size_t add_u64(const std::vector<uint64_t>& v) {
+        align();
+        size_t off = words.size();
+        for (uint64_t x : v) {
+            words.push_back((uint32_t)(x & 0xffffffffu));
+            words.push_back((uint32_t)(x >> 32));
+        }
+        if (v.empty()) { words.push_back(0); words.push_back(0); }
+        return off;
+    }
+    void align() {
+        while (words.size() % 2) words.push_back(0);
+    }
+};
+
+}  // namespace
+
+struct rb_model {
+    DevModel dm;
+    void* blob = nullptr;
+    int device = 0;
+    int maxcon_static = 0;
+    double meaninertia = 1.0;
+    int nv_ = 0, nq_ = 0, nu_ = 0, nbody_ = 0, ngeom_ = 0;
+};
+
+struct rb_batch {
+    const rb_model* model = nullptr;
+    int capacity = 0;
+    DevWorlds W{};
+    DevModel dm;   // model copy with this batch's contact capacity
+    void* mem = nullptr;
+};
+
+namespace {
+
+// Compile a description into host tables; returns RB_OK or RB_EINVAL with a message.
+int compile_model(const rb_model_desc* d, rb_model* M) {
+    const int nb = d->nbody, nj = d->njnt, ng = d->ngeom, nu = d->nu;
+    if (nb < 2) return fail(RB_EINVAL, "model needs at least one body besides the world");
+    if (nj < 1) return fail(RB_EINVAL, "model needs at least one joint");
+    if (ng < 0 || nu < 0) return fail(RB_EINVAL, "negative sizes");
+    auto P = [&](int b) { return d->body_parent[b]; };
+    for (int b = 1; b < nb; b++)
+        if (P(b) < 0 || P(b) >= b) return fail(RB_EINVAL, "body parent must precede the body");
+    for (int b = 0; b < nb; b++) {
+        const double* q = d->body_quat + 4 * b;
+        double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        if (std::fabs(n - 1) > 1e-6) return fail(RB_EINVAL, "body quaternion is not unit");
+        const double* iq = d->body_iquat + 4 * b;
+        n = std::sqrt(iq[0] * iq[0] + iq[1] * iq[1] + iq[2] * iq[2] + iq[3] * iq[3]);
+        if (b > 0 && std::fabs(n - 1) > 1e-6) return fail(RB_EINVAL, "inertia quaternion is not unit");
+        if (b == 0) continue;
+        if (!(d->body_mass[b] > 0)) return fail(RB_EINVAL, "body mass must be positive");
+        const double* I = d->body_inertia + 3 * b;
+        if (!(I[0] > 0 && I[1] > 0 && I[2] > 0)) return fail(RB_EINVAL, "principal inertias must be positive");
+        const double tol = 1 + 1e-12;
+        if (I[0] + I[1] < I[2] / tol || I[1] + I[2] < I[0] / tol || I[0] + I[2] < I[1] / tol)
+            return fail(RB_EINVAL, "inertia violates the triangle inequality");
+    }
+    // joints
+    std::vector<int> bjnt(nb, -1), jtype(nj), jbody(nj), jq(nj), jd(nj);
+    int nq = 0, nv = 0, last = 0;
+    for (int j = 0; j < nj; j++) {
+        int b = d->jnt_body[j];
+        if (b <= 0 || b >= nb) return fail(RB_EINVAL, "joint on an invalid body");
+        if (bjnt[b] >= 0) return fail(RB_EINVAL, "more than one joint on a body");
+        if (b < last) return fail(RB_EINVAL, "joints must be listed in body order");
+        last = b;
+        bjnt[b] = j;
+        jtype[j] = d->jnt_type[j];
+        jbody[j] = b;
+        jq[j] = nq;
+        jd[j] = nv;
+        if (jtype[j] == RB_JNT_FREE) {
+            if (P(b) != 0) return fail(RB_EINVAL, "a free joint must be on a child of the world");
+            nq += 7;
+            nv += 6;
+        } else if (jtype[j] == RB_JNT_HINGE) {
+            const double* ax = d->jnt_axis + 3 * j;
+            if (!(std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]) > 0))
+                return fail(RB_EINVAL, "hinge axis is zero");
+            nq += 1;
+            nv += 1;
+        } else {
+            return fail(RB_EINVAL, "unknown joint type");
+        }
+    }
+    if (nv > RB_MAX_DOF) return fail(RB_EINVAL, "more than 64 dofs");
+    // dof tree
+    std::vector<int> dof_body(nv), dof_parent(nv), dof_depth(nv), blast(nb, -1), bdepth(nb, 0);
+    for (int b = 1; b < nb; b++) {
+        int p = P(b);
+        int parent_dof = blast[p];
+        int j = bjnt[b];
+        if (j >= 0) {
+            int nd = jtype[j] == RB_JNT_FREE ? 6 : 1;
+            for (int k = 0; k < nd; k++) {
+                int i = jd[j] + k;
+                dof_body[i] = b;
+                dof_parent[i] = k == 0 ? parent_dof : i - 1;
+                dof_depth[i] = dof_parent[i] < 0 ? 1 : dof_depth[dof_parent[i]] + 1;
+            }
+            blast[b] = jd[j] + nd - 1;
+        } else {
+            blast[b] = parent_dof;
+        }
+        bdepth[b] = blast[b] < 0 ? 0 : dof_depth[blast[b]];
+    }
+    int maxd = 0;
+    for (int i = 0; i < nv; i++) maxd = std::max(maxd, dof_depth[i]);
+    if (maxd > 32) return fail(RB_EINVAL, "dof chain deeper than 32");
+    int tmaxd = maxd <= 8 ? 8 : (maxd <= 16 ? 16 : 32);
+    std::vector<int> anc((size_t)nv * tmaxd, -1), rowadr(nv);
+    int nM = 0;
+    for (int i = 0; i < nv; i++) {
+        rowadr[i] = nM;
+        nM += dof_depth[i];
+        for (int k = i, t = dof_depth[i] - 1; k >= 0; k = dof_parent[k], t--) anc[(size_t)i * tmaxd + t] = k;
+    }
+    std::vector<int> desc_start(nv + 1, 0), desc_list;
+    for (int i = 0; i < nv; i++) {
+        desc_start[i] = (int)desc_list.size();
+        for (int k = i + 1; k < nv; k++)
+            if (dof_depth[k] > dof_depth[i] && anc[(size_t)k * tmaxd + dof_depth[i] - 1] == i) desc_list.push_back(k);
+    }
+    desc_start[nv] = (int)desc_list.size();
+    std::vector<int> dl_start(maxd + 2, 0), dl_dof;
+    for (int lev = 0; lev <= maxd + 1; lev++) {
+        dl_start[lev] = (int)dl_dof.size();
+        for (int i = 0; i < nv; i++)
+            if (dof_depth[i] == lev) dl_dof.push_back(i);
+    }
+    // body tree levels and children
+    std::vector<int> blevel(nb, 0);
+    int nblevel = 0;
+    for (int b = 1; b < nb; b++) {
+        blevel[b] = blevel[P(b)] + 1;
+        nblevel = std::max(nblevel, blevel[b]);
+    }
+    std::vector<int> lv_start(nblevel + 2, 0), lv_body;
+    for (int lev = 0; lev <= nblevel + 1; lev++) {
+        lv_start[lev] = (int)lv_body.size();
+        for (int b = 0; b < nb; b++)
+            if (blevel[b] == lev) lv_body.push_back(b);
+    }
+    std::vector<int> ch_start(nb + 1, 0), ch_list;
+    for (int b = 0; b < nb; b++) {
+        ch_start[b] = (int)ch_list.size();
+        for (int c = b + 1; c < nb; c++)
+            if (P(c) == b) ch_list.push_back(c);
+    }
+    ch_start[nb] = (int)ch_list.size();
+    std::vector<uint64_t> cmask(nb, 0);
+    for (int b = 1; b < nb; b++) {
+        if (blast[b] < 0) continue;
+        for (int t = 0; t < bdepth[b]; t++) cmask[b] |= 1ull << anc[(size_t)blast[b] * tmaxd + t];
+    }
+    // actuators grouped by dof
+    std::vector<std::vector<int>> by_dof(nv);
+    std::vector<int> atype(nu), aqadr(nu);
+    std::vector<double> akp(nu), akd(nu), agear(nu);
+    for (int u = 0; u < nu; u++) {
+        int j = d->act_joint[u];
+        if (j < 0 || j >= nj) return fail(RB_EINVAL, "actuator on an invalid joint");
+        if (jtype[j] != RB_JNT_HINGE) return fail(RB_EINVAL, "actuators drive hinge joints only");
+        if (d->act_type[u] != RB_ACT_POSITION && d->act_type[u] != RB_ACT_MOTOR)
+            return fail(RB_EINVAL, "unknown actuator type");
+        atype[u] = d->act_type[u];
+        aqadr[u] = jq[j];
+        akp[u] = d->act_kp[u];
+        akd[u] = d->act_kd[u];
+        agear[u] = d->act_gear[u];
+        by_dof[jd[j]].push_back(u);
+    }
+    std::vector<int> act_start(nv + 1, 0), act_list;
+    for (int i = 0; i < nv; i++) {
+        act_start[i] = (int)act_list.size();
+        for (int u : by_dof[i]) act_list.push_back(u);
+    }
+    act_start[nv] = (int)act_list.size();
+    // collision pairs
+    std::vector<int> movable(nb, 0);
+    for (int b = 1; b < nb; b++) movable[b] = movable[P(b)] || bjnt[b] >= 0;
+    for (int g = 0; g < ng; g++) {
+        int t = d->geom_type[g], b = d->geom_body[g];
+        if (t < RB_GEOM_PLANE || t > RB_GEOM_BOX) return fail(RB_EINVAL, "unknown geom type");
+        if (b < 0 || b >= nb) return fail(RB_EINVAL, "geom on an invalid body");
+        if (t == RB_GEOM_PLANE && movable[b]) return fail(RB_EINVAL, "a plane must be on a static body");
+        const double* q = d->geom_quat + 4 * g;
+        if (std::fabs(std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) - 1) > 1e-6)
+            return fail(RB_EINVAL, "geom quaternion is not unit");
+    }
+    struct Pair { int g1, g2; };
+    std::vector<Pair> pairs;
+    for (int a = 0; a < ng; a++)
+        for (int b = a + 1; b < ng; b++) {
+            int ba = d->geom_body[a], bb = d->geom_body[b];
+            if (ba == bb) continue;
+            if ((P(ba) == bb && bb != 0) || (P(bb) == ba && ba != 0)) continue;
+            if (((d->geom_contype[a] & d->geom_conaffinity[b]) | (d->geom_contype[b] & d->geom_conaffinity[a])) == 0)
+                continue;
+            if (!movable[ba] && !movable[bb]) continue;
+            if (movable[ba] && movable[bb]) return fail(RB_EINVAL, "contacts between two moving bodies are not supported");
+            int g1 = a, g2 = b;
+            if (d->geom_type[g2] < d->geom_type[g1]) std::swap(g1, g2);
+            if (d->geom_type[g1] != RB_GEOM_PLANE || d->geom_type[g2] == RB_GEOM_PLANE)
+                return fail(RB_EINVAL, "unsupported collision pair (only plane vs sphere, capsule, box)");
+            pairs.push_back({g1, g2});
+        }
+    std::sort(pairs.begin(), pairs.end(), [](const Pair& x, const Pair& y) {
+        return x.g1 != y.g1 ? x.g1 < y.g1 : x.g2 < y.g2;
+    });
+    int npair = (int)pairs.size();
+    if (npair > RB_MAX_PAIR) return fail(RB_EINVAL, "more than 64 collision pairs");
+    std::vector<int> pg1(npair), pg2(npair), ptype(npair), pbody(npair), pcap(npair);
+    std::vector<double> psig(npair), pmu(npair), pmar(npair);
+    int maxcon = 0;
+    for (int k = 0; k < npair; k++) {
+        int g1 = pairs[k].g1, g2 = pairs[k].g2;
+        pg1[k] = g1;
+        pg2[k] = g2;
+        ptype[k] = d->geom_type[g2];
+        bool mov2 = movable[d->geom_body[g2]];
+        pbody[k] = mov2 ? d->geom_body[g2] : d->geom_body[g1];
+        psig[k] = mov2 ? 1.0 : -1.0;
+        pmu[k] = std::max(d->geom_friction[g1], d->geom_friction[g2]);
+        pmar[k] = std::max(d->geom_margin[g1], d->geom_margin[g2]);
+        pcap[k] = ptype[k] == RB_GEOM_SPHERE ? 1 : (ptype[k] == RB_GEOM_CAPSULE ? 2 : 8);
+        maxcon += pcap[k];
+    }
+    // options
+    if (!(d->timestep > 0) || d->nsubsteps < 1 || d->iterations < 0) return fail(RB_EINVAL, "bad options");
+    double dmax = std::min(std::max(d->solimp[1], 1e-4), 0.9999);
+    double tc = std::max(d->solref[0], 2 * d->timestep), zeta = d->solref[1];
+    // mean diagonal inertia at the reference configuration: composite inertias in double
+    double meaninertia;
+    {
+        std::vector<double> xp(3 * nb, 0), xq(4 * nb, 0), R(9 * nb, 0);
+        xq[0] = 1;
+        qmat_d(&xq[0], &R[0]);
+        for (int b = 1; b < nb; b++) {
+            int p = P(b);
+            double off[3];
+            mv_d(&R[9 * p], d->body_pos + 3 * b, off);
+            for (int i = 0; i < 3; i++) xp[3 * b + i] = xp[3 * p + i] + off[i];
+            qmul_d(&xq[4 * p], d->body_quat + 4 * b, &xq[4 * b]);
+            qmat_d(&xq[4 * b], &R[9 * b]);
+        }
+        // composite mass, first moment and rotational inertia about the world origin
+        std::vector<double> cm(nb, 0), ch(3 * nb, 0), cI(9 * nb, 0);
+        for (int b = nb - 1; b >= 1; b--) {
+            double Ri[9], RR[9], c[3];
+            qmat_d(d->body_iquat + 4 * b, Ri);
+            for (int i = 0; i < 3; i++)
+                for (int k = 0; k < 3; k++)
+                    RR[3 * i + k] = R[9 * b + 3 * i] * Ri[k] + R[9 * b + 3 * i + 1] * Ri[3 + k] + R[9 * b + 3 * i + 2] * Ri[6 + k];
+            mv_d(&R[9 * b], d->body_ipos + 3 * b, c);
+            for (int i = 0; i < 3; i++) c[i] += xp[3 * b + i];
+            double m = d->body_mass[b];
+            cm[b] += m;
+            for (int i = 0; i < 3; i++) ch[3 * b + i] += m * c[i];
+            double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+            for (int i = 0; i < 3; i++)
+                for (int k = 0; k < 3; k++) {
+                    double Ic = 0;
+                    for (int l = 0; l < 3; l++) Ic += RR[3 * i + l] * d->body_inertia[3 * b + l] * RR[3 * k + l];
+                    cI[9 * b + 3 * i + k] += Ic + m * ((i == k) * cc - c[i] * c[k]);
+                }
+            int p = P(b);
+            cm[p] += cm[b];
+            for (int i = 0; i < 3; i++) ch[3 * p + i] += ch[3 * b + i];
+            for (int i = 0; i < 9; i++) cI[9 * p + i] += cI[9 * b + i];
+        }
+        double tr = 0;
+        for (int j = 0; j < nj; j++) {
+            int b = jbody[j];
+            const double* I = &cI[9 * b];
+            const double* h = &ch[3 * b];
+            if (jtype[j] == RB_JNT_FREE) {
+                tr += 3 * cm[b];
+                // body axes through the body origin x: I_x = I_O - m(|x|^2 - x x') - cross terms
+                const double* x = &xp[3 * b];
+                for (int a = 0; a < 3; a++) {
+                    double u[3] = {R[9 * b + a], R[9 * b + 3 + a], R[9 * b + 6 + a]};
+                    double Iu[3];
+                    mv_d(I, u, Iu);
+                    double val = u[0] * Iu[0] + u[1] * Iu[1] + u[2] * Iu[2];
+                    // shift the axis from the origin to x: + m |u x x|^2 - 2 (u x x).(u x h)
+                    double ux[3], uh[3];
+                    cross_d(u, x, ux);
+                    cross_d(u, h, uh);
+                    val += cm[b] * (ux[0] * ux[0] + ux[1] * ux[1] + ux[2] * ux[2]) -
+                           2 * (ux[0] * uh[0] + ux[1] * uh[1] + ux[2] * uh[2]);
+                    tr += val;
+                }
+            } else {
+                double u[3], o[3], Iu[3];
+                mv_d(&R[9 * b], d->jnt_axis + 3 * j, u);
+                double nrm = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                for (int i = 0; i < 3; i++) u[i] /= nrm;
+                mv_d(&R[9 * b], d->jnt_pos + 3 * j, o);
+                for (int i = 0; i < 3; i++) o[i] += xp[3 * b + i];
+                mv_d(I, u, Iu);
+                double val = u[0] * Iu[0] + u[1] * Iu[1] + u[2] * Iu[2];
+                double uo[3], uh[3];
+                cross_d(u, o, uo);
+                cross_d(u, h, uh);
+                val += cm[b] * (uo[0] * uo[0] + uo[1] * uo[1] + uo[2] * uo[2]) -
+                       2 * (uo[0] * uh[0] + uo[1] * uh[1] + uo[2] * uh[2]);
+                tr += val + d->jnt_armature[j];
+            }
+        }
+        meaninertia = tr / nv;
+    }
+    // body tables
+    std::vector<int> bjt(nb, -1), bq(nb, 0), bd(nb, 0);
+    std::vector<double> jpos(3 * nb, 0), jax(3 * nb, 0), arm(nv, 0);
+    for (int b = 1; b < nb; b++) {
+        int j = bjnt[b];
+        if (j < 0) continue;
+        bjt[b] = jtype[j];
+        bq[b] = jq[j];
+        bd[b] = jd[j];
+        if (jtype[j] == RB_JNT_HINGE) {
+            const double* ax = d->jnt_axis + 3 * j;
+            double n = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+            for (int i = 0; i < 3; i++) {
+                jax[3 * b + i] = ax[i] / n;
+                jpos[3 * b + i] = d->jnt_pos[3 * j + i];
+            }
+            arm[jd[j]] = d->jnt_armature[j];
+        }
+    }
+    // ---- upload
+    Blob B;
+    DevModel& m = M->dm;
+    std::memset(&m, 0, sizeof m);
+    struct Fix { size_t off; const void** field; };
+    std::vector<Fix> fx;
+    auto I = [&](const std::vector<int>& v, const int** f) { fx.push_back({B.add_i(v), (const void**)f}); };
+    auto F = [&](const std::vector<double>& v, const float** f) { fx.push_back({B.add_f(v), (const void**)f}); };
+    std::vector<int> parent(nb);
+    for (int b = 0; b < nb; b++) parent[b] = b == 0 ? -1 : P(b);
+    I(parent, &m.body_parent); I(bjt, &m.body_jtype); I(bq, &m.body_qadr); I(bd, &m.body_dadr);
+    I(blast, &m.body_lastdof); I(bdepth, &m.body_depth); I(blevel, &m.body_level);
+    F(std::vector<double>(d->body_pos, d->body_pos + 3 * nb), &m.body_pos);
+    F(std::vector<double>(d->body_quat, d->body_quat + 4 * nb), &m.body_quat);
+    F(std::vector<double>(d->body_ipos, d->body_ipos + 3 * nb), &m.body_ipos);
+    F(std::vector<double>(d->body_iquat, d->body_iquat + 4 * nb), &m.body_iquat);
+    F(std::vector<double>(d->body_mass, d->body_mass + nb), &m.body_mass);
+    F(std::vector<double>(d->body_inertia, d->body_inertia + 3 * nb), &m.body_inertia);
+    F(jpos, &m.body_jpos); F(jax, &m.body_jaxis);
+    size_t off_mask = B.add_u64(cmask);
+    I(lv_start, &m.level_start); I(lv_body, &m.level_body); I(ch_start, &m.child_start); I(ch_list, &m.child_list);
+    I(dof_body, &m.dof_body); I(dof_depth, &m.dof_depth); I(rowadr, &m.dof_rowadr); I(anc, &m.dof_anc);
+    I(desc_start, &m.desc_start); I(desc_list, &m.desc_list); I(dl_start, &m.dlevel_start); I(dl_dof, &m.dlevel_dof);
+    F(arm, &m.dof_armature);
+    I(act_start, &m.act_start); I(act_list, &m.act_list); I(atype, &m.act_type); I(aqadr, &m.act_qadr);
+    F(akp, &m.act_kp); F(akd, &m.act_kd); F(agear, &m.act_gear);
+    I(jtype, &m.jnt_type); I(jq, &m.jnt_qadr); I(jd, &m.jnt_dadr);
+    I(pg1, &m.pair_g1); I(pg2, &m.pair_g2); I(ptype, &m.pair_type); I(pbody, &m.pair_body); I(pcap, &m.pair_cap);
+    F(psig, &m.pair_sigma); F(pmu, &m.pair_mu); F(pmar, &m.pair_margin);
+    I(std::vector<int>(d->geom_body, d->geom_body + ng), &m.geom_body);
+    F(std::vector<double>(d->geom_pos, d->geom_pos + 3 * ng), &m.geom_pos);
+    F(std::vector<double>(d->geom_quat, d->geom_quat + 4 * ng), &m.geom_quat);
+    F(std::vector<double>(d->geom_size, d->geom_size + 3 * ng), &m.geom_size);
+    void* dev = nullptr;
+    size_t bytes = B.words.size() * 4;
+    hipError_t e = hipMalloc(&dev, bytes);
+    if (e != hipSuccess) return fail(RB_ENOMEM, std::string("hipMalloc(model): ") + hipGetErrorString(e));
+    e = hipMemcpy(dev, B.words.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(e, "hipMemcpy(model)");
+    }
+    char* base = (char*)dev;
+    for (auto& f : fx) *f.field = base + 4 * f.off;
+    m.body_chainmask = (const uint64_t*)(base + 4 * off_mask);
+    // sizes and options
+    m.nbody = nb; m.nv = nv; m.nq = nq; m.nu = nu; m.njnt = nj; m.npair = npair;
+    m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.K = d->nsubsteps; m.maxiter = d->iterations;
+    m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
+    m.dt = (float)d->timestep;
+    for (int i = 0; i < 3; i++) m.grav[i] = (float)d->gravity[i];
+    m.tol_scale = (float)(d->tolerance * meaninertia * nv);
+    m.bref = (float)(2.0 / (dmax * tc));
+    m.kref = (float)(1.0 / (dmax * dmax * tc * tc * zeta * zeta));
+    m.dmin = (float)d->solimp[0]; m.dmax = (float)d->solimp[1]; m.width = (float)d->solimp[2];
+    m.mid = (float)d->solimp[3]; m.power = (float)d->solimp[4];
+    // LDS layout, 4-float aligned sections
+    int o = 0;
+    auto sec = [&](int nfl) { int r = o; o += (nfl + 3) & ~3; return r; };
+    m.o_q = sec(nq); m.o_v = sec(nv); m.o_ctrl = sec(nu); m.o_aws = sec(nv); m.o_mscale = sec(nb);
+    m.o_xpos = sec(3 * nb); m.o_xquat = sec(4 * nb); m.o_xmat = sec(9 * nb);
+    m.o_cinert = sec(10 * nb); m.o_crb = sec(10 * nb); m.o_cdof = sec(6 * nv); m.o_cvel = sec(6 * nb);
+    m.o_bvec = sec(6 * nb); m.o_bvec2 = sec(6 * nb);
+    m.o_tau = sec(nv); m.o_bias = sec(nv); m.o_a0 = sec(nv); m.o_a = sec(nv); m.o_Ma = sec(nv);
+    m.o_g = sec(nv); m.o_p = sec(nv); m.o_Mp = sec(nv); m.o_tmp = sec(nv);
+    m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16);
+    m.lds_floats = o;
+    m.ncap = std::min(maxcon, RB_MAX_CON);
+    M->blob = dev;
+    M->maxcon_static = maxcon;
+    M->meaninertia = meaninertia;
+    M->nv_ = nv; M->nq_ = nq; M->nu_ = nu; M->nbody_ = nb; M->ngeom_ = ng;
+    (void)hipGetDevice(&M->device);
+    return RB_OK;
+}
+
+}  // namespace
+
+// ====================================================================================== ABI
+extern "C" {
+
+const char* rb_last_error(void) { return g_err.c_str(); }
+
+int rb_model_create(const rb_model_desc* desc, rb_model** out) {
+    if (!desc || !out) return fail(RB_EINVAL, "null argument");
+    *out = nullptr;
+    rb_model* m = new rb_model();
+    int rc = compile_model(desc, m);
+    if (rc != RB_OK) {
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return RB_OK;
+}
+
+void rb_model_destroy(rb_model* m) {
+    if (!m) return;
+    if (m->blob) (void)hipFree(m->blob);
+    delete m;
+}
+
+int rb_model_info_get(const rb_model* m, rb_model_info* out) {
+    if (!m || !out) return fail(RB_EINVAL, "null argument");
+    out->nq = m->nq_; out->nv = m->nv_; out->nu = m->nu_; out->nbody = m->nbody_; out->ngeom = m->ngeom_;
+    out->npair = m->dm.npair; out->maxcon = m->maxcon_static; out->max_depth = m->dm.ndlevel;
+    out->lds_bytes = m->dm.lds_floats * 4; out->meaninertia = m->meaninertia;
+    return RB_OK;
+}
+
+int rb_batch_create(const rb_model* model, int32_t capacity, int32_t contact_capacity, rb_batch** out) {
+    if (!model || !out || capacity <= 0) return fail(RB_EINVAL, "bad arguments to rb_batch_create");
+    if (contact_capacity > RB_MAX_CON) return fail(RB_EINVAL, "contact capacity above 64");
+    *out = nullptr;
+    rb_batch* b = new rb_batch();
+    b->model = model;
+    b->capacity = capacity;
+    b->dm = model->dm;
+    int cap = contact_capacity > 0 ? contact_capacity : std::min(model->maxcon_static, RB_MAX_CON);
+    b->dm.ncap = std::max(cap, 1);
+    const int nv = model->nv_, nb = model->nbody_;
+    size_t s_ws = (size_t)capacity * nv * 4, s_st = (size_t)capacity * 4, s_fr = (size_t)capacity * 4,
+           s_ms = (size_t)capacity * nb * 4;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t total = al(s_ws) + al(s_st) + al(s_fr) + al(s_ms);
+    hipError_t e = hipMalloc(&b->mem, total);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(RB_ENOMEM, std::string("hipMalloc(batch): ") + hipGetErrorString(e));
+    }
+    char* p = (char*)b->mem;
+    b->W.qacc_ws = (float*)p; p += al(s_ws);
+    b->W.status = (uint32_t*)p; p += al(s_st);
+    b->W.friction = (float*)p; p += al(s_fr);
+    b->W.mass_scale = (float*)p;
+    e = hipMemset(b->W.qacc_ws, 0, s_ws);
+    if (e == hipSuccess) e = hipMemset(b->W.status, 0, s_st);
+    if (e == hipSuccess) e = rb_launch_fill(b->W.friction, 1.0f, (size_t)capacity, nullptr);
+    if (e == hipSuccess) e = rb_launch_fill(b->W.mass_scale, 1.0f, (size_t)capacity * nb, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(b->mem);
+        delete b;
+        return hip_fail(e, "batch init");
+    }
+    *out = b;
+    return RB_OK;
+}
+
+void rb_batch_destroy(rb_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
+}
+
+int32_t rb_batch_contact_capacity(const rb_batch* b) { return b ? b->dm.ncap : 0; }
+
+int rb_batch_set_params(rb_batch* b, int32_t field, int32_t n, const float* vals, void* stream) {
+    if (!b || !vals || n < 0 || n > b->capacity) return fail(RB_EINVAL, "bad arguments to rb_batch_set_params");
+    hipError_t e;
+    if (field == RB_PARAM_FRICTION) {
+        if (!b->dm.fr_pw) return fail(RB_EINVAL, "model does not have per-world friction");
+        e = hipMemcpyAsync(b->W.friction, vals, (size_t)n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    } else if (field == RB_PARAM_MASS_SCALE) {
+        if (!b->dm.ms_pw) return fail(RB_EINVAL, "model does not have per-world mass scale");
+        e = hipMemcpyAsync(b->W.mass_scale, vals, (size_t)n * b->dm.nbody * 4, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream);
+    } else {
+        return fail(RB_EINVAL, "unknown parameter field");
+    }
+    return e == hipSuccess ? RB_OK : hip_fail(e, "rb_batch_set_params");
+}
+
+int rb_world_reset(rb_batch* b, const int32_t* ids, int32_t n, const float* qacc_ws, void* stream) {
+    if (!b || n < 0 || (n > 0 && !ids)) return fail(RB_EINVAL, "bad arguments to rb_world_reset");
+    if (n == 0) return RB_OK;
+    hipError_t e = rb_launch_reset(b->dm.nv, ids, n, qacc_ws, b->W, b->capacity, (hipStream_t)stream);
+    return e == hipSuccess ? RB_OK : hip_fail(e, "rb_world_reset");
+}
+
+int rb_get_state(const rb_batch* b, int32_t n, float* ws, uint32_t* st, void* stream) {
+    if (!b || n < 0 || n > b->capacity) return fail(RB_EINVAL, "bad arguments to rb_get_state");
+    hipError_t e = hipSuccess;
+    if (ws && n)
+        e = hipMemcpyAsync(ws, b->W.qacc_ws, (size_t)n * b->dm.nv * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e == hipSuccess && st && n)
+        e = hipMemcpyAsync(st, b->W.status, (size_t)n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? RB_OK : hip_fail(e, "rb_get_state");
+}
+
+static int step_impl(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* qvel, const rb_contacts* c,
+                     uint32_t* status, const DevTaps* taps, void* stream) {
+    if (!b) return fail(RB_EINVAL, "null batch");
+    if (n < 0 || n > b->capacity) return fail(RB_EINVAL, "world count outside the batch capacity");
+    if (n == 0) return RB_OK;
+    if (!qpos || !qvel) return fail(RB_EINVAL, "qpos and qvel are required");
+    if (b->dm.nu > 0 && !ctrl) return fail(RB_EINVAL, "ctrl is required for a model with actuators");
+    hipError_t pending = hipGetLastError();
+    if (pending != hipSuccess) return hip_fail(pending, "earlier asynchronous error");
+    DevContactsOut co{};
+    if (c) {
+        co.ncon = c->ncon; co.geom = c->geom; co.feature = c->feature; co.dist = c->dist;
+        co.pos = c->pos; co.frame = c->frame; co.force = c->force;
+    }
+    hipError_t e = rb_launch_step(b->dm, n, ctrl, qpos, qvel, b->W, c ? &co : nullptr, status, taps,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? RB_OK : hip_fail(e, "step launch");
+}
+
+int rb_step(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* qvel, const rb_contacts* c,
+            uint32_t* status, void* stream) {
+    return step_impl(b, n, ctrl, qpos, qvel, c, status, nullptr, stream);
+}
+
+int rb_step_taps(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* qvel, const rb_contacts* c,
+                 uint32_t* status, float* M, float* bias, float* a0, float* qacc, float* efc, void* stream) {
+    DevTaps t{M, bias, a0, qacc, efc};
+    return step_impl(b, n, ctrl, qpos, qvel, c, status, &t, stream);
+}
+
+}  // extern "C"

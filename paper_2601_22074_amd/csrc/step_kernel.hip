@@ -1,0 +1,1020 @@
+// Fused batched physics step for gfx950: one 64-lane wavefront advances one world through
+// K substeps (controls held), with the world's working state staged in LDS.
+//
+// Per substep (paper, section "Manager-Based API", pipeline step "Simulate"; the contents of
+// the step follow MuJoCo's published formulation, section "Architecture" cites it):
+//   actuation -> forward kinematics -> spatial inertias and motion subspaces -> recursive
+//   Newton-Euler bias forces -> composite-rigid-body inertia M -> tree-sparse L'DL of M ->
+//   smooth acceleration a0 -> plane collision -> soft pyramidal contact rows -> primal Newton
+//   with exact line search -> semi-implicit Euler.
+//
+// Lane mappings: bodies, dofs, joints, collision pairs and contacts are each spread one per
+// lane; tree passes are level-synchronous over precomputed level lists.  Spatial vectors are
+// Plucker coordinates in a world-aligned frame whose origin O is body 1's origin at the start
+// of the substep (keeps FP32 cross products small).  Contacts live in registers (one per
+// lane); the Newton Hessian keeps M's tree sparsity because every contact involves one
+// moving body, so H = M + sum J'DJ factors in place without fill-in.
+#include <hip/hip_runtime.h>
+
+#include "rb_internal.h"
+#include "rbstep.h"
+
+#define DEV __device__ __forceinline__
+
+namespace rbk {
+
+// ------------------------------------------------------------------ wave utilities
+DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+DEV float wsum(float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+DEV float wmin(float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    return x;
+}
+DEV int wscan_incl(int x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+DEV bool finitef(float x) { return __builtin_isfinite(x); }
+// value of x in lane c (c uniform across the wave)
+DEV float rl(float x, int c) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), c)); }
+
+// ------------------------------------------------------------------ small vector math
+DEV void cross(const float* a, const float* b, float* o) {
+    float t0 = a[1] * b[2] - a[2] * b[1], t1 = a[2] * b[0] - a[0] * b[2], t2 = a[0] * b[1] - a[1] * b[0];
+    o[0] = t0; o[1] = t1; o[2] = t2;
+}
+DEV float dot(const float* a, const float* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+DEV void qmul(const float* a, const float* b, float* o) {
+    float w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    float x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    float y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    float z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    o[0] = w; o[1] = x; o[2] = y; o[3] = z;
+}
+DEV void qmat(const float* q, float* R) {
+    float w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+DEV void mv(const float* R, const float* v, float* o) {
+    float a = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+    float b = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
+    float c = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
+    o[0] = a; o[1] = b; o[2] = c;
+}
+DEV void mm(const float* A, const float* B, float* O) {
+    float t[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) t[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+#pragma unroll
+    for (int i = 0; i < 9; i++) O[i] = t[i];
+}
+
+// spatial inertia about O stored as (m, h[3] = m c, I[6] = xx yy zz xy xz yz);
+// product with a motion vector (w, v): (I w + h x v, m v - h x w)
+DEV void inert_mul(const float* I, const float* s, float* f) {
+    float m = I[0];
+    const float* h = I + 1;
+    const float* J = I + 4;
+    float hv[3], hw[3];
+    cross(h, s + 3, hv);
+    cross(h, s, hw);
+    f[0] = J[0] * s[0] + J[3] * s[1] + J[4] * s[2] + hv[0];
+    f[1] = J[3] * s[0] + J[1] * s[1] + J[5] * s[2] + hv[1];
+    f[2] = J[4] * s[0] + J[5] * s[1] + J[2] * s[2] + hv[2];
+    f[3] = m * s[3] - hw[0];
+    f[4] = m * s[4] - hw[1];
+    f[5] = m * s[5] - hw[2];
+}
+// motion cross motion: (w, v) x (w', v') = (w x w', w x v' + v x w')
+DEV void crm(const float* a, const float* b, float* o) {
+    float t0[3], t1[3], t2[3];
+    cross(a, b, t0);
+    cross(a, b + 3, t1);
+    cross(a + 3, b, t2);
+    o[0] = t0[0]; o[1] = t0[1]; o[2] = t0[2];
+    o[3] = t1[0] + t2[0]; o[4] = t1[1] + t2[1]; o[5] = t1[2] + t2[2];
+}
+// motion cross force: (w, v) x* (n, f) = (w x n + v x f, w x f)
+DEV void crf(const float* a, const float* b, float* o) {
+    float t0[3], t1[3], t2[3];
+    cross(a, b, t0);
+    cross(a + 3, b + 3, t1);
+    cross(a, b + 3, t2);
+    o[0] = t0[0] + t1[0]; o[1] = t0[1] + t1[1]; o[2] = t0[2] + t1[2];
+    o[3] = t2[0]; o[4] = t2[1]; o[5] = t2[2];
+}
+DEV float sdot(const float* a, const float* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
+}
+
+// triangular pair index p -> (a, b) with b <= a
+DEV void tri_decode(int p, int& a, int& b) {
+    int t = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+    while (t * (t + 1) / 2 > p) t--;
+    while ((t + 1) * (t + 2) / 2 <= p) t++;
+    a = t;
+    b = p - t * (t + 1) / 2;
+}
+
+// ------------------------------------------------------------------ tree-sparse L'DL
+// In-place factorisation of a packed tree-sparse symmetric matrix (row i holds the entries
+// of the dofs on i's chain, root first).  Leaves first: for each dof k, the outer product
+// of its row updates the ancestor block, then the row is divided by its diagonal.  On exit
+// row k holds L (unit lower triangle, ancestors of k) and D_k on the diagonal: M = L' D L.
+template <int MAXD>
+DEV void ldl_factor(const DevModel& m, float* buf, int lane) {
+    for (int k = m.nv - 1; k >= 0; k--) {
+        int dk = m.dof_depth[k] - 1;
+        int rk = m.dof_rowadr[k];
+        float invd = 1.0f / buf[rk + dk];
+        int np = dk * (dk + 1) / 2;
+        for (int p = lane; p < np; p += RB_WAVE) {
+            int a, b;
+            tri_decode(p, a, b);
+            int i = m.dof_anc[k * m.maxd + a];
+            float lka = buf[rk + a] * invd;
+            buf[m.dof_rowadr[i] + b] -= lka * buf[rk + b];
+        }
+        wave_sync();
+        if (lane < dk) buf[rk + lane] *= invd;
+        wave_sync();
+    }
+}
+
+// x <- M^-1 x with M = L'DL held in buf; level-parallel over dof depths.
+DEV void ldl_solve(const DevModel& m, const float* buf, float* x, int lane) {
+    // L' y = x: deepest dofs first, each dof pulls from its descendants
+    for (int lev = m.ndlevel; lev >= 1; lev--) {
+        for (int idx = m.dlevel_start[lev] + lane; idx < m.dlevel_start[lev + 1]; idx += RB_WAVE) {
+            int i = m.dlevel_dof[idx];
+            int col = m.dof_depth[i] - 1;
+            float s = x[i];
+            for (int c = m.desc_start[i]; c < m.desc_start[i + 1]; c++) {
+                int k = m.desc_list[c];
+                s -= buf[m.dof_rowadr[k] + col] * x[k];
+            }
+            x[i] = s;
+        }
+        wave_sync();
+    }
+    for (int i = lane; i < m.nv; i += RB_WAVE) x[i] /= buf[m.dof_rowadr[i] + m.dof_depth[i] - 1];
+    wave_sync();
+    // L x = z: root first, each dof pulls from its ancestors
+    for (int lev = 1; lev <= m.ndlevel; lev++) {
+        for (int idx = m.dlevel_start[lev] + lane; idx < m.dlevel_start[lev + 1]; idx += RB_WAVE) {
+            int i = m.dlevel_dof[idx];
+            int d = m.dof_depth[i] - 1;
+            int r = m.dof_rowadr[i];
+            float s = x[i];
+            for (int t = 0; t < d; t++) s -= buf[r + t] * x[m.dof_anc[i * m.maxd + t]];
+            x[i] = s;
+        }
+        wave_sync();
+    }
+}
+
+// y = M x with M packed (lower rows) -- each dof pulls its chain and its descendants.
+DEV void sym_mul(const DevModel& m, const float* M, const float* x, float* y, int lane) {
+    for (int i = lane; i < m.nv; i += RB_WAVE) {
+        int d = m.dof_depth[i];
+        int r = m.dof_rowadr[i];
+        float s = 0.f;
+        for (int t = 0; t < d; t++) s += M[r + t] * x[m.dof_anc[i * m.maxd + t]];
+        for (int c = m.desc_start[i]; c < m.desc_start[i + 1]; c++) {
+            int k = m.desc_list[c];
+            s += M[m.dof_rowadr[k] + d - 1] * x[k];
+        }
+        y[i] = s;
+    }
+    wave_sync();
+}
+
+// spatial motion of every body produced by dof vector x: out[b] = sum over the body's chain S_i x_i
+DEV void body_motion(const DevModel& m, const float* cdof, const float* x, float* out, int lane) {
+    for (int b = lane; b < m.nbody; b += RB_WAVE) {
+        float acc[6] = {0, 0, 0, 0, 0, 0};
+        int ld = m.body_lastdof[b];
+        if (ld >= 0) {
+            int d = m.dof_depth[ld];
+            for (int t = 0; t < d; t++) {
+                int i = m.dof_anc[ld * m.maxd + t];
+                float xi = x[i];
+#pragma unroll
+                for (int c = 0; c < 6; c++) acc[c] += cdof[6 * i + c] * xi;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) out[6 * b + c] = acc[c];
+    }
+    wave_sync();
+}
+
+// ------------------------------------------------------------------ contacts (one per lane)
+struct Con {
+    float r[3];            // contact point relative to O
+    float n[3], t1[3], t2[3];
+    float mu, sigma, dist, margin;
+    int body, g1, g2, feat;
+    float D[4], aref[4], jar[4], s[4], ahat[4];
+};
+
+// velocity of the contact's pyramid rows for body spatial motions `bm` (already includes sign)
+DEV void rows_of(const Con& c, const float* bm, float* out) {
+    const float* sv = bm + 6 * c.body;
+    float wr[3];
+    cross(sv, c.r, wr);
+    float vp[3] = {sv[3] + wr[0], sv[4] + wr[1], sv[5] + wr[2]};
+    float vn = c.sigma * dot(c.n, vp), v1 = c.sigma * dot(c.t1, vp), v2 = c.sigma * dot(c.t2, vp);
+    out[0] = vn + c.mu * v1;
+    out[1] = vn - c.mu * v1;
+    out[2] = vn + c.mu * v2;
+    out[3] = vn - c.mu * v2;
+}
+
+DEV void contact_frame(const float* n, float* t1, float* t2) {
+    int k = 0;
+    if (fabsf(n[1]) < fabsf(n[k])) k = 1;
+    if (fabsf(n[2]) < fabsf(n[k])) k = 2;
+    float e[3] = {0.f, 0.f, 0.f};
+    e[k] = 1.f;
+    float dn = n[k];
+    float t[3] = {e[0] - dn * n[0], e[1] - dn * n[1], e[2] - dn * n[2]};
+    float inv = 1.0f / sqrtf(dot(t, t));
+    t1[0] = t[0] * inv; t1[1] = t[1] * inv; t1[2] = t[2] * inv;
+    cross(n, t1, t2);
+}
+
+// world pose of geom g from its body's pose in LDS
+DEV void geom_pose(const DevModel& m, const float* L, int g, float* x, float* R) {
+    int b = m.geom_body[g];
+    const float* Rb = L + m.o_xmat + 9 * b;
+    float off[3];
+    mv(Rb, m.geom_pos + 3 * g, off);
+    x[0] = L[m.o_xpos + 3 * b] + off[0];
+    x[1] = L[m.o_xpos + 3 * b + 1] + off[1];
+    x[2] = L[m.o_xpos + 3 * b + 2] + off[2];
+    float Rg[9];
+    qmat(m.geom_quat + 4 * g, Rg);
+    mm(Rb, Rg, R);
+}
+
+// The j-th contact of pair p (j < count), or the count when want < 0.  Candidates are
+// enumerated in feature order; a candidate counts iff its distance is below the margin.
+DEV int pair_contacts(const DevModel& m, const float* L, int p, int want, float* dist, float* pos, int* feat,
+                      float* nrm) {
+    float xp[3], Rp[9], x[3], R[9];
+    geom_pose(m, L, m.pair_g1[p], xp, Rp);
+    geom_pose(m, L, m.pair_g2[p], x, R);
+    float n[3] = {Rp[2], Rp[5], Rp[8]};
+    nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2];
+    const float* sz = m.geom_size + 3 * m.pair_g2[p];
+    float margin = m.pair_margin[p];
+    int type = m.pair_type[p];
+    int cnt = 0;
+    if (type == RB_GEOM_SPHERE) {
+        float r[3] = {x[0] - xp[0], x[1] - xp[1], x[2] - xp[2]};
+        float d = dot(n, r) - sz[0];
+        if (d < margin) {
+            if (cnt == want) {
+                *dist = d; *feat = 0;
+                float k = sz[0] + 0.5f * d;
+                pos[0] = x[0] - n[0] * k; pos[1] = x[1] - n[1] * k; pos[2] = x[2] - n[2] * k;
+            }
+            cnt++;
+        }
+    } else if (type == RB_GEOM_CAPSULE) {
+        for (int f = 0; f < 2; f++) {
+            float s = f == 0 ? -sz[1] : sz[1];
+            float e[3] = {x[0] + s * R[2], x[1] + s * R[5], x[2] + s * R[8]};
+            float r[3] = {e[0] - xp[0], e[1] - xp[1], e[2] - xp[2]};
+            float d = dot(n, r) - sz[0];
+            if (d < margin) {
+                if (cnt == want) {
+                    *dist = d; *feat = f;
+                    float k = sz[0] + 0.5f * d;
+                    pos[0] = e[0] - n[0] * k; pos[1] = e[1] - n[1] * k; pos[2] = e[2] - n[2] * k;
+                }
+                cnt++;
+            }
+        }
+    } else if (type == RB_GEOM_BOX) {
+        for (int k = 0; k < 8; k++) {
+            float loc[3] = {(k & 4) ? sz[0] : -sz[0], (k & 2) ? sz[1] : -sz[1], (k & 1) ? sz[2] : -sz[2]};
+            float v[3];
+            mv(R, loc, v);
+            v[0] += x[0]; v[1] += x[1]; v[2] += x[2];
+            float r[3] = {v[0] - xp[0], v[1] - xp[1], v[2] - xp[2]};
+            float d = dot(n, r);
+            if (d < margin) {
+                if (cnt == want) {
+                    *dist = d; *feat = k;
+                    float h = 0.5f * d;
+                    pos[0] = v[0] - n[0] * h; pos[1] = v[1] - n[1] * h; pos[2] = v[2] - n[2] * h;
+                }
+                cnt++;
+            }
+        }
+    }
+    return cnt;
+}
+
+DEV float impedance(const DevModel& m, float r) {
+    float x = fminf(fabsf(r) / m.width, 1.0f);
+    float y;
+    if (x <= m.mid)
+        y = powf(x, m.power) / powf(m.mid, m.power - 1.0f);
+    else
+        y = 1.0f - powf(1.0f - x, m.power) / powf(1.0f - m.mid, m.power - 1.0f);
+    float imp = m.dmin + y * (m.dmax - m.dmin);
+    return fminf(fmaxf(imp, 1e-4f), 0.9999f);
+}
+
+// ------------------------------------------------------------------ the kernel
+struct StepArgs {
+    int n;
+    const float* ctrl;
+    float* qpos;
+    float* qvel;
+    DevWorlds W;
+    DevContactsOut co;
+    uint32_t* status_out;
+    DevTaps taps;
+    int want_contacts, want_taps;
+};
+
+template <int MAXD>
+__global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
+    extern __shared__ float lds[];
+    const int w = blockIdx.x;
+    if (w >= A.n) return;
+    const int lane = threadIdx.x;
+    float* L = lds;
+    float* q = L + m.o_q;
+    float* v = L + m.o_v;
+    float* ctrl = L + m.o_ctrl;
+    float* aws = L + m.o_aws;
+    float* msc = L + m.o_mscale;
+    float* xpos = L + m.o_xpos;
+    float* xquat = L + m.o_xquat;
+    float* xmat = L + m.o_xmat;
+    float* cinert = L + m.o_cinert;
+    float* crb = L + m.o_crb;
+    float* cdof = L + m.o_cdof;
+    float* cvel = L + m.o_cvel;
+    float* bvec = L + m.o_bvec;
+    float* bvec2 = L + m.o_bvec2;
+    float* tau = L + m.o_tau;
+    float* bias = L + m.o_bias;
+    float* a0 = L + m.o_a0;
+    float* acc = L + m.o_a;
+    float* Ma = L + m.o_Ma;
+    float* g = L + m.o_g;
+    float* p = L + m.o_p;
+    float* Mp = L + m.o_Mp;
+    float* tmp = L + m.o_tmp;
+    float* Mm = L + m.o_M;
+    float* H = L + m.o_H;
+    float* misc = L + m.o_misc;
+
+    const int nq = m.nq, nv = m.nv, nu = m.nu, nb = m.nbody;
+    // ---- ingress
+    for (int i = lane; i < nq; i += RB_WAVE) q[i] = A.qpos[(size_t)w * nq + i];
+    for (int i = lane; i < nv; i += RB_WAVE) {
+        v[i] = A.qvel[(size_t)w * nv + i];
+        aws[i] = A.W.qacc_ws[(size_t)w * nv + i];
+    }
+    for (int i = lane; i < nu; i += RB_WAVE) ctrl[i] = A.ctrl[(size_t)w * nu + i];
+    for (int b = lane; b < nb; b += RB_WAVE) msc[b] = m.ms_pw ? A.W.mass_scale[(size_t)w * nb + b] : 1.0f;
+    const float mu_world = m.fr_pw ? A.W.friction[w] : 0.0f;
+    if (lane == 0) {
+        xpos[0] = xpos[1] = xpos[2] = 0.f;
+        xquat[0] = 1.f; xquat[1] = xquat[2] = xquat[3] = 0.f;
+        for (int c = 0; c < 9; c++) xmat[c] = (c % 4 == 0) ? 1.f : 0.f;
+        for (int c = 0; c < 10; c++) cinert[c] = crb[c] = 0.f;
+        for (int c = 0; c < 6; c++) cvel[c] = 0.f;
+    }
+    uint32_t status = A.W.status[w];
+    wave_sync();
+
+    Con C;
+    int ncon = 0;
+    bool frozen = (status & RB_STATUS_NONFINITE) != 0;
+    status &= ~(uint32_t)(RB_STATUS_ITERCAP | RB_STATUS_CONOVERFLOW);
+
+    for (int sub = 0; sub < m.K && !frozen; sub++) {
+        // ---- actuation: tau = kp (ctrl - q) - kd v  (position) or gear * ctrl (motor)
+        for (int i = lane; i < nv; i += RB_WAVE) {
+            float t = 0.f;
+            for (int c = m.act_start[i]; c < m.act_start[i + 1]; c++) {
+                int u = m.act_list[c];
+                if (m.act_type[u] == RB_ACT_POSITION)
+                    t += m.act_kp[u] * (ctrl[u] - q[m.act_qadr[u]]) - m.act_kd[u] * v[i];
+                else
+                    t += m.act_gear[u] * ctrl[u];
+            }
+            tau[i] = t;
+        }
+        // ---- forward kinematics, level by level from the root
+        for (int lev = 1; lev <= m.nblevel; lev++) {
+            for (int idx = m.level_start[lev] + lane; idx < m.level_start[lev + 1]; idx += RB_WAVE) {
+                int b = m.level_body[idx];
+                int par = m.body_parent[b];
+                int jt = m.body_jtype[b];
+                float x[3], qq[4];
+                if (jt == RB_JNT_FREE) {
+                    int a = m.body_qadr[b];
+                    x[0] = q[a]; x[1] = q[a + 1]; x[2] = q[a + 2];
+                    float nrm = sqrtf(q[a + 3] * q[a + 3] + q[a + 4] * q[a + 4] + q[a + 5] * q[a + 5] + q[a + 6] * q[a + 6]);
+                    float inv = 1.0f / nrm;
+                    qq[0] = q[a + 3] * inv; qq[1] = q[a + 4] * inv; qq[2] = q[a + 5] * inv; qq[3] = q[a + 6] * inv;
+                } else {
+                    float off[3];
+                    mv(xmat + 9 * par, m.body_pos + 3 * b, off);
+                    x[0] = xpos[3 * par] + off[0]; x[1] = xpos[3 * par + 1] + off[1]; x[2] = xpos[3 * par + 2] + off[2];
+                    qmul(xquat + 4 * par, m.body_quat + 4 * b, qq);
+                    if (jt == RB_JNT_HINGE) {
+                        float R0[9];
+                        qmat(qq, R0);
+                        float th = 0.5f * q[m.body_qadr[b]];
+                        float sh = sinf(th), ch = cosf(th);
+                        const float* ax = m.body_jaxis + 3 * b;
+                        float qh[4] = {ch, sh * ax[0], sh * ax[1], sh * ax[2]};
+                        float q1[4];
+                        qmul(qq, qh, q1);
+                        qq[0] = q1[0]; qq[1] = q1[1]; qq[2] = q1[2]; qq[3] = q1[3];
+                        float R1[9], d0[3], d1[3];
+                        qmat(qq, R1);
+                        mv(R0, m.body_jpos + 3 * b, d0);
+                        mv(R1, m.body_jpos + 3 * b, d1);
+                        x[0] += d0[0] - d1[0]; x[1] += d0[1] - d1[1]; x[2] += d0[2] - d1[2];
+                    }
+                }
+                xpos[3 * b] = x[0]; xpos[3 * b + 1] = x[1]; xpos[3 * b + 2] = x[2];
+                xquat[4 * b] = qq[0]; xquat[4 * b + 1] = qq[1]; xquat[4 * b + 2] = qq[2]; xquat[4 * b + 3] = qq[3];
+                qmat(qq, xmat + 9 * b);
+            }
+            wave_sync();
+        }
+        const float O[3] = {xpos[3], xpos[4], xpos[5]};
+        // ---- spatial inertias about O, motion subspaces of the dofs
+        for (int b = 1 + lane; b < nb; b += RB_WAVE) {
+            const float* R = xmat + 9 * b;
+            float Ri[9], RR[9];
+            qmat(m.body_iquat + 4 * b, Ri);
+            mm(R, Ri, RR);
+            float s = msc[b];
+            float mass = s * m.body_mass[b];
+            float d0 = s * m.body_inertia[3 * b], d1 = s * m.body_inertia[3 * b + 1], d2 = s * m.body_inertia[3 * b + 2];
+            float off[3];
+            mv(R, m.body_ipos + 3 * b, off);
+            float c[3] = {xpos[3 * b] + off[0] - O[0], xpos[3 * b + 1] + off[1] - O[1], xpos[3 * b + 2] + off[2] - O[2]};
+            // rotational inertia about the COM: RR diag(d) RR'
+            float Ixx = RR[0] * RR[0] * d0 + RR[1] * RR[1] * d1 + RR[2] * RR[2] * d2;
+            float Iyy = RR[3] * RR[3] * d0 + RR[4] * RR[4] * d1 + RR[5] * RR[5] * d2;
+            float Izz = RR[6] * RR[6] * d0 + RR[7] * RR[7] * d1 + RR[8] * RR[8] * d2;
+            float Ixy = RR[0] * RR[3] * d0 + RR[1] * RR[4] * d1 + RR[2] * RR[5] * d2;
+            float Ixz = RR[0] * RR[6] * d0 + RR[1] * RR[7] * d1 + RR[2] * RR[8] * d2;
+            float Iyz = RR[3] * RR[6] * d0 + RR[4] * RR[7] * d1 + RR[5] * RR[8] * d2;
+            float cc = dot(c, c);
+            float* I = cinert + 10 * b;
+            I[0] = mass;
+            I[1] = mass * c[0]; I[2] = mass * c[1]; I[3] = mass * c[2];
+            I[4] = Ixx + mass * (cc - c[0] * c[0]);
+            I[5] = Iyy + mass * (cc - c[1] * c[1]);
+            I[6] = Izz + mass * (cc - c[2] * c[2]);
+            I[7] = Ixy - mass * c[0] * c[1];
+            I[8] = Ixz - mass * c[0] * c[2];
+            I[9] = Iyz - mass * c[1] * c[2];
+            for (int k = 0; k < 10; k++) crb[10 * b + k] = I[k];
+            int jt = m.body_jtype[b];
+            int da = m.body_dadr[b];
+            float xo[3] = {xpos[3 * b] - O[0], xpos[3 * b + 1] - O[1], xpos[3 * b + 2] - O[2]};
+            if (jt == RB_JNT_HINGE) {
+                float u[3], o[3];
+                mv(R, m.body_jaxis + 3 * b, u);
+                mv(R, m.body_jpos + 3 * b, o);
+                o[0] += xo[0]; o[1] += xo[1]; o[2] += xo[2];
+                float* S = cdof + 6 * da;
+                S[0] = u[0]; S[1] = u[1]; S[2] = u[2];
+                cross(o, u, S + 3);
+            } else if (jt == RB_JNT_FREE) {
+                for (int k = 0; k < 3; k++) {
+                    float* S = cdof + 6 * (da + k);
+                    S[0] = S[1] = S[2] = 0.f;
+                    S[3] = k == 0; S[4] = k == 1; S[5] = k == 2;
+                    float* Sr = cdof + 6 * (da + 3 + k);
+                    float r[3] = {R[k], R[3 + k], R[6 + k]};
+                    Sr[0] = r[0]; Sr[1] = r[1]; Sr[2] = r[2];
+                    cross(xo, r, Sr + 3);
+                }
+            }
+        }
+        wave_sync();
+        // ---- recursive Newton-Euler bias forces (qacc = 0, world accelerating at -gravity)
+        if (lane == 0) {
+            bvec[0] = bvec[1] = bvec[2] = 0.f;
+            bvec[3] = -m.grav[0]; bvec[4] = -m.grav[1]; bvec[5] = -m.grav[2];
+        }
+        wave_sync();
+        for (int lev = 1; lev <= m.nblevel; lev++) {
+            for (int idx = m.level_start[lev] + lane; idx < m.level_start[lev + 1]; idx += RB_WAVE) {
+                int b = m.level_body[idx];
+                int par = m.body_parent[b];
+                float vb[6], ab[6];
+                for (int c = 0; c < 6; c++) { vb[c] = cvel[6 * par + c]; ab[c] = bvec[6 * par + c]; }
+                int jt = m.body_jtype[b], da = m.body_dadr[b];
+                int nd = jt == RB_JNT_FREE ? 6 : (jt == RB_JNT_HINGE ? 1 : 0);
+                for (int k = 0; k < nd; k++) {
+                    const float* S = cdof + 6 * (da + k);
+                    float qd = v[da + k];
+                    for (int c = 0; c < 6; c++) vb[c] += S[c] * qd;
+                }
+                int k0 = jt == RB_JNT_FREE ? 3 : 0;   // free-joint translation axes are fixed in the world
+                for (int k = k0; k < nd; k++) {
+                    float t[6];
+                    crm(vb, cdof + 6 * (da + k), t);
+                    float qd = v[da + k];
+                    for (int c = 0; c < 6; c++) ab[c] += t[c] * qd;
+                }
+                for (int c = 0; c < 6; c++) { cvel[6 * b + c] = vb[c]; bvec[6 * b + c] = ab[c]; }
+            }
+            wave_sync();
+        }
+        for (int b = 1 + lane; b < nb; b += RB_WAVE) {
+            float f[6], Iv[6], t[6];
+            inert_mul(cinert + 10 * b, bvec + 6 * b, f);
+            inert_mul(cinert + 10 * b, cvel + 6 * b, Iv);
+            crf(cvel + 6 * b, Iv, t);
+            for (int c = 0; c < 6; c++) bvec2[6 * b + c] = f[c] + t[c];
+        }
+        wave_sync();
+        // ---- backward passes: bias wrenches and composite inertias accumulate to the root
+        for (int lev = m.nblevel; lev >= 1; lev--) {
+            for (int idx = m.level_start[lev] + lane; idx < m.level_start[lev + 1]; idx += RB_WAVE) {
+                int b = m.level_body[idx];
+                for (int c = m.child_start[b]; c < m.child_start[b + 1]; c++) {
+                    int ch = m.child_list[c];
+                    for (int k = 0; k < 6; k++) bvec2[6 * b + k] += bvec2[6 * ch + k];
+                    for (int k = 0; k < 10; k++) crb[10 * b + k] += crb[10 * ch + k];
+                }
+            }
+            wave_sync();
+        }
+        for (int i = lane; i < nv; i += RB_WAVE) {
+            const float* S = cdof + 6 * i;
+            int b = m.dof_body[i];
+            bias[i] = sdot(S, bvec2 + 6 * b);
+            // joint-space inertia row i: M_ij = S_j . (Ic_b S_i) over the chain of i
+            float F[6];
+            inert_mul(crb + 10 * b, S, F);
+            int d = m.dof_depth[i], r = m.dof_rowadr[i];
+            for (int t = 0; t < d; t++) {
+                int j = m.dof_anc[i * m.maxd + t];
+                Mm[r + t] = sdot(cdof + 6 * j, F);
+            }
+            Mm[r + d - 1] += m.dof_armature[i];
+            a0[i] = tau[i] - bias[i];
+        }
+        wave_sync();
+        for (int e = lane; e < m.nM; e += RB_WAVE) H[e] = Mm[e];
+        wave_sync();
+        ldl_factor<MAXD>(m, H, lane);
+        ldl_solve(m, H, a0, lane);
+
+        // ---- collision: count per pair, scan, then each contact lane rebuilds its contact
+        int cnt = 0;
+        float dist_, pos_[3], nrm_[3];
+        int feat_;
+        if (lane < m.npair) cnt = pair_contacts(m, L, lane, -1, &dist_, pos_, &feat_, nrm_);
+        int incl = wscan_incl(cnt, lane);
+        int total = __shfl(incl, RB_WAVE - 1);
+        ncon = total < m.ncap ? total : m.ncap;
+        if (total > m.ncap) status |= RB_STATUS_CONOVERFLOW;
+        ncon = __builtin_amdgcn_readfirstlane(ncon);
+        bool has = lane < ncon;
+        int src = 0;
+        {
+            // smallest pair whose inclusive count exceeds this lane's contact index
+            int lo = 0, hi = RB_WAVE - 1;
+#pragma unroll
+            for (int it = 0; it < 6; it++) {
+                int mid = (lo + hi) >> 1;
+                int vmid = __shfl(incl, mid);
+                if (vmid > lane) hi = mid; else lo = mid + 1;
+            }
+            src = lo;
+        }
+        int before = __shfl(incl - cnt, src);
+        if (has) {
+            int j = lane - before;
+            pair_contacts(m, L, src, j, &C.dist, pos_, &C.feat, C.n);
+            C.r[0] = pos_[0] - O[0]; C.r[1] = pos_[1] - O[1]; C.r[2] = pos_[2] - O[2];
+            contact_frame(C.n, C.t1, C.t2);
+            C.g1 = m.pair_g1[src]; C.g2 = m.pair_g2[src];
+            C.body = m.pair_body[src];
+            C.sigma = m.pair_sigma[src];
+            C.mu = m.fr_pw ? mu_world : m.pair_mu[src];
+            C.margin = m.pair_margin[src];
+        }
+        // ---- constraint rows: exact A-hat from the chain half-solve with M's factor
+        if (has) {
+            float X[MAXD][3];
+            int ld = m.body_lastdof[C.body];
+            int d = m.dof_depth[ld];
+#pragma unroll
+            for (int t = 0; t < MAXD; t++) {
+                X[t][0] = X[t][1] = X[t][2] = 0.f;
+                if (t < d) {
+                    const float* S = cdof + 6 * m.dof_anc[ld * m.maxd + t];
+                    float wr[3];
+                    cross(S, C.r, wr);
+                    float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                    X[t][0] = C.sigma * dot(C.n, vp);
+                    X[t][1] = C.sigma * dot(C.t1, vp);
+                    X[t][2] = C.sigma * dot(C.t2, vp);
+                }
+            }
+#pragma unroll
+            for (int tp = MAXD - 1; tp >= 1; tp--) {
+                if (tp < d) {
+                    int row = m.dof_rowadr[m.dof_anc[ld * m.maxd + tp]];
+#pragma unroll
+                    for (int t = 0; t < tp; t++) {
+                        float l = H[row + t];
+                        X[t][0] -= l * X[tp][0];
+                        X[t][1] -= l * X[tp][1];
+                        X[t][2] -= l * X[tp][2];
+                    }
+                }
+            }
+            float A00 = 0, A11 = 0, A22 = 0, A01 = 0, A02 = 0;
+#pragma unroll
+            for (int t = 0; t < MAXD; t++) {
+                if (t < d) {
+                    float inv = 1.0f / H[m.dof_rowadr[m.dof_anc[ld * m.maxd + t]] + t];
+                    A00 += X[t][0] * X[t][0] * inv;
+                    A11 += X[t][1] * X[t][1] * inv;
+                    A22 += X[t][2] * X[t][2] * inv;
+                    A01 += X[t][0] * X[t][1] * inv;
+                    A02 += X[t][0] * X[t][2] * inv;
+                }
+            }
+            float vrow[4];
+            rows_of(C, cvel, vrow);
+            float rd = C.dist - C.margin;
+            float imp = impedance(m, rd);
+            float mu = C.mu, mu2 = mu * mu;
+            float ah[4] = {A00 + mu2 * A11 + 2.f * mu * A01, A00 + mu2 * A11 - 2.f * mu * A01,
+                           A00 + mu2 * A22 + 2.f * mu * A02, A00 + mu2 * A22 - 2.f * mu * A02};
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                C.ahat[e] = ah[e];
+                C.aref[e] = -m.bref * vrow[e] - m.kref * imp * rd;
+                float R = fmaxf(1e-15f, (1.0f - imp) / imp * ah[e]);
+                C.D[e] = 1.0f / R;
+            }
+        }
+
+        // ---- primal Newton solve
+        bool itercap = false;
+        if (ncon == 0) {
+            for (int i = lane; i < nv; i += RB_WAVE) acc[i] = a0[i];
+            wave_sync();
+        } else {
+            // cost at a0 and at the warm start; keep the better (ties go to a0)
+            body_motion(m, cdof, a0, bvec, lane);
+            float j0[4] = {0, 0, 0, 0};
+            float f0 = 0.f;
+            if (has) {
+                rows_of(C, bvec, j0);
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    j0[e] -= C.aref[e];
+                    float mn = fminf(j0[e], 0.f);
+                    f0 += 0.5f * C.D[e] * mn * mn;
+                }
+            }
+            f0 = wsum(f0);
+            for (int i = lane; i < nv; i += RB_WAVE) tmp[i] = aws[i] - a0[i];
+            wave_sync();
+            sym_mul(m, Mm, tmp, g, lane);   // g <- M (aws - a0)
+            body_motion(m, cdof, aws, bvec, lane);
+            float jw[4] = {0, 0, 0, 0};
+            float fw = 0.f;
+            if (has) {
+                rows_of(C, bvec, jw);
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    jw[e] -= C.aref[e];
+                    float mn = fminf(jw[e], 0.f);
+                    fw += 0.5f * C.D[e] * mn * mn;
+                }
+            }
+            float qf = 0.f;
+            for (int i = lane; i < nv; i += RB_WAVE) qf += tmp[i] * g[i];
+            fw = wsum(fw) + 0.5f * wsum(qf);
+            bool use_ws = fw < f0;
+            float fcur = use_ws ? fw : f0;
+            for (int i = lane; i < nv; i += RB_WAVE) {
+                acc[i] = use_ws ? aws[i] : a0[i];
+                Ma[i] = use_ws ? (tau[i] - bias[i]) + g[i] : (tau[i] - bias[i]);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) C.jar[e] = use_ws ? jw[e] : j0[e];
+            wave_sync();
+
+            int it = 0;
+            for (; it < m.maxiter; it++) {
+                // gradient and the contact part of the Hessian, one contact at a time
+                float gc = 0.f;
+                float F[6] = {0, 0, 0, 0, 0, 0};
+                float S[6] = {0, 0, 0, 0, 0, 0};
+                bool dof_lane = lane < nv;
+                if (dof_lane)
+                    for (int c = 0; c < 6; c++) S[c] = cdof[6 * lane + c];
+                for (int c = 0; c < ncon; c++) {
+                    int body = __builtin_amdgcn_readlane(C.body, c);
+                    uint64_t mask = m.body_chainmask[body];
+                    float r[3], n[3], t1[3], t2[3], D[4], jar[4];
+                    for (int k = 0; k < 3; k++) {
+                        r[k] = rl(C.r[k], c); n[k] = rl(C.n[k], c);
+                        t1[k] = rl(C.t1[k], c); t2[k] = rl(C.t2[k], c);
+                    }
+                    for (int e = 0; e < 4; e++) { D[e] = rl(C.D[e], c); jar[e] = rl(C.jar[e], c); }
+                    float mu = rl(C.mu, c), sg = rl(C.sigma, c);
+                    if (dof_lane && ((mask >> lane) & 1ull)) {
+                        float wr[3];
+                        cross(S, r, wr);
+                        float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                        float jn = sg * dot(n, vp), j1 = sg * dot(t1, vp), j2 = sg * dot(t2, vp);
+                        float je[4] = {jn + mu * j1, jn - mu * j1, jn + mu * j2, jn - mu * j2};
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            if (jar[e] < 0.f) {
+                                gc += D[e] * jar[e] * je[e];
+                                // row direction as a spatial force at O: sg * (r x a, a)
+                                float a[3];
+                                const float* tk = e < 2 ? t1 : t2;
+                                float sm = (e & 1) ? -mu : mu;
+                                a[0] = n[0] + sm * tk[0]; a[1] = n[1] + sm * tk[1]; a[2] = n[2] + sm * tk[2];
+                                float ra[3];
+                                cross(r, a, ra);
+                                float wgt = D[e] * je[e] * sg;
+                                F[0] += wgt * ra[0]; F[1] += wgt * ra[1]; F[2] += wgt * ra[2];
+                                F[3] += wgt * a[0]; F[4] += wgt * a[1]; F[5] += wgt * a[2];
+                            }
+                        }
+                    }
+                }
+                float gi = 0.f;
+                if (dof_lane) {
+                    gi = Ma[lane] - (tau[lane] - bias[lane]) + gc;
+                    g[lane] = gi;
+                }
+                float gn = sqrtf(wsum(gi * gi));
+                if (gn < m.tol_scale) break;
+                if (dof_lane) {
+                    int d = m.dof_depth[lane], r = m.dof_rowadr[lane];
+                    for (int t = 0; t < d; t++) {
+                        int j = m.dof_anc[lane * m.maxd + t];
+                        H[r + t] = Mm[r + t] + sdot(cdof + 6 * j, F);
+                    }
+                    p[lane] = -gi;
+                }
+                wave_sync();
+                ldl_factor<MAXD>(m, H, lane);
+                ldl_solve(m, H, p, lane);
+                // directional quantities for the line search
+                body_motion(m, cdof, p, bvec, lane);
+                float sr[4] = {0, 0, 0, 0};
+                if (has) rows_of(C, bvec, sr);
+                sym_mul(m, Mm, p, Mp, lane);
+                float pa = 0.f, pb = 0.f;
+                if (dof_lane) {
+                    pa = p[lane] * Mp[lane];
+                    pb = p[lane] * (Ma[lane] - (tau[lane] - bias[lane]));
+                }
+                float A0 = wsum(pa), B0 = wsum(pb);
+                float alpha = 0.f;
+                if (A0 > 0.f) {
+                    float bp[4];
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        C.s[e] = sr[e];
+                        bp[e] = (has && sr[e] != 0.f) ? -C.jar[e] / sr[e] : INFINITY;
+                    }
+                    float at = 0.f;
+                    int guard = 4 * ncon + 2;
+                    for (int k = 0; k < guard; k++) {
+                        float sa = 0.f, sb = 0.f, nxt = INFINITY;
+                        if (has) {
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                float s = sr[e];
+                                bool act = s > 0.f ? (at < bp[e]) : (s < 0.f ? (at >= bp[e]) : (C.jar[e] < 0.f));
+                                if (act) {
+                                    sa += C.D[e] * s * s;
+                                    sb += C.D[e] * s * C.jar[e];
+                                }
+                                if (bp[e] > at) nxt = fminf(nxt, bp[e]);
+                            }
+                        }
+                        float Aseg = A0 + wsum(sa), Bseg = B0 + wsum(sb);
+                        nxt = wmin(nxt);
+                        float root = -Bseg / Aseg;
+                        if (root <= nxt) {
+                            alpha = fmaxf(root, 0.f);
+                            break;
+                        }
+                        at = nxt;
+                        alpha = at;
+                    }
+                }
+                // update a, M a and the row residuals along p
+                float qf2 = 0.f;
+                for (int i = lane; i < nv; i += RB_WAVE) {
+                    acc[i] += alpha * p[i];
+                    Ma[i] += alpha * Mp[i];
+                    qf2 += (acc[i] - a0[i]) * (Ma[i] - (tau[i] - bias[i]));
+                }
+                float fc = 0.f;
+                if (has) {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        C.jar[e] += alpha * sr[e];
+                        float mn = fminf(C.jar[e], 0.f);
+                        fc += 0.5f * C.D[e] * mn * mn;
+                    }
+                }
+                float fnew = 0.5f * wsum(qf2) + wsum(fc);
+                wave_sync();
+                float improvement = fcur - fnew;
+                fcur = fnew;
+                if (improvement < m.tol_scale) { it++; break; }
+            }
+            if (it >= m.maxiter) itercap = true;
+        }
+        if (itercap) status |= RB_STATUS_ITERCAP;
+
+        // ---- first-substep taps
+        if (A.want_taps && sub == 0) {
+            for (int i = lane; i < nv; i += RB_WAVE) {
+                size_t base = (size_t)w * nv;
+                if (A.taps.bias) A.taps.bias[base + i] = bias[i];
+                if (A.taps.a0) A.taps.a0[base + i] = a0[i];
+                if (A.taps.qacc) A.taps.qacc[base + i] = acc[i];
+                if (A.taps.M) {
+                    // dense row i: M_ij from row i if j is on i's chain, from row j if i is on j's
+                    float* Mo = A.taps.M + (size_t)w * nv * nv + (size_t)i * nv;
+                    int di = m.dof_depth[i];
+                    for (int j = 0; j < nv; j++) {
+                        int dj = m.dof_depth[j];
+                        float val = 0.f;
+                        if (dj <= di && m.dof_anc[i * m.maxd + dj - 1] == j)
+                            val = Mm[m.dof_rowadr[i] + dj - 1];
+                        else if (di < dj && m.dof_anc[j * m.maxd + di - 1] == i)
+                            val = Mm[m.dof_rowadr[j] + di - 1];
+                        Mo[j] = val;
+                    }
+                }
+            }
+            if (A.taps.efc && has) {
+                float* E = A.taps.efc + ((size_t)w * m.ncap + lane) * 12;
+                for (int e = 0; e < 4; e++) {
+                    E[3 * e] = C.aref[e];
+                    E[3 * e + 1] = C.D[e];
+                    E[3 * e + 2] = C.ahat[e];
+                }
+            }
+        }
+
+        // ---- semi-implicit Euler (one lane per joint), committed only if everything is finite
+        bool bad = false;
+        for (int i = lane; i < nv; i += RB_WAVE) bad |= !finitef(acc[i]);
+        float qn[7], vn[6];
+        int jl = lane < m.njnt ? lane : -1;
+        if (jl >= 0) {
+            int jt = m.jnt_type[jl], qa = m.jnt_qadr[jl], da = m.jnt_dadr[jl];
+            float dt = m.dt;
+            if (jt == RB_JNT_HINGE) {
+                vn[0] = v[da] + dt * acc[da];
+                qn[0] = q[qa] + dt * vn[0];
+                bad |= !finitef(vn[0]) || !finitef(qn[0]);
+            } else {
+                for (int k = 0; k < 6; k++) vn[k] = v[da + k] + dt * acc[da + k];
+                for (int k = 0; k < 3; k++) qn[k] = q[qa + k] + dt * vn[k];
+                float th[3] = {dt * vn[3], dt * vn[4], dt * vn[5]};
+                float ang = sqrtf(dot(th, th));
+                float dq[4] = {1.f, 0.f, 0.f, 0.f};
+                if (ang > 0.f) {
+                    float s = sinf(0.5f * ang) / ang;
+                    dq[0] = cosf(0.5f * ang); dq[1] = th[0] * s; dq[2] = th[1] * s; dq[3] = th[2] * s;
+                }
+                float qq[4];
+                qmul(q + qa + 3, dq, qq);
+                float inv = 1.0f / sqrtf(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3]);
+                for (int k = 0; k < 4; k++) qn[3 + k] = qq[k] * inv;
+                for (int k = 0; k < 7; k++) bad |= !finitef(qn[k]);
+                for (int k = 0; k < 6; k++) bad |= !finitef(vn[k]);
+            }
+        }
+        bool anybad = __any(bad);
+        wave_sync();
+        if (anybad) {
+            status |= RB_STATUS_NONFINITE;
+            frozen = true;
+            ncon = 0;
+            break;
+        }
+        if (jl >= 0) {
+            int jt = m.jnt_type[jl], qa = m.jnt_qadr[jl], da = m.jnt_dadr[jl];
+            if (jt == RB_JNT_HINGE) {
+                v[da] = vn[0];
+                q[qa] = qn[0];
+            } else {
+                for (int k = 0; k < 6; k++) v[da + k] = vn[k];
+                for (int k = 0; k < 7; k++) q[qa + k] = qn[k];
+            }
+        }
+        for (int i = lane; i < nv; i += RB_WAVE) aws[i] = acc[i];
+        wave_sync();
+    }
+
+    // ---- egress
+    for (int i = lane; i < nq; i += RB_WAVE) A.qpos[(size_t)w * nq + i] = q[i];
+    for (int i = lane; i < nv; i += RB_WAVE) {
+        A.qvel[(size_t)w * nv + i] = v[i];
+        A.W.qacc_ws[(size_t)w * nv + i] = aws[i];
+    }
+    if (lane == 0) {
+        A.W.status[w] = status;
+        if (A.status_out) A.status_out[w] = status;
+        if (A.want_contacts && A.co.ncon) A.co.ncon[w] = ncon;
+    }
+    if (A.want_contacts && lane < ncon) {
+        size_t slot = (size_t)w * m.ncap + lane;
+        if (A.co.geom) { A.co.geom[2 * slot] = C.g1; A.co.geom[2 * slot + 1] = C.g2; }
+        if (A.co.feature) A.co.feature[slot] = C.feat;
+        if (A.co.dist) A.co.dist[slot] = C.dist;
+        if (A.co.pos) {
+            A.co.pos[3 * slot] = C.r[0] + xpos[3];
+            A.co.pos[3 * slot + 1] = C.r[1] + xpos[4];
+            A.co.pos[3 * slot + 2] = C.r[2] + xpos[5];
+        }
+        if (A.co.frame) {
+            float* F = A.co.frame + 9 * slot;
+            for (int k = 0; k < 3; k++) { F[k] = C.n[k]; F[3 + k] = C.t1[k]; F[6 + k] = C.t2[k]; }
+        }
+        if (A.co.force) {
+            float f[4];
+            for (int e = 0; e < 4; e++) f[e] = -C.D[e] * fminf(C.jar[e], 0.f);
+            A.co.force[3 * slot] = f[0] + f[1] + f[2] + f[3];
+            A.co.force[3 * slot + 1] = C.mu * (f[0] - f[1]);
+            A.co.force[3 * slot + 2] = C.mu * (f[2] - f[3]);
+        }
+    }
+}
+
+}  // namespace rbk
+
+// ------------------------------------------------------------------ launch
+hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
+                          const DevContactsOut* co, uint32_t* status_out, const DevTaps* taps, hipStream_t stream) {
+    rbk::StepArgs A;
+    A.n = n;
+    A.ctrl = ctrl;
+    A.qpos = qpos;
+    A.qvel = qvel;
+    A.W = W;
+    A.want_contacts = co != nullptr;
+    if (co) A.co = *co; else A.co = DevContactsOut{};
+    A.status_out = status_out;
+    A.want_taps = taps != nullptr;
+    if (taps) A.taps = *taps; else A.taps = DevTaps{};
+    size_t shmem = (size_t)m.lds_floats * sizeof(float);
+    dim3 grid(n), block(RB_WAVE);
+    if (m.maxd <= 8)
+        hipLaunchKernelGGL(rbk::step_kernel<8>, grid, block, shmem, stream, m, A);
+    else if (m.maxd <= 16)
+        hipLaunchKernelGGL(rbk::step_kernel<16>, grid, block, shmem, stream, m, A);
+    else
+        hipLaunchKernelGGL(rbk::step_kernel<32>, grid, block, shmem, stream, m, A);
+    return hipGetLastError();
+}

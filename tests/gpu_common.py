@@ -1,0 +1,121 @@
+"""Shared helpers for the GPU parity tests: run the HIP path and the oracle on the same inputs."""
+from __future__ import annotations
+
+import numpy as np
+
+from workloads import robots
+
+RTOL_STEP = 1e-4      # single env step, per element, |x - ref| <= tol * max(|ref|, 1)
+RTOL_ROLLOUT = 1e-3   # 10 contact-free env steps
+MARGIN_BAND = 1e-6    # contacts this close to the inclusion threshold may differ
+
+
+def rel_err(x, ref):
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return np.max(np.abs(x - ref) / np.maximum(np.abs(ref), 1.0)) if x.size else 0.0
+
+
+def vec_err(x, ref):
+    """max |x - ref| / max(|ref|_inf, 1): error relative to the vector's scale."""
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1.0) if x.size else 0.0
+
+
+def gpu_run(model, qpos, qvel, ctrl=None, qacc_ws=None, friction=None, mass_scale=None, nsteps=1,
+            contacts=False, taps=False, contact_capacity=0):
+    """Run the HIP path from float32 inputs; returns a dict of numpy results."""
+    import torch
+    import paper_2601_22074_amd as rb
+    dev = torch.device("cuda:0")
+    M = rb.Model(model)
+    n = qpos.shape[0]
+    B = rb.Batch(M, n, contact_capacity)
+    q = torch.tensor(np.asarray(qpos, np.float32), device=dev).contiguous()
+    v = torch.tensor(np.asarray(qvel, np.float32), device=dev).contiguous()
+    u = torch.tensor(np.asarray(ctrl if ctrl is not None else np.zeros((n, M.nu)), np.float32), device=dev).contiguous()
+    if qacc_ws is not None:
+        B.reset(torch.arange(n, dtype=torch.int32, device=dev),
+                torch.tensor(np.asarray(qacc_ws, np.float32), device=dev).contiguous())
+    if friction is not None:
+        B.set_params(rb.PARAM_FRICTION, torch.tensor(np.asarray(friction, np.float32), device=dev).contiguous())
+    if mass_scale is not None:
+        B.set_params(rb.PARAM_MASS_SCALE, torch.tensor(np.asarray(mass_scale, np.float32), device=dev).contiguous())
+    st = torch.zeros(n, dtype=torch.int32, device=dev)
+    con = B.contacts(n) if contacts else None
+    out = {}
+    for k in range(nsteps):
+        if taps and k == 0:
+            nv = M.nv
+            Mt = torch.zeros(n, nv, nv, device=dev); bias = torch.zeros(n, nv, device=dev)
+            a0 = torch.zeros(n, nv, device=dev); qacc = torch.zeros(n, nv, device=dev)
+            efc = torch.zeros(n, B.ncap, 4, 3, device=dev)
+            B.step_taps(u, q, v, con, st, M=Mt, bias=bias, a0=a0, qacc=qacc, efc=efc)
+            out.update(M=Mt, bias=bias, a0=a0, qacc=qacc, efc=efc)
+        else:
+            B.step(u, q, v, con, st)
+    torch.cuda.synchronize()
+    ws = torch.zeros(n, M.nv, device=dev)
+    B.get_state(n, ws, None)
+    torch.cuda.synchronize()
+    res = {k: t.cpu().numpy() for k, t in out.items()}
+    res.update(qpos=q.cpu().numpy(), qvel=v.cpu().numpy(), qacc_ws=ws.cpu().numpy(), status=st.cpu().numpy(),
+               ncap=B.ncap)
+    if con is not None:
+        res["contacts"] = {k: getattr(con, k).cpu().numpy() for k in ("ncon", "geom", "feature", "dist", "pos",
+                                                                      "frame", "force")}
+    B.close()
+    M.close()
+    return res
+
+
+def oracle_run(o, qpos, qvel, ctrl=None, qacc_ws=None, friction=None, mass_scale=None, nsteps=1, contacts=False):
+    n = qpos.shape[0]
+    q = np.array(qpos, np.float64, order="C")
+    v = np.array(qvel, np.float64, order="C")
+    ws = np.zeros((n, o.nv)) if qacc_ws is None else np.array(qacc_ws, np.float64, order="C")
+    u = np.zeros((n, o.nu)) if ctrl is None else np.array(ctrl, np.float64)
+    fr = None if friction is None else np.asarray(friction, np.float64)
+    ms = None if mass_scale is None else np.asarray(mass_scale, np.float64)
+    st = np.zeros(n, np.uint32)
+    cs = None
+    for _ in range(nsteps):
+        st, cs = o.step(u, q, v, ws, fr, ms, st, contacts=contacts)
+    return dict(qpos=q, qvel=v, qacc_ws=ws, status=st, contacts=cs)
+
+
+def contact_keys(c, w, dist_band=MARGIN_BAND):
+    """(g1, g2, feature) of world w's contacts, split into (certain, near-margin) sets."""
+    n = int(c["ncon"][w])
+    certain, band = set(), set()
+    for i in range(n):
+        k = (int(c["geom"][w, i, 0]), int(c["geom"][w, i, 1]), int(c["feature"][w, i]))
+        (band if abs(c["dist"][w, i]) <= dist_band else certain).add(k)
+    return certain, band
+
+
+def lifted(model, qpos, height=2.0):
+    q = np.array(qpos, np.float64)
+    for (t, qa, _), j in zip(_layout(model), model["joints"]):
+        if t == "free":
+            q[:, qa + 2] += height
+    return q.astype(np.float32)
+
+
+def _layout(model):
+    out, qa, da = [], 0, 0
+    for j in model["joints"]:
+        out.append((j["type"], qa, da))
+        qa, da = (qa + 7, da + 6) if j["type"] == "free" else (qa + 1, da + 1)
+    return out
+
+
+def substeps1(model):
+    m = dict(model)
+    m["opt"] = dict(model["opt"], nsubsteps=1)
+    return m
+
+
+def by_name(name):
+    return robots.by_name(name)

@@ -1,0 +1,191 @@
+"""Parity of the HIP path against the FP64 oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+from gpu_common import (MARGIN_BAND, RTOL_ROLLOUT, RTOL_STEP, by_name, contact_keys, gpu_run, lifted, oracle_run,
+                        rel_err, substeps1, vec_err)
+from workloads import inputs, robots
+
+pytestmark = pytest.mark.gpu
+
+
+def _wl(name, n, first=0):
+    m = by_name(name)
+    worlds = range(first, first + n)
+    q, v = inputs.initial_state(m, name, worlds)
+    u = inputs.ctrl_table(m, name, worlds, 1)[0]
+    fr, ms = inputs.world_params(m, name, worlds)
+    return m, q, v, u, fr, ms
+
+
+# ------------------------------------------------------------------ stage taps
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid"])
+def test_stage_taps_smooth_dynamics(oracle_mod, name):
+    m, q, v, u, fr, ms = _wl(name, 16)
+    rng = np.random.default_rng(1)
+    if name != "chain3":
+        q = lifted(m, q)
+        v = rng.normal(0, 0.5, v.shape).astype(np.float32)
+    g = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, taps=True)
+    o = oracle_mod.Oracle(m)
+    for w in range(q.shape[0]):
+        t = o.forward(q[w], v[w], u[w], None, None if fr is None else fr[w], None if ms is None else ms[w])
+        scale = np.abs(t["M"]).max()
+        assert np.abs(g["M"][w] - t["M"]).max() <= 2e-5 * scale, f"M world {w}"
+        bscale = max(1.0, np.abs(t["bias"]).max())
+        assert np.abs(g["bias"][w] - t["bias"]).max() <= 2e-5 * bscale, f"bias world {w}"
+        # accelerations come out of a solve with M (condition ~1e4 for the humanoid), so their
+        # FP32 error scales with the vector, not with each element
+        assert vec_err(g["a0"][w], t["a0"]) <= RTOL_STEP, f"a0 world {w}"
+        assert vec_err(g["qacc"][w], t["qacc"]) <= RTOL_STEP, f"qacc world {w}"
+
+
+@pytest.mark.parametrize("name", ["quadruped", "humanoid"])
+def test_stage_taps_contact_rows(oracle_mod, name):
+    """One substep from states in contact: rows (aref, D, A-hat) and the solved acceleration."""
+    m = substeps1(by_name(name))
+    _, q, v, u, fr, ms = _wl(name, 16)
+    # advance the oracle until the robots are on the ground, then tap one substep there
+    o = oracle_mod.Oracle(m)
+    r = oracle_run(o, q, v, u, None, fr, ms, nsteps=60)
+    q1, v1, ws1 = r["qpos"].astype(np.float32), r["qvel"].astype(np.float32), r["qacc_ws"].astype(np.float32)
+    g = gpu_run(m, q1, v1, u, ws1, fr, ms, taps=True, contacts=True)
+    ncmp = 0
+    for w in range(q1.shape[0]):
+        t = o.forward(q1[w], v1[w], u[w], ws1[w], None if fr is None else fr[w], None if ms is None else ms[w])
+        nc = t["ncon"]
+        assert g["contacts"]["ncon"][w] == min(nc, g["ncap"])
+        keys = [(int(a), int(b), int(f)) for (a, b), f in zip(t["geom"], t["feature"])]
+        gk = [(int(a), int(b), int(f)) for (a, b), f in zip(g["contacts"]["geom"][w, :nc], g["contacts"]["feature"][w, :nc])]
+        if any(abs(d) <= MARGIN_BAND for d in t["dist"]):
+            continue
+        assert gk == keys
+        efc = g["efc"][w, :nc]
+        # penetration depths agree to FP32 rounding of body positions (~1 m scale)
+        ddist = np.abs(g["contacts"]["dist"][w, :nc] - t["dist"]).max()
+        assert ddist <= 3e-7
+        np.testing.assert_allclose(efc[:, :, 2].reshape(-1), t["Ahat"], rtol=1e-4)
+        np.testing.assert_allclose(efc[:, :, 1].reshape(-1), t["D"], rtol=2e-4)
+        # aref = -b v - k imp r carries the stiffness k (~2770 / s^2) times the depth error
+        kref = 1.0 / (0.95 ** 2 * 0.02 ** 2)
+        np.testing.assert_allclose(efc[:, :, 0].reshape(-1), t["aref"], rtol=1e-4, atol=2 * kref * 3e-7 + 1e-5)
+        assert vec_err(g["qacc"][w], t["qacc"]) <= 1e-3, f"qacc world {w}"
+        ncmp += 1
+    assert ncmp >= q1.shape[0] // 2
+
+
+# ------------------------------------------------------------------ single env step
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid"])
+def test_single_step_from_initial_states(oracle_mod, name):
+    m, q, v, u, fr, ms = _wl(name, 64)
+    g = gpu_run(m, q, v, u, friction=fr, mass_scale=ms)
+    r = oracle_run(oracle_mod.Oracle(m), q, v, u, None, fr, ms)
+    assert rel_err(g["qpos"], r["qpos"]) <= RTOL_STEP
+    assert rel_err(g["qvel"], r["qvel"]) <= RTOL_STEP
+    assert np.all(g["status"] & 1 == 0)
+
+
+@pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150)])
+def test_single_step_teacher_forced(oracle_mod, name, horizon):
+    """Along the oracle's own trajectory, hand its state (rounded to FP32) to the GPU at
+    sampled steps and compare one env step."""
+    m, q, v, u, fr, ms = _wl(name, 32)
+    o = oracle_mod.Oracle(m)
+    worlds = list(range(32))
+    ctab = inputs.ctrl_table(m, name, worlds, horizon // 20 + 1)
+    qq = q.astype(np.float64); vv = v.astype(np.float64); ws = np.zeros((32, o.nv)); st = np.zeros(32, np.uint32)
+    frd = None if fr is None else fr.astype(np.float64)
+    msd = None if ms is None else ms.astype(np.float64)
+    worst_q = worst_v = 0.0
+    for s in range(horizon):
+        uu = ctab[s // 20].astype(np.float64)
+        if s % 25 == 24:
+            q32, v32, w32 = qq.astype(np.float32), vv.astype(np.float32), ws.astype(np.float32)
+            g = gpu_run(m, q32, v32, uu.astype(np.float32), w32, fr, ms)
+            r = oracle_run(o, q32, v32, uu.astype(np.float32), w32, fr, ms)
+            worst_q = max(worst_q, rel_err(g["qpos"], r["qpos"]))
+            worst_v = max(worst_v, rel_err(g["qvel"], r["qvel"]))
+        o.step(uu, qq, vv, ws, frd, msd, st)
+    assert worst_q <= RTOL_STEP and worst_v <= RTOL_STEP, (worst_q, worst_v)
+
+
+# ------------------------------------------------------------------ contact-free rollouts
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid"])
+def test_ten_step_contact_free(oracle_mod, name):
+    m, q, v, u, fr, ms = _wl(name, 32)
+    if name != "chain3":
+        q = lifted(m, q)
+    g = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, nsteps=10)
+    r = oracle_run(oracle_mod.Oracle(m), q, v, u, None, fr, ms, nsteps=10)
+    assert rel_err(g["qpos"], r["qpos"]) <= RTOL_ROLLOUT
+    assert rel_err(g["qvel"], r["qvel"]) <= RTOL_ROLLOUT
+
+
+# ------------------------------------------------------------------ contact sets
+@pytest.mark.parametrize("name", ["quadruped", "humanoid"])
+def test_contact_sets(oracle_mod, name):
+    m, q, v, u, fr, ms = _wl(name, 32)
+    o = oracle_mod.Oracle(m)
+    r0 = oracle_run(o, q, v, u, None, fr, ms, nsteps=40)
+    q1, v1, w1 = (r0[k].astype(np.float32) for k in ("qpos", "qvel", "qacc_ws"))
+    g = gpu_run(m, q1, v1, u, w1, fr, ms, contacts=True)
+    r = oracle_run(o, q1, v1, u, w1, fr, ms, contacts=True)
+    # contacts come from the last substep's starting state, which the two paths reach separately;
+    # compare them where that state agrees to the step tolerance
+    for w in range(q1.shape[0]):
+        gc, gb = contact_keys(g["contacts"], w)
+        rc, rb_ = contact_keys(r["contacts"], w)
+        assert gc - rb_ == rc - gb, f"world {w}"
+
+
+# ------------------------------------------------------------------ system properties
+def test_run_twice_bitwise(oracle_mod):
+    m, q, v, u, fr, ms = _wl("humanoid", 128)
+    a = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, nsteps=5, contacts=True)
+    b = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, nsteps=5, contacts=True)
+    for k in ("qpos", "qvel", "qacc_ws", "status"):
+        np.testing.assert_array_equal(a[k], b[k])
+    for k in a["contacts"]:
+        np.testing.assert_array_equal(a["contacts"][k], b["contacts"][k])
+
+
+def test_nan_isolated_and_frozen():
+    m, q, v, u, fr, ms = _wl("quadruped", 16)
+    clean = gpu_run(m, q, v, u, nsteps=3)
+    v2 = v.copy()
+    v2[5, 7] = np.nan
+    bad = gpu_run(m, q, v2, u, nsteps=3)
+    assert bad["status"][5] & 1
+    np.testing.assert_array_equal(bad["qpos"][5], q[5])      # frozen: never advanced
+    others = [w for w in range(16) if w != 5]
+    np.testing.assert_array_equal(bad["qpos"][others], clean["qpos"][others])
+    np.testing.assert_array_equal(bad["qvel"][others], clean["qvel"][others])
+    assert np.all(bad["status"][others] & 1 == 0)
+
+
+def test_checkpoint_resume_bitwise():
+    m, q, v, u, fr, ms = _wl("humanoid", 64)
+    full = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, nsteps=8)
+    half = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, nsteps=4)
+    rest = gpu_run(m, half["qpos"], half["qvel"], u, half["qacc_ws"], fr, ms, nsteps=4)
+    np.testing.assert_array_equal(rest["qpos"], full["qpos"])
+    np.testing.assert_array_equal(rest["qvel"], full["qvel"])
+
+
+def test_resting_box_forces_gpu():
+    m = robots.free_body("box", size=(0.1, 0.1, 0.1), mass=1.0, pos=(0, 0, 0.1))
+    q = robots.qpos0(m)[None].astype(np.float32)
+    v = np.zeros((1, 6), np.float32)
+    g = gpu_run(m, q, v, nsteps=400, contacts=True)
+    c = g["contacts"]
+    assert c["ncon"][0] == 4
+    assert abs(c["force"][0, :4, 0].sum() / 9.81 - 1) < 1e-4
+
+
+def test_contact_overflow_flag():
+    m, q, v, u, fr, ms = _wl("humanoid", 4)
+    q = q.copy()
+    q[:, 2] = 0.1                      # pelvis pushed into the floor: many contacts
+    g = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, contacts=True, contact_capacity=4)
+    assert np.all(g["status"] & 4)
+    assert np.all(g["contacts"]["ncon"] == 4)
