@@ -1,0 +1,294 @@
+"""Benchmark of the batched physics step on one MI355X.
+
+Default workload: the 29-hinge humanoid (free base, 30 bodies, 40 colliding geoms vs a
+plane), 8192 worlds, dt 5 ms x 4 substeps, Newton <= 4 iterations, per-world friction and
+mass scale, controls ~N(0, 0.2) resampled every 20 env steps, contacts returned every step.
+Inputs are synthetic and seeded (workloads/), resident on the GPU before timing starts.
+
+Prints one JSON line: env-steps/s over the timed steps, per-call p50/p99 latency, the
+roofline of the step kernel (FP32 ALU bound: algorithmic FLOPs per launch over the measured
+launch time, against the 157.3 TFLOP/s vector peak), HBM bytes and their fraction of 8 TB/s,
+and the FP64 oracle timed on this host's cores on a bounded sample (a baseline only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+WORKLOAD_TEXT = {
+    "humanoid": "humanoid: free base + 29 hinges, 30 bodies, 40 capsule/box geoms vs plane, dt 5 ms x 4 substeps, "
+                "Newton <= 4 iters, per-world friction U[0.3,1.2] and mass scale U[0.8,1.2], ctrl N(0,0.2)/20 steps",
+    "quadruped": "quadruped: free base + 12 hinges, 13 bodies, sphere feet + box torso vs plane, friction 1, "
+                 "PD kp 20 kd 0.5, dt 5 ms x 4 substeps, ctrl N(0,0.3)/20 steps",
+    "chain3": "3-link planar hinge chain, contact-free, dt 2 ms, K = 1",
+}
+
+
+# ------------------------------------------------------------------ work model
+def tree_info(model):
+    """Dof depths and per-body chain depths of a model description (bookkeeping only)."""
+    bodies, joints = model["bodies"], model["joints"]
+    nb = len(bodies)
+    bj = {j["body"]: j for j in joints}
+    last = [-1] * nb
+    depth = []
+    nfree = nhinge = 0
+    for b in range(1, nb):
+        p = bodies[b]["parent"]
+        pd = last[p]
+        j = bj.get(b)
+        if j is None:
+            last[b] = pd
+            continue
+        nd = 6 if j["type"] == "free" else 1
+        nfree += j["type"] == "free"
+        nhinge += j["type"] == "hinge"
+        for k in range(nd):
+            par = pd if k == 0 else len(depth) - 1
+            depth.append(1 if par < 0 else depth[par] + 1)
+        last[b] = len(depth) - 1
+    bdepth = [0 if last[b] < 0 else depth[last[b]] for b in range(nb)]
+    return dict(nb=nb, nv=len(depth), depth=depth, bdepth=bdepth, nfree=nfree, nhinge=nhinge,
+                nfixed=nb - 1 - nfree - nhinge, nM=sum(depth))
+
+
+def flops_per_env_step(model, stats_mean):
+    """Algorithmic FP32 operations of one env step of the tree-sparse method (multiply-add = 2).
+
+    stats_mean: per-substep means of (contacts, active rows, Newton iterations, line-search
+    segments), measured by the kernel's stats tap on a subset of the same worlds."""
+    t = tree_info(model)
+    nb, nv, nM = t["nb"], t["nv"], t["nM"]
+    dep = np.array(t["depth"])
+    nu = len(model["actuators"])
+    K = model["opt"]["nsubsteps"]
+    con, rows, iters, segs = stats_mean
+    # pairs and colliding-body chain depth
+    caps = []
+    cdepth = []
+    for g in model["geoms"]:
+        if g["type"] == "plane" or g["contype"] == 0:
+            continue
+        caps.append({"sphere": 1, "capsule": 2, "box": 8}[g["type"]])
+        cdepth.append(t["bdepth"][g["body"]])
+    npair = len(caps)
+    d_c = float(np.mean(cdepth)) if cdepth else 0.0
+    ldl = float(np.sum(1.5 * (dep - 1) * dep + dep))
+    solve = 4.0 * (nM - nv) + nv
+    msum = 4.0 * (nM - nv) + 2 * nv
+    bm = 12.0 * sum(t["bdepth"])
+    smooth = (5 * nu + 190 * t["nhinge"] + 60 * t["nfree"] + 46 * t["nfixed"] + 170 * (nb - 1)
+              + 42 * t["nhinge"] + 27 * t["nfree"] + 54 * t["nhinge"] + 198 * t["nfree"] + 124 * (nb - 1)
+              + 48 * nv + 11 * nM + ldl + solve + nv + 4 * nv + 60 * t["nfree"])
+    coll = sum(186 + 25 * c for c in caps) + con * (186 + 25 * (np.mean(caps) if caps else 0) + 28)
+    rowsf = con * (42 * d_c + 3 * d_c * d_c + 100)
+    newton = 0.0
+    if con > 0:
+        init = 2 * bm + 2 * con * 46 + msum + 6 * nv
+        per_it = (con * d_c * 35 + rows * d_c * 30 + 3 * nv + 11 * nM + ldl + solve + bm + 30 * con + msum
+                  + 4 * nv + 6 * nv + 20 * con)
+        per_seg = 32 * con + 10
+        newton = init + iters * per_it + segs * per_seg
+    return K * (smooth + coll + rowsf + newton)
+
+
+def hbm_bytes_per_env_step(model, con_last, contacts_on):
+    t = tree_info(model)
+    nq = sum(7 if j["type"] == "free" else 1 for j in model["joints"])
+    nv, nb = t["nv"], t["nb"]
+    nu = len(model["actuators"])
+    pw = model["per_world"]
+    rd = 4 * (nq + nv + nu + nv + 1) + (4 if pw.get("friction") else 0) + (4 * nb if pw.get("mass_scale") else 0)
+    wr = 4 * (nq + nv + nv + 1)
+    if contacts_on:
+        wr += 4 + con_last * 4 * (2 + 1 + 1 + 3 + 9 + 3)
+    return rd + wr
+
+
+# ------------------------------------------------------------------ CPU baseline
+def cpu_baseline(W, budget_s=12.0):
+    """The FP64 oracle on the host cores (OpenMP over worlds) over a bounded sample."""
+    from oracle import Oracle
+    m = W["model"]
+    o = Oracle(m)
+    cores = os.cpu_count() or 1
+    nw = min(len(W["worlds"]), 512 if W["name"] == "humanoid" else 2048)
+    q = W["qpos"][:nw].astype(np.float64)
+    v = W["qvel"][:nw].astype(np.float64)
+    ws = np.zeros_like(v)
+    fr = None if W["friction"] is None else W["friction"][:nw].astype(np.float64)
+    ms = None if W["mass_scale"] is None else W["mass_scale"][:nw].astype(np.float64)
+    st = np.zeros(nw, np.uint32)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < W["nsteps"]:
+        u = W["ctrl"][done // 20][:nw].astype(np.float64)
+        o.step(u, q, v, ws, fr, ms, st, nthreads=cores)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": nw * done / dt, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nw} worlds x {done} env steps of the same workload from the same initial states, "
+                      f"FP64, OpenMP over worlds, {dt:.1f} s"}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("step_kernel.hip", "rb_internal.h"):
+        with open(os.path.join(ROOT, "paper_2601_22074_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name, nworlds):
+    """HBM bytes per launch from committed PMC counters, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"step_kernel_{name}_x{nworlds}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+# ------------------------------------------------------------------ main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="humanoid", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--worlds", type=int, default=None)
+    ap.add_argument("--no-contacts", action="store_true", help="do not return contacts")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--stats-worlds", type=int, default=512)
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: worlds are independent and this build runs on a single MI355X; "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2601_22074_amd as rb
+    from workloads import inputs
+
+    default_worlds = {"humanoid": 8192, "quadruped": 4096, "chain3": 64}
+    nw = args.worlds or default_worlds[args.workload]
+    K, warm = args.steps, args.warmup
+    W = inputs.workload(args.workload, nw, warm + K)
+    m = W["model"]
+    dev = torch.device("cuda:0")
+    model = rb.Model(m)
+    batch = rb.Batch(model, nw)
+    q = torch.tensor(W["qpos"], device=dev)
+    v = torch.tensor(W["qvel"], device=dev)
+    ctab = torch.tensor(W["ctrl"], device=dev).contiguous()
+    if W["friction"] is not None:
+        batch.set_params(rb.PARAM_FRICTION, torch.tensor(W["friction"], device=dev))
+    if W["mass_scale"] is not None:
+        batch.set_params(rb.PARAM_MASS_SCALE, torch.tensor(W["mass_scale"], device=dev))
+    status = torch.zeros(nw, dtype=torch.int32, device=dev)
+    con = None if args.no_contacts else batch.contacts(nw)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calib_mb:
+        a = torch.empty(args.copy_calib_mb * 2 ** 20 // 4, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    def ctrl_at(s):
+        return ctab[min(s // inputs.CTRL_PERIOD, ctab.shape[0] - 1)]
+
+    for s in range(warm):
+        batch.step(ctrl_at(s), q, v, con, status)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(K):
+        batch.step(ctrl_at(warm + s), q, v, con, status)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(K)])  # ms, on the kernel's stream
+    total_ms = ev[0].elapsed_time(ev[K])
+    value = nw * K / (total_ms / 1e3)
+    st = status.cpu().numpy()
+    ncon_last = float(con.ncon.float().mean().item()) if con is not None else float("nan")
+
+    # work statistics on a subset of the same worlds, replayed untimed from the same inputs
+    ns = min(args.stats_worlds, nw)
+    sub = rb.Batch(model, ns)
+    qs = torch.tensor(W["qpos"][:ns], device=dev)
+    vs = torch.tensor(W["qvel"][:ns], device=dev)
+    if W["friction"] is not None:
+        sub.set_params(rb.PARAM_FRICTION, torch.tensor(W["friction"][:ns], device=dev))
+    if W["mass_scale"] is not None:
+        sub.set_params(rb.PARAM_MASS_SCALE, torch.tensor(W["mass_scale"][:ns], device=dev))
+    stats = torch.zeros(ns, 4, dtype=torch.int32, device=dev)
+    acc = np.zeros(4)
+    for s in range(warm + K):
+        sub.step_taps(ctab[min(s // inputs.CTRL_PERIOD, ctab.shape[0] - 1)][:ns].contiguous(), qs, vs, stats=stats)
+        if s >= warm:
+            acc += stats.sum(0).cpu().numpy()
+    Ksub = m["opt"]["nsubsteps"]
+    stats_mean = acc / (ns * K * Ksub)          # per substep per world
+    fl = flops_per_env_step(m, stats_mean)
+    hb = hbm_bytes_per_env_step(m, ncon_last if con is not None else 0, con is not None)
+    launch_s = float(np.mean(per)) / 1e3
+    achieved_tf = fl * nw / launch_s / 1e12
+    traffic = load_traffic(args.workload, nw)
+
+    out = {
+        "metric": "env-steps/sec, 29-DoF humanoid x8192 worlds; p50/p99 rollout latency"
+        if args.workload == "humanoid" else f"env-steps/sec, {args.workload} x{nw} worlds",
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": warm,
+        "ms_per_step": total_ms / K,
+        "p50_ms": float(np.percentile(per, 50)),
+        "p99_ms": float(np.percentile(per, 99)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "worlds": nw, "env_steps": K,
+                   "substeps": Ksub, "contacts_returned": con is not None},
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / PEAK_FP32_TFLOPS,
+                     "traffic": None if traffic is None else traffic,
+                     "flops_per_env_step": fl, "launch_ms": launch_s * 1e3},
+        "hbm": {"algorithmic_bytes_per_env_step": hb, "achieved_GBs": hb * nw / launch_s / 1e9,
+                "peak_GBs": PEAK_HBM_GBS, "frac": hb * nw / launch_s / 1e9 / PEAK_HBM_GBS},
+        "work_per_substep": {"contacts": stats_mean[0], "active_rows": stats_mean[1],
+                             "newton_iters": stats_mean[2], "line_search_segments": stats_mean[3]},
+        "nonfinite_worlds": int(np.sum(st & 1)),
+        "wall_s": wall,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

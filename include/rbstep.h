@@ -141,14 +141,16 @@ int rb_get_state(const rb_batch* batch, int32_t n, float* dev_qacc_ws, uint32_t*
 int rb_step(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
             const rb_contacts* contacts, uint32_t* dev_status, void* hip_stream);
 
-/* Diagnostic taps of the first substep of one step of slots [0, n), for parity checks:
- * the same computation as rb_step (and it advances the state the same way), plus per world
- * dev_M [n, nv, nv] joint-space inertia, dev_bias [n, nv] bias forces c(q, v),
- * dev_a0 [n, nv] smooth acceleration, dev_qacc [n, nv] constrained acceleration of the
- * first substep, dev_efc [n, cap, 4, 3] per pyramid row (aref, D, A-hat).  Any may be NULL. */
+/* Diagnostic taps of the first substep of one step of slots [0, n), for parity checks and
+ * work accounting: the same computation as rb_step (and it advances the state the same
+ * way), plus per world dev_M [n, nv, nv] joint-space inertia, dev_bias [n, nv] bias forces
+ * c(q, v), dev_a0 [n, nv] smooth acceleration, dev_qacc [n, nv] constrained acceleration of
+ * the first substep, dev_efc [n, cap, 4, 3] per pyramid row (aref, D, A-hat), and
+ * dev_stats [n, 4] int32 totals over the K substeps (contacts, pyramid rows active at the
+ * solution, Newton iterations, line-search segments).  Any output may be NULL. */
 int rb_step_taps(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
                  const rb_contacts* contacts, uint32_t* dev_status, float* dev_M, float* dev_bias,
-                 float* dev_a0, float* dev_qacc, float* dev_efc, void* hip_stream);
+                 float* dev_a0, float* dev_qacc, float* dev_efc, int32_t* dev_stats, void* hip_stream);
 
 #ifdef __cplusplus
 }

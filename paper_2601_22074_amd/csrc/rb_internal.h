@@ -111,4 +111,5 @@ struct DevTaps {
     float* a0;
     float* qacc;
     float* efc;
+    int32_t* stats;
 };

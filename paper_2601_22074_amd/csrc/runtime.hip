@@ -630,8 +630,9 @@ int rb_step(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* qvel,
 }
 
 int rb_step_taps(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* qvel, const rb_contacts* c,
-                 uint32_t* status, float* M, float* bias, float* a0, float* qacc, float* efc, void* stream) {
-    DevTaps t{M, bias, a0, qacc, efc};
+                 uint32_t* status, float* M, float* bias, float* a0, float* qacc, float* efc, int32_t* stats,
+                 void* stream) {
+    DevTaps t{M, bias, a0, qacc, efc, stats};
     return step_impl(b, n, ctrl, qpos, qvel, c, status, &t, stream);
 }
 

@@ -415,6 +415,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
 
     Con C;
     int ncon = 0;
+    int st_con = 0, st_rows = 0, st_iter = 0, st_seg = 0;   // work totals for the stats tap
     bool frozen = (status & RB_STATUS_NONFINITE) != 0;
     status &= ~(uint32_t)(RB_STATUS_ITERCAP | RB_STATUS_CONOVERFLOW);
 
@@ -823,6 +824,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                     float at = 0.f;
                     int guard = 4 * ncon + 2;
                     for (int k = 0; k < guard; k++) {
+                        st_seg++;
                         float sa = 0.f, sb = 0.f, nxt = INFINITY;
                         if (has) {
 #pragma unroll
@@ -870,7 +872,13 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                 if (improvement < m.tol_scale) { it++; break; }
             }
             if (it >= m.maxiter) itercap = true;
+            st_iter += it;
+            int act = 0;
+            if (has)
+                for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f;
+            st_rows += (int)wsum((float)act);
         }
+        st_con += ncon;
         if (itercap) status |= RB_STATUS_ITERCAP;
 
         // ---- first-substep taps
@@ -962,6 +970,10 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
     for (int i = lane; i < nv; i += RB_WAVE) {
         A.qvel[(size_t)w * nv + i] = v[i];
         A.W.qacc_ws[(size_t)w * nv + i] = aws[i];
+    }
+    if (A.want_taps && A.taps.stats && lane == 0) {
+        int32_t* S = A.taps.stats + (size_t)w * 4;
+        S[0] = st_con; S[1] = st_rows; S[2] = st_iter; S[3] = st_seg;
     }
     if (lane == 0) {
         A.W.status[w] = status;

@@ -88,7 +88,7 @@ def lib():
         L.rb_world_reset.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.rb_get_state.argtypes = [vp, C.c_int32, vp, vp, vp]
         L.rb_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp]
-        L.rb_step_taps.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp, vp, vp, vp, vp, vp]
+        L.rb_step_taps.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -273,7 +273,7 @@ class Batch:
         _check(lib().rb_step(self._h, int(n), pc, pq, pv, cs, ps, _stream(stream)))
 
     def step_taps(self, ctrl, qpos, qvel, contacts=None, status=None, M=None, bias=None, a0=None, qacc=None,
-                  efc=None, stream=None) -> None:
+                  efc=None, stats=None, stream=None) -> None:
         import torch
         n, pc, pq, pv, ps = self._common(ctrl, qpos, qvel, status)
         nv = self.model.nv
@@ -281,4 +281,5 @@ class Batch:
         _check(lib().rb_step_taps(self._h, int(n), pc, pq, pv, cs, ps,
                                   _ptr(M, torch.float32, (n, nv, nv), "M"), _ptr(bias, torch.float32, (n, nv), "bias"),
                                   _ptr(a0, torch.float32, (n, nv), "a0"), _ptr(qacc, torch.float32, (n, nv), "qacc"),
-                                  _ptr(efc, torch.float32, (n, self.ncap, 4, 3), "efc"), _stream(stream)))
+                                  _ptr(efc, torch.float32, (n, self.ncap, 4, 3), "efc"),
+                                  _ptr(stats, torch.int32, (n, 4), "stats"), _stream(stream)))
