@@ -241,14 +241,16 @@ def main():
         sub.set_params(rb.PARAM_FRICTION, torch.tensor(W["friction"][:ns], device=dev))
     if W["mass_scale"] is not None:
         sub.set_params(rb.PARAM_MASS_SCALE, torch.tensor(W["mass_scale"][:ns], device=dev))
-    stats = torch.zeros(ns, 4, dtype=torch.int32, device=dev)
-    acc = np.zeros(4)
+    stats = torch.zeros(ns, rb.rbstep.NSTATS, dtype=torch.int32, device=dev)
+    acc = np.zeros(rb.rbstep.NSTATS)
     for s in range(warm + K):
         sub.step_taps(ctab[min(s // inputs.CTRL_PERIOD, ctab.shape[0] - 1)][:ns].contiguous(), qs, vs, stats=stats)
         if s >= warm:
-            acc += stats.sum(0).cpu().numpy()
+            acc += stats.double().sum(0).cpu().numpy()
     Ksub = m["opt"]["nsubsteps"]
-    stats_mean = acc / (ns * K * Ksub)          # per substep per world
+    stats_mean = acc[:4] / (ns * K * Ksub)      # per substep per world
+    cyc = acc[4:]
+    stage_share = {n: float(c / cyc.sum()) for n, c in zip(rb.rbstep.STAGES, cyc)} if cyc.sum() > 0 else {}
     fl = flops_per_env_step(m, stats_mean)
     hb = hbm_bytes_per_env_step(m, ncon_last if con is not None else 0, con is not None)
     launch_s = float(np.mean(per)) / 1e3
@@ -281,6 +283,7 @@ def main():
                 "peak_GBs": PEAK_HBM_GBS, "frac": hb * nw / launch_s / 1e9 / PEAK_HBM_GBS},
         "work_per_substep": {"contacts": stats_mean[0], "active_rows": stats_mean[1],
                              "newton_iters": stats_mean[2], "line_search_segments": stats_mean[3]},
+        "stage_cycle_share": stage_share,
         "nonfinite_worlds": int(np.sum(st & 1)),
         "wall_s": wall,
         "kernel_source_hash": kernel_source_hash(),

@@ -146,8 +146,11 @@ int rb_step(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_qpos, 
  * way), plus per world dev_M [n, nv, nv] joint-space inertia, dev_bias [n, nv] bias forces
  * c(q, v), dev_a0 [n, nv] smooth acceleration, dev_qacc [n, nv] constrained acceleration of
  * the first substep, dev_efc [n, cap, 4, 3] per pyramid row (aref, D, A-hat), and
- * dev_stats [n, 4] int32 totals over the K substeps (contacts, pyramid rows active at the
- * solution, Newton iterations, line-search segments).  Any output may be NULL. */
+ * dev_stats [n, 14] int32 totals over the K substeps: contacts, pyramid rows active at the
+ * solution, Newton iterations, line-search segments, then shader-clock cycles / 16 spent in
+ * ten stages (kinematics; inertia, bias forces and M; factorisation of M and a0;
+ * collision; constraint rows; Newton start; gradient and Hessian; Hessian factorisation
+ * and solve; line search and update; integration).  Any output may be NULL. */
 int rb_step_taps(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
                  const rb_contacts* contacts, uint32_t* dev_status, float* dev_M, float* dev_bias,
                  float* dev_a0, float* dev_qacc, float* dev_efc, int32_t* dev_stats, void* hip_stream);

@@ -10,6 +10,8 @@
 #define RB_MAX_DOF 64
 #define RB_MAX_PAIR 64
 #define RB_MAX_CON 64
+#define RB_NSTAGE 10              // timed kernel stages in the stats tap
+#define RB_NSTATS (4 + RB_NSTAGE) // stats tap columns per world
 
 struct DevModel {
     // sizes
@@ -50,6 +52,7 @@ struct DevModel {
     const int* dof_depth;      // chain length including the dof itself
     const int* dof_rowadr;     // start of the dof's row in the packed matrices
     const int* dof_anc;        // [nv * maxd] dof at chain position t (root first), -1 padded
+    const uint64_t* dof_descmask;  // bit k set iff dof k is a strict descendant of the dof
     const int* desc_start;     // [nv + 1] CSR of strict descendants
     const int* desc_list;
     const int* dlevel_start;   // [ndlevel + 2] CSR of dofs by depth, depths 1..ndlevel
@@ -83,7 +86,7 @@ struct DevModel {
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
     int o_xpos, o_xquat, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
     int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp;
-    int o_M, o_H, o_misc;
+    int o_M, o_H, o_misc, o_piv;
     int lds_floats;
 };
 

@@ -233,6 +233,9 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             if (P(c) == b) ch_list.push_back(c);
     }
     ch_start[nb] = (int)ch_list.size();
+    std::vector<uint64_t> dmask(nv, 0);
+    for (int i = 0; i < nv; i++)
+        for (int c = desc_start[i]; c < desc_start[i + 1]; c++) dmask[i] |= 1ull << desc_list[c];
     std::vector<uint64_t> cmask(nb, 0);
     for (int b = 1; b < nb; b++) {
         if (blast[b] < 0) continue;
@@ -434,6 +437,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     F(std::vector<double>(d->body_inertia, d->body_inertia + 3 * nb), &m.body_inertia);
     F(jpos, &m.body_jpos); F(jax, &m.body_jaxis);
     size_t off_mask = B.add_u64(cmask);
+    size_t off_dmask = B.add_u64(dmask);
     I(lv_start, &m.level_start); I(lv_body, &m.level_body); I(ch_start, &m.child_start); I(ch_list, &m.child_list);
     I(dof_body, &m.dof_body); I(dof_depth, &m.dof_depth); I(rowadr, &m.dof_rowadr); I(anc, &m.dof_anc);
     I(desc_start, &m.desc_start); I(desc_list, &m.desc_list); I(dl_start, &m.dlevel_start); I(dl_dof, &m.dlevel_dof);
@@ -459,6 +463,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     char* base = (char*)dev;
     for (auto& f : fx) *f.field = base + 4 * f.off;
     m.body_chainmask = (const uint64_t*)(base + 4 * off_mask);
+    m.dof_descmask = (const uint64_t*)(base + 4 * off_dmask);
     // sizes and options
     m.nbody = nb; m.nv = nv; m.nq = nq; m.nu = nu; m.njnt = nj; m.npair = npair;
     m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.K = d->nsubsteps; m.maxiter = d->iterations;
@@ -479,7 +484,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.o_bvec = sec(6 * nb); m.o_bvec2 = sec(6 * nb);
     m.o_tau = sec(nv); m.o_bias = sec(nv); m.o_a0 = sec(nv); m.o_a = sec(nv); m.o_Ma = sec(nv);
     m.o_g = sec(nv); m.o_p = sec(nv); m.o_Mp = sec(nv); m.o_tmp = sec(nv);
-    m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16);
+    m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16); m.o_piv = sec(36);
     m.lds_floats = o;
     m.ncap = std::min(maxcon, RB_MAX_CON);
     M->blob = dev;

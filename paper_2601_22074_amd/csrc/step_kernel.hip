@@ -226,6 +226,86 @@ DEV void body_motion(const DevModel& m, const float* cdof, const float* x, float
     wave_sync();
 }
 
+// ------------------------------------------------------------------ register-resident L'DL
+// Per-lane constants of the dof held by the lane (lanes >= nv: depth 0).
+template <int MAXD>
+struct DofLane {
+    int depth;             // chain length including the dof
+    int rowadr;            // start of its row in the packed matrices
+    uint64_t descmask;     // strict descendants
+    uint32_t anc[MAXD / 4];   // chain dofs, root first, one byte each
+    DEV int ancestor(int t) const { return (int)((anc[t >> 2] >> (8 * (t & 3))) & 0xffu); }
+};
+
+template <int MAXD>
+DEV DofLane<MAXD> load_dof_lane(const DevModel& m, int lane) {
+    DofLane<MAXD> D;
+    bool on = lane < m.nv;
+    D.depth = on ? m.dof_depth[lane] : 0;
+    D.rowadr = on ? m.dof_rowadr[lane] : 0;
+    D.descmask = on ? m.dof_descmask[lane] : 0ull;
+#pragma unroll
+    for (int w = 0; w < MAXD / 4; w++) D.anc[w] = 0u;
+#pragma unroll
+    for (int t = 0; t < MAXD; t++) {
+        int a = (on && t < D.depth) ? m.dof_anc[lane * m.maxd + t] : 0;
+        D.anc[t >> 2] |= (uint32_t)a << (8 * (t & 3));
+    }
+    return D;
+}
+
+// Factor the tree-sparse matrix whose row i (chain positions, root first) sits in lane i's
+// registers Hr, as L'DL, and solve (L'DL) x = b for the lane's right-hand side bi.
+// Leaves first: the pivot lane k publishes its row, its right-hand side y_k and 1/D_k in the
+// LDS buffer piv; every lane reads the row back with broadcast loads and its own multiplier
+// l_i = H_ki / D_k with one addressed load (0 for lanes that are not ancestors of k), then
+// applies H_i. -= l_i H_k. and b_i -= l_i y_k (the L' solve rides along).  Updates land only
+// in positions a lane never reads as data, so no lane masking is needed.  Rows stay unscaled:
+// L_ij = H_ij / D_i is applied in the L solve, which runs by depth level with one cross-lane
+// shuffle per level.  On return Hr holds the unscaled factor rows, *inv_out = 1/D_i; returns x_i.
+template <int MAXD>
+DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MAXD], float bi, int lane,
+                       float* piv, float* inv_out) {
+    float inv_self = 0.f;
+    const int di = D.depth;
+    const int a = di - 1;
+    for (int k = m.nv - 1; k >= 0; k--) {
+        const int dk = __builtin_amdgcn_readlane(di, k);
+        if (lane == k) {
+#pragma unroll
+            for (int t = 0; t < MAXD; t++) piv[t] = Hr[t];
+            piv[MAXD] = bi;
+        }
+        wave_sync();
+        float hk[MAXD];
+#pragma unroll
+        for (int t = 0; t < MAXD; t++) hk[t] = piv[t];
+        const float yk = piv[MAXD];
+        const float d = piv[dk - 1];
+        const bool anc = (D.descmask >> k) & 1ull;
+        const float hka = anc ? piv[a < 0 ? 0 : a] : 0.f;
+        wave_sync();
+        const float inv = __builtin_amdgcn_rcpf(d);
+        if (lane == k) inv_self = inv;
+        const float l = hka * inv;
+#pragma unroll
+        for (int b = 0; b < MAXD; b++)
+            if (b < dk - 1) Hr[b] -= l * hk[b];
+        bi -= l * yk;
+    }
+    const float z = bi * inv_self;
+    float acc = 0.f, x = 0.f;
+#pragma unroll
+    for (int t = 0; t < MAXD; t++) {
+        if (t >= m.ndlevel) break;
+        if (di == t + 1) x = z - acc * inv_self;
+        const float xa = __shfl(x, D.ancestor(t));
+        if (di > t + 1) acc += Hr[t] * xa;
+    }
+    *inv_out = inv_self;
+    return x;
+}
+
 // ------------------------------------------------------------------ contacts (one per lane)
 struct Con {
     float r[3];            // contact point relative to O
@@ -392,8 +472,10 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
     float* Mm = L + m.o_M;
     float* H = L + m.o_H;
     float* misc = L + m.o_misc;
+    float* piv = L + m.o_piv;
 
     const int nq = m.nq, nv = m.nv, nu = m.nu, nb = m.nbody;
+    const DofLane<MAXD> DL = load_dof_lane<MAXD>(m, lane);
     // ---- ingress
     for (int i = lane; i < nq; i += RB_WAVE) q[i] = A.qpos[(size_t)w * nq + i];
     for (int i = lane; i < nv; i += RB_WAVE) {
@@ -416,6 +498,14 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
     Con C;
     int ncon = 0;
     int st_con = 0, st_rows = 0, st_iter = 0, st_seg = 0;   // work totals for the stats tap
+    uint64_t stage_cyc[RB_NSTAGE] = {};                          // cycles per stage (stats tap)
+    uint64_t t_mark = clock64();
+#define RB_STAGE(id)                                    \
+    do {                                                \
+        uint64_t t_now = clock64();                     \
+        stage_cyc[id] += t_now - t_mark;                \
+        t_mark = t_now;                                 \
+    } while (0)
     bool frozen = (status & RB_STATUS_NONFINITE) != 0;
     status &= ~(uint32_t)(RB_STATUS_ITERCAP | RB_STATUS_CONOVERFLOW);
 
@@ -473,6 +563,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             }
             wave_sync();
         }
+        RB_STAGE(0);
         const float O[3] = {xpos[3], xpos[4], xpos[5]};
         // ---- spatial inertias about O, motion subspaces of the dofs
         for (int b = 1 + lane; b < nb; b += RB_WAVE) {
@@ -594,10 +685,25 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             a0[i] = tau[i] - bias[i];
         }
         wave_sync();
-        for (int e = lane; e < m.nM; e += RB_WAVE) H[e] = Mm[e];
-        wave_sync();
-        ldl_factor<MAXD>(m, H, lane);
-        ldl_solve(m, H, a0, lane);
+        RB_STAGE(1);
+        {
+            // factor M with a0 = M^-1 (tau - c) solved in the same sweep; keep the factor in H
+            float Hr[MAXD];
+#pragma unroll
+            for (int t = 0; t < MAXD; t++) Hr[t] = t < DL.depth ? Mm[DL.rowadr + t] : 0.f;
+            float invd;
+            float x = factor_solve<MAXD>(m, DL, Hr, lane < nv ? a0[lane] : 0.f, lane, piv, &invd);
+            if (lane < nv) {
+                // packed factor for the contact rows: L (scaled) off the diagonal, D on it
+                a0[lane] = x;
+#pragma unroll
+                for (int t = 0; t < MAXD; t++)
+                    if (t < DL.depth - 1) H[DL.rowadr + t] = Hr[t] * invd;
+                H[DL.rowadr + DL.depth - 1] = 1.0f / invd;
+            }
+            wave_sync();
+        }
+        RB_STAGE(2);
 
         // ---- collision: count per pair, scan, then each contact lane rebuilds its contact
         int cnt = 0;
@@ -634,6 +740,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             C.mu = m.fr_pw ? mu_world : m.pair_mu[src];
             C.margin = m.pair_margin[src];
         }
+        RB_STAGE(3);
         // ---- constraint rows: exact A-hat from the chain half-solve with M's factor
         if (has) {
             float X[MAXD][3];
@@ -693,6 +800,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             }
         }
 
+        RB_STAGE(4);
         // ---- primal Newton solve
         bool itercap = false;
         if (ncon == 0) {
@@ -740,6 +848,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
 #pragma unroll
             for (int e = 0; e < 4; e++) C.jar[e] = use_ws ? jw[e] : j0[e];
             wave_sync();
+            RB_STAGE(5);
 
             int it = 0;
             for (; it < m.maxiter; it++) {
@@ -791,17 +900,21 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                 }
                 float gn = sqrtf(wsum(gi * gi));
                 if (gn < m.tol_scale) break;
-                if (dof_lane) {
-                    int d = m.dof_depth[lane], r = m.dof_rowadr[lane];
-                    for (int t = 0; t < d; t++) {
-                        int j = m.dof_anc[lane * m.maxd + t];
-                        H[r + t] = Mm[r + t] + sdot(cdof + 6 * j, F);
-                    }
-                    p[lane] = -gi;
+                // Hessian row in registers: H_ij = M_ij + S_j . F_i over the chain of i
+                float Hr[MAXD];
+#pragma unroll
+                for (int t = 0; t < MAXD; t++) {
+                    Hr[t] = 0.f;
+                    if (t < DL.depth) Hr[t] = Mm[DL.rowadr + t] + sdot(cdof + 6 * DL.ancestor(t), F);
                 }
-                wave_sync();
-                ldl_factor<MAXD>(m, H, lane);
-                ldl_solve(m, H, p, lane);
+                RB_STAGE(6);
+                {
+                    float invd;
+                    float x = factor_solve<MAXD>(m, DL, Hr, -gi, lane, piv, &invd);
+                    if (dof_lane) p[lane] = x;
+                    wave_sync();
+                }
+                RB_STAGE(7);
                 // directional quantities for the line search
                 body_motion(m, cdof, p, bvec, lane);
                 float sr[4] = {0, 0, 0, 0};
@@ -869,6 +982,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                 wave_sync();
                 float improvement = fcur - fnew;
                 fcur = fnew;
+                RB_STAGE(8);
                 if (improvement < m.tol_scale) { it++; break; }
             }
             if (it >= m.maxiter) itercap = true;
@@ -879,6 +993,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             st_rows += (int)wsum((float)act);
         }
         st_con += ncon;
+        RB_STAGE(6);
         if (itercap) status |= RB_STATUS_ITERCAP;
 
         // ---- first-substep taps
@@ -963,6 +1078,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
         }
         for (int i = lane; i < nv; i += RB_WAVE) aws[i] = acc[i];
         wave_sync();
+        RB_STAGE(9);
     }
 
     // ---- egress
@@ -972,8 +1088,9 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
         A.W.qacc_ws[(size_t)w * nv + i] = aws[i];
     }
     if (A.want_taps && A.taps.stats && lane == 0) {
-        int32_t* S = A.taps.stats + (size_t)w * 4;
+        int32_t* S = A.taps.stats + (size_t)w * RB_NSTATS;
         S[0] = st_con; S[1] = st_rows; S[2] = st_iter; S[3] = st_seg;
+        for (int k = 0; k < RB_NSTAGE; k++) S[4 + k] = (int32_t)(stage_cyc[k] >> 4);
     }
     if (lane == 0) {
         A.W.status[w] = status;

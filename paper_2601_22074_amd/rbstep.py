@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(HERE, "librbstep.so")
 RB_OK, RB_EINVAL, RB_ENOMEM, RB_EHIP, RB_EBUDGET, RB_ESTATE = 0, -1, -2, -3, -4, -5
 STATUS_NONFINITE, STATUS_ITERCAP, STATUS_CONOVERFLOW = 1, 2, 4
 PARAM_FRICTION, PARAM_MASS_SCALE = 0, 1
+NSTATS = 14
+STAGES = ["kinematics", "inertia+bias+M", "factor M + a0", "collision", "constraint rows", "newton start",
+          "gradient+hessian", "hessian factor+solve", "line search+update", "integrate"]
 
 _GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3}
 _JNT = {"free": 0, "hinge": 1}
@@ -282,4 +285,4 @@ class Batch:
                                   _ptr(M, torch.float32, (n, nv, nv), "M"), _ptr(bias, torch.float32, (n, nv), "bias"),
                                   _ptr(a0, torch.float32, (n, nv), "a0"), _ptr(qacc, torch.float32, (n, nv), "qacc"),
                                   _ptr(efc, torch.float32, (n, self.ncap, 4, 3), "efc"),
-                                  _ptr(stats, torch.int32, (n, 4), "stats"), _stream(stream)))
+                                  _ptr(stats, torch.int32, (n, NSTATS), "stats"), _stream(stream)))
