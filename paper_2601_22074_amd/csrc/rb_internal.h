@@ -55,6 +55,12 @@ struct DevModel {
     const uint64_t* dof_descmask;  // bit k set iff dof k is a strict descendant of the dof
     const int* desc_start;     // [nv + 1] CSR of strict descendants
     const int* desc_list;
+    const int* dof_height;     // steps from the dof to its deepest descendant leaf
+    const int* hlevel_start;   // [nhlevel + 1] CSR of dofs by height above their deepest leaf
+    const int* hlevel_dof;
+    int nhlevel, maxpiv;       // height levels, most dofs in one height level
+    const int* body_size;      // bodies in the subtree (bodies are in depth-first order)
+    const int* body_children;  // up to 4 children, one byte each (0xff = none)
     const int* dlevel_start;   // [ndlevel + 2] CSR of dofs by depth, depths 1..ndlevel
     const int* dlevel_dof;
     const float* dof_armature;
@@ -86,7 +92,7 @@ struct DevModel {
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
     int o_xpos, o_xquat, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
     int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp;
-    int o_M, o_H, o_misc, o_piv;
+    int o_M, o_H, o_misc, o_piv, o_rowadr;
     int lds_floats;
 };
 

@@ -226,13 +226,44 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         for (int b = 0; b < nb; b++)
             if (blevel[b] == lev) lv_body.push_back(b);
     }
-    std::vector<int> ch_start(nb + 1, 0), ch_list;
+    if (nb > 64) return fail(RB_EINVAL, "more than 64 bodies");
+    std::vector<int> ch_start(nb + 1, 0), ch_list, bchild(nb, 0), bsize(nb, 1);
     for (int b = 0; b < nb; b++) {
         ch_start[b] = (int)ch_list.size();
+        uint32_t packed = 0xffffffffu;
+        int nc = 0;
         for (int c = b + 1; c < nb; c++)
-            if (P(c) == b) ch_list.push_back(c);
+            if (P(c) == b) {
+                ch_list.push_back(c);
+                if (b > 0 && nc >= 4) return fail(RB_EINVAL, "a body has more than 4 children");
+                if (nc < 4) packed = (packed & ~(0xffu << (8 * nc))) | ((uint32_t)c << (8 * nc));
+                nc++;
+            }
+        bchild[b] = (int)packed;
     }
     ch_start[nb] = (int)ch_list.size();
+    for (int b = nb - 1; b >= 1; b--) bsize[P(b)] += bsize[b];
+    for (int b = 1; b < nb; b++)       // subtrees must be contiguous: bodies listed depth first
+        for (int c = b + 1; c < b + bsize[b]; c++) {
+            int a = c;
+            while (a > b) a = P(a);
+            if (a != b) return fail(RB_EINVAL, "bodies must be listed in depth-first order");
+        }
+    // dof heights (0 for dofs without child dofs) and their level lists
+    std::vector<int> height(nv, 0);
+    for (int i = nv - 1; i >= 0; i--)
+        if (dof_parent[i] >= 0) height[dof_parent[i]] = std::max(height[dof_parent[i]], height[i] + 1);
+    int nhlevel = 0;
+    for (int i = 0; i < nv; i++) nhlevel = std::max(nhlevel, height[i] + 1);
+    std::vector<int> hl_start(nhlevel + 1, 0), hl_dof;
+    int maxpiv = 0;
+    for (int h = 0; h < nhlevel; h++) {
+        hl_start[h] = (int)hl_dof.size();
+        for (int i = nv - 1; i >= 0; i--)
+            if (height[i] == h) hl_dof.push_back(i);
+        maxpiv = std::max(maxpiv, (int)hl_dof.size() - hl_start[h]);
+    }
+    hl_start[nhlevel] = (int)hl_dof.size();
     std::vector<uint64_t> dmask(nv, 0);
     for (int i = 0; i < nv; i++)
         for (int c = desc_start[i]; c < desc_start[i + 1]; c++) dmask[i] |= 1ull << desc_list[c];
@@ -441,6 +472,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     I(lv_start, &m.level_start); I(lv_body, &m.level_body); I(ch_start, &m.child_start); I(ch_list, &m.child_list);
     I(dof_body, &m.dof_body); I(dof_depth, &m.dof_depth); I(rowadr, &m.dof_rowadr); I(anc, &m.dof_anc);
     I(desc_start, &m.desc_start); I(desc_list, &m.desc_list); I(dl_start, &m.dlevel_start); I(dl_dof, &m.dlevel_dof);
+    I(height, &m.dof_height); I(hl_start, &m.hlevel_start); I(hl_dof, &m.hlevel_dof); I(bsize, &m.body_size); I(bchild, &m.body_children);
     F(arm, &m.dof_armature);
     I(act_start, &m.act_start); I(act_list, &m.act_list); I(atype, &m.act_type); I(aqadr, &m.act_qadr);
     F(akp, &m.act_kp); F(akd, &m.act_kd); F(agear, &m.act_gear);
@@ -466,7 +498,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.dof_descmask = (const uint64_t*)(base + 4 * off_dmask);
     // sizes and options
     m.nbody = nb; m.nv = nv; m.nq = nq; m.nu = nu; m.njnt = nj; m.npair = npair;
-    m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.K = d->nsubsteps; m.maxiter = d->iterations;
+    m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.nhlevel = nhlevel; m.maxpiv = maxpiv; m.K = d->nsubsteps; m.maxiter = d->iterations;
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.dt = (float)d->timestep;
     for (int i = 0; i < 3; i++) m.grav[i] = (float)d->gravity[i];
@@ -484,7 +516,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.o_bvec = sec(6 * nb); m.o_bvec2 = sec(6 * nb);
     m.o_tau = sec(nv); m.o_bias = sec(nv); m.o_a0 = sec(nv); m.o_a = sec(nv); m.o_Ma = sec(nv);
     m.o_g = sec(nv); m.o_p = sec(nv); m.o_Mp = sec(nv); m.o_tmp = sec(nv);
-    m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16); m.o_piv = sec(36);
+    m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16); m.o_piv = sec(maxpiv * (tmaxd + 4)); m.o_rowadr = sec(nv);
     m.lds_floats = o;
     m.ncap = std::min(maxcon, RB_MAX_CON);
     M->blob = dev;

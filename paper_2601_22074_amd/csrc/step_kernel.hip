@@ -29,15 +29,32 @@ DEV void wave_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// x from the lane selected by a DPP control (rows of 16 lanes); lanes without a source keep `old`
+template <int CTRL, int ROWMASK>
+DEV float dpp(float old, float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROWMASK, 0xf, false));
+}
+DEV float rl(float x, int c);
+// Wave-wide sum: prefix sums within each row of 16 lanes (row_shr 1, 2, 4, 8), then the row
+// totals carried across rows (row_bcast 15, 31); lane 63 ends with the total, which is
+// broadcast.  The association order is fixed, so the result is deterministic.
 DEV float wsum(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+    x += dpp<0x111, 0xf>(0.f, x);
+    x += dpp<0x112, 0xf>(0.f, x);
+    x += dpp<0x114, 0xf>(0.f, x);
+    x += dpp<0x118, 0xf>(0.f, x);
+    x += dpp<0x142, 0xa>(0.f, x);
+    x += dpp<0x143, 0xc>(0.f, x);
+    return rl(x, 63);
 }
 DEV float wmin(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
-    return x;
+    x = fminf(x, dpp<0x111, 0xf>(INFINITY, x));
+    x = fminf(x, dpp<0x112, 0xf>(INFINITY, x));
+    x = fminf(x, dpp<0x114, 0xf>(INFINITY, x));
+    x = fminf(x, dpp<0x118, 0xf>(INFINITY, x));
+    x = fminf(x, dpp<0x142, 0xa>(INFINITY, x));
+    x = fminf(x, dpp<0x143, 0xc>(INFINITY, x));
+    return rl(x, 63);
 }
 DEV int wscan_incl(int x, int lane) {
 #pragma unroll
@@ -207,21 +224,41 @@ DEV void sym_mul(const DevModel& m, const float* M, const float* x, float* y, in
 }
 
 // spatial motion of every body produced by dof vector x: out[b] = sum over the body's chain S_i x_i
-DEV void body_motion(const DevModel& m, const float* cdof, const float* x, float* out, int lane) {
-    for (int b = lane; b < m.nbody; b += RB_WAVE) {
+template <typename BL_t>
+DEV void body_motion(const DevModel& m, const BL_t& BL, const float* cdof, const float* x, float* out, int lane) {
+    if (lane < m.nbody) {
         float acc[6] = {0, 0, 0, 0, 0, 0};
-        int ld = m.body_lastdof[b];
-        if (ld >= 0) {
-            int d = m.dof_depth[ld];
-            for (int t = 0; t < d; t++) {
-                int i = m.dof_anc[ld * m.maxd + t];
-                float xi = x[i];
+        for (int t = 0; t < BL.depth; t++) {
+            int i = BL.ancestor(t);
+            float xi = x[i];
 #pragma unroll
-                for (int c = 0; c < 6; c++) acc[c] += cdof[6 * i + c] * xi;
-            }
+            for (int c = 0; c < 6; c++) acc[c] += cdof[6 * i + c] * xi;
         }
 #pragma unroll
-        for (int c = 0; c < 6; c++) out[6 * b + c] = acc[c];
+        for (int c = 0; c < 6; c++) out[6 * lane + c] = acc[c];
+    }
+    wave_sync();
+}
+
+// y = M x through the bodies: y_i = S_i . sum over the subtree of body(i) of I_b (J_b x),
+// plus armature; `bm` receives the body motions J_b x and `bf` the body momenta I_b J_b x.
+template <typename BL_t, typename DL_t>
+DEV void spatial_mul(const DevModel& m, const BL_t& BL, const DL_t& DL, const float* cdof, const float* cinert,
+                     const float* x, float* bm, float* bf, float* y, int lane) {
+    body_motion(m, BL, cdof, x, bm, lane);
+    if (lane < m.nbody) {
+        float f[6];
+        inert_mul(cinert + 10 * lane, bm + 6 * lane, f);
+#pragma unroll
+        for (int c = 0; c < 6; c++) bf[6 * lane + c] = f[c];
+    }
+    wave_sync();
+    if (lane < m.nv) {
+        float F[6] = {0, 0, 0, 0, 0, 0};
+        for (int b = DL.body; b < DL.body + DL.bsize; b++)
+#pragma unroll
+            for (int c = 0; c < 6; c++) F[c] += bf[6 * b + c];
+        y[lane] = sdot(cdof + 6 * lane, F) + DL.arm * x[lane];
     }
     wave_sync();
 }
@@ -232,8 +269,23 @@ template <int MAXD>
 struct DofLane {
     int depth;             // chain length including the dof
     int rowadr;            // start of its row in the packed matrices
+    int body;              // body the dof moves
+    int height;            // elimination level: steps to its deepest descendant leaf (-1 off lanes)
+    int bsize;             // bodies in that body's subtree
+    float arm;             // armature
     uint64_t descmask;     // strict descendants
     uint32_t anc[MAXD / 4];   // chain dofs, root first, one byte each
+    DEV int ancestor(int t) const { return (int)((anc[t >> 2] >> (8 * (t & 3))) & 0xffu); }
+};
+
+// Per-lane constants of the body held by the lane (lane b holds body b).
+template <int MAXD>
+struct BodyLane {
+    int parent, jtype, qadr, dadr, level;
+    int depth;             // dofs on the chain (0 for static bodies)
+    uint32_t children;     // up to 4 child bodies, one byte each (0xff = none)
+    uint64_t chainmask;    // dofs on the chain
+    uint32_t anc[MAXD / 4];   // chain dofs, root first
     DEV int ancestor(int t) const { return (int)((anc[t >> 2] >> (8 * (t & 3))) & 0xffu); }
 };
 
@@ -243,6 +295,10 @@ DEV DofLane<MAXD> load_dof_lane(const DevModel& m, int lane) {
     bool on = lane < m.nv;
     D.depth = on ? m.dof_depth[lane] : 0;
     D.rowadr = on ? m.dof_rowadr[lane] : 0;
+    D.body = on ? m.dof_body[lane] : 0;
+    D.height = on ? m.dof_height[lane] : -1;
+    D.bsize = on ? m.body_size[D.body] : 0;
+    D.arm = on ? m.dof_armature[lane] : 0.f;
     D.descmask = on ? m.dof_descmask[lane] : 0ull;
 #pragma unroll
     for (int w = 0; w < MAXD / 4; w++) D.anc[w] = 0u;
@@ -252,6 +308,27 @@ DEV DofLane<MAXD> load_dof_lane(const DevModel& m, int lane) {
         D.anc[t >> 2] |= (uint32_t)a << (8 * (t & 3));
     }
     return D;
+}
+
+template <int MAXD>
+DEV BodyLane<MAXD> load_body_lane(const DevModel& m, const DofLane<MAXD>& DL, int lane) {
+    BodyLane<MAXD> B;
+    bool on = lane < m.nbody;
+    B.parent = on ? m.body_parent[lane] : 0;
+    B.jtype = on ? m.body_jtype[lane] : -1;
+    B.qadr = on ? m.body_qadr[lane] : 0;
+    B.dadr = on ? m.body_dadr[lane] : 0;
+    B.level = on ? m.body_level[lane] : -1;
+    B.children = on ? (uint32_t)m.body_children[lane] : 0xffffffffu;
+    B.chainmask = on ? m.body_chainmask[lane] : 0ull;
+    int ld = on ? m.body_lastdof[lane] : -1;
+    // the body's chain is the chain of its deepest dof: copy that dof lane's constants
+    int src = ld < 0 ? 0 : ld;
+    int dsrc = __shfl(DL.depth, src);
+    B.depth = ld < 0 ? 0 : dsrc;
+#pragma unroll
+    for (int w = 0; w < MAXD / 4; w++) B.anc[w] = (uint32_t)__shfl((int)DL.anc[w], src);
+    return B;
 }
 
 // Factor the tree-sparse matrix whose row i (chain positions, root first) sits in lane i's
@@ -268,30 +345,46 @@ DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MA
                        float* piv, float* inv_out) {
     float inv_self = 0.f;
     const int di = D.depth;
-    const int a = di - 1;
-    for (int k = m.nv - 1; k >= 0; k--) {
-        const int dk = __builtin_amdgcn_readlane(di, k);
-        if (lane == k) {
+    const int a = di - 1 < 0 ? 0 : di - 1;
+    constexpr int STRIDE = MAXD + 4;
+    // dofs of equal height never lie on each other's chain, so a whole height level is
+    // eliminated in one step; an ancestor applies the level's pivots one after another
+    for (int h = 0; h < m.nhlevel; h++) {
+        // the level's pivots: a wave ballot over the lanes' heights, no table reads
+        const bool mine = D.height == h;
+        const uint64_t pmask = __ballot(mine);
+        if (mine) {
+            const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(pmask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)pmask, 0u));
+            float* P = piv + slot * STRIDE;
+            // publish the row with its padding zeroed, so unguarded updates below add exact zeros
 #pragma unroll
-            for (int t = 0; t < MAXD; t++) piv[t] = Hr[t];
-            piv[MAXD] = bi;
+            for (int t = 0; t < MAXD; t++) P[t] = t < di ? Hr[t] : 0.f;
+            P[MAXD] = bi;
         }
         wave_sync();
-        float hk[MAXD];
+        uint64_t left = pmask;
+        for (int pp = 0; left != 0ull; pp++) {
+            const int k = __builtin_ctzll(left);
+            left &= left - 1ull;
+            const int dk = __builtin_amdgcn_readlane(di, k);
+            const float* P = piv + pp * STRIDE;
+            float hk[MAXD];
 #pragma unroll
-        for (int t = 0; t < MAXD; t++) hk[t] = piv[t];
-        const float yk = piv[MAXD];
-        const float d = piv[dk - 1];
-        const bool anc = (D.descmask >> k) & 1ull;
-        const float hka = anc ? piv[a < 0 ? 0 : a] : 0.f;
+            for (int t = 0; t < MAXD; t++) hk[t] = P[t];
+            const float yk = P[MAXD];
+            const float d = P[dk - 1];
+            const bool anc = (D.descmask >> k) & 1ull;
+            const float hka = anc ? P[a] : 0.f;
+            const float inv = __builtin_amdgcn_rcpf(d);
+            if (lane == k) inv_self = inv;
+            const float l = hka * inv;
+            // l = 0 off the pivot's chain; positions past an ancestor's own depth are padding
+#pragma unroll
+            for (int b = 0; b < MAXD; b++) Hr[b] -= l * hk[b];
+            bi -= l * yk;
+        }
         wave_sync();
-        const float inv = __builtin_amdgcn_rcpf(d);
-        if (lane == k) inv_self = inv;
-        const float l = hka * inv;
-#pragma unroll
-        for (int b = 0; b < MAXD; b++)
-            if (b < dk - 1) Hr[b] -= l * hk[b];
-        bi -= l * yk;
     }
     const float z = bi * inv_self;
     float acc = 0.f, x = 0.f;
@@ -309,26 +402,28 @@ DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MA
 // ------------------------------------------------------------------ contacts (one per lane)
 struct Con {
     float r[3];            // contact point relative to O
-    float n[3], t1[3], t2[3];
-    float mu, sigma, dist, margin;
-    int body, g1, g2, feat;
-    float D[4], aref[4], jar[4], s[4], ahat[4];
+    float n[3], t1[3];     // normal and first tangent (t2 = n x t1)
+    float mu, sigma, dist;
+    int body;
+    int ids;               // g1 | g2 << 8 | feature << 16
+    float D[4], aref[4], jar[4];
 };
 
 // velocity of the contact's pyramid rows for body spatial motions `bm` (already includes sign)
 DEV void rows_of(const Con& c, const float* bm, float* out) {
     const float* sv = bm + 6 * c.body;
-    float wr[3];
+    float wr[3], t2[3];
     cross(sv, c.r, wr);
+    cross(c.n, c.t1, t2);
     float vp[3] = {sv[3] + wr[0], sv[4] + wr[1], sv[5] + wr[2]};
-    float vn = c.sigma * dot(c.n, vp), v1 = c.sigma * dot(c.t1, vp), v2 = c.sigma * dot(c.t2, vp);
+    float vn = c.sigma * dot(c.n, vp), v1 = c.sigma * dot(c.t1, vp), v2 = c.sigma * dot(t2, vp);
     out[0] = vn + c.mu * v1;
     out[1] = vn - c.mu * v1;
     out[2] = vn + c.mu * v2;
     out[3] = vn - c.mu * v2;
 }
 
-DEV void contact_frame(const float* n, float* t1, float* t2) {
+DEV void contact_frame(const float* n, float* t1) {
     int k = 0;
     if (fabsf(n[1]) < fabsf(n[k])) k = 1;
     if (fabsf(n[2]) < fabsf(n[k])) k = 2;
@@ -338,7 +433,6 @@ DEV void contact_frame(const float* n, float* t1, float* t2) {
     float t[3] = {e[0] - dn * n[0], e[1] - dn * n[1], e[2] - dn * n[2]};
     float inv = 1.0f / sqrtf(dot(t, t));
     t1[0] = t[0] * inv; t1[1] = t[1] * inv; t1[2] = t[2] * inv;
-    cross(n, t1, t2);
 }
 
 // world pose of geom g from its body's pose in LDS
@@ -439,8 +533,11 @@ struct StepArgs {
     int want_contacts, want_taps;
 };
 
-template <int MAXD>
-__global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
+// MAXD: longest dof chain the instantiation supports; TIMED: accumulate per-stage shader-clock
+// cycles for the stats tap (diagnostic builds of the same kernel).
+template <int MAXD, bool TIMED>
+__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(2, 8))) void step_kernel(DevModel m,
+                                                                                                   StepArgs A) {
     extern __shared__ float lds[];
     const int w = blockIdx.x;
     if (w >= A.n) return;
@@ -476,6 +573,9 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
 
     const int nq = m.nq, nv = m.nv, nu = m.nu, nb = m.nbody;
     const DofLane<MAXD> DL = load_dof_lane<MAXD>(m, lane);
+    const BodyLane<MAXD> BL = load_body_lane<MAXD>(m, DL, lane);
+    int* rowadr_l = (int*)(L + m.o_rowadr);
+    if (lane < m.nv) rowadr_l[lane] = DL.rowadr;
     // ---- ingress
     for (int i = lane; i < nq; i += RB_WAVE) q[i] = A.qpos[(size_t)w * nq + i];
     for (int i = lane; i < nv; i += RB_WAVE) {
@@ -499,12 +599,14 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
     int ncon = 0;
     int st_con = 0, st_rows = 0, st_iter = 0, st_seg = 0;   // work totals for the stats tap
     uint64_t stage_cyc[RB_NSTAGE] = {};                          // cycles per stage (stats tap)
-    uint64_t t_mark = clock64();
+    uint64_t t_mark = TIMED ? clock64() : 0;
 #define RB_STAGE(id)                                    \
     do {                                                \
-        uint64_t t_now = clock64();                     \
-        stage_cyc[id] += t_now - t_mark;                \
-        t_mark = t_now;                                 \
+        if (TIMED) {                                    \
+            uint64_t t_now = clock64();                 \
+            stage_cyc[id] += t_now - t_mark;            \
+            t_mark = t_now;                             \
+        }                                               \
     } while (0)
     bool frozen = (status & RB_STATUS_NONFINITE) != 0;
     status &= ~(uint32_t)(RB_STATUS_ITERCAP | RB_STATUS_CONOVERFLOW);
@@ -524,13 +626,13 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
         }
         // ---- forward kinematics, level by level from the root
         for (int lev = 1; lev <= m.nblevel; lev++) {
-            for (int idx = m.level_start[lev] + lane; idx < m.level_start[lev + 1]; idx += RB_WAVE) {
-                int b = m.level_body[idx];
-                int par = m.body_parent[b];
-                int jt = m.body_jtype[b];
+            if (BL.level == lev) {
+                const int b = lane;
+                const int par = BL.parent;
+                const int jt = BL.jtype;
                 float x[3], qq[4];
                 if (jt == RB_JNT_FREE) {
-                    int a = m.body_qadr[b];
+                    int a = BL.qadr;
                     x[0] = q[a]; x[1] = q[a + 1]; x[2] = q[a + 2];
                     float nrm = sqrtf(q[a + 3] * q[a + 3] + q[a + 4] * q[a + 4] + q[a + 5] * q[a + 5] + q[a + 6] * q[a + 6]);
                     float inv = 1.0f / nrm;
@@ -543,7 +645,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                     if (jt == RB_JNT_HINGE) {
                         float R0[9];
                         qmat(qq, R0);
-                        float th = 0.5f * q[m.body_qadr[b]];
+                        float th = 0.5f * q[BL.qadr];
                         float sh = sinf(th), ch = cosf(th);
                         const float* ax = m.body_jaxis + 3 * b;
                         float qh[4] = {ch, sh * ax[0], sh * ax[1], sh * ax[2]};
@@ -566,7 +668,8 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
         RB_STAGE(0);
         const float O[3] = {xpos[3], xpos[4], xpos[5]};
         // ---- spatial inertias about O, motion subspaces of the dofs
-        for (int b = 1 + lane; b < nb; b += RB_WAVE) {
+        if (lane >= 1 && lane < nb) {
+            const int b = lane;
             const float* R = xmat + 9 * b;
             float Ri[9], RR[9];
             qmat(m.body_iquat + 4 * b, Ri);
@@ -595,8 +698,8 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             I[8] = Ixz - mass * c[0] * c[2];
             I[9] = Iyz - mass * c[1] * c[2];
             for (int k = 0; k < 10; k++) crb[10 * b + k] = I[k];
-            int jt = m.body_jtype[b];
-            int da = m.body_dadr[b];
+            const int jt = BL.jtype;
+            const int da = BL.dadr;
             float xo[3] = {xpos[3 * b] - O[0], xpos[3 * b + 1] - O[1], xpos[3 * b + 2] - O[2]};
             if (jt == RB_JNT_HINGE) {
                 float u[3], o[3];
@@ -626,12 +729,12 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
         }
         wave_sync();
         for (int lev = 1; lev <= m.nblevel; lev++) {
-            for (int idx = m.level_start[lev] + lane; idx < m.level_start[lev + 1]; idx += RB_WAVE) {
-                int b = m.level_body[idx];
-                int par = m.body_parent[b];
+            if (BL.level == lev) {
+                const int b = lane;
+                const int par = BL.parent;
                 float vb[6], ab[6];
                 for (int c = 0; c < 6; c++) { vb[c] = cvel[6 * par + c]; ab[c] = bvec[6 * par + c]; }
-                int jt = m.body_jtype[b], da = m.body_dadr[b];
+                const int jt = BL.jtype, da = BL.dadr;
                 int nd = jt == RB_JNT_FREE ? 6 : (jt == RB_JNT_HINGE ? 1 : 0);
                 for (int k = 0; k < nd; k++) {
                     const float* S = cdof + 6 * (da + k);
@@ -649,7 +752,8 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             }
             wave_sync();
         }
-        for (int b = 1 + lane; b < nb; b += RB_WAVE) {
+        if (lane >= 1 && lane < nb) {
+            const int b = lane;
             float f[6], Iv[6], t[6];
             inert_mul(cinert + 10 * b, bvec + 6 * b, f);
             inert_mul(cinert + 10 * b, cvel + 6 * b, Iv);
@@ -658,30 +762,32 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
         }
         wave_sync();
         // ---- backward passes: bias wrenches and composite inertias accumulate to the root
-        for (int lev = m.nblevel; lev >= 1; lev--) {
-            for (int idx = m.level_start[lev] + lane; idx < m.level_start[lev + 1]; idx += RB_WAVE) {
-                int b = m.level_body[idx];
-                for (int c = m.child_start[b]; c < m.child_start[b + 1]; c++) {
-                    int ch = m.child_list[c];
+        for (int lev = m.nblevel - 1; lev >= 1; lev--) {
+            if (BL.level == lev) {
+                const int b = lane;
+#pragma unroll
+                for (int c = 0; c < 4; c++) {
+                    int ch = (BL.children >> (8 * c)) & 0xff;
+                    if (ch == 0xff) break;
                     for (int k = 0; k < 6; k++) bvec2[6 * b + k] += bvec2[6 * ch + k];
                     for (int k = 0; k < 10; k++) crb[10 * b + k] += crb[10 * ch + k];
                 }
             }
             wave_sync();
         }
-        for (int i = lane; i < nv; i += RB_WAVE) {
+        if (lane < nv) {
+            const int i = lane;
             const float* S = cdof + 6 * i;
-            int b = m.dof_body[i];
+            const int b = DL.body;
             bias[i] = sdot(S, bvec2 + 6 * b);
             // joint-space inertia row i: M_ij = S_j . (Ic_b S_i) over the chain of i
             float F[6];
             inert_mul(crb + 10 * b, S, F);
-            int d = m.dof_depth[i], r = m.dof_rowadr[i];
-            for (int t = 0; t < d; t++) {
-                int j = m.dof_anc[i * m.maxd + t];
-                Mm[r + t] = sdot(cdof + 6 * j, F);
-            }
-            Mm[r + d - 1] += m.dof_armature[i];
+            const int d = DL.depth, r = DL.rowadr;
+#pragma unroll
+            for (int t = 0; t < MAXD; t++)
+                if (t < d) Mm[r + t] = sdot(cdof + 6 * DL.ancestor(t), F);
+            Mm[r + d - 1] += DL.arm;
             a0[i] = tau[i] - bias[i];
         }
         wave_sync();
@@ -729,40 +835,50 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             src = lo;
         }
         int before = __shfl(incl - cnt, src);
+        float margin_c = 0.f;
         if (has) {
-            int j = lane - before;
-            pair_contacts(m, L, src, j, &C.dist, pos_, &C.feat, C.n);
+            int j = lane - before, feat;
+            pair_contacts(m, L, src, j, &C.dist, pos_, &feat, C.n);
             C.r[0] = pos_[0] - O[0]; C.r[1] = pos_[1] - O[1]; C.r[2] = pos_[2] - O[2];
-            contact_frame(C.n, C.t1, C.t2);
-            C.g1 = m.pair_g1[src]; C.g2 = m.pair_g2[src];
+            contact_frame(C.n, C.t1);
+            C.ids = m.pair_g1[src] | (m.pair_g2[src] << 8) | (feat << 16);
             C.body = m.pair_body[src];
             C.sigma = m.pair_sigma[src];
             C.mu = m.fr_pw ? mu_world : m.pair_mu[src];
-            C.margin = m.pair_margin[src];
+            margin_c = m.pair_margin[src];
+        } else {
+            C.body = 0;
         }
         RB_STAGE(3);
         // ---- constraint rows: exact A-hat from the chain half-solve with M's factor
+        {
+            // the contact body's chain, from the body lane
+            const int d = __shfl(BL.depth, C.body);
+            uint32_t cw[MAXD / 4];
+#pragma unroll
+            for (int w2 = 0; w2 < MAXD / 4; w2++) cw[w2] = (uint32_t)__shfl((int)BL.anc[w2], C.body);
+#define CROW(t) rowadr_l[(int)((cw[(t) >> 2] >> (8 * ((t) & 3))) & 0xffu)]
         if (has) {
             float X[MAXD][3];
-            int ld = m.body_lastdof[C.body];
-            int d = m.dof_depth[ld];
+            float t2c[3];
+            cross(C.n, C.t1, t2c);
 #pragma unroll
             for (int t = 0; t < MAXD; t++) {
                 X[t][0] = X[t][1] = X[t][2] = 0.f;
                 if (t < d) {
-                    const float* S = cdof + 6 * m.dof_anc[ld * m.maxd + t];
+                    const float* S = cdof + 6 * (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu);
                     float wr[3];
                     cross(S, C.r, wr);
                     float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
                     X[t][0] = C.sigma * dot(C.n, vp);
                     X[t][1] = C.sigma * dot(C.t1, vp);
-                    X[t][2] = C.sigma * dot(C.t2, vp);
+                    X[t][2] = C.sigma * dot(t2c, vp);
                 }
             }
 #pragma unroll
             for (int tp = MAXD - 1; tp >= 1; tp--) {
                 if (tp < d) {
-                    int row = m.dof_rowadr[m.dof_anc[ld * m.maxd + tp]];
+                    const int row = CROW(tp);
 #pragma unroll
                     for (int t = 0; t < tp; t++) {
                         float l = H[row + t];
@@ -776,7 +892,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
 #pragma unroll
             for (int t = 0; t < MAXD; t++) {
                 if (t < d) {
-                    float inv = 1.0f / H[m.dof_rowadr[m.dof_anc[ld * m.maxd + t]] + t];
+                    float inv = 1.0f / H[CROW(t) + t];
                     A00 += X[t][0] * X[t][0] * inv;
                     A11 += X[t][1] * X[t][1] * inv;
                     A22 += X[t][2] * X[t][2] * inv;
@@ -786,18 +902,26 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             }
             float vrow[4];
             rows_of(C, cvel, vrow);
-            float rd = C.dist - C.margin;
+            float rd = C.dist - margin_c;
             float imp = impedance(m, rd);
             float mu = C.mu, mu2 = mu * mu;
             float ah[4] = {A00 + mu2 * A11 + 2.f * mu * A01, A00 + mu2 * A11 - 2.f * mu * A01,
                            A00 + mu2 * A22 + 2.f * mu * A02, A00 + mu2 * A22 - 2.f * mu * A02};
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                C.ahat[e] = ah[e];
                 C.aref[e] = -m.bref * vrow[e] - m.kref * imp * rd;
                 float R = fmaxf(1e-15f, (1.0f - imp) / imp * ah[e]);
                 C.D[e] = 1.0f / R;
             }
+            if (A.want_taps && sub == 0 && A.taps.efc) {
+                float* E = A.taps.efc + ((size_t)w * m.ncap + lane) * 12;
+                for (int e = 0; e < 4; e++) {
+                    E[3 * e] = C.aref[e];
+                    E[3 * e + 1] = C.D[e];
+                    E[3 * e + 2] = ah[e];
+                }
+            }
+        }
         }
 
         RB_STAGE(4);
@@ -808,7 +932,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             wave_sync();
         } else {
             // cost at a0 and at the warm start; keep the better (ties go to a0)
-            body_motion(m, cdof, a0, bvec, lane);
+            body_motion(m, BL, cdof, a0, bvec, lane);
             float j0[4] = {0, 0, 0, 0};
             float f0 = 0.f;
             if (has) {
@@ -823,8 +947,8 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
             f0 = wsum(f0);
             for (int i = lane; i < nv; i += RB_WAVE) tmp[i] = aws[i] - a0[i];
             wave_sync();
-            sym_mul(m, Mm, tmp, g, lane);   // g <- M (aws - a0)
-            body_motion(m, cdof, aws, bvec, lane);
+            spatial_mul(m, BL, DL, cdof, cinert, tmp, bvec, bvec2, g, lane);   // g <- M (aws - a0)
+            body_motion(m, BL, cdof, aws, bvec, lane);
             float jw[4] = {0, 0, 0, 0};
             float fw = 0.f;
             if (has) {
@@ -860,13 +984,16 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                 if (dof_lane)
                     for (int c = 0; c < 6; c++) S[c] = cdof[6 * lane + c];
                 for (int c = 0; c < ncon; c++) {
-                    int body = __builtin_amdgcn_readlane(C.body, c);
-                    uint64_t mask = m.body_chainmask[body];
+                    const int body = __builtin_amdgcn_readlane(C.body, c);
+                    const uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)BL.chainmask, body);
+                    const uint32_t mhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(BL.chainmask >> 32), body);
+                    const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
                     float r[3], n[3], t1[3], t2[3], D[4], jar[4];
                     for (int k = 0; k < 3; k++) {
                         r[k] = rl(C.r[k], c); n[k] = rl(C.n[k], c);
-                        t1[k] = rl(C.t1[k], c); t2[k] = rl(C.t2[k], c);
+                        t1[k] = rl(C.t1[k], c);
                     }
+                    cross(n, t1, t2);
                     for (int e = 0; e < 4; e++) { D[e] = rl(C.D[e], c); jar[e] = rl(C.jar[e], c); }
                     float mu = rl(C.mu, c), sg = rl(C.sigma, c);
                     if (dof_lane && ((mask >> lane) & 1ull)) {
@@ -916,10 +1043,9 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                 }
                 RB_STAGE(7);
                 // directional quantities for the line search
-                body_motion(m, cdof, p, bvec, lane);
+                spatial_mul(m, BL, DL, cdof, cinert, p, bvec, bvec2, Mp, lane);
                 float sr[4] = {0, 0, 0, 0};
                 if (has) rows_of(C, bvec, sr);
-                sym_mul(m, Mm, p, Mp, lane);
                 float pa = 0.f, pb = 0.f;
                 if (dof_lane) {
                     pa = p[lane] * Mp[lane];
@@ -931,7 +1057,6 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                     float bp[4];
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        C.s[e] = sr[e];
                         bp[e] = (has && sr[e] != 0.f) ? -C.jar[e] / sr[e] : INFINITY;
                     }
                     float at = 0.f;
@@ -1018,14 +1143,7 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
                     }
                 }
             }
-            if (A.taps.efc && has) {
-                float* E = A.taps.efc + ((size_t)w * m.ncap + lane) * 12;
-                for (int e = 0; e < 4; e++) {
-                    E[3 * e] = C.aref[e];
-                    E[3 * e + 1] = C.D[e];
-                    E[3 * e + 2] = C.ahat[e];
-                }
-            }
+
         }
 
         // ---- semi-implicit Euler (one lane per joint), committed only if everything is finite
@@ -1099,8 +1217,8 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
     }
     if (A.want_contacts && lane < ncon) {
         size_t slot = (size_t)w * m.ncap + lane;
-        if (A.co.geom) { A.co.geom[2 * slot] = C.g1; A.co.geom[2 * slot + 1] = C.g2; }
-        if (A.co.feature) A.co.feature[slot] = C.feat;
+        if (A.co.geom) { A.co.geom[2 * slot] = C.ids & 0xff; A.co.geom[2 * slot + 1] = (C.ids >> 8) & 0xff; }
+        if (A.co.feature) A.co.feature[slot] = (C.ids >> 16) & 0xff;
         if (A.co.dist) A.co.dist[slot] = C.dist;
         if (A.co.pos) {
             A.co.pos[3 * slot] = C.r[0] + xpos[3];
@@ -1109,7 +1227,9 @@ __global__ __launch_bounds__(RB_WAVE) void step_kernel(DevModel m, StepArgs A) {
         }
         if (A.co.frame) {
             float* F = A.co.frame + 9 * slot;
-            for (int k = 0; k < 3; k++) { F[k] = C.n[k]; F[3 + k] = C.t1[k]; F[6 + k] = C.t2[k]; }
+            float t2o[3];
+            cross(C.n, C.t1, t2o);
+            for (int k = 0; k < 3; k++) { F[k] = C.n[k]; F[3 + k] = C.t1[k]; F[6 + k] = t2o[k]; }
         }
         if (A.co.force) {
             float f[4];
@@ -1139,11 +1259,16 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     if (taps) A.taps = *taps; else A.taps = DevTaps{};
     size_t shmem = (size_t)m.lds_floats * sizeof(float);
     dim3 grid(n), block(RB_WAVE);
-    if (m.maxd <= 8)
-        hipLaunchKernelGGL(rbk::step_kernel<8>, grid, block, shmem, stream, m, A);
-    else if (m.maxd <= 16)
-        hipLaunchKernelGGL(rbk::step_kernel<16>, grid, block, shmem, stream, m, A);
-    else
-        hipLaunchKernelGGL(rbk::step_kernel<32>, grid, block, shmem, stream, m, A);
+    const bool timed = taps != nullptr && taps->stats != nullptr;
+    if (m.maxd <= 8) {
+        if (timed) hipLaunchKernelGGL((rbk::step_kernel<8, true>), grid, block, shmem, stream, m, A);
+        else hipLaunchKernelGGL((rbk::step_kernel<8, false>), grid, block, shmem, stream, m, A);
+    } else if (m.maxd <= 16) {
+        if (timed) hipLaunchKernelGGL((rbk::step_kernel<16, true>), grid, block, shmem, stream, m, A);
+        else hipLaunchKernelGGL((rbk::step_kernel<16, false>), grid, block, shmem, stream, m, A);
+    } else {
+        if (timed) hipLaunchKernelGGL((rbk::step_kernel<32, true>), grid, block, shmem, stream, m, A);
+        else hipLaunchKernelGGL((rbk::step_kernel<32, false>), grid, block, shmem, stream, m, A);
+    }
     return hipGetLastError();
 }
