@@ -206,10 +206,12 @@ def main():
     stream = torch.cuda.current_stream()
 
     if args.copy_calib_mb:
-        a = torch.empty(args.copy_calib_mb * 2 ** 20 // 4, device=dev)
+        # a plain elementwise kernel of known traffic (reads and writes calib_mb MiB each) whose
+        # counter readings calibrate FETCH_SIZE / WRITE_SIZE
+        a = torch.ones(args.copy_calib_mb * 2 ** 20 // 4, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.neg(a, out=b)
         torch.cuda.synchronize()
 
     def ctrl_at(s):

@@ -624,40 +624,55 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(2, 8)))
             }
             tau[i] = t;
         }
-        // ---- forward kinematics, level by level from the root
+        // ---- forward kinematics.  Each body's pose relative to its parent is computed for all
+        // bodies at once: q_loc = quat_b * rot(axis, theta) and t_loc = pos_b + R(quat_b) p - R(q_loc) p
+        // for a hinge anchored at p (the anchor stays put while the child turns about it); free
+        // bodies take their pose from qpos.  Then levels compose x_b = x_p + R_p t_loc,
+        // q_b = q_p * q_loc from the root.
+        float tl[3] = {0.f, 0.f, 0.f}, ql[4] = {1.f, 0.f, 0.f, 0.f};
+        if (lane >= 1 && lane < nb) {
+            const int b = lane;
+            if (BL.jtype == RB_JNT_FREE) {
+                const int a = BL.qadr;
+                tl[0] = q[a]; tl[1] = q[a + 1]; tl[2] = q[a + 2];
+                float nrm = sqrtf(q[a + 3] * q[a + 3] + q[a + 4] * q[a + 4] + q[a + 5] * q[a + 5] + q[a + 6] * q[a + 6]);
+                float inv = 1.0f / nrm;
+                ql[0] = q[a + 3] * inv; ql[1] = q[a + 4] * inv; ql[2] = q[a + 5] * inv; ql[3] = q[a + 6] * inv;
+            } else {
+                const float* qb = m.body_quat + 4 * b;
+                const float* pb = m.body_pos + 3 * b;
+                ql[0] = qb[0]; ql[1] = qb[1]; ql[2] = qb[2]; ql[3] = qb[3];
+                tl[0] = pb[0]; tl[1] = pb[1]; tl[2] = pb[2];
+                if (BL.jtype == RB_JNT_HINGE) {
+                    const float* ax = m.body_jaxis + 3 * b;
+                    const float* jp = m.body_jpos + 3 * b;
+                    float th = 0.5f * q[BL.qadr];
+                    float sh = sinf(th), ch = cosf(th);
+                    float qh[4] = {ch, sh * ax[0], sh * ax[1], sh * ax[2]};
+                    float R0[9], R1[9], d0[3], d1[3], q1[4];
+                    qmat(ql, R0);
+                    qmul(ql, qh, q1);
+                    ql[0] = q1[0]; ql[1] = q1[1]; ql[2] = q1[2]; ql[3] = q1[3];
+                    qmat(ql, R1);
+                    mv(R0, jp, d0);
+                    mv(R1, jp, d1);
+                    tl[0] += d0[0] - d1[0]; tl[1] += d0[1] - d1[1]; tl[2] += d0[2] - d1[2];
+                }
+            }
+        }
         for (int lev = 1; lev <= m.nblevel; lev++) {
             if (BL.level == lev) {
                 const int b = lane;
                 const int par = BL.parent;
-                const int jt = BL.jtype;
                 float x[3], qq[4];
-                if (jt == RB_JNT_FREE) {
-                    int a = BL.qadr;
-                    x[0] = q[a]; x[1] = q[a + 1]; x[2] = q[a + 2];
-                    float nrm = sqrtf(q[a + 3] * q[a + 3] + q[a + 4] * q[a + 4] + q[a + 5] * q[a + 5] + q[a + 6] * q[a + 6]);
-                    float inv = 1.0f / nrm;
-                    qq[0] = q[a + 3] * inv; qq[1] = q[a + 4] * inv; qq[2] = q[a + 5] * inv; qq[3] = q[a + 6] * inv;
+                if (BL.jtype == RB_JNT_FREE) {
+                    x[0] = tl[0]; x[1] = tl[1]; x[2] = tl[2];
+                    qq[0] = ql[0]; qq[1] = ql[1]; qq[2] = ql[2]; qq[3] = ql[3];
                 } else {
                     float off[3];
-                    mv(xmat + 9 * par, m.body_pos + 3 * b, off);
+                    mv(xmat + 9 * par, tl, off);
                     x[0] = xpos[3 * par] + off[0]; x[1] = xpos[3 * par + 1] + off[1]; x[2] = xpos[3 * par + 2] + off[2];
-                    qmul(xquat + 4 * par, m.body_quat + 4 * b, qq);
-                    if (jt == RB_JNT_HINGE) {
-                        float R0[9];
-                        qmat(qq, R0);
-                        float th = 0.5f * q[BL.qadr];
-                        float sh = sinf(th), ch = cosf(th);
-                        const float* ax = m.body_jaxis + 3 * b;
-                        float qh[4] = {ch, sh * ax[0], sh * ax[1], sh * ax[2]};
-                        float q1[4];
-                        qmul(qq, qh, q1);
-                        qq[0] = q1[0]; qq[1] = q1[1]; qq[2] = q1[2]; qq[3] = q1[3];
-                        float R1[9], d0[3], d1[3];
-                        qmat(qq, R1);
-                        mv(R0, m.body_jpos + 3 * b, d0);
-                        mv(R1, m.body_jpos + 3 * b, d1);
-                        x[0] += d0[0] - d1[0]; x[1] += d0[1] - d1[1]; x[2] += d0[2] - d1[2];
-                    }
+                    qmul(xquat + 4 * par, ql, qq);
                 }
                 xpos[3 * b] = x[0]; xpos[3 * b + 1] = x[1]; xpos[3 * b + 2] = x[2];
                 xquat[4 * b] = qq[0]; xquat[4 * b + 1] = qq[1]; xquat[4 * b + 2] = qq[2]; xquat[4 * b + 3] = qq[3];
