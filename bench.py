@@ -163,6 +163,64 @@ def load_traffic(name, nworlds):
     return d.get("bytes_per_launch")
 
 
+# ------------------------------------------------------------------ rocprofv3 summaries
+def summarize_profiles(trace_db, fetch_db, write_db, name, nworlds, calib_mb, commands):
+    """Summaries of rocprofv3 databases: per-kernel time, and HBM bytes of the step kernel from
+    FETCH_SIZE / WRITE_SIZE scaled by what they read for an elementwise kernel of known size."""
+    import sqlite3
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    base = f"step_kernel_{name}_x{nworlds}"
+    c = sqlite3.connect(trace_db)
+    rows = list(c.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    lines = [f"# rocprofv3 kernel trace: {name} x{nworlds}", "", "Command:", "", "```", commands["trace"], "```", "",
+             "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for n, calls, tot, avg, pct in rows[:8]:
+        short = n if len(n) < 70 else n[:67] + "..."
+        lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.1f} | {pct:.2f} |")
+    step = [r for r in rows if r[0].startswith("void rbk::step_kernel") and "false" in r[0]]
+    if step:
+        lines += ["", f"Step kernel average duration: {step[0][3]:.1f} us per launch (one env step of {nworlds} worlds)."]
+    with open(os.path.join(ROOT, "profiles", base + "_trace.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def counter(db, cname):
+        cc = sqlite3.connect(db)
+        q = "select kernel_name, value from counters_collection where counter_name = ?"
+        step_v = [v for k, v in cc.execute(q, (cname,)) if k.startswith("void rbk::step_kernel") and "false" in k]
+        copy_v = [v for k, v in cc.execute(q, (cname,)) if "neg_kernel" in k or ("elementwise" in k and "neg" in k)]
+        return step_v, copy_v
+
+    fs, fc = counter(fetch_db, "FETCH_SIZE")
+    ws, wc = counter(write_db, "WRITE_SIZE")
+    calib_kib = calib_mb * 1024.0
+    ffac = calib_kib / float(np.median(fc)) if fc else float("nan")
+    wfac = calib_kib / float(np.median(wc)) if wc else float("nan")
+    fetch_kib = float(np.median(fs)) if fs else float("nan")
+    write_kib = float(np.median(ws)) if ws else float("nan")
+    bytes_per_launch = (fetch_kib * ffac + write_kib * wfac) * 1024.0
+    d = {"kernel": "step_kernel<16,false>", "workload": f"{name} x{nworlds}",
+         "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
+         "calibration": {"kernel": f"elementwise neg of {calib_mb} MiB (reads and writes {calib_mb} MiB)",
+                         "fetch_kib": float(np.median(fc)) if fc else None,
+                         "write_kib": float(np.median(wc)) if wc else None,
+                         "fetch_factor": ffac, "write_factor": wfac},
+         "bytes_per_launch": bytes_per_launch, "kernel_source_hash": kernel_source_hash(),
+         "commands": commands}
+    with open(os.path.join(ROOT, "profiles", base + "_traffic.json"), "w") as f:
+        json.dump(d, f, indent=1)
+    md = [f"# HBM traffic of the step kernel: {name} x{nworlds}", "", "Commands:", "", "```", commands["fetch"],
+          commands["write"], "```", "",
+          f"- FETCH_SIZE per dispatch: {fetch_kib:.0f} KiB; WRITE_SIZE per dispatch: {write_kib:.0f} KiB",
+          f"- calibration kernel (elementwise neg of {calib_mb} MiB): FETCH_SIZE {d['calibration']['fetch_kib']} KiB, "
+          f"WRITE_SIZE {d['calibration']['write_kib']} KiB -> factors {ffac:.3f} / {wfac:.3f}",
+          f"- calibrated HBM bytes per launch: {bytes_per_launch / 1e6:.2f} MB "
+          f"({bytes_per_launch / nworlds:.0f} B per world per env step)",
+          f"- kernel source hash: {d['kernel_source_hash']}"]
+    with open(os.path.join(ROOT, "profiles", base + "_traffic.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(json.dumps(d))
+
+
 # ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
@@ -176,7 +234,20 @@ def main():
     ap.add_argument("--stats-worlds", type=int, default=512)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
+                    help="write profiles/ summaries from rocprofv3 databases and exit")
     args = ap.parse_args()
+    if args.summarize:
+        wl = args.workload
+        nwd = args.worlds or {"humanoid": 8192, "quadruped": 4096, "chain3": 64}[wl]
+        cmds = {"trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace -- "
+                         "python bench.py --steps 50 --warmup 5 --no-cpu --stats-worlds 64",
+                "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch -- "
+                         "python bench.py --steps 10 --warmup 2 --no-cpu --stats-worlds 16 --copy-calib-mb 256",
+                "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write -- "
+                         "python bench.py --steps 10 --warmup 2 --no-cpu --stats-worlds 16 --copy-calib-mb 256"}
+        summarize_profiles(*args.summarize, wl, nwd, args.copy_calib_mb or 256, cmds)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: worlds are independent and this build runs on a single MI355X; "
               "use --gpus 1", file=sys.stderr)
