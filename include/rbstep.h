@@ -155,6 +155,43 @@ int rb_step_taps(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_q
                  const rb_contacts* contacts, uint32_t* dev_status, float* dev_M, float* dev_bias,
                  float* dev_a0, float* dev_qacc, float* dev_efc, int32_t* dev_stats, void* hip_stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Mixed-model batching: one fused launch steps several batches (of the same or different
+ * models) together.  Every world runs the same per-world code as rb_step, so its results do
+ * not depend on the schedule or on the other batches; the schedule only decides the order in
+ * which worlds are dispatched and the grid.  A fixed sequence of fused steps can be captured
+ * once in a hipGraph and replayed (the paper's graph capture of the simulation step, section
+ * "Architecture").
+ * --------------------------------------------------------------------------------------- */
+typedef struct rb_multi rb_multi;
+
+enum { RB_ORDER_BATCH = 0,        /* batch after batch, worlds in index order */
+       RB_ORDER_HEAVY_FIRST = 1,  /* most expensive batches first (by cost per world) */
+       RB_ORDER_INTERLEAVE = 2 }; /* worlds of all batches interleaved in proportion */
+
+/* A plan over nbatch existing batches (not owned; they must outlive the plan). */
+int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out);
+void rb_multi_destroy(rb_multi* plan);
+
+/* Step inputs of batch i for the following fused steps (device pointers as in rb_step,
+ * slots [0, n)).  Copies a small argument block to the device; synchronous. */
+int rb_multi_bind(rb_multi* plan, int32_t i, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
+                  const rb_contacts* contacts, uint32_t* dev_status);
+
+/* Dispatch order and grid of the fused launch.  cost [nbatch] (host, nullable) is the
+ * relative cost of one world of each batch, used by RB_ORDER_HEAVY_FIRST (default: a
+ * per-model estimate).  grid <= 0 launches one workgroup per world; grid > 0 launches that
+ * many persistent workgroups walking the list.  Call after every batch is bound. */
+int rb_multi_set_schedule(rb_multi* plan, int32_t order, int32_t grid, const float* cost);
+
+/* One env step of every bound batch in one launch on the stream. */
+int rb_multi_step(rb_multi* plan, void* hip_stream);
+
+/* Capture nsteps fused steps into a graph on the (non-default) stream, replacing any earlier
+ * capture; rb_multi_graph_launch replays them (all nsteps env steps) on a stream. */
+int rb_multi_graph_capture(rb_multi* plan, int32_t nsteps, void* hip_stream);
+int rb_multi_graph_launch(rb_multi* plan, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,5 +2,6 @@
 
 ``rbstep`` is the ctypes binding of ``librbstep.so`` (see ``include/rbstep.h``).
 """
-from .rbstep import (Batch, Contacts, Model, RbError, PARAM_FRICTION, PARAM_MASS_SCALE,  # noqa: F401
-                     STATUS_CONOVERFLOW, STATUS_ITERCAP, STATUS_NONFINITE, lib)
+from .rbstep import (Batch, Contacts, Model, Multi, RbError, PARAM_FRICTION, PARAM_MASS_SCALE,  # noqa: F401
+                     ORDER_BATCH, ORDER_HEAVY_FIRST, ORDER_INTERLEAVE, STATUS_CONOVERFLOW, STATUS_ITERCAP,
+                     STATUS_NONFINITE, lib)

@@ -21,6 +21,11 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
 hipError_t rb_launch_reset(int nv, const int32_t* ids, int n, const float* qacc_ws, DevWorlds W, int capacity,
                            hipStream_t stream);
 hipError_t rb_launch_fill(float* dst, float value, size_t count, hipStream_t stream);
+size_t rb_step_args_size();
+void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
+                       const DevContactsOut* co, uint32_t* status_out);
+hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
+                           int lds_floats, int grid, hipStream_t stream);
 
 namespace {
 
@@ -671,6 +676,179 @@ int rb_step_taps(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* 
                  void* stream) {
     DevTaps t{M, bias, a0, qacc, efc, stats};
     return step_impl(b, n, ctrl, qpos, qvel, c, status, &t, stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// mixed-model batching
+// ---------------------------------------------------------------------------------------
+struct rb_multi {
+    std::vector<rb_batch*> batches;
+    std::vector<int> bound_n;
+    std::vector<char> args_host;   // nbatch step-argument blocks
+    DevModel* d_models = nullptr;
+    void* d_args = nullptr;
+    int* d_items = nullptr;
+    int nitems = 0, grid = 0, maxd = 0, lds_floats = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void multi_free_graph(rb_multi* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out) {
+    if (!batches || nbatch <= 0 || nbatch > 127 || !out) return fail(RB_EINVAL, "bad arguments to rb_multi_create");
+    *out = nullptr;
+    rb_multi* p = new rb_multi();
+    std::vector<DevModel> models(nbatch);
+    for (int i = 0; i < nbatch; i++) {
+        if (!batches[i]) {
+            delete p;
+            return fail(RB_EINVAL, "null batch");
+        }
+        p->batches.push_back(batches[i]);
+        models[i] = batches[i]->dm;
+        p->maxd = std::max(p->maxd, models[i].maxd);
+        p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);
+    }
+    p->bound_n.assign(nbatch, -1);
+    p->args_host.assign(rb_step_args_size() * nbatch, 0);
+    hipError_t e = hipMalloc((void**)&p->d_models, sizeof(DevModel) * nbatch);
+    if (e == hipSuccess) e = hipMalloc(&p->d_args, rb_step_args_size() * nbatch);
+    if (e == hipSuccess) e = hipMemcpy(p->d_models, models.data(), sizeof(DevModel) * nbatch, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (p->d_models) (void)hipFree(p->d_models);
+        if (p->d_args) (void)hipFree(p->d_args);
+        delete p;
+        return hip_fail(e, "rb_multi_create");
+    }
+    *out = p;
+    return RB_OK;
+}
+
+void rb_multi_destroy(rb_multi* p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    multi_free_graph(p);
+    if (p->d_models) (void)hipFree(p->d_models);
+    if (p->d_args) (void)hipFree(p->d_args);
+    if (p->d_items) (void)hipFree(p->d_items);
+    delete p;
+}
+
+int rb_multi_bind(rb_multi* p, int32_t i, int32_t n, const float* ctrl, float* qpos, float* qvel, const rb_contacts* c,
+                  uint32_t* status) {
+    if (!p || i < 0 || i >= (int)p->batches.size()) return fail(RB_EINVAL, "bad batch index");
+    rb_batch* b = p->batches[i];
+    if (n < 0 || n > b->capacity) return fail(RB_EINVAL, "world count outside the batch capacity");
+    if (n > 0 && (!qpos || !qvel)) return fail(RB_EINVAL, "qpos and qvel are required");
+    if (n > 0 && b->dm.nu > 0 && !ctrl) return fail(RB_EINVAL, "ctrl is required for a model with actuators");
+    DevContactsOut co{};
+    if (c) {
+        co.ncon = c->ncon; co.geom = c->geom; co.feature = c->feature; co.dist = c->dist;
+        co.pos = c->pos; co.frame = c->frame; co.force = c->force;
+    }
+    size_t sz = rb_step_args_size();
+    rb_fill_step_args(p->args_host.data() + sz * i, n, ctrl, qpos, qvel, b->W, c ? &co : nullptr, status);
+    hipError_t e = hipMemcpy((char*)p->d_args + sz * i, p->args_host.data() + sz * i, sz, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "rb_multi_bind");
+    p->bound_n[i] = n;
+    multi_free_graph(p);
+    return RB_OK;
+}
+
+int rb_multi_set_schedule(rb_multi* p, int32_t order, int32_t grid, const float* cost) {
+    if (!p) return fail(RB_EINVAL, "null plan");
+    const int nb = (int)p->batches.size();
+    for (int i = 0; i < nb; i++)
+        if (p->bound_n[i] < 0) return fail(RB_ESTATE, "every batch must be bound before scheduling");
+    std::vector<double> w(nb);
+    for (int i = 0; i < nb; i++) {
+        const DevModel& m = p->batches[i]->dm;
+        w[i] = cost ? (double)cost[i] : (double)m.K * (m.nM + 8.0 * m.ncap + 4.0 * m.nbody);
+    }
+    std::vector<int> items;
+    if (order == RB_ORDER_BATCH || order == RB_ORDER_HEAVY_FIRST) {
+        std::vector<int> idx(nb);
+        for (int i = 0; i < nb; i++) idx[i] = i;
+        if (order == RB_ORDER_HEAVY_FIRST)
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] > w[b]; });
+        for (int i : idx)
+            for (int k = 0; k < p->bound_n[i]; k++) items.push_back(i << 24 | k);
+    } else if (order == RB_ORDER_INTERLEAVE) {
+        // each batch advances through its worlds at a rate proportional to its world count
+        std::vector<int> next(nb, 0);
+        int total = 0;
+        for (int i = 0; i < nb; i++) total += p->bound_n[i];
+        for (int t = 0; t < total; t++) {
+            int best = -1;
+            double bestf = 2.0;
+            for (int i = 0; i < nb; i++) {
+                if (next[i] >= p->bound_n[i]) continue;
+                double f = (next[i] + 0.5) / p->bound_n[i];
+                if (f < bestf) { bestf = f; best = i; }
+            }
+            items.push_back(best << 24 | next[best]++);
+        }
+    } else {
+        return fail(RB_EINVAL, "unknown order");
+    }
+    if (p->d_items) (void)hipFree(p->d_items);
+    p->d_items = nullptr;
+    p->nitems = (int)items.size();
+    if (p->nitems > 0) {
+        hipError_t e = hipMalloc((void**)&p->d_items, sizeof(int) * items.size());
+        if (e == hipSuccess) e = hipMemcpy(p->d_items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "rb_multi_set_schedule");
+    }
+    p->grid = grid > 0 ? std::min(grid, std::max(p->nitems, 1)) : p->nitems;
+    multi_free_graph(p);
+    return RB_OK;
+}
+
+int rb_multi_step(rb_multi* p, void* stream) {
+    if (!p) return fail(RB_EINVAL, "null plan");
+    if (!p->d_items && p->nitems == 0) return RB_OK;
+    if (!p->d_items) return fail(RB_ESTATE, "no schedule");
+    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->lds_floats, p->grid,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? RB_OK : hip_fail(e, "rb_multi_step");
+}
+
+int rb_multi_graph_capture(rb_multi* p, int32_t nsteps, void* stream) {
+    if (!p || nsteps <= 0) return fail(RB_EINVAL, "bad arguments to rb_multi_graph_capture");
+    if (!stream) return fail(RB_EINVAL, "graph capture needs a non-default stream");
+    if (!p->d_items) return fail(RB_ESTATE, "no schedule");
+    multi_free_graph(p);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    for (int k = 0; k < nsteps && e == hipSuccess; k++)
+        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->lds_floats, p->grid, s);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+    }
+    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    p->graph = g;
+    return RB_OK;
+}
+
+int rb_multi_graph_launch(rb_multi* p, void* stream) {
+    if (!p) return fail(RB_EINVAL, "null plan");
+    if (!p->exec) return fail(RB_ESTATE, "nothing captured");
+    hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    return e == hipSuccess ? RB_OK : hip_fail(e, "hipGraphLaunch");
 }
 
 }  // extern "C"

@@ -535,12 +535,11 @@ struct StepArgs {
 
 // MAXD: longest dof chain the instantiation supports; TIMED: accumulate per-stage shader-clock
 // cycles for the stats tap (diagnostic builds of the same kernel).
+#ifndef RB_WAVES_PER_EU
+#define RB_WAVES_PER_EU 3
+#endif
 template <int MAXD, bool TIMED>
-__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(2, 8))) void step_kernel(DevModel m,
-                                                                                                   StepArgs A) {
-    extern __shared__ float lds[];
-    const int w = blockIdx.x;
-    if (w >= A.n) return;
+DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* lds) {
     const int lane = threadIdx.x;
     float* L = lds;
     float* q = L + m.o_q;
@@ -874,46 +873,64 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(2, 8)))
             for (int w2 = 0; w2 < MAXD / 4; w2++) cw[w2] = (uint32_t)__shfl((int)BL.anc[w2], C.body);
 #define CROW(t) rowadr_l[(int)((cw[(t) >> 2] >> (8 * ((t) & 3))) & 0xffu)]
         if (has) {
-            float X[MAXD][3];
+            // A_c = J_c M^-1 J_c' from Y = L'^-1 J_c' on the body's chain (positions t < d):
+            // one column (normal, t1, t2) at a time, keeping only the normal column
             float t2c[3];
             cross(C.n, C.t1, t2c);
+            auto half_solve = [&](const float* dir, float (&Y)[MAXD]) {
 #pragma unroll
-            for (int t = 0; t < MAXD; t++) {
-                X[t][0] = X[t][1] = X[t][2] = 0.f;
-                if (t < d) {
-                    const float* S = cdof + 6 * (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu);
-                    float wr[3];
-                    cross(S, C.r, wr);
-                    float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
-                    X[t][0] = C.sigma * dot(C.n, vp);
-                    X[t][1] = C.sigma * dot(C.t1, vp);
-                    X[t][2] = C.sigma * dot(t2c, vp);
+                for (int t = 0; t < MAXD; t++) {
+                    Y[t] = 0.f;
+                    if (t < d) {
+                        const float* S = cdof + 6 * (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu);
+                        float wr[3];
+                        cross(S, C.r, wr);
+                        float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                        Y[t] = C.sigma * dot(dir, vp);
+                    }
                 }
-            }
 #pragma unroll
-            for (int tp = MAXD - 1; tp >= 1; tp--) {
-                if (tp < d) {
-                    const int row = CROW(tp);
+                for (int tp = MAXD - 1; tp >= 1; tp--) {
+                    if (tp < d) {
+                        const int row = CROW(tp);
 #pragma unroll
-                    for (int t = 0; t < tp; t++) {
-                        float l = H[row + t];
-                        X[t][0] -= l * X[tp][0];
-                        X[t][1] -= l * X[tp][1];
-                        X[t][2] -= l * X[tp][2];
+                        for (int t = 0; t < tp; t++) Y[t] -= H[row + t] * Y[tp];
+                    }
+                }
+            };
+            float Z0[MAXD];
+            float A00 = 0, A11 = 0, A22 = 0, A01 = 0, A02 = 0;
+            {
+                float Y[MAXD];
+                half_solve(C.n, Y);
+#pragma unroll
+                for (int t = 0; t < MAXD; t++) {
+                    Z0[t] = 0.f;
+                    if (t < d) {
+                        Z0[t] = Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
+                        A00 += Y[t] * Z0[t];
                     }
                 }
             }
-            float A00 = 0, A11 = 0, A22 = 0, A01 = 0, A02 = 0;
+            {
+                float Y[MAXD];
+                half_solve(C.t1, Y);
 #pragma unroll
-            for (int t = 0; t < MAXD; t++) {
-                if (t < d) {
-                    float inv = 1.0f / H[CROW(t) + t];
-                    A00 += X[t][0] * X[t][0] * inv;
-                    A11 += X[t][1] * X[t][1] * inv;
-                    A22 += X[t][2] * X[t][2] * inv;
-                    A01 += X[t][0] * X[t][1] * inv;
-                    A02 += X[t][0] * X[t][2] * inv;
-                }
+                for (int t = 0; t < MAXD; t++)
+                    if (t < d) {
+                        A11 += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
+                        A01 += Z0[t] * Y[t];
+                    }
+            }
+            {
+                float Y[MAXD];
+                half_solve(t2c, Y);
+#pragma unroll
+                for (int t = 0; t < MAXD; t++)
+                    if (t < d) {
+                        A22 += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
+                        A02 += Z0[t] * Y[t];
+                    }
             }
             float vrow[4];
             rows_of(C, cvel, vrow);
@@ -1256,9 +1273,84 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(2, 8)))
     }
 }
 
+// One world per 64-lane workgroup.
+template <int MAXD, bool TIMED>
+__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void step_kernel(
+    DevModel m, StepArgs A) {
+    extern __shared__ float lds[];
+    const int w = blockIdx.x;
+    if (w >= A.n) return;
+    world_step<MAXD, TIMED>(m, A, w, lds);
+}
+
+// Mixed-model launch: the grid walks an ordered list of (batch, world) items; each batch has
+// its own compiled model and step arguments.  Every world runs exactly the code of the plain
+// launch, so its result does not depend on the schedule or on the other batches.
+struct MultiArgs {
+    const DevModel* models;   // [nbatch]
+    const StepArgs* args;     // [nbatch]
+    const int* items;         // [nitems] batch << 24 | world
+    int nitems;
+};
+
+template <int MAXD>
+__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
+    MultiArgs M) {
+    extern __shared__ float lds[];
+    for (int it = blockIdx.x; it < M.nitems; it += gridDim.x) {
+        const int item = __builtin_amdgcn_readfirstlane(M.items[it]);
+        const int b = item >> 24, w = item & 0xffffff;
+        const DevModel m = M.models[b];
+        const StepArgs A = M.args[b];
+        if (w < A.n) world_step<MAXD, false>(m, A, w, lds);
+    }
+}
+
 }  // namespace rbk
 
 // ------------------------------------------------------------------ launch
+rbk::StepArgs rb_make_args(int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
+                           const DevContactsOut* co, uint32_t* status_out) {
+    rbk::StepArgs A;
+    A.n = n;
+    A.ctrl = ctrl;
+    A.qpos = qpos;
+    A.qvel = qvel;
+    A.W = W;
+    A.want_contacts = co != nullptr;
+    if (co) A.co = *co; else A.co = DevContactsOut{};
+    A.status_out = status_out;
+    A.want_taps = 0;
+    A.taps = DevTaps{};
+    return A;
+}
+
+size_t rb_step_args_size() { return sizeof(rbk::StepArgs); }
+
+void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
+                       const DevContactsOut* co, uint32_t* status_out) {
+    rbk::StepArgs A = rb_make_args(n, ctrl, qpos, qvel, W, co, status_out);
+    *(rbk::StepArgs*)dst = A;
+}
+
+hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
+                           int lds_floats, int grid, hipStream_t stream) {
+    rbk::MultiArgs M;
+    M.models = models;
+    M.args = (const rbk::StepArgs*)args;
+    M.items = items;
+    M.nitems = nitems;
+    size_t shmem = (size_t)lds_floats * sizeof(float);
+    dim3 g(grid), block(RB_WAVE);
+    if (maxd <= 8)
+        hipLaunchKernelGGL((rbk::multi_kernel<8>), g, block, shmem, stream, M);
+    else if (maxd <= 16)
+        hipLaunchKernelGGL((rbk::multi_kernel<16>), g, block, shmem, stream, M);
+    else
+        hipLaunchKernelGGL((rbk::multi_kernel<32>), g, block, shmem, stream, M);
+    return hipGetLastError();
+}
+
 hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
                           const DevContactsOut* co, uint32_t* status_out, const DevTaps* taps, hipStream_t stream) {
     rbk::StepArgs A;

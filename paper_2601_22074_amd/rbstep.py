@@ -31,7 +31,9 @@ _f64p = C.POINTER(C.c_double)
 
 EXPORTED = ["rb_last_error", "rb_model_create", "rb_model_destroy", "rb_model_info_get", "rb_batch_create",
             "rb_batch_destroy", "rb_batch_contact_capacity", "rb_batch_set_params", "rb_world_reset",
-            "rb_get_state", "rb_step", "rb_step_taps"]
+            "rb_get_state", "rb_step", "rb_step_taps", "rb_multi_create", "rb_multi_destroy", "rb_multi_bind",
+            "rb_multi_set_schedule", "rb_multi_step", "rb_multi_graph_capture", "rb_multi_graph_launch"]
+ORDER_BATCH, ORDER_HEAVY_FIRST, ORDER_INTERLEAVE = 0, 1, 2
 
 
 class RbError(RuntimeError):
@@ -92,6 +94,13 @@ def lib():
         L.rb_get_state.argtypes = [vp, C.c_int32, vp, vp, vp]
         L.rb_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp]
         L.rb_step_taps.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rb_multi_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
+        L.rb_multi_destroy.argtypes = [vp]
+        L.rb_multi_bind.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp]
+        L.rb_multi_set_schedule.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_float)]
+        L.rb_multi_step.argtypes = [vp, vp]
+        L.rb_multi_graph_capture.argtypes = [vp, C.c_int32, vp]
+        L.rb_multi_graph_launch.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -286,3 +295,49 @@ class Batch:
                                   _ptr(a0, torch.float32, (n, nv), "a0"), _ptr(qacc, torch.float32, (n, nv), "qacc"),
                                   _ptr(efc, torch.float32, (n, self.ncap, 4, 3), "efc"),
                                   _ptr(stats, torch.int32, (n, NSTATS), "stats"), _stream(stream)))
+
+
+class Multi:
+    """One fused launch over several batches (rb_multi_*): the batching form."""
+
+    def __init__(self, batches):
+        L = lib()
+        arr = (C.c_void_p * len(batches))(*[b._h for b in batches])
+        h = C.c_void_p()
+        _check(L.rb_multi_create(arr, len(batches), C.byref(h)))
+        self._h = h
+        self.batches = list(batches)
+        self.bound = [None] * len(batches)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rb_multi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bind(self, i, ctrl, qpos, qvel, contacts: Contacts | None = None, status=None) -> None:
+        """Step inputs of batch i (kept alive by the plan until rebound)."""
+        n, pc, pq, pv, ps = self.batches[i]._common(ctrl, qpos, qvel, status)
+        cs = C.byref(contacts._struct(n)) if contacts is not None else None
+        _check(lib().rb_multi_bind(self._h, int(i), int(n), pc, pq, pv, cs, ps))
+        self.bound[i] = (ctrl, qpos, qvel, contacts, status)
+
+    def set_schedule(self, order: int = ORDER_HEAVY_FIRST, grid: int = 0, cost=None) -> None:
+        c = None
+        if cost is not None:
+            c = (C.c_float * len(self.batches))(*[float(x) for x in cost])
+        _check(lib().rb_multi_set_schedule(self._h, int(order), int(grid), c))
+
+    def step(self, stream=None) -> None:
+        _check(lib().rb_multi_step(self._h, _stream(stream)))
+
+    def graph_capture(self, nsteps: int, stream) -> None:
+        _check(lib().rb_multi_graph_capture(self._h, int(nsteps), _stream(stream)))
+
+    def graph_launch(self, stream=None) -> None:
+        _check(lib().rb_multi_graph_launch(self._h, _stream(stream)))
