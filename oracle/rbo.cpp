@@ -24,6 +24,7 @@
 #include "rbo.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -395,6 +396,7 @@ int pair_capacity(int t1, int t2) {
     if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_SPHERE) return 1;
     if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_CAPSULE) return 2;
     if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_BOX) return 8;
+    if (t1 == RBO_GEOM_BOX && t2 == RBO_GEOM_BOX) return 8;
     return -1;
 }
 
@@ -429,6 +431,158 @@ void add_contact(const Model& m, Data& d, int g1, int g2, int feature, double di
     d.con.push_back(c);
 }
 
+// Box-box by the separating-axis test (Ericson 2004, ch. 4.4 and 5.2): overlaps along the 6
+// face normals and the 9 edge-edge cross products; the axis of least overlap (earlier axes
+// win unless a later one is smaller by more than 1e-5 (1 + overlap)) gives the normal from
+// g1 to g2.  Face axis: the incident face (most anti-parallel to the reference face) is
+// clipped against the reference face's four side planes and every clipped point below the
+// reference face is a contact, midway between the point and the face.  Edge axis: one
+// contact midway between the closest points of the two supporting edges, depth -overlap.
+void box_box(const Model& m, Data& d, int g1, int g2, double margin) {
+    const double* cA = &d.gx[3 * g1];
+    const double* cB = &d.gx[3 * g2];
+    const double* RA = &d.gR[9 * g1];
+    const double* RB = &d.gR[9 * g2];
+    const double* hA = &m.gsize[3 * g1];
+    const double* hB = &m.gsize[3 * g2];
+    double aA[3][3], aB[3][3], dc[3];
+    for (int i = 0; i < 3; i++)
+        for (int k = 0; k < 3; k++) {
+            aA[i][k] = RA[3 * k + i];  // column i of the rotation = box axis i
+            aB[i][k] = RB[3 * k + i];
+        }
+    for (int k = 0; k < 3; k++) dc[k] = cB[k] - cA[k];
+    int best = -1;
+    double best_ov = 0, best_ax[3] = {0, 0, 0};
+    for (int ax = 0; ax < 15; ax++) {
+        double L[3];
+        if (ax < 3) {
+            for (int k = 0; k < 3; k++) L[k] = aA[ax][k];
+        } else if (ax < 6) {
+            for (int k = 0; k < 3; k++) L[k] = aB[ax - 3][k];
+        } else {
+            int i = (ax - 6) / 3, j = (ax - 6) % 3;
+            cross3(aA[i], aB[j], L);
+            double n = std::sqrt(dot3(L, L));
+            if (n < 1e-6) continue;
+            for (int k = 0; k < 3; k++) L[k] /= n;
+        }
+        double rA = 0, rB = 0;
+        for (int i = 0; i < 3; i++) {
+            rA += hA[i] * std::fabs(dot3(L, aA[i]));
+            rB += hB[i] * std::fabs(dot3(L, aB[i]));
+        }
+        double ov = rA + rB - std::fabs(dot3(L, dc));
+        if (-ov >= margin) return;  // separated along this axis
+        if (best < 0 || ov < best_ov - 1e-5 * (1 + std::fabs(best_ov))) {
+            best = ax;
+            best_ov = ov;
+            for (int k = 0; k < 3; k++) best_ax[k] = L[k];
+        }
+    }
+    if (best < 0) return;
+    double n[3];
+    double sgn = dot3(best_ax, dc) < 0 ? -1.0 : 1.0;
+    for (int k = 0; k < 3; k++) n[k] = sgn * best_ax[k];
+    if (best < 6) {
+        bool refA = best < 3;
+        int rax = refA ? best : best - 3;
+        const double* cR = refA ? cA : cB;
+        const double* hR = refA ? hA : hB;
+        double (*aR)[3] = refA ? aA : aB;
+        const double* cI = refA ? cB : cA;
+        const double* hI = refA ? hB : hA;
+        double (*aI)[3] = refA ? aB : aA;
+        double nr[3];  // outward normal of the reference face
+        for (int k = 0; k < 3; k++) nr[k] = refA ? n[k] : -n[k];
+        double pR[3];
+        for (int k = 0; k < 3; k++) pR[k] = cR[k] + hR[rax] * nr[k];
+        int u = (rax + 1) % 3, v = (rax + 2) % 3;
+        if (u > v) std::swap(u, v);
+        // incident face: most anti-parallel to the reference normal (lowest axis on ties)
+        int ia = 0;
+        double bestdot = -1;
+        for (int j = 0; j < 3; j++) {
+            double a = std::fabs(dot3(aI[j], nr));
+            if (a > bestdot + 1e-12) { bestdot = a; ia = j; }
+        }
+        double s = dot3(aI[ia], nr) > 0 ? -1.0 : 1.0;
+        int p = (ia + 1) % 3, q = (ia + 2) % 3;
+        if (p > q) std::swap(p, q);
+        double fc[3];
+        for (int k = 0; k < 3; k++) fc[k] = cI[k] + s * hI[ia] * aI[ia][k];
+        const double sp[4] = {1, -1, -1, 1}, sq[4] = {1, 1, -1, -1};
+        std::vector<std::array<double, 3>> poly(4);
+        for (int c = 0; c < 4; c++)
+            for (int k = 0; k < 3; k++) poly[c][k] = fc[k] + sp[c] * hI[p] * aI[p][k] + sq[c] * hI[q] * aI[q][k];
+        // Sutherland-Hodgman against (x.u <= hu), (-x.u <= hu), (x.v <= hv), (-x.v <= hv), x = point - pR
+        for (int plane = 0; plane < 4; plane++) {
+            const double* dir = plane < 2 ? aR[u] : aR[v];
+            double ext = plane < 2 ? hR[u] : hR[v];
+            double sg = (plane % 2 == 0) ? 1.0 : -1.0;
+            std::vector<std::array<double, 3>> out;
+            size_t np = poly.size();
+            for (size_t i = 0; i < np; i++) {
+                const auto& P = poly[i];
+                const auto& Q = poly[(i + 1) % np];
+                double x[3], y[3];
+                for (int k = 0; k < 3; k++) { x[k] = P[k] - pR[k]; y[k] = Q[k] - pR[k]; }
+                double fp = sg * dot3(x, dir) - ext, fq = sg * dot3(y, dir) - ext;
+                if (fp <= 0) out.push_back(P);
+                if ((fp < 0 && fq > 0) || (fp > 0 && fq < 0)) {
+                    double t = fp / (fp - fq);
+                    std::array<double, 3> I;
+                    for (int k = 0; k < 3; k++) I[k] = P[k] + t * (Q[k] - P[k]);
+                    out.push_back(I);
+                }
+            }
+            poly.swap(out);
+            if (poly.empty()) return;
+        }
+        int feat = 0;
+        for (const auto& P : poly) {
+            double x[3];
+            for (int k = 0; k < 3; k++) x[k] = P[k] - pR[k];
+            double dist = dot3(x, nr);
+            if (dist < margin && feat < 8) {
+                double pos[3];
+                for (int k = 0; k < 3; k++) pos[k] = P[k] - nr[k] * dist / 2;
+                add_contact(m, d, g1, g2, feat, dist, pos, n);
+            }
+            feat++;
+        }
+    } else {
+        int i = (best - 6) / 3, j = (best - 6) % 3;
+        double PA[3], PB[3];
+        for (int k = 0; k < 3; k++) { PA[k] = cA[k]; PB[k] = cB[k]; }
+        for (int a = 0; a < 3; a++) {
+            if (a != i) {
+                double sa = dot3(n, aA[a]) >= 0 ? 1.0 : -1.0;
+                for (int k = 0; k < 3; k++) PA[k] += sa * hA[a] * aA[a][k];
+            }
+            if (a != j) {
+                double sb = dot3(n, aB[a]) >= 0 ? -1.0 : 1.0;
+                for (int k = 0; k < 3; k++) PB[k] += sb * hB[a] * aB[a][k];
+            }
+        }
+        // closest points of PA + t aA_i (|t| <= hA_i) and PB + w aB_j (|w| <= hB_j)
+        double r[3];
+        for (int k = 0; k < 3; k++) r[k] = PA[k] - PB[k];
+        double b = dot3(aA[i], aB[j]), c = dot3(aA[i], r), f = dot3(aB[j], r);
+        double den = 1 - b * b;
+        double t = den > 1e-12 ? (b * f - c) / den : 0.0;
+        t = std::min(std::max(t, -hA[i]), hA[i]);
+        double w = b * t + f;
+        if (w < -hB[j] || w > hB[j]) {
+            w = std::min(std::max(w, -hB[j]), hB[j]);
+            t = std::min(std::max(b * w - c, -hA[i]), hA[i]);
+        }
+        double pos[3];
+        for (int k = 0; k < 3; k++) pos[k] = 0.5 * (PA[k] + t * aA[i][k] + PB[k] + w * aB[j][k]);
+        add_contact(m, d, g1, g2, 0, -best_ov, pos, n);
+    }
+}
+
 void collide(const Model& m, Data& d) {
     d.con.clear();
     for (int ga = 0; ga < m.ngeom; ga++)
@@ -438,7 +592,11 @@ void collide(const Model& m, Data& d) {
             if (m.gtype[g2] < m.gtype[g1]) std::swap(g1, g2);
             int t1 = m.gtype[g1], t2 = m.gtype[g2];
             double margin = std::max(m.gmargin[g1], m.gmargin[g2]);
-            if (t1 != RBO_GEOM_PLANE) continue;  // pairs without a plane were rejected at creation
+            if (t1 == RBO_GEOM_BOX && t2 == RBO_GEOM_BOX) {
+                box_box(m, d, g1, g2, margin);
+                continue;
+            }
+            if (t1 != RBO_GEOM_PLANE) continue;  // other pairs were rejected at creation
             const double* Rp = &d.gR[9 * g1];
             double n[3] = {Rp[2], Rp[5], Rp[8]};  // plane normal = plane's local +z
             const double* p0 = &d.gx[3 * g1];

@@ -330,3 +330,154 @@ def test_no_contact_means_smooth_acceleration(oracle_mod):
     np.testing.assert_allclose(t["M"] @ t["a0"], t["tau"] - t["bias"], rtol=1e-12, atol=1e-12)
     # position actuators: tau = kp (ctrl - q) - kd v on each driven hinge
     np.testing.assert_allclose(t["tau"][6:], 20 * (0.3 - q[7:]) - 0.5 * 0.1, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- box-box
+def _table_cube(cube_pos, cube_quat=(1, 0, 0, 0), table_half=(0.3, 0.3, 0.2), h=0.025):
+    mb = robots.ModelBuilder("table_cube", timestep=0.005, nsubsteps=1)
+    mb.geom(0, "box", list(table_half), pos=(0, 0, table_half[2]), contype=0, conaffinity=1)
+    b = mb.body("cube", 0, (0, 0, 1), 0.1, robots.box_inertia(0.1, h, h, h))
+    mb.joint(b, "free")
+    mb.geom(b, "box", [h, h, h], contype=1, conaffinity=0)
+    m = mb.build()
+    q = np.concatenate([cube_pos, cube_quat])
+    return m, q
+
+
+def test_box_box_resting_cube_corners(oracle_mod):
+    dz = 2e-4
+    m, q = _table_cube([0.1, -0.05, 0.4 + 0.025 - dz])
+    o = oracle_mod.Oracle(m)
+    assert o.maxcon == 8
+    t = o.forward(q, np.zeros(6))
+    assert t["ncon"] == 4
+    np.testing.assert_allclose(t["frame"][:, 0], np.tile([0, 0, 1.0], (4, 1)), atol=1e-15)
+    np.testing.assert_allclose(t["dist"], -dz, atol=1e-12)
+    exp = {(0.1 + sx * 0.025, -0.05 + sy * 0.025) for sx in (-1, 1) for sy in (-1, 1)}
+    got = {(round(p[0], 12), round(p[1], 12)) for p in t["pos"]}
+    assert got == {(round(a, 12), round(b, 12)) for a, b in exp}
+    np.testing.assert_allclose(t["pos"][:, 2], 0.4 - dz / 2, atol=1e-12)
+    assert list(t["feature"]) == [0, 1, 2, 3]
+
+
+def test_box_box_overhanging_cube_clipped(oracle_mod):
+    dz = 1e-4
+    x = 0.3 - 0.01       # cube spans x in [0.265, 0.315]: clipped at the table edge x = 0.3
+    m, q = _table_cube([x, 0.0, 0.4 + 0.025 - dz])
+    o = oracle_mod.Oracle(m)
+    t = o.forward(q, np.zeros(6))
+    assert t["ncon"] == 4
+    xs = sorted(set(np.round(t["pos"][:, 0], 12)))
+    np.testing.assert_allclose(xs, [x - 0.025, 0.3], atol=1e-12)
+    ys = sorted(set(np.round(t["pos"][:, 1], 12)))
+    np.testing.assert_allclose(ys, [-0.025, 0.025], atol=1e-12)
+    np.testing.assert_allclose(t["dist"], -dz, atol=1e-12)
+
+
+def test_box_box_rotated_cube(oracle_mod):
+    dz = 3e-4
+    qz = robots.quat_axis_angle((0, 0, 1), math.pi / 4)
+    m, q = _table_cube([0.0, 0.0, 0.4 + 0.025 - dz], qz)
+    t = oracle_mod.Oracle(m).forward(q, np.zeros(6))
+    assert t["ncon"] == 4
+    r = 0.025 * math.sqrt(2)
+    pts = {(round(p[0], 10), round(p[1], 10)) for p in t["pos"]}
+    assert pts == {(round(a, 10), round(b, 10)) for a, b in [(r, 0), (-r, 0), (0, r), (0, -r)]}
+
+
+def test_box_box_separated_and_touching(oracle_mod):
+    m, q = _table_cube([0.0, 0.0, 0.4 + 0.025 + 1e-4])
+    assert oracle_mod.Oracle(m).forward(q, np.zeros(6))["ncon"] == 0
+    m, q = _table_cube([0.0, 0.0, 0.4 + 0.025])            # exactly touching: dist 0 is not < 0
+    assert oracle_mod.Oracle(m).forward(q, np.zeros(6))["ncon"] == 0
+
+
+def test_box_box_edge_edge(oracle_mod):
+    """A table edge (along y) pressed by a cube edge crossing it at right angles: one contact
+    at the crossing, depth = the edge-edge overlap."""
+    qt = robots.quat_axis_angle((0, 1, 0), math.pi / 4)        # table turned: its top edge ridge along y
+    mb = robots.ModelBuilder("edges", timestep=0.005, nsubsteps=1)
+    mb.geom(0, "box", [0.3, 0.3, 0.3], pos=(0, 0, 0), quat=qt, contype=0, conaffinity=1)
+    b = mb.body("cube", 0, (0, 0, 1), 0.1, robots.box_inertia(0.1, 0.025, 0.025, 0.025))
+    mb.joint(b, "free")
+    mb.geom(b, "box", [0.025, 0.025, 0.025], contype=1, conaffinity=0)
+    m = mb.build()
+    qc = robots.quat_axis_angle((1, 0, 0), math.pi / 4)        # cube turned: its bottom edge along x
+    ridge = 0.3 * math.sqrt(2)
+    pen = 1e-3
+    zc = ridge + 0.025 * math.sqrt(2) - pen
+    t = oracle_mod.Oracle(m).forward(np.concatenate([[0.0, 0.0, zc], qc]), np.zeros(6))
+    assert t["ncon"] == 1 and t["feature"][0] == 0
+    np.testing.assert_allclose(t["dist"][0], -pen, atol=1e-12)
+    np.testing.assert_allclose(t["frame"][0][0], [0, 0, 1], atol=1e-12)
+    np.testing.assert_allclose(t["pos"][0], [0, 0, ridge - pen / 2], atol=1e-12)
+
+
+def _box_vertices(center, R, half):
+    s = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], float)
+    return center + (s * half) @ R.T
+
+
+def _overlap(va, vb, u):
+    pa, pb = va @ u, vb @ u
+    return min(pa.max() - pb.min(), pb.max() - pa.min())
+
+
+def test_box_box_depth_is_minimal_overlap(oracle_mod):
+    """Random orientations: the reported normal carries the smallest projection overlap of the
+    two boxes over all directions (checked against a dense direction sample), and no contact is
+    deeper than that overlap."""
+    rng = np.random.default_rng(7)
+    k = np.arange(40000) + 0.5
+    phi = np.arccos(1 - 2 * k / len(k))
+    th = math.pi * (1 + 5 ** 0.5) * k
+    dirs = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    half_t = np.array([0.3, 0.3, 0.2])
+    half_c = np.array([0.025, 0.025, 0.025])
+    seen = 0
+    for _ in range(12):
+        qc = rng.normal(size=4)
+        qc /= np.linalg.norm(qc)
+        Rc = rot(qc)
+        zext = np.abs(Rc[2]) @ half_c
+        pen = rng.uniform(1e-4, 4e-3)
+        c = np.array([rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2), 0.4 + zext - pen])
+        m, q = _table_cube(c, qc)
+        t = oracle_mod.Oracle(m).forward(q, np.zeros(6))
+        assert t["ncon"] >= 1
+        vt = _box_vertices(np.array([0, 0, 0.2]), np.eye(3), half_t)
+        vc = _box_vertices(c, Rc, half_c)
+        n = t["frame"][0, 0]
+        ov = _overlap(vt, vc, n)
+        ovs = np.array([_overlap(vt, vc, d) for d in dirs])
+        best, u = ovs.min(), dirs[ovs.argmin()]
+        for r in (0.03, 3e-3, 3e-4):            # refine around the best direction found so far
+            cap = u + r * rng.normal(size=(4000, 3))
+            cap /= np.linalg.norm(cap, axis=1, keepdims=True)
+            o2 = np.array([_overlap(vt, vc, d) for d in cap])
+            if o2.min() < best:
+                best, u = o2.min(), cap[o2.argmin()]
+        assert ov <= best + 1e-9
+        assert ov >= best - 2e-5
+        assert np.all(-t["dist"][: t["ncon"]] <= ov + 1e-12)
+        seen += t["ncon"]
+    assert seen > 12
+
+
+def test_box_box_cube_settles_on_table(oracle_mod):
+    """The arm-and-cube scene: the cube dropped 1 mm onto the static table comes to rest on four
+    corner contacts that together carry exactly its weight."""
+    m = robots.arm_box()
+    o = oracle_mod.Oracle(m)
+    q = np.array([robots.qpos0(m)], np.float64)
+    v = np.zeros((1, o.nv))
+    ws = np.zeros((1, o.nv))
+    st = np.zeros(1, np.uint32)
+    for _ in range(60):
+        _, c = o.step(np.zeros((1, o.nu)), q, v, ws, status=st, contacts=True)
+    n = c["ncon"][0]
+    assert st[0] == 0 and n == 4
+    assert all(tuple(g) == (1, len(m["geoms"]) - 1) for g in c["geom"][0, :n])
+    np.testing.assert_allclose(c["force"][0, :n, 0].sum(), 0.1 * 9.81, rtol=1e-6)
+    assert np.abs(v[0, -6:]).max() < 1e-6
+    assert abs(q[0, -7] - 0.5) < 1e-12 and 0.4 + 0.025 - 1e-3 < q[0, -5] < 0.4 + 0.025
