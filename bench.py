@@ -33,7 +33,216 @@ WORKLOAD_TEXT = {
     "quadruped": "quadruped: free base + 12 hinges, 13 bodies, sphere feet + box torso vs plane, friction 1, "
                  "PD kp 20 kd 0.5, dt 5 ms x 4 substeps, ctrl N(0,0.3)/20 steps",
     "chain3": "3-link planar hinge chain, contact-free, dt 2 ms, K = 1",
+    "arm_box": "7-hinge arm (non-colliding links) beside a static table box with a 5 cm free cube on it: "
+               "box-box and box-plane contacts, dt 5 ms x 4 substeps, ctrl N(0,0.2)/20 steps",
+    "mix": "mixed batch: chain3 x512 + quadruped x4096 + humanoid x2048 + arm_box x1024 (7680 worlds), "
+           "each model's own dt and substeps, contacts returned",
 }
+MIX = [("chain3", 512), ("quadruped", 4096), ("humanoid", 2048), ("arm_box", 1024)]
+WORKLOAD_TEXT["serve"] = ("serving: Poisson arrivals of rollout requests, model uniform over chain3/quadruped/humanoid/"
+                          "arm_box, worlds log-uniform 16-4096, horizon uniform 50-500 env steps, device-side seeded "
+                          "inputs, HBM-budget admission, continuous batching in one fused launch per tick")
+
+
+# ------------------------------------------------------------------ mixed-model batching
+def run_mix(args):
+    """The batching form on the mixed batch: one env step of every world per call, timed for
+    (a) separate plain launches back to back on one stream, (b) the same on one stream per
+    model, (c) the fused launch under the autotuned schedule and (d) that launch replayed from
+    a captured hipGraph of one control period.  Every form starts from the same state; its
+    final state is compared bit for bit with (a)."""
+    import torch
+    import paper_2601_22074_amd as rb
+    from paper_2601_22074_amd import autotune
+    from workloads import inputs
+
+    dev = torch.device("cuda:0")
+    K, warm = args.steps, args.warmup
+    P = inputs.CTRL_PERIOD
+    K = max(P, K // P * P)
+    warm = (warm + P - 1) // P * P
+    Ws = [inputs.workload(name, n, warm + K) for name, n in MIX]
+    models = [rb.Model(W["model"]) for W in Ws]
+
+    def fresh():
+        S = []
+        for (name, n), W, model in zip(MIX, Ws, models):
+            b = rb.Batch(model, n)
+            if W["friction"] is not None:
+                b.set_params(rb.PARAM_FRICTION, torch.tensor(W["friction"], device=dev))
+            if W["mass_scale"] is not None:
+                b.set_params(rb.PARAM_MASS_SCALE, torch.tensor(W["mass_scale"], device=dev))
+            ctab = torch.tensor(W["ctrl"], device=dev).contiguous()
+            if ctab.shape[-1] == 0:
+                ctab = torch.zeros(ctab.shape[0], n, 1, device=dev)
+            S.append(dict(batch=b, n=n, ctab=ctab, u=ctab[0].clone(), q=torch.tensor(W["qpos"], device=dev),
+                          v=torch.tensor(W["qvel"], device=dev), con=b.contacts(n),
+                          st=torch.zeros(n, dtype=torch.int32, device=dev)))
+        torch.cuda.synchronize()
+        return S
+
+    def seg(S, s):
+        return [x["ctab"][min(s // P, x["ctab"].shape[0] - 1)] for x in S]
+
+    def timed(S, step_fn, period_fn=None):
+        stream = torch.cuda.current_stream()
+        for s in range(warm):
+            if s % P == 0 and period_fn:
+                period_fn(S, s)
+            step_fn(S, s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for s in range(warm, warm + K):
+            if s % P == 0 and period_fn:
+                period_fn(S, s)
+            step_fn(S, s)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    def finals(S):
+        return [(x["q"].cpu().numpy(), x["v"].cpu().numpy(), x["st"].cpu().numpy()) for x in S]
+
+    nworlds = sum(n for _, n in MIX)
+    res, equal = {}, {}
+    # (a) separate launches, one stream
+    S = fresh()
+
+    def sep(S, s):
+        for x, u in zip(S, seg(S, s)):
+            x["batch"].step(u, x["q"], x["v"], x["con"], x["st"])
+    res["separate"] = timed(S, sep)
+    ref = finals(S)
+
+    # (b) separate launches, one stream per model (default priority), joined every step
+    S = fresh()
+    streams = [torch.cuda.Stream() for _ in S]
+    main = torch.cuda.current_stream()
+
+    def sep4(S, s):
+        ev = torch.cuda.Event()
+        ev.record(main)
+        for x, u, st in zip(S, seg(S, s), streams):
+            st.wait_event(ev)
+            x["batch"].step(u, x["q"], x["v"], x["con"], x["st"], stream=st)
+        for st in streams:
+            e = torch.cuda.Event()
+            e.record(st)
+            main.wait_event(e)
+    res["separate_streams"] = timed(S, sep4)
+    equal["separate_streams"] = all(all(np.array_equal(a, b) for a, b in zip(r, f)) for r, f in zip(ref, finals(S)))
+
+    # (c) fused launch, autotuned schedule
+    S = fresh()
+    plan = rb.Multi([x["batch"] for x in S])
+    for i, x in enumerate(S):
+        plan.bind(i, x["u"], x["q"], x["v"], x["con"], x["st"])
+    choice, timings = autotune.tune(plan, [(x["u"], x["q"], x["v"]) for x in S], reps=3, resident=args.resident)
+    for i, x in enumerate(S):
+        plan.bind(i, x["u"], x["q"], x["v"], x["con"], x["st"])
+    if choice[0] != "fused":
+        choice = ("fused", rb.ORDER_HEAVY_FIRST, 0)
+    plan.set_schedule(choice[1], choice[2])
+
+    def load_ctrl(S, s):
+        for x, u in zip(S, seg(S, s)):
+            x["u"].copy_(u)
+
+    res["fused"] = timed(S, lambda S, s: plan.step(), load_ctrl)
+    equal["fused"] = all(all(np.array_equal(a, b) for a, b in zip(r, f)) for r, f in zip(ref, finals(S)))
+    plan.close()
+
+    # (d) fused launch replayed from a hipGraph of one control period (P env steps)
+    S = fresh()
+    plan = rb.Multi([x["batch"] for x in S])
+    for i, x in enumerate(S):
+        plan.bind(i, x["u"], x["q"], x["v"], x["con"], x["st"])
+    plan.set_schedule(choice[1], choice[2])
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    plan.graph_capture(P, side)
+    torch.cuda.synchronize()
+
+    def graph_period(S, s):
+        load_ctrl(S, s)
+        plan.graph_launch(torch.cuda.current_stream())
+
+    ms = timed(S, lambda S, s: None, graph_period)
+    res["fused_graph"] = ms
+    equal["fused_graph"] = all(all(np.array_equal(a, b) for a, b in zip(r, f)) for r, f in zip(ref, finals(S)))
+    plan.close()
+
+    rates = {k: nworlds / (v / 1e3) for k, v in res.items()}
+    best = max(("fused", "fused_graph"), key=lambda k: rates[k])
+    out = {
+        "metric": "env-steps/sec, mixed batch (chain3 x512 + quadruped x4096 + humanoid x2048 + arm_box x1024)",
+        "value": rates[best],
+        "unit": "env-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": warm,
+        "ms_per_step": res[best],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["mix"], "worlds": nworlds, "env_steps": K, "form": best,
+                   "schedule": {"order": choice[1], "grid": choice[2]}, "graph_steps": P},
+        "forms_env_steps_per_s": rates,
+        "forms_ms_per_step": res,
+        "speedup_vs_separate": rates[best] / rates["separate"],
+        "bitwise_equal_to_separate": equal,
+        "autotune_timings_ms": timings,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ serving
+def run_serve(args):
+    """The serving form: (a) the offered load (Poisson rate --rate for --seconds), stopped at
+    that time with whatever is still queued counted as backlog; (b) a rate the measured
+    throughput sustains (80 % of it), run to completion, for steady-state latency."""
+    import torch
+    from paper_2601_22074_amd.serve import Server
+    from workloads import robots
+    from workloads.requests import NAMES, DeviceSource, mean_request_work, poisson_requests
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    src = DeviceSource({k: robots.by_name(k) for k in NAMES})
+    budget = int(args.budget_mb) << 20
+
+    srv = Server(src, budget=budget)
+    # warm-up: compile and first launches outside the timed runs
+    srv.run_script(poisson_requests(50.0, 0.2, seed=99, wmax=64, hmax=50))
+    srv.close()
+
+    srv = Server(src, budget=budget)
+    reqs = poisson_requests(args.rate, args.seconds, seed=1)
+    log(f"serve: offered {len(reqs)} requests over {args.seconds} s")
+    a = srv.run_timed(reqs, stop_after=args.seconds, progress=log)
+    srv.close()
+    offered = args.rate * mean_request_work()
+    lam = 0.8 * a["env_steps_per_s"] / mean_request_work()
+    srv = Server(src, budget=budget)
+    reqs_b = poisson_requests(lam, args.sustain_seconds, seed=2)
+    log(f"serve: sustainable-rate run at {lam:.2f}/s, {len(reqs_b)} requests")
+    b = srv.run_timed(reqs_b, progress=log)
+    srv.close()
+    out = {
+        "metric": f"env-steps/sec served at Poisson {args.rate:g} requests/s; p50/p99 request latency",
+        "value": a["env_steps_per_s"],
+        "unit": "env-steps/s",
+        "n_gpus": 1, "steps": a["ticks"], "warmup": 0,
+        "ms_per_step": 1e3 * a["wall_s"] / max(a["ticks"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["serve"], "rate_per_s": args.rate, "seconds": args.seconds,
+                   "budget_bytes": budget},
+        "offered_env_steps_per_s": offered,
+        "offered_load": a,
+        "sustainable_rate_per_s": lam,
+        "sustainable": b,
+    }
+    print(json.dumps(out), flush=True)
 
 
 # ------------------------------------------------------------------ work model
@@ -234,12 +443,18 @@ def main():
     ap.add_argument("--stats-worlds", type=int, default=512)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
+    ap.add_argument("--resident", type=int, default=2048,
+                    help="mix: resident-grid size the autotuner tries (persistent launch)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: request arrival rate (1/s)")
+    ap.add_argument("--seconds", type=float, default=60.0, help="serve: arrival window of the offered-load run")
+    ap.add_argument("--sustain-seconds", type=float, default=20.0, help="serve: arrival window at the sustained rate")
+    ap.add_argument("--budget-mb", type=int, default=1024, help="serve: HBM budget for admitted requests (MiB)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
                     help="write profiles/ summaries from rocprofv3 databases and exit")
     args = ap.parse_args()
     if args.summarize:
         wl = args.workload
-        nwd = args.worlds or {"humanoid": 8192, "quadruped": 4096, "chain3": 64}[wl]
+        nwd = args.worlds or {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 1024}[wl]
         cmds = {"trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace -- "
                          "python bench.py --steps 50 --warmup 5 --no-cpu --stats-worlds 64",
                 "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch -- "
@@ -253,11 +468,17 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "mix":
+        run_mix(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
+        return
     import torch
     import paper_2601_22074_amd as rb
     from workloads import inputs
 
-    default_worlds = {"humanoid": 8192, "quadruped": 4096, "chain3": 64}
+    default_worlds = {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 1024}
     nw = args.worlds or default_worlds[args.workload]
     K, warm = args.steps, args.warmup
     W = inputs.workload(args.workload, nw, warm + K)

@@ -106,7 +106,7 @@ const char* rb_last_error(void);
 /* Validate and compile a model; uploads its constants to the current HIP device.
  * Rejects (RB_EINVAL): parent >= child, non-positive mass or inertia violating the
  * triangle inequality, non-unit quaternions, misplaced joints, unknown types,
- * collision pairs other than plane-{sphere, capsule, box}, pairs whose bodies can both
+ * collision pairs other than plane-{sphere, capsule, box} and box-box, pairs whose bodies can both
  * move, more than 64 dofs, 64 collision pairs or a dof chain deeper than 32. */
 int rb_model_create(const rb_model_desc* desc, rb_model** out);
 void rb_model_destroy(rb_model* model);
@@ -125,6 +125,11 @@ int32_t rb_batch_contact_capacity(const rb_batch* batch);
  * [n, nbody] floats (scales each body's mass and rotational inertia; the model must have
  * mass_scale_per_world).  Device pointer; copied on the stream. */
 int rb_batch_set_params(rb_batch* batch, int32_t field, int32_t n, const float* dev_vals, void* hip_stream);
+
+/* As rb_batch_set_params for slots [first, first + n): dev_vals holds those n worlds' values.
+ * RB_EINVAL when the range leaves the batch. */
+int rb_batch_set_params_at(rb_batch* batch, int32_t field, int32_t first, int32_t n, const float* dev_vals,
+                           void* hip_stream);
 
 /* Reset n worlds named by dev_ids [n] (int32, device): clear their status and set their
  * warm start from dev_qacc_ws [n, nv] (device; NULL = zero). */
@@ -184,7 +189,16 @@ int rb_multi_bind(rb_multi* plan, int32_t i, int32_t n, const float* dev_ctrl, f
  * many persistent workgroups walking the list.  Call after every batch is bound. */
 int rb_multi_set_schedule(rb_multi* plan, int32_t order, int32_t grid, const float* cost);
 
-/* One env step of every bound batch in one launch on the stream. */
+/* An explicit work list instead of a schedule: host_items [n] (host memory, read before the
+ * call returns) of batch << 24 | world, each world below the n bound for its batch, in
+ * dispatch order; grid as in rb_multi_set_schedule.  The list is uploaded asynchronously on
+ * the stream (through pinned staging owned by the plan), so later rb_multi_step calls on the
+ * same stream use it and earlier ones keep the previous list; steps must therefore be issued
+ * on that stream.  This is how a serving loop steps exactly the worlds of its live requests
+ * without stopping the device.  RB_EINVAL on an item outside the bound batches. */
+int rb_multi_set_items(rb_multi* plan, const int32_t* host_items, int32_t n, int32_t grid, void* hip_stream);
+
+/* One env step of every scheduled world in one launch on the stream. */
 int rb_multi_step(rb_multi* plan, void* hip_stream);
 
 /* Capture nsteps fused steps into a graph on the (non-default) stream, replacing any earlier

@@ -12,10 +12,13 @@
 #define RB_MAX_CON 64
 #define RB_NSTAGE 10              // timed kernel stages in the stats tap
 #define RB_NSTATS (4 + RB_NSTAGE) // stats tap columns per world
+#define RB_PAIR_BOXBOX 16         // pair_type of a box-box pair (other pairs hold g2's geom type)
+#define RB_BB_FLOATS 96           // LDS floats per box-box pair: clip buffers, contacts, normal
 
 struct DevModel {
     // sizes
     int nbody, nv, nq, nu, njnt, npair, ncap, maxd;
+    int nbb;       // box-box pairs (each has an LDS block)
     int nblevel;   // body levels 1..nblevel (level 0 = world)
     int ndlevel;   // dof depth levels 1..ndlevel
     int K, maxiter;
@@ -75,10 +78,11 @@ struct DevModel {
     const int* jnt_type;
     const int* jnt_qadr;
     const int* jnt_dadr;
-    // collision pairs [npair], in (g1, g2) order; g1 is the plane
+    // collision pairs [npair], in (g1, g2) order; g1 is the plane, or the lower-numbered box
     const int* pair_g1;
     const int* pair_g2;
-    const int* pair_type;      // geom type of g2
+    const int* pair_type;      // geom type of g2 (plane pairs) or RB_PAIR_BOXBOX
+    const int* pair_slot;      // box-box pairs: index of the pair's LDS block; -1 otherwise
     const int* pair_body;      // the body that can move
     const int* pair_cap;       // contacts the pair can produce
     const float* pair_sigma;   // +1 if the moving body carries g2, -1 if it carries g1
@@ -92,7 +96,7 @@ struct DevModel {
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
     int o_xpos, o_xquat, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
     int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp;
-    int o_M, o_H, o_misc, o_piv, o_rowadr;
+    int o_M, o_H, o_misc, o_piv, o_rowadr, o_bb;
     int lds_floats;
 };
 

@@ -25,7 +25,7 @@ size_t rb_step_args_size();
 void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
                        const DevContactsOut* co, uint32_t* status_out);
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
-                           int lds_floats, int grid, hipStream_t stream);
+                           bool boxbox, int lds_floats, int grid, hipStream_t stream);
 
 namespace {
 
@@ -325,8 +325,10 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             if (movable[ba] && movable[bb]) return fail(RB_EINVAL, "contacts between two moving bodies are not supported");
             int g1 = a, g2 = b;
             if (d->geom_type[g2] < d->geom_type[g1]) std::swap(g1, g2);
-            if (d->geom_type[g1] != RB_GEOM_PLANE || d->geom_type[g2] == RB_GEOM_PLANE)
-                return fail(RB_EINVAL, "unsupported collision pair (only plane vs sphere, capsule, box)");
+            bool plane_pair = d->geom_type[g1] == RB_GEOM_PLANE && d->geom_type[g2] != RB_GEOM_PLANE;
+            bool box_pair = d->geom_type[g1] == RB_GEOM_BOX && d->geom_type[g2] == RB_GEOM_BOX;
+            if (!plane_pair && !box_pair)
+                return fail(RB_EINVAL, "unsupported collision pair (only plane vs sphere, capsule, box and box vs box)");
             pairs.push_back({g1, g2});
         }
     std::sort(pairs.begin(), pairs.end(), [](const Pair& x, const Pair& y) {
@@ -334,14 +336,16 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     });
     int npair = (int)pairs.size();
     if (npair > RB_MAX_PAIR) return fail(RB_EINVAL, "more than 64 collision pairs");
-    std::vector<int> pg1(npair), pg2(npair), ptype(npair), pbody(npair), pcap(npair);
+    std::vector<int> pg1(npair), pg2(npair), ptype(npair), pbody(npair), pcap(npair), pslot(npair, -1);
+    int nbb = 0;
     std::vector<double> psig(npair), pmu(npair), pmar(npair);
     int maxcon = 0;
     for (int k = 0; k < npair; k++) {
         int g1 = pairs[k].g1, g2 = pairs[k].g2;
         pg1[k] = g1;
         pg2[k] = g2;
-        ptype[k] = d->geom_type[g2];
+        ptype[k] = d->geom_type[g1] == RB_GEOM_BOX ? RB_PAIR_BOXBOX : d->geom_type[g2];
+        if (ptype[k] == RB_PAIR_BOXBOX) pslot[k] = nbb++;
         bool mov2 = movable[d->geom_body[g2]];
         pbody[k] = mov2 ? d->geom_body[g2] : d->geom_body[g1];
         psig[k] = mov2 ? 1.0 : -1.0;
@@ -483,6 +487,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     F(akp, &m.act_kp); F(akd, &m.act_kd); F(agear, &m.act_gear);
     I(jtype, &m.jnt_type); I(jq, &m.jnt_qadr); I(jd, &m.jnt_dadr);
     I(pg1, &m.pair_g1); I(pg2, &m.pair_g2); I(ptype, &m.pair_type); I(pbody, &m.pair_body); I(pcap, &m.pair_cap);
+    I(pslot, &m.pair_slot);
     F(psig, &m.pair_sigma); F(pmu, &m.pair_mu); F(pmar, &m.pair_margin);
     I(std::vector<int>(d->geom_body, d->geom_body + ng), &m.geom_body);
     F(std::vector<double>(d->geom_pos, d->geom_pos + 3 * ng), &m.geom_pos);
@@ -502,7 +507,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.body_chainmask = (const uint64_t*)(base + 4 * off_mask);
     m.dof_descmask = (const uint64_t*)(base + 4 * off_dmask);
     // sizes and options
-    m.nbody = nb; m.nv = nv; m.nq = nq; m.nu = nu; m.njnt = nj; m.npair = npair;
+    m.nbody = nb; m.nv = nv; m.nq = nq; m.nu = nu; m.njnt = nj; m.npair = npair; m.nbb = nbb;
     m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.nhlevel = nhlevel; m.maxpiv = maxpiv; m.K = d->nsubsteps; m.maxiter = d->iterations;
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.dt = (float)d->timestep;
@@ -522,6 +527,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.o_tau = sec(nv); m.o_bias = sec(nv); m.o_a0 = sec(nv); m.o_a = sec(nv); m.o_Ma = sec(nv);
     m.o_g = sec(nv); m.o_p = sec(nv); m.o_Mp = sec(nv); m.o_tmp = sec(nv);
     m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16); m.o_piv = sec(maxpiv * (tmaxd + 4)); m.o_rowadr = sec(nv);
+    m.o_bb = sec(RB_BB_FLOATS * nbb);
     m.lds_floats = o;
     m.ncap = std::min(maxcon, RB_MAX_CON);
     M->blob = dev;
@@ -614,20 +620,27 @@ void rb_batch_destroy(rb_batch* b) {
 
 int32_t rb_batch_contact_capacity(const rb_batch* b) { return b ? b->dm.ncap : 0; }
 
-int rb_batch_set_params(rb_batch* b, int32_t field, int32_t n, const float* vals, void* stream) {
-    if (!b || !vals || n < 0 || n > b->capacity) return fail(RB_EINVAL, "bad arguments to rb_batch_set_params");
-    hipError_t e;
+int rb_batch_set_params_at(rb_batch* b, int32_t field, int32_t first, int32_t n, const float* vals, void* stream) {
+    if (!b || n < 0 || first < 0 || first > b->capacity || n > b->capacity - first || (n > 0 && !vals))
+        return fail(RB_EINVAL, "bad arguments to rb_batch_set_params");
+    hipError_t e = hipSuccess;
     if (field == RB_PARAM_FRICTION) {
         if (!b->dm.fr_pw) return fail(RB_EINVAL, "model does not have per-world friction");
-        e = hipMemcpyAsync(b->W.friction, vals, (size_t)n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+        if (n) e = hipMemcpyAsync(b->W.friction + first, vals, (size_t)n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream);
     } else if (field == RB_PARAM_MASS_SCALE) {
         if (!b->dm.ms_pw) return fail(RB_EINVAL, "model does not have per-world mass scale");
-        e = hipMemcpyAsync(b->W.mass_scale, vals, (size_t)n * b->dm.nbody * 4, hipMemcpyDeviceToDevice,
-                           (hipStream_t)stream);
+        const size_t nb = (size_t)b->dm.nbody;
+        if (n) e = hipMemcpyAsync(b->W.mass_scale + (size_t)first * nb, vals, (size_t)n * nb * 4, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream);
     } else {
         return fail(RB_EINVAL, "unknown parameter field");
     }
     return e == hipSuccess ? RB_OK : hip_fail(e, "rb_batch_set_params");
+}
+
+int rb_batch_set_params(rb_batch* b, int32_t field, int32_t n, const float* vals, void* stream) {
+    if (!vals && n > 0) return fail(RB_EINVAL, "bad arguments to rb_batch_set_params");
+    return rb_batch_set_params_at(b, field, 0, n, vals, stream);
 }
 
 int rb_world_reset(rb_batch* b, const int32_t* ids, int32_t n, const float* qacc_ws, void* stream) {
@@ -689,6 +702,14 @@ struct rb_multi {
     void* d_args = nullptr;
     int* d_items = nullptr;
     int nitems = 0, grid = 0, maxd = 0, lds_floats = 0;
+    bool boxbox = false;
+    int items_cap = 0;                         // capacity of d_items
+    // pinned staging ring for rb_multi_set_items (a slot is reused once its copy is done)
+    static constexpr int RING = 4;
+    int32_t* stage[RING] = {};
+    hipEvent_t stage_ev[RING] = {};
+    bool stage_used[RING] = {};
+    int stage_cap = 0, stage_next = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -713,6 +734,7 @@ int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out) {
         p->batches.push_back(batches[i]);
         models[i] = batches[i]->dm;
         p->maxd = std::max(p->maxd, models[i].maxd);
+        p->boxbox = p->boxbox || models[i].nbb > 0;
         p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);
     }
     p->bound_n.assign(nbatch, -1);
@@ -737,6 +759,10 @@ void rb_multi_destroy(rb_multi* p) {
     if (p->d_models) (void)hipFree(p->d_models);
     if (p->d_args) (void)hipFree(p->d_args);
     if (p->d_items) (void)hipFree(p->d_items);
+    for (int r = 0; r < rb_multi::RING; r++) {
+        if (p->stage[r]) (void)hipHostFree(p->stage[r]);
+        if (p->stage_ev[r]) (void)hipEventDestroy(p->stage_ev[r]);
+    }
     delete p;
 }
 
@@ -805,16 +831,74 @@ int rb_multi_set_schedule(rb_multi* p, int32_t order, int32_t grid, const float*
         if (e == hipSuccess) e = hipMemcpy(p->d_items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "rb_multi_set_schedule");
     }
+    p->items_cap = p->nitems;
     p->grid = grid > 0 ? std::min(grid, std::max(p->nitems, 1)) : p->nitems;
+    multi_free_graph(p);
+    return RB_OK;
+}
+
+int rb_multi_set_items(rb_multi* p, const int32_t* items, int32_t n, int32_t grid, void* stream) {
+    if (!p || n < 0 || (n > 0 && !items)) return fail(RB_EINVAL, "bad arguments to rb_multi_set_items");
+    const int nb = (int)p->batches.size();
+    for (int k = 0; k < n; k++) {
+        const int b = (int)((uint32_t)items[k] >> 24), w = items[k] & 0xffffff;
+        if (b >= nb || p->bound_n[b] < 0 || w >= p->bound_n[b])
+            return fail(RB_EINVAL, "work item outside the bound batches");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (n > p->items_cap) {
+        // launches queued on the stream may still read the old list
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "rb_multi_set_items");
+        if (p->d_items) (void)hipFree(p->d_items);
+        p->d_items = nullptr;
+        p->items_cap = 0;
+        const int cap = std::max(n, 1024);
+        e = hipMalloc((void**)&p->d_items, sizeof(int32_t) * cap);
+        if (e != hipSuccess) return hip_fail(e, "rb_multi_set_items");
+        p->items_cap = cap;
+    }
+    if (n > p->stage_cap) {
+        for (int r = 0; r < rb_multi::RING; r++) {
+            if (p->stage_used[r]) (void)hipEventSynchronize(p->stage_ev[r]);
+            if (p->stage[r]) (void)hipHostFree(p->stage[r]);
+            p->stage[r] = nullptr;
+            p->stage_used[r] = false;
+        }
+        p->stage_cap = 0;
+        const int cap = std::max(n, 1024);
+        for (int r = 0; r < rb_multi::RING && e == hipSuccess; r++) {
+            e = hipHostMalloc((void**)&p->stage[r], sizeof(int32_t) * cap, hipHostMallocDefault);
+            if (e == hipSuccess && !p->stage_ev[r]) e = hipEventCreateWithFlags(&p->stage_ev[r], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) return hip_fail(e, "rb_multi_set_items");
+        p->stage_cap = cap;
+    }
+    if (n > 0) {
+        const int r = p->stage_next;
+        p->stage_next = (r + 1) % rb_multi::RING;
+        if (p->stage_used[r]) {
+            e = hipEventSynchronize(p->stage_ev[r]);
+            if (e != hipSuccess) return hip_fail(e, "rb_multi_set_items");
+        }
+        std::memcpy(p->stage[r], items, sizeof(int32_t) * n);
+        e = hipMemcpyAsync(p->d_items, p->stage[r], sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(p->stage_ev[r], s);
+        if (e != hipSuccess) return hip_fail(e, "rb_multi_set_items");
+        p->stage_used[r] = true;
+    }
+    p->nitems = n;
+    p->grid = grid > 0 ? std::min(grid, std::max(n, 1)) : n;
     multi_free_graph(p);
     return RB_OK;
 }
 
 int rb_multi_step(rb_multi* p, void* stream) {
     if (!p) return fail(RB_EINVAL, "null plan");
-    if (!p->d_items && p->nitems == 0) return RB_OK;
+    if (p->nitems == 0) return RB_OK;
     if (!p->d_items) return fail(RB_ESTATE, "no schedule");
-    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->lds_floats, p->grid,
+    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats, p->grid,
                                    (hipStream_t)stream);
     return e == hipSuccess ? RB_OK : hip_fail(e, "rb_multi_step");
 }
@@ -828,7 +912,7 @@ int rb_multi_graph_capture(rb_multi* p, int32_t nsteps, void* stream) {
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     for (int k = 0; k < nsteps && e == hipSuccess; k++)
-        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->lds_floats, p->grid, s);
+        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats, p->grid, s);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

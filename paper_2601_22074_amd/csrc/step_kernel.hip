@@ -509,6 +509,207 @@ DEV int pair_contacts(const DevModel& m, const float* L, int p, int want, float*
     return cnt;
 }
 
+DEV float pick3(const float* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
+DEV void pick_axis(const float (&a)[3][3], int i, float* o) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) o[k] = i == 0 ? a[0][k] : (i == 1 ? a[1][k] : a[2][k]);
+}
+
+// Box-box contacts of pair p by the separating-axis test (Ericson, Real-Time Collision
+// Detection, 2004, sections 4.4 and 5.2), written into the pair's LDS block S:
+//   S[0, 24), S[24, 48)   clip buffers (8 points each)
+//   S[48 + 5 j ...]       contact j: dist, pos[3], feature
+//   S[88, 91)             normal, from g1 towards g2
+// The 15 candidate axes are the 6 face normals and the 9 normalised edge cross products
+// (skipped when nearly parallel).  The axis of least overlap wins; a later axis displaces an
+// earlier one only when smaller by more than 1e-5 (1 + overlap).  A face axis clips the
+// incident face (the other box's face most anti-parallel to the reference face) against the
+// reference face's four side planes; every clipped point below the reference face is a
+// contact, placed halfway between the point and the face, numbered by its position in the
+// clipped polygon.  An edge axis gives one contact halfway between the closest points of
+// the two supporting edges, at depth minus the overlap.  Returns the number of contacts.
+DEV int box_box(const DevModel& m, const float* L, int p, float* S) {
+    float cA[3], RA[9], cB[3], RB[9];
+    const int g1 = m.pair_g1[p], g2 = m.pair_g2[p];
+    geom_pose(m, L, g1, cA, RA);
+    geom_pose(m, L, g2, cB, RB);
+    const float hA[3] = {m.geom_size[3 * g1], m.geom_size[3 * g1 + 1], m.geom_size[3 * g1 + 2]};
+    const float hB[3] = {m.geom_size[3 * g2], m.geom_size[3 * g2 + 1], m.geom_size[3 * g2 + 2]};
+    const float margin = m.pair_margin[p];
+    float aA[3][3], aB[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            aA[i][k] = RA[3 * k + i];
+            aB[i][k] = RB[3 * k + i];
+        }
+    const float dc[3] = {cB[0] - cA[0], cB[1] - cA[1], cB[2] - cA[2]};
+    int best = -1;
+    float best_ov = 0.f, bx[3] = {0.f, 0.f, 0.f};
+    bool separated = false;
+#pragma unroll
+    for (int ax = 0; ax < 15; ax++) {
+        float Lx[3];
+        bool skip = false;
+        if (ax < 3) {
+            Lx[0] = aA[ax][0]; Lx[1] = aA[ax][1]; Lx[2] = aA[ax][2];
+        } else if (ax < 6) {
+            Lx[0] = aB[ax - 3][0]; Lx[1] = aB[ax - 3][1]; Lx[2] = aB[ax - 3][2];
+        } else {
+            cross(aA[(ax - 6) / 3], aB[(ax - 6) % 3], Lx);
+            float nl = sqrtf(dot(Lx, Lx));
+            skip = nl < 1e-6f;
+            float inv = skip ? 0.f : 1.0f / nl;
+            Lx[0] *= inv; Lx[1] *= inv; Lx[2] *= inv;
+        }
+        float rA = hA[0] * fabsf(dot(Lx, aA[0])) + hA[1] * fabsf(dot(Lx, aA[1])) + hA[2] * fabsf(dot(Lx, aA[2]));
+        float rB = hB[0] * fabsf(dot(Lx, aB[0])) + hB[1] * fabsf(dot(Lx, aB[1])) + hB[2] * fabsf(dot(Lx, aB[2]));
+        float ov = rA + rB - fabsf(dot(Lx, dc));
+        if (!skip) {
+            separated = separated || (-ov >= margin);
+            if (best < 0 || ov < best_ov - 1e-5f * (1.f + fabsf(best_ov))) {
+                best = ax;
+                best_ov = ov;
+                bx[0] = Lx[0]; bx[1] = Lx[1]; bx[2] = Lx[2];
+            }
+        }
+    }
+    if (separated || best < 0) return 0;
+    const float sgn = dot(bx, dc) < 0.f ? -1.f : 1.f;
+    const float n[3] = {sgn * bx[0], sgn * bx[1], sgn * bx[2]};
+    S[88] = n[0]; S[89] = n[1]; S[90] = n[2];
+    if (best >= 6) {
+        const int i = (best - 6) / 3, j = (best - 6) % 3;
+        float PA[3] = {cA[0], cA[1], cA[2]}, PB[3] = {cB[0], cB[1], cB[2]};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            float sa = a == i ? 0.f : (dot(n, aA[a]) >= 0.f ? hA[a] : -hA[a]);
+            float sb = a == j ? 0.f : (dot(n, aB[a]) >= 0.f ? -hB[a] : hB[a]);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                PA[k] += sa * aA[a][k];
+                PB[k] += sb * aB[a][k];
+            }
+        }
+        float ei[3], ej[3];
+        pick_axis(aA, i, ei);
+        pick_axis(aB, j, ej);
+        const float hi = pick3(hA, i), hj = pick3(hB, j);
+        const float r[3] = {PA[0] - PB[0], PA[1] - PB[1], PA[2] - PB[2]};
+        const float b = dot(ei, ej), c = dot(ei, r), f = dot(ej, r);
+        const float den = 1.f - b * b;
+        float t = den > 1e-12f ? (b * f - c) / den : 0.f;
+        t = fminf(fmaxf(t, -hi), hi);
+        float w = b * t + f;
+        if (w < -hj || w > hj) {
+            w = fminf(fmaxf(w, -hj), hj);
+            t = fminf(fmaxf(b * w - c, -hi), hi);
+        }
+        S[48] = -best_ov;
+#pragma unroll
+        for (int k = 0; k < 3; k++) S[49 + k] = 0.5f * (PA[k] + t * ei[k] + PB[k] + w * ej[k]);
+        S[52] = 0.f;
+        return 1;
+    }
+    // face axis: reference box R, incident box I
+    const bool refA = best < 3;
+    const int rax = refA ? best : best - 3;
+    float aR[3][3], aI[3][3], hR[3], hI[3], cR[3], cI[3], nr[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        hR[a] = refA ? hA[a] : hB[a];
+        hI[a] = refA ? hB[a] : hA[a];
+        cR[a] = refA ? cA[a] : cB[a];
+        cI[a] = refA ? cB[a] : cA[a];
+        nr[a] = refA ? n[a] : -n[a];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            aR[a][k] = refA ? aA[a][k] : aB[a][k];
+            aI[a][k] = refA ? aB[a][k] : aA[a][k];
+        }
+    }
+    const float hr = pick3(hR, rax);
+    const float pR[3] = {cR[0] + hr * nr[0], cR[1] + hr * nr[1], cR[2] + hr * nr[2]};
+    // side axes of the reference face, in increasing axis order
+    const int u = rax == 0 ? 1 : 0, v = rax == 2 ? 1 : 2;
+    float du[3], dv[3];
+    pick_axis(aR, u, du);
+    pick_axis(aR, v, dv);
+    const float hu = pick3(hR, u), hv = pick3(hR, v);
+    int ia = 0;
+    float bestdot = -1.f;
+#pragma unroll
+    for (int jj = 0; jj < 3; jj++) {
+        float a = fabsf(dot(aI[jj], nr));
+        if (a > bestdot + 1e-12f) { bestdot = a; ia = jj; }
+    }
+    float ea[3];
+    pick_axis(aI, ia, ea);
+    const float s = dot(ea, nr) > 0.f ? -1.f : 1.f;
+    const int pa = ia == 0 ? 1 : 0, qa = ia == 2 ? 1 : 2;
+    float ep[3], eq[3];
+    pick_axis(aI, pa, ep);
+    pick_axis(aI, qa, eq);
+    const float hia = pick3(hI, ia), hp = pick3(hI, pa), hq = pick3(hI, qa);
+    float* buf = S;
+    float* out = S + 24;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const float sp = (c == 0 || c == 3) ? 1.f : -1.f, sq = c < 2 ? 1.f : -1.f;
+#pragma unroll
+        for (int k = 0; k < 3; k++) buf[3 * c + k] = cI[k] + s * hia * ea[k] + sp * hp * ep[k] + sq * hq * eq[k];
+    }
+    int np = 4;
+    // Sutherland-Hodgman against x.u <= hu, -x.u <= hu, x.v <= hv, -x.v <= hv (x = point - pR)
+#pragma unroll
+    for (int plane = 0; plane < 4; plane++) {
+        const float* dir = plane < 2 ? du : dv;
+        const float ext = plane < 2 ? hu : hv;
+        const float sg = (plane & 1) ? -1.f : 1.f;
+        int no = 0;
+        for (int a = 0; a < np; a++) {
+            const int b2 = a + 1 == np ? 0 : a + 1;
+            const float P[3] = {buf[3 * a], buf[3 * a + 1], buf[3 * a + 2]};
+            const float Q[3] = {buf[3 * b2], buf[3 * b2 + 1], buf[3 * b2 + 2]};
+            const float x[3] = {P[0] - pR[0], P[1] - pR[1], P[2] - pR[2]};
+            const float y[3] = {Q[0] - pR[0], Q[1] - pR[1], Q[2] - pR[2]};
+            const float fp = sg * dot(x, dir) - ext, fq = sg * dot(y, dir) - ext;
+            // a convex quad clipped by four half-planes keeps at most 8 points; the bound
+            // also holds the buffers when rounding bends the polygon
+            if (fp <= 0.f && no < 8) {
+                out[3 * no] = P[0]; out[3 * no + 1] = P[1]; out[3 * no + 2] = P[2];
+                no++;
+            }
+            if (((fp < 0.f && fq > 0.f) || (fp > 0.f && fq < 0.f)) && no < 8) {
+                const float t = fp / (fp - fq);
+                out[3 * no] = P[0] + t * (Q[0] - P[0]);
+                out[3 * no + 1] = P[1] + t * (Q[1] - P[1]);
+                out[3 * no + 2] = P[2] + t * (Q[2] - P[2]);
+                no++;
+            }
+        }
+        float* tmpb = buf; buf = out; out = tmpb;
+        np = no;
+        if (np == 0) return 0;
+    }
+    int cnt = 0;
+    for (int a = 0; a < np; a++) {
+        const float x[3] = {buf[3 * a] - pR[0], buf[3 * a + 1] - pR[1], buf[3 * a + 2] - pR[2]};
+        const float dd = dot(x, nr);
+        if (dd < margin) {
+            float* o = S + 48 + 5 * cnt;
+            o[0] = dd;
+            o[1] = buf[3 * a] - 0.5f * dd * nr[0];
+            o[2] = buf[3 * a + 1] - 0.5f * dd * nr[1];
+            o[3] = buf[3 * a + 2] - 0.5f * dd * nr[2];
+            o[4] = (float)a;
+            cnt++;
+        }
+    }
+    return cnt;
+}
+
 DEV float impedance(const DevModel& m, float r) {
     float x = fminf(fabsf(r) / m.width, 1.0f);
     float y;
@@ -538,7 +739,7 @@ struct StepArgs {
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
-template <int MAXD, bool TIMED>
+template <int MAXD, bool TIMED, bool BB>
 DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* lds) {
     const int lane = threadIdx.x;
     float* L = lds;
@@ -829,7 +1030,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         int cnt = 0;
         float dist_, pos_[3], nrm_[3];
         int feat_;
-        if (lane < m.npair) cnt = pair_contacts(m, L, lane, -1, &dist_, pos_, &feat_, nrm_);
+        if (lane < m.npair) {
+            if (BB && m.pair_type[lane] == RB_PAIR_BOXBOX)
+                cnt = box_box(m, L, lane, L + m.o_bb + RB_BB_FLOATS * m.pair_slot[lane]);
+            else
+                cnt = pair_contacts(m, L, lane, -1, &dist_, pos_, &feat_, nrm_);
+        }
+        if (BB) wave_sync();   // box-box blocks written by their pair lanes are read by contact lanes
         int incl = wscan_incl(cnt, lane);
         int total = __shfl(incl, RB_WAVE - 1);
         ncon = total < m.ncap ? total : m.ncap;
@@ -852,7 +1059,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         float margin_c = 0.f;
         if (has) {
             int j = lane - before, feat;
-            pair_contacts(m, L, src, j, &C.dist, pos_, &feat, C.n);
+            if (BB && m.pair_type[src] == RB_PAIR_BOXBOX) {
+                const float* S = L + m.o_bb + RB_BB_FLOATS * m.pair_slot[src];
+                C.dist = S[48 + 5 * j];
+                pos_[0] = S[49 + 5 * j]; pos_[1] = S[50 + 5 * j]; pos_[2] = S[51 + 5 * j];
+                feat = (int)S[52 + 5 * j];
+                C.n[0] = S[88]; C.n[1] = S[89]; C.n[2] = S[90];
+            } else {
+                pair_contacts(m, L, src, j, &C.dist, pos_, &feat, C.n);
+            }
             C.r[0] = pos_[0] - O[0]; C.r[1] = pos_[1] - O[1]; C.r[2] = pos_[2] - O[2];
             contact_frame(C.n, C.t1);
             C.ids = m.pair_g1[src] | (m.pair_g2[src] << 8) | (feat << 16);
@@ -1007,7 +1222,20 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             RB_STAGE(5);
 
             int it = 0;
+            uint32_t prev_bits = 0;
             for (; it < m.maxiter; it++) {
+                // Converged when no row changed sides since the Hessian was last built: the
+                // step then stayed inside one quadratic piece of the cost, and the exact line
+                // search along the Newton direction of that piece lands on its minimiser, where
+                // the gradient vanishes (in exact arithmetic; the FP32 gradient does not reach
+                // the tolerance, so this is the test that ends the iteration).
+                uint32_t bits = 0;
+                if (has) {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) bits |= (C.jar[e] < 0.f ? 1u : 0u) << e;
+                }
+                if (it > 0 && __ballot(bits != prev_bits) == 0) break;
+                prev_bits = bits;
                 // gradient and the contact part of the Hessian, one contact at a time
                 float gc = 0.f;
                 float F[6] = {0, 0, 0, 0, 0, 0};
@@ -1273,14 +1501,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     }
 }
 
-// One world per 64-lane workgroup.
-template <int MAXD, bool TIMED>
+// One world per 64-lane workgroup.  BB: the model has box-box pairs (kept out of the other
+// instantiations so their register allocation is not shaped by that code).
+template <int MAXD, bool TIMED, bool BB>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void step_kernel(
     DevModel m, StepArgs A) {
     extern __shared__ float lds[];
     const int w = blockIdx.x;
     if (w >= A.n) return;
-    world_step<MAXD, TIMED>(m, A, w, lds);
+    world_step<MAXD, TIMED, BB>(m, A, w, lds);
 }
 
 // Mixed-model launch: the grid walks an ordered list of (batch, world) items; each batch has
@@ -1293,16 +1522,16 @@ struct MultiArgs {
     int nitems;
 };
 
-template <int MAXD>
+template <int MAXD, bool BB>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
     MultiArgs M) {
     extern __shared__ float lds[];
     for (int it = blockIdx.x; it < M.nitems; it += gridDim.x) {
         const int item = __builtin_amdgcn_readfirstlane(M.items[it]);
         const int b = item >> 24, w = item & 0xffffff;
-        const DevModel m = M.models[b];
-        const StepArgs A = M.args[b];
-        if (w < A.n) world_step<MAXD, false>(m, A, w, lds);
+        const DevModel& m = M.models[b];
+        const StepArgs& A = M.args[b];
+        if (w < A.n) world_step<MAXD, false, BB>(m, A, w, lds);
     }
 }
 
@@ -1333,22 +1562,40 @@ void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* 
     *(rbk::StepArgs*)dst = A;
 }
 
+template <int MAXD, bool BB>
+static void launch_multi_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_t stream) {
+    hipLaunchKernelGGL((rbk::multi_kernel<MAXD, BB>), g, dim3(RB_WAVE), shmem, stream, M);
+}
+template <bool BB>
+static void launch_multi_b(int maxd, const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_t stream) {
+    if (maxd <= 8) launch_multi_t<8, BB>(M, g, shmem, stream);
+    else if (maxd <= 16) launch_multi_t<16, BB>(M, g, shmem, stream);
+    else launch_multi_t<32, BB>(M, g, shmem, stream);
+}
+
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
-                           int lds_floats, int grid, hipStream_t stream) {
+                           bool boxbox, int lds_floats, int grid, hipStream_t stream) {
     rbk::MultiArgs M;
     M.models = models;
     M.args = (const rbk::StepArgs*)args;
     M.items = items;
     M.nitems = nitems;
     size_t shmem = (size_t)lds_floats * sizeof(float);
-    dim3 g(grid), block(RB_WAVE);
-    if (maxd <= 8)
-        hipLaunchKernelGGL((rbk::multi_kernel<8>), g, block, shmem, stream, M);
-    else if (maxd <= 16)
-        hipLaunchKernelGGL((rbk::multi_kernel<16>), g, block, shmem, stream, M);
-    else
-        hipLaunchKernelGGL((rbk::multi_kernel<32>), g, block, shmem, stream, M);
+    dim3 g(grid);
+    if (boxbox) launch_multi_b<true>(maxd, M, g, shmem, stream);
+    else launch_multi_b<false>(maxd, M, g, shmem, stream);
     return hipGetLastError();
+}
+
+template <int MAXD, bool TIMED, bool BB>
+static void launch_step_t(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
+    hipLaunchKernelGGL((rbk::step_kernel<MAXD, TIMED, BB>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+}
+template <bool TIMED, bool BB>
+static void launch_step_d(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
+    if (m.maxd <= 8) launch_step_t<8, TIMED, BB>(m, A, n, shmem, stream);
+    else if (m.maxd <= 16) launch_step_t<16, TIMED, BB>(m, A, n, shmem, stream);
+    else launch_step_t<32, TIMED, BB>(m, A, n, shmem, stream);
 }
 
 hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
@@ -1365,17 +1612,14 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     A.want_taps = taps != nullptr;
     if (taps) A.taps = *taps; else A.taps = DevTaps{};
     size_t shmem = (size_t)m.lds_floats * sizeof(float);
-    dim3 grid(n), block(RB_WAVE);
     const bool timed = taps != nullptr && taps->stats != nullptr;
-    if (m.maxd <= 8) {
-        if (timed) hipLaunchKernelGGL((rbk::step_kernel<8, true>), grid, block, shmem, stream, m, A);
-        else hipLaunchKernelGGL((rbk::step_kernel<8, false>), grid, block, shmem, stream, m, A);
-    } else if (m.maxd <= 16) {
-        if (timed) hipLaunchKernelGGL((rbk::step_kernel<16, true>), grid, block, shmem, stream, m, A);
-        else hipLaunchKernelGGL((rbk::step_kernel<16, false>), grid, block, shmem, stream, m, A);
+    const bool bb = m.nbb > 0;
+    if (timed) {
+        if (bb) launch_step_d<true, true>(m, A, n, shmem, stream);
+        else launch_step_d<true, false>(m, A, n, shmem, stream);
     } else {
-        if (timed) hipLaunchKernelGGL((rbk::step_kernel<32, true>), grid, block, shmem, stream, m, A);
-        else hipLaunchKernelGGL((rbk::step_kernel<32, false>), grid, block, shmem, stream, m, A);
+        if (bb) launch_step_d<false, true>(m, A, n, shmem, stream);
+        else launch_step_d<false, false>(m, A, n, shmem, stream);
     }
     return hipGetLastError();
 }

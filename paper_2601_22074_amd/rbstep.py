@@ -30,9 +30,10 @@ _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
 
 EXPORTED = ["rb_last_error", "rb_model_create", "rb_model_destroy", "rb_model_info_get", "rb_batch_create",
-            "rb_batch_destroy", "rb_batch_contact_capacity", "rb_batch_set_params", "rb_world_reset",
+            "rb_batch_destroy", "rb_batch_contact_capacity", "rb_batch_set_params", "rb_batch_set_params_at",
+            "rb_world_reset",
             "rb_get_state", "rb_step", "rb_step_taps", "rb_multi_create", "rb_multi_destroy", "rb_multi_bind",
-            "rb_multi_set_schedule", "rb_multi_step", "rb_multi_graph_capture", "rb_multi_graph_launch"]
+            "rb_multi_set_schedule", "rb_multi_set_items", "rb_multi_step", "rb_multi_graph_capture", "rb_multi_graph_launch"]
 ORDER_BATCH, ORDER_HEAVY_FIRST, ORDER_INTERLEAVE = 0, 1, 2
 
 
@@ -90,6 +91,7 @@ def lib():
         L.rb_batch_contact_capacity.argtypes = [vp]
         L.rb_batch_contact_capacity.restype = C.c_int32
         L.rb_batch_set_params.argtypes = [vp, C.c_int32, C.c_int32, vp, vp]
+        L.rb_batch_set_params_at.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]
         L.rb_world_reset.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.rb_get_state.argtypes = [vp, C.c_int32, vp, vp, vp]
         L.rb_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp]
@@ -98,6 +100,7 @@ def lib():
         L.rb_multi_destroy.argtypes = [vp]
         L.rb_multi_bind.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp]
         L.rb_multi_set_schedule.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_float)]
+        L.rb_multi_set_items.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32, C.c_int32, vp]
         L.rb_multi_step.argtypes = [vp, vp]
         L.rb_multi_graph_capture.argtypes = [vp, C.c_int32, vp]
         L.rb_multi_graph_launch.argtypes = [vp, vp]
@@ -259,6 +262,14 @@ class Batch:
         _check(lib().rb_batch_set_params(self._h, int(field), int(n), _ptr(vals, torch.float32, shape, "vals"),
                                          _stream(stream)))
 
+    def set_params_at(self, field: int, first: int, vals, stream=None) -> None:
+        """Per-world parameters of slots [first, first + n), n = vals.shape[0]."""
+        import torch
+        n = vals.shape[0]
+        shape = (n,) if field == PARAM_FRICTION else (n, self.model.nbody)
+        _check(lib().rb_batch_set_params_at(self._h, int(field), int(first), int(n),
+                                            _ptr(vals, torch.float32, shape, "vals"), _stream(stream)))
+
     def reset(self, ids, qacc_ws=None, stream=None) -> None:
         import torch
         n = ids.shape[0]
@@ -332,6 +343,12 @@ class Multi:
         if cost is not None:
             c = (C.c_float * len(self.batches))(*[float(x) for x in cost])
         _check(lib().rb_multi_set_schedule(self._h, int(order), int(grid), c))
+
+    def set_items(self, items, grid: int = 0, stream=None) -> None:
+        """Explicit work list (host int32 array of batch << 24 | world), uploaded on the stream."""
+        a = np.ascontiguousarray(np.asarray(items, dtype=np.int32).reshape(-1))
+        _check(lib().rb_multi_set_items(self._h, a.ctypes.data_as(C.POINTER(C.c_int32)), int(a.size), int(grid),
+                                        _stream(stream)))
 
     def step(self, stream=None) -> None:
         _check(lib().rb_multi_step(self._h, _stream(stream)))

@@ -6,7 +6,7 @@ from workloads import inputs
 
 pytestmark = pytest.mark.gpu
 
-MIX = [("chain3", 48), ("quadruped", 96), ("humanoid", 64)]
+MIX = [("chain3", 48), ("quadruped", 96), ("humanoid", 64), ("arm_box", 40)]
 
 
 def _setup(rb, torch, mix=MIX, first=0):

@@ -4,6 +4,7 @@ import pytest
 
 from gpu_common import (MARGIN_BAND, RTOL_ROLLOUT, RTOL_STEP, by_name, contact_keys, gpu_run, lifted, oracle_run,
                         rel_err, substeps1, vec_err)
+from helpers import rot
 from workloads import inputs, robots
 
 pytestmark = pytest.mark.gpu
@@ -19,7 +20,7 @@ def _wl(name, n, first=0):
 
 
 # ------------------------------------------------------------------ stage taps
-@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid"])
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box"])
 def test_stage_taps_smooth_dynamics(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 16)
     rng = np.random.default_rng(1)
@@ -40,7 +41,7 @@ def test_stage_taps_smooth_dynamics(oracle_mod, name):
         assert vec_err(g["qacc"][w], t["qacc"]) <= RTOL_STEP, f"qacc world {w}"
 
 
-@pytest.mark.parametrize("name", ["quadruped", "humanoid"])
+@pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box"])
 def test_stage_taps_contact_rows(oracle_mod, name):
     """One substep from states in contact: rows (aref, D, A-hat) and the solved acceleration."""
     m = substeps1(by_name(name))
@@ -75,7 +76,7 @@ def test_stage_taps_contact_rows(oracle_mod, name):
 
 
 # ------------------------------------------------------------------ single env step
-@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid"])
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box"])
 def test_single_step_from_initial_states(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 64)
     g = gpu_run(m, q, v, u, friction=fr, mass_scale=ms)
@@ -85,7 +86,7 @@ def test_single_step_from_initial_states(oracle_mod, name):
     assert np.all(g["status"] & 1 == 0)
 
 
-@pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150)])
+@pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150), ("arm_box", 150)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory, hand its state (rounded to FP32) to the GPU at
     sampled steps and compare one env step."""
@@ -110,7 +111,7 @@ def test_single_step_teacher_forced(oracle_mod, name, horizon):
 
 
 # ------------------------------------------------------------------ contact-free rollouts
-@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid"])
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box"])
 def test_ten_step_contact_free(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     if name != "chain3":
@@ -122,7 +123,7 @@ def test_ten_step_contact_free(oracle_mod, name):
 
 
 # ------------------------------------------------------------------ contact sets
-@pytest.mark.parametrize("name", ["quadruped", "humanoid"])
+@pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -136,6 +137,75 @@ def test_contact_sets(oracle_mod, name):
         gc, gb = contact_keys(g["contacts"], w)
         rc, rb_ = contact_keys(r["contacts"], w)
         assert gc - rb_ == rc - gb, f"world {w}"
+
+
+def test_box_box_contacts_random_poses(oracle_mod):
+    """Cube at random orientations pressed 0.1-3 mm into the table: face, edge and vertex
+    contacts (keys, depths, points, normals) against the oracle on the same FP32 state."""
+    m = substeps1(by_name("arm_box"))
+    n = 64
+    rng = np.random.default_rng(11)
+    q = np.tile(robots.qpos0(m), (n, 1))
+    for w in range(n):
+        qc = rng.normal(size=4)
+        if w < 8:                       # a few face-down cubes turned about z only
+            qc = np.array([np.cos(w / 5), 0, 0, np.sin(w / 5)])
+        qc /= np.linalg.norm(qc)
+        R = rot(qc)
+        zext = np.abs(R[2]) @ np.full(3, 0.025)
+        c = [0.5 + rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2), 0.4 + zext - rng.uniform(1e-4, 3e-3)]
+        q[w, -7:-4] = c
+        q[w, -4:] = qc
+    q = q.astype(np.float32)
+    v = np.zeros((n, 13), np.float32)
+    g = gpu_run(m, q, v, contacts=True)
+    c = g["contacts"]
+    o = oracle_mod.Oracle(m)
+    kinds = set()
+    for w in range(n):
+        t = o.forward(q[w], v[w])
+        if any(abs(d) <= MARGIN_BAND for d in t["dist"]):
+            continue
+        nc = t["ncon"]
+        assert c["ncon"][w] == nc, f"world {w}"
+        assert [tuple(x) for x in c["geom"][w, :nc]] == [tuple(x) for x in t["geom"]]
+        assert list(c["feature"][w, :nc]) == list(t["feature"])
+        assert np.abs(c["dist"][w, :nc] - t["dist"]).max() <= 2e-6, f"world {w}"
+        assert np.abs(c["pos"][w, :nc] - t["pos"]).max() <= 2e-5, f"world {w}"
+        assert np.abs(c["frame"][w, :nc].reshape(nc, 9) - t["frame"].reshape(nc, 9)).max() <= 2e-5, f"world {w}"
+        kinds.add(nc)
+    assert 1 in kinds and 4 in kinds
+
+
+@pytest.mark.parametrize("name", ["quadruped", "humanoid"])
+def test_newton_iterations_match_oracle(oracle_mod, name):
+    """The GPU ends Newton when no row changed sides since the last Hessian; the oracle ends
+    it by its FP64 gradient test.  On the same states both take the same number of
+    iterations, except where a row sits on its breakpoint to rounding."""
+    import torch
+    import paper_2601_22074_amd as rb
+    m = substeps1(by_name(name))
+    _, q, v, u, fr, ms = _wl(name, 64)
+    o = oracle_mod.Oracle(m)
+    r = oracle_run(o, q, v, u, None, fr, ms, nsteps=40)
+    q1, v1, ws1 = r["qpos"].astype(np.float32), r["qvel"].astype(np.float32), r["qacc_ws"].astype(np.float32)
+    dev = torch.device("cuda:0")
+    M = rb.Model(m)
+    B = rb.Batch(M, 64)
+    B.reset(torch.arange(64, dtype=torch.int32, device=dev), torch.tensor(ws1, device=dev))
+    if fr is not None:
+        B.set_params(rb.PARAM_FRICTION, torch.tensor(fr, device=dev))
+    if ms is not None:
+        B.set_params(rb.PARAM_MASS_SCALE, torch.tensor(ms, device=dev))
+    stats = torch.zeros(64, rb.rbstep.NSTATS, dtype=torch.int32, device=dev)
+    B.step_taps(torch.tensor(u, device=dev), torch.tensor(q1, device=dev), torch.tensor(v1, device=dev), stats=stats)
+    gi = stats[:, 2].cpu().numpy()
+    B.close()
+    M.close()
+    oi = np.array([o.forward(q1[w], v1[w], u[w], ws1[w], None if fr is None else fr[w],
+                             None if ms is None else ms[w])["niter"] for w in range(64)])
+    assert np.mean(gi == oi) >= 0.85, (gi, oi)
+    assert abs(gi.mean() - oi.mean()) <= 0.25
 
 
 # ------------------------------------------------------------------ system properties
