@@ -225,7 +225,7 @@ def run_serve(args):
     srv = Server(src, budget=budget)
     reqs_b = poisson_requests(lam, args.sustain_seconds, seed=2)
     log(f"serve: sustainable-rate run at {lam:.2f}/s, {len(reqs_b)} requests")
-    b = srv.run_timed(reqs_b, progress=log)
+    b = srv.run_timed(reqs_b, stop_after=3 * args.sustain_seconds, progress=log)
     srv.close()
     out = {
         "metric": f"env-steps/sec served at Poisson {args.rate:g} requests/s; p50/p99 request latency",

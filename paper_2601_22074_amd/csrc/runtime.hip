@@ -121,6 +121,20 @@ struct rb_batch {
 
 namespace {
 
+// LDS sections from the pivot buffer on.  The pivot buffer holds one row per pivot of a height
+// level at the stride of the kernel instantiation that runs the model (its chain bound + 4),
+// so a model run by a deeper instantiation (a fused launch beside a deeper model) needs this
+// tail laid out again for that bound.
+void layout_tail(DevModel& m, int kernel_maxd) {
+    auto r4 = [](int n) { return (n + 3) & ~3; };
+    int o = m.o_piv + r4(m.maxpiv * (kernel_maxd + 4));
+    m.o_rowadr = o;
+    o += r4(m.nv);
+    m.o_bb = o;
+    o += r4(RB_BB_FLOATS * m.nbb);
+    m.lds_floats = o;
+}
+
 // Compile a description into host tables; returns RB_OK or RB_EINVAL with a message.
 int compile_model(const rb_model_desc* d, rb_model* M) {
     const int nb = d->nbody, nj = d->njnt, ng = d->ngeom, nu = d->nu;
@@ -526,9 +540,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.o_bvec = sec(6 * nb); m.o_bvec2 = sec(6 * nb);
     m.o_tau = sec(nv); m.o_bias = sec(nv); m.o_a0 = sec(nv); m.o_a = sec(nv); m.o_Ma = sec(nv);
     m.o_g = sec(nv); m.o_p = sec(nv); m.o_Mp = sec(nv); m.o_tmp = sec(nv);
-    m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16); m.o_piv = sec(maxpiv * (tmaxd + 4)); m.o_rowadr = sec(nv);
-    m.o_bb = sec(RB_BB_FLOATS * nbb);
-    m.lds_floats = o;
+    m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16); m.o_piv = o;
+    layout_tail(m, tmaxd);
     m.ncap = std::min(maxcon, RB_MAX_CON);
     M->blob = dev;
     M->maxcon_static = maxcon;
@@ -735,6 +748,10 @@ int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out) {
         models[i] = batches[i]->dm;
         p->maxd = std::max(p->maxd, models[i].maxd);
         p->boxbox = p->boxbox || models[i].nbb > 0;
+    }
+    // every batch runs in the instantiation for the deepest model
+    for (int i = 0; i < nbatch; i++) {
+        layout_tail(models[i], p->maxd);
         p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);
     }
     p->bound_n.assign(nbatch, -1);

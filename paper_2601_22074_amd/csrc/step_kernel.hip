@@ -369,9 +369,6 @@ DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MA
             left &= left - 1ull;
             const int dk = __builtin_amdgcn_readlane(di, k);
             const float* P = piv + pp * STRIDE;
-            float hk[MAXD];
-#pragma unroll
-            for (int t = 0; t < MAXD; t++) hk[t] = P[t];
             const float yk = P[MAXD];
             const float d = P[dk - 1];
             const bool anc = (D.descmask >> k) & 1ull;
@@ -379,9 +376,16 @@ DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MA
             const float inv = __builtin_amdgcn_rcpf(d);
             if (lane == k) inv_self = inv;
             const float l = hka * inv;
-            // l = 0 off the pivot's chain; positions past an ancestor's own depth are padding
+            // l = 0 off the pivot's chain; positions past an ancestor's own depth are padding.
+            // Only the pivot's chain positions can change anything: blocks of four past its
+            // depth (a wave-uniform bound) are skipped, the zeroed padding covers the rest.
 #pragma unroll
-            for (int b = 0; b < MAXD; b++) Hr[b] -= l * hk[b];
+            for (int blk = 0; blk < MAXD / 4; blk++) {
+                if (4 * blk < dk) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) Hr[4 * blk + j] -= l * P[4 * blk + j];
+                }
+            }
             bi -= l * yk;
         }
         wave_sync();
