@@ -392,9 +392,11 @@ def test_box_box_separated_and_touching(oracle_mod):
     assert oracle_mod.Oracle(m).forward(q, np.zeros(6))["ncon"] == 0
 
 
-def test_box_box_edge_edge(oracle_mod):
+@pytest.mark.parametrize("dx,dy", [(0.0, 0.0), (0.01, 0.1), (-0.015, -0.2)])
+def test_box_box_edge_edge(oracle_mod, dx, dy):
     """A table edge (along y) pressed by a cube edge crossing it at right angles: one contact
-    at the crossing, depth = the edge-edge overlap."""
+    at the crossing, depth = the edge-edge overlap.  Offsets move the crossing away from
+    both edges' midpoints."""
     qt = robots.quat_axis_angle((0, 1, 0), math.pi / 4)        # table turned: its top edge ridge along y
     mb = robots.ModelBuilder("edges", timestep=0.005, nsubsteps=1)
     mb.geom(0, "box", [0.3, 0.3, 0.3], pos=(0, 0, 0), quat=qt, contype=0, conaffinity=1)
@@ -406,11 +408,11 @@ def test_box_box_edge_edge(oracle_mod):
     ridge = 0.3 * math.sqrt(2)
     pen = 1e-3
     zc = ridge + 0.025 * math.sqrt(2) - pen
-    t = oracle_mod.Oracle(m).forward(np.concatenate([[0.0, 0.0, zc], qc]), np.zeros(6))
+    t = oracle_mod.Oracle(m).forward(np.concatenate([[dx, dy, zc], qc]), np.zeros(6))
     assert t["ncon"] == 1 and t["feature"][0] == 0
     np.testing.assert_allclose(t["dist"][0], -pen, atol=1e-12)
     np.testing.assert_allclose(t["frame"][0][0], [0, 0, 1], atol=1e-12)
-    np.testing.assert_allclose(t["pos"][0], [0, 0, ridge - pen / 2], atol=1e-12)
+    np.testing.assert_allclose(t["pos"][0], [0, dy, ridge - pen / 2], atol=1e-12)
 
 
 def _box_vertices(center, R, half):
