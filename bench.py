@@ -353,11 +353,20 @@ def cpu_baseline(W, budget_s=12.0):
 
 
 def kernel_source_hash():
+    """Hash of what decides the step kernel's code: its sources and the compile flags."""
+    from paper_2601_22074_amd import build as _b
     h = hashlib.sha256()
     for f in ("step_kernel.hip", "rb_internal.h"):
         with open(os.path.join(ROOT, "paper_2601_22074_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(_b.FLAGS).encode())
     return h.hexdigest()[:16]
+
+
+def _is_plain_step(kernel_name):
+    """The untimed plain step kernel (rbk::step_kernel<MAXD, false, BB>)."""
+    import re
+    return re.match(r"void rbk::step_kernel<\d+, false", kernel_name) is not None
 
 
 def load_traffic(name, nworlds):
@@ -386,7 +395,7 @@ def summarize_profiles(trace_db, fetch_db, write_db, name, nworlds, calib_mb, co
     for n, calls, tot, avg, pct in rows[:8]:
         short = n if len(n) < 70 else n[:67] + "..."
         lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.1f} | {pct:.2f} |")
-    step = [r for r in rows if r[0].startswith("void rbk::step_kernel") and "false" in r[0]]
+    step = [r for r in rows if _is_plain_step(r[0])]
     if step:
         lines += ["", f"Step kernel average duration: {step[0][3]:.1f} us per launch (one env step of {nworlds} worlds)."]
     with open(os.path.join(ROOT, "profiles", base + "_trace.md"), "w") as f:
@@ -395,7 +404,7 @@ def summarize_profiles(trace_db, fetch_db, write_db, name, nworlds, calib_mb, co
     def counter(db, cname):
         cc = sqlite3.connect(db)
         q = "select kernel_name, value from counters_collection where counter_name = ?"
-        step_v = [v for k, v in cc.execute(q, (cname,)) if k.startswith("void rbk::step_kernel") and "false" in k]
+        step_v = [v for k, v in cc.execute(q, (cname,)) if _is_plain_step(k)]
         copy_v = [v for k, v in cc.execute(q, (cname,)) if "neg_kernel" in k or ("elementwise" in k and "neg" in k)]
         return step_v, copy_v
 
@@ -407,7 +416,7 @@ def summarize_profiles(trace_db, fetch_db, write_db, name, nworlds, calib_mb, co
     fetch_kib = float(np.median(fs)) if fs else float("nan")
     write_kib = float(np.median(ws)) if ws else float("nan")
     bytes_per_launch = (fetch_kib * ffac + write_kib * wfac) * 1024.0
-    d = {"kernel": "step_kernel<16,false>", "workload": f"{name} x{nworlds}",
+    d = {"kernel": "step_kernel<16, false, false>", "workload": f"{name} x{nworlds}",
          "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
          "calibration": {"kernel": f"elementwise neg of {calib_mb} MiB (reads and writes {calib_mb} MiB)",
                          "fetch_kib": float(np.median(fc)) if fc else None,
@@ -430,6 +439,40 @@ def summarize_profiles(trace_db, fetch_db, write_db, name, nworlds, calib_mb, co
     print(json.dumps(d))
 
 
+def summarize_trace(db, title, out, command, note=""):
+    """Top kernels of a rocprofv3 --kernel-trace --stats database as a short markdown table."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = list(c.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    lines = [f"# rocprofv3 kernel trace: {title}", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for n, calls, tot, avg, pct in rows[:10]:
+        short = n if len(n) < 70 else n[:67] + "..."
+        lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.1f} | {pct:.2f} |")
+    if note:
+        lines += ["", note]
+    with open(os.path.join(ROOT, "profiles", out), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def summarize_pmc(db, title, out, command):
+    """Median per-dispatch counter values of the plain step kernel from a rocprofv3 --pmc database."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    vals = {}
+    for k, cn, v in c.execute("select kernel_name, counter_name, value from counters_collection"):
+        if _is_plain_step(k):
+            vals.setdefault(cn, []).append(v)
+    lines = [f"# rocprofv3 counters of the step kernel: {title}", "", "Command:", "", "```", command, "```", "",
+             "| counter | median per dispatch |", "|---|---|"]
+    for cn in sorted(vals):
+        lines.append(f"| {cn} | {float(np.median(vals[cn])):.6g} |")
+    lines += ["", f"kernel source hash: {kernel_source_hash()}"]
+    with open(os.path.join(ROOT, "profiles", out), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return {cn: float(np.median(v)) for cn, v in vals.items()}
+
+
 # ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
@@ -449,9 +492,19 @@ def main():
     ap.add_argument("--seconds", type=float, default=60.0, help="serve: arrival window of the offered-load run")
     ap.add_argument("--sustain-seconds", type=float, default=20.0, help="serve: arrival window at the sustained rate")
     ap.add_argument("--budget-mb", type=int, default=1024, help="serve: HBM budget for admitted requests (MiB)")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("DB", "TITLE", "OUT", "COMMAND"),
+                    help="write a profiles/ table of the top kernels of a trace database and exit")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("DB", "TITLE", "OUT", "COMMAND"),
+                    help="write a profiles/ table of step-kernel counters from a --pmc database and exit")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
                     help="write profiles/ summaries from rocprofv3 databases and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc)))
+        return
     if args.summarize:
         wl = args.workload
         nwd = args.worlds or {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 1024}[wl]

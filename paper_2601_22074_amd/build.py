@@ -12,8 +12,11 @@ LIB = os.path.join(HERE, "librbstep.so")
 SOURCES = ["runtime.hip", "step_kernel.hip", "aux_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# -ffp-contract=on: multiply-adds are fused only inside one source expression, so every kernel
+# instantiation (plain or fused launch, any chain bound) rounds a world's arithmetic the same way
+# and the batched forms reproduce the plain launch bit for bit.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on",
          "-Wall", "-Wno-unused-result", "-Wno-unused-variable"]
 
 

@@ -337,7 +337,10 @@ DEV BodyLane<MAXD> load_body_lane(const DevModel& m, const DofLane<MAXD>& DL, in
 // LDS buffer piv; every lane reads the row back with broadcast loads and its own multiplier
 // l_i = H_ki / D_k with one addressed load (0 for lanes that are not ancestors of k), then
 // applies H_i. -= l_i H_k. and b_i -= l_i y_k (the L' solve rides along).  Updates land only
-// in positions a lane never reads as data, so no lane masking is needed.  Rows stay unscaled:
+// in positions a lane never reads as data, so no lane masking is needed: an ancestor i of k
+// (depth d_i < d_k) takes k's entries t < d_i, and everything from d_i on is its own padding;
+// any other lane has l_i = 0 exactly.  Padding starts at zero and only ever receives
+// multiples of other rows' entries, so it stays finite and rows are published whole.  Rows stay unscaled:
 // L_ij = H_ij / D_i is applied in the L solve, which runs by depth level with one cross-lane
 // shuffle per level.  On return Hr holds the unscaled factor rows, *inv_out = 1/D_i; returns x_i.
 template <int MAXD>
@@ -357,9 +360,8 @@ DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MA
             const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(pmask >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)pmask, 0u));
             float* P = piv + slot * STRIDE;
-            // publish the row with its padding zeroed, so unguarded updates below add exact zeros
 #pragma unroll
-            for (int t = 0; t < MAXD; t++) P[t] = t < di ? Hr[t] : 0.f;
+            for (int t = 0; t < MAXD; t++) P[t] = Hr[t];
             P[MAXD] = bi;
         }
         wave_sync();
@@ -369,23 +371,21 @@ DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MA
             left &= left - 1ull;
             const int dk = __builtin_amdgcn_readlane(di, k);
             const float* P = piv + pp * STRIDE;
+            float hk[MAXD];
+#pragma unroll
+            for (int t = 0; t < MAXD; t++) hk[t] = P[t];
             const float yk = P[MAXD];
             const float d = P[dk - 1];
             const bool anc = (D.descmask >> k) & 1ull;
-            const float hka = anc ? P[a] : 0.f;
+            const float pa = P[a];               // a < MAXD: inside the published row
+            const float hka = anc ? pa : 0.f;
             const float inv = __builtin_amdgcn_rcpf(d);
             if (lane == k) inv_self = inv;
             const float l = hka * inv;
-            // l = 0 off the pivot's chain; positions past an ancestor's own depth are padding.
-            // Only the pivot's chain positions can change anything: blocks of four past its
-            // depth (a wave-uniform bound) are skipped, the zeroed padding covers the rest.
+            // l = 0 off the pivot's chain; positions past an ancestor's own depth are padding
+            // (bounding the update by the pivot's depth with uniform branches measured slower)
 #pragma unroll
-            for (int blk = 0; blk < MAXD / 4; blk++) {
-                if (4 * blk < dk) {
-#pragma unroll
-                    for (int j = 0; j < 4; j++) Hr[4 * blk + j] -= l * P[4 * blk + j];
-                }
-            }
+            for (int b = 0; b < MAXD; b++) Hr[b] -= l * hk[b];
             bi -= l * yk;
         }
         wave_sync();
@@ -453,64 +453,53 @@ DEV void geom_pose(const DevModel& m, const float* L, int g, float* x, float* R)
     mm(Rb, Rg, R);
 }
 
-// The j-th contact of pair p (j < count), or the count when want < 0.  Candidates are
-// enumerated in feature order; a candidate counts iff its distance is below the margin.
-DEV int pair_contacts(const DevModel& m, const float* L, int p, int want, float* dist, float* pos, int* feat,
-                      float* nrm) {
+// Candidate contacts of a plane pair, in feature order: sphere 0; capsule ends 0 (-z), 1 (+z);
+// box vertices k = 4x + 2y + z by sign bits.
+DEV int pair_ncand(int type) { return type == RB_GEOM_SPHERE ? 1 : (type == RB_GEOM_CAPSULE ? 2 : 8); }
+
+// Candidate k of plane pair p: distance to the plane, contact point (halfway between the
+// surfaces) and the plane normal.
+DEV void pair_candidate(const DevModel& m, const float* L, int p, int k, float* dist, float* pos, float* nrm) {
     float xp[3], Rp[9], x[3], R[9];
     geom_pose(m, L, m.pair_g1[p], xp, Rp);
     geom_pose(m, L, m.pair_g2[p], x, R);
-    float n[3] = {Rp[2], Rp[5], Rp[8]};
+    const float n[3] = {Rp[2], Rp[5], Rp[8]};
     nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2];
     const float* sz = m.geom_size + 3 * m.pair_g2[p];
-    float margin = m.pair_margin[p];
-    int type = m.pair_type[p];
-    int cnt = 0;
+    const int type = m.pair_type[p];
+    float e[3], rad = 0.f;
     if (type == RB_GEOM_SPHERE) {
-        float r[3] = {x[0] - xp[0], x[1] - xp[1], x[2] - xp[2]};
-        float d = dot(n, r) - sz[0];
-        if (d < margin) {
-            if (cnt == want) {
-                *dist = d; *feat = 0;
-                float k = sz[0] + 0.5f * d;
-                pos[0] = x[0] - n[0] * k; pos[1] = x[1] - n[1] * k; pos[2] = x[2] - n[2] * k;
-            }
-            cnt++;
-        }
+        e[0] = x[0]; e[1] = x[1]; e[2] = x[2];
+        rad = sz[0];
     } else if (type == RB_GEOM_CAPSULE) {
-        for (int f = 0; f < 2; f++) {
-            float s = f == 0 ? -sz[1] : sz[1];
-            float e[3] = {x[0] + s * R[2], x[1] + s * R[5], x[2] + s * R[8]};
-            float r[3] = {e[0] - xp[0], e[1] - xp[1], e[2] - xp[2]};
-            float d = dot(n, r) - sz[0];
-            if (d < margin) {
-                if (cnt == want) {
-                    *dist = d; *feat = f;
-                    float k = sz[0] + 0.5f * d;
-                    pos[0] = e[0] - n[0] * k; pos[1] = e[1] - n[1] * k; pos[2] = e[2] - n[2] * k;
-                }
-                cnt++;
-            }
-        }
-    } else if (type == RB_GEOM_BOX) {
-        for (int k = 0; k < 8; k++) {
-            float loc[3] = {(k & 4) ? sz[0] : -sz[0], (k & 2) ? sz[1] : -sz[1], (k & 1) ? sz[2] : -sz[2]};
-            float v[3];
-            mv(R, loc, v);
-            v[0] += x[0]; v[1] += x[1]; v[2] += x[2];
-            float r[3] = {v[0] - xp[0], v[1] - xp[1], v[2] - xp[2]};
-            float d = dot(n, r);
-            if (d < margin) {
-                if (cnt == want) {
-                    *dist = d; *feat = k;
-                    float h = 0.5f * d;
-                    pos[0] = v[0] - n[0] * h; pos[1] = v[1] - n[1] * h; pos[2] = v[2] - n[2] * h;
-                }
-                cnt++;
-            }
-        }
+        const float sgn = k == 0 ? -sz[1] : sz[1];
+        e[0] = x[0] + sgn * R[2]; e[1] = x[1] + sgn * R[5]; e[2] = x[2] + sgn * R[8];
+        rad = sz[0];
+    } else {
+        const float loc[3] = {(k & 4) ? sz[0] : -sz[0], (k & 2) ? sz[1] : -sz[1], (k & 1) ? sz[2] : -sz[2]};
+        mv(R, loc, e);
+        e[0] += x[0]; e[1] += x[1]; e[2] += x[2];
     }
-    return cnt;
+    const float r[3] = {e[0] - xp[0], e[1] - xp[1], e[2] - xp[2]};
+    const float d = dot(n, r) - rad;
+    *dist = d;
+    const float h = rad + 0.5f * d;
+    pos[0] = e[0] - n[0] * h; pos[1] = e[1] - n[1] * h; pos[2] = e[2] - n[2] * h;
+}
+
+// Bit k set iff candidate k of plane pair p is below the margin.  Computed once per pair; the
+// contact lanes then pick their candidate from these bits, so membership never depends on
+// re-evaluating a distance that sits on the margin.
+DEV uint32_t pair_mask(const DevModel& m, const float* L, int p) {
+    const int nc = pair_ncand(m.pair_type[p]);
+    const float margin = m.pair_margin[p];
+    uint32_t mask = 0;
+    for (int k = 0; k < nc; k++) {
+        float d, pos[3], nrm[3];
+        pair_candidate(m, L, p, k, &d, pos, nrm);
+        if (d < margin) mask |= 1u << k;
+    }
+    return mask;
 }
 
 DEV float pick3(const float* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
@@ -1032,13 +1021,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 
         // ---- collision: count per pair, scan, then each contact lane rebuilds its contact
         int cnt = 0;
-        float dist_, pos_[3], nrm_[3];
-        int feat_;
+        uint32_t cmask = 0;    // plane pairs: candidates below the margin
+        float pos_[3];
         if (lane < m.npair) {
-            if (BB && m.pair_type[lane] == RB_PAIR_BOXBOX)
+            if (BB && m.pair_type[lane] == RB_PAIR_BOXBOX) {
                 cnt = box_box(m, L, lane, L + m.o_bb + RB_BB_FLOATS * m.pair_slot[lane]);
-            else
-                cnt = pair_contacts(m, L, lane, -1, &dist_, pos_, &feat_, nrm_);
+            } else {
+                cmask = pair_mask(m, L, lane);
+                cnt = __builtin_popcount(cmask);
+            }
         }
         if (BB) wave_sync();   // box-box blocks written by their pair lanes are read by contact lanes
         int incl = wscan_incl(cnt, lane);
@@ -1060,6 +1051,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             src = lo;
         }
         int before = __shfl(incl - cnt, src);
+        uint32_t smask = (uint32_t)__shfl((int)cmask, src);
         float margin_c = 0.f;
         if (has) {
             int j = lane - before, feat;
@@ -1070,7 +1062,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 feat = (int)S[52 + 5 * j];
                 C.n[0] = S[88]; C.n[1] = S[89]; C.n[2] = S[90];
             } else {
-                pair_contacts(m, L, src, j, &C.dist, pos_, &feat, C.n);
+                // the j-th set bit of the pair's candidate mask
+                for (int t = 0; t < j; t++) smask &= smask - 1u;
+                feat = __builtin_ctz(smask);
+                pair_candidate(m, L, src, feat, &C.dist, pos_, C.n);
             }
             C.r[0] = pos_[0] - O[0]; C.r[1] = pos_[1] - O[1]; C.r[2] = pos_[2] - O[2];
             contact_frame(C.n, C.t1);

@@ -125,9 +125,9 @@ class Result:
     qpos: object                  # device tensor [n, nq]
     qvel: object                  # device tensor [n, nv]
     status: object                # device tensor [n] int32
-    arrival: float
+    arrival: float                # seconds after the start of the run
     event: object = None
-    finish: float | None = None
+    finish: float | None = None   # seconds after the start of the run
     extra: dict = field(default_factory=dict)
 
 
@@ -260,7 +260,8 @@ class Server:
             if block:
                 r.event.synchronize()
             if block or r.event.query():
-                r.finish = self.t0 + self.ev0.elapsed_time(r.event) / 1e3
+                # seconds after the start of the run, on the device clock (ev0 marks the start)
+                r.finish = self.ev0.elapsed_time(r.event) / 1e3
                 self.results[r.rid] = r
             else:
                 keep.append(r)

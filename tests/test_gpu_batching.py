@@ -28,8 +28,8 @@ def _setup(rb, torch, mix=MIX, first=0):
     return out
 
 
-def _run_separate(rb, torch, steps):
-    S = _setup(rb, torch)
+def _run_separate(rb, torch, steps, mix=MIX):
+    S = _setup(rb, torch, mix)
     for _ in range(steps):
         for s in S:
             s["batch"].step(s["u"], s["q"], s["v"])
@@ -48,6 +48,26 @@ def test_fused_equals_separate(order, grid):
         plan.bind(i, s["u"], s["q"], s["v"])
     plan.set_schedule(order, grid)
     for _ in range(3):
+        plan.step()
+    torch.cuda.synchronize()
+    for (q, v), s in zip(ref, S):
+        np.testing.assert_array_equal(s["q"].cpu().numpy(), q)
+        np.testing.assert_array_equal(s["v"].cpu().numpy(), v)
+
+
+def test_fused_equals_separate_long_rollout():
+    """300 env steps of contact-rich worlds: any rounding difference between the fused and the
+    plain instantiations would have grown into visible divergence by then."""
+    import torch
+    import paper_2601_22074_amd as rb
+    mix = [("chain3", 64), ("quadruped", 256), ("humanoid", 256), ("arm_box", 128)]
+    ref = _run_separate(rb, torch, 300, mix)
+    S = _setup(rb, torch, mix)
+    plan = rb.Multi([s["batch"] for s in S])
+    for i, s in enumerate(S):
+        plan.bind(i, s["u"], s["q"], s["v"])
+    plan.set_schedule(rb.ORDER_INTERLEAVE, 0)
+    for _ in range(300):
         plan.step()
     torch.cuda.synchronize()
     for (q, v), s in zip(ref, S):
