@@ -128,6 +128,7 @@ struct Data {
     int nrows = 0;
     std::vector<double> J, aref, D, Ahat, efc_force, a, cforce;
     int niter = 0;
+    bool itercap = false;   // the Newton loop used every iteration without meeting a tolerance
     double cost = 0;
 
     explicit Data(const Model* mm) : m(mm) {
@@ -771,6 +772,7 @@ void newton(const Model& m, Data& d) {
     double tol = m.mode == 1 ? 1e-12 : m.tol;
     double scale = m.meaninertia * nv;
     d.niter = 0;
+    d.itercap = false;
     d.a = d.a0;
     if (nr == 0) {
         d.efc_force.assign(0, 0.0);
@@ -779,6 +781,7 @@ void newton(const Model& m, Data& d) {
     }
     if (cost(m, d, d.aws.data()) < cost(m, d, d.a0.data())) d.a = d.aws;
     std::vector<double> jar(nr), g(nv), H(nv * nv), LH, p(nv), anew(nv);
+    bool stopped = false;
     for (int it = 0; it < maxiter; it++) {
         for (int e = 0; e < nr; e++) {
             double t = -d.aref[e];
@@ -801,8 +804,8 @@ void newton(const Model& m, Data& d) {
         }
         double gn = 0;
         for (int k = 0; k < nv; k++) gn += g[k] * g[k];
-        if (std::sqrt(gn) / scale < tol) break;
-        if (!cholesky(H, nv, LH)) break;
+        if (std::sqrt(gn) / scale < tol) { stopped = true; break; }
+        if (!cholesky(H, nv, LH)) { stopped = true; break; }
         std::vector<double> ng(nv);
         for (int k = 0; k < nv; k++) ng[k] = -g[k];
         chol_solve(LH, nv, ng.data(), p.data());
@@ -812,8 +815,9 @@ void newton(const Model& m, Data& d) {
         double fnew = cost(m, d, anew.data());
         d.a = anew;
         d.niter = it + 1;
-        if ((fold - fnew) / scale < tol) break;
+        if ((fold - fnew) / scale < tol) { stopped = true; break; }
     }
+    d.itercap = !stopped && maxiter > 0;
     d.cost = cost(m, d, d.a.data());
     d.efc_force.assign(nr, 0.0);
     for (int e = 0; e < nr; e++) {
@@ -1115,10 +1119,12 @@ int rbo_step(const void* mp, int32_t n, const double* ctrl, double* qpos, double
             const double* fr = friction ? friction + w : nullptr;
             const double* ms = mass_scale ? mass_scale + (size_t)w * m.nbody : nullptr;
             int ncon = 0;
+            status[w] &= ~2u;
             if (!(status[w] & 1u)) {
                 for (int k = 0; k < m.K; k++) {
                     load_world(m, d, q, v, u, aws, fr, ms);
                     forward(m, d);
+                    if (d.itercap) status[w] |= 2u;
                     integrate(m, q, v, d.a.data(), q1.data(), v1.data());
                     if (!all_finite(q1.data(), m.nq) || !all_finite(v1.data(), m.nv) || !all_finite(d.a.data(), m.nv)) {
                         status[w] |= 1u;

@@ -99,7 +99,8 @@ int rbo_forward(const void* m, const double* qpos, const double* qvel, const dou
 
 /* n env steps of K substeps each (OpenMP over worlds, nthreads <= 0 -> all cores).
  * qpos [n,nq], qvel [n,nv], qacc_ws [n,nv] in/out; ctrl [n,nu]; friction [n] / mass_scale
- * [n,nbody] may be NULL; status [n] in/out (bit 0 = non-finite, world frozen);
+ * [n,nbody] may be NULL; status [n] in/out (bit 0 = non-finite, world frozen; bit 1 =
+ * some substep's Newton loop stopped at the iteration cap, cleared at the start of each step);
  * contacts may be NULL and receive the last substep's contacts. */
 int rbo_step(const void* m, int32_t n, const double* ctrl, double* qpos, double* qvel,
              double* qacc_ws, const double* friction, const double* mass_scale, uint32_t* status,

@@ -360,8 +360,9 @@ DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MA
             const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(pmask >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)pmask, 0u));
             float* P = piv + slot * STRIDE;
+            float4* P4 = reinterpret_cast<float4*>(P);
 #pragma unroll
-            for (int t = 0; t < MAXD; t++) P[t] = Hr[t];
+            for (int j = 0; j < MAXD / 4; j++) P4[j] = make_float4(Hr[4 * j], Hr[4 * j + 1], Hr[4 * j + 2], Hr[4 * j + 3]);
             P[MAXD] = bi;
         }
         wave_sync();
@@ -371,9 +372,15 @@ DEV float factor_solve(const DevModel& m, const DofLane<MAXD>& D, float (&Hr)[MA
             left &= left - 1ull;
             const int dk = __builtin_amdgcn_readlane(di, k);
             const float* P = piv + pp * STRIDE;
+            // pivot rows start on 16-byte boundaries (section offsets and the row stride are
+            // multiples of four floats): read them four at a time
             float hk[MAXD];
+            const float4* P4 = reinterpret_cast<const float4*>(P);
 #pragma unroll
-            for (int t = 0; t < MAXD; t++) hk[t] = P[t];
+            for (int j = 0; j < MAXD / 4; j++) {
+                const float4 x4 = P4[j];
+                hk[4 * j] = x4.x; hk[4 * j + 1] = x4.y; hk[4 * j + 2] = x4.z; hk[4 * j + 3] = x4.w;
+            }
             const float yk = P[MAXD];
             const float d = P[dk - 1];
             const bool anc = (D.descmask >> k) & 1ull;
@@ -973,13 +980,25 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         for (int lev = m.nblevel - 1; lev >= 1; lev--) {
             if (BL.level == lev) {
                 const int b = lane;
+                // accumulate in registers: one read and one write of the body's own entries
+                float fw[6], ci[10];
+#pragma unroll
+                for (int k = 0; k < 6; k++) fw[k] = bvec2[6 * b + k];
+#pragma unroll
+                for (int k = 0; k < 10; k++) ci[k] = crb[10 * b + k];
 #pragma unroll
                 for (int c = 0; c < 4; c++) {
                     int ch = (BL.children >> (8 * c)) & 0xff;
                     if (ch == 0xff) break;
-                    for (int k = 0; k < 6; k++) bvec2[6 * b + k] += bvec2[6 * ch + k];
-                    for (int k = 0; k < 10; k++) crb[10 * b + k] += crb[10 * ch + k];
+#pragma unroll
+                    for (int k = 0; k < 6; k++) fw[k] += bvec2[6 * ch + k];
+#pragma unroll
+                    for (int k = 0; k < 10; k++) ci[k] += crb[10 * ch + k];
                 }
+#pragma unroll
+                for (int k = 0; k < 6; k++) bvec2[6 * b + k] = fw[k];
+#pragma unroll
+                for (int k = 0; k < 10; k++) crb[10 * b + k] = ci[k];
             }
             wave_sync();
         }
@@ -1087,65 +1106,48 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             for (int w2 = 0; w2 < MAXD / 4; w2++) cw[w2] = (uint32_t)__shfl((int)BL.anc[w2], C.body);
 #define CROW(t) rowadr_l[(int)((cw[(t) >> 2] >> (8 * ((t) & 3))) & 0xffu)]
         if (has) {
-            // A_c = J_c M^-1 J_c' from Y = L'^-1 J_c' on the body's chain (positions t < d):
-            // one column (normal, t1, t2) at a time, keeping only the normal column
+            // A_c = J_c M^-1 J_c' from Y = L'^-1 J_c' on the body's chain (positions t < d), the
+            // normal and both tangent columns together so each factor entry is read once
             float t2c[3];
             cross(C.n, C.t1, t2c);
-            auto half_solve = [&](const float* dir, float (&Y)[MAXD]) {
+            float Yn[MAXD], Y1[MAXD], Y2[MAXD];
 #pragma unroll
-                for (int t = 0; t < MAXD; t++) {
-                    Y[t] = 0.f;
-                    if (t < d) {
-                        const float* S = cdof + 6 * (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu);
-                        float wr[3];
-                        cross(S, C.r, wr);
-                        float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
-                        Y[t] = C.sigma * dot(dir, vp);
+            for (int t = 0; t < MAXD; t++) {
+                // past the chain the byte is 0, a valid dof: computed and discarded
+                const float* S = cdof + 6 * (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu);
+                float wr[3];
+                cross(S, C.r, wr);
+                const float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                const bool on = t < d;
+                Yn[t] = on ? C.sigma * dot(C.n, vp) : 0.f;
+                Y1[t] = on ? C.sigma * dot(C.t1, vp) : 0.f;
+                Y2[t] = on ? C.sigma * dot(t2c, vp) : 0.f;
+            }
+#pragma unroll
+            for (int tp = MAXD - 1; tp >= 1; tp--) {
+                if (tp < d) {
+                    const int row = CROW(tp);
+#pragma unroll
+                    for (int t = 0; t < tp; t++) {
+                        const float h = H[row + t];
+                        Yn[t] -= h * Yn[tp];
+                        Y1[t] -= h * Y1[tp];
+                        Y2[t] -= h * Y2[tp];
                     }
                 }
-#pragma unroll
-                for (int tp = MAXD - 1; tp >= 1; tp--) {
-                    if (tp < d) {
-                        const int row = CROW(tp);
-#pragma unroll
-                        for (int t = 0; t < tp; t++) Y[t] -= H[row + t] * Y[tp];
-                    }
-                }
-            };
-            float Z0[MAXD];
+            }
             float A00 = 0, A11 = 0, A22 = 0, A01 = 0, A02 = 0;
-            {
-                float Y[MAXD];
-                half_solve(C.n, Y);
 #pragma unroll
-                for (int t = 0; t < MAXD; t++) {
-                    Z0[t] = 0.f;
-                    if (t < d) {
-                        Z0[t] = Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
-                        A00 += Y[t] * Z0[t];
-                    }
+            for (int t = 0; t < MAXD; t++)
+                if (t < d) {
+                    const float id = __builtin_amdgcn_rcpf(H[CROW(t) + t]);
+                    const float zn = Yn[t] * id;
+                    A00 += Yn[t] * zn;
+                    A11 += Y1[t] * Y1[t] * id;
+                    A22 += Y2[t] * Y2[t] * id;
+                    A01 += zn * Y1[t];
+                    A02 += zn * Y2[t];
                 }
-            }
-            {
-                float Y[MAXD];
-                half_solve(C.t1, Y);
-#pragma unroll
-                for (int t = 0; t < MAXD; t++)
-                    if (t < d) {
-                        A11 += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
-                        A01 += Z0[t] * Y[t];
-                    }
-            }
-            {
-                float Y[MAXD];
-                half_solve(t2c, Y);
-#pragma unroll
-                for (int t = 0; t < MAXD; t++)
-                    if (t < d) {
-                        A22 += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
-                        A02 += Z0[t] * Y[t];
-                    }
-            }
             float vrow[4];
             rows_of(C, cvel, vrow);
             float rd = C.dist - margin_c;
@@ -1193,15 +1195,16 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             f0 = wsum(f0);
             for (int i = lane; i < nv; i += RB_WAVE) tmp[i] = aws[i] - a0[i];
             wave_sync();
-            spatial_mul(m, BL, DL, cdof, cinert, tmp, bvec, bvec2, g, lane);   // g <- M (aws - a0)
-            body_motion(m, BL, cdof, aws, bvec, lane);
+            // g <- M (aws - a0); bvec keeps the body motions of (aws - a0), and the rows are
+            // linear in the motion, so the residuals at aws are those at a0 plus these
+            spatial_mul(m, BL, DL, cdof, cinert, tmp, bvec, bvec2, g, lane);
             float jw[4] = {0, 0, 0, 0};
             float fw = 0.f;
             if (has) {
                 rows_of(C, bvec, jw);
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    jw[e] -= C.aref[e];
+                    jw[e] += j0[e];
                     float mn = fminf(jw[e], 0.f);
                     fw += 0.5f * C.D[e] * mn * mn;
                 }
@@ -1287,11 +1290,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 float gn = sqrtf(wsum(gi * gi));
                 if (gn < m.tol_scale) break;
                 // Hessian row in registers: H_ij = M_ij + S_j . F_i over the chain of i
+                // (computed for every position and selected: past the chain the index stays in
+                // LDS -- the next rows of M, or H after it -- and the value is discarded)
                 float Hr[MAXD];
 #pragma unroll
                 for (int t = 0; t < MAXD; t++) {
-                    Hr[t] = 0.f;
-                    if (t < DL.depth) Hr[t] = Mm[DL.rowadr + t] + sdot(cdof + 6 * DL.ancestor(t), F);
+                    const float h = Mm[DL.rowadr + t] + sdot(cdof + 6 * DL.ancestor(t), F);
+                    Hr[t] = t < DL.depth ? h : 0.f;
                 }
                 RB_STAGE(6);
                 {
@@ -1316,7 +1321,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     float bp[4];
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        bp[e] = (has && sr[e] != 0.f) ? -C.jar[e] / sr[e] : INFINITY;
+                        bp[e] = (has && sr[e] != 0.f) ? -C.jar[e] * __builtin_amdgcn_rcpf(sr[e]) : INFINITY;
                     }
                     float at = 0.f;
                     int guard = 4 * ncon + 2;
@@ -1337,7 +1342,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         }
                         float Aseg = A0 + wsum(sa), Bseg = B0 + wsum(sb);
                         nxt = wmin(nxt);
-                        float root = -Bseg / Aseg;
+                        float root = -Bseg * __builtin_amdgcn_rcpf(Aseg);
                         if (root <= nxt) {
                             alpha = fmaxf(root, 0.f);
                             break;

@@ -483,3 +483,25 @@ def test_box_box_cube_settles_on_table(oracle_mod):
     np.testing.assert_allclose(c["force"][0, :n, 0].sum(), 0.1 * 9.81, rtol=1e-6)
     assert np.abs(v[0, -6:]).max() < 1e-6
     assert abs(q[0, -7] - 0.5) < 1e-12 and 0.4 + 0.025 - 1e-3 < q[0, -5] < 0.4 + 0.025
+
+
+def test_newton_iteration_cap_status(oracle_mod):
+    """Status bit 1 reports a Newton loop stopped by the iteration cap: set with a single
+    iteration on a contact-rich state, clear when the loop may converge."""
+    import copy
+    m = robots.humanoid()
+    q = np.array([robots.qpos0(m)], np.float64)
+    q[0, 2] -= 0.02                      # pressed into the floor: many active rows
+    v = np.zeros((1, len(q[0]) - 1))
+    m1 = copy.deepcopy(m)
+    m1["opt"]["iterations"] = 1
+    o1 = oracle_mod.Oracle(m1)
+    st = np.zeros(1, np.uint32)
+    o1.step(np.zeros((1, o1.nu)), q.copy(), v.copy(), np.zeros((1, o1.nv)), status=st)
+    assert st[0] & 2
+    m50 = copy.deepcopy(m)
+    m50["opt"]["iterations"] = 50
+    o50 = oracle_mod.Oracle(m50)
+    st = np.array([2], np.uint32)        # cleared at the start of the step
+    o50.step(np.zeros((1, o50.nu)), q.copy(), v.copy(), np.zeros((1, o50.nv)), status=st)
+    assert st[0] == 0
