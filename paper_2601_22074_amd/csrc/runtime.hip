@@ -749,11 +749,8 @@ int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out) {
         p->maxd = std::max(p->maxd, models[i].maxd);
         p->boxbox = p->boxbox || models[i].nbb > 0;
     }
-    // every batch runs in the instantiation for the deepest model
-    for (int i = 0; i < nbatch; i++) {
-        layout_tail(models[i], p->maxd);
-        p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);
-    }
+    // every batch runs in its own model's instantiation, with its own LDS layout
+    for (int i = 0; i < nbatch; i++) p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);
     p->bound_n.assign(nbatch, -1);
     p->args_host.assign(rb_step_args_size() * nbatch, 0);
     hipError_t e = hipMalloc((void**)&p->d_models, sizeof(DevModel) * nbatch);

@@ -1526,6 +1526,24 @@ struct MultiArgs {
     int nitems;
 };
 
+// Each item runs the instantiation the plain launch would use for its model (chain bound and
+// box-box code), so a world computes exactly as in rb_step and small models keep lean code;
+// MAXD and BB bound what the plan's models need.
+template <int MAXD, bool BB>
+DEV void world_step_as_plain(const DevModel& m, const StepArgs& A, int w, float* lds) {
+    const bool bb = BB && m.nbb > 0;
+    if (MAXD >= 32 && m.maxd > 16) {
+        if (bb) world_step<(MAXD >= 32 ? 32 : MAXD), false, BB>(m, A, w, lds);
+        else world_step<(MAXD >= 32 ? 32 : MAXD), false, false>(m, A, w, lds);
+    } else if (MAXD >= 16 && m.maxd > 8) {
+        if (bb) world_step<(MAXD >= 16 ? 16 : MAXD), false, BB>(m, A, w, lds);
+        else world_step<(MAXD >= 16 ? 16 : MAXD), false, false>(m, A, w, lds);
+    } else {
+        if (bb) world_step<8, false, BB>(m, A, w, lds);
+        else world_step<8, false, false>(m, A, w, lds);
+    }
+}
+
 template <int MAXD, bool BB>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
     MultiArgs M) {
@@ -1535,7 +1553,7 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVE
         const int b = item >> 24, w = item & 0xffffff;
         const DevModel& m = M.models[b];
         const StepArgs& A = M.args[b];
-        if (w < A.n) world_step<MAXD, false, BB>(m, A, w, lds);
+        if (w < A.n) world_step_as_plain<MAXD, BB>(m, A, w, lds);
     }
 }
 
