@@ -142,8 +142,9 @@ def run_mix(args):
     for i, x in enumerate(S):
         plan.bind(i, x["u"], x["q"], x["v"], x["con"], x["st"])
     if choice[0] != "fused":
-        choice = ("fused", rb.ORDER_HEAVY_FIRST, 0)
+        choice = ("fused", rb.ORDER_HEAVY_FIRST, 0, 0)
     plan.set_schedule(choice[1], choice[2])
+    plan.set_occupancy(choice[3])
 
     def load_ctrl(S, s):
         for x, u in zip(S, seg(S, s)):
@@ -159,6 +160,7 @@ def run_mix(args):
     for i, x in enumerate(S):
         plan.bind(i, x["u"], x["q"], x["v"], x["con"], x["st"])
     plan.set_schedule(choice[1], choice[2])
+    plan.set_occupancy(choice[3])
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
     plan.graph_capture(P, side)
@@ -184,7 +186,8 @@ def run_mix(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT["mix"], "worlds": nworlds, "env_steps": K, "form": best,
-                   "schedule": {"order": choice[1], "grid": choice[2]}, "graph_steps": P},
+                   "schedule": {"order": choice[1], "grid": choice[2], "waves_per_simd_cap": choice[3]},
+                   "graph_steps": P},
         "forms_env_steps_per_s": rates,
         "forms_ms_per_step": res,
         "speedup_vs_separate": rates[best] / rates["separate"],

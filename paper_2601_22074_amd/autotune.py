@@ -1,9 +1,11 @@
 """Schedule autotuner for mixed-model batching.
 
 Given batches with bound step inputs, time each candidate schedule of one env step --
-separate plain launches, or the fused launch under every dispatch order and a few grid
-sizes -- on cloned state, and keep the fastest.  Decisions are cached in a JSON file keyed
-by the batch signature (model shapes and world counts), so a configuration is tuned once.
+separate plain launches, or the fused launch under every dispatch order, a few grid sizes
+(one workgroup per world, or a persistent grid of 1x / 2x the resident capacity) and two
+occupancy caps (none, or 2 resident waves per SIMD) -- on cloned state, and keep the fastest.
+Decisions are cached in a JSON file keyed by the batch signature (model shapes and world
+counts), so a configuration is tuned once.
 """
 from __future__ import annotations
 
@@ -25,13 +27,15 @@ def signature(batches, ns) -> str:
 
 
 def candidates(nitems: int, resident: int):
-    out = [("separate", None, None)]
-    for order in (rbstep.ORDER_HEAVY_FIRST, rbstep.ORDER_INTERLEAVE, rbstep.ORDER_BATCH):
-        out.append(("fused", order, 0))
-        for mult in (1, 2):
-            g = resident * mult
-            if g < nitems:
-                out.append(("fused", order, g))
+    """(kind, order, grid, waves per SIMD cap) tuples."""
+    out = [("separate", None, None, None)]
+    for occ in (0, 2):
+        for order in (rbstep.ORDER_HEAVY_FIRST, rbstep.ORDER_INTERLEAVE, rbstep.ORDER_BATCH):
+            out.append(("fused", order, 0, occ))
+            for mult in (1, 2):
+                g = resident * mult
+                if g < nitems:
+                    out.append(("fused", order, g, occ))
     return out
 
 
@@ -73,23 +77,23 @@ def tune(multi: "rbstep.Multi", inputs, reps: int = 3, resident: int = 2048, use
     for i, (u, q, v) in enumerate(clones):
         multi.bind(i, u, q, v)
     timings = {}
-    if use_cache and sig in cache:
+    if use_cache and sig in cache and len(cache[sig].get("choice", ())) == 4:
         choice = tuple(cache[sig]["choice"])
     else:
-        for kind, order, grid in candidates(sum(ns), resident):
+        for kind, order, grid, occ in candidates(sum(ns), resident):
             if kind == "separate":
                 def fn():
                     for b, (u, q, v) in zip(batches, clones):
                         b.step(u, q, v)
             else:
                 multi.set_schedule(order, grid)
+                multi.set_occupancy(occ)
 
                 def fn():
                     multi.step()
-            timings[f"{kind}/{order}/{grid}"] = _time(fn, stream, reps)
+            timings[f"{kind}/{order}/{grid}/{occ}"] = _time(fn, stream, reps)
         best = min(timings, key=timings.get)
-        k, o, g = best.split("/")
-        choice = (k, None if o == "None" else int(o), None if g == "None" else int(g))
+        choice = tuple(None if x == "None" else (x if i == 0 else int(x)) for i, x in enumerate(best.split("/")))
         cache[sig] = {"choice": list(choice), "timings_ms": timings}
         if use_cache:
             os.makedirs(os.path.dirname(CACHE), exist_ok=True)
@@ -102,5 +106,6 @@ def tune(multi: "rbstep.Multi", inputs, reps: int = 3, resident: int = 2048, use
         multi.bind(i, u, q, v)
     if choice[0] == "fused":
         multi.set_schedule(choice[1], choice[2])
+        multi.set_occupancy(choice[3])
     torch.cuda.synchronize()
     return choice, timings

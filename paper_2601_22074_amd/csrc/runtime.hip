@@ -717,6 +717,7 @@ struct rb_multi {
     int nitems = 0, grid = 0, maxd = 0, lds_floats = 0;
     bool boxbox = false;
     int items_cap = 0;                         // capacity of d_items
+    int lds_pad = 0;                           // extra LDS floats per workgroup (occupancy cap)
     // pinned staging ring for rb_multi_set_items (a slot is reused once its copy is done)
     static constexpr int RING = 4;
     int32_t* stage[RING] = {};
@@ -908,11 +909,31 @@ int rb_multi_set_items(rb_multi* p, const int32_t* items, int32_t n, int32_t gri
     return RB_OK;
 }
 
+int rb_multi_set_occupancy(rb_multi* p, int32_t waves_per_simd) {
+    if (!p || waves_per_simd < 0 || waves_per_simd > 8) return fail(RB_EINVAL, "bad arguments to rb_multi_set_occupancy");
+    p->lds_pad = 0;
+    if (waves_per_simd > 0) {
+        // one wave per workgroup, four SIMDs per CU: cap the CU at 4 w workgroups by making
+        // each one need more than 1 / (4 w + 1) of the CU's LDS
+        int dev = 0;
+        hipDeviceProp_t prop;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "rb_multi_set_occupancy");
+        const size_t per_cu = prop.maxSharedMemoryPerMultiProcessor;
+        const int need = (int)(per_cu / (4 * waves_per_simd + 1) / 4) + 1;   // floats
+        if ((size_t)need * 4 > prop.sharedMemPerBlock) return fail(RB_EINVAL, "occupancy cap needs more LDS than a workgroup may use");
+        p->lds_pad = std::max(0, need - p->lds_floats);
+    }
+    multi_free_graph(p);
+    return RB_OK;
+}
+
 int rb_multi_step(rb_multi* p, void* stream) {
     if (!p) return fail(RB_EINVAL, "null plan");
     if (p->nitems == 0) return RB_OK;
     if (!p->d_items) return fail(RB_ESTATE, "no schedule");
-    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats, p->grid,
+    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid,
                                    (hipStream_t)stream);
     return e == hipSuccess ? RB_OK : hip_fail(e, "rb_multi_step");
 }
@@ -926,7 +947,7 @@ int rb_multi_graph_capture(rb_multi* p, int32_t nsteps, void* stream) {
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     for (int k = 0; k < nsteps && e == hipSuccess; k++)
-        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats, p->grid, s);
+        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid, s);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

@@ -55,6 +55,25 @@ def test_fused_equals_separate(order, grid):
         np.testing.assert_array_equal(s["v"].cpu().numpy(), v)
 
 
+@pytest.mark.parametrize("occ", [1, 2])
+def test_fused_with_occupancy_cap_equals_separate(occ):
+    import torch
+    import paper_2601_22074_amd as rb
+    ref = _run_separate(rb, torch, 3)
+    S = _setup(rb, torch)
+    plan = rb.Multi([s["batch"] for s in S])
+    for i, s in enumerate(S):
+        plan.bind(i, s["u"], s["q"], s["v"])
+    plan.set_schedule(rb.ORDER_HEAVY_FIRST, 0)
+    plan.set_occupancy(occ)
+    for _ in range(3):
+        plan.step()
+    torch.cuda.synchronize()
+    for (q, v), s in zip(ref, S):
+        np.testing.assert_array_equal(s["q"].cpu().numpy(), q)
+        np.testing.assert_array_equal(s["v"].cpu().numpy(), v)
+
+
 def test_fused_equals_separate_long_rollout():
     """300 env steps of contact-rich worlds: any rounding difference between the fused and the
     plain instantiations would have grown into visible divergence by then."""
