@@ -224,13 +224,19 @@ DEV void sym_mul(const DevModel& m, const float* M, const float* x, float* y, in
 }
 
 // spatial motion of every body produced by dof vector x: out[b] = sum over the body's chain S_i x_i
-template <typename BL_t>
-DEV void body_motion(const DevModel& m, const BL_t& BL, const float* cdof, const float* x, float* out, int lane) {
+// (the chain comes from the body's deepest dof lane).
+template <typename BL_t, typename DL_t>
+DEV void body_motion(const DevModel& m, const BL_t& BL, const DL_t& DL, const float* cdof, const float* x, float* out,
+                     int lane) {
+    constexpr int NW = sizeof(DL.anc) / sizeof(DL.anc[0]);
+    uint32_t ba[NW];
+#pragma unroll
+    for (int w = 0; w < NW; w++) ba[w] = (uint32_t)__shfl((int)DL.anc[w], BL.src);
     if (lane < m.nbody) {
         float acc[6] = {0, 0, 0, 0, 0, 0};
         for (int t = 0; t < BL.depth; t++) {
-            int i = BL.ancestor(t);
-            float xi = x[i];
+            const int i = (int)((ba[t >> 2] >> (8 * (t & 3))) & 0xffu);
+            const float xi = x[i];
 #pragma unroll
             for (int c = 0; c < 6; c++) acc[c] += cdof[6 * i + c] * xi;
         }
@@ -245,7 +251,7 @@ DEV void body_motion(const DevModel& m, const BL_t& BL, const float* cdof, const
 template <typename BL_t, typename DL_t>
 DEV void spatial_mul(const DevModel& m, const BL_t& BL, const DL_t& DL, const float* cdof, const float* cinert,
                      const float* x, float* bm, float* bf, float* y, int lane) {
-    body_motion(m, BL, cdof, x, bm, lane);
+    body_motion(m, BL, DL, cdof, x, bm, lane);
     if (lane < m.nbody) {
         float f[6];
         inert_mul(cinert + 10 * lane, bm + 6 * lane, f);
@@ -285,8 +291,7 @@ struct BodyLane {
     int depth;             // dofs on the chain (0 for static bodies)
     uint32_t children;     // up to 4 child bodies, one byte each (0xff = none)
     uint64_t chainmask;    // dofs on the chain
-    uint32_t anc[MAXD / 4];   // chain dofs, root first
-    DEV int ancestor(int t) const { return (int)((anc[t >> 2] >> (8 * (t & 3))) & 0xffu); }
+    int src;               // the chain's deepest dof, whose lane holds the chain (0 if none)
 };
 
 template <int MAXD>
@@ -322,12 +327,11 @@ DEV BodyLane<MAXD> load_body_lane(const DevModel& m, const DofLane<MAXD>& DL, in
     B.children = on ? (uint32_t)m.body_children[lane] : 0xffffffffu;
     B.chainmask = on ? m.body_chainmask[lane] : 0ull;
     int ld = on ? m.body_lastdof[lane] : -1;
-    // the body's chain is the chain of its deepest dof: copy that dof lane's constants
+    // the body's chain is the chain of its deepest dof: that dof lane holds it
     int src = ld < 0 ? 0 : ld;
     int dsrc = __shfl(DL.depth, src);
     B.depth = ld < 0 ? 0 : dsrc;
-#pragma unroll
-    for (int w = 0; w < MAXD / 4; w++) B.anc[w] = (uint32_t)__shfl((int)DL.anc[w], src);
+    B.src = src;
     return B;
 }
 
@@ -734,8 +738,9 @@ struct StepArgs {
     int want_contacts, want_taps;
 };
 
-// MAXD: longest dof chain the instantiation supports; TIMED: accumulate per-stage shader-clock
-// cycles for the stats tap (diagnostic builds of the same kernel).
+// MAXD: longest dof chain the instantiation supports; TIMED: the diagnostic instantiation that
+// serves rb_step_taps (stage taps, work totals and per-stage shader-clock cycles); the plain
+// instantiation carries none of that code.
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
@@ -1101,9 +1106,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         {
             // the contact body's chain, from the body lane
             const int d = __shfl(BL.depth, C.body);
+            const int csrc = __shfl(BL.src, C.body);
             uint32_t cw[MAXD / 4];
 #pragma unroll
-            for (int w2 = 0; w2 < MAXD / 4; w2++) cw[w2] = (uint32_t)__shfl((int)BL.anc[w2], C.body);
+            for (int w2 = 0; w2 < MAXD / 4; w2++) cw[w2] = (uint32_t)__shfl((int)DL.anc[w2], csrc);
 #define CROW(t) rowadr_l[(int)((cw[(t) >> 2] >> (8 * ((t) & 3))) & 0xffu)]
         if (has) {
             // A_c = J_c M^-1 J_c' from Y = L'^-1 J_c' on the body's chain (positions t < d), the
@@ -1161,7 +1167,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 float R = fmaxf(1e-15f, (1.0f - imp) / imp * ah[e]);
                 C.D[e] = 1.0f / R;
             }
-            if (A.want_taps && sub == 0 && A.taps.efc) {
+            if (TIMED && A.want_taps && sub == 0 && A.taps.efc) {
                 float* E = A.taps.efc + ((size_t)w * m.ncap + lane) * 12;
                 for (int e = 0; e < 4; e++) {
                     E[3 * e] = C.aref[e];
@@ -1180,7 +1186,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             wave_sync();
         } else {
             // cost at a0 and at the warm start; keep the better (ties go to a0)
-            body_motion(m, BL, cdof, a0, bvec, lane);
+            body_motion(m, BL, DL, cdof, a0, bvec, lane);
             float j0[4] = {0, 0, 0, 0};
             float f0 = 0.f;
             if (has) {
@@ -1326,7 +1332,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     float at = 0.f;
                     int guard = 4 * ncon + 2;
                     for (int k = 0; k < guard; k++) {
-                        st_seg++;
+                        if (TIMED) st_seg++;
                         float sa = 0.f, sb = 0.f, nxt = INFINITY;
                         if (has) {
 #pragma unroll
@@ -1375,18 +1381,20 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 if (improvement < m.tol_scale) { it++; break; }
             }
             if (it >= m.maxiter) itercap = true;
-            st_iter += it;
-            int act = 0;
-            if (has)
-                for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f;
-            st_rows += (int)wsum((float)act);
+            if (TIMED) {
+                st_iter += it;
+                int act = 0;
+                if (has)
+                    for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f;
+                st_rows += (int)wsum((float)act);
+            }
         }
-        st_con += ncon;
+        if (TIMED) st_con += ncon;
         RB_STAGE(6);
         if (itercap) status |= RB_STATUS_ITERCAP;
 
         // ---- first-substep taps
-        if (A.want_taps && sub == 0) {
+        if (TIMED && A.want_taps && sub == 0) {
             for (int i = lane; i < nv; i += RB_WAVE) {
                 size_t base = (size_t)w * nv;
                 if (A.taps.bias) A.taps.bias[base + i] = bias[i];
@@ -1469,7 +1477,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         A.qvel[(size_t)w * nv + i] = v[i];
         A.W.qacc_ws[(size_t)w * nv + i] = aws[i];
     }
-    if (A.want_taps && A.taps.stats && lane == 0) {
+    if (TIMED && A.want_taps && A.taps.stats && lane == 0) {
         int32_t* S = A.taps.stats + (size_t)w * RB_NSTATS;
         S[0] = st_con; S[1] = st_rows; S[2] = st_iter; S[3] = st_seg;
         for (int k = 0; k < RB_NSTAGE; k++) S[4 + k] = (int32_t)(stage_cyc[k] >> 4);
@@ -1634,7 +1642,7 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     A.want_taps = taps != nullptr;
     if (taps) A.taps = *taps; else A.taps = DevTaps{};
     size_t shmem = (size_t)m.lds_floats * sizeof(float);
-    const bool timed = taps != nullptr && taps->stats != nullptr;
+    const bool timed = taps != nullptr;   // every tap is served by the diagnostic instantiation
     const bool bb = m.nbb > 0;
     if (timed) {
         if (bb) launch_step_d<true, true>(m, A, n, shmem, stream);
