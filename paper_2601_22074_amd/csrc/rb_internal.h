@@ -97,6 +97,7 @@ struct DevModel {
     int o_xpos, o_xquat, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
     int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp;
     int o_M, o_H, o_misc, o_piv, o_rowadr, o_bb;
+    int o_btab, o_dtab;    // per-body (6 ints) and per-dof (3 words) constants, copied at start
     int lds_floats;
 };
 

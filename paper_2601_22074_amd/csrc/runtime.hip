@@ -536,11 +536,14 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     auto sec = [&](int nfl) { int r = o; o += (nfl + 3) & ~3; return r; };
     m.o_q = sec(nq); m.o_v = sec(nv); m.o_ctrl = sec(nu); m.o_aws = sec(nv); m.o_mscale = sec(nb);
     m.o_xpos = sec(3 * nb); m.o_xquat = sec(4 * nb); m.o_xmat = sec(9 * nb);
-    m.o_cinert = sec(10 * nb); m.o_crb = sec(10 * nb); m.o_cdof = sec(6 * nv); m.o_cvel = sec(6 * nb);
+    m.o_cinert = sec(10 * nb); m.o_cdof = sec(6 * nv); m.o_cvel = sec(6 * nb);
     m.o_bvec = sec(6 * nb); m.o_bvec2 = sec(6 * nb);
     m.o_tau = sec(nv); m.o_bias = sec(nv); m.o_a0 = sec(nv); m.o_a = sec(nv); m.o_Ma = sec(nv);
     m.o_g = sec(nv); m.o_p = sec(nv); m.o_Mp = sec(nv); m.o_tmp = sec(nv);
-    m.o_M = sec(nM); m.o_H = sec(nM); m.o_misc = sec(16); m.o_piv = o;
+    // composite inertias are dead once M is built, before M's factor is written: they share H
+    m.o_M = sec(nM); m.o_H = sec(std::max(nM, 10 * nb)); m.o_crb = m.o_H;
+    m.o_btab = sec(6 * nb); m.o_dtab = sec(3 * nv);
+    m.o_misc = sec(16); m.o_piv = o;
     layout_tail(m, tmaxd);
     m.ncap = std::min(maxcon, RB_MAX_CON);
     M->blob = dev;

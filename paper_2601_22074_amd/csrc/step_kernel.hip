@@ -250,7 +250,7 @@ DEV void body_motion(const DevModel& m, const BL_t& BL, const DL_t& DL, const fl
 // plus armature; `bm` receives the body motions J_b x and `bf` the body momenta I_b J_b x.
 template <typename BL_t, typename DL_t>
 DEV void spatial_mul(const DevModel& m, const BL_t& BL, const DL_t& DL, const float* cdof, const float* cinert,
-                     const float* x, float* bm, float* bf, float* y, int lane) {
+                     const float* dtab, const float* x, float* bm, float* bf, float* y, int lane) {
     body_motion(m, BL, DL, cdof, x, bm, lane);
     if (lane < m.nbody) {
         float f[6];
@@ -260,11 +260,13 @@ DEV void spatial_mul(const DevModel& m, const BL_t& BL, const DL_t& DL, const fl
     }
     wave_sync();
     if (lane < m.nv) {
+        const float* dt = dtab + 3 * lane;
+        const int b0 = __float_as_int(dt[0]), bs = __float_as_int(dt[1]);
         float F[6] = {0, 0, 0, 0, 0, 0};
-        for (int b = DL.body; b < DL.body + DL.bsize; b++)
+        for (int b = b0; b < b0 + bs; b++)
 #pragma unroll
             for (int c = 0; c < 6; c++) F[c] += bf[6 * b + c];
-        y[lane] = sdot(cdof + 6 * lane, F) + DL.arm * x[lane];
+        y[lane] = sdot(cdof + 6 * lane, F) + dt[2] * x[lane];
     }
     wave_sync();
 }
@@ -275,10 +277,7 @@ template <int MAXD>
 struct DofLane {
     int depth;             // chain length including the dof
     int rowadr;            // start of its row in the packed matrices
-    int body;              // body the dof moves
     int height;            // elimination level: steps to its deepest descendant leaf (-1 off lanes)
-    int bsize;             // bodies in that body's subtree
-    float arm;             // armature
     uint64_t descmask;     // strict descendants
     uint32_t anc[MAXD / 4];   // chain dofs, root first, one byte each
     DEV int ancestor(int t) const { return (int)((anc[t >> 2] >> (8 * (t & 3))) & 0xffu); }
@@ -287,12 +286,20 @@ struct DofLane {
 // Per-lane constants of the body held by the lane (lane b holds body b).
 template <int MAXD>
 struct BodyLane {
-    int parent, jtype, qadr, dadr, level;
     int depth;             // dofs on the chain (0 for static bodies)
-    uint32_t children;     // up to 4 child bodies, one byte each (0xff = none)
     uint64_t chainmask;    // dofs on the chain
     int src;               // the chain's deepest dof, whose lane holds the chain (0 if none)
 };
+
+// Constants used once per substep (tree passes, inertias) stay in LDS tables rather than in
+// registers that would be live through the Newton loop: per body parent, joint type, qpos
+// and dof address, level, packed children; per dof its body, subtree size and armature.
+struct BodyTab { int parent, jtype, qadr, dadr, level; uint32_t children; };
+DEV BodyTab body_tab(const int* bt, int lane, int nb) {
+    if (lane >= nb) return BodyTab{0, -1, 0, 0, -1, 0xffffffffu};
+    const int* e = bt + 6 * lane;
+    return BodyTab{e[0], e[1], e[2], e[3], e[4], (uint32_t)e[5]};
+}
 
 template <int MAXD>
 DEV DofLane<MAXD> load_dof_lane(const DevModel& m, int lane) {
@@ -300,10 +307,7 @@ DEV DofLane<MAXD> load_dof_lane(const DevModel& m, int lane) {
     bool on = lane < m.nv;
     D.depth = on ? m.dof_depth[lane] : 0;
     D.rowadr = on ? m.dof_rowadr[lane] : 0;
-    D.body = on ? m.dof_body[lane] : 0;
     D.height = on ? m.dof_height[lane] : -1;
-    D.bsize = on ? m.body_size[D.body] : 0;
-    D.arm = on ? m.dof_armature[lane] : 0.f;
     D.descmask = on ? m.dof_descmask[lane] : 0ull;
 #pragma unroll
     for (int w = 0; w < MAXD / 4; w++) D.anc[w] = 0u;
@@ -319,12 +323,6 @@ template <int MAXD>
 DEV BodyLane<MAXD> load_body_lane(const DevModel& m, const DofLane<MAXD>& DL, int lane) {
     BodyLane<MAXD> B;
     bool on = lane < m.nbody;
-    B.parent = on ? m.body_parent[lane] : 0;
-    B.jtype = on ? m.body_jtype[lane] : -1;
-    B.qadr = on ? m.body_qadr[lane] : 0;
-    B.dadr = on ? m.body_dadr[lane] : 0;
-    B.level = on ? m.body_level[lane] : -1;
-    B.children = on ? (uint32_t)m.body_children[lane] : 0xffffffffu;
     B.chainmask = on ? m.body_chainmask[lane] : 0ull;
     int ld = on ? m.body_lastdof[lane] : -1;
     // the body's chain is the chain of its deepest dof: that dof lane holds it
@@ -781,6 +779,19 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     const BodyLane<MAXD> BL = load_body_lane<MAXD>(m, DL, lane);
     int* rowadr_l = (int*)(L + m.o_rowadr);
     if (lane < m.nv) rowadr_l[lane] = DL.rowadr;
+    int* btab = (int*)(L + m.o_btab);
+    float* dtab = L + m.o_dtab;
+    if (lane < nb) {
+        int* e = btab + 6 * lane;
+        e[0] = m.body_parent[lane]; e[1] = m.body_jtype[lane]; e[2] = m.body_qadr[lane];
+        e[3] = m.body_dadr[lane]; e[4] = m.body_level[lane]; e[5] = m.body_children[lane];
+    }
+    if (lane < nv) {
+        const int b = m.dof_body[lane];
+        dtab[3 * lane] = __int_as_float(b);
+        dtab[3 * lane + 1] = __int_as_float(m.body_size[b]);
+        dtab[3 * lane + 2] = m.dof_armature[lane];
+    }
     // ---- ingress
     for (int i = lane; i < nq; i += RB_WAVE) q[i] = A.qpos[(size_t)w * nq + i];
     for (int i = lane; i < nv; i += RB_WAVE) {
@@ -794,7 +805,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         xpos[0] = xpos[1] = xpos[2] = 0.f;
         xquat[0] = 1.f; xquat[1] = xquat[2] = xquat[3] = 0.f;
         for (int c = 0; c < 9; c++) xmat[c] = (c % 4 == 0) ? 1.f : 0.f;
-        for (int c = 0; c < 10; c++) cinert[c] = crb[c] = 0.f;
+        for (int c = 0; c < 10; c++) cinert[c] = 0.f;
         for (int c = 0; c < 6; c++) cvel[c] = 0.f;
     }
     uint32_t status = A.W.status[w];
@@ -835,10 +846,11 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         // bodies take their pose from qpos.  Then levels compose x_b = x_p + R_p t_loc,
         // q_b = q_p * q_loc from the root.
         float tl[3] = {0.f, 0.f, 0.f}, ql[4] = {1.f, 0.f, 0.f, 0.f};
+        const BodyTab BK = body_tab(btab, lane, nb);
         if (lane >= 1 && lane < nb) {
             const int b = lane;
-            if (BL.jtype == RB_JNT_FREE) {
-                const int a = BL.qadr;
+            if (BK.jtype == RB_JNT_FREE) {
+                const int a = BK.qadr;
                 tl[0] = q[a]; tl[1] = q[a + 1]; tl[2] = q[a + 2];
                 float nrm = sqrtf(q[a + 3] * q[a + 3] + q[a + 4] * q[a + 4] + q[a + 5] * q[a + 5] + q[a + 6] * q[a + 6]);
                 float inv = 1.0f / nrm;
@@ -848,10 +860,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 const float* pb = m.body_pos + 3 * b;
                 ql[0] = qb[0]; ql[1] = qb[1]; ql[2] = qb[2]; ql[3] = qb[3];
                 tl[0] = pb[0]; tl[1] = pb[1]; tl[2] = pb[2];
-                if (BL.jtype == RB_JNT_HINGE) {
+                if (BK.jtype == RB_JNT_HINGE) {
                     const float* ax = m.body_jaxis + 3 * b;
                     const float* jp = m.body_jpos + 3 * b;
-                    float th = 0.5f * q[BL.qadr];
+                    float th = 0.5f * q[BK.qadr];
                     float sh = sinf(th), ch = cosf(th);
                     float qh[4] = {ch, sh * ax[0], sh * ax[1], sh * ax[2]};
                     float R0[9], R1[9], d0[3], d1[3], q1[4];
@@ -866,11 +878,11 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             }
         }
         for (int lev = 1; lev <= m.nblevel; lev++) {
-            if (BL.level == lev) {
+            if (BK.level == lev) {
                 const int b = lane;
-                const int par = BL.parent;
+                const int par = BK.parent;
                 float x[3], qq[4];
-                if (BL.jtype == RB_JNT_FREE) {
+                if (BK.jtype == RB_JNT_FREE) {
                     x[0] = tl[0]; x[1] = tl[1]; x[2] = tl[2];
                     qq[0] = ql[0]; qq[1] = ql[1]; qq[2] = ql[2]; qq[3] = ql[3];
                 } else {
@@ -918,8 +930,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             I[8] = Ixz - mass * c[0] * c[2];
             I[9] = Iyz - mass * c[1] * c[2];
             for (int k = 0; k < 10; k++) crb[10 * b + k] = I[k];
-            const int jt = BL.jtype;
-            const int da = BL.dadr;
+            const BodyTab BI = body_tab(btab, lane, nb);
+            const int jt = BI.jtype;
+            const int da = BI.dadr;
             float xo[3] = {xpos[3 * b] - O[0], xpos[3 * b + 1] - O[1], xpos[3 * b + 2] - O[2]};
             if (jt == RB_JNT_HINGE) {
                 float u[3], o[3];
@@ -948,13 +961,14 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             bvec[3] = -m.grav[0]; bvec[4] = -m.grav[1]; bvec[5] = -m.grav[2];
         }
         wave_sync();
+        const BodyTab BR = body_tab(btab, lane, nb);
         for (int lev = 1; lev <= m.nblevel; lev++) {
-            if (BL.level == lev) {
+            if (BR.level == lev) {
                 const int b = lane;
-                const int par = BL.parent;
+                const int par = BR.parent;
                 float vb[6], ab[6];
                 for (int c = 0; c < 6; c++) { vb[c] = cvel[6 * par + c]; ab[c] = bvec[6 * par + c]; }
-                const int jt = BL.jtype, da = BL.dadr;
+                const int jt = BR.jtype, da = BR.dadr;
                 int nd = jt == RB_JNT_FREE ? 6 : (jt == RB_JNT_HINGE ? 1 : 0);
                 for (int k = 0; k < nd; k++) {
                     const float* S = cdof + 6 * (da + k);
@@ -982,8 +996,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         }
         wave_sync();
         // ---- backward passes: bias wrenches and composite inertias accumulate to the root
+        const BodyTab BB2 = body_tab(btab, lane, nb);
         for (int lev = m.nblevel - 1; lev >= 1; lev--) {
-            if (BL.level == lev) {
+            if (BB2.level == lev) {
                 const int b = lane;
                 // accumulate in registers: one read and one write of the body's own entries
                 float fw[6], ci[10];
@@ -993,7 +1008,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 for (int k = 0; k < 10; k++) ci[k] = crb[10 * b + k];
 #pragma unroll
                 for (int c = 0; c < 4; c++) {
-                    int ch = (BL.children >> (8 * c)) & 0xff;
+                    int ch = (BB2.children >> (8 * c)) & 0xff;
                     if (ch == 0xff) break;
 #pragma unroll
                     for (int k = 0; k < 6; k++) fw[k] += bvec2[6 * ch + k];
@@ -1010,7 +1025,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         if (lane < nv) {
             const int i = lane;
             const float* S = cdof + 6 * i;
-            const int b = DL.body;
+            const int b = __float_as_int(dtab[3 * i]);
             bias[i] = sdot(S, bvec2 + 6 * b);
             // joint-space inertia row i: M_ij = S_j . (Ic_b S_i) over the chain of i
             float F[6];
@@ -1019,7 +1034,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 #pragma unroll
             for (int t = 0; t < MAXD; t++)
                 if (t < d) Mm[r + t] = sdot(cdof + 6 * DL.ancestor(t), F);
-            Mm[r + d - 1] += DL.arm;
+            Mm[r + d - 1] += dtab[3 * i + 2];
             a0[i] = tau[i] - bias[i];
         }
         wave_sync();
@@ -1203,7 +1218,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             wave_sync();
             // g <- M (aws - a0); bvec keeps the body motions of (aws - a0), and the rows are
             // linear in the motion, so the residuals at aws are those at a0 plus these
-            spatial_mul(m, BL, DL, cdof, cinert, tmp, bvec, bvec2, g, lane);
+            spatial_mul(m, BL, DL, cdof, cinert, dtab, tmp, bvec, bvec2, g, lane);
             float jw[4] = {0, 0, 0, 0};
             float fw = 0.f;
             if (has) {
@@ -1313,7 +1328,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 }
                 RB_STAGE(7);
                 // directional quantities for the line search
-                spatial_mul(m, BL, DL, cdof, cinert, p, bvec, bvec2, Mp, lane);
+                spatial_mul(m, BL, DL, cdof, cinert, dtab, p, bvec, bvec2, Mp, lane);
                 float sr[4] = {0, 0, 0, 0};
                 if (has) rows_of(C, bvec, sr);
                 float pa = 0.f, pb = 0.f;
