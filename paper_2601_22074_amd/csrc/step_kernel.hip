@@ -65,6 +65,12 @@ DEV int wscan_incl(int x, int lane) {
     return x;
 }
 DEV bool finitef(float x) { return __builtin_isfinite(x); }
+// x, opaque to the optimiser at this point: values derived from it are computed where they are
+// used instead of being hoisted out of loops (and then spilled) as loop invariants
+DEV uint32_t opaque(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
 // value of x in lane c (c uniform across the wave)
 DEV float rl(float x, int c) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), c)); }
 
@@ -1316,7 +1322,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 float Hr[MAXD];
 #pragma unroll
                 for (int t = 0; t < MAXD; t++) {
-                    const float h = Mm[DL.rowadr + t] + sdot(cdof + 6 * DL.ancestor(t), F);
+                    const int anc_t = (int)((opaque(DL.anc[t >> 2]) >> (8 * (t & 3))) & 0xffu);
+                    const float h = Mm[DL.rowadr + t] + sdot(cdof + 6 * anc_t, F);
                     Hr[t] = t < DL.depth ? h : 0.f;
                 }
                 RB_STAGE(6);
@@ -1433,27 +1440,30 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 
         }
 
-        // ---- semi-implicit Euler (one lane per joint), committed only if everything is finite
-        bool bad = false;
-        for (int i = lane; i < nv; i += RB_WAVE) bad |= !finitef(acc[i]);
-        float qn[7], vn[6];
-        int jl = lane < m.njnt ? lane : -1;
-        if (jl >= 0) {
-            int jt = m.jnt_type[jl], qa = m.jnt_qadr[jl], da = m.jnt_dadr[jl];
-            float dt = m.dt;
+        // ---- semi-implicit Euler (one lane per joint), committed only if everything is finite.
+        // The joint update is evaluated twice -- once to test, once to write -- rather than
+        // holding the new state in registers across the wave-wide test.
+        const int jl = lane < m.njnt ? lane : -1;
+        auto euler = [&](bool commit) {
+            bool bad = false;
+            if (jl < 0) return bad;
+            const int jt = m.jnt_type[jl], qa = m.jnt_qadr[jl], da = m.jnt_dadr[jl];
+            const float dt = m.dt;
             if (jt == RB_JNT_HINGE) {
-                vn[0] = v[da] + dt * acc[da];
-                qn[0] = q[qa] + dt * vn[0];
-                bad |= !finitef(vn[0]) || !finitef(qn[0]);
+                const float vn = v[da] + dt * acc[da];
+                const float qn = q[qa] + dt * vn;
+                bad = !finitef(vn) || !finitef(qn);
+                if (commit) { v[da] = vn; q[qa] = qn; }
             } else {
+                float vn[6], qn[7];
                 for (int k = 0; k < 6; k++) vn[k] = v[da + k] + dt * acc[da + k];
                 for (int k = 0; k < 3; k++) qn[k] = q[qa + k] + dt * vn[k];
                 float th[3] = {dt * vn[3], dt * vn[4], dt * vn[5]};
                 float ang = sqrtf(dot(th, th));
                 float dq[4] = {1.f, 0.f, 0.f, 0.f};
                 if (ang > 0.f) {
-                    float s = sinf(0.5f * ang) / ang;
-                    dq[0] = cosf(0.5f * ang); dq[1] = th[0] * s; dq[2] = th[1] * s; dq[3] = th[2] * s;
+                    float sn = sinf(0.5f * ang) / ang;
+                    dq[0] = cosf(0.5f * ang); dq[1] = th[0] * sn; dq[2] = th[1] * sn; dq[3] = th[2] * sn;
                 }
                 float qq[4];
                 qmul(q + qa + 3, dq, qq);
@@ -1461,8 +1471,16 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 for (int k = 0; k < 4; k++) qn[3 + k] = qq[k] * inv;
                 for (int k = 0; k < 7; k++) bad |= !finitef(qn[k]);
                 for (int k = 0; k < 6; k++) bad |= !finitef(vn[k]);
+                if (commit) {
+                    for (int k = 0; k < 6; k++) v[da + k] = vn[k];
+                    for (int k = 0; k < 7; k++) q[qa + k] = qn[k];
+                }
             }
-        }
+            return bad;
+        };
+        bool bad = false;
+        for (int i = lane; i < nv; i += RB_WAVE) bad |= !finitef(acc[i]);
+        bad |= euler(false);
         bool anybad = __any(bad);
         wave_sync();
         if (anybad) {
@@ -1471,16 +1489,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             ncon = 0;
             break;
         }
-        if (jl >= 0) {
-            int jt = m.jnt_type[jl], qa = m.jnt_qadr[jl], da = m.jnt_dadr[jl];
-            if (jt == RB_JNT_HINGE) {
-                v[da] = vn[0];
-                q[qa] = qn[0];
-            } else {
-                for (int k = 0; k < 6; k++) v[da + k] = vn[k];
-                for (int k = 0; k < 7; k++) q[qa + k] = qn[k];
-            }
-        }
+        euler(true);
         for (int i = lane; i < nv; i += RB_WAVE) aws[i] = acc[i];
         wave_sync();
         RB_STAGE(9);
