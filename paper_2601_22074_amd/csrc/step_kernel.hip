@@ -834,6 +834,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     status &= ~(uint32_t)(RB_STATUS_ITERCAP | RB_STATUS_CONOVERFLOW);
 
     for (int sub = 0; sub < m.K && !frozen; sub++) {
+        // the lane index, opaque at the top of each substep: per-lane addresses are recomputed
+        // in the substep rather than hoisted out of the loop and spilled
+        const int lane = (int)opaque((uint32_t)threadIdx.x);
         // ---- actuation: tau = kp (ctrl - q) - kd v  (position) or gear * ctrl (motor)
         for (int i = lane; i < nv; i += RB_WAVE) {
             float t = 0.f;
