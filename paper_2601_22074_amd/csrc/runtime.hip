@@ -17,7 +17,8 @@
 #include "rbstep.h"
 
 hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
-                          const DevContactsOut* co, uint32_t* status_out, const DevTaps* taps, hipStream_t stream);
+                          const DevContactsOut* co, uint32_t* status_out, const DevTaps* taps, int waves,
+                          hipStream_t stream);
 hipError_t rb_launch_reset(int nv, const int32_t* ids, int n, const float* qacc_ws, DevWorlds W, int capacity,
                            hipStream_t stream);
 hipError_t rb_launch_fill(float* dst, float value, size_t count, hipStream_t stream);
@@ -114,6 +115,7 @@ struct rb_model {
 struct rb_batch {
     const rb_model* model = nullptr;
     int capacity = 0;
+    int waves = 0;          // resident waves per SIMD of the plain launch: 0 automatic, 3 or 4
     DevWorlds W{};
     DevModel dm;   // model copy with this batch's contact capacity
     void* mem = nullptr;
@@ -659,6 +661,12 @@ int rb_batch_set_params(rb_batch* b, int32_t field, int32_t n, const float* vals
     return rb_batch_set_params_at(b, field, 0, n, vals, stream);
 }
 
+int rb_batch_set_waves(rb_batch* b, int32_t waves) {
+    if (!b || (waves != 0 && waves != 3 && waves != 4)) return fail(RB_EINVAL, "waves must be 0, 3 or 4");
+    b->waves = waves;
+    return RB_OK;
+}
+
 int rb_world_reset(rb_batch* b, const int32_t* ids, int32_t n, const float* qacc_ws, void* stream) {
     if (!b || n < 0 || (n > 0 && !ids)) return fail(RB_EINVAL, "bad arguments to rb_world_reset");
     if (n == 0) return RB_OK;
@@ -676,6 +684,27 @@ int rb_get_state(const rb_batch* b, int32_t n, float* ws, uint32_t* st, void* st
     return e == hipSuccess ? RB_OK : hip_fail(e, "rb_get_state");
 }
 
+// Resident waves per SIMD for a plain launch of n worlds: the batch's setting, or
+// automatically 4 when the model's LDS lets 16 worlds share a compute unit, its code fits the
+// 4-wave instantiation (chain bound <= 16, no box-box pairs) and n is more than one round of
+// the 3-wave kernel; otherwise 3.
+static int plain_waves(const rb_batch* b, int n) {
+    const DevModel& m = b->dm;
+    const bool fits = m.maxd <= 16 && m.nbb == 0;
+    if (b->waves == 3 || !fits) return 3;
+    if (b->waves == 4) return 4;
+    static int ncu = 0, lds_cu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 3;
+        ncu = prop.multiProcessorCount;
+        lds_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+    }
+    const bool lds_ok = (long)m.lds_floats * 4 * 16 <= (long)lds_cu;
+    return lds_ok && n > 12 * ncu ? 4 : 3;
+}
+
 static int step_impl(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* qvel, const rb_contacts* c,
                      uint32_t* status, const DevTaps* taps, void* stream) {
     if (!b) return fail(RB_EINVAL, "null batch");
@@ -691,7 +720,7 @@ static int step_impl(rb_batch* b, int32_t n, const float* ctrl, float* qpos, flo
         co.pos = c->pos; co.frame = c->frame; co.force = c->force;
     }
     hipError_t e = rb_launch_step(b->dm, n, ctrl, qpos, qvel, b->W, c ? &co : nullptr, status, taps,
-                                  (hipStream_t)stream);
+                                  plain_waves(b, n), (hipStream_t)stream);
     return e == hipSuccess ? RB_OK : hip_fail(e, "step launch");
 }
 

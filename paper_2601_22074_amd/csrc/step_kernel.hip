@@ -1551,6 +1551,18 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVE
     world_step<MAXD, TIMED, BB>(m, A, w, lds);
 }
 
+// The same step compiled for 4 resident waves per SIMD (at most 128 registers, more spills):
+// worth it when the model's LDS lets 16 worlds share a CU and the batch is more than one
+// round of the 3-wave kernel -- the last round then has fewer worlds waiting on it.
+template <int MAXD>
+__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_kernel_w4(
+    DevModel m, StepArgs A) {
+    extern __shared__ float lds[];
+    const int w = blockIdx.x;
+    if (w >= A.n) return;
+    world_step<MAXD, false, false>(m, A, w, lds);
+}
+
 // Mixed-model launch: the grid walks an ordered list of (batch, world) items; each batch has
 // its own compiled model and step arguments.  Every world runs exactly the code of the plain
 // launch, so its result does not depend on the schedule or on the other batches.
@@ -1656,7 +1668,8 @@ static void launch_step_d(const DevModel& m, const rbk::StepArgs& A, int n, size
 }
 
 hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
-                          const DevContactsOut* co, uint32_t* status_out, const DevTaps* taps, hipStream_t stream) {
+                          const DevContactsOut* co, uint32_t* status_out, const DevTaps* taps, int waves,
+                          hipStream_t stream) {
     rbk::StepArgs A;
     A.n = n;
     A.ctrl = ctrl;
@@ -1674,6 +1687,11 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     if (timed) {
         if (bb) launch_step_d<true, true>(m, A, n, shmem, stream);
         else launch_step_d<true, false>(m, A, n, shmem, stream);
+    } else if (waves == 4 && !bb && m.maxd <= 16) {
+        if (m.maxd <= 8)
+            hipLaunchKernelGGL((rbk::step_kernel_w4<8>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+        else
+            hipLaunchKernelGGL((rbk::step_kernel_w4<16>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
     } else {
         if (bb) launch_step_d<false, true>(m, A, n, shmem, stream);
         else launch_step_d<false, false>(m, A, n, shmem, stream);

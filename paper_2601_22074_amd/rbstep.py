@@ -30,7 +30,7 @@ _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
 
 EXPORTED = ["rb_last_error", "rb_model_create", "rb_model_destroy", "rb_model_info_get", "rb_batch_create",
-            "rb_batch_destroy", "rb_batch_contact_capacity", "rb_batch_set_params", "rb_batch_set_params_at",
+            "rb_batch_destroy", "rb_batch_contact_capacity", "rb_batch_set_params", "rb_batch_set_params_at", "rb_batch_set_waves",
             "rb_world_reset",
             "rb_get_state", "rb_step", "rb_step_taps", "rb_multi_create", "rb_multi_destroy", "rb_multi_bind",
             "rb_multi_set_schedule", "rb_multi_set_items", "rb_multi_set_occupancy", "rb_multi_step", "rb_multi_graph_capture", "rb_multi_graph_launch"]
@@ -92,6 +92,7 @@ def lib():
         L.rb_batch_contact_capacity.restype = C.c_int32
         L.rb_batch_set_params.argtypes = [vp, C.c_int32, C.c_int32, vp, vp]
         L.rb_batch_set_params_at.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]
+        L.rb_batch_set_waves.argtypes = [vp, C.c_int32]
         L.rb_world_reset.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.rb_get_state.argtypes = [vp, C.c_int32, vp, vp, vp]
         L.rb_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp]
@@ -270,6 +271,10 @@ class Batch:
         shape = (n,) if field == PARAM_FRICTION else (n, self.model.nbody)
         _check(lib().rb_batch_set_params_at(self._h, int(field), int(first), int(n),
                                             _ptr(vals, torch.float32, shape, "vals"), _stream(stream)))
+
+    def set_waves(self, waves: int) -> None:
+        """Resident waves per SIMD of plain launches: 3, 4, or 0 (automatic)."""
+        _check(lib().rb_batch_set_waves(self._h, int(waves)))
 
     def reset(self, ids, qacc_ws=None, stream=None) -> None:
         import torch

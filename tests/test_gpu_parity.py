@@ -222,6 +222,28 @@ def test_newton_iterations_match_oracle(oracle_mod, name):
 
 
 # ------------------------------------------------------------------ system properties
+def test_plain_launch_occupancy_bitwise():
+    """The 3- and 4-wave instantiations of the plain step compute the same bits."""
+    import torch
+    import paper_2601_22074_amd as rb
+    m, q, v, u, fr, ms = _wl("quadruped", 256)
+    out = []
+    for waves in (3, 4):
+        M = rb.Model(m)
+        B = rb.Batch(M, 256)
+        B.set_waves(waves)
+        qt, vt = torch.tensor(q, device="cuda"), torch.tensor(v, device="cuda")
+        ut = torch.tensor(u, device="cuda")
+        for _ in range(20):
+            B.step(ut, qt, vt)
+        torch.cuda.synchronize()
+        out.append((qt.cpu().numpy(), vt.cpu().numpy()))
+        B.close()
+        M.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
 def test_run_twice_bitwise(oracle_mod):
     m, q, v, u, fr, ms = _wl("humanoid", 128)
     a = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, nsteps=5, contacts=True)
