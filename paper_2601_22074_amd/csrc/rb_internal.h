@@ -94,10 +94,9 @@ struct DevModel {
     const float* geom_size;    // [3]
     // LDS layout (offsets in floats from the world's base)
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
-    int o_xpos, o_xquat, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
+    int o_xpos, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
     int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp;
-    int o_M, o_H, o_misc, o_piv, o_rowadr, o_bb;
-    int o_btab, o_dtab;    // per-body (6 ints) and per-dof (3 words) constants, copied at start
+    int o_M, o_H, o_piv, o_rowadr, o_bb;
     int lds_floats;
 };
 

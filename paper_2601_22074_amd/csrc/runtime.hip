@@ -537,15 +537,20 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     int o = 0;
     auto sec = [&](int nfl) { int r = o; o += (nfl + 3) & ~3; return r; };
     m.o_q = sec(nq); m.o_v = sec(nv); m.o_ctrl = sec(nu); m.o_aws = sec(nv); m.o_mscale = sec(nb);
-    m.o_xpos = sec(3 * nb); m.o_xquat = sec(4 * nb); m.o_xmat = sec(9 * nb);
-    m.o_cinert = sec(10 * nb); m.o_cdof = sec(6 * nv); m.o_cvel = sec(6 * nb);
-    m.o_bvec = sec(6 * nb); m.o_bvec2 = sec(6 * nb);
+    m.o_xpos = sec(3 * nb);
+    // sections that are dead at the same time share space (world counts per CU depend on it):
+    // the Newton vectors g, p, Mp, tmp live in the rotation matrices' space (dead from the end
+    // of collision to the next substep's kinematics); the bias pass's body forces in M's
+    // (consumed before M's rows are written); the composite inertias in M's factor's (dead
+    // once M is built, before it is factored)
+    const int r4nv = (nv + 3) & ~3;
+    m.o_xmat = sec(std::max(9 * nb, 4 * r4nv));
+    m.o_g = m.o_xmat; m.o_p = m.o_g + r4nv; m.o_Mp = m.o_p + r4nv; m.o_tmp = m.o_Mp + r4nv;
+    m.o_cinert = sec(10 * nb); m.o_cdof = sec(6 * nv); m.o_cvel = sec(6 * nb); m.o_bvec = sec(6 * nb);
     m.o_tau = sec(nv); m.o_bias = sec(nv); m.o_a0 = sec(nv); m.o_a = sec(nv); m.o_Ma = sec(nv);
-    m.o_g = sec(nv); m.o_p = sec(nv); m.o_Mp = sec(nv); m.o_tmp = sec(nv);
-    // composite inertias are dead once M is built, before M's factor is written: they share H
-    m.o_M = sec(nM); m.o_H = sec(std::max(nM, 10 * nb)); m.o_crb = m.o_H;
-    m.o_btab = sec(6 * nb); m.o_dtab = sec(3 * nv);
-    m.o_misc = sec(16); m.o_piv = o;
+    m.o_M = sec(std::max(nM, 6 * nb)); m.o_bvec2 = m.o_M;
+    m.o_H = sec(std::max(nM, 10 * nb)); m.o_crb = m.o_H;
+    m.o_piv = o;
     layout_tail(m, tmaxd);
     m.ncap = std::min(maxcon, RB_MAX_CON);
     M->blob = dev;

@@ -256,7 +256,7 @@ DEV void body_motion(const DevModel& m, const BL_t& BL, const DL_t& DL, const fl
 // plus armature; `bm` receives the body motions J_b x and `bf` the body momenta I_b J_b x.
 template <typename BL_t, typename DL_t>
 DEV void spatial_mul(const DevModel& m, const BL_t& BL, const DL_t& DL, const float* cdof, const float* cinert,
-                     const float* dtab, const float* x, float* bm, float* bf, float* y, int lane) {
+                     const float* x, float* bm, float* bf, float* y, int lane) {
     body_motion(m, BL, DL, cdof, x, bm, lane);
     if (lane < m.nbody) {
         float f[6];
@@ -266,13 +266,12 @@ DEV void spatial_mul(const DevModel& m, const BL_t& BL, const DL_t& DL, const fl
     }
     wave_sync();
     if (lane < m.nv) {
-        const float* dt = dtab + 3 * lane;
-        const int b0 = __float_as_int(dt[0]), bs = __float_as_int(dt[1]);
+        const int b0 = m.dof_body[lane], bs = m.body_size[b0];
         float F[6] = {0, 0, 0, 0, 0, 0};
         for (int b = b0; b < b0 + bs; b++)
 #pragma unroll
             for (int c = 0; c < 6; c++) F[c] += bf[6 * b + c];
-        y[lane] = sdot(cdof + 6 * lane, F) + dt[2] * x[lane];
+        y[lane] = sdot(cdof + 6 * lane, F) + m.dof_armature[lane] * x[lane];
     }
     wave_sync();
 }
@@ -297,14 +296,14 @@ struct BodyLane {
     int src;               // the chain's deepest dof, whose lane holds the chain (0 if none)
 };
 
-// Constants used once per substep (tree passes, inertias) stay in LDS tables rather than in
-// registers that would be live through the Newton loop: per body parent, joint type, qpos
-// and dof address, level, packed children; per dof its body, subtree size and armature.
+// Constants used once per substep (tree passes, inertias) are read from the model tables in
+// the stage that needs them rather than held in registers through the Newton loop: per body
+// parent, joint type, qpos and dof address, level, packed children.
 struct BodyTab { int parent, jtype, qadr, dadr, level; uint32_t children; };
-DEV BodyTab body_tab(const int* bt, int lane, int nb) {
-    if (lane >= nb) return BodyTab{0, -1, 0, 0, -1, 0xffffffffu};
-    const int* e = bt + 6 * lane;
-    return BodyTab{e[0], e[1], e[2], e[3], e[4], (uint32_t)e[5]};
+DEV BodyTab body_tab(const DevModel& m, int lane) {
+    if (lane >= m.nbody) return BodyTab{0, -1, 0, 0, -1, 0xffffffffu};
+    return BodyTab{m.body_parent[lane], m.body_jtype[lane], m.body_qadr[lane], m.body_dadr[lane],
+                   m.body_level[lane], (uint32_t)m.body_children[lane]};
 }
 
 template <int MAXD>
@@ -758,7 +757,6 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     float* aws = L + m.o_aws;
     float* msc = L + m.o_mscale;
     float* xpos = L + m.o_xpos;
-    float* xquat = L + m.o_xquat;
     float* xmat = L + m.o_xmat;
     float* cinert = L + m.o_cinert;
     float* crb = L + m.o_crb;
@@ -777,7 +775,6 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     float* tmp = L + m.o_tmp;
     float* Mm = L + m.o_M;
     float* H = L + m.o_H;
-    float* misc = L + m.o_misc;
     float* piv = L + m.o_piv;
 
     const int nq = m.nq, nv = m.nv, nu = m.nu, nb = m.nbody;
@@ -785,19 +782,6 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     const BodyLane<MAXD> BL = load_body_lane<MAXD>(m, DL, lane);
     int* rowadr_l = (int*)(L + m.o_rowadr);
     if (lane < m.nv) rowadr_l[lane] = DL.rowadr;
-    int* btab = (int*)(L + m.o_btab);
-    float* dtab = L + m.o_dtab;
-    if (lane < nb) {
-        int* e = btab + 6 * lane;
-        e[0] = m.body_parent[lane]; e[1] = m.body_jtype[lane]; e[2] = m.body_qadr[lane];
-        e[3] = m.body_dadr[lane]; e[4] = m.body_level[lane]; e[5] = m.body_children[lane];
-    }
-    if (lane < nv) {
-        const int b = m.dof_body[lane];
-        dtab[3 * lane] = __int_as_float(b);
-        dtab[3 * lane + 1] = __int_as_float(m.body_size[b]);
-        dtab[3 * lane + 2] = m.dof_armature[lane];
-    }
     // ---- ingress
     for (int i = lane; i < nq; i += RB_WAVE) q[i] = A.qpos[(size_t)w * nq + i];
     for (int i = lane; i < nv; i += RB_WAVE) {
@@ -809,8 +793,6 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     const float mu_world = m.fr_pw ? A.W.friction[w] : 0.0f;
     if (lane == 0) {
         xpos[0] = xpos[1] = xpos[2] = 0.f;
-        xquat[0] = 1.f; xquat[1] = xquat[2] = xquat[3] = 0.f;
-        for (int c = 0; c < 9; c++) xmat[c] = (c % 4 == 0) ? 1.f : 0.f;
         for (int c = 0; c < 10; c++) cinert[c] = 0.f;
         for (int c = 0; c < 6; c++) cvel[c] = 0.f;
     }
@@ -850,14 +832,19 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             tau[i] = t;
         }
         // ---- forward kinematics.  Each body's pose relative to its parent is computed for all
-        // bodies at once: q_loc = quat_b * rot(axis, theta) and t_loc = pos_b + R(quat_b) p - R(q_loc) p
-        // for a hinge anchored at p (the anchor stays put while the child turns about it); free
-        // bodies take their pose from qpos.  Then levels compose x_b = x_p + R_p t_loc,
-        // q_b = q_p * q_loc from the root.
-        float tl[3] = {0.f, 0.f, 0.f}, ql[4] = {1.f, 0.f, 0.f, 0.f};
-        const BodyTab BK = body_tab(btab, lane, nb);
+        // bodies at once: R_loc = R(quat_b * rot(axis, theta)) and t_loc = pos_b + R(quat_b) p -
+        // R_loc p for a hinge anchored at p (the anchor stays put while the child turns about it);
+        // free bodies take their pose from qpos.  Then levels compose x_b = x_p + R_p t_loc,
+        // R_b = R_p R_loc from the root.
+        float tl[3] = {0.f, 0.f, 0.f};
+        float Rl[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+        const BodyTab BK = body_tab(m, lane);
+        // the world's rotation: its space held the Newton vectors of the previous substep
+        if (lane == 0)
+            for (int c = 0; c < 9; c++) xmat[c] = (c % 4 == 0) ? 1.f : 0.f;
         if (lane >= 1 && lane < nb) {
             const int b = lane;
+            float ql[4], d0[3] = {0.f, 0.f, 0.f};
             if (BK.jtype == RB_JNT_FREE) {
                 const int a = BK.qadr;
                 tl[0] = q[a]; tl[1] = q[a + 1]; tl[2] = q[a + 2];
@@ -875,34 +862,38 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     float th = 0.5f * q[BK.qadr];
                     float sh = sinf(th), ch = cosf(th);
                     float qh[4] = {ch, sh * ax[0], sh * ax[1], sh * ax[2]};
-                    float R0[9], R1[9], d0[3], d1[3], q1[4];
+                    float R0[9], q1[4];
                     qmat(ql, R0);
+                    mv(R0, jp, d0);
                     qmul(ql, qh, q1);
                     ql[0] = q1[0]; ql[1] = q1[1]; ql[2] = q1[2]; ql[3] = q1[3];
-                    qmat(ql, R1);
-                    mv(R0, jp, d0);
-                    mv(R1, jp, d1);
-                    tl[0] += d0[0] - d1[0]; tl[1] += d0[1] - d1[1]; tl[2] += d0[2] - d1[2];
                 }
             }
+            qmat(ql, Rl);
+            if (BK.jtype == RB_JNT_HINGE) {
+                const float* jp = m.body_jpos + 3 * b;
+                float d1[3];
+                mv(Rl, jp, d1);
+                tl[0] += d0[0] - d1[0]; tl[1] += d0[1] - d1[1]; tl[2] += d0[2] - d1[2];
+            }
         }
+        wave_sync();
         for (int lev = 1; lev <= m.nblevel; lev++) {
             if (BK.level == lev) {
                 const int b = lane;
                 const int par = BK.parent;
-                float x[3], qq[4];
                 if (BK.jtype == RB_JNT_FREE) {
-                    x[0] = tl[0]; x[1] = tl[1]; x[2] = tl[2];
-                    qq[0] = ql[0]; qq[1] = ql[1]; qq[2] = ql[2]; qq[3] = ql[3];
+                    xpos[3 * b] = tl[0]; xpos[3 * b + 1] = tl[1]; xpos[3 * b + 2] = tl[2];
+#pragma unroll
+                    for (int c = 0; c < 9; c++) xmat[9 * b + c] = Rl[c];
                 } else {
                     float off[3];
                     mv(xmat + 9 * par, tl, off);
-                    x[0] = xpos[3 * par] + off[0]; x[1] = xpos[3 * par + 1] + off[1]; x[2] = xpos[3 * par + 2] + off[2];
-                    qmul(xquat + 4 * par, ql, qq);
+                    xpos[3 * b] = xpos[3 * par] + off[0];
+                    xpos[3 * b + 1] = xpos[3 * par + 1] + off[1];
+                    xpos[3 * b + 2] = xpos[3 * par + 2] + off[2];
+                    mm(xmat + 9 * par, Rl, xmat + 9 * b);
                 }
-                xpos[3 * b] = x[0]; xpos[3 * b + 1] = x[1]; xpos[3 * b + 2] = x[2];
-                xquat[4 * b] = qq[0]; xquat[4 * b + 1] = qq[1]; xquat[4 * b + 2] = qq[2]; xquat[4 * b + 3] = qq[3];
-                qmat(qq, xmat + 9 * b);
             }
             wave_sync();
         }
@@ -939,7 +930,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             I[8] = Ixz - mass * c[0] * c[2];
             I[9] = Iyz - mass * c[1] * c[2];
             for (int k = 0; k < 10; k++) crb[10 * b + k] = I[k];
-            const BodyTab BI = body_tab(btab, lane, nb);
+            const BodyTab BI = body_tab(m, lane);
             const int jt = BI.jtype;
             const int da = BI.dadr;
             float xo[3] = {xpos[3 * b] - O[0], xpos[3 * b + 1] - O[1], xpos[3 * b + 2] - O[2]};
@@ -970,7 +961,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             bvec[3] = -m.grav[0]; bvec[4] = -m.grav[1]; bvec[5] = -m.grav[2];
         }
         wave_sync();
-        const BodyTab BR = body_tab(btab, lane, nb);
+        const BodyTab BR = body_tab(m, lane);
         for (int lev = 1; lev <= m.nblevel; lev++) {
             if (BR.level == lev) {
                 const int b = lane;
@@ -1005,7 +996,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         }
         wave_sync();
         // ---- backward passes: bias wrenches and composite inertias accumulate to the root
-        const BodyTab BB2 = body_tab(btab, lane, nb);
+        const BodyTab BB2 = body_tab(m, lane);
         for (int lev = m.nblevel - 1; lev >= 1; lev--) {
             if (BB2.level == lev) {
                 const int b = lane;
@@ -1031,11 +1022,12 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             }
             wave_sync();
         }
+        if (lane < nv) bias[lane] = sdot(cdof + 6 * lane, bvec2 + 6 * m.dof_body[lane]);
+        wave_sync();   // the body forces share space with M, whose rows are written next
         if (lane < nv) {
             const int i = lane;
             const float* S = cdof + 6 * i;
-            const int b = __float_as_int(dtab[3 * i]);
-            bias[i] = sdot(S, bvec2 + 6 * b);
+            const int b = m.dof_body[i];
             // joint-space inertia row i: M_ij = S_j . (Ic_b S_i) over the chain of i
             float F[6];
             inert_mul(crb + 10 * b, S, F);
@@ -1043,7 +1035,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 #pragma unroll
             for (int t = 0; t < MAXD; t++)
                 if (t < d) Mm[r + t] = sdot(cdof + 6 * DL.ancestor(t), F);
-            Mm[r + d - 1] += dtab[3 * i + 2];
+            Mm[r + d - 1] += m.dof_armature[i];
             a0[i] = tau[i] - bias[i];
         }
         wave_sync();
@@ -1227,7 +1219,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             wave_sync();
             // g <- M (aws - a0); bvec keeps the body motions of (aws - a0), and the rows are
             // linear in the motion, so the residuals at aws are those at a0 plus these
-            spatial_mul(m, BL, DL, cdof, cinert, dtab, tmp, bvec, bvec2, g, lane);
+            spatial_mul(m, BL, DL, cdof, cinert, tmp, bvec, cvel, g, lane);
             float jw[4] = {0, 0, 0, 0};
             float fw = 0.f;
             if (has) {
@@ -1338,7 +1330,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 }
                 RB_STAGE(7);
                 // directional quantities for the line search
-                spatial_mul(m, BL, DL, cdof, cinert, dtab, p, bvec, bvec2, Mp, lane);
+                spatial_mul(m, BL, DL, cdof, cinert, p, bvec, cvel, Mp, lane);
                 float sr[4] = {0, 0, 0, 0};
                 if (has) rows_of(C, bvec, sr);
                 float pa = 0.f, pb = 0.f;
