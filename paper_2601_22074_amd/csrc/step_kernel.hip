@@ -1128,48 +1128,64 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             for (int w2 = 0; w2 < MAXD / 4; w2++) cw[w2] = (uint32_t)__shfl((int)DL.anc[w2], csrc);
 #define CROW(t) rowadr_l[(int)((cw[(t) >> 2] >> (8 * ((t) & 3))) & 0xffu)]
         if (has) {
-            // A_c = J_c M^-1 J_c' from Y = L'^-1 J_c' on the body's chain (positions t < d), the
-            // normal and both tangent columns together so each factor entry is read once
+            // A_c = J_c M^-1 J_c' from Y = L'^-1 J_c' on the body's chain (positions t < d): one
+            // column (normal, t1, t2) at a time, keeping only the normal column (fewer values live
+            // than solving the three together)
             float t2c[3];
             cross(C.n, C.t1, t2c);
-            float Yn[MAXD], Y1[MAXD], Y2[MAXD];
+            auto half_solve = [&](const float* dir, float (&Y)[MAXD]) {
 #pragma unroll
-            for (int t = 0; t < MAXD; t++) {
-                // past the chain the byte is 0, a valid dof: computed and discarded
-                const float* S = cdof + 6 * (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu);
-                float wr[3];
-                cross(S, C.r, wr);
-                const float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
-                const bool on = t < d;
-                Yn[t] = on ? C.sigma * dot(C.n, vp) : 0.f;
-                Y1[t] = on ? C.sigma * dot(C.t1, vp) : 0.f;
-                Y2[t] = on ? C.sigma * dot(t2c, vp) : 0.f;
-            }
+                for (int t = 0; t < MAXD; t++) {
+                    // past the chain the byte is 0, a valid dof: computed and discarded
+                    const float* S = cdof + 6 * (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu);
+                    float wr[3];
+                    cross(S, C.r, wr);
+                    const float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                    Y[t] = t < d ? C.sigma * dot(dir, vp) : 0.f;
+                }
 #pragma unroll
-            for (int tp = MAXD - 1; tp >= 1; tp--) {
-                if (tp < d) {
-                    const int row = CROW(tp);
+                for (int tp = MAXD - 1; tp >= 1; tp--) {
+                    if (tp < d) {
+                        const int row = CROW(tp);
 #pragma unroll
-                    for (int t = 0; t < tp; t++) {
-                        const float h = H[row + t];
-                        Yn[t] -= h * Yn[tp];
-                        Y1[t] -= h * Y1[tp];
-                        Y2[t] -= h * Y2[tp];
+                        for (int t = 0; t < tp; t++) Y[t] -= H[row + t] * Y[tp];
+                    }
+                }
+            };
+            float Z0[MAXD];
+            float A00 = 0, A11 = 0, A22 = 0, A01 = 0, A02 = 0;
+            {
+                float Y[MAXD];
+                half_solve(C.n, Y);
+#pragma unroll
+                for (int t = 0; t < MAXD; t++) {
+                    Z0[t] = 0.f;
+                    if (t < d) {
+                        Z0[t] = Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
+                        A00 += Y[t] * Z0[t];
                     }
                 }
             }
-            float A00 = 0, A11 = 0, A22 = 0, A01 = 0, A02 = 0;
+            {
+                float Y[MAXD];
+                half_solve(C.t1, Y);
 #pragma unroll
-            for (int t = 0; t < MAXD; t++)
-                if (t < d) {
-                    const float id = __builtin_amdgcn_rcpf(H[CROW(t) + t]);
-                    const float zn = Yn[t] * id;
-                    A00 += Yn[t] * zn;
-                    A11 += Y1[t] * Y1[t] * id;
-                    A22 += Y2[t] * Y2[t] * id;
-                    A01 += zn * Y1[t];
-                    A02 += zn * Y2[t];
-                }
+                for (int t = 0; t < MAXD; t++)
+                    if (t < d) {
+                        A11 += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
+                        A01 += Z0[t] * Y[t];
+                    }
+            }
+            {
+                float Y[MAXD];
+                half_solve(t2c, Y);
+#pragma unroll
+                for (int t = 0; t < MAXD; t++)
+                    if (t < d) {
+                        A22 += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
+                        A02 += Z0[t] * Y[t];
+                    }
+            }
             float vrow[4];
             rows_of(C, cvel, vrow);
             float rd = C.dist - margin_c;
