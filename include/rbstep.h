@@ -205,11 +205,12 @@ int rb_multi_set_schedule(rb_multi* plan, int32_t order, int32_t grid, const flo
  * without stopping the device.  RB_EINVAL on an item outside the bound batches. */
 int rb_multi_set_items(rb_multi* plan, const int32_t* host_items, int32_t n, int32_t grid, void* hip_stream);
 
-/* Cap the fused launch at waves_per_simd resident waves per SIMD (1..8) by giving each
- * workgroup enough LDS that no more fit on a compute unit; 0 removes the cap (registers and
- * the models' own LDS then decide).  A schedule knob for the autotuner: fewer resident waves
- * leave each more cache.  RB_EINVAL when the cap would need more LDS than a workgroup may
- * use. */
+/* Resident waves per SIMD of the fused launch: 4 selects the instantiation compiled for 4
+ * (RB_EINVAL unless every model has a chain bound <= 16 and LDS small enough for 16 worlds per
+ * compute unit); 3 the default one; 1 or 2 that one capped by giving each workgroup enough LDS
+ * that no more fit; 0 the automatic choice (4 when the models fit and the work list is more
+ * than one round of 3 waves per SIMD, else 3).  A schedule knob for the autotuner; results do
+ * not depend on it. */
 int rb_multi_set_occupancy(rb_multi* plan, int32_t waves_per_simd);
 
 /* One env step of every scheduled world in one launch on the stream. */

@@ -2,8 +2,8 @@
 
 Given batches with bound step inputs, time each candidate schedule of one env step --
 separate plain launches, or the fused launch under every dispatch order, a few grid sizes
-(one workgroup per world, or a persistent grid of 1x / 2x the resident capacity) and two
-occupancy caps (none, or 2 resident waves per SIMD) -- on cloned state, and keep the fastest.
+(one workgroup per world, or a persistent grid of 1x / 2x the resident capacity) and the
+resident waves per SIMD (automatic, 3, or capped at 2) -- on cloned state, and keep the fastest.
 Decisions are cached in a JSON file keyed by the batch signature (model shapes and world
 counts), so a configuration is tuned once.
 """
@@ -29,7 +29,7 @@ def signature(batches, ns) -> str:
 def candidates(nitems: int, resident: int):
     """(kind, order, grid, waves per SIMD cap) tuples."""
     out = [("separate", None, None, None)]
-    for occ in (0, 2):
+    for occ in (0, 3, 2):
         for order in (rbstep.ORDER_HEAVY_FIRST, rbstep.ORDER_INTERLEAVE, rbstep.ORDER_BATCH):
             out.append(("fused", order, 0, occ))
             for mult in (1, 2):

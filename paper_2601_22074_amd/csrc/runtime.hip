@@ -26,7 +26,7 @@ size_t rb_step_args_size();
 void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
                        const DevContactsOut* co, uint32_t* status_out);
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
-                           bool boxbox, int lds_floats, int grid, hipStream_t stream);
+                           bool boxbox, int lds_floats, int grid, int waves, hipStream_t stream);
 
 namespace {
 
@@ -755,6 +755,7 @@ struct rb_multi {
     bool boxbox = false;
     int items_cap = 0;                         // capacity of d_items
     int lds_pad = 0;                           // extra LDS floats per workgroup (occupancy cap)
+    int occ = 0;                               // requested waves per SIMD (0 automatic)
     // pinned staging ring for rb_multi_set_items (a slot is reused once its copy is done)
     static constexpr int RING = 4;
     int32_t* stage[RING] = {};
@@ -946,10 +947,43 @@ int rb_multi_set_items(rb_multi* p, const int32_t* items, int32_t n, int32_t gri
     return RB_OK;
 }
 
+static void device_cu(int* ncu, int* lds_cu) {
+    static int n = 0, l = 0;
+    if (n == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            n = prop.multiProcessorCount;
+            l = (int)prop.maxSharedMemoryPerMultiProcessor;
+        }
+    }
+    *ncu = n;
+    *lds_cu = l;
+}
+
+// whether the plan's models fit the 4-wave fused kernel (chain bound and LDS)
+static bool multi_fits_w4(const rb_multi* p) {
+    int ncu, lds_cu;
+    device_cu(&ncu, &lds_cu);
+    return p->maxd <= 16 && (long)p->lds_floats * 4 * 16 <= (long)lds_cu;
+}
+
+// waves per SIMD of the fused launch: as requested, or automatically 4 when the models fit and
+// the work list is more than one round of the 3-wave kernel
+static int multi_waves(const rb_multi* p) {
+    if (p->occ == 4) return 4;
+    if (p->occ != 0) return 3;
+    int ncu, lds_cu;
+    device_cu(&ncu, &lds_cu);
+    return multi_fits_w4(p) && p->nitems > 12 * ncu ? 4 : 3;
+}
+
 int rb_multi_set_occupancy(rb_multi* p, int32_t waves_per_simd) {
-    if (!p || waves_per_simd < 0 || waves_per_simd > 8) return fail(RB_EINVAL, "bad arguments to rb_multi_set_occupancy");
+    if (!p || waves_per_simd < 0 || waves_per_simd > 4) return fail(RB_EINVAL, "bad arguments to rb_multi_set_occupancy");
+    if (waves_per_simd == 4 && !multi_fits_w4(p)) return fail(RB_EINVAL, "the plan's models do not fit 4 waves per SIMD");
+    p->occ = waves_per_simd;
     p->lds_pad = 0;
-    if (waves_per_simd > 0) {
+    if (waves_per_simd > 0 && waves_per_simd < 3) {
         // one wave per workgroup, four SIMDs per CU: cap the CU at 4 w workgroups by making
         // each one need more than 1 / (4 w + 1) of the CU's LDS
         int dev = 0;
@@ -970,7 +1004,7 @@ int rb_multi_step(rb_multi* p, void* stream) {
     if (!p) return fail(RB_EINVAL, "null plan");
     if (p->nitems == 0) return RB_OK;
     if (!p->d_items) return fail(RB_ESTATE, "no schedule");
-    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid,
+    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid, multi_waves(p),
                                    (hipStream_t)stream);
     return e == hipSuccess ? RB_OK : hip_fail(e, "rb_multi_step");
 }
@@ -984,7 +1018,7 @@ int rb_multi_graph_capture(rb_multi* p, int32_t nsteps, void* stream) {
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     for (int k = 0; k < nsteps && e == hipSuccess; k++)
-        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid, s);
+        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid, multi_waves(p), s);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

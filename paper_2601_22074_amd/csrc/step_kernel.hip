@@ -1600,9 +1600,7 @@ DEV void world_step_as_plain(const DevModel& m, const StepArgs& A, int w, float*
 }
 
 template <int MAXD, bool BB>
-__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
-    MultiArgs M) {
-    extern __shared__ float lds[];
+DEV void multi_items(const MultiArgs& M, float* lds) {
     for (int it = blockIdx.x; it < M.nitems; it += gridDim.x) {
         const int item = __builtin_amdgcn_readfirstlane(M.items[it]);
         const int b = item >> 24, w = item & 0xffffff;
@@ -1610,6 +1608,22 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVE
         const StepArgs& A = M.args[b];
         if (w < A.n) world_step_as_plain<MAXD, BB>(m, A, w, lds);
     }
+}
+
+template <int MAXD, bool BB>
+__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
+    MultiArgs M) {
+    extern __shared__ float lds[];
+    multi_items<MAXD, BB>(M, lds);
+}
+
+// 4 resident waves per SIMD, for plans whose models all fit that (chain bound <= 16 and LDS
+// small enough for 16 worlds per CU)
+template <int MAXD, bool BB>
+__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void multi_kernel_w4(
+    MultiArgs M) {
+    extern __shared__ float lds[];
+    multi_items<MAXD, BB>(M, lds);
 }
 
 }  // namespace rbk
@@ -1640,18 +1654,21 @@ void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* 
 }
 
 template <int MAXD, bool BB>
-static void launch_multi_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_t stream) {
-    hipLaunchKernelGGL((rbk::multi_kernel<MAXD, BB>), g, dim3(RB_WAVE), shmem, stream, M);
+static void launch_multi_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, bool w4, hipStream_t stream) {
+    if (w4 && MAXD <= 16)
+        hipLaunchKernelGGL((rbk::multi_kernel_w4<(MAXD <= 16 ? MAXD : 16), BB>), g, dim3(RB_WAVE), shmem, stream, M);
+    else
+        hipLaunchKernelGGL((rbk::multi_kernel<MAXD, BB>), g, dim3(RB_WAVE), shmem, stream, M);
 }
 template <bool BB>
-static void launch_multi_b(int maxd, const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_t stream) {
-    if (maxd <= 8) launch_multi_t<8, BB>(M, g, shmem, stream);
-    else if (maxd <= 16) launch_multi_t<16, BB>(M, g, shmem, stream);
-    else launch_multi_t<32, BB>(M, g, shmem, stream);
+static void launch_multi_b(int maxd, const rbk::MultiArgs& M, dim3 g, size_t shmem, bool w4, hipStream_t stream) {
+    if (maxd <= 8) launch_multi_t<8, BB>(M, g, shmem, w4, stream);
+    else if (maxd <= 16) launch_multi_t<16, BB>(M, g, shmem, w4, stream);
+    else launch_multi_t<32, BB>(M, g, shmem, false, stream);
 }
 
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
-                           bool boxbox, int lds_floats, int grid, hipStream_t stream) {
+                           bool boxbox, int lds_floats, int grid, int waves, hipStream_t stream) {
     rbk::MultiArgs M;
     M.models = models;
     M.args = (const rbk::StepArgs*)args;
@@ -1659,8 +1676,8 @@ hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* 
     M.nitems = nitems;
     size_t shmem = (size_t)lds_floats * sizeof(float);
     dim3 g(grid);
-    if (boxbox) launch_multi_b<true>(maxd, M, g, shmem, stream);
-    else launch_multi_b<false>(maxd, M, g, shmem, stream);
+    if (boxbox) launch_multi_b<true>(maxd, M, g, shmem, waves == 4, stream);
+    else launch_multi_b<false>(maxd, M, g, shmem, waves == 4, stream);
     return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ def test_fused_equals_separate(order, grid):
         np.testing.assert_array_equal(s["v"].cpu().numpy(), v)
 
 
-@pytest.mark.parametrize("occ", [1, 2])
+@pytest.mark.parametrize("occ", [1, 2, 4])
 def test_fused_with_occupancy_cap_equals_separate(occ):
     import torch
     import paper_2601_22074_amd as rb
