@@ -367,9 +367,10 @@ def kernel_source_hash():
 
 
 def _is_plain_step(kernel_name):
-    """The untimed plain step kernel (rbk::step_kernel<MAXD, false, BB>)."""
+    """The plain step kernel: rbk::step_kernel<MAXD, false, BB> (3 waves per SIMD) or
+    rbk::step_kernel_w4<MAXD> (4 waves per SIMD), not the diagnostic instantiation."""
     import re
-    return re.match(r"void rbk::step_kernel<\d+, false", kernel_name) is not None
+    return re.match(r"void rbk::step_kernel(<\d+, false|_w4<)", kernel_name) is not None
 
 
 def load_traffic(name, nworlds):
@@ -419,7 +420,7 @@ def summarize_profiles(trace_db, fetch_db, write_db, name, nworlds, calib_mb, co
     fetch_kib = float(np.median(fs)) if fs else float("nan")
     write_kib = float(np.median(ws)) if ws else float("nan")
     bytes_per_launch = (fetch_kib * ffac + write_kib * wfac) * 1024.0
-    d = {"kernel": "step_kernel<16, false, false>", "workload": f"{name} x{nworlds}",
+    d = {"kernel": "plain step kernel (step_kernel_w4<16> for this workload)", "workload": f"{name} x{nworlds}",
          "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
          "calibration": {"kernel": f"elementwise neg of {calib_mb} MiB (reads and writes {calib_mb} MiB)",
                          "fetch_kib": float(np.median(fc)) if fc else None,
