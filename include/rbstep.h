@@ -84,6 +84,9 @@ typedef struct rb_model_info {
     int32_t maxcon;          /* static per-world contact bound of the model */
     int32_t max_depth;       /* longest chain of dofs from the root */
     int32_t lds_bytes;       /* on-chip memory one world uses during a step */
+    int32_t bytes_per_world; /* device memory a batch holds per world slot (warm start,
+                                status, per-world parameters); the caller's state,
+                                control and contact buffers come on top */
     double meaninertia;
 } rb_model_info;
 
@@ -109,6 +112,22 @@ const char* rb_last_error(void);
  * collision pairs other than plane-{sphere, capsule, box} and box-box, pairs whose bodies can both
  * move, more than 64 dofs, 64 collision pairs or a dof chain deeper than 32. */
 int rb_model_create(const rb_model_desc* desc, rb_model** out);
+
+/* The same model as JSON text (NUL-terminated, owned by the caller): an object with
+ *   "opt": {"timestep", "nsubsteps", "gravity": [3], "iterations", "tolerance",
+ *           "solref": [2], "solimp": [5]},
+ *   "bodies": [{"parent", "pos": [3], "quat": [4], "ipos": [3], "iquat": [4], "mass",
+ *               "inertia": [3]}, ...]   (body 0 = world),
+ *   "joints": [{"type": "free" | "hinge", "body", "pos": [3], "axis": [3], "armature"}, ...],
+ *   "geoms": [{"type": "plane" | "sphere" | "capsule" | "box", "body", "pos": [3],
+ *              "quat": [4], "size": [3], "friction", "contype", "conaffinity", "margin"}, ...],
+ *   "actuators": [{"type": "position" | "motor", "joint", "kp", "kd", "gear"}, ...],
+ *   "per_world": {"friction": bool, "mass_scale": bool}   (optional, default false);
+ * other keys are ignored.  Each entry maps to the rb_model_desc field of the same name, in
+ * list order.  Malformed JSON or a missing or mistyped field is RB_EINVAL (with the field
+ * named in rb_last_error) before any device call; the parsed description then goes through
+ * rb_model_create and its validation. */
+int rb_model_create_json(const char* json, rb_model** out);
 void rb_model_destroy(rb_model* model);
 int rb_model_info_get(const rb_model* model, rb_model_info* out);
 

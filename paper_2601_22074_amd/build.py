@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbstep.so")
-SOURCES = ["runtime.hip", "step_kernel.hip", "aux_kernels.hip"]
+SOURCES = ["runtime.hip", "step_kernel.hip", "aux_kernels.hip", "model_json.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=on: multiply-adds are fused only inside one source expression, so every kernel

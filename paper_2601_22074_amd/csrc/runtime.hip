@@ -563,6 +563,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
 
 }  // namespace
 
+int rb_record_error(int code, const char* msg) { return fail(code, msg); }
+
 // ====================================================================================== ABI
 extern "C" {
 
@@ -592,6 +594,8 @@ int rb_model_info_get(const rb_model* m, rb_model_info* out) {
     out->nq = m->nq_; out->nv = m->nv_; out->nu = m->nu_; out->nbody = m->nbody_; out->ngeom = m->ngeom_;
     out->npair = m->dm.npair; out->maxcon = m->maxcon_static; out->max_depth = m->dm.ndlevel;
     out->lds_bytes = m->dm.lds_floats * 4; out->meaninertia = m->meaninertia;
+    // a batch slot: warm start [nv], status, friction, mass scales [nbody] (rb_batch_create)
+    out->bytes_per_world = 4 * (m->nv_ + 2 + m->nbody_);
     return RB_OK;
 }
 

@@ -29,7 +29,7 @@ _ACT = {"position": 0, "motor": 1}
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
 
-EXPORTED = ["rb_last_error", "rb_model_create", "rb_model_destroy", "rb_model_info_get", "rb_batch_create",
+EXPORTED = ["rb_last_error", "rb_model_create", "rb_model_create_json", "rb_model_destroy", "rb_model_info_get", "rb_batch_create",
             "rb_batch_destroy", "rb_batch_contact_capacity", "rb_batch_set_params", "rb_batch_set_params_at", "rb_batch_set_waves",
             "rb_world_reset",
             "rb_get_state", "rb_step", "rb_step_taps", "rb_multi_create", "rb_multi_destroy", "rb_multi_bind",
@@ -63,7 +63,7 @@ class _Desc(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("nq", C.c_int32), ("nv", C.c_int32), ("nu", C.c_int32), ("nbody", C.c_int32),
                 ("ngeom", C.c_int32), ("npair", C.c_int32), ("maxcon", C.c_int32), ("max_depth", C.c_int32),
-                ("lds_bytes", C.c_int32), ("meaninertia", C.c_double)]
+                ("lds_bytes", C.c_int32), ("bytes_per_world", C.c_int32), ("meaninertia", C.c_double)]
 
 
 class _Contacts(C.Structure):
@@ -84,6 +84,7 @@ def lib():
         vp = C.c_void_p
         L.rb_last_error.restype = C.c_char_p
         L.rb_model_create.argtypes = [C.POINTER(_Desc), C.POINTER(vp)]
+        L.rb_model_create_json.argtypes = [C.c_char_p, C.POINTER(vp)]
         L.rb_model_destroy.argtypes = [vp]
         L.rb_model_info_get.argtypes = [vp, C.POINTER(_Info)]
         L.rb_batch_create.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(vp)]
@@ -183,11 +184,17 @@ def marshal_desc(model: dict):
 class Model:
     """A compiled model resident on the current GPU (rb_model_create)."""
 
-    def __init__(self, model: dict):
+    def __init__(self, model: dict | str):
+        """model: a description dict, or JSON text of the same fields (rb_model_create_json)."""
         L = lib()
-        d, keep = marshal_desc(model)
         h = C.c_void_p()
-        _check(L.rb_model_create(C.byref(d), C.byref(h)))
+        if isinstance(model, str):
+            _check(L.rb_model_create_json(model.encode(), C.byref(h)))
+            import json
+            model = json.loads(model)
+        else:
+            d, keep = marshal_desc(model)
+            _check(L.rb_model_create(C.byref(d), C.byref(h)))
         self._h = h
         self.desc = model
         info = _Info()
@@ -195,6 +202,7 @@ class Model:
         self.nq, self.nv, self.nu, self.nbody, self.ngeom = info.nq, info.nv, info.nu, info.nbody, info.ngeom
         self.npair, self.maxcon, self.max_depth, self.lds_bytes = info.npair, info.maxcon, info.max_depth, info.lds_bytes
         self.meaninertia = info.meaninertia
+        self.bytes_per_world = info.bytes_per_world
 
     def close(self):
         if getattr(self, "_h", None):

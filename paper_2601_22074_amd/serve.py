@@ -135,7 +135,7 @@ def bytes_per_world(model: "rbstep.Model", ncap: int) -> int:
     """Device bytes one world holds while served: pool state (qpos, qvel, ctrl, status out),
     the batch's per-world data (warm start, status, friction, mass scales), the result copy,
     and its share of the work list."""
-    return 4 * (2 * model.nq + 2 * model.nv + max(model.nu, 1) + model.nv + 3 + model.nbody + 1)
+    return model.bytes_per_world + 4 * (2 * model.nq + 2 * model.nv + max(model.nu, 1) + 2)
 
 
 class Server:

@@ -66,3 +66,73 @@ def test_invalid_models_rejected(rb, case):
     rc, msg = _create_error(m)
     assert rc == -1, (rc, msg)
     assert msg
+
+
+def _create_json_error(text):
+    from paper_2601_22074_amd import rbstep
+    import ctypes as C
+    h = C.c_void_p()
+    rc = rbstep.lib().rb_model_create_json(text.encode(), C.byref(h))
+    return rc, rbstep.lib().rb_last_error().decode()
+
+
+@pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
+                                  "moving_pair", "actuator_free"])
+def test_json_models_validated_like_descriptions(rb, case):
+    """The JSON entry point hands the same description to the same validation: every invalid
+    model above is rejected with the message the struct entry point gives."""
+    import json
+    m = robots.quadruped()
+    if case == "parent":
+        m["bodies"][3]["parent"] = 5
+    elif case == "mass":
+        m["bodies"][2]["mass"] = 0.0
+    elif case == "triangle":
+        m["bodies"][2]["inertia"] = [1.0, 0.1, 0.1]
+    elif case == "quat":
+        m["bodies"][2]["quat"] = [1.0, 0.1, 0.0, 0.0]
+    elif case == "free_not_root":
+        m["joints"][1]["type"] = "free"
+    elif case == "two_joints":
+        m["joints"].insert(2, dict(m["joints"][1]))
+    elif case == "pair":
+        m["geoms"][0]["type"] = "sphere"; m["geoms"][0]["size"] = [0.1, 0, 0]
+    elif case == "moving_pair":
+        m["geoms"][1]["conaffinity"] = 1
+    elif case == "actuator_free":
+        m["actuators"][0]["joint"] = 0
+    rc_d, msg_d = _create_error(m)
+    rc_j, msg_j = _create_json_error(json.dumps(m))
+    assert (rc_j, msg_j) == (rc_d, msg_d)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda s: s[:-1], "offset"),                                        # truncated
+    (lambda s: s + " x", "trailing"),
+    (lambda s: s.replace('"mass": 6.0', '"mass": "6.0"', 1), "body 1: \"mass\" is not a number"),
+    (lambda s: s.replace('"iquat": [1.0, 0.0, 0.0, 0.0]', '"iquat": [1.0, 0.0, 0.0]', 1), "\"iquat\" is not an array of 4"),
+    (lambda s: s.replace('"type": "hinge"', '"type": "slide"', 1), "unknown type \"slide\""),
+    (lambda s: s.replace('"type": "capsule"', '"type": "mesh"', 1), "unknown type \"mesh\""),
+    (lambda s: s.replace('"contype": 1', '"contype": 1.5', 1), "not an integer"),
+    (lambda s: s.replace('"solimp"', '"solimp_"', 1), "opt: missing \"solimp\""),
+    (lambda s: s.replace('"joints"', '"joint_list"', 1), "model: missing \"joints\""),
+    (lambda s: "[" + s + "]", "not an object"),
+    (lambda s: "", "offset 0"),
+])
+def test_malformed_json_rejected(rb, mutate, needle):
+    import json
+    text = json.dumps(robots.quadruped())
+    bad = mutate(text)
+    assert bad != text
+    rc, msg = _create_json_error(bad)
+    assert rc == -1, (rc, msg)
+    assert needle in msg, msg
+
+
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box"])
+def test_model_files_match_generators(name):
+    """workloads/models/<name>.json holds exactly what the generator builds (float values
+    round-trip through JSON unchanged)."""
+    import json
+    with open(os.path.join(ROOT, "workloads", "models", name + ".json")) as f:
+        assert json.load(f) == json.loads(json.dumps(robots.by_name(name)))

@@ -254,6 +254,23 @@ def test_run_twice_bitwise(oracle_mod):
         np.testing.assert_array_equal(a["contacts"][k], b["contacts"][k])
 
 
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box"])
+def test_json_model_bitwise(name):
+    """A model created from its JSON file (rb_model_create_json) steps exactly like the same
+    model created from the description struct."""
+    import os
+    m, q, v, u, fr, ms = _wl(name, 64)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "workloads", "models", name + ".json")) as f:
+        text = f.read()
+    a = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, nsteps=5, contacts=True)
+    b = gpu_run(text, q, v, u, friction=fr, mass_scale=ms, nsteps=5, contacts=True)
+    for k in ("qpos", "qvel", "qacc_ws", "status"):
+        np.testing.assert_array_equal(a[k], b[k])
+    for k in a["contacts"]:
+        np.testing.assert_array_equal(a["contacts"][k], b["contacts"][k])
+
+
 def test_nan_isolated_and_frozen():
     m, q, v, u, fr, ms = _wl("quadruped", 16)
     clean = gpu_run(m, q, v, u, nsteps=3)

@@ -1,0 +1,24 @@
+"""Write the four workload models (chain3, quadruped, humanoid, arm_box) as JSON files in the
+form rb_model_create_json reads.  The generators in workloads/robots.py are the source; the
+files are for callers that load a model without Python."""
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from workloads import robots  # noqa: E402
+
+NAMES = ("chain3", "quadruped", "humanoid", "arm_box")
+
+
+def main():
+    for name in NAMES:
+        with open(os.path.join(HERE, name + ".json"), "w") as f:
+            json.dump(robots.by_name(name), f, indent=1)
+            f.write("\n")
+
+
+if __name__ == "__main__":
+    main()
