@@ -330,29 +330,49 @@ def hbm_bytes_per_env_step(model, con_last, contacts_on):
 
 
 # ------------------------------------------------------------------ CPU baseline
-def cpu_baseline(W, budget_s=12.0):
-    """The FP64 oracle on the host cores (OpenMP over worlds) over a bounded sample."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W, budget_s=12.0, single_budget_s=3.0):
+    """The FP64 oracle on the host cores (OpenMP over worlds) over a bounded sample, and the
+    same sample on one thread."""
     from oracle import Oracle
     m = W["model"]
     o = Oracle(m)
-    cores = os.cpu_count() or 1
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
     nw = min(len(W["worlds"]), 512 if W["name"] == "humanoid" else 2048)
-    q = W["qpos"][:nw].astype(np.float64)
-    v = W["qvel"][:nw].astype(np.float64)
-    ws = np.zeros_like(v)
-    fr = None if W["friction"] is None else W["friction"][:nw].astype(np.float64)
-    ms = None if W["mass_scale"] is None else W["mass_scale"][:nw].astype(np.float64)
-    st = np.zeros(nw, np.uint32)
-    done = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and done < W["nsteps"]:
-        u = W["ctrl"][done // 20][:nw].astype(np.float64)
-        o.step(u, q, v, ws, fr, ms, st, nthreads=cores)
-        done += 1
-    dt = time.perf_counter() - t0
+
+    def run(threads, budget):
+        q = W["qpos"][:nw].astype(np.float64)
+        v = W["qvel"][:nw].astype(np.float64)
+        ws = np.zeros_like(v)
+        fr = None if W["friction"] is None else W["friction"][:nw].astype(np.float64)
+        ms = None if W["mass_scale"] is None else W["mass_scale"][:nw].astype(np.float64)
+        st = np.zeros(nw, np.uint32)
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget and done < W["nsteps"]:
+            u = W["ctrl"][done // 20][:nw].astype(np.float64)
+            o.step(u, q, v, ws, fr, ms, st, nthreads=threads)
+            done += 1
+        return done, time.perf_counter() - t0
+
+    done, dt = run(cores, budget_s)
+    done1, dt1 = run(1, single_budget_s)
     return {"value": nw * done / dt, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{nw} worlds x {done} env steps of the same workload from the same initial states, "
-                      f"FP64, OpenMP over worlds, {dt:.1f} s"}
+                      f"FP64, OpenMP over worlds, {dt:.1f} s",
+            "single_thread_value": nw * done1 / dt1, "cpu_model": _cpu_model(), "cpu_count": os.cpu_count()}
 
 
 def kernel_source_hash():
@@ -639,6 +659,9 @@ def main():
         "wall_s": wall,
         "kernel_source_hash": kernel_source_hash(),
     }
+    if nw < 4 * 256:
+        out["roofline"]["note"] = (f"{nw} worlds occupy {nw} of the chip's 256 compute units' wave slots once: "
+                                   "the launch is latency-bound and its roofline fraction is not meaningful")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)

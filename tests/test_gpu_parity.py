@@ -135,6 +135,76 @@ def test_ten_step_contact_free(oracle_mod, name):
     assert rel_err(g["qvel"], r["qvel"]) <= RTOL_ROLLOUT
 
 
+def test_chain3_500_steps(oracle_mod):
+    """The chain workload at its size (64 worlds x 500 env steps, contact-free): a single step
+    teacher-forced at every step of the oracle's trajectory matches at the step tolerance; every
+    10-step window started from the oracle's state matches at the rollout tolerance; and the
+    free-running FP32 trajectory's energy drift (semi-implicit Euler does not conserve energy)
+    stays with the oracle's own drift.  Prints the divergence curve of the free runs."""
+    import torch
+    import paper_2601_22074_amd as rb
+    m, q, v, u, fr, ms = _wl("chain3", 64)
+    n, T = 64, 500
+    o = oracle_mod.Oracle(m)
+    M = rb.Model(m)
+    B = rb.Batch(M, n)
+    dev = torch.device("cuda:0")
+    uz = torch.zeros(n, 0, device=dev)
+
+    def gstep(q32, v32, k=1):
+        qt = torch.tensor(q32, device=dev)
+        vt = torch.tensor(v32, device=dev)
+        for _ in range(k):
+            B.step(uz, qt, vt)
+        return qt.cpu().numpy(), vt.cpu().numpy()
+
+    def ostep(q32, v32, k=1):
+        qq = q32.astype(np.float64); vv = v32.astype(np.float64); ws = np.zeros((n, o.nv))
+        for _ in range(k):
+            o.step(np.zeros((n, 0)), qq, vv, ws)
+        return qq, vv
+
+    qq = q.astype(np.float64); vv = v.astype(np.float64); ws = np.zeros((n, o.nv))
+    worst1 = worst10 = 0.0
+    for s in range(T):
+        q32, v32 = qq.astype(np.float32), vv.astype(np.float32)
+        g = gstep(q32, v32)
+        r = ostep(q32, v32)
+        worst1 = max(worst1, rel_err(g[0], r[0]), rel_err(g[1], r[1]))
+        if s % 10 == 0:
+            g = gstep(q32, v32, 10)
+            r = ostep(q32, v32, 10)
+            worst10 = max(worst10, rel_err(g[0], r[0]), rel_err(g[1], r[1]))
+        o.step(np.zeros((n, 0)), qq, vv, ws)
+    assert worst1 <= RTOL_STEP, worst1
+    assert worst10 <= RTOL_ROLLOUT, worst10
+
+    def energies(qs, vs):
+        return np.array([sum(o.energy(qs[w], vs[w])) for w in range(n)])
+
+    qg, vg = q.copy(), v.copy()
+    qo, vo = q.astype(np.float64), v.astype(np.float64)
+    wso = np.zeros((n, o.nv))
+    E0 = energies(qo, vo)
+    Dg = np.zeros(n); Do = np.zeros(n); curve = {}
+    qt = torch.tensor(qg, device=dev); vt = torch.tensor(vg, device=dev)
+    for s in range(1, T + 1):
+        B.step(uz, qt, vt)
+        o.step(np.zeros((n, 0)), qo, vo, wso)
+        qg, vg = qt.cpu().numpy(), vt.cpu().numpy()
+        Dg = np.maximum(Dg, np.abs(energies(qg, vg) - E0))
+        Do = np.maximum(Do, np.abs(energies(qo, vo) - E0))
+        if s in (1, 10, 50, 100, 200, 300, 500):
+            curve[s] = float(np.max(np.abs(qg - qo)))
+    B.close(); M.close()
+    scale = np.maximum(np.abs(E0), 1.0)
+    print("chain3 x64 free-run max |qpos_gpu - qpos_oracle| by step:", curve)
+    print("chain3 x64 energy drift / max(|E0|, 1): gpu median %.3e max %.3e, oracle median %.3e max %.3e"
+          % (np.median(Dg / scale), np.max(Dg / scale), np.median(Do / scale), np.max(Do / scale)))
+    assert curve[10] <= RTOL_ROLLOUT
+    assert np.all(np.abs(Dg - Do) <= 0.02 * Do + 1e-3 * scale), np.max(np.abs(Dg - Do) / (Do + scale))
+
+
 # ------------------------------------------------------------------ contact sets
 @pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box"])
 def test_contact_sets(oracle_mod, name):
