@@ -30,7 +30,8 @@ class _Desc(C.Structure):
                 ("act_kp", _f64p), ("act_kd", _f64p), ("act_gear", _f64p),
                 ("timestep", C.c_double), ("nsubsteps", C.c_int32), ("gravity", C.c_double * 3),
                 ("iterations", C.c_int32), ("tolerance", C.c_double), ("solref", C.c_double * 2),
-                ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32)]
+                ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32),
+                ("jnt_range", _f64p)]
 
 
 class _Info(C.Structure):
@@ -51,7 +52,7 @@ _TAP_FIELDS = [("xpos", "f", "nb3"), ("xquat", "f", "nb4"), ("xmat", "f", "nb9")
                ("dist", "f", "mc"), ("pos", "f", "mc3"), ("frame", "f", "mc9"), ("mu", "f", "mc"),
                ("J", "f", "mrnv"), ("aref", "f", "mr"), ("D", "f", "mr"), ("Ahat", "f", "mr"),
                ("efc_force", "f", "mr"), ("qacc", "f", "nv"), ("cforce", "f", "mc3"),
-               ("niter", "i", "1"), ("cost", "f", "1")]
+               ("niter", "i", "1"), ("cost", "f", "1"), ("nrows", "i", "1")]
 
 
 class _Taps(C.Structure):
@@ -143,6 +144,7 @@ class Oracle:
         d.solref = (C.c_double * 2)(*o["solref"]); d.solimp = (C.c_double * 5)(*o["solimp"])
         d.friction_per_world = int(bool(model["per_world"].get("friction")))
         d.mass_scale_per_world = int(bool(model["per_world"].get("mass_scale")))
+        d.jnt_range = f64([j.get("range", [0.0, 0.0]) for j in Jt] or [0.0, 0.0])
         h = C.c_void_p()
         _check(L.rbo_model_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -183,7 +185,7 @@ class Oracle:
         ms = _d(mass_scale, nb) if mass_scale is not None else None
         _check(lib().rbo_forward(self._h, _f(q), _f(v), _f(u), _f(ws), _f(fr), _f(ms), C.byref(taps)))
         nc = int(bufs["ncon"][0])
-        nr = 4 * nc
+        nr = int(bufs["nrows"][0])
         out = dict(xpos=bufs["xpos"].reshape(nb, 3), xquat=bufs["xquat"].reshape(nb, 4),
                    xmat=bufs["xmat"].reshape(nb, 3, 3), com=bufs["com"].reshape(nb, 3),
                    gpos=bufs["gpos"][:ng * 3].reshape(ng, 3), gmat=bufs["gmat"][:ng * 9].reshape(ng, 3, 3),

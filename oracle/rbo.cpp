@@ -91,6 +91,9 @@ struct Model {
     std::vector<double> bpos, bquat, ipos, iquat, mass, inertia;
     std::vector<int> jtype, jbody, jqadr, jdadr;
     std::vector<double> jpos, jaxis, jarm;
+    std::vector<double> jrange;   // [njnt, 2]
+    std::vector<char> jlimited;   // hinge with lower < upper
+    int nlim = 0;
     std::vector<int> gtype, gbody, gcontype, gconaff;
     std::vector<double> gpos, gquat, gsize, gfric, gmargin;
     std::vector<int> atype, ajoint;
@@ -662,9 +665,25 @@ double impedance(const Model& m, double r) {
     return std::min(std::max(imp, 1e-4), 0.9999);
 }
 
+// Rows of the soft constraints, contacts first (4 pyramid rows each, in contact order), then
+// joint limits in joint order.  A limited hinge whose angle lies below its lower bound (or
+// above its upper bound) contributes one frictionless unilateral row with Jacobian +e_i
+// (-e_i) on its dof and distance q - lower (upper - q); limits use the same solref/solimp as
+// contacts and no margin.
 void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
     int nv = m.nv, nc = (int)d.con.size();
-    d.nrows = 4 * nc;
+    // limit rows: (dof, sign, distance)
+    std::vector<int> ldof;
+    std::vector<double> lsgn, ldist;
+    for (int j = 0; j < m.njnt; j++) {
+        if (!m.jlimited[j]) continue;
+        double q = d.q[m.jqadr[j]];
+        double lo = q - m.jrange[2 * j], hi = m.jrange[2 * j + 1] - q;
+        if (lo < 0) { ldof.push_back(m.jdadr[j]); lsgn.push_back(1.0); ldist.push_back(lo); }
+        if (hi < 0) { ldof.push_back(m.jdadr[j]); lsgn.push_back(-1.0); ldist.push_back(hi); }
+    }
+    const int nl = (int)ldof.size();
+    d.nrows = 4 * nc + nl;
     d.J.assign((size_t)d.nrows * nv, 0.0);
     d.aref.assign(d.nrows, 0.0);
     d.D.assign(d.nrows, 0.0);
@@ -674,6 +693,20 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
     double bcoef = 2.0 / (dmax * tc);
     double kcoef = 1.0 / (dmax * dmax * tc * tc * zeta * zeta);
     std::vector<double> jp1(3 * nv), jr1(3 * nv), jp2(3 * nv), jr2(3 * nv), Jc(3 * nv), x(nv);
+    // reference acceleration and regulariser of row `row` (Jacobian already in place)
+    auto finish_row = [&](int row, double rdist) {
+        const double* Je = &d.J[(size_t)row * nv];
+        double imp = impedance(m, rdist);
+        double vel = 0;
+        for (int k = 0; k < nv; k++) vel += Je[k] * d.v[k];
+        chol_solve(LM, nv, Je, x.data());
+        double A = 0;
+        for (int k = 0; k < nv; k++) A += Je[k] * x[k];
+        d.Ahat[row] = A;
+        d.aref[row] = -bcoef * vel - kcoef * imp * rdist;
+        double R = std::max(1e-15, (1 - imp) / imp * A);
+        d.D[row] = 1.0 / R;
+    };
     for (int ci = 0; ci < nc; ci++) {
         const Contact& c = d.con[ci];
         jacobian(m, d, c.b2, c.pos, jp2.data(), jr2.data());
@@ -685,23 +718,19 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
                 Jc[r * nv + k] = acc;
             }
         double rdist = c.dist - std::max(m.gmargin[c.g1], m.gmargin[c.g2]);
-        double imp = impedance(m, rdist);
         for (int e = 0; e < 4; e++) {
             int row = 4 * ci + e;
             int t = 1 + e / 2;
             double sgn = (e % 2 == 0) ? 1.0 : -1.0;
             double* Je = &d.J[(size_t)row * nv];
             for (int k = 0; k < nv; k++) Je[k] = Jc[k] + sgn * c.mu * Jc[t * nv + k];
-            double vel = 0;
-            for (int k = 0; k < nv; k++) vel += Je[k] * d.v[k];
-            chol_solve(LM, nv, Je, x.data());
-            double A = 0;
-            for (int k = 0; k < nv; k++) A += Je[k] * x[k];
-            d.Ahat[row] = A;
-            d.aref[row] = -bcoef * vel - kcoef * imp * rdist;
-            double R = std::max(1e-15, (1 - imp) / imp * A);
-            d.D[row] = 1.0 / R;
+            finish_row(row, rdist);
         }
+    }
+    for (int l = 0; l < nl; l++) {
+        int row = 4 * nc + l;
+        d.J[(size_t)row * nv + ldof[l]] = lsgn[l];
+        finish_row(row, ldist[l]);
     }
 }
 
@@ -941,6 +970,10 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
         M.jaxis.assign(dsc->jnt_axis, dsc->jnt_axis + 3 * nj);
         M.jarm.assign(dsc->jnt_armature, dsc->jnt_armature + nj);
     }
+    M.jrange.assign(2 * nj, 0.0);
+    if (dsc->jnt_range) M.jrange.assign(dsc->jnt_range, dsc->jnt_range + 2 * nj);
+    M.jlimited.assign(nj, 0);
+    M.nlim = 0;
     M.jqadr.assign(nj, 0); M.jdadr.assign(nj, 0);
     // joints must be listed in body order so dof order follows body order
     int qa = 0, da = 0, lastb = 0;
@@ -955,8 +988,13 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
         if (M.jtype[j] == RBO_JNT_FREE) {
             if (M.parent[b] != 0) return bad("free joint must be on a child of the world");
             qa += 7; da += 6;
+            if (M.jrange[2 * j] != M.jrange[2 * j + 1]) return bad("free joints take no range");
         } else if (M.jtype[j] == RBO_JNT_HINGE) {
             qa += 1; da += 1;
+            const double lo = M.jrange[2 * j], hi = M.jrange[2 * j + 1];
+            if (!(std::isfinite(lo) && std::isfinite(hi)) || lo > hi) return bad("joint range must be finite with lower <= upper");
+            M.jlimited[j] = lo < hi;
+            M.nlim += M.jlimited[j];
             double* ax = &M.jaxis[3 * j];
             double n = std::sqrt(dot3(ax, ax));
             if (!(n > 0)) return bad("zero hinge axis");
@@ -1050,7 +1088,7 @@ int rbo_model_info(const void* mp, rbo_info* out) {
     if (!mp || !out) return fail("null argument");
     const Model& m = *static_cast<const Model*>(mp);
     out->nq = m.nq; out->nv = m.nv; out->nu = m.nu; out->nbody = m.nbody; out->ngeom = m.ngeom;
-    out->maxcon = m.maxcon; out->maxrows = 4 * m.maxcon; out->npair = m.npair;
+    out->maxcon = m.maxcon; out->maxrows = 4 * m.maxcon + m.nlim; out->npair = m.npair;
     out->meaninertia = m.meaninertia;
     return 0;
 }
@@ -1093,6 +1131,7 @@ int rbo_forward(const void* mp, const double* qpos, const double* qvel, const do
     put(t->J, d.J); put(t->aref, d.aref); put(t->D, d.D); put(t->Ahat, d.Ahat); put(t->efc_force, d.efc_force);
     if (t->niter) *t->niter = d.niter;
     if (t->cost) *t->cost = d.cost;
+    if (t->nrows) *t->nrows = d.nrows;
     return 0;
 }
 

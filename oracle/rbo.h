@@ -53,6 +53,9 @@ typedef struct rbo_desc {
     double solref[2];
     double solimp[5];
     int32_t friction_per_world, mass_scale_per_world;
+    /* joint ranges [njnt, 2] (lower, upper), or NULL: a hinge is limited when lower < upper;
+       free joints take no range (both entries equal) */
+    const double* jnt_range;
 } rbo_desc;
 
 typedef struct rbo_info {
@@ -83,6 +86,7 @@ typedef struct rbo_taps {
     double *qacc, *cforce;                      /* [nv] [maxcon,3] */
     int32_t* niter;                             /* [1] Newton iterations run */
     double* cost;                               /* [1] final cost f(qacc) */
+    int32_t* nrows;                             /* [1] constraint rows: 4 per contact, then limits */
 } rbo_taps;
 
 const char* rbo_last_error(void);

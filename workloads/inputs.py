@@ -14,9 +14,11 @@ import numpy as np
 
 from . import robots
 
-WORKLOAD_IDS = {"chain3": 1, "quadruped": 2, "humanoid": 3, "arm_box": 4}
+WORKLOAD_IDS = {"chain3": 1, "quadruped": 2, "humanoid": 3, "arm_box": 4,
+                "chain3_lim": 6, "quadruped_lim": 7, "humanoid_lim": 8}
 CTRL_PERIOD = 20          # env steps between control resamples
-CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3}
+CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3,
+            "chain3_lim": 0.0, "quadruped_lim": 0.3, "humanoid_lim": 0.2}
 
 
 def rng(workload_id: int, world: int, stream: int) -> np.random.Generator:
@@ -49,6 +51,14 @@ def initial_state(model: dict, name: str, worlds, workload_id: int | None = None
         if name == "chain3":
             qpos[i, :] = g.uniform(-math.pi, math.pi, d["nq"])
             qvel[i, :] = g.normal(0.0, 0.5, d["nv"])
+        elif name == "chain3_lim":
+            # inside the +-0.6 rad limits, fast enough to reach them
+            qpos[i, :] = g.uniform(-0.5, 0.5, d["nq"])
+            qvel[i, :] = g.normal(0.0, 2.0, d["nv"])
+        elif name == "quadruped_lim":
+            qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))
+        elif name == "humanoid_lim":
+            qpos[i, hq] = g.uniform(-0.05, 0.05, len(hq))
         elif name == "quadruped":
             qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))
         elif name == "humanoid":

@@ -126,10 +126,14 @@ class ModelBuilder:
         return self.body(name, parent, pos, mass, capsule_inertia(mass, radius, length),
                          ipos=(a + b) / 2.0, iquat=quat_z_to(b - a) if length > 0 else (1, 0, 0, 0), quat=quat)
 
-    def joint(self, body, type_, axis=(0, 0, 1), pos=(0, 0, 0), armature=0.0) -> int:
+    def joint(self, body, type_, axis=(0, 0, 1), pos=(0, 0, 0), armature=0.0, range_=None) -> int:
+        """range_: (lower, upper) angle limits of a hinge, or None for an unlimited joint."""
         bid = body if isinstance(body, int) else self.body_id(body)
-        self.joints.append(dict(type=type_, body=bid, pos=list(map(float, pos)), axis=list(map(float, axis)),
-                                armature=float(armature)))
+        j = dict(type=type_, body=bid, pos=list(map(float, pos)), axis=list(map(float, axis)),
+                 armature=float(armature))
+        if range_ is not None:
+            j["range"] = [float(range_[0]), float(range_[1])]
+        self.joints.append(j)
         return len(self.joints) - 1
 
     def geom(self, body, type_, size, pos=(0, 0, 0), quat=(1, 0, 0, 0), friction=1.0, contype=1, conaffinity=1,
@@ -368,7 +372,34 @@ def free_offset(gravity=(0, 0, -9.81), timestep=0.005) -> dict:
     return mb.build()
 
 
-BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box}
+def with_limits(model: dict, lower: float, upper: float, name: str | None = None) -> dict:
+    """Copy of ``model`` whose hinges are limited to [lower, upper] (radians)."""
+    out = copy.deepcopy(model)
+    for j in out["joints"]:
+        if j["type"] == "hinge":
+            j["range"] = [float(lower), float(upper)]
+    if name:
+        out["name"] = name
+    return out
+
+
+def chain3_lim() -> dict:
+    """chain3 with every hinge limited to +-0.6 rad."""
+    return with_limits(chain3(), -0.6, 0.6, "chain3_lim")
+
+
+def quadruped_lim() -> dict:
+    """quadruped with every hinge limited to +-0.25 rad (the control targets often lie beyond)."""
+    return with_limits(quadruped(), -0.25, 0.25, "quadruped_lim")
+
+
+def humanoid_lim() -> dict:
+    """humanoid with every hinge limited to +-0.15 rad (the control targets often lie beyond)."""
+    return with_limits(humanoid(), -0.15, 0.15, "humanoid_lim")
+
+
+BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
+                "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim}
 
 
 def by_name(name: str) -> dict:
