@@ -37,8 +37,13 @@ WORKLOAD_TEXT = {
                "box-box and box-plane contacts, dt 5 ms x 4 substeps, ctrl N(0,0.2)/20 steps",
     "mix": "mixed batch: chain3 x512 + quadruped x4096 + humanoid x2048 + arm_box x1024 (7680 worlds), "
            "each model's own dt and substeps, contacts returned",
+    "humanoid_lim": "humanoid with every hinge limited to +-0.15 rad (limit rows solved with the contacts), "
+                    "otherwise as humanoid",
+    "quadruped_lim": "quadruped with every hinge limited to +-0.25 rad, otherwise as quadruped",
 }
 MIX = [("chain3", 512), ("quadruped", 4096), ("humanoid", 2048), ("arm_box", 1024)]
+DEFAULT_WORLDS = {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 1024, "humanoid_lim": 8192,
+                  "quadruped_lim": 4096}
 WORKLOAD_TEXT["serve"] = ("serving: Poisson arrivals of rollout requests, model uniform over chain3/quadruped/humanoid/"
                           "arm_box, worlds log-uniform 16-4096, horizon uniform 50-500 env steps, device-side seeded "
                           "inputs, HBM-budget admission, continuous batching in one fused launch per tick")
@@ -350,7 +355,7 @@ def cpu_baseline(W, budget_s=12.0, single_budget_s=3.0):
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     if os.environ.get("OMP_NUM_THREADS", "").isdigit():
         cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
-    nw = min(len(W["worlds"]), 512 if W["name"] == "humanoid" else 2048)
+    nw = min(len(W["worlds"]), 512 if W["name"].startswith("humanoid") else 2048)
 
     def run(threads, budget):
         q = W["qpos"][:nw].astype(np.float64)
@@ -531,7 +536,7 @@ def main():
         return
     if args.summarize:
         wl = args.workload
-        nwd = args.worlds or {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 1024}[wl]
+        nwd = args.worlds or DEFAULT_WORLDS[wl]
         cmds = {"trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace -- "
                          "python bench.py --steps 50 --warmup 5 --no-cpu --stats-worlds 64",
                 "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch -- "
@@ -555,8 +560,7 @@ def main():
     import paper_2601_22074_amd as rb
     from workloads import inputs
 
-    default_worlds = {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 1024}
-    nw = args.worlds or default_worlds[args.workload]
+    nw = args.worlds or DEFAULT_WORLDS[args.workload]
     K, warm = args.steps, args.warmup
     W = inputs.workload(args.workload, nw, warm + K)
     m = W["model"]

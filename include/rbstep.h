@@ -74,6 +74,11 @@ typedef struct rb_model_desc {
     double solref[2];       /* (time constant, damping ratio) */
     double solimp[5];       /* (dmin, dmax, width, midpoint, power) */
     int32_t friction_per_world, mass_scale_per_world;
+    /* joint ranges [njnt, 2] (lower, upper), or NULL for none: a hinge is limited when
+     * lower < upper (finite, lower <= upper required); free joints take no range (equal
+     * entries).  A limited hinge outside its range gets one soft unilateral constraint row
+     * pushing it back, solved with the contacts. */
+    const double* jnt_range;
 } rb_model_desc;
 
 typedef struct rb_model rb_model;
@@ -118,7 +123,8 @@ int rb_model_create(const rb_model_desc* desc, rb_model** out);
  *           "solref": [2], "solimp": [5]},
  *   "bodies": [{"parent", "pos": [3], "quat": [4], "ipos": [3], "iquat": [4], "mass",
  *               "inertia": [3]}, ...]   (body 0 = world),
- *   "joints": [{"type": "free" | "hinge", "body", "pos": [3], "axis": [3], "armature"}, ...],
+ *   "joints": [{"type": "free" | "hinge", "body", "pos": [3], "axis": [3], "armature",
+ *               "range": [2] (optional, hinges only)}, ...],
  *   "geoms": [{"type": "plane" | "sphere" | "capsule" | "box", "body", "pos": [3],
  *              "quat": [4], "size": [3], "friction", "contype", "conaffinity", "margin"}, ...],
  *   "actuators": [{"type": "position" | "motor", "joint", "kp", "kd", "gear"}, ...],
@@ -232,7 +238,8 @@ int rb_multi_set_items(rb_multi* plan, const int32_t* host_items, int32_t n, int
  * not depend on it. */
 int rb_multi_set_occupancy(rb_multi* plan, int32_t waves_per_simd);
 
-/* One env step of every scheduled world in one launch on the stream. */
+/* One env step of every scheduled world in one launch on the stream.  RB_ESTATE until a work
+ * list has been set (rb_multi_set_schedule or rb_multi_set_items); an empty one is a no-op. */
 int rb_multi_step(rb_multi* plan, void* hip_stream);
 
 /* Capture nsteps fused steps into a graph on the (non-default) stream, replacing any earlier

@@ -67,6 +67,10 @@ struct DevModel {
     const int* dlevel_start;   // [ndlevel + 2] CSR of dofs by depth, depths 1..ndlevel
     const int* dlevel_dof;
     const float* dof_armature;
+    const int* dof_limq;       // qpos index of a limited hinge's angle, -1 if the dof is unlimited
+    const float* dof_limlo;    // its lower and upper bounds
+    const float* dof_limhi;
+    int nlim;                  // limited hinges
     const int* act_start;      // [nv + 1] CSR of actuators driving each dof
     const int* act_list;
     const int* act_type;
@@ -95,7 +99,7 @@ struct DevModel {
     // LDS layout (offsets in floats from the world's base)
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
     int o_xpos, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
-    int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp;
+    int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp, o_lD, o_ljar;
     int o_M, o_H, o_piv, o_rowadr, o_bb;
     int lds_floats;
 };

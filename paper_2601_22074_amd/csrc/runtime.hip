@@ -175,14 +175,18 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         jbody[j] = b;
         jq[j] = nq;
         jd[j] = nv;
+        const double rlo = d->jnt_range ? d->jnt_range[2 * j] : 0.0, rhi = d->jnt_range ? d->jnt_range[2 * j + 1] : 0.0;
         if (jtype[j] == RB_JNT_FREE) {
             if (P(b) != 0) return fail(RB_EINVAL, "a free joint must be on a child of the world");
+            if (rlo != rhi) return fail(RB_EINVAL, "free joints take no range");
             nq += 7;
             nv += 6;
         } else if (jtype[j] == RB_JNT_HINGE) {
             const double* ax = d->jnt_axis + 3 * j;
             if (!(std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]) > 0))
                 return fail(RB_EINVAL, "hinge axis is zero");
+            if (!(std::isfinite(rlo) && std::isfinite(rhi)) || rlo > rhi)
+                return fail(RB_EINVAL, "joint range must be finite with lower <= upper");
             nq += 1;
             nv += 1;
         } else {
@@ -473,6 +477,17 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             arm[jd[j]] = d->jnt_armature[j];
         }
     }
+    // joint limits per dof: the hinge's qpos index (-1 when unlimited) and its bounds
+    std::vector<int> limq(nv, -1);
+    std::vector<double> limlo(nv, 0.0), limhi(nv, 0.0);
+    int nlim = 0;
+    for (int j = 0; j < nj && d->jnt_range; j++)
+        if (jtype[j] == RB_JNT_HINGE && d->jnt_range[2 * j] < d->jnt_range[2 * j + 1]) {
+            limq[jd[j]] = jq[j];
+            limlo[jd[j]] = d->jnt_range[2 * j];
+            limhi[jd[j]] = d->jnt_range[2 * j + 1];
+            nlim++;
+        }
     // ---- upload
     Blob B;
     DevModel& m = M->dm;
@@ -499,6 +514,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     I(desc_start, &m.desc_start); I(desc_list, &m.desc_list); I(dl_start, &m.dlevel_start); I(dl_dof, &m.dlevel_dof);
     I(height, &m.dof_height); I(hl_start, &m.hlevel_start); I(hl_dof, &m.hlevel_dof); I(bsize, &m.body_size); I(bchild, &m.body_children);
     F(arm, &m.dof_armature);
+    I(limq, &m.dof_limq); F(limlo, &m.dof_limlo); F(limhi, &m.dof_limhi);
     I(act_start, &m.act_start); I(act_list, &m.act_list); I(atype, &m.act_type); I(aqadr, &m.act_qadr);
     F(akp, &m.act_kp); F(akd, &m.act_kd); F(agear, &m.act_gear);
     I(jtype, &m.jnt_type); I(jq, &m.jnt_qadr); I(jd, &m.jnt_dadr);
@@ -526,6 +542,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.nbody = nb; m.nv = nv; m.nq = nq; m.nu = nu; m.njnt = nj; m.npair = npair; m.nbb = nbb;
     m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.nhlevel = nhlevel; m.maxpiv = maxpiv; m.K = d->nsubsteps; m.maxiter = d->iterations;
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
+    m.nlim = nlim;
     m.dt = (float)d->timestep;
     for (int i = 0; i < 3; i++) m.grav[i] = (float)d->gravity[i];
     m.tol_scale = (float)(d->tolerance * meaninertia * nv);
@@ -539,13 +556,15 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.o_q = sec(nq); m.o_v = sec(nv); m.o_ctrl = sec(nu); m.o_aws = sec(nv); m.o_mscale = sec(nb);
     m.o_xpos = sec(3 * nb);
     // sections that are dead at the same time share space (world counts per CU depend on it):
-    // the Newton vectors g, p, Mp, tmp live in the rotation matrices' space (dead from the end
-    // of collision to the next substep's kinematics); the bias pass's body forces in M's
-    // (consumed before M's rows are written); the composite inertias in M's factor's (dead
-    // once M is built, before it is factored)
+    // the Newton vectors g, p, Mp, tmp (and, with joint limits, the limit rows' signed D and
+    // residual) live in the rotation matrices' space (dead from the end of collision to the next
+    // substep's kinematics); the bias pass's body forces in M's (consumed before M's rows are
+    // written); the composite inertias in M's factor's (dead once M is built, before it is
+    // factored)
     const int r4nv = (nv + 3) & ~3;
-    m.o_xmat = sec(std::max(9 * nb, 4 * r4nv));
+    m.o_xmat = sec(std::max(9 * nb, (nlim > 0 ? 6 : 4) * r4nv));
     m.o_g = m.o_xmat; m.o_p = m.o_g + r4nv; m.o_Mp = m.o_p + r4nv; m.o_tmp = m.o_Mp + r4nv;
+    m.o_lD = m.o_tmp + r4nv; m.o_ljar = m.o_lD + r4nv;
     m.o_cinert = sec(10 * nb); m.o_cdof = sec(6 * nv); m.o_cvel = sec(6 * nb); m.o_bvec = sec(6 * nb);
     m.o_tau = sec(nv); m.o_bias = sec(nv); m.o_a0 = sec(nv); m.o_a = sec(nv); m.o_Ma = sec(nv);
     m.o_M = sec(std::max(nM, 6 * nb)); m.o_bvec2 = m.o_M;
@@ -695,11 +714,11 @@ int rb_get_state(const rb_batch* b, int32_t n, float* ws, uint32_t* st, void* st
 
 // Resident waves per SIMD for a plain launch of n worlds: the batch's setting, or
 // automatically 4 when the model's LDS lets 16 worlds share a compute unit, its code fits the
-// 4-wave instantiation (chain bound <= 16, no box-box pairs) and n is more than one round of
+// 4-wave instantiation (chain bound <= 16, no box-box pairs or joint limits) and n is more than one round of
 // the 3-wave kernel; otherwise 3.
 static int plain_waves(const rb_batch* b, int n) {
     const DevModel& m = b->dm;
-    const bool fits = m.maxd <= 16 && m.nbb == 0;
+    const bool fits = m.maxd <= 16 && m.nbb == 0 && m.nlim == 0;
     if (b->waves == 3 || !fits) return 3;
     if (b->waves == 4) return 4;
     static int ncu = 0, lds_cu = 0;
@@ -756,7 +775,8 @@ struct rb_multi {
     void* d_args = nullptr;
     int* d_items = nullptr;
     int nitems = 0, grid = 0, maxd = 0, lds_floats = 0;
-    bool boxbox = false;
+    bool boxbox = false;                       // some model needs the extended instantiation
+    bool scheduled = false;                    // a work list was set (possibly empty)
     int items_cap = 0;                         // capacity of d_items
     int lds_pad = 0;                           // extra LDS floats per workgroup (occupancy cap)
     int occ = 0;                               // requested waves per SIMD (0 automatic)
@@ -790,7 +810,7 @@ int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out) {
         p->batches.push_back(batches[i]);
         models[i] = batches[i]->dm;
         p->maxd = std::max(p->maxd, models[i].maxd);
-        p->boxbox = p->boxbox || models[i].nbb > 0;
+        p->boxbox = p->boxbox || models[i].nbb > 0 || models[i].nlim > 0;   // extended code
     }
     // every batch runs in its own model's instantiation, with its own LDS layout
     for (int i = 0; i < nbatch; i++) p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);
@@ -883,6 +903,7 @@ int rb_multi_set_schedule(rb_multi* p, int32_t order, int32_t grid, const float*
     if (p->d_items) (void)hipFree(p->d_items);
     p->d_items = nullptr;
     p->nitems = (int)items.size();
+    p->scheduled = true;
     if (p->nitems > 0) {
         hipError_t e = hipMalloc((void**)&p->d_items, sizeof(int) * items.size());
         if (e == hipSuccess) e = hipMemcpy(p->d_items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice);
@@ -946,6 +967,7 @@ int rb_multi_set_items(rb_multi* p, const int32_t* items, int32_t n, int32_t gri
         p->stage_used[r] = true;
     }
     p->nitems = n;
+    p->scheduled = true;
     p->grid = grid > 0 ? std::min(grid, std::max(n, 1)) : n;
     multi_free_graph(p);
     return RB_OK;
@@ -1006,8 +1028,8 @@ int rb_multi_set_occupancy(rb_multi* p, int32_t waves_per_simd) {
 
 int rb_multi_step(rb_multi* p, void* stream) {
     if (!p) return fail(RB_EINVAL, "null plan");
+    if (!p->scheduled) return fail(RB_ESTATE, "no schedule: set one (rb_multi_set_schedule or rb_multi_set_items) after binding");
     if (p->nitems == 0) return RB_OK;
-    if (!p->d_items) return fail(RB_ESTATE, "no schedule");
     hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid, multi_waves(p),
                                    (hipStream_t)stream);
     return e == hipSuccess ? RB_OK : hip_fail(e, "rb_multi_step");
@@ -1016,7 +1038,7 @@ int rb_multi_step(rb_multi* p, void* stream) {
 int rb_multi_graph_capture(rb_multi* p, int32_t nsteps, void* stream) {
     if (!p || nsteps <= 0) return fail(RB_EINVAL, "bad arguments to rb_multi_graph_capture");
     if (!stream) return fail(RB_EINVAL, "graph capture needs a non-default stream");
-    if (!p->d_items) return fail(RB_ESTATE, "no schedule");
+    if (!p->scheduled || !p->d_items) return fail(RB_ESTATE, "no schedule");
     multi_free_graph(p);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);

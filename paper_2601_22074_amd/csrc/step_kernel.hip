@@ -743,11 +743,12 @@ struct StepArgs {
 
 // MAXD: longest dof chain the instantiation supports; TIMED: the diagnostic instantiation that
 // serves rb_step_taps (stage taps, work totals and per-stage shader-clock cycles); the plain
-// instantiation carries none of that code.
+// instantiation carries none of that code.  EXT: the extended instantiation, with the code of
+// box-box pairs and joint limits, used for models that have either.
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
-template <int MAXD, bool TIMED, bool BB>
+template <int MAXD, bool TIMED, bool EXT>
 DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* lds) {
     const int lane = threadIdx.x;
     float* L = lds;
@@ -1064,14 +1065,14 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         uint32_t cmask = 0;    // plane pairs: candidates below the margin
         float pos_[3];
         if (lane < m.npair) {
-            if (BB && m.pair_type[lane] == RB_PAIR_BOXBOX) {
+            if (EXT && m.pair_type[lane] == RB_PAIR_BOXBOX) {
                 cnt = box_box(m, L, lane, L + m.o_bb + RB_BB_FLOATS * m.pair_slot[lane]);
             } else {
                 cmask = pair_mask(m, L, lane);
                 cnt = __builtin_popcount(cmask);
             }
         }
-        if (BB) wave_sync();   // box-box blocks written by their pair lanes are read by contact lanes
+        if (EXT) wave_sync();   // box-box blocks written by their pair lanes are read by contact lanes
         int incl = wscan_incl(cnt, lane);
         int total = __shfl(incl, RB_WAVE - 1);
         ncon = total < m.ncap ? total : m.ncap;
@@ -1095,7 +1096,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         float margin_c = 0.f;
         if (has) {
             int j = lane - before, feat;
-            if (BB && m.pair_type[src] == RB_PAIR_BOXBOX) {
+            if (EXT && m.pair_type[src] == RB_PAIR_BOXBOX) {
                 const float* S = L + m.o_bb + RB_BB_FLOATS * m.pair_slot[src];
                 C.dist = S[48 + 5 * j];
                 pos_[0] = S[49 + 5 * j]; pos_[1] = S[50 + 5 * j]; pos_[2] = S[51 + 5 * j];
@@ -1210,10 +1211,56 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         }
         }
 
+        // ---- joint limits: a hinge outside its range gets one row J = s e_i (s = +1 below the
+        // lower bound, -1 above the upper one), held in LDS by the dof's lane: lD = s D (0 when
+        // the hinge is inside its range) and ljar, the residual J a - aref (-aref until the
+        // Newton start).  Only the owning lane ever reads them.
+        float* lD = L + m.o_lD;
+        float* ljar = L + m.o_ljar;
+        bool limact = false;
+        if (EXT && m.nlim > 0) {
+            const int lq = lane < nv ? m.dof_limq[lane] : -1;
+            float dist = 0.f, sgn = 0.f;
+            if (lq >= 0) {
+                const float qa = q[lq];
+                const float dlo = qa - m.dof_limlo[lane], dhi = m.dof_limhi[lane] - qa;
+                if (dlo < 0.f) { dist = dlo; sgn = 1.f; }
+                else if (dhi < 0.f) { dist = dhi; sgn = -1.f; }
+            }
+            limact = __ballot(sgn != 0.f) != 0ull;
+            if (limact && lane < nv) {
+                float Ds = 0.f, nar = 0.f;
+                if (sgn != 0.f) {
+                    // A-hat = (M^-1)_ii = sum_t y_t^2 / D_t with y = L'^-1 e_i on the lane's chain
+                    const int d = DL.depth;
+                    float Y[MAXD];
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++) Y[t] = t == d - 1 ? 1.f : 0.f;
+#pragma unroll
+                    for (int tp = MAXD - 1; tp >= 1; tp--) {
+                        if (tp < d) {
+                            const int row = rowadr_l[DL.ancestor(tp)];
+#pragma unroll
+                            for (int t = 0; t < tp; t++) Y[t] -= H[row + t] * Y[tp];
+                        }
+                    }
+                    float Ah = 0.f;
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++)
+                        if (t < d) Ah += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[rowadr_l[DL.ancestor(t)] + t]);
+                    const float imp = impedance(m, dist);
+                    nar = m.bref * sgn * v[lane] + m.kref * imp * dist;
+                    Ds = sgn / fmaxf(1e-15f, (1.0f - imp) / imp * Ah);
+                }
+                lD[lane] = Ds;
+                ljar[lane] = nar;
+            }
+        }
+
         RB_STAGE(4);
         // ---- primal Newton solve
         bool itercap = false;
-        if (ncon == 0) {
+        if (ncon == 0 && !limact) {
             for (int i = lane; i < nv; i += RB_WAVE) acc[i] = a0[i];
             wave_sync();
         } else {
@@ -1229,6 +1276,17 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     float mn = fminf(j0[e], 0.f);
                     f0 += 0.5f * C.D[e] * mn * mn;
                 }
+            }
+            // limit rows at a0 and at the warm start (their residuals are linear in a too);
+            // recomputed from LDS where needed rather than held across the tree passes
+            auto lim_res = [&](bool at_ws) {
+                const float Ds = lD[lane], sl = Ds > 0.f ? 1.f : (Ds < 0.f ? -1.f : 0.f);
+                const float j0l = sl * a0[lane] + ljar[lane];
+                return at_ws ? j0l + sl * (aws[lane] - a0[lane]) : j0l;
+            };
+            if (limact && lane < nv) {
+                const float mn = fminf(lim_res(false), 0.f);
+                f0 += 0.5f * fabsf(lD[lane]) * mn * mn;
             }
             f0 = wsum(f0);
             for (int i = lane; i < nv; i += RB_WAVE) tmp[i] = aws[i] - a0[i];
@@ -1249,8 +1307,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             }
             float qf = 0.f;
             for (int i = lane; i < nv; i += RB_WAVE) qf += tmp[i] * g[i];
+            if (limact && lane < nv) {
+                const float mn = fminf(lim_res(true), 0.f);
+                fw += 0.5f * fabsf(lD[lane]) * mn * mn;
+            }
             fw = wsum(fw) + 0.5f * wsum(qf);
             bool use_ws = fw < f0;
+            if (limact && lane < nv) ljar[lane] = lim_res(use_ws);
             float fcur = use_ws ? fw : f0;
             for (int i = lane; i < nv; i += RB_WAVE) {
                 acc[i] = use_ws ? aws[i] : a0[i];
@@ -1274,6 +1337,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 #pragma unroll
                     for (int e = 0; e < 4; e++) bits |= (C.jar[e] < 0.f ? 1u : 0u) << e;
                 }
+                if (limact && lane < nv) bits |= (ljar[lane] < 0.f ? 1u : 0u) << 4;
                 if (it > 0 && __ballot(bits != prev_bits) == 0) break;
                 prev_bits = bits;
                 // gradient and the contact part of the Hessian, one contact at a time
@@ -1323,6 +1387,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 float gi = 0.f;
                 if (dof_lane) {
                     gi = Ma[lane] - (tau[lane] - bias[lane]) + gc;
+                    if (limact) {
+                        const float lj = ljar[lane];
+                        if (lj < 0.f) gi += lD[lane] * lj;
+                    }
                     g[lane] = gi;
                 }
                 float gn = sqrtf(wsum(gi * gi));
@@ -1336,6 +1404,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     const int anc_t = (int)((opaque(DL.anc[t >> 2]) >> (8 * (t & 3))) & 0xffu);
                     const float h = Mm[DL.rowadr + t] + sdot(cdof + 6 * anc_t, F);
                     Hr[t] = t < DL.depth ? h : 0.f;
+                }
+                if (limact) {
+                    // the active limit row's term D on the dof's diagonal
+                    const float hl = (dof_lane && ljar[lane] < 0.f) ? fabsf(lD[lane]) : 0.f;
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++)
+                        if (t == DL.depth - 1) Hr[t] += hl;
                 }
                 RB_STAGE(6);
                 {
@@ -1356,6 +1431,11 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 }
                 float A0 = wsum(pa), B0 = wsum(pb);
                 float alpha = 0.f;
+                // the limit row's direction J p, from LDS wherever it is needed
+                auto lim_dir = [&]() {
+                    const float Ds = lD[lane];
+                    return Ds > 0.f ? p[lane] : (Ds < 0.f ? -p[lane] : 0.f);
+                };
                 if (A0 > 0.f) {
                     float bp[4];
 #pragma unroll
@@ -1363,7 +1443,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         bp[e] = (has && sr[e] != 0.f) ? -C.jar[e] * __builtin_amdgcn_rcpf(sr[e]) : INFINITY;
                     }
                     float at = 0.f;
-                    int guard = 4 * ncon + 2;
+                    int guard = 4 * ncon + 2 + (limact ? nv : 0);
                     for (int k = 0; k < guard; k++) {
                         if (TIMED) st_seg++;
                         float sa = 0.f, sb = 0.f, nxt = INFINITY;
@@ -1378,6 +1458,16 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                                 }
                                 if (bp[e] > at) nxt = fminf(nxt, bp[e]);
                             }
+                        }
+                        if (limact && dof_lane) {
+                            const float lj = ljar[lane], Dl = fabsf(lD[lane]), sl = lim_dir();
+                            const float bpl = sl != 0.f ? -lj * __builtin_amdgcn_rcpf(sl) : INFINITY;
+                            const bool act = sl > 0.f ? (at < bpl) : (sl < 0.f ? (at >= bpl) : (lj < 0.f));
+                            if (act) {
+                                sa += Dl * sl * sl;
+                                sb += Dl * sl * lj;
+                            }
+                            if (bpl > at) nxt = fminf(nxt, bpl);
                         }
                         float Aseg = A0 + wsum(sa), Bseg = B0 + wsum(sb);
                         nxt = wmin(nxt);
@@ -1406,6 +1496,12 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         fc += 0.5f * C.D[e] * mn * mn;
                     }
                 }
+                if (limact && dof_lane) {
+                    const float lj = ljar[lane] + alpha * lim_dir();
+                    ljar[lane] = lj;
+                    const float mn = fminf(lj, 0.f);
+                    fc += 0.5f * fabsf(lD[lane]) * mn * mn;
+                }
                 float fnew = 0.5f * wsum(qf2) + wsum(fc);
                 wave_sync();
                 float improvement = fcur - fnew;
@@ -1419,6 +1515,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 int act = 0;
                 if (has)
                     for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f;
+                if (limact && lane < nv) act += ljar[lane] < 0.f;
                 st_rows += (int)wsum((float)act);
             }
         }
@@ -1548,15 +1645,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     }
 }
 
-// One world per 64-lane workgroup.  BB: the model has box-box pairs (kept out of the other
-// instantiations so their register allocation is not shaped by that code).
-template <int MAXD, bool TIMED, bool BB>
+// One world per 64-lane workgroup.  EXT: the model has box-box pairs or joint limits (that code
+// is kept out of the other instantiations so their register allocation is not shaped by it).
+template <int MAXD, bool TIMED, bool EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void step_kernel(
     DevModel m, StepArgs A) {
     extern __shared__ float lds[];
     const int w = blockIdx.x;
     if (w >= A.n) return;
-    world_step<MAXD, TIMED, BB>(m, A, w, lds);
+    world_step<MAXD, TIMED, EXT>(m, A, w, lds);
 }
 
 // The same step compiled for 4 resident waves per SIMD (at most 128 registers, more spills):
@@ -1583,47 +1680,47 @@ struct MultiArgs {
 
 // Each item runs the instantiation the plain launch would use for its model (chain bound and
 // box-box code), so a world computes exactly as in rb_step and small models keep lean code;
-// MAXD and BB bound what the plan's models need.
-template <int MAXD, bool BB>
+// MAXD and EXT bound what the plan's models need.
+template <int MAXD, bool EXT>
 DEV void world_step_as_plain(const DevModel& m, const StepArgs& A, int w, float* lds) {
-    const bool bb = BB && m.nbb > 0;
+    const bool bb = EXT && (m.nbb > 0 || m.nlim > 0);
     if (MAXD >= 32 && m.maxd > 16) {
-        if (bb) world_step<(MAXD >= 32 ? 32 : MAXD), false, BB>(m, A, w, lds);
+        if (bb) world_step<(MAXD >= 32 ? 32 : MAXD), false, EXT>(m, A, w, lds);
         else world_step<(MAXD >= 32 ? 32 : MAXD), false, false>(m, A, w, lds);
     } else if (MAXD >= 16 && m.maxd > 8) {
-        if (bb) world_step<(MAXD >= 16 ? 16 : MAXD), false, BB>(m, A, w, lds);
+        if (bb) world_step<(MAXD >= 16 ? 16 : MAXD), false, EXT>(m, A, w, lds);
         else world_step<(MAXD >= 16 ? 16 : MAXD), false, false>(m, A, w, lds);
     } else {
-        if (bb) world_step<8, false, BB>(m, A, w, lds);
+        if (bb) world_step<8, false, EXT>(m, A, w, lds);
         else world_step<8, false, false>(m, A, w, lds);
     }
 }
 
-template <int MAXD, bool BB>
+template <int MAXD, bool EXT>
 DEV void multi_items(const MultiArgs& M, float* lds) {
     for (int it = blockIdx.x; it < M.nitems; it += gridDim.x) {
         const int item = __builtin_amdgcn_readfirstlane(M.items[it]);
         const int b = item >> 24, w = item & 0xffffff;
         const DevModel& m = M.models[b];
         const StepArgs& A = M.args[b];
-        if (w < A.n) world_step_as_plain<MAXD, BB>(m, A, w, lds);
+        if (w < A.n) world_step_as_plain<MAXD, EXT>(m, A, w, lds);
     }
 }
 
-template <int MAXD, bool BB>
+template <int MAXD, bool EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
     MultiArgs M) {
     extern __shared__ float lds[];
-    multi_items<MAXD, BB>(M, lds);
+    multi_items<MAXD, EXT>(M, lds);
 }
 
 // 4 resident waves per SIMD, for plans whose models all fit that (chain bound <= 16 and LDS
 // small enough for 16 worlds per CU)
-template <int MAXD, bool BB>
+template <int MAXD, bool EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void multi_kernel_w4(
     MultiArgs M) {
     extern __shared__ float lds[];
-    multi_items<MAXD, BB>(M, lds);
+    multi_items<MAXD, EXT>(M, lds);
 }
 
 }  // namespace rbk
@@ -1653,18 +1750,18 @@ void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* 
     *(rbk::StepArgs*)dst = A;
 }
 
-template <int MAXD, bool BB>
+template <int MAXD, bool EXT>
 static void launch_multi_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, bool w4, hipStream_t stream) {
     if (w4 && MAXD <= 16)
-        hipLaunchKernelGGL((rbk::multi_kernel_w4<(MAXD <= 16 ? MAXD : 16), BB>), g, dim3(RB_WAVE), shmem, stream, M);
+        hipLaunchKernelGGL((rbk::multi_kernel_w4<(MAXD <= 16 ? MAXD : 16), EXT>), g, dim3(RB_WAVE), shmem, stream, M);
     else
-        hipLaunchKernelGGL((rbk::multi_kernel<MAXD, BB>), g, dim3(RB_WAVE), shmem, stream, M);
+        hipLaunchKernelGGL((rbk::multi_kernel<MAXD, EXT>), g, dim3(RB_WAVE), shmem, stream, M);
 }
-template <bool BB>
+template <bool EXT>
 static void launch_multi_b(int maxd, const rbk::MultiArgs& M, dim3 g, size_t shmem, bool w4, hipStream_t stream) {
-    if (maxd <= 8) launch_multi_t<8, BB>(M, g, shmem, w4, stream);
-    else if (maxd <= 16) launch_multi_t<16, BB>(M, g, shmem, w4, stream);
-    else launch_multi_t<32, BB>(M, g, shmem, false, stream);
+    if (maxd <= 8) launch_multi_t<8, EXT>(M, g, shmem, w4, stream);
+    else if (maxd <= 16) launch_multi_t<16, EXT>(M, g, shmem, w4, stream);
+    else launch_multi_t<32, EXT>(M, g, shmem, false, stream);
 }
 
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
@@ -1681,15 +1778,15 @@ hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* 
     return hipGetLastError();
 }
 
-template <int MAXD, bool TIMED, bool BB>
+template <int MAXD, bool TIMED, bool EXT>
 static void launch_step_t(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
-    hipLaunchKernelGGL((rbk::step_kernel<MAXD, TIMED, BB>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+    hipLaunchKernelGGL((rbk::step_kernel<MAXD, TIMED, EXT>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
 }
-template <bool TIMED, bool BB>
+template <bool TIMED, bool EXT>
 static void launch_step_d(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
-    if (m.maxd <= 8) launch_step_t<8, TIMED, BB>(m, A, n, shmem, stream);
-    else if (m.maxd <= 16) launch_step_t<16, TIMED, BB>(m, A, n, shmem, stream);
-    else launch_step_t<32, TIMED, BB>(m, A, n, shmem, stream);
+    if (m.maxd <= 8) launch_step_t<8, TIMED, EXT>(m, A, n, shmem, stream);
+    else if (m.maxd <= 16) launch_step_t<16, TIMED, EXT>(m, A, n, shmem, stream);
+    else launch_step_t<32, TIMED, EXT>(m, A, n, shmem, stream);
 }
 
 hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
@@ -1708,7 +1805,7 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     if (taps) A.taps = *taps; else A.taps = DevTaps{};
     size_t shmem = (size_t)m.lds_floats * sizeof(float);
     const bool timed = taps != nullptr;   // every tap is served by the diagnostic instantiation
-    const bool bb = m.nbb > 0;
+    const bool bb = m.nbb > 0 || m.nlim > 0;   // the extended instantiation
     if (timed) {
         if (bb) launch_step_d<true, true>(m, A, n, shmem, stream);
         else launch_step_d<true, false>(m, A, n, shmem, stream);

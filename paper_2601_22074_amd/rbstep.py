@@ -57,7 +57,8 @@ class _Desc(C.Structure):
                 ("act_kp", _f64p), ("act_kd", _f64p), ("act_gear", _f64p),
                 ("timestep", C.c_double), ("nsubsteps", C.c_int32), ("gravity", C.c_double * 3),
                 ("iterations", C.c_int32), ("tolerance", C.c_double), ("solref", C.c_double * 2),
-                ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32)]
+                ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32),
+                ("jnt_range", _f64p)]
 
 
 class _Info(C.Structure):
@@ -178,6 +179,7 @@ def marshal_desc(model: dict):
     d.solref = (C.c_double * 2)(*o["solref"]); d.solimp = (C.c_double * 5)(*o["solimp"])
     d.friction_per_world = int(bool(model["per_world"].get("friction")))
     d.mass_scale_per_world = int(bool(model["per_world"].get("mass_scale")))
+    d.jnt_range = f64([j.get("range", [0.0, 0.0]) for j in Jt] or [0.0, 0.0])
     return d, keep
 
 

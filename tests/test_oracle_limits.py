@@ -6,28 +6,8 @@ import math
 import numpy as np
 import pytest
 
+from helpers import lever, lever_rest_angle
 from workloads import robots
-
-DT = 0.002
-
-
-def lever(range_, gravity=(0, 0, -9.81), motor=False, l=0.5, m=2.0, r=0.02):
-    """One hinge about +y at the origin with a mass m on a massless lever of length l along +x
-    (a small solid sphere of radius r).  Positive angles lower the mass."""
-    mb = robots.ModelBuilder("lever", timestep=DT, nsubsteps=1, gravity=list(gravity))
-    b = mb.body("lever", 0, (0, 0, 0), m, robots.sphere_inertia(m, r), ipos=(l, 0, 0))
-    j = mb.joint(b, "hinge", axis=(0, 1, 0), range_=range_)
-    if motor:
-        mb.actuator(j, "motor", gear=1.0)
-    return mb.build()
-
-
-def impedance(r, solimp=(0.9, 0.95, 0.001, 0.5, 2.0)):
-    """The soft-constraint impedance curve (dmin, dmax, width, midpoint, power)."""
-    dmin, dmax, width, mid, p = solimp
-    x = min(abs(r) / width, 1.0)
-    y = x ** p / mid ** (p - 1) if x <= mid else 1 - (1 - x) ** p / (1 - mid) ** (p - 1)
-    return min(max(dmin + y * (dmax - dmin), 1e-4), 0.9999)
 
 
 def settle(o, q, v, steps, ctrl=None):
@@ -47,19 +27,7 @@ def test_lever_rests_at_the_soft_equilibrium(oracle_mod):
     l, mass, r = 0.5, 2.0, 0.02
     o = oracle_mod.Oracle(lever([-1.0, 0.0], l=l, m=mass, r=r))
     q, v = settle(o, 0.0, 0.0, 4000)
-    I = mass * l * l + 0.4 * mass * r * r
-    tc, zeta, dmax = max(0.02, 2 * DT), 1.0, 0.95
-    k = 1.0 / (dmax * dmax * tc * tc * zeta * zeta)
-
-    def resid(d):
-        a0 = mass * 9.81 * l * math.cos(d) / I
-        imp = impedance(d)
-        return k * imp * d - a0 * (1 - imp) / imp
-
-    lo, hi = 0.0, 0.1
-    for _ in range(200):
-        mid = 0.5 * (lo + hi)
-        lo, hi = (mid, hi) if resid(mid) < 0 else (lo, mid)
+    lo = lever_rest_angle(l, mass, r)
     assert abs(v[0]) < 1e-9
     assert q[0] > 0
     assert abs(q[0] - lo) <= 1e-9 * max(lo, 1e-6) + 1e-12, (q[0], lo)

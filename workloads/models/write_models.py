@@ -1,5 +1,5 @@
-"""Write the four workload models (chain3, quadruped, humanoid, arm_box) as JSON files in the
-form rb_model_create_json reads.  The generators in workloads/robots.py are the source; the
+"""Write the workload models (chain3, quadruped, humanoid, arm_box and the joint-limited
+chain3_lim, quadruped_lim, humanoid_lim) as JSON files in the form rb_model_create_json reads.  The generators in workloads/robots.py are the source; the
 files are for callers that load a model without Python."""
 import json
 import os
@@ -10,7 +10,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from workloads import robots  # noqa: E402
 
-NAMES = ("chain3", "quadruped", "humanoid", "arm_box")
+NAMES = ("chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim", "humanoid_lim")
 
 
 def main():
