@@ -392,8 +392,8 @@ def kernel_source_hash():
 
 
 def _is_plain_step(kernel_name):
-    """The plain step kernel: rbk::step_kernel<MAXD, false, BB> (3 waves per SIMD) or
-    rbk::step_kernel_w4<MAXD> (4 waves per SIMD), not the diagnostic instantiation."""
+    """The plain step kernel: rbk::step_kernel<MAXD, false, EXT> (3 waves per SIMD) or
+    rbk::step_kernel_w4<MAXD, EXT> (4 waves per SIMD), not the diagnostic instantiation."""
     import re
     return re.match(r"void rbk::step_kernel(<\d+, false|_w4<)", kernel_name) is not None
 
@@ -511,6 +511,8 @@ def main():
     ap.add_argument("--workload", default="humanoid", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--worlds", type=int, default=None)
     ap.add_argument("--no-contacts", action="store_true", help="do not return contacts")
+    ap.add_argument("--waves", type=int, default=0, choices=(0, 3, 4),
+                    help="resident waves per SIMD of the plain launch (0: automatic)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--stats-worlds", type=int, default=512)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -567,6 +569,7 @@ def main():
     dev = torch.device("cuda:0")
     model = rb.Model(m)
     batch = rb.Batch(model, nw)
+    batch.set_waves(args.waves)
     q = torch.tensor(W["qpos"], device=dev)
     v = torch.tensor(W["qvel"], device=dev)
     ctab = torch.tensor(W["ctrl"], device=dev).contiguous()
@@ -649,7 +652,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "worlds": nw, "env_steps": K,
-                   "substeps": Ksub, "contacts_returned": con is not None},
+                   "substeps": Ksub, "contacts_returned": con is not None, "waves_per_simd": args.waves or "auto"},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_TFLOPS,
                      "traffic": None if traffic is None else traffic,

@@ -157,10 +157,9 @@ int rb_batch_set_params_at(rb_batch* batch, int32_t field, int32_t first, int32_
                            void* hip_stream);
 
 /* Resident waves per SIMD of this batch's plain launches: 3, 4, or 0 for the automatic choice
- * (4 when the model's LDS lets 16 worlds share a compute unit, its chain bound is at most 16,
- * it has no box-box pairs and the launch has more worlds than one round of 3 waves per SIMD
- * holds; 3 otherwise).  4 is ignored where the model does not fit that instantiation.  Results
- * do not depend on it. */
+ * (4 when the model's LDS lets 16 worlds share a compute unit, its chain bound is at most 16
+ * and the launch has more worlds than one round of 3 waves per SIMD holds; 3 otherwise).  4 is
+ * ignored where the chain bound exceeds 16.  Results do not depend on it. */
 int rb_batch_set_waves(rb_batch* batch, int32_t waves);
 
 /* Reset n worlds named by dev_ids [n] (int32, device): clear their status and set their

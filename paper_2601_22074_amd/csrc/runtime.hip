@@ -713,13 +713,11 @@ int rb_get_state(const rb_batch* b, int32_t n, float* ws, uint32_t* st, void* st
 }
 
 // Resident waves per SIMD for a plain launch of n worlds: the batch's setting, or
-// automatically 4 when the model's LDS lets 16 worlds share a compute unit, its code fits the
-// 4-wave instantiation (chain bound <= 16, no box-box pairs or joint limits) and n is more than one round of
-// the 3-wave kernel; otherwise 3.
+// automatically 4 when the model's LDS lets 16 worlds share a compute unit, its chain bound is
+// at most 16 and n is more than one round of the 3-wave kernel; otherwise 3.
 static int plain_waves(const rb_batch* b, int n) {
     const DevModel& m = b->dm;
-    const bool fits = m.maxd <= 16 && m.nbb == 0 && m.nlim == 0;
-    if (b->waves == 3 || !fits) return 3;
+    if (b->waves == 3 || m.maxd > 16) return 3;
     if (b->waves == 4) return 4;
     static int ncu = 0, lds_cu = 0;
     if (ncu == 0) {

@@ -1659,13 +1659,13 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVE
 // The same step compiled for 4 resident waves per SIMD (at most 128 registers, more spills):
 // worth it when the model's LDS lets 16 worlds share a CU and the batch is more than one
 // round of the 3-wave kernel -- the last round then has fewer worlds waiting on it.
-template <int MAXD>
+template <int MAXD, bool EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_kernel_w4(
     DevModel m, StepArgs A) {
     extern __shared__ float lds[];
     const int w = blockIdx.x;
     if (w >= A.n) return;
-    world_step<MAXD, false, false>(m, A, w, lds);
+    world_step<MAXD, false, EXT>(m, A, w, lds);
 }
 
 // Mixed-model launch: the grid walks an ordered list of (batch, world) items; each batch has
@@ -1809,11 +1809,14 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     if (timed) {
         if (bb) launch_step_d<true, true>(m, A, n, shmem, stream);
         else launch_step_d<true, false>(m, A, n, shmem, stream);
-    } else if (waves == 4 && !bb && m.maxd <= 16) {
-        if (m.maxd <= 8)
-            hipLaunchKernelGGL((rbk::step_kernel_w4<8>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-        else
-            hipLaunchKernelGGL((rbk::step_kernel_w4<16>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+    } else if (waves == 4 && m.maxd <= 16) {
+        if (m.maxd <= 8) {
+            if (bb) hipLaunchKernelGGL((rbk::step_kernel_w4<8, true>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            else hipLaunchKernelGGL((rbk::step_kernel_w4<8, false>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+        } else {
+            if (bb) hipLaunchKernelGGL((rbk::step_kernel_w4<16, true>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            else hipLaunchKernelGGL((rbk::step_kernel_w4<16, false>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+        }
     } else {
         if (bb) launch_step_d<false, true>(m, A, n, shmem, stream);
         else launch_step_d<false, false>(m, A, n, shmem, stream);

@@ -300,16 +300,21 @@ def test_newton_iterations_match_oracle(oracle_mod, name):
 
 
 # ------------------------------------------------------------------ system properties
-def test_plain_launch_occupancy_bitwise():
-    """The 3- and 4-wave instantiations of the plain step compute the same bits."""
+@pytest.mark.parametrize("name", ["quadruped", "arm_box", "humanoid_lim"])
+def test_plain_launch_occupancy_bitwise(name):
+    """The 3- and 4-wave instantiations of the plain step (plain and extended code) compute the
+    same bits."""
     import torch
     import paper_2601_22074_amd as rb
-    m, q, v, u, fr, ms = _wl("quadruped", 256)
+    m, q, v, u, fr, ms = _wl(name, 256)
     out = []
     for waves in (3, 4):
         M = rb.Model(m)
         B = rb.Batch(M, 256)
         B.set_waves(waves)
+        if fr is not None:
+            B.set_params(rb.PARAM_FRICTION, torch.tensor(fr, device="cuda"))
+            B.set_params(rb.PARAM_MASS_SCALE, torch.tensor(ms, device="cuda"))
         qt, vt = torch.tensor(q, device="cuda"), torch.tensor(v, device="cuda")
         ut = torch.tensor(u, device="cuda")
         for _ in range(20):
