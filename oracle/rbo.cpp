@@ -401,6 +401,7 @@ int pair_capacity(int t1, int t2) {
     if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_CAPSULE) return 2;
     if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_BOX) return 8;
     if (t1 == RBO_GEOM_BOX && t2 == RBO_GEOM_BOX) return 8;
+    if (t1 == RBO_GEOM_SPHERE && t2 == RBO_GEOM_BOX) return 1;
     return -1;
 }
 
@@ -587,6 +588,46 @@ void box_box(const Model& m, Data& d, int g1, int g2, double margin) {
     }
 }
 
+// Sphere g1 against box g2: the closest point of the box to the sphere's centre c (the centre
+// clamped to the box in the box frame); when c lies inside the box, the nearest face instead
+// (least depth h_i - |p_i|, lowest axis on ties, towards the side of p_i, + at 0).  Signed
+// distance = |c - closest| - r outside, -(depth + r) inside; normal from the sphere towards
+// the box; the contact point lies halfway between the sphere's surface and the box's.
+void sphere_box(const Model& m, Data& d, int g1, int g2, double margin) {
+    const double* c = &d.gx[3 * g1];
+    const double r = m.gsize[3 * g1];
+    const double* x = &d.gx[3 * g2];
+    const double* R = &d.gR[9 * g2];
+    const double* h = &m.gsize[3 * g2];
+    double rel[3] = {c[0] - x[0], c[1] - x[1], c[2] - x[2]}, p[3];
+    for (int i = 0; i < 3; i++) p[i] = R[i] * rel[0] + R[3 + i] * rel[1] + R[6 + i] * rel[2];   // R' rel
+    double q[3];
+    bool inside = true;
+    for (int i = 0; i < 3; i++) {
+        q[i] = std::min(std::max(p[i], -h[i]), h[i]);
+        if (q[i] != p[i]) inside = false;
+    }
+    double nl[3] = {0, 0, 0}, dist;   // nl: box towards sphere, box frame
+    if (!inside) {
+        double df[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+        double len = std::sqrt(dot3(df, df));
+        for (int i = 0; i < 3; i++) nl[i] = df[i] / len;
+        dist = len - r;
+    } else {
+        int k = 0;
+        for (int i = 1; i < 3; i++)
+            if (h[i] - std::fabs(p[i]) < h[k] - std::fabs(p[k])) k = i;
+        nl[k] = p[k] < 0 ? -1.0 : 1.0;
+        dist = -(h[k] - std::fabs(p[k]) + r);
+    }
+    if (!(dist < margin)) return;
+    double nw[3];
+    matvec3(R, nl, nw);
+    double n[3] = {-nw[0], -nw[1], -nw[2]}, pos[3];
+    for (int i = 0; i < 3; i++) pos[i] = c[i] - nw[i] * (r + dist / 2);
+    add_contact(m, d, g1, g2, 0, dist, pos, n);
+}
+
 void collide(const Model& m, Data& d) {
     d.con.clear();
     for (int ga = 0; ga < m.ngeom; ga++)
@@ -598,6 +639,10 @@ void collide(const Model& m, Data& d) {
             double margin = std::max(m.gmargin[g1], m.gmargin[g2]);
             if (t1 == RBO_GEOM_BOX && t2 == RBO_GEOM_BOX) {
                 box_box(m, d, g1, g2, margin);
+                continue;
+            }
+            if (t1 == RBO_GEOM_SPHERE && t2 == RBO_GEOM_BOX) {
+                sphere_box(m, d, g1, g2, margin);
                 continue;
             }
             if (t1 != RBO_GEOM_PLANE) continue;  // other pairs were rejected at creation

@@ -505,3 +505,113 @@ def test_newton_iteration_cap_status(oracle_mod):
     st = np.array([2], np.uint32)        # cleared at the start of the step
     o50.step(np.zeros((1, o50.nu)), q.copy(), v.copy(), np.zeros((1, o50.nv)), status=st)
     assert st[0] == 0
+
+
+# ---------------------------------------------------------------- sphere vs static box
+def _box_ball(ball_pos, box_quat=(1, 0, 0, 0), box_half=(0.3, 0.2, 0.1), box_pos=(0.0, 0.0, 0.1), r=0.05,
+              gravity=(0, 0, -9.81), mass=0.5):
+    """A free ball (radius r) and a static box on the world body."""
+    mb = robots.ModelBuilder("box_ball", timestep=0.005, nsubsteps=1, gravity=list(gravity))
+    mb.geom(0, "box", list(box_half), pos=box_pos, quat=box_quat, contype=0, conaffinity=1)
+    b = mb.body("ball", 0, (0, 0, 1), mass, robots.sphere_inertia(mass, r))
+    mb.joint(b, "free")
+    mb.geom(b, "sphere", [r], contype=1, conaffinity=0)
+    m = mb.build()
+    return m, np.concatenate([ball_pos, [1.0, 0, 0, 0]])
+
+
+def _box_surface_points(box_pos, box_quat, half, n=121):
+    """Dense grid on the box's six faces, world frame (brute-force closest point)."""
+    g = np.linspace(-1, 1, n)
+    A, B = np.meshgrid(g, g)
+    pts = []
+    for ax in range(3):
+        o1, o2 = [i for i in range(3) if i != ax]
+        for sgn in (-1, 1):
+            P = np.zeros((A.size, 3))
+            P[:, ax] = sgn * half[ax]
+            P[:, o1] = A.ravel() * half[o1]
+            P[:, o2] = B.ravel() * half[o2]
+            pts.append(P)
+    P = np.concatenate(pts)
+    return P @ rot(box_quat).T + np.asarray(box_pos)
+
+
+def test_sphere_on_box_face(oracle_mod):
+    """A ball 1e-4 into the top face: one contact, normal from the ball down into the box, the
+    point halfway between the surfaces."""
+    dz = 1e-4
+    m, q = _box_ball([0.1, -0.05, 0.2 + 0.05 - dz])
+    t = oracle_mod.Oracle(m).forward(q, np.zeros(6))
+    assert t["ncon"] == 1 and tuple(t["geom"][0]) == (1, 0)
+    np.testing.assert_allclose(t["frame"][0, 0], [0, 0, -1.0], atol=1e-15)
+    assert abs(t["dist"][0] + dz) < 1e-12
+    np.testing.assert_allclose(t["pos"][0], [0.1, -0.05, 0.2 - dz / 2], atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sphere_box_distance_brute_force(oracle_mod, seed):
+    """Ball near a rotated box (centre outside or inside): the signed distance and contact
+    normal against the closest point of a dense sampling of the box surface (the grid's
+    spacing bounds the difference)."""
+    rng = np.random.default_rng(seed)
+    ax = rng.normal(size=3)
+    quat = robots.quat_axis_angle(ax / np.linalg.norm(ax), rng.uniform(0, np.pi))
+    half = (0.3, 0.2, 0.1)
+    box_pos = (0.0, 0.0, 0.5)
+    r = 0.05
+    # a direction away from the box; place the ball just within the margin band
+    while True:
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        c = np.asarray(box_pos) + d * rng.uniform(0.2, 0.45)
+        P = _box_surface_points(box_pos, quat, half)
+        dist = np.linalg.norm(P - c, axis=1)
+        k = np.argmin(dist)
+        if dist[k] - r < 0.03 and dist[k] > r * 0.5:
+            break
+    mb = robots.ModelBuilder("box_ball", timestep=0.005, nsubsteps=1)
+    mb.geom(0, "box", list(half), pos=box_pos, quat=quat, contype=0, conaffinity=1)
+    b = mb.body("ball", 0, (0, 0, 1), 0.5, robots.sphere_inertia(0.5, r))
+    mb.joint(b, "free")
+    mb.geom(b, "sphere", [r], contype=1, conaffinity=0, margin=0.05)
+    m = mb.build()
+    t = oracle_mod.Oracle(m).forward(np.concatenate([c, [1.0, 0, 0, 0]]), np.zeros(6))
+    assert t["ncon"] == 1
+    spacing = 2 * max(half) / 120
+    inside = np.all(np.abs(rot(quat).T @ (c - np.asarray(box_pos))) <= np.asarray(half))
+    sgn = -1.0 if inside else 1.0        # a centre inside is -(depth to the nearest face) from it
+    assert abs(t["dist"][0] - (sgn * dist[k] - r)) <= spacing
+    n_bf = sgn * (P[k] - c) / dist[k]    # from the ball towards the box
+    assert np.dot(t["frame"][0, 0], n_bf) > 1 - 5 * spacing / dist[k]
+    # the point lies on the segment from the centre along the normal, halfway into the gap
+    np.testing.assert_allclose(t["pos"][0], c + t["frame"][0, 0] * (r + t["dist"][0] / 2), atol=1e-12)
+
+
+def test_sphere_center_inside_box(oracle_mod):
+    """Centre inside the box: the nearest face wins, depth = r + distance to that face."""
+    m, q = _box_ball([0.25, 0.0, 0.12])          # x face 0.05 away, z top 0.08 away
+    t = oracle_mod.Oracle(m).forward(q, np.zeros(6))
+    assert t["ncon"] == 1
+    np.testing.assert_allclose(t["frame"][0, 0], [-1.0, 0, 0], atol=1e-15)
+    assert abs(t["dist"][0] + (0.05 + 0.05)) < 1e-12
+
+
+def test_sphere_box_separated(oracle_mod):
+    m, q = _box_ball([0.0, 0.0, 0.2 + 0.05 + 1e-3])
+    assert oracle_mod.Oracle(m).forward(q, np.zeros(6))["ncon"] == 0
+
+
+def test_ball_rests_on_box(oracle_mod):
+    """Dropped on the box, the ball comes to rest on the face with its contact carrying its
+    weight (normal force = m g, no tangential force)."""
+    o = oracle_mod.Oracle(_box_ball([0.05, 0.02, 0.3])[0])
+    q = np.array([[0.05, 0.02, 0.3, 1.0, 0, 0, 0]]); v = np.zeros((1, 6)); ws = np.zeros((1, 6))
+    for _ in range(600):
+        o.step(np.zeros((1, 0)), q, v, ws)
+    t = o.forward(q[0], v[0], None, ws[0])
+    assert t["ncon"] == 1
+    assert abs(t["cforce"][0, 0] - 0.5 * 9.81) < 1e-6 * 0.5 * 9.81
+    assert np.abs(t["cforce"][0, 1:]).max() < 1e-9
+    assert np.abs(v).max() < 1e-6
+    assert 0.2 + 0.05 - 1e-3 < q[0, 2] < 0.2 + 0.05
