@@ -102,7 +102,8 @@ typedef struct rb_model_info {
 typedef struct rb_contacts {
     int32_t* ncon;     /* [n] */
     int32_t* geom;     /* [n, cap, 2]  (g1, g2), normal points from g1 to g2 */
-    int32_t* feature;  /* [n, cap]     0 sphere; 0/1 capsule -z/+z end; 0..7 box vertex */
+    int32_t* feature;  /* [n, cap]     0 sphere (on a plane or a box); 0/1 capsule -z/+z end;
+                                      0..7 box vertex on a plane; box-box: clipped-point index */
     float* dist;       /* [n, cap]     signed distance, < 0 when penetrating */
     float* pos;        /* [n, cap, 3]  contact point (midway between the surfaces) */
     float* frame;      /* [n, cap, 9]  rows: normal, tangent 1, tangent 2 */
@@ -114,7 +115,7 @@ const char* rb_last_error(void);
 /* Validate and compile a model; uploads its constants to the current HIP device.
  * Rejects (RB_EINVAL): parent >= child, non-positive mass or inertia violating the
  * triangle inequality, non-unit quaternions, misplaced joints, unknown types,
- * collision pairs other than plane-{sphere, capsule, box} and box-box, pairs whose bodies can both
+ * collision pairs other than plane-{sphere, capsule, box}, box-box and sphere-box, pairs whose bodies can both
  * move, more than 64 dofs, 64 collision pairs or a dof chain deeper than 32. */
 int rb_model_create(const rb_model_desc* desc, rb_model** out);
 

@@ -12,7 +12,8 @@
 #define RB_MAX_CON 64
 #define RB_NSTAGE 10              // timed kernel stages in the stats tap
 #define RB_NSTATS (4 + RB_NSTAGE) // stats tap columns per world
-#define RB_PAIR_BOXBOX 16         // pair_type of a box-box pair (other pairs hold g2's geom type)
+#define RB_PAIR_BOXBOX 16         // pair_type of a box-box pair (plane pairs hold g2's geom type)
+#define RB_PAIR_SPHEREBOX 17      // pair_type of a sphere (g1) - box (g2) pair
 #define RB_BB_FLOATS 96           // LDS floats per box-box pair: clip buffers, contacts, normal
 
 struct DevModel {
@@ -71,6 +72,7 @@ struct DevModel {
     const float* dof_limlo;    // its lower and upper bounds
     const float* dof_limhi;
     int nlim;                  // limited hinges
+    int ext;                   // needs the extended code: box-box or sphere-box pairs, joint limits
     const int* act_start;      // [nv + 1] CSR of actuators driving each dof
     const int* act_list;
     const int* act_type;
@@ -82,10 +84,11 @@ struct DevModel {
     const int* jnt_type;
     const int* jnt_qadr;
     const int* jnt_dadr;
-    // collision pairs [npair], in (g1, g2) order; g1 is the plane, or the lower-numbered box
+    // collision pairs [npair], in (g1, g2) order; g1 is the plane, the sphere of a sphere-box
+    // pair, or the lower-numbered box
     const int* pair_g1;
     const int* pair_g2;
-    const int* pair_type;      // geom type of g2 (plane pairs) or RB_PAIR_BOXBOX
+    const int* pair_type;      // geom type of g2 (plane pairs), RB_PAIR_BOXBOX or RB_PAIR_SPHEREBOX
     const int* pair_slot;      // box-box pairs: index of the pair's LDS block; -1 otherwise
     const int* pair_body;      // the body that can move
     const int* pair_cap;       // contacts the pair can produce

@@ -347,8 +347,10 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             if (d->geom_type[g2] < d->geom_type[g1]) std::swap(g1, g2);
             bool plane_pair = d->geom_type[g1] == RB_GEOM_PLANE && d->geom_type[g2] != RB_GEOM_PLANE;
             bool box_pair = d->geom_type[g1] == RB_GEOM_BOX && d->geom_type[g2] == RB_GEOM_BOX;
-            if (!plane_pair && !box_pair)
-                return fail(RB_EINVAL, "unsupported collision pair (only plane vs sphere, capsule, box and box vs box)");
+            bool sphere_box = d->geom_type[g1] == RB_GEOM_SPHERE && d->geom_type[g2] == RB_GEOM_BOX;
+            if (!plane_pair && !box_pair && !sphere_box)
+                return fail(RB_EINVAL,
+                            "unsupported collision pair (only plane vs sphere, capsule, box; box vs box; sphere vs box)");
             pairs.push_back({g1, g2});
         }
     std::sort(pairs.begin(), pairs.end(), [](const Pair& x, const Pair& y) {
@@ -364,14 +366,16 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         int g1 = pairs[k].g1, g2 = pairs[k].g2;
         pg1[k] = g1;
         pg2[k] = g2;
-        ptype[k] = d->geom_type[g1] == RB_GEOM_BOX ? RB_PAIR_BOXBOX : d->geom_type[g2];
+        ptype[k] = d->geom_type[g1] == RB_GEOM_BOX      ? RB_PAIR_BOXBOX
+                   : d->geom_type[g1] == RB_GEOM_SPHERE ? RB_PAIR_SPHEREBOX
+                                                        : d->geom_type[g2];
         if (ptype[k] == RB_PAIR_BOXBOX) pslot[k] = nbb++;
         bool mov2 = movable[d->geom_body[g2]];
         pbody[k] = mov2 ? d->geom_body[g2] : d->geom_body[g1];
         psig[k] = mov2 ? 1.0 : -1.0;
         pmu[k] = std::max(d->geom_friction[g1], d->geom_friction[g2]);
         pmar[k] = std::max(d->geom_margin[g1], d->geom_margin[g2]);
-        pcap[k] = ptype[k] == RB_GEOM_SPHERE ? 1 : (ptype[k] == RB_GEOM_CAPSULE ? 2 : 8);
+        pcap[k] = (ptype[k] == RB_GEOM_SPHERE || ptype[k] == RB_PAIR_SPHEREBOX) ? 1 : (ptype[k] == RB_GEOM_CAPSULE ? 2 : 8);
         maxcon += pcap[k];
     }
     // options
@@ -543,6 +547,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.nhlevel = nhlevel; m.maxpiv = maxpiv; m.K = d->nsubsteps; m.maxiter = d->iterations;
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.nlim = nlim;
+    m.ext = (nbb > 0 || nlim > 0 || std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0) ? 1 : 0;
     m.dt = (float)d->timestep;
     for (int i = 0; i < 3; i++) m.grav[i] = (float)d->gravity[i];
     m.tol_scale = (float)(d->tolerance * meaninertia * nv);
@@ -808,7 +813,7 @@ int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out) {
         p->batches.push_back(batches[i]);
         models[i] = batches[i]->dm;
         p->maxd = std::max(p->maxd, models[i].maxd);
-        p->boxbox = p->boxbox || models[i].nbb > 0 || models[i].nlim > 0;   // extended code
+        p->boxbox = p->boxbox || models[i].ext;   // some model needs the extended code
     }
     // every batch runs in its own model's instantiation, with its own LDS layout
     for (int i = 0; i < nbatch; i++) p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);

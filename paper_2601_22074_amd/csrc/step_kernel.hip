@@ -467,20 +467,63 @@ DEV void geom_pose(const DevModel& m, const float* L, int g, float* x, float* R)
     mm(Rb, Rg, R);
 }
 
+DEV float pick3(const float* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
+
 // Candidate contacts of a plane pair, in feature order: sphere 0; capsule ends 0 (-z), 1 (+z);
-// box vertices k = 4x + 2y + z by sign bits.
-DEV int pair_ncand(int type) { return type == RB_GEOM_SPHERE ? 1 : (type == RB_GEOM_CAPSULE ? 2 : 8); }
+// box vertices k = 4x + 2y + z by sign bits.  A sphere-box pair has the one candidate 0.
+DEV int pair_ncand(int type) {
+    return (type == RB_GEOM_SPHERE || type == RB_PAIR_SPHEREBOX) ? 1 : (type == RB_GEOM_CAPSULE ? 2 : 8);
+}
 
 // Candidate k of plane pair p: distance to the plane, contact point (halfway between the
-// surfaces) and the plane normal.
+// surfaces) and the plane normal.  Sphere-box pair: the box's point closest to the sphere's
+// centre c (c clamped to the box in its frame), or the nearest face when c is inside (least
+// depth, lowest axis on ties, + side at 0); distance |c - closest| - r outside, -(depth + r)
+// inside; normal from the sphere towards the box.
+template <bool EXT>
 DEV void pair_candidate(const DevModel& m, const float* L, int p, int k, float* dist, float* pos, float* nrm) {
     float xp[3], Rp[9], x[3], R[9];
     geom_pose(m, L, m.pair_g1[p], xp, Rp);
     geom_pose(m, L, m.pair_g2[p], x, R);
-    const float n[3] = {Rp[2], Rp[5], Rp[8]};
-    nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2];
     const float* sz = m.geom_size + 3 * m.pair_g2[p];
     const int type = m.pair_type[p];
+    if (EXT && type == RB_PAIR_SPHEREBOX) {
+        const float rad = m.geom_size[3 * m.pair_g1[p]];
+        const float rel[3] = {xp[0] - x[0], xp[1] - x[1], xp[2] - x[2]};
+        float pl[3], ql[3];
+        bool inside = true;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            pl[i] = R[i] * rel[0] + R[3 + i] * rel[1] + R[6 + i] * rel[2];
+            ql[i] = fminf(fmaxf(pl[i], -sz[i]), sz[i]);
+            inside = inside && ql[i] == pl[i];
+        }
+        float nl[3] = {0.f, 0.f, 0.f}, d;
+        if (!inside) {
+            const float df[3] = {pl[0] - ql[0], pl[1] - ql[1], pl[2] - ql[2]};
+            const float len = sqrtf(dot(df, df));
+            const float il = 1.0f / len;
+            nl[0] = df[0] * il; nl[1] = df[1] * il; nl[2] = df[2] * il;
+            d = len - rad;
+        } else {
+            int a = 0;
+            if (sz[1] - fabsf(pl[1]) < sz[a] - fabsf(pl[a])) a = 1;
+            if (sz[2] - fabsf(pl[2]) < sz[a] - fabsf(pl[a])) a = 2;
+            const float pa = pick3(pl, a), ha = pick3(sz, a);
+            const float sg = pa < 0.f ? -1.f : 1.f;
+            nl[0] = a == 0 ? sg : 0.f; nl[1] = a == 1 ? sg : 0.f; nl[2] = a == 2 ? sg : 0.f;
+            d = -(ha - fabsf(pa) + rad);
+        }
+        float nw[3];
+        mv(R, nl, nw);
+        nrm[0] = -nw[0]; nrm[1] = -nw[1]; nrm[2] = -nw[2];
+        *dist = d;
+        const float h = rad + 0.5f * d;
+        pos[0] = xp[0] - nw[0] * h; pos[1] = xp[1] - nw[1] * h; pos[2] = xp[2] - nw[2] * h;
+        return;
+    }
+    const float n[3] = {Rp[2], Rp[5], Rp[8]};
+    nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2];
     float e[3], rad = 0.f;
     if (type == RB_GEOM_SPHERE) {
         e[0] = x[0]; e[1] = x[1]; e[2] = x[2];
@@ -504,19 +547,19 @@ DEV void pair_candidate(const DevModel& m, const float* L, int p, int k, float* 
 // Bit k set iff candidate k of plane pair p is below the margin.  Computed once per pair; the
 // contact lanes then pick their candidate from these bits, so membership never depends on
 // re-evaluating a distance that sits on the margin.
+template <bool EXT>
 DEV uint32_t pair_mask(const DevModel& m, const float* L, int p) {
     const int nc = pair_ncand(m.pair_type[p]);
     const float margin = m.pair_margin[p];
     uint32_t mask = 0;
     for (int k = 0; k < nc; k++) {
         float d, pos[3], nrm[3];
-        pair_candidate(m, L, p, k, &d, pos, nrm);
+        pair_candidate<EXT>(m, L, p, k, &d, pos, nrm);
         if (d < margin) mask |= 1u << k;
     }
     return mask;
 }
 
-DEV float pick3(const float* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
 DEV void pick_axis(const float (&a)[3][3], int i, float* o) {
 #pragma unroll
     for (int k = 0; k < 3; k++) o[k] = i == 0 ? a[0][k] : (i == 1 ? a[1][k] : a[2][k]);
@@ -744,7 +787,7 @@ struct StepArgs {
 // MAXD: longest dof chain the instantiation supports; TIMED: the diagnostic instantiation that
 // serves rb_step_taps (stage taps, work totals and per-stage shader-clock cycles); the plain
 // instantiation carries none of that code.  EXT: the extended instantiation, with the code of
-// box-box pairs and joint limits, used for models that have either.
+// box-box and sphere-box pairs and joint limits, used for models that have any of them.
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
@@ -1068,7 +1111,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             if (EXT && m.pair_type[lane] == RB_PAIR_BOXBOX) {
                 cnt = box_box(m, L, lane, L + m.o_bb + RB_BB_FLOATS * m.pair_slot[lane]);
             } else {
-                cmask = pair_mask(m, L, lane);
+                cmask = pair_mask<EXT>(m, L, lane);
                 cnt = __builtin_popcount(cmask);
             }
         }
@@ -1106,7 +1149,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 // the j-th set bit of the pair's candidate mask
                 for (int t = 0; t < j; t++) smask &= smask - 1u;
                 feat = __builtin_ctz(smask);
-                pair_candidate(m, L, src, feat, &C.dist, pos_, C.n);
+                pair_candidate<EXT>(m, L, src, feat, &C.dist, pos_, C.n);
             }
             C.r[0] = pos_[0] - O[0]; C.r[1] = pos_[1] - O[1]; C.r[2] = pos_[2] - O[2];
             contact_frame(C.n, C.t1);
@@ -1645,8 +1688,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     }
 }
 
-// One world per 64-lane workgroup.  EXT: the model has box-box pairs or joint limits (that code
-// is kept out of the other instantiations so their register allocation is not shaped by it).
+// One world per 64-lane workgroup.  EXT: the model has box-box or sphere-box pairs or joint
+// limits (that code is kept out of the other instantiations so their register allocation is not
+// shaped by it).
 template <int MAXD, bool TIMED, bool EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void step_kernel(
     DevModel m, StepArgs A) {
@@ -1683,7 +1727,7 @@ struct MultiArgs {
 // MAXD and EXT bound what the plan's models need.
 template <int MAXD, bool EXT>
 DEV void world_step_as_plain(const DevModel& m, const StepArgs& A, int w, float* lds) {
-    const bool bb = EXT && (m.nbb > 0 || m.nlim > 0);
+    const bool bb = EXT && m.ext;
     if (MAXD >= 32 && m.maxd > 16) {
         if (bb) world_step<(MAXD >= 32 ? 32 : MAXD), false, EXT>(m, A, w, lds);
         else world_step<(MAXD >= 32 ? 32 : MAXD), false, false>(m, A, w, lds);
@@ -1805,7 +1849,7 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     if (taps) A.taps = *taps; else A.taps = DevTaps{};
     size_t shmem = (size_t)m.lds_floats * sizeof(float);
     const bool timed = taps != nullptr;   // every tap is served by the diagnostic instantiation
-    const bool bb = m.nbb > 0 || m.nlim > 0;   // the extended instantiation
+    const bool bb = m.ext != 0;   // the extended instantiation
     if (timed) {
         if (bb) launch_step_d<true, true>(m, A, n, shmem, stream);
         else launch_step_d<true, false>(m, A, n, shmem, stream);

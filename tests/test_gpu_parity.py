@@ -87,7 +87,8 @@ def test_single_step_from_initial_states(oracle_mod, name):
 
 
 @pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150), ("arm_box", 150),
-                                          ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 150)])
+                                          ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 150),
+                                          ("quadruped_terrain", 200)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory, hand its state (rounded to FP32) to the GPU at
     sampled steps and compare one env step."""
@@ -214,7 +215,7 @@ def test_chain3_500_steps(oracle_mod):
 
 
 # ------------------------------------------------------------------ contact sets
-@pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box"])
+@pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -266,6 +267,53 @@ def test_box_box_contacts_random_poses(oracle_mod):
         assert np.abs(c["frame"][w, :nc].reshape(nc, 9) - t["frame"].reshape(nc, 9)).max() <= 2e-5, f"world {w}"
         kinds.add(nc)
     assert 1 in kinds and 4 in kinds
+
+
+def test_sphere_box_contacts_random_poses(oracle_mod):
+    """A ball at random places around a rotated static box, within a 2 cm margin band or
+    penetrating (centre outside or inside): contact keys, depths, points and normals against
+    the oracle on the same FP32 state."""
+    n = 64
+    r = 0.05
+    quat = robots.quat_axis_angle([0.3, -0.5, 0.8], 0.7)
+    mb = robots.ModelBuilder("box_ball", timestep=0.005, nsubsteps=1)
+    mb.geom(0, "box", [0.3, 0.2, 0.1], pos=(0.0, 0.0, 0.5), quat=quat, contype=0, conaffinity=1)
+    b = mb.body("ball", 0, (0, 0, 1), 0.5, robots.sphere_inertia(0.5, r))
+    mb.joint(b, "free")
+    mb.geom(b, "sphere", [r], contype=1, conaffinity=0, margin=0.02)
+    m = mb.build()
+    rng = np.random.default_rng(5)
+    R = rot(quat)
+    q = np.zeros((n, 7))
+    for w in range(n):
+        # a point on a random face, pushed out (or in) along that face's normal
+        ax = rng.integers(3)
+        loc = rng.uniform(-1, 1, 3) * np.array([0.3, 0.2, 0.1])
+        sg = rng.choice([-1.0, 1.0])
+        loc[ax] = sg * ([0.3, 0.2, 0.1][ax] + rng.uniform(-0.06, 0.09))
+        q[w, :3] = np.array([0.0, 0.0, 0.5]) + R @ loc
+        q[w, 3] = 1.0
+    q = q.astype(np.float32)
+    v = np.zeros((n, 6), np.float32)
+    g = gpu_run(m, q, v, contacts=True)
+    c = g["contacts"]
+    o = oracle_mod.Oracle(m)
+    kinds = set()
+    for w in range(n):
+        t = o.forward(q[w], v[w])
+        if any(abs(d - 0.02) <= MARGIN_BAND for d in t["dist"]):
+            continue
+        nc = t["ncon"]
+        assert c["ncon"][w] == nc, f"world {w}"
+        if nc == 0:
+            kinds.add("none")
+            continue
+        assert [tuple(x) for x in c["geom"][w, :nc]] == [tuple(x) for x in t["geom"]]
+        assert abs(c["dist"][w, 0] - t["dist"][0]) <= 2e-6, f"world {w}"
+        assert np.abs(c["pos"][w, 0] - t["pos"][0]).max() <= 2e-6, f"world {w}"
+        assert np.abs(c["frame"][w, 0].reshape(9) - t["frame"][0].reshape(9)).max() <= 2e-5, f"world {w}"
+        kinds.add("inside" if t["dist"][0] < -r else ("touch" if t["dist"][0] < 0 else "band"))
+    assert {"none", "band", "touch", "inside"} <= kinds
 
 
 @pytest.mark.parametrize("name", ["quadruped", "humanoid", "quadruped_lim", "humanoid_lim"])
@@ -337,7 +385,7 @@ def test_run_twice_bitwise(oracle_mod):
         np.testing.assert_array_equal(a["contacts"][k], b["contacts"][k])
 
 
-@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim"])
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim", "quadruped_terrain"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""

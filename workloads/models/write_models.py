@@ -1,5 +1,6 @@
 """Write the workload models (chain3, quadruped, humanoid, arm_box and the joint-limited
-chain3_lim, quadruped_lim, humanoid_lim) as JSON files in the form rb_model_create_json reads.  The generators in workloads/robots.py are the source; the
+chain3_lim, quadruped_lim, humanoid_lim, and the quadruped on a random-height grid of box tiles)
+as JSON files in the form rb_model_create_json reads.  The generators in workloads/robots.py are the source; the
 files are for callers that load a model without Python."""
 import json
 import os
@@ -10,7 +11,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from workloads import robots  # noqa: E402
 
-NAMES = ("chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim", "humanoid_lim")
+NAMES = ("chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim", "humanoid_lim",
+         "quadruped_terrain")
 
 
 def main():

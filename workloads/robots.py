@@ -372,6 +372,32 @@ def free_offset(gravity=(0, 0, -9.81), timestep=0.005) -> dict:
     return mb.build()
 
 
+TERRAIN_GEOM = dict(contype=0, conaffinity=2)      # terrain tiles: touched by geoms with contype bit 2
+
+
+def quadruped_terrain(tile=0.4, n=3, max_height=0.04, seed=2601) -> dict:
+    """The quadruped on a random-height grid: n x n static box tiles of side ``tile`` centred
+    under the robot, tops at heights U[0, max_height] from a fixed seed; the sphere feet touch
+    the tiles (and the plane), the torso only the plane.  The torso starts ``max_height``
+    higher."""
+    m = quadruped()
+    m["name"] = "quadruped_terrain"
+    rng = np.random.default_rng(seed)
+    heights = rng.uniform(0.0, max_height, (n, n))
+    half = tile / 2
+    for i in range(n):
+        for j in range(n):
+            cx, cy = (i - (n - 1) / 2) * tile, (j - (n - 1) / 2) * tile
+            m["geoms"].append(dict(type="box", body=0, pos=[cx, cy, float(heights[i, j]) - 0.05],
+                                   quat=[1.0, 0.0, 0.0, 0.0], size=[half, half, 0.05], friction=1.0,
+                                   margin=0.0, **TERRAIN_GEOM))
+    for g in m["geoms"]:
+        if g["type"] == "sphere":
+            g["contype"] = 3
+    m["bodies"][1]["pos"][2] += max_height
+    return m
+
+
 def with_limits(model: dict, lower: float, upper: float, name: str | None = None) -> dict:
     """Copy of ``model`` whose hinges are limited to [lower, upper] (radians)."""
     out = copy.deepcopy(model)
@@ -399,7 +425,8 @@ def humanoid_lim() -> dict:
 
 
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
-                "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim}
+                "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
+                "quadruped_terrain": quadruped_terrain}
 
 
 def by_name(name: str) -> dict:
