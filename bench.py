@@ -447,7 +447,7 @@ def summarize_profiles(trace_db, fetch_db, write_db, name, nworlds, calib_mb, co
     fetch_kib = float(np.median(fs)) if fs else float("nan")
     write_kib = float(np.median(ws)) if ws else float("nan")
     bytes_per_launch = (fetch_kib * ffac + write_kib * wfac) * 1024.0
-    d = {"kernel": "plain step kernel (step_kernel_w4<16> for this workload)", "workload": f"{name} x{nworlds}",
+    d = {"kernel": "plain step kernel (step_kernel_w4<16, false> for this workload)", "workload": f"{name} x{nworlds}",
          "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
          "calibration": {"kernel": f"elementwise neg of {calib_mb} MiB (reads and writes {calib_mb} MiB)",
                          "fetch_kib": float(np.median(fc)) if fc else None,
