@@ -119,3 +119,40 @@ def substeps1(model):
 
 def by_name(name):
     return robots.by_name(name)
+
+
+BAND_SPEED = 1e-4     # normal speed above which a contact on its threshold matters (m/s)
+
+
+def margin_band_worlds(oracle_mod, model, qpos, qvel, ctrl, qacc_ws, friction, mass_scale):
+    """Per world: whether one env step from this FP32 state passes a contact within
+    MARGIN_BAND of its inclusion threshold, moving along its normal faster than BAND_SPEED, at
+    the start of some substep.  The two paths may then include the contact on one side only,
+    and its reference acceleration, which damps the normal speed (about b |v_n| with
+    b = 2 / (dmax tc) ~ 105 / s), changes the velocity by about dt b |v_n|: past the step
+    tolerance above ~2e-4 m/s.  Found with the oracle alone: its substeps are replayed one at a
+    time, each starting state listed by a copy of the model whose margins are widened by the
+    band."""
+    import copy
+    m1 = substeps1(model)
+    wide = copy.deepcopy(m1)
+    for g in wide["geoms"]:
+        g["margin"] = g["margin"] + MARGIN_BAND
+    o1, ow = oracle_mod.Oracle(m1), oracle_mod.Oracle(wide)
+    n = qpos.shape[0]
+    q = np.array(qpos, np.float64); v = np.array(qvel, np.float64)
+    ws = np.zeros((n, o1.nv)) if qacc_ws is None else np.array(qacc_ws, np.float64)
+    u = np.zeros((n, o1.nu)) if ctrl is None else np.asarray(ctrl, np.float64)
+    gm = [g["margin"] for g in model["geoms"]]
+    band = np.zeros(n, bool)
+    for _ in range(model["opt"]["nsubsteps"]):
+        for w in range(n):
+            t = ow.forward(q[w], v[w], u[w] if o1.nu else None, ws[w],
+                           None if friction is None else friction[w], None if mass_scale is None else mass_scale[w])
+            for i, ((g1, g2), d) in enumerate(zip(t["geom"], t["dist"])):
+                if abs(d - max(gm[g1], gm[g2])) <= MARGIN_BAND:
+                    vn = 0.5 * (t["J"][4 * i] + t["J"][4 * i + 1]) @ v[w]
+                    band[w] |= abs(vn) > BAND_SPEED
+        o1.step(u, q, v, ws, None if friction is None else np.asarray(friction, np.float64),
+                None if mass_scale is None else np.asarray(mass_scale, np.float64))
+    return band

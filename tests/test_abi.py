@@ -139,7 +139,7 @@ def test_malformed_json_rejected(rb, mutate, needle):
 
 
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim",
-                                  "humanoid_lim", "quadruped_terrain"])
+                                  "humanoid_lim", "quadruped_terrain", "humanoid_terrain"])
 def test_model_files_match_generators(name):
     """workloads/models/<name>.json holds exactly what the generator builds (float values
     round-trip through JSON unchanged)."""

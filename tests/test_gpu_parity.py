@@ -2,8 +2,8 @@
 import numpy as np
 import pytest
 
-from gpu_common import (MARGIN_BAND, RTOL_ROLLOUT, RTOL_STEP, by_name, contact_keys, gpu_run, lifted, oracle_run,
-                        rel_err, substeps1, vec_err)
+from gpu_common import (MARGIN_BAND, RTOL_ROLLOUT, RTOL_STEP, by_name, contact_keys, gpu_run, lifted,
+                        margin_band_worlds, oracle_run, rel_err, substeps1, vec_err)
 from helpers import rot
 from workloads import inputs, robots
 
@@ -88,10 +88,11 @@ def test_single_step_from_initial_states(oracle_mod, name):
 
 @pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150), ("arm_box", 150),
                                           ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 150),
-                                          ("quadruped_terrain", 200)])
+                                          ("quadruped_terrain", 200), ("humanoid_terrain", 100)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory, hand its state (rounded to FP32) to the GPU at
-    sampled steps and compare one env step."""
+    sampled steps and compare one env step.  Samples where a moving contact starts a substep
+    on its inclusion threshold (found by the oracle, see margin_band_worlds) are left out."""
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
     worlds = list(range(32))
@@ -101,7 +102,7 @@ def test_single_step_teacher_forced(oracle_mod, name, horizon):
     msd = None if ms is None else ms.astype(np.float64)
     worst = 0.0
     ntrunc = 0
-    nover = nsamp = 0
+    nover = nsamp = nband = 0
     # joint limits put stiff rows on light distal dofs: a rare sample then carries FP32 solve
     # error a little past the step tolerance with the same iterations and active set as the
     # oracle; those may reach twice the tolerance, at most 1 % of the samples
@@ -115,7 +116,11 @@ def test_single_step_teacher_forced(oracle_mod, name, horizon):
             o.set_mode("converged")
             rc = oracle_run(o, q32, v32, uu.astype(np.float32), w32, fr, ms)
             o.set_mode("mirror")
+            band = margin_band_worlds(oracle_mod, m, q32, v32, uu.astype(np.float32), w32, fr, ms)
+            nband += int(band.sum())
             for w in range(32):
+                if band[w]:
+                    continue
                 # distance of the truncated (4-iteration) FP64 step from the converged one: where
                 # the truncated Newton has not reached the solution its iterate depends on the
                 # rounding along the way, and the comparison is conditioned by that distance
@@ -130,6 +135,8 @@ def test_single_step_teacher_forced(oracle_mod, name, horizon):
         o.step(uu, qq, vv, ws, frd, msd, st)
     # most sampled worlds are compared at the plain step tolerance
     assert worst <= slack and nover <= nsamp // 100 and ntrunc <= 32 * (horizon // 25) // 2, (worst, nover, ntrunc)
+    # samples with a moving contact on its inclusion threshold (feet landing) stay a minority
+    assert nband <= 32 * (horizon // 25) // 6, nband
 
 
 # ------------------------------------------------------------------ contact-free rollouts
@@ -215,7 +222,7 @@ def test_chain3_500_steps(oracle_mod):
 
 
 # ------------------------------------------------------------------ contact sets
-@pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain"])
+@pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain", "humanoid_terrain"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -385,7 +392,8 @@ def test_run_twice_bitwise(oracle_mod):
         np.testing.assert_array_equal(a["contacts"][k], b["contacts"][k])
 
 
-@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim", "quadruped_terrain"])
+@pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim", "quadruped_terrain",
+                                  "humanoid_terrain"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""

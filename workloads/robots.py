@@ -398,6 +398,29 @@ def quadruped_terrain(tile=0.4, n=3, max_height=0.04, seed=2601) -> dict:
     return m
 
 
+def humanoid_terrain(tile=0.6, n=2, max_height=0.03, seed=2602) -> dict:
+    """The humanoid on a random-height grid: n x n static box tiles of side ``tile`` centred
+    under the robot, tops at heights U[0, max_height] from a fixed seed; the four foot boxes
+    touch the tiles (box against box), every other geom only the plane.  The pelvis starts
+    ``max_height`` higher."""
+    m = humanoid()
+    m["name"] = "humanoid_terrain"
+    rng = np.random.default_rng(seed)
+    heights = rng.uniform(0.0, max_height, (n, n))
+    half = tile / 2
+    for i in range(n):
+        for j in range(n):
+            cx, cy = (i - (n - 1) / 2) * tile, (j - (n - 1) / 2) * tile
+            m["geoms"].append(dict(type="box", body=0, pos=[cx, cy, float(heights[i, j]) - 0.05],
+                                   quat=[1.0, 0.0, 0.0, 0.0], size=[half, half, 0.05], friction=1.0,
+                                   margin=0.0, **TERRAIN_GEOM))
+    for g in m["geoms"]:
+        if g["type"] == "box" and m["bodies"][g["body"]]["name"].endswith("ankle_roll"):
+            g["contype"] = 3
+    m["bodies"][1]["pos"][2] += max_height
+    return m
+
+
 def with_limits(model: dict, lower: float, upper: float, name: str | None = None) -> dict:
     """Copy of ``model`` whose hinges are limited to [lower, upper] (radians)."""
     out = copy.deepcopy(model)
@@ -426,7 +449,7 @@ def humanoid_lim() -> dict:
 
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
-                "quadruped_terrain": quadruped_terrain}
+                "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain}
 
 
 def by_name(name: str) -> dict:
