@@ -94,6 +94,8 @@ struct Model {
     std::vector<double> jrange;   // [njnt, 2]
     std::vector<char> jlimited;   // hinge with lower < upper
     int nlim = 0;
+    std::vector<double> jdamp;    // hinge damping
+    int ndamp = 0;
     std::vector<int> gtype, gbody, gcontype, gconaff;
     std::vector<double> gpos, gquat, gsize, gfric, gmargin;
     std::vector<int> atype, ajoint;
@@ -130,6 +132,7 @@ struct Data {
     std::vector<Contact> con;
     int nrows = 0;
     std::vector<double> J, aref, D, Ahat, efc_force, a, cforce;
+    std::vector<double> aint;   // acceleration the integrator applies (a, or its damped correction)
     int niter = 0;
     bool itercap = false;   // the Newton loop used every iteration without meeting a tolerance
     double cost = 0;
@@ -143,6 +146,7 @@ struct Data {
         janchor.assign(3 * nj, 0); jaxw.assign(3 * nj, 0);
         gx.assign(3 * ng, 0); gR.assign(9 * ng, 0);
         M.assign(nv * nv, 0); c.assign(nv, 0); tau.assign(nv, 0); a0.assign(nv, 0); a.assign(nv, 0);
+        aint.assign(nv, 0);
     }
 };
 
@@ -352,6 +356,12 @@ void actuation(const Model& m, Data& d) {
         else
             d.tau[k] += m.agear[u] * d.ctrl[u];
     }
+}
+
+// passive joint damping: -damping * qvel on each damped hinge, added to the applied forces
+void passive(const Model& m, Data& d) {
+    for (int j = 0; j < m.njnt; j++)
+        if (m.jdamp[j] > 0) d.tau[m.jdadr[j]] -= m.jdamp[j] * d.v[m.jdadr[j]];
 }
 
 // dense Cholesky A = L L' (lower); returns false if not positive definite
@@ -906,6 +916,7 @@ void newton(const Model& m, Data& d) {
 // ------------------------------------------------------------------------------------
 void forward(const Model& m, Data& d) {
     actuation(m, d);
+    passive(m, d);
     kinematics(m, d);
     mass_matrix(m, d);
     bias_forces(m, d);
@@ -930,6 +941,20 @@ void forward(const Model& m, Data& d) {
         d.cforce[3 * ci] = f[0] + f[1] + f[2] + f[3];
         d.cforce[3 * ci + 1] = mu * (f[0] - f[1]);
         d.cforce[3 * ci + 2] = mu * (f[2] - f[3]);
+    }
+    // Damping integrated implicitly: the step applies a_int = (M + dt B)^-1 M a, B the diagonal
+    // of joint dampings -- the damping force taken at the end-of-step velocity, to first order
+    // (M a is the total force the solution carries: applied, passive, bias and constraint)
+    d.aint = d.a;
+    if (m.ndamp > 0) {
+        const int nv = m.nv;
+        std::vector<double> H = d.M, LH, Ma(nv, 0.0);
+        for (int j = 0; j < m.njnt; j++)
+            if (m.jdamp[j] > 0) H[m.jdadr[j] * (nv + 1)] += m.dt * m.jdamp[j];
+        for (int r = 0; r < nv; r++)
+            for (int k = 0; k < nv; k++) Ma[r] += d.M[r * nv + k] * d.a[k];
+        if (cholesky(H, nv, LH)) chol_solve(LH, nv, Ma.data(), d.aint.data());
+        else std::fill(d.aint.begin(), d.aint.end(), NAN);
     }
 }
 
@@ -1019,6 +1044,13 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
     if (dsc->jnt_range) M.jrange.assign(dsc->jnt_range, dsc->jnt_range + 2 * nj);
     M.jlimited.assign(nj, 0);
     M.nlim = 0;
+    M.jdamp.assign(nj, 0.0);
+    if (dsc->jnt_damping) M.jdamp.assign(dsc->jnt_damping, dsc->jnt_damping + nj);
+    M.ndamp = 0;
+    for (int j = 0; j < nj; j++) {
+        if (!(std::isfinite(M.jdamp[j]) && M.jdamp[j] >= 0)) return bad("joint damping must be finite and >= 0");
+        M.ndamp += M.jdamp[j] > 0;
+    }
     M.jqadr.assign(nj, 0); M.jdadr.assign(nj, 0);
     // joints must be listed in body order so dof order follows body order
     int qa = 0, da = 0, lastb = 0;
@@ -1034,6 +1066,7 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
             if (M.parent[b] != 0) return bad("free joint must be on a child of the world");
             qa += 7; da += 6;
             if (M.jrange[2 * j] != M.jrange[2 * j + 1]) return bad("free joints take no range");
+            if (M.jdamp[j] != 0) return bad("free joints take no damping");
         } else if (M.jtype[j] == RBO_JNT_HINGE) {
             qa += 1; da += 1;
             const double lo = M.jrange[2 * j], hi = M.jrange[2 * j + 1];
@@ -1209,8 +1242,8 @@ int rbo_step(const void* mp, int32_t n, const double* ctrl, double* qpos, double
                     load_world(m, d, q, v, u, aws, fr, ms);
                     forward(m, d);
                     if (d.itercap) status[w] |= 2u;
-                    integrate(m, q, v, d.a.data(), q1.data(), v1.data());
-                    if (!all_finite(q1.data(), m.nq) || !all_finite(v1.data(), m.nv) || !all_finite(d.a.data(), m.nv)) {
+                    integrate(m, q, v, d.aint.data(), q1.data(), v1.data());
+                    if (!all_finite(q1.data(), m.nq) || !all_finite(v1.data(), m.nv) || !all_finite(d.aint.data(), m.nv)) {
                         status[w] |= 1u;
                         ncon = 0;
                         break;

@@ -56,6 +56,9 @@ typedef struct rbo_desc {
     /* joint ranges [njnt, 2] (lower, upper), or NULL: a hinge is limited when lower < upper;
        free joints take no range (both entries equal) */
     const double* jnt_range;
+    /* joint damping [njnt] (>= 0, hinges only), or NULL: a passive torque -damping * qvel,
+       integrated implicitly (see rbo_step) */
+    const double* jnt_damping;
 } rbo_desc;
 
 typedef struct rbo_info {

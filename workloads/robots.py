@@ -126,13 +126,16 @@ class ModelBuilder:
         return self.body(name, parent, pos, mass, capsule_inertia(mass, radius, length),
                          ipos=(a + b) / 2.0, iquat=quat_z_to(b - a) if length > 0 else (1, 0, 0, 0), quat=quat)
 
-    def joint(self, body, type_, axis=(0, 0, 1), pos=(0, 0, 0), armature=0.0, range_=None) -> int:
-        """range_: (lower, upper) angle limits of a hinge, or None for an unlimited joint."""
+    def joint(self, body, type_, axis=(0, 0, 1), pos=(0, 0, 0), armature=0.0, range_=None, damping=0.0) -> int:
+        """range_: (lower, upper) angle limits of a hinge, or None for an unlimited joint;
+        damping: passive torque -damping * velocity on a hinge (integrated implicitly)."""
         bid = body if isinstance(body, int) else self.body_id(body)
         j = dict(type=type_, body=bid, pos=list(map(float, pos)), axis=list(map(float, axis)),
                  armature=float(armature))
         if range_ is not None:
             j["range"] = [float(range_[0]), float(range_[1])]
+        if damping:
+            j["damping"] = float(damping)
         self.joints.append(j)
         return len(self.joints) - 1
 
@@ -432,6 +435,27 @@ def with_limits(model: dict, lower: float, upper: float, name: str | None = None
     return out
 
 
+def with_damping(model: dict, damping: float, name: str | None = None) -> dict:
+    """Copy of ``model`` whose hinges carry joint damping ``damping`` (N m s / rad)."""
+    out = copy.deepcopy(model)
+    for j in out["joints"]:
+        if j["type"] == "hinge":
+            j["damping"] = float(damping)
+    if name:
+        out["name"] = name
+    return out
+
+
+def chain3_damp() -> dict:
+    """chain3 with strong joint damping (2 N m s / rad on each hinge)."""
+    return with_damping(chain3(), 2.0, "chain3_damp")
+
+
+def humanoid_damp() -> dict:
+    """humanoid with joint damping 0.5 N m s / rad on every hinge."""
+    return with_damping(humanoid(), 0.5, "humanoid_damp")
+
+
 def chain3_lim() -> dict:
     """chain3 with every hinge limited to +-0.6 rad."""
     return with_limits(chain3(), -0.6, 0.6, "chain3_lim")
@@ -449,7 +473,8 @@ def humanoid_lim() -> dict:
 
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
-                "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain}
+                "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
+                "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp}
 
 
 def by_name(name: str) -> dict:
