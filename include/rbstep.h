@@ -79,6 +79,10 @@ typedef struct rb_model_desc {
      * entries).  A limited hinge outside its range gets one soft unilateral constraint row
      * pushing it back, solved with the contacts. */
     const double* jnt_range;
+    /* joint damping [njnt] (>= 0; hinges only), or NULL for none: a passive torque
+     * -damping * qvel, integrated implicitly -- the step applies (M + dt B)^-1 M qacc, B the
+     * diagonal of dampings, instead of the solved qacc (which stays the warm start). */
+    const double* jnt_damping;
 } rb_model_desc;
 
 typedef struct rb_model rb_model;
@@ -125,7 +129,7 @@ int rb_model_create(const rb_model_desc* desc, rb_model** out);
  *   "bodies": [{"parent", "pos": [3], "quat": [4], "ipos": [3], "iquat": [4], "mass",
  *               "inertia": [3]}, ...]   (body 0 = world),
  *   "joints": [{"type": "free" | "hinge", "body", "pos": [3], "axis": [3], "armature",
- *               "range": [2] (optional, hinges only)}, ...],
+ *               "range": [2], "damping" (both optional, hinges only)}, ...],
  *   "geoms": [{"type": "plane" | "sphere" | "capsule" | "box", "body", "pos": [3],
  *              "quat": [4], "size": [3], "friction", "contype", "conaffinity", "margin"}, ...],
  *   "actuators": [{"type": "position" | "motor", "joint", "kp", "kd", "gear"}, ...],

@@ -6,14 +6,14 @@
 //  "bodies": [{"parent", "pos": [3], "quat": [4], "ipos": [3], "iquat": [4], "mass",
 //              "inertia": [3]}, ...],                    body 0 is the world
 //  "joints": [{"type": "free"|"hinge", "body", "pos": [3], "axis": [3], "armature",
-//              "range": [2] (optional)}, ...],
+//              "range": [2], "damping" (both optional)}, ...],
 //  "geoms": [{"type": "plane"|"sphere"|"capsule"|"box", "body", "pos": [3], "quat": [4],
 //             "size": [3], "friction", "contype", "conaffinity", "margin"}, ...],
 //  "actuators": [{"type": "position"|"motor", "joint", "kp", "kd", "gear"}, ...],
 //  "per_world": {"friction": bool, "mass_scale": bool}}      optional, default false
 //
 // Other keys (names, comments) are ignored.  Every listed field is required except a joint's
-// range and per_world; a missing or mistyped field is RB_EINVAL with the field named.
+// range and damping and per_world; a missing or mistyped field is RB_EINVAL with the field named.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -218,7 +218,7 @@ int rb_model_create_json(const char* json, rb_model** out) {
     const int b1 = nb + 1, j1 = nj + 1, g1 = ng + 1, u1 = nu + 1;
     std::vector<int32_t> bpar(b1), jtype(j1), jbody(j1), gtype(g1), gbody(g1), gct(g1), gca(g1), atype(u1), ajnt(u1);
     std::vector<double> bpos(3 * b1), bquat(4 * b1), bipos(3 * b1), biquat(4 * b1), bmass(b1), binert(3 * b1);
-    std::vector<double> jpos(3 * j1), jaxis(3 * j1), jarm(j1), jrange(2 * j1, 0.0);
+    std::vector<double> jpos(3 * j1), jaxis(3 * j1), jarm(j1), jrange(2 * j1, 0.0), jdamp(j1, 0.0);
     std::vector<double> gpos(3 * g1), gquat(4 * g1), gsize(3 * g1), gfric(g1), gmarg(g1);
     std::vector<double> akp(u1), akd(u1), agear(u1);
     bool ok = true;
@@ -238,6 +238,7 @@ int rb_model_create_json(const char* json, rb_model** out) {
              R.vec(o, "pos", w, 3, &jpos[3 * j]) && R.vec(o, "axis", w, 3, &jaxis[3 * j]) &&
              R.num(o, "armature", w, &jarm[j]);
         if (ok && o.obj.count("range")) ok = R.vec(o, "range", w, 2, &jrange[2 * j]);
+        if (ok && o.obj.count("damping")) ok = R.num(o, "damping", w, &jdamp[j]);
     }
     static const char* const gnames[] = {"plane", "sphere", "capsule", "box"};
     for (int g = 0; g < ng && ok; g++) {
@@ -281,6 +282,7 @@ int rb_model_create_json(const char* json, rb_model** out) {
     d.jnt_type = jtype.data(); d.jnt_body = jbody.data(); d.jnt_pos = jpos.data(); d.jnt_axis = jaxis.data();
     d.jnt_armature = jarm.data();
     d.jnt_range = jrange.data();
+    d.jnt_damping = jdamp.data();
     d.geom_type = gtype.data(); d.geom_body = gbody.data(); d.geom_contype = gct.data(); d.geom_conaffinity = gca.data();
     d.geom_pos = gpos.data(); d.geom_quat = gquat.data(); d.geom_size = gsize.data(); d.geom_friction = gfric.data();
     d.geom_margin = gmarg.data();

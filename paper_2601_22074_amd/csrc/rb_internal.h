@@ -72,7 +72,9 @@ struct DevModel {
     const float* dof_limlo;    // its lower and upper bounds
     const float* dof_limhi;
     int nlim;                  // limited hinges
-    int ext;                   // needs the extended code: box-box or sphere-box pairs, joint limits
+    const float* dof_damping;  // hinge damping (0 when undamped)
+    int ndamp;                 // damped hinges
+    int ext;                   // needs the extended code: box-box or sphere-box pairs, joint limits, damping
     const int* act_start;      // [nv + 1] CSR of actuators driving each dof
     const int* act_list;
     const int* act_type;

@@ -176,9 +176,12 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         jq[j] = nq;
         jd[j] = nv;
         const double rlo = d->jnt_range ? d->jnt_range[2 * j] : 0.0, rhi = d->jnt_range ? d->jnt_range[2 * j + 1] : 0.0;
+        const double damp = d->jnt_damping ? d->jnt_damping[j] : 0.0;
+        if (!(std::isfinite(damp) && damp >= 0)) return fail(RB_EINVAL, "joint damping must be finite and >= 0");
         if (jtype[j] == RB_JNT_FREE) {
             if (P(b) != 0) return fail(RB_EINVAL, "a free joint must be on a child of the world");
             if (rlo != rhi) return fail(RB_EINVAL, "free joints take no range");
+            if (damp != 0) return fail(RB_EINVAL, "free joints take no damping");
             nq += 7;
             nv += 6;
         } else if (jtype[j] == RB_JNT_HINGE) {
@@ -481,6 +484,14 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             arm[jd[j]] = d->jnt_armature[j];
         }
     }
+    // joint damping per dof (hinges only)
+    std::vector<double> ddamp(nv, 0.0);
+    int ndamp = 0;
+    for (int j = 0; j < nj && d->jnt_damping; j++)
+        if (jtype[j] == RB_JNT_HINGE && d->jnt_damping[j] > 0) {
+            ddamp[jd[j]] = d->jnt_damping[j];
+            ndamp++;
+        }
     // joint limits per dof: the hinge's qpos index (-1 when unlimited) and its bounds
     std::vector<int> limq(nv, -1);
     std::vector<double> limlo(nv, 0.0), limhi(nv, 0.0);
@@ -518,7 +529,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     I(desc_start, &m.desc_start); I(desc_list, &m.desc_list); I(dl_start, &m.dlevel_start); I(dl_dof, &m.dlevel_dof);
     I(height, &m.dof_height); I(hl_start, &m.hlevel_start); I(hl_dof, &m.hlevel_dof); I(bsize, &m.body_size); I(bchild, &m.body_children);
     F(arm, &m.dof_armature);
-    I(limq, &m.dof_limq); F(limlo, &m.dof_limlo); F(limhi, &m.dof_limhi);
+    I(limq, &m.dof_limq); F(limlo, &m.dof_limlo); F(limhi, &m.dof_limhi); F(ddamp, &m.dof_damping);
     I(act_start, &m.act_start); I(act_list, &m.act_list); I(atype, &m.act_type); I(aqadr, &m.act_qadr);
     F(akp, &m.act_kp); F(akd, &m.act_kd); F(agear, &m.act_gear);
     I(jtype, &m.jnt_type); I(jq, &m.jnt_qadr); I(jd, &m.jnt_dadr);
@@ -547,7 +558,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.nhlevel = nhlevel; m.maxpiv = maxpiv; m.K = d->nsubsteps; m.maxiter = d->iterations;
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.nlim = nlim;
-    m.ext = (nbb > 0 || nlim > 0 || std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0) ? 1 : 0;
+    m.ndamp = ndamp;
+    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0) ? 1 : 0;
     m.dt = (float)d->timestep;
     for (int i = 0; i < 3; i++) m.grav[i] = (float)d->gravity[i];
     m.tol_scale = (float)(d->tolerance * meaninertia * nv);

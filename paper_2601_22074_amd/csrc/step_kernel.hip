@@ -787,7 +787,7 @@ struct StepArgs {
 // MAXD: longest dof chain the instantiation supports; TIMED: the diagnostic instantiation that
 // serves rb_step_taps (stage taps, work totals and per-stage shader-clock cycles); the plain
 // instantiation carries none of that code.  EXT: the extended instantiation, with the code of
-// box-box and sphere-box pairs and joint limits, used for models that have any of them.
+// box-box and sphere-box pairs, joint limits and joint damping, used for models that have any.
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
@@ -873,6 +873,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 else
                     t += m.act_gear[u] * ctrl[u];
             }
+            // passive joint damping (its implicit integration follows the solve)
+            if (EXT && m.ndamp > 0) t -= m.dof_damping[i] * v[i];
             tau[i] = t;
         }
         // ---- forward kinematics.  Each body's pose relative to its parent is computed for all
@@ -1591,6 +1593,28 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 
         }
 
+        // ---- joint damping integrated implicitly: the step applies a_int = (M + dt B)^-1 M a,
+        // M a being the total force the solution carries (tau - c without a solve, the tracked
+        // M a after one).  Factored like M, with dt B on the damped dofs' diagonals; a_int goes
+        // to tmp, while the solver's a stays the next warm start.
+        const float* aI = acc;
+        if (EXT && m.ndamp > 0) {
+            float Hr[MAXD];
+#pragma unroll
+            for (int t = 0; t < MAXD; t++) Hr[t] = t < DL.depth ? Mm[DL.rowadr + t] : 0.f;
+            const float bd = lane < nv ? m.dt * m.dof_damping[lane] : 0.f;
+#pragma unroll
+            for (int t = 0; t < MAXD; t++)
+                if (t == DL.depth - 1) Hr[t] += bd;
+            const bool solved = ncon > 0 || limact;
+            const float rhs = lane < nv ? (solved ? Ma[lane] : tau[lane] - bias[lane]) : 0.f;
+            float invd;
+            const float x = factor_solve<MAXD>(m, DL, Hr, rhs, lane, piv, &invd);
+            if (lane < nv) tmp[lane] = x;
+            wave_sync();
+            aI = tmp;
+        }
+
         // ---- semi-implicit Euler (one lane per joint), committed only if everything is finite.
         // The joint update is evaluated twice -- once to test, once to write -- rather than
         // holding the new state in registers across the wave-wide test.
@@ -1601,13 +1625,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             const int jt = m.jnt_type[jl], qa = m.jnt_qadr[jl], da = m.jnt_dadr[jl];
             const float dt = m.dt;
             if (jt == RB_JNT_HINGE) {
-                const float vn = v[da] + dt * acc[da];
+                const float vn = v[da] + dt * aI[da];
                 const float qn = q[qa] + dt * vn;
                 bad = !finitef(vn) || !finitef(qn);
                 if (commit) { v[da] = vn; q[qa] = qn; }
             } else {
                 float vn[6], qn[7];
-                for (int k = 0; k < 6; k++) vn[k] = v[da + k] + dt * acc[da + k];
+                for (int k = 0; k < 6; k++) vn[k] = v[da + k] + dt * aI[da + k];
                 for (int k = 0; k < 3; k++) qn[k] = q[qa + k] + dt * vn[k];
                 float th[3] = {dt * vn[3], dt * vn[4], dt * vn[5]};
                 float ang = sqrtf(dot(th, th));
@@ -1630,7 +1654,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             return bad;
         };
         bool bad = false;
-        for (int i = lane; i < nv; i += RB_WAVE) bad |= !finitef(acc[i]);
+        for (int i = lane; i < nv; i += RB_WAVE) bad |= !finitef(aI[i]);
         bad |= euler(false);
         bool anybad = __any(bad);
         wave_sync();

@@ -42,7 +42,8 @@ def _create_error(m):
 
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
-                                  "moving_pair", "actuator_free", "free_range", "inverted_range"])
+                                  "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
+                                  "negative_damping"])
 def test_invalid_models_rejected(rb, case):
     m = robots.quadruped()
     if case == "parent":
@@ -67,6 +68,10 @@ def test_invalid_models_rejected(rb, case):
         m["joints"][0]["range"] = [-1.0, 1.0]
     elif case == "inverted_range":
         m["joints"][2]["range"] = [0.5, -0.5]
+    elif case == "free_damping":
+        m["joints"][0]["damping"] = 1.0
+    elif case == "negative_damping":
+        m["joints"][2]["damping"] = -1.0
     rc, msg = _create_error(m)
     assert rc == -1, (rc, msg)
     assert msg
@@ -81,7 +86,8 @@ def _create_json_error(text):
 
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
-                                  "moving_pair", "actuator_free", "free_range", "inverted_range"])
+                                  "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
+                                  "negative_damping"])
 def test_json_models_validated_like_descriptions(rb, case):
     """The JSON entry point hands the same description to the same validation: every invalid
     model above is rejected with the message the struct entry point gives."""
@@ -109,6 +115,10 @@ def test_json_models_validated_like_descriptions(rb, case):
         m["joints"][0]["range"] = [-1.0, 1.0]
     elif case == "inverted_range":
         m["joints"][2]["range"] = [0.5, -0.5]
+    elif case == "free_damping":
+        m["joints"][0]["damping"] = 1.0
+    elif case == "negative_damping":
+        m["joints"][2]["damping"] = -1.0
     rc_d, msg_d = _create_error(m)
     rc_j, msg_j = _create_json_error(json.dumps(m))
     assert (rc_j, msg_j) == (rc_d, msg_d)
@@ -139,7 +149,8 @@ def test_malformed_json_rejected(rb, mutate, needle):
 
 
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim",
-                                  "humanoid_lim", "quadruped_terrain", "humanoid_terrain"])
+                                  "humanoid_lim", "quadruped_terrain", "humanoid_terrain", "chain3_damp",
+                                  "humanoid_damp"])
 def test_model_files_match_generators(name):
     """workloads/models/<name>.json holds exactly what the generator builds (float values
     round-trip through JSON unchanged)."""

@@ -88,7 +88,8 @@ def test_single_step_from_initial_states(oracle_mod, name):
 
 @pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150), ("arm_box", 150),
                                           ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 150),
-                                          ("quadruped_terrain", 200), ("humanoid_terrain", 100)])
+                                          ("quadruped_terrain", 200), ("humanoid_terrain", 100),
+                                          ("humanoid_damp", 150)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory, hand its state (rounded to FP32) to the GPU at
     sampled steps and compare one env step.  Samples where a moving contact starts a substep
@@ -393,7 +394,7 @@ def test_run_twice_bitwise(oracle_mod):
 
 
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim", "quadruped_terrain",
-                                  "humanoid_terrain"])
+                                  "humanoid_terrain", "humanoid_damp"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""
