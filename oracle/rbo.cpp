@@ -96,7 +96,7 @@ struct Model {
     int nlim = 0;
     std::vector<double> jdamp;    // hinge damping
     int ndamp = 0;
-    std::vector<int> gtype, gbody, gcontype, gconaff;
+    std::vector<int> gtype, gbody, gcontype, gconaff, gcondim;
     std::vector<double> gpos, gquat, gsize, gfric, gmargin;
     std::vector<int> atype, ajoint;
     std::vector<double> akp, akd, agear;
@@ -116,6 +116,7 @@ struct Model {
 
 struct Contact {
     int g1, g2, feature, b1, b2;
+    int dim;   // 1: frictionless (one normal row), 3: pyramidal friction (four rows)
     double dist, pos[3], frame[9], mu;
 };
 
@@ -131,6 +132,7 @@ struct Data {
     // constraints
     std::vector<Contact> con;
     int nrows = 0;
+    std::vector<int> crow;   // first row of each contact
     std::vector<double> J, aref, D, Ahat, efc_force, a, cforce;
     std::vector<double> aint;   // acceleration the integrator applies (a, or its damped correction)
     int niter = 0;
@@ -442,7 +444,8 @@ void add_contact(const Model& m, Data& d, int g1, int g2, int feature, double di
     c.b1 = m.gbody[g1]; c.b2 = m.gbody[g2];
     std::memcpy(c.pos, pos, 3 * sizeof(double));
     contact_frame(n, c.frame);
-    c.mu = m.fr_pw ? d.fr : std::max(m.gfric[g1], m.gfric[g2]);
+    c.dim = std::max(m.gcondim[g1], m.gcondim[g2]);
+    c.mu = c.dim == 1 ? 0.0 : (m.fr_pw ? d.fr : std::max(m.gfric[g1], m.gfric[g2]));
     d.con.push_back(c);
 }
 
@@ -720,7 +723,8 @@ double impedance(const Model& m, double r) {
     return std::min(std::max(imp, 1e-4), 0.9999);
 }
 
-// Rows of the soft constraints, contacts first (4 pyramid rows each, in contact order), then
+// Rows of the soft constraints, contacts first (4 pyramid rows each, or the normal row alone for
+// a frictionless contact, in contact order), then
 // joint limits in joint order.  A limited hinge whose angle lies below its lower bound (or
 // above its upper bound) contributes one frictionless unilateral row with Jacobian +e_i
 // (-e_i) on its dof and distance q - lower (upper - q); limits use the same solref/solimp as
@@ -738,7 +742,13 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
         if (hi < 0) { ldof.push_back(m.jdadr[j]); lsgn.push_back(-1.0); ldist.push_back(hi); }
     }
     const int nl = (int)ldof.size();
-    d.nrows = 4 * nc + nl;
+    d.crow.assign(nc, 0);
+    int nr = 0;
+    for (int ci = 0; ci < nc; ci++) {
+        d.crow[ci] = nr;
+        nr += d.con[ci].dim == 1 ? 1 : 4;
+    }
+    d.nrows = nr + nl;
     d.J.assign((size_t)d.nrows * nv, 0.0);
     d.aref.assign(d.nrows, 0.0);
     d.D.assign(d.nrows, 0.0);
@@ -773,8 +783,8 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
                 Jc[r * nv + k] = acc;
             }
         double rdist = c.dist - std::max(m.gmargin[c.g1], m.gmargin[c.g2]);
-        for (int e = 0; e < 4; e++) {
-            int row = 4 * ci + e;
+        for (int e = 0; e < (c.dim == 1 ? 1 : 4); e++) {
+            int row = d.crow[ci] + e;
             int t = 1 + e / 2;
             double sgn = (e % 2 == 0) ? 1.0 : -1.0;
             double* Je = &d.J[(size_t)row * nv];
@@ -783,7 +793,7 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
         }
     }
     for (int l = 0; l < nl; l++) {
-        int row = 4 * nc + l;
+        int row = nr + l;
         d.J[(size_t)row * nv + ldof[l]] = lsgn[l];
         finish_row(row, ldist[l]);
     }
@@ -936,8 +946,12 @@ void forward(const Model& m, Data& d) {
     newton(m, d);
     d.cforce.assign(3 * d.con.size(), 0.0);
     for (size_t ci = 0; ci < d.con.size(); ci++) {
-        const double* f = &d.efc_force[4 * ci];
+        const double* f = &d.efc_force[d.crow[ci]];
         double mu = d.con[ci].mu;
+        if (d.con[ci].dim == 1) {
+            d.cforce[3 * ci] = f[0];
+            continue;
+        }
         d.cforce[3 * ci] = f[0] + f[1] + f[2] + f[3];
         d.cforce[3 * ci + 1] = mu * (f[0] - f[1]);
         d.cforce[3 * ci + 2] = mu * (f[2] - f[3]);
@@ -1105,6 +1119,10 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
         M.gfric.assign(dsc->geom_friction, dsc->geom_friction + ng);
         M.gmargin.assign(dsc->geom_margin, dsc->geom_margin + ng);
     }
+    M.gcondim.assign(ng, 3);
+    if (dsc->geom_condim) M.gcondim.assign(dsc->geom_condim, dsc->geom_condim + ng);
+    for (int g = 0; g < ng; g++)
+        if (M.gcondim[g] != 1 && M.gcondim[g] != 3) return bad("geom condim must be 1 or 3");
     for (int g = 0; g < ng; g++) {
         if (M.gtype[g] < 0 || M.gtype[g] > 3) return bad("unknown geom type");
         if (M.gbody[g] < 0 || M.gbody[g] >= nb) return bad("geom on invalid body");

@@ -59,6 +59,9 @@ typedef struct rbo_desc {
     /* joint damping [njnt] (>= 0, hinges only), or NULL: a passive torque -damping * qvel,
        integrated implicitly (see rbo_step) */
     const double* jnt_damping;
+    /* geom contact dimensionality [ngeom] (1 frictionless, 3 pyramidal friction), or NULL for
+       3 everywhere; a pair takes the larger of its two geoms' */
+    const int32_t* geom_condim;
 } rbo_desc;
 
 typedef struct rbo_info {

@@ -615,3 +615,61 @@ def test_ball_rests_on_box(oracle_mod):
     assert np.abs(t["cforce"][0, 1:]).max() < 1e-9
     assert np.abs(v).max() < 1e-6
     assert 0.2 + 0.05 - 1e-3 < q[0, 2] < 0.2 + 0.05
+
+
+# ---------------------------------------------------------------- frictionless contacts (condim 1)
+def _incline_box(theta, box_condim, plane_condim=1, h=0.05):
+    """A free box resting on a plane tilted by theta about +y (downhill along the plane's +x)."""
+    mb = robots.ModelBuilder("incline", timestep=0.002, nsubsteps=1)
+    mb.geom(0, "plane", [0, 0, 0], quat=robots.quat_axis_angle([0, 1, 0], theta), contype=0, conaffinity=1)
+    mb.geoms[-1]["condim"] = plane_condim
+    b = mb.body("box", 0, (0, 0, 1), 1.0, robots.box_inertia(1.0, h, h, h))
+    mb.joint(b, "free")
+    mb.geom(b, "box", [h, h, h], contype=1, conaffinity=0)
+    mb.geoms[-1]["condim"] = box_condim
+    m = mb.build()
+    R = rot(robots.quat_axis_angle([0, 1, 0], theta))
+    n = R[:, 2]
+    q = np.concatenate([n * (h - 1e-4), robots.quat_axis_angle([0, 1, 0], theta)])
+    return m, q, R
+
+
+def _slide(oracle_mod, m, q, steps):
+    o = oracle_mod.Oracle(m)
+    qq = q[None].copy(); v = np.zeros((1, 6)); ws = np.zeros((1, 6))
+    vs = []
+    for _ in range(steps):
+        o.step(np.zeros((1, 0)), qq, v, ws)
+        vs.append(v[0, :3].copy())
+    return o, qq, v, np.array(vs)
+
+
+def test_frictionless_box_slides_at_g_sin_theta(oracle_mod):
+    """On a 0.3 rad incline a frictionless box (pair condim 1: one normal row per contact)
+    accelerates downhill at g sin(theta) once the normal transient has settled."""
+    th = 0.3
+    m, q, R = _incline_box(th, 1)
+    o, qq, v, vs = _slide(oracle_mod, m, q, 600)
+    downhill = R[:, 0]                       # rotated about +y, the plane's +x axis points down the slope
+    a = np.diff(vs @ downhill)[-100:] / 0.002
+    np.testing.assert_allclose(a, 9.81 * np.sin(th), rtol=1e-6)
+    t = o.forward(qq[0], v[0])
+    assert t["ncon"] == 4 and t["J"].shape[0] == 4          # one row per contact
+    assert np.abs(t["cforce"][:, 1:]).max() == 0.0
+    assert abs(t["cforce"][:, 0].sum() - 9.81 * np.cos(th)) < 1e-6
+
+
+def test_pair_condim_is_the_larger(oracle_mod):
+    """A condim-1 box on a condim-3 plane keeps friction (the pair takes the larger), and with
+    mu = 1 > tan(0.3) it stays nearly at rest where the frictionless box slides."""
+    m, q, R = _incline_box(0.3, 1, plane_condim=3)
+    o, qq, v, vs = _slide(oracle_mod, m, q, 600)
+    t = o.forward(qq[0], v[0])
+    assert t["J"].shape[0] == 4 * t["ncon"]
+    assert np.abs(vs[-1]).max() < 0.05 * 9.81 * np.sin(0.3) * 600 * 0.002
+
+
+def test_invalid_condim_rejected(oracle_mod):
+    m, q, R = _incline_box(0.3, 2)
+    with pytest.raises(Exception):
+        oracle_mod.Oracle(m)
