@@ -83,6 +83,10 @@ typedef struct rb_model_desc {
      * -damping * qvel, integrated implicitly -- the step applies (M + dt B)^-1 M qacc, B the
      * diagonal of dampings, instead of the solved qacc (which stays the warm start). */
     const double* jnt_damping;
+    /* geom contact dimensionality [ngeom] (1 frictionless, 3 pyramidal friction), or NULL for 3
+     * everywhere; a pair takes the larger of its two geoms' (a condim-1 pair keeps the normal
+     * row only and reports zero tangential force) */
+    const int32_t* geom_condim;
 } rb_model_desc;
 
 typedef struct rb_model rb_model;
@@ -131,7 +135,8 @@ int rb_model_create(const rb_model_desc* desc, rb_model** out);
  *   "joints": [{"type": "free" | "hinge", "body", "pos": [3], "axis": [3], "armature",
  *               "range": [2], "damping" (both optional, hinges only)}, ...],
  *   "geoms": [{"type": "plane" | "sphere" | "capsule" | "box", "body", "pos": [3],
- *              "quat": [4], "size": [3], "friction", "contype", "conaffinity", "margin"}, ...],
+ *              "quat": [4], "size": [3], "friction", "contype", "conaffinity", "margin",
+ *              "condim" (optional, 1 or 3)}, ...],
  *   "actuators": [{"type": "position" | "motor", "joint", "kp", "kd", "gear"}, ...],
  *   "per_world": {"friction": bool, "mass_scale": bool}   (optional, default false);
  * other keys are ignored.  Each entry maps to the rb_model_desc field of the same name, in

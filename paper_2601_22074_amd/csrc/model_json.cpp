@@ -8,12 +8,13 @@
 //  "joints": [{"type": "free"|"hinge", "body", "pos": [3], "axis": [3], "armature",
 //              "range": [2], "damping" (both optional)}, ...],
 //  "geoms": [{"type": "plane"|"sphere"|"capsule"|"box", "body", "pos": [3], "quat": [4],
-//             "size": [3], "friction", "contype", "conaffinity", "margin"}, ...],
+//             "size": [3], "friction", "contype", "conaffinity", "margin", "condim" (optional)}, ...],
 //  "actuators": [{"type": "position"|"motor", "joint", "kp", "kd", "gear"}, ...],
 //  "per_world": {"friction": bool, "mass_scale": bool}}      optional, default false
 //
 // Other keys (names, comments) are ignored.  Every listed field is required except a joint's
-// range and damping and per_world; a missing or mistyped field is RB_EINVAL with the field named.
+// range and damping, a geom's condim and per_world; a missing or mistyped field is RB_EINVAL with
+// the field named.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -216,7 +217,8 @@ int rb_model_create_json(const char* json, rb_model** out) {
     const int nb = (int)bodies->size(), nj = (int)joints->size(), ng = (int)geoms->size(), nu = (int)acts->size();
     // one spare element each, so that an empty list still hands over a valid pointer
     const int b1 = nb + 1, j1 = nj + 1, g1 = ng + 1, u1 = nu + 1;
-    std::vector<int32_t> bpar(b1), jtype(j1), jbody(j1), gtype(g1), gbody(g1), gct(g1), gca(g1), atype(u1), ajnt(u1);
+    std::vector<int32_t> bpar(b1), jtype(j1), jbody(j1), gtype(g1), gbody(g1), gct(g1), gca(g1), atype(u1), ajnt(u1),
+        gdim(g1, 3);
     std::vector<double> bpos(3 * b1), bquat(4 * b1), bipos(3 * b1), biquat(4 * b1), bmass(b1), binert(3 * b1);
     std::vector<double> jpos(3 * j1), jaxis(3 * j1), jarm(j1), jrange(2 * j1, 0.0), jdamp(j1, 0.0);
     std::vector<double> gpos(3 * g1), gquat(4 * g1), gsize(3 * g1), gfric(g1), gmarg(g1);
@@ -249,6 +251,7 @@ int rb_model_create_json(const char* json, rb_model** out) {
              R.vec(o, "size", w, 3, &gsize[3 * g]) && R.num(o, "friction", w, &gfric[g]) &&
              R.integer(o, "contype", w, &gct[g]) && R.integer(o, "conaffinity", w, &gca[g]) &&
              R.num(o, "margin", w, &gmarg[g]);
+        if (ok && o.obj.count("condim")) ok = R.integer(o, "condim", w, &gdim[g]);
     }
     static const char* const anames[] = {"position", "motor"};
     for (int u = 0; u < nu && ok; u++) {
@@ -283,6 +286,7 @@ int rb_model_create_json(const char* json, rb_model** out) {
     d.jnt_armature = jarm.data();
     d.jnt_range = jrange.data();
     d.jnt_damping = jdamp.data();
+    d.geom_condim = gdim.data();
     d.geom_type = gtype.data(); d.geom_body = gbody.data(); d.geom_contype = gct.data(); d.geom_conaffinity = gca.data();
     d.geom_pos = gpos.data(); d.geom_quat = gquat.data(); d.geom_size = gsize.data(); d.geom_friction = gfric.data();
     d.geom_margin = gmarg.data();

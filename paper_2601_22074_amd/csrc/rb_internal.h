@@ -97,6 +97,7 @@ struct DevModel {
     const float* pair_sigma;   // +1 if the moving body carries g2, -1 if it carries g1
     const float* pair_mu;      // friction when it is not per world
     const float* pair_margin;
+    const int* pair_frictionless;  // 1 when the pair's larger geom condim is 1 (normal row only)
     const int* geom_body;
     const float* geom_pos;     // [3]
     const float* geom_quat;    // [4]

@@ -329,6 +329,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     for (int g = 0; g < ng; g++) {
         int t = d->geom_type[g], b = d->geom_body[g];
         if (t < RB_GEOM_PLANE || t > RB_GEOM_BOX) return fail(RB_EINVAL, "unknown geom type");
+        if (d->geom_condim && d->geom_condim[g] != 1 && d->geom_condim[g] != 3)
+            return fail(RB_EINVAL, "geom condim must be 1 or 3");
         if (b < 0 || b >= nb) return fail(RB_EINVAL, "geom on an invalid body");
         if (t == RB_GEOM_PLANE && movable[b]) return fail(RB_EINVAL, "a plane must be on a static body");
         const double* q = d->geom_quat + 4 * g;
@@ -364,6 +366,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     std::vector<int> pg1(npair), pg2(npair), ptype(npair), pbody(npair), pcap(npair), pslot(npair, -1);
     int nbb = 0;
     std::vector<double> psig(npair), pmu(npair), pmar(npair);
+    std::vector<int> pfric0(npair, 0);
     int maxcon = 0;
     for (int k = 0; k < npair; k++) {
         int g1 = pairs[k].g1, g2 = pairs[k].g2;
@@ -378,6 +381,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         psig[k] = mov2 ? 1.0 : -1.0;
         pmu[k] = std::max(d->geom_friction[g1], d->geom_friction[g2]);
         pmar[k] = std::max(d->geom_margin[g1], d->geom_margin[g2]);
+        if (d->geom_condim) pfric0[k] = std::max(d->geom_condim[g1], d->geom_condim[g2]) == 1;
         pcap[k] = (ptype[k] == RB_GEOM_SPHERE || ptype[k] == RB_PAIR_SPHEREBOX) ? 1 : (ptype[k] == RB_GEOM_CAPSULE ? 2 : 8);
         maxcon += pcap[k];
     }
@@ -535,7 +539,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     I(jtype, &m.jnt_type); I(jq, &m.jnt_qadr); I(jd, &m.jnt_dadr);
     I(pg1, &m.pair_g1); I(pg2, &m.pair_g2); I(ptype, &m.pair_type); I(pbody, &m.pair_body); I(pcap, &m.pair_cap);
     I(pslot, &m.pair_slot);
-    F(psig, &m.pair_sigma); F(pmu, &m.pair_mu); F(pmar, &m.pair_margin);
+    F(psig, &m.pair_sigma); F(pmu, &m.pair_mu); F(pmar, &m.pair_margin); I(pfric0, &m.pair_frictionless);
     I(std::vector<int>(d->geom_body, d->geom_body + ng), &m.geom_body);
     F(std::vector<double>(d->geom_pos, d->geom_pos + 3 * ng), &m.geom_pos);
     F(std::vector<double>(d->geom_quat, d->geom_quat + 4 * ng), &m.geom_quat);
@@ -559,7 +563,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.nlim = nlim;
     m.ndamp = ndamp;
-    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0) ? 1 : 0;
+    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
+             std::count(pfric0.begin(), pfric0.end(), 1) > 0) ? 1 : 0;
     m.dt = (float)d->timestep;
     for (int i = 0; i < 3; i++) m.grav[i] = (float)d->gravity[i];
     m.tol_scale = (float)(d->tolerance * meaninertia * nv);

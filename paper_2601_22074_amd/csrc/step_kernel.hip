@@ -787,7 +787,8 @@ struct StepArgs {
 // MAXD: longest dof chain the instantiation supports; TIMED: the diagnostic instantiation that
 // serves rb_step_taps (stage taps, work totals and per-stage shader-clock cycles); the plain
 // instantiation carries none of that code.  EXT: the extended instantiation, with the code of
-// box-box and sphere-box pairs, joint limits and joint damping, used for models that have any.
+// box-box and sphere-box pairs, frictionless pairs, joint limits and joint damping, used for
+// models that have any.
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
@@ -1159,6 +1160,12 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             C.body = m.pair_body[src];
             C.sigma = m.pair_sigma[src];
             C.mu = m.fr_pw ? mu_world : m.pair_mu[src];
+            if (EXT && m.pair_frictionless[src]) {
+                // frictionless pair: mu = 0 makes the four rows the normal row; only the first
+                // is kept (the others get D = 0 below)
+                C.mu = 0.f;
+                C.ids |= 1 << 24;
+            }
             margin_c = m.pair_margin[src];
         } else {
             C.body = 0;
@@ -1245,6 +1252,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 float R = fmaxf(1e-15f, (1.0f - imp) / imp * ah[e]);
                 C.D[e] = 1.0f / R;
             }
+            if (EXT && (C.ids >> 24)) C.D[1] = C.D[2] = C.D[3] = 0.f;
             if (TIMED && A.want_taps && sub == 0 && A.taps.efc) {
                 float* E = A.taps.efc + ((size_t)w * m.ncap + lane) * 12;
                 for (int e = 0; e < 4; e++) {

@@ -58,7 +58,7 @@ class _Desc(C.Structure):
                 ("timestep", C.c_double), ("nsubsteps", C.c_int32), ("gravity", C.c_double * 3),
                 ("iterations", C.c_int32), ("tolerance", C.c_double), ("solref", C.c_double * 2),
                 ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32),
-                ("jnt_range", _f64p), ("jnt_damping", _f64p)]
+                ("jnt_range", _f64p), ("jnt_damping", _f64p), ("geom_condim", _i32p)]
 
 
 class _Info(C.Structure):
@@ -181,6 +181,7 @@ def marshal_desc(model: dict):
     d.mass_scale_per_world = int(bool(model["per_world"].get("mass_scale")))
     d.jnt_range = f64([j.get("range", [0.0, 0.0]) for j in Jt] or [0.0, 0.0])
     d.jnt_damping = f64([j.get("damping", 0.0) for j in Jt] or [0.0])
+    d.geom_condim = i32([g.get("condim", 3) for g in G] or [3])
     return d, keep
 
 

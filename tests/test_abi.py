@@ -43,7 +43,7 @@ def _create_error(m):
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
                                   "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
-                                  "negative_damping"])
+                                  "negative_damping", "condim"])
 def test_invalid_models_rejected(rb, case):
     m = robots.quadruped()
     if case == "parent":
@@ -72,6 +72,8 @@ def test_invalid_models_rejected(rb, case):
         m["joints"][0]["damping"] = 1.0
     elif case == "negative_damping":
         m["joints"][2]["damping"] = -1.0
+    elif case == "condim":
+        m["geoms"][1]["condim"] = 4
     rc, msg = _create_error(m)
     assert rc == -1, (rc, msg)
     assert msg
@@ -87,7 +89,7 @@ def _create_json_error(text):
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
                                   "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
-                                  "negative_damping"])
+                                  "negative_damping", "condim"])
 def test_json_models_validated_like_descriptions(rb, case):
     """The JSON entry point hands the same description to the same validation: every invalid
     model above is rejected with the message the struct entry point gives."""
@@ -119,6 +121,8 @@ def test_json_models_validated_like_descriptions(rb, case):
         m["joints"][0]["damping"] = 1.0
     elif case == "negative_damping":
         m["joints"][2]["damping"] = -1.0
+    elif case == "condim":
+        m["geoms"][1]["condim"] = 4
     rc_d, msg_d = _create_error(m)
     rc_j, msg_j = _create_json_error(json.dumps(m))
     assert (rc_j, msg_j) == (rc_d, msg_d)

@@ -89,7 +89,7 @@ def test_single_step_from_initial_states(oracle_mod, name):
 @pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150), ("arm_box", 150),
                                           ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 150),
                                           ("quadruped_terrain", 200), ("humanoid_terrain", 100),
-                                          ("humanoid_damp", 150)])
+                                          ("humanoid_damp", 150), ("quadruped_slip", 200)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory, hand its state (rounded to FP32) to the GPU at
     sampled steps and compare one env step.  Samples where a moving contact starts a substep
@@ -223,7 +223,8 @@ def test_chain3_500_steps(oracle_mod):
 
 
 # ------------------------------------------------------------------ contact sets
-@pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain", "humanoid_terrain"])
+@pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain", "humanoid_terrain",
+                                  "quadruped_slip"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -275,6 +276,41 @@ def test_box_box_contacts_random_poses(oracle_mod):
         assert np.abs(c["frame"][w, :nc].reshape(nc, 9) - t["frame"].reshape(nc, 9)).max() <= 2e-5, f"world {w}"
         kinds.add(nc)
     assert 1 in kinds and 4 in kinds
+
+
+def test_frictionless_box_slides_gpu(oracle_mod):
+    """A frictionless box (condim 1) on a 0.3 rad incline accelerates downhill at g sin(theta)
+    on the HIP path too, with zero tangential contact force."""
+    import torch
+    import paper_2601_22074_amd as rb
+    th, h = 0.3, 0.05
+    mb = robots.ModelBuilder("incline", timestep=0.002, nsubsteps=1)
+    mb.geom(0, "plane", [0, 0, 0], quat=robots.quat_axis_angle([0, 1, 0], th), contype=0, conaffinity=1)
+    mb.geoms[-1]["condim"] = 1
+    b = mb.body("box", 0, (0, 0, 1), 1.0, robots.box_inertia(1.0, h, h, h))
+    mb.joint(b, "free")
+    mb.geom(b, "box", [h, h, h], contype=1, conaffinity=0)
+    mb.geoms[-1]["condim"] = 1                   # the pair takes the larger of the two
+    m = mb.build()
+    R = rot(robots.quat_axis_angle([0, 1, 0], th))
+    q0 = np.concatenate([R[:, 2] * (h - 1e-4), robots.quat_axis_angle([0, 1, 0], th)])
+    M = rb.Model(m)
+    B = rb.Batch(M, 4)
+    q = torch.tensor(np.tile(q0, (4, 1)), dtype=torch.float32, device="cuda")
+    v = torch.zeros(4, 6, device="cuda")
+    u = torch.zeros(4, 0, device="cuda")
+    con = B.contacts(4)
+    vs = []
+    for _ in range(600):
+        B.step(u, q, v, con)
+        vs.append(v[0, :3].cpu().numpy().astype(np.float64))
+    f = con.force[0, :int(con.ncon[0].item())].cpu().numpy()
+    B.close()
+    M.close()
+    a = np.diff(np.array(vs) @ R[:, 0])[-100:] / 0.002
+    assert np.abs(a.mean() - 9.81 * np.sin(th)) <= 1e-3 * 9.81 * np.sin(th)
+    assert f.shape[0] == 4 and np.abs(f[:, 1:]).max() == 0.0
+    assert abs(f[:, 0].sum() - 9.81 * np.cos(th)) <= 1e-3 * 9.81
 
 
 def test_sphere_box_contacts_random_poses(oracle_mod):

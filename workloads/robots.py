@@ -456,6 +456,16 @@ def humanoid_damp() -> dict:
     return with_damping(humanoid(), 0.5, "humanoid_damp")
 
 
+def quadruped_slip() -> dict:
+    """quadruped whose sphere feet are frictionless (condim 1) against the ground."""
+    m = quadruped()
+    m["name"] = "quadruped_slip"
+    for g in m["geoms"]:
+        if g["type"] == "sphere":
+            g["condim"] = 1
+    return m
+
+
 def chain3_lim() -> dict:
     """chain3 with every hinge limited to +-0.6 rad."""
     return with_limits(chain3(), -0.6, 0.6, "chain3_lim")
@@ -474,7 +484,7 @@ def humanoid_lim() -> dict:
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
                 "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
-                "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp}
+                "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp, "quadruped_slip": quadruped_slip}
 
 
 def by_name(name: str) -> dict:
