@@ -154,7 +154,7 @@ def test_malformed_json_rejected(rb, mutate, needle):
 
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim",
                                   "humanoid_lim", "quadruped_terrain", "humanoid_terrain", "chain3_damp",
-                                  "humanoid_damp"])
+                                  "humanoid_damp", "quadruped_slip"])
 def test_model_files_match_generators(name):
     """workloads/models/<name>.json holds exactly what the generator builds (float values
     round-trip through JSON unchanged)."""
