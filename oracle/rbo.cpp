@@ -1204,7 +1204,7 @@ int rbo_forward(const void* mp, const double* qpos, const double* qvel, const do
     load_world(m, d, qpos, qvel, ctrl ? ctrl : zero.data(), qacc_ws, friction, mass_scale);
     forward(m, d);
     if (!t) return 0;
-    int nv = m.nv, nb = m.nbody, ng = m.ngeom, nc = (int)d.con.size();
+    int nb = m.nbody, ng = m.ngeom, nc = (int)d.con.size();
     auto put = [](double* dst, const std::vector<double>& src) {
         if (dst) std::copy(src.begin(), src.end(), dst);
     };
