@@ -131,6 +131,8 @@ struct Parser {
             v.kind = JVal::NUM;
             v.num = std::strtod(s + i, &end);
             if (end == s + i) return fail("bad number");
+            // JSON numbers are finite; strtod would also take "-inf" and "-nan"
+            if (!std::isfinite(v.num)) return fail("non-finite number");
             i = (size_t)(end - s);
             return true;
         }

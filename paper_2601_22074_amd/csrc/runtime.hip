@@ -143,6 +143,24 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     if (nb < 2) return fail(RB_EINVAL, "model needs at least one body besides the world");
     if (nj < 1) return fail(RB_EINVAL, "model needs at least one joint");
     if (ng < 0 || nu < 0) return fail(RB_EINVAL, "negative sizes");
+    // every real number of the description must be finite
+    auto finite = [](const double* x, int n) {
+        for (int i = 0; i < n; i++)
+            if (!std::isfinite(x[i])) return false;
+        return true;
+    };
+    const struct { const double* x; int n; const char* what; } reals[] = {
+        {d->body_pos, 3 * nb, "body pos"}, {d->body_quat, 4 * nb, "body quat"}, {d->body_ipos, 3 * nb, "body ipos"},
+        {d->body_iquat, 4 * nb, "body iquat"}, {d->body_mass, nb, "body mass"}, {d->body_inertia, 3 * nb, "body inertia"},
+        {d->jnt_pos, 3 * nj, "joint pos"}, {d->jnt_axis, 3 * nj, "joint axis"}, {d->jnt_armature, nj, "joint armature"},
+        {d->geom_pos, 3 * ng, "geom pos"}, {d->geom_quat, 4 * ng, "geom quat"}, {d->geom_size, 3 * ng, "geom size"},
+        {d->geom_friction, ng, "geom friction"}, {d->geom_margin, ng, "geom margin"}, {d->act_kp, nu, "actuator kp"},
+        {d->act_kd, nu, "actuator kd"}, {d->act_gear, nu, "actuator gear"}, {&d->timestep, 1, "timestep"},
+        {d->gravity, 3, "gravity"}, {&d->tolerance, 1, "tolerance"}, {d->solref, 2, "solref"}, {d->solimp, 5, "solimp"}};
+    for (const auto& r : reals) {
+        if (r.n > 0 && !r.x) return fail(RB_EINVAL, std::string("missing ") + r.what);
+        if (r.n > 0 && !finite(r.x, r.n)) return fail(RB_EINVAL, std::string("non-finite ") + r.what);
+    }
     auto P = [&](int b) { return d->body_parent[b]; };
     for (int b = 1; b < nb; b++)
         if (P(b) < 0 || P(b) >= b) return fail(RB_EINVAL, "body parent must precede the body");

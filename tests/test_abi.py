@@ -43,7 +43,7 @@ def _create_error(m):
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
                                   "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
-                                  "negative_damping", "condim"])
+                                  "negative_damping", "condim", "nan_pos", "inf_size"])
 def test_invalid_models_rejected(rb, case):
     m = robots.quadruped()
     if case == "parent":
@@ -74,6 +74,10 @@ def test_invalid_models_rejected(rb, case):
         m["joints"][2]["damping"] = -1.0
     elif case == "condim":
         m["geoms"][1]["condim"] = 4
+    elif case == "nan_pos":
+        m["bodies"][2]["pos"][0] = float("nan")
+    elif case == "inf_size":
+        m["geoms"][1]["size"][0] = float("inf")
     rc, msg = _create_error(m)
     assert rc == -1, (rc, msg)
     assert msg
@@ -89,7 +93,7 @@ def _create_json_error(text):
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
                                   "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
-                                  "negative_damping", "condim"])
+                                  "negative_damping", "condim", "nan_pos", "inf_size"])
 def test_json_models_validated_like_descriptions(rb, case):
     """The JSON entry point hands the same description to the same validation: every invalid
     model above is rejected with the message the struct entry point gives."""
@@ -123,8 +127,16 @@ def test_json_models_validated_like_descriptions(rb, case):
         m["joints"][2]["damping"] = -1.0
     elif case == "condim":
         m["geoms"][1]["condim"] = 4
+    elif case == "nan_pos":
+        m["bodies"][2]["pos"][0] = float("nan")
+    elif case == "inf_size":
+        m["geoms"][1]["size"][0] = float("inf")
     rc_d, msg_d = _create_error(m)
     rc_j, msg_j = _create_json_error(json.dumps(m))
+    if case in ("nan_pos", "inf_size"):
+        # JSON has no NaN or infinity: the parser already refuses the text
+        assert rc_j == -1 and "model JSON" in msg_j, msg_j
+        return
     assert (rc_j, msg_j) == (rc_d, msg_d)
 
 
@@ -140,6 +152,7 @@ def test_json_models_validated_like_descriptions(rb, case):
     (lambda s: s.replace('"joints"', '"joint_list"', 1), "model: missing \"joints\""),
     (lambda s: "[" + s + "]", "not an object"),
     (lambda s: "", "offset 0"),
+    (lambda s: s.replace('"mass": 6.0', '"mass": -inf', 1), "non-finite number"),
     (lambda s: s.replace('"armature": 0.01}', '"armature": 0.01, "range": [0.1]}', 1), "\"range\" is not an array of 2"),
 ])
 def test_malformed_json_rejected(rb, mutate, needle):
