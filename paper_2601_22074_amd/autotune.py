@@ -19,10 +19,13 @@ CACHE = os.environ.get("RBSTEP_TUNE_CACHE", os.path.join(os.path.expanduser("~")
 
 
 def signature(batches, ns) -> str:
+    """Key of a tuning decision: each batch's model description, contact capacity and world
+    count (two models of equal sizes but different features must not share a decision)."""
     h = hashlib.sha256()
     for b, n in zip(batches, ns):
         m = b.model
-        h.update(f"{m.nq},{m.nv},{m.nu},{m.nbody},{m.npair},{m.lds_bytes},{b.ncap},{n};".encode())
+        desc = json.dumps(m.desc, sort_keys=True, default=str)
+        h.update(f"{hashlib.sha256(desc.encode()).hexdigest()},{m.lds_bytes},{b.ncap},{n};".encode())
     return h.hexdigest()[:20]
 
 
