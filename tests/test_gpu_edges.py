@@ -99,3 +99,38 @@ def test_fused_plan_with_an_empty_batch():
             x.close()
     np.testing.assert_array_equal(out[0][0], out[1][0])
     np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_plain_step_in_a_captured_graph():
+    """The plain step records into a HIP graph (torch.cuda.graph); every replay, with eager
+    work between them, matches the eager steps bit for bit."""
+    import torch
+    import paper_2601_22074_amd as rb
+    m, M, B = _batch(rb, torch, "humanoid", 128)
+    q0, v0 = inputs.initial_state(m, "humanoid", range(128))
+    u = torch.tensor(inputs.ctrl_table(m, "humanoid", range(128), 1)[0], device="cuda")
+    # eager reference: 4 steps, state after each
+    qe, ve = torch.tensor(q0, device="cuda"), torch.tensor(v0, device="cuda")
+    ws0 = torch.zeros(128, M.nv, device="cuda")
+    ref = []
+    for _ in range(4):
+        B.step(u, qe, ve)
+        ref.append((qe.cpu().numpy(), ve.cpu().numpy()))
+    # the same from the same start, replayed from a graph of one step
+    B.reset(torch.arange(128, dtype=torch.int32, device="cuda"), ws0)
+    qg, vg = torch.tensor(q0, device="cuda"), torch.tensor(v0, device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    # capture records without running, so the graph starts from the same state
+    with torch.cuda.graph(graph, stream=side):
+        B.step(u, qg, vg)
+    torch.cuda.synchronize()
+    for k in range(4):
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = float(qg.sum())                       # eager work between replays
+        np.testing.assert_array_equal(qg.cpu().numpy(), ref[k][0])
+        np.testing.assert_array_equal(vg.cpu().numpy(), ref[k][1])
+    B.close()
+    M.close()
