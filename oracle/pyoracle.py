@@ -61,6 +61,12 @@ class _Taps(C.Structure):
 
 _lib = None
 
+FPITER = 4                 # active-set fingerprints per substep (rbo.h)
+SUBCOLS = 5 + FPITER       # per-substep work columns
+NSTAGE = 7                 # operation-count stages
+STAGES = ("kinematics", "inertia and bias", "factorisation and a0", "collision", "constraint rows", "newton",
+          "integration")
+
 
 def build_if_missing() -> None:
     if not os.path.exists(_build.LIB):
@@ -80,6 +86,10 @@ def lib():
         L.rbo_forward.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, C.POINTER(_Taps)]
         L.rbo_step.argtypes = [C.c_void_p, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
                                C.POINTER(C.c_uint32), C.POINTER(_Contacts), C.c_int32]
+        L.rbo_step_work.argtypes = [C.c_void_p, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                    C.POINTER(C.c_uint32), C.POINTER(_Contacts), _i32p, _f64p, C.c_int32]
+        L.rbo_line_search.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                      _f64p, _f64p]
         L.rbo_energy.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p]
         L.rbo_jacobian.argtypes = [C.c_void_p, _f64p, C.c_int32, _f64p, _f64p, _f64p]
         L.rbo_integrate.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p]
@@ -202,8 +212,13 @@ class Oracle:
         return out
 
     def step(self, ctrl, qpos, qvel, qacc_ws, friction=None, mass_scale=None, status=None, contacts=False,
-             nthreads=0):
-        """One env step (K substeps) for n worlds, in place on float64 arrays; returns (status, contacts)."""
+             nthreads=0, work=None):
+        """One env step (K substeps) for n worlds, in place on float64 arrays; returns (status, contacts).
+
+        work: an optional dict that receives ``sub`` [n, K, SUBCOLS] int32 (per substep: contacts,
+        rows, Newton updates, active rows at the solution, line-search segments, active-set
+        fingerprints of the first FPITER updates) and ``ops`` [n, 2, NSTAGE] float64 (operation
+        counts per stage: the oracle's plain definitions, the tree-sparse formulation)."""
         n = qpos.shape[0]
         for a in (qpos, qvel, qacc_ws):
             assert a.dtype == np.float64 and a.flags.c_contiguous
@@ -221,10 +236,34 @@ class Oracle:
             cs = _Contacts()
             for k, v in out.items():
                 setattr(cs, k, v.ctypes.data_as(_i32p if v.dtype == np.int32 else _f64p))
-        _check(lib().rbo_step(self._h, n, _f(u), _f(qpos), _f(qvel), _f(qacc_ws), _f(fr), _f(ms),
-                              st.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(cs) if cs is not None else None,
-                              int(nthreads)))
+        if work is None:
+            _check(lib().rbo_step(self._h, n, _f(u), _f(qpos), _f(qvel), _f(qacc_ws), _f(fr), _f(ms),
+                                  st.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(cs) if cs is not None else None,
+                                  int(nthreads)))
+        else:
+            K = self.model["opt"]["nsubsteps"]
+            sub = np.zeros((n, K, SUBCOLS), np.int32)
+            ops = np.zeros((n, 2, NSTAGE), np.float64)
+            _check(lib().rbo_step_work(self._h, n, _f(u), _f(qpos), _f(qvel), _f(qacc_ws), _f(fr), _f(ms),
+                                       st.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                       C.byref(cs) if cs is not None else None, sub.ctypes.data_as(_i32p),
+                                       ops.ctypes.data_as(_f64p), int(nthreads)))
+            work["sub"] = sub
+            work["ops"] = ops
         return st, out
+
+    def line_search(self, qpos, qvel, a, p, ctrl=None, qacc_ws=None, friction=None, mass_scale=None):
+        """(f(a), alpha*) for the rows of one substep's state: the constraint cost at a and the
+        exact line search's step along p."""
+        nv = self.nv
+        u = _d(ctrl if ctrl is not None else np.zeros(self.nu), self.nu) if self.nu else None
+        ws = _d(qacc_ws, nv) if qacc_ws is not None else None
+        fr = _d([friction]) if friction is not None else None
+        ms = _d(mass_scale, self.nbody) if mass_scale is not None else None
+        c, al = C.c_double(), C.c_double()
+        _check(lib().rbo_line_search(self._h, _f(_d(qpos, self.nq)), _f(_d(qvel, nv)), _f(u), _f(ws), _f(fr),
+                                     _f(ms), _f(_d(a, nv)), _f(_d(p, nv)), C.byref(c), C.byref(al)))
+        return c.value, al.value
 
     def energy(self, qpos, qvel, mass_scale=None):
         T, V = C.c_double(), C.c_double()

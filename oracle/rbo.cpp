@@ -101,6 +101,8 @@ struct Model {
     std::vector<int> atype, ajoint;
     std::vector<double> akp, akd, agear;
     std::vector<int> movable;  // body has a joint on its path to the world
+    std::vector<int> dof_depth;    // dofs on the dof's chain from the root, itself included
+    std::vector<int> body_cdepth;  // dofs on the body's chain from the root
     double dt = 0.005;
     int K = 1;
     double grav[3] = {0, 0, -9.81};
@@ -138,6 +140,13 @@ struct Data {
     int niter = 0;
     bool itercap = false;   // the Newton loop used every iteration without meeting a tolerance
     double cost = 0;
+    // work record of the substep (for the work and operation-count outputs)
+    std::vector<int> row_id;        // per row: 4 c + e (pyramid row e of contact c), 256 + dof (limit)
+    std::vector<int> row_nnz;       // per row: non-zero Jacobian entries (the dofs it touches)
+    int segments = 0;               // quadratic pieces the line searches examined
+    int active_final = 0;           // rows active at the solution
+    uint32_t fp[RBO_FPITER] = {};   // active-set fingerprint before each of the first Newton updates
+    std::vector<std::vector<int>> act_iter;   // rows active when each Newton Hessian was formed
 
     explicit Data(const Model* mm) : m(mm) {
         int nb = m->nbody, nv = m->nv, nj = m->njnt, ng = m->ngeom;
@@ -750,6 +759,8 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
     }
     d.nrows = nr + nl;
     d.J.assign((size_t)d.nrows * nv, 0.0);
+    d.row_id.assign(d.nrows, 0);
+    d.row_nnz.assign(d.nrows, 0);
     d.aref.assign(d.nrows, 0.0);
     d.D.assign(d.nrows, 0.0);
     d.Ahat.assign(d.nrows, 0.0);
@@ -761,6 +772,7 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
     // reference acceleration and regulariser of row `row` (Jacobian already in place)
     auto finish_row = [&](int row, double rdist) {
         const double* Je = &d.J[(size_t)row * nv];
+        for (int k = 0; k < nv; k++) d.row_nnz[row] += Je[k] != 0.0;
         double imp = impedance(m, rdist);
         double vel = 0;
         for (int k = 0; k < nv; k++) vel += Je[k] * d.v[k];
@@ -789,12 +801,14 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
             double sgn = (e % 2 == 0) ? 1.0 : -1.0;
             double* Je = &d.J[(size_t)row * nv];
             for (int k = 0; k < nv; k++) Je[k] = Jc[k] + sgn * c.mu * Jc[t * nv + k];
+            d.row_id[row] = 4 * ci + e;
             finish_row(row, rdist);
         }
     }
     for (int l = 0; l < nl; l++) {
         int row = nr + l;
         d.J[(size_t)row * nv + ldof[l]] = lsgn[l];
+        d.row_id[row] = 256 + ldof[l];
         finish_row(row, ldist[l]);
     }
 }
@@ -816,7 +830,8 @@ double cost(const Model& m, const Data& d, const double* a) {
 }
 
 // exact minimiser over alpha >= 0 of the convex piecewise quadratic phi(alpha) = f(a + alpha p)
-double line_search(const Model& m, const Data& d, const std::vector<double>& jar, const std::vector<double>& p) {
+double line_search(const Model& m, const Data& d, const std::vector<double>& jar, const std::vector<double>& p,
+                   int* nseg) {
     int nv = m.nv, nr = d.nrows;
     bool any = false;
     for (int k = 0; k < nv; k++) any |= (p[k] != 0);
@@ -844,6 +859,7 @@ double line_search(const Model& m, const Data& d, const std::vector<double>& jar
     for (int e = 0; e < nr; e++) act[e] = (jar[e] < 0) || (jar[e] == 0 && s[e] < 0);
     size_t i = 0;
     while (true) {
+        if (nseg) ++*nseg;
         double A = A0, B = B0;
         for (int e = 0; e < nr; e++)
             if (act[e]) {
@@ -868,6 +884,10 @@ void newton(const Model& m, Data& d) {
     d.niter = 0;
     d.itercap = false;
     d.a = d.a0;
+    d.segments = 0;
+    d.active_final = 0;
+    std::fill(d.fp, d.fp + RBO_FPITER, 0u);
+    d.act_iter.clear();
     if (nr == 0) {
         d.efc_force.assign(0, 0.0);
         d.cost = 0;
@@ -899,11 +919,21 @@ void newton(const Model& m, Data& d) {
         double gn = 0;
         for (int k = 0; k < nv; k++) gn += g[k] * g[k];
         if (std::sqrt(gn) / scale < tol) { stopped = true; break; }
+        // record the active set this update is built from
+        std::vector<int> act;
+        uint32_t fp = 0;
+        for (int e = 0; e < nr; e++)
+            if (jar[e] < 0) {
+                act.push_back(e);
+                fp += ((uint32_t)d.row_id[e] + 1u) * 2654435761u;
+            }
+        if (it < RBO_FPITER) d.fp[it] = fp;
+        d.act_iter.push_back(act);
         if (!cholesky(H, nv, LH)) { stopped = true; break; }
         std::vector<double> ng(nv);
         for (int k = 0; k < nv; k++) ng[k] = -g[k];
         chol_solve(LH, nv, ng.data(), p.data());
-        double alpha = line_search(m, d, jar, p);
+        double alpha = line_search(m, d, jar, p, &d.segments);
         double fold = cost(m, d, d.a.data());
         for (int k = 0; k < nv; k++) anew[k] = d.a[k] + alpha * p[k];
         double fnew = cost(m, d, anew.data());
@@ -918,7 +948,132 @@ void newton(const Model& m, Data& d) {
         double t = -d.aref[e];
         for (int k = 0; k < nv; k++) t += d.J[(size_t)e * nv + k] * d.a[k];
         d.efc_force[e] = -d.D[e] * std::min(t, 0.0);
+        d.active_final += t < 0;
     }
+}
+
+// ------------------------------------------------------------------------------------
+// operation counts of one substep (work outputs; a multiply-add counts 2).  Unit costs of the
+// small kernels used throughout: 3x3 matrix-vector 15, 3x3 matrix product 45, quaternion
+// product 28, quaternion to matrix 39, cross product 9, dot product 5, spatial inertia times
+// motion vector 45, spatial cross product 30, spatial dot product 11.
+// ------------------------------------------------------------------------------------
+enum { ST_KIN, ST_DYN, ST_FAC, ST_COL, ST_ROW, ST_NEWTON, ST_INT };
+
+double chol_ops(int n) {   // cholesky(): per column j, 2j + 1 for the diagonal, 2j + 1 per row below
+    double f = 0;
+    for (int j = 0; j < n; j++) f += 2.0 * j + 1 + (double)(n - 1 - j) * (2.0 * j + 1);
+    return f;
+}
+
+// primitive tests of the collision pairs (plane-sphere, plane-capsule ends, plane-box vertices,
+// sphere-box closest point, box-box separating axes and clipping) and per contact its frame
+double collision_ops(const Model& m, const Data& d) {
+    double f = 0;
+    for (int a = 0; a < m.ngeom; a++)
+        for (int b = a + 1; b < m.ngeom; b++) {
+            if (!pair_allowed(m, a, b)) continue;
+            int t1 = std::min(m.gtype[a], m.gtype[b]), t2 = std::max(m.gtype[a], m.gtype[b]);
+            if (t1 == RBO_GEOM_PLANE) f += t2 == RBO_GEOM_SPHERE ? 20 : (t2 == RBO_GEOM_CAPSULE ? 60 : 8 * 25);
+            else if (t1 == RBO_GEOM_SPHERE) f += 80;
+            else f += 15 * 40 + 300;
+        }
+    return f + 25.0 * d.con.size();
+}
+
+void count_ops(const Model& m, const Data& d, double* plain, double* tree) {
+    const int nv = m.nv, nb = m.nbody, nr = d.nrows, nc = (int)d.con.size();
+    int nh = 0, nf = 0;
+    for (int j = 0; j < m.njnt; j++) (m.jtype[j] == RBO_JNT_HINGE ? nh : nf)++;
+    double nM = 0, sumcd = 0, ldl = 0;
+    for (int i = 0; i < nv; i++) {
+        nM += m.dof_depth[i];
+        ldl += (double)(m.dof_depth[i] - 1) * m.dof_depth[i] + m.dof_depth[i];
+    }
+    for (int b = 1; b < nb; b++) sumcd += m.body_cdepth[b];
+    const double tsolve = 4 * (nM - nv) + nv, symmul = 4 * nM - 2 * nv, bmot = 12 * sumcd;
+    // stage 0, kinematics (one body at a time in either formulation): parent composition, the
+    // hinge's anchored rotation or the free joint's normalisation, rotation matrix; per body the
+    // centre of mass, mass and world inertia; per geom its pose
+    double kin = 46.0 * (nb - 1) + 163.0 * nh + 12.0 * nf + 39.0 * (nb - 1) + 211.0 * nb + 102.0 * m.ngeom;
+    plain[ST_KIN] += kin;
+    tree[ST_KIN] += kin;
+    // stage 1: plain -- per body its Jacobians (12 per hinge, 30 per free joint on the chain),
+    // m Jp'Jp + Jr' I Jr over all dof pairs, the bias wrench and its projection
+    double jac = 0;
+    for (int b = 1; b < nb; b++)
+        for (int bb = b; bb > 0; bb = m.parent[bb])
+            if (m.body_jnt[bb] >= 0) jac += m.jtype[m.body_jnt[bb]] == RBO_JNT_HINGE ? 12 : 30;
+    plain[ST_DYN] += 2 * jac + (nb - 1) * (15.0 * nv + 16.0 * nv * nv + 12.0 * nv + 45) + 90.0 * nh + 39.0 * nf + nh;
+    // tree: spatial inertias about a common origin, motion subspaces, recursive Newton-Euler
+    // (forward velocities and accelerations, body forces, backward sums, projection) and the
+    // composite-rigid-body rows M_ij = S_j . (Ic_i S_i) over each dof's chain
+    double crba = 0;
+    for (int i = 0; i < nv; i++) crba += 45 + 11.0 * m.dof_depth[i] + 1;
+    tree[ST_DYN] += 33.0 * (nb - 1) + 42.0 * nh + 27.0 * nf + 54.0 * nh + 198.0 * nf + 126.0 * (nb - 1) + 16.0 * (nb - 1) +
+                    11.0 * nv + crba;
+    // stage 2: factorisation of M and a0 = M^-1 (tau - c)
+    plain[ST_FAC] += chol_ops(nv) + 2.0 * nv * nv + nv;
+    tree[ST_FAC] += ldl + tsolve + nv;
+    // stage 3: collision
+    const double col = collision_ops(m, d);
+    plain[ST_COL] += col;
+    tree[ST_COL] += col;
+    // stage 4: constraint rows.  plain: per contact two point Jacobians and the frame product, per
+    // row its Jacobian, velocity, A-hat by a dense solve, impedance, aref and D.  tree: per
+    // contact the point-velocity Jacobian over the dofs it touches (27 per dof), the 3x3 block of
+    // J M^-1 J' by three half-solves over the chain, the pyramid combinations; per limit row one
+    // half-solve
+    double rows_plain = 0, rows_tree = 0;
+    for (int ci = 0; ci < nc; ci++) {
+        const Contact& c = d.con[ci];
+        double jc = 0;
+        for (int body : {c.b1, c.b2})
+            for (int bb = body; bb > 0; bb = m.parent[bb])
+                if (m.body_jnt[bb] >= 0) jc += m.jtype[m.body_jnt[bb]] == RBO_JNT_HINGE ? 12 : 30;
+        rows_plain += jc + 27.0 * nv;
+        const double dd = d.row_nnz[d.crow[ci]];
+        rows_tree += 27 * dd + 3 * dd * (dd - 1) + 16 * dd + 24 + 15 + 44 + 20;
+    }
+    for (int e = 0; e < nr; e++) {
+        rows_plain += (d.row_id[e] >= 256 ? 4.0 * nv : 7.0 * nv) + 2.0 * nv * nv + 26;
+        if (d.row_id[e] >= 256) rows_tree += d.row_nnz[e] * (d.row_nnz[e] - 1.0) + 3.0 * d.row_nnz[e] + 26;
+    }
+    plain[ST_ROW] += rows_plain;
+    tree[ST_ROW] += rows_tree;
+    // stage 5: Newton.  plain: costs, residuals, gradient and Hessian over all dofs, dense
+    // Cholesky and solves, the line search's products and segments.  tree: body motions and
+    // packed products through the tree, per active row its gradient and Hessian entries over
+    // the dofs it touches, the no-fill-in L'DL and its solves, per segment the active rows' sums
+    if (nr > 0) {
+        const double cost = 6.0 * nv * nv + nr * (2.0 * nv + 5);
+        const int nit = (int)d.act_iter.size();
+        double pl = 3 * cost + nr * (2.0 * nv + 3);
+        double tr = 2 * bmot + 2 * 20.0 * nc + 8.0 * nr + symmul + 4.0 * nv;
+        for (int it = 0; it < nit; it++) {
+            pl += nr * 2.0 * nv + 3.0 * nv * nv + 2.0 * nv + chol_ops(nv) + nv + 2.0 * nv * nv;   // jar, g, |g|, H, p
+            pl += nr * 2.0 * nv + 2.0 * nv * nv + 5.0 * nv + nr + 2.0 * nv + 2 * cost;             // line search, update
+            double hess = 0;
+            for (int e : d.act_iter[it]) {
+                pl += 3.0 * nv + 3.0 * nv * nv;
+                const double dd = d.row_nnz[e];
+                hess += 4 * dd + dd * (dd + 1);
+            }
+            double jrows = 0;
+            for (int ci = 0; ci < nc; ci++) jrows += 27.0 * d.row_nnz[d.crow[ci]];
+            tr += jrows + hess + nM + 2.0 * nv + ldl + tsolve;                     // gradient, Hessian, p
+            tr += symmul + bmot + 20.0 * nc + 4.0 * nv + nr + 6.0 * nv + 6.0 * nr;  // line search, update
+        }
+        // every examined segment sums the active rows' quadratic coefficients
+        pl += d.segments * (6.0 * nr + 2);
+        tr += d.segments * (6.0 * nr + 2);
+        plain[ST_NEWTON] += pl;
+        tree[ST_NEWTON] += tr;
+    }
+    // stage 6: semi-implicit Euler
+    const double integ = 2.0 * nv + 2.0 * nh + 64.0 * nf;
+    plain[ST_INT] += integ;
+    tree[ST_INT] += integ;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1108,6 +1263,18 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
     }
     M.movable.assign(nb, 0);
     for (int b = 1; b < nb; b++) M.movable[b] = M.movable[M.parent[b]] || M.body_jnt[b] >= 0;
+    M.body_cdepth.assign(nb, 0);
+    M.dof_depth.assign(M.nv, 0);
+    for (int b = 1; b < nb; b++) {
+        int e = M.body_cdepth[M.parent[b]];
+        int j = M.body_jnt[b];
+        if (j >= 0) {
+            int nd = M.jtype[j] == RBO_JNT_FREE ? 6 : 1;
+            for (int k = 0; k < nd; k++) M.dof_depth[M.jdadr[j] + k] = e + k + 1;
+            e += nd;
+        }
+        M.body_cdepth[b] = e;
+    }
     if (ng) {
         M.gtype.assign(dsc->geom_type, dsc->geom_type + ng);
         M.gbody.assign(dsc->geom_body, dsc->geom_body + ng);
@@ -1233,6 +1400,13 @@ int rbo_forward(const void* mp, const double* qpos, const double* qvel, const do
 
 int rbo_step(const void* mp, int32_t n, const double* ctrl, double* qpos, double* qvel, double* qacc_ws,
              const double* friction, const double* mass_scale, uint32_t* status, rbo_contacts* out, int32_t nthreads) {
+    return rbo_step_work(mp, n, ctrl, qpos, qvel, qacc_ws, friction, mass_scale, status, out, nullptr, nullptr,
+                         nthreads);
+}
+
+int rbo_step_work(const void* mp, int32_t n, const double* ctrl, double* qpos, double* qvel, double* qacc_ws,
+                  const double* friction, const double* mass_scale, uint32_t* status, rbo_contacts* out, int32_t* sub,
+                  double* ops, int32_t nthreads) {
     if (!mp || n < 0 || !qpos || !qvel || !qacc_ws || !status) return fail("null argument");
     const Model& m = *static_cast<const Model*>(mp);
     if (m.nu && !ctrl) return fail("ctrl required");
@@ -1255,11 +1429,25 @@ int rbo_step(const void* mp, int32_t n, const double* ctrl, double* qpos, double
             const double* ms = mass_scale ? mass_scale + (size_t)w * m.nbody : nullptr;
             int ncon = 0;
             status[w] &= ~2u;
+            int32_t* sw = sub ? sub + (size_t)w * m.K * RBO_SUBCOLS : nullptr;
+            double* ow = ops ? ops + (size_t)w * 2 * RBO_NSTAGE : nullptr;
+            if (sw) std::fill(sw, sw + m.K * RBO_SUBCOLS, 0);
+            if (ow) std::fill(ow, ow + 2 * RBO_NSTAGE, 0.0);
             if (!(status[w] & 1u)) {
                 for (int k = 0; k < m.K; k++) {
                     load_world(m, d, q, v, u, aws, fr, ms);
                     forward(m, d);
                     if (d.itercap) status[w] |= 2u;
+                    if (sw) {
+                        int32_t* r = sw + k * RBO_SUBCOLS;
+                        r[0] = (int32_t)d.con.size();
+                        r[1] = d.nrows;
+                        r[2] = d.niter;
+                        r[3] = d.active_final;
+                        r[4] = d.segments;
+                        for (int i = 0; i < RBO_FPITER; i++) r[5 + i] = (int32_t)d.fp[i];
+                    }
+                    if (ow) count_ops(m, d, ow, ow + RBO_NSTAGE);
                     integrate(m, q, v, d.aint.data(), q1.data(), v1.data());
                     if (!all_finite(q1.data(), m.nq) || !all_finite(v1.data(), m.nv) || !all_finite(d.aint.data(), m.nv)) {
                         status[w] |= 1u;
@@ -1286,6 +1474,29 @@ int rbo_step(const void* mp, int32_t n, const double* ctrl, double* qpos, double
                 }
             }
         }
+    }
+    return 0;
+}
+
+int rbo_line_search(const void* mp, const double* qpos, const double* qvel, const double* ctrl, const double* qacc_ws,
+                    const double* friction, const double* mass_scale, const double* a, const double* p, double* cost_out,
+                    double* alpha_out) {
+    if (!mp || !qpos || !qvel || !a || !p) return fail("null argument");
+    const Model& m = *static_cast<const Model*>(mp);
+    Data d(&m);
+    std::vector<double> zero(m.nu, 0.0);
+    load_world(m, d, qpos, qvel, ctrl ? ctrl : zero.data(), qacc_ws, friction, mass_scale);
+    forward(m, d);
+    std::copy(a, a + m.nv, d.a.begin());
+    if (cost_out) *cost_out = cost(m, d, d.a.data());
+    if (alpha_out) {
+        std::vector<double> jar(d.nrows), pv(p, p + m.nv);
+        for (int e = 0; e < d.nrows; e++) {
+            double t = -d.aref[e];
+            for (int k = 0; k < m.nv; k++) t += d.J[(size_t)e * m.nv + k] * d.a[k];
+            jar[e] = t;
+        }
+        *alpha_out = line_search(m, d, jar, pv, nullptr);
     }
     return 0;
 }

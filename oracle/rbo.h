@@ -95,6 +95,28 @@ typedef struct rbo_taps {
     int32_t* nrows;                             /* [1] constraint rows: 4 per contact, then limits */
 } rbo_taps;
 
+/* Work outputs of rbo_step_work.
+ *
+ * Per substep s < K of each world, RBO_SUBCOLS int32 ([n, K, RBO_SUBCOLS]):
+ *   0 contacts, 1 constraint rows, 2 Newton updates made, 3 rows active at the solution,
+ *   4 line-search segments examined (quadratic pieces whose minimiser was tried),
+ *   5 .. 5 + RBO_FPITER - 1: fingerprint of the active set each of the first RBO_FPITER Newton
+ *   updates was built from (0 past the last update).  The fingerprint of a set A of rows is
+ *   sum over e in A of (id_e + 1) * 2654435761 mod 2^32, with id = 4 c + e for pyramid row e of
+ *   contact c (a frictionless contact's one row has e = 0) and 256 + dof for a joint-limit row.
+ *
+ * Per world, 2 x RBO_NSTAGE doubles ([n, 2, RBO_NSTAGE]), summed over the K substeps: arithmetic
+ * operations (a multiply-add counts 2) of the stages kinematics, inertia and bias forces,
+ * factorisation and smooth acceleration, collision, constraint rows, Newton solve, integration;
+ * row 0 as this oracle's plain definitions perform them (dense Jacobian sums, dense Cholesky,
+ * brute-force pairs), row 1 for the recursive tree-sparse formulation of the same quantities
+ * (composite-rigid-body inertia, recursive Newton-Euler, no-fill-in L'DL over the dof tree,
+ * Jacobian rows over the dofs they touch, Hessian updates over those dofs), evaluated on this
+ * oracle's own contacts, rows, active sets, iterations and line-search segments. */
+#define RBO_FPITER 4
+#define RBO_SUBCOLS (5 + RBO_FPITER)
+#define RBO_NSTAGE 7
+
 const char* rbo_last_error(void);
 int rbo_model_create(const rbo_desc* d, void** out);
 void rbo_model_destroy(void* m);
@@ -115,6 +137,19 @@ int rbo_forward(const void* m, const double* qpos, const double* qvel, const dou
 int rbo_step(const void* m, int32_t n, const double* ctrl, double* qpos, double* qvel,
              double* qacc_ws, const double* friction, const double* mass_scale, uint32_t* status,
              rbo_contacts* contacts, int32_t nthreads);
+
+/* rbo_step plus the work outputs above: sub [n, K, RBO_SUBCOLS] and ops [n, 2, RBO_NSTAGE]
+ * (either may be NULL). */
+int rbo_step_work(const void* m, int32_t n, const double* ctrl, double* qpos, double* qvel,
+                  double* qacc_ws, const double* friction, const double* mass_scale, uint32_t* status,
+                  rbo_contacts* contacts, int32_t* sub, double* ops, int32_t nthreads);
+
+/* The constraint cost f(a) of one substep's state (rows built as in rbo_forward) and the exact
+ * line search of the Newton method from acceleration a along direction p:
+ * alpha = argmin over alpha >= 0 of f(a + alpha p) (cost_out, alpha_out nullable). */
+int rbo_line_search(const void* m, const double* qpos, const double* qvel, const double* ctrl,
+                    const double* qacc_ws, const double* friction, const double* mass_scale,
+                    const double* a, const double* p, double* cost_out, double* alpha_out);
 
 /* Energies of one world: kinetic 0.5 v'Mv and gravitational potential -sum m g.com. */
 int rbo_energy(const void* m, const double* qpos, const double* qvel, const double* mass_scale,
