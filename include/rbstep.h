@@ -118,16 +118,23 @@ typedef struct rb_contacts {
     float* force;      /* [n, cap, 3]  (normal, tangent 1, tangent 2) contact force */
 } rb_contacts;
 
+/* The message of this thread's last nonzero return.  Cites: no passage (error reporting of this
+ * library). */
 const char* rb_last_error(void);
 
 /* Validate and compile a model; uploads its constants to the current HIP device.
+ * Cites: paper, section "Architecture", paragraph "Scene pipeline" (a compiled model is
+ * transferred to the GPU, put_model), and its paragraph on the GPU physics backend (the static
+ * model shared by all worlds).
  * Rejects (RB_EINVAL): parent >= child, non-positive mass or inertia violating the
  * triangle inequality, non-unit quaternions, misplaced joints, unknown types,
  * collision pairs other than plane-{sphere, capsule, box}, box-box and sphere-box, pairs whose bodies can both
- * move, more than 64 dofs, 64 collision pairs or a dof chain deeper than 32. */
+ * move, more than 64 dofs, 64 collision pairs, 256 geoms or a dof chain deeper than 32. */
 int rb_model_create(const rb_model_desc* desc, rb_model** out);
 
-/* The same model as JSON text (NUL-terminated, owned by the caller): an object with
+/* The same model as JSON text (NUL-terminated, owned by the caller).  Cites: paper, section
+ * "Architecture", paragraph "Scene pipeline" (a scene description compiled into a model).
+ * The text is an object with
  *   "opt": {"timestep", "nsubsteps", "gravity": [3], "iterations", "tolerance",
  *           "solref": [2], "solimp": [5]},
  *   "bodies": [{"parent", "pos": [3], "quat": [4], "ipos": [3], "iquat": [4], "mass",
@@ -144,42 +151,72 @@ int rb_model_create(const rb_model_desc* desc, rb_model** out);
  * named in rb_last_error) before any device call; the parsed description then goes through
  * rb_model_create and its validation. */
 int rb_model_create_json(const char* json, rb_model** out);
+
+/* Release a model and its device constants (after every batch made from it).  Cites: paper,
+ * section "Architecture", paragraph "Scene pipeline". */
 void rb_model_destroy(rb_model* model);
+
+/* Sizes of a compiled model (rb_model_info), host memory owned by the caller.  RB_EINVAL on
+ * NULL.  Cites: paper, section "Architecture", paragraph on the GPU physics backend (the
+ * static model description). */
 int rb_model_info_get(const rb_model* model, rb_model_info* out);
 
 /* A batch of `capacity` world slots of one model: owns each world's warm start (qacc of
  * the previous substep), status word, per-world parameters and contact capacity.
  * contact_capacity <= 0 selects min(model maxcon, 64); at most 64.  Worlds start with a
- * zero warm start, status 0, friction = model friction and mass scale 1. */
+ * zero warm start, status 0, per-world friction 1.0 and mass scale 1 (the per-world values
+ * are read only by models that declare them per world).  RB_ENOMEM when the device memory
+ * cannot be allocated.  Cites: paper, section "Architecture", paragraph on the GPU physics
+ * backend (the time-varying state with a leading world dimension) and paragraph "Scene
+ * pipeline" (put_data). */
 int rb_batch_create(const rb_model* model, int32_t capacity, int32_t contact_capacity, rb_batch** out);
+
+/* Release a batch's device memory (after the work using it has completed).  Cites: as
+ * rb_batch_create. */
 void rb_batch_destroy(rb_batch* batch);
+
+/* Contact slots per world of the batch's contact output (0 for NULL).  Cites: as rb_step. */
 int32_t rb_batch_contact_capacity(const rb_batch* batch);
 
 /* Per-world parameters for slots [0, n): RB_PARAM_FRICTION takes [n] floats (friction of
  * every contact in the world; the model must have friction_per_world), RB_PARAM_MASS_SCALE
  * [n, nbody] floats (scales each body's mass and rotational inertia; the model must have
- * mass_scale_per_world).  Device pointer; copied on the stream. */
+ * mass_scale_per_world).  Device pointer; copied on the stream.  RB_EINVAL for another field,
+ * a model without that per-world field, or n outside [0, capacity].  Cites: paper, section
+ * "Architecture", paragraph on the GPU physics backend (model fields expanded to vary per
+ * world), and section "Manager-Based API", paragraph "Event manager" (domain randomisation
+ * writing per-world values). */
 int rb_batch_set_params(rb_batch* batch, int32_t field, int32_t n, const float* dev_vals, void* hip_stream);
 
 /* As rb_batch_set_params for slots [first, first + n): dev_vals holds those n worlds' values.
- * RB_EINVAL when the range leaves the batch. */
+ * RB_EINVAL when the range leaves the batch.  Cites: as rb_batch_set_params. */
 int rb_batch_set_params_at(rb_batch* batch, int32_t field, int32_t first, int32_t n, const float* dev_vals,
                            void* hip_stream);
 
 /* Resident waves per SIMD of this batch's plain launches: 3, 4, or 0 for the automatic choice
  * (4 when the model's LDS lets 16 worlds share a compute unit, its chain bound is at most 16
  * and the launch has more worlds than one round of 3 waves per SIMD holds; 3 otherwise).  4 is
- * ignored where the chain bound exceeds 16.  Results do not depend on it. */
+ * ignored where the chain bound exceeds 16.  Results do not depend on it.  Cites: no passage (a
+ * launch knob of this implementation). */
 int rb_batch_set_waves(rb_batch* batch, int32_t waves);
 
-/* Reset n worlds named by dev_ids [n] (int32, device): clear their status and set their
- * warm start from dev_qacc_ws [n, nv] (device; NULL = zero). */
+/* Reset n worlds named by dev_ids [n] (int32, device, each in [0, capacity)): clear their
+ * status and set their warm start from dev_qacc_ws [n, nv] (device; NULL = zero); the caller
+ * writes their qpos/qvel.  Cites: paper, section "Manager-Based API", pipeline step "Reset"
+ * (entity states reinitialised) and section "Architecture", paragraph "Scene pipeline"
+ * (put_data). */
 int rb_world_reset(rb_batch* batch, const int32_t* dev_ids, int32_t n, const float* dev_qacc_ws, void* hip_stream);
 
-/* Copy the warm start [n, nv] and status [n] of slots [0, n) out (either may be NULL). */
+/* Copy the warm start [n, nv] and status [n] of slots [0, n) out (either may be NULL; device
+ * pointers), for checkpoints: rb_world_reset with the saved warm start resumes bit for bit.
+ * Cites: paper, section "Architecture", paragraph on the GPU physics backend (the per-world
+ * time-varying state). */
 int rb_get_state(const rb_batch* batch, int32_t n, float* dev_qacc_ws, uint32_t* dev_status, void* hip_stream);
 
-/* One env step (K substeps) of slots [0, n).  dev_qpos [n, nq] and dev_qvel [n, nv] are
+/* One env step (K substeps) of slots [0, n).  Cites: paper, section "Manager-Based API",
+ * pipeline step "Simulate" (d decimation substeps with the controls held), and section
+ * "Manager-Based API", paragraph "Termination manager" (non-finite states caught per world).
+ * dev_qpos [n, nq] and dev_qvel [n, nv] are
  * read and overwritten in place; dev_ctrl [n, nu] is held for the K substeps (NULL when
  * nu = 0).  contacts (nullable) receives the last substep's contacts; dev_status [n]
  * (nullable) receives each world's status word.  A world with RB_STATUS_NONFINITE set is
@@ -192,11 +229,16 @@ int rb_step(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_qpos, 
  * way), plus per world dev_M [n, nv, nv] joint-space inertia, dev_bias [n, nv] bias forces
  * c(q, v), dev_a0 [n, nv] smooth acceleration, dev_qacc [n, nv] constrained acceleration of
  * the first substep, dev_efc [n, cap, 4, 3] per pyramid row (aref, D, A-hat), and
- * dev_stats [n, 14] int32 totals over the K substeps: contacts, pyramid rows active at the
- * solution, Newton iterations, line-search segments, then shader-clock cycles / 16 spent in
- * ten stages (kinematics; inertia, bias forces and M; factorisation of M and a0;
- * collision; constraint rows; Newton start; gradient and Hessian; Hessian factorisation
- * and solve; line search and update; integration).  Any output may be NULL. */
+ * dev_stats [n, 50] int32: totals over the K substeps of contacts, rows active at the
+ * solution, Newton updates and line-search segments; shader-clock cycles / 16 spent in ten
+ * stages (kinematics; inertia, bias forces and M; factorisation of M and a0; collision;
+ * constraint rows; Newton start; gradient and Hessian; Hessian factorisation and solve; line
+ * search and update; integration); then for each of the first 4 substeps 9 columns: contacts,
+ * constraint rows, Newton updates, rows active at the solution, line-search segments, and the
+ * fingerprint of the active set each of the first 4 updates was built from (sum over its rows
+ * of (id + 1) * 2654435761 mod 2^32, id = 4 c + e for pyramid row e of contact c, a
+ * frictionless contact's one row e = 0, 256 + dof for a joint-limit row; 0 past the last
+ * update).  Any output may be NULL.  Cites: as rb_step. */
 int rb_step_taps(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
                  const rb_contacts* contacts, uint32_t* dev_status, float* dev_M, float* dev_bias,
                  float* dev_a0, float* dev_qacc, float* dev_efc, int32_t* dev_stats, void* hip_stream);
@@ -215,19 +257,24 @@ enum { RB_ORDER_BATCH = 0,        /* batch after batch, worlds in index order */
        RB_ORDER_HEAVY_FIRST = 1,  /* most expensive batches first (by cost per world) */
        RB_ORDER_INTERLEAVE = 2 }; /* worlds of all batches interleaved in proportion */
 
-/* A plan over nbatch existing batches (not owned; they must outlive the plan). */
+/* A plan over nbatch existing batches (not owned; they must outlive the plan).  Cites: paper,
+ * section "Architecture", paragraph on the GPU physics backend (many worlds stepped at once). */
 int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out);
+
+/* Release a plan and its captured graph.  Cites: as rb_multi_create. */
 void rb_multi_destroy(rb_multi* plan);
 
 /* Step inputs of batch i for the following fused steps (device pointers as in rb_step,
- * slots [0, n)).  Copies a small argument block to the device; synchronous. */
+ * slots [0, n)).  Copies a small argument block to the device; synchronous.  Cites: as
+ * rb_step. */
 int rb_multi_bind(rb_multi* plan, int32_t i, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
                   const rb_contacts* contacts, uint32_t* dev_status);
 
 /* Dispatch order and grid of the fused launch.  cost [nbatch] (host, nullable) is the
  * relative cost of one world of each batch, used by RB_ORDER_HEAVY_FIRST (default: a
  * per-model estimate).  grid <= 0 launches one workgroup per world; grid > 0 launches that
- * many persistent workgroups walking the list.  Call after every batch is bound. */
+ * many persistent workgroups walking the list.  Call after every batch is bound.  Cites: no
+ * passage (a schedule of this implementation). */
 int rb_multi_set_schedule(rb_multi* plan, int32_t order, int32_t grid, const float* cost);
 
 /* An explicit work list instead of a schedule: host_items [n] (host memory, read before the
@@ -236,7 +283,8 @@ int rb_multi_set_schedule(rb_multi* plan, int32_t order, int32_t grid, const flo
  * the stream (through pinned staging owned by the plan), so later rb_multi_step calls on the
  * same stream use it and earlier ones keep the previous list; steps must therefore be issued
  * on that stream.  This is how a serving loop steps exactly the worlds of its live requests
- * without stopping the device.  RB_EINVAL on an item outside the bound batches. */
+ * without stopping the device.  RB_EINVAL on an item outside the bound batches.  Cites: no
+ * passage (the serving form's work list). */
 int rb_multi_set_items(rb_multi* plan, const int32_t* host_items, int32_t n, int32_t grid, void* hip_stream);
 
 /* Resident waves per SIMD of the fused launch: 4 selects the instantiation compiled for 4
@@ -244,16 +292,21 @@ int rb_multi_set_items(rb_multi* plan, const int32_t* host_items, int32_t n, int
  * compute unit); 3 the default one; 1 or 2 that one capped by giving each workgroup enough LDS
  * that no more fit; 0 the automatic choice (4 when the models fit and the work list is more
  * than one round of 3 waves per SIMD, else 3).  A schedule knob for the autotuner; results do
- * not depend on it. */
+ * not depend on it.  Cites: no passage. */
 int rb_multi_set_occupancy(rb_multi* plan, int32_t waves_per_simd);
 
 /* One env step of every scheduled world in one launch on the stream.  RB_ESTATE until a work
- * list has been set (rb_multi_set_schedule or rb_multi_set_items); an empty one is a no-op. */
+ * list has been set (rb_multi_set_schedule or rb_multi_set_items); an empty one is a no-op.
+ * Cites: paper, section "Manager-Based API", pipeline step "Simulate". */
 int rb_multi_step(rb_multi* plan, void* hip_stream);
 
 /* Capture nsteps fused steps into a graph on the (non-default) stream, replacing any earlier
- * capture; rb_multi_graph_launch replays them (all nsteps env steps) on a stream. */
+ * capture.  RB_ESTATE without a work list.  Cites: paper, section "Architecture", paragraph
+ * on the GPU physics backend (the simulation step recorded once as a graph and replayed). */
 int rb_multi_graph_capture(rb_multi* plan, int32_t nsteps, void* hip_stream);
+
+/* Replay the captured graph (all nsteps env steps) on a stream; RB_ESTATE when nothing has
+ * been captured.  Cites: as rb_multi_graph_capture. */
 int rb_multi_graph_launch(rb_multi* plan, void* hip_stream);
 
 #ifdef __cplusplus

@@ -10,8 +10,12 @@
 #define RB_MAX_DOF 64
 #define RB_MAX_PAIR 64
 #define RB_MAX_CON 64
+#define RB_MAX_GEOM 256           // contact ids pack geom indices into 8-bit fields
 #define RB_NSTAGE 10              // timed kernel stages in the stats tap
-#define RB_NSTATS (4 + RB_NSTAGE) // stats tap columns per world
+#define RB_STATS_SUB 4            // substeps with a per-substep record in the stats tap
+#define RB_STATS_FP 4             // Newton updates with an active-set fingerprint per substep
+#define RB_SUBSTAT (5 + RB_STATS_FP)   // per-substep record columns
+#define RB_NSTATS (4 + RB_NSTAGE + RB_STATS_SUB * RB_SUBSTAT)   // stats tap columns per world
 #define RB_PAIR_BOXBOX 16         // pair_type of a box-box pair (plane pairs hold g2's geom type)
 #define RB_PAIR_SPHEREBOX 17      // pair_type of a sphere (g1) - box (g2) pair
 #define RB_BB_FLOATS 96           // LDS floats per box-box pair: clip buffers, contacts, normal

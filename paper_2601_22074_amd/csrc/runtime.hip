@@ -143,6 +143,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     if (nb < 2) return fail(RB_EINVAL, "model needs at least one body besides the world");
     if (nj < 1) return fail(RB_EINVAL, "model needs at least one joint");
     if (ng < 0 || nu < 0) return fail(RB_EINVAL, "negative sizes");
+    // contact ids carry geom indices in 8-bit fields
+    if (ng > RB_MAX_GEOM) return fail(RB_EINVAL, "more than 256 geoms");
     // every real number of the description must be finite
     auto finite = [](const double* x, int n) {
         for (int i = 0; i < n; i++)

@@ -64,6 +64,12 @@ DEV int wscan_incl(int x, int lane) {
     }
     return x;
 }
+// wave-wide sum of unsigned 32-bit integers (modulo 2^32)
+DEV uint32_t wsum_u32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o);
+    return x;
+}
 DEV bool finitef(float x) { return __builtin_isfinite(x); }
 // x, opaque to the optimiser at this point: values derived from it are computed where they are
 // used instead of being hoisted out of loops (and then spilled) as loop invariants
@@ -842,6 +848,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         for (int c = 0; c < 6; c++) cvel[c] = 0.f;
     }
     uint32_t status = A.W.status[w];
+    // per-substep record of the stats tap: substeps and updates never reached stay 0
+    int32_t* SUBREC = (TIMED && A.want_taps && A.taps.stats) ? A.taps.stats + (size_t)w * RB_NSTATS + 4 + RB_NSTAGE
+                                                               : nullptr;
+    if (TIMED && SUBREC && lane < RB_STATS_SUB * RB_SUBSTAT) SUBREC[lane] = 0;
     wave_sync();
 
     Con C;
@@ -1378,6 +1388,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             RB_STAGE(5);
 
             int it = 0;
+            int seg_sub = 0;   // line-search segments of this substep (stats tap)
             uint32_t prev_bits = 0;
             for (; it < m.maxiter; it++) {
                 // Converged when no row changed sides since the Hessian was last built: the
@@ -1448,6 +1459,22 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 }
                 float gn = sqrtf(wsum(gi * gi));
                 if (gn < m.tol_scale) break;
+                if (TIMED && SUBREC && sub < RB_STATS_SUB && it < RB_STATS_FP) {
+                    // fingerprint of the active set this update is built from: sum over active rows
+                    // of (id + 1) * 2654435761 mod 2^32, id = 4 c + e for pyramid row e of contact c
+                    // (a frictionless contact's one row is e = 0), 256 + dof for a limit row
+                    uint32_t fpl = 0;
+                    if (has) {
+#pragma unroll
+                        for (int e = 0; e < 4; e++)
+                            if (C.jar[e] < 0.f && (e == 0 || !(EXT && (C.ids >> 24))))
+                                fpl += (uint32_t)(4 * lane + e + 1) * 2654435761u;
+                    }
+                    if (limact && dof_lane && lD[lane] != 0.f && ljar[lane] < 0.f)
+                        fpl += (uint32_t)(256 + lane + 1) * 2654435761u;
+                    fpl = wsum_u32(fpl);
+                    if (lane == 0) SUBREC[RB_SUBSTAT * sub + 5 + it] = (int32_t)fpl;
+                }
                 // Hessian row in registers: H_ij = M_ij + S_j . F_i over the chain of i
                 // (computed for every position and selected: past the chain the index stays in
                 // LDS -- the next rows of M, or H after it -- and the value is discarded)
@@ -1498,7 +1525,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     float at = 0.f;
                     int guard = 4 * ncon + 2 + (limact ? nv : 0);
                     for (int k = 0; k < guard; k++) {
-                        if (TIMED) st_seg++;
+                        if (TIMED) seg_sub++;
                         float sa = 0.f, sb = 0.f, nxt = INFINITY;
                         if (has) {
 #pragma unroll
@@ -1565,14 +1592,29 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             if (it >= m.maxiter) itercap = true;
             if (TIMED) {
                 st_iter += it;
-                int act = 0;
+                st_seg += seg_sub;
+                // rows, and rows active at the solution (a frictionless contact has one row)
+                const bool fl = has && EXT && (C.ids >> 24);
+                int act = 0, nrow = has ? (fl ? 1 : 4) : 0;
                 if (has)
-                    for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f;
-                if (limact && lane < nv) act += ljar[lane] < 0.f;
-                st_rows += (int)wsum((float)act);
+                    for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f && (e == 0 || !fl);
+                if (limact && lane < nv && lD[lane] != 0.f) {
+                    act += ljar[lane] < 0.f;
+                    nrow += 1;
+                }
+                const int actw = (int)wsum_u32((uint32_t)act);
+                const int nroww = (int)wsum_u32((uint32_t)nrow);
+                st_rows += actw;
+                if (SUBREC && sub < RB_STATS_SUB && lane == 0) {
+                    SUBREC[RB_SUBSTAT * sub + 1] = nroww;
+                    SUBREC[RB_SUBSTAT * sub + 2] = it;
+                    SUBREC[RB_SUBSTAT * sub + 3] = actw;
+                    SUBREC[RB_SUBSTAT * sub + 4] = seg_sub;
+                }
             }
         }
         if (TIMED) st_con += ncon;
+        if (TIMED && SUBREC && sub < RB_STATS_SUB && lane == 0) SUBREC[RB_SUBSTAT * sub] = ncon;
         RB_STAGE(6);
         if (itercap) status |= RB_STATUS_ITERCAP;
 

@@ -18,7 +18,11 @@ LIB_PATH = os.path.join(HERE, "librbstep.so")
 RB_OK, RB_EINVAL, RB_ENOMEM, RB_EHIP, RB_EBUDGET, RB_ESTATE = 0, -1, -2, -3, -4, -5
 STATUS_NONFINITE, STATUS_ITERCAP, STATUS_CONOVERFLOW = 1, 2, 4
 PARAM_FRICTION, PARAM_MASS_SCALE = 0, 1
-NSTATS = 14
+NSTAGE = 10             # timed stages in the stats tap
+STATS_SUB = 4           # substeps with a per-substep record in the stats tap
+STATS_FP = 4            # Newton updates with an active-set fingerprint per substep
+SUBSTAT = 5 + STATS_FP  # per substep: contacts, rows, updates, active rows, segments, fingerprints
+NSTATS = 4 + NSTAGE + STATS_SUB * SUBSTAT
 STAGES = ["kinematics", "inertia+bias+M", "factor M + a0", "collision", "constraint rows", "newton start",
           "gradient+hessian", "hessian factor+solve", "line search+update", "integrate"]
 
@@ -234,9 +238,11 @@ class Contacts:
         self.force = torch.zeros(n, cap, 3, dtype=torch.float32, device=device)
         self.n, self.cap = n, cap
 
-    def _struct(self, n):
+    def _struct(self, n, cap):
         if n > self.n:
             raise ValueError("contact buffers hold fewer worlds than stepped")
+        if cap != self.cap:
+            raise ValueError(f"contact buffers have {self.cap} slots per world, the batch needs {cap}")
         s = _Contacts()
         for k in ("ncon", "geom", "feature", "dist", "pos", "frame", "force"):
             setattr(s, k, getattr(self, k).data_ptr())
@@ -310,7 +316,7 @@ class Batch:
     def step(self, ctrl, qpos, qvel, contacts: Contacts | None = None, status=None, stream=None) -> None:
         """One env step (K substeps) of worlds [0, n), n = qpos.shape[0]; qpos/qvel in place."""
         n, pc, pq, pv, ps = self._common(ctrl, qpos, qvel, status)
-        cs = C.byref(contacts._struct(n)) if contacts is not None else None
+        cs = C.byref(contacts._struct(n, self.ncap)) if contacts is not None else None
         _check(lib().rb_step(self._h, int(n), pc, pq, pv, cs, ps, _stream(stream)))
 
     def step_taps(self, ctrl, qpos, qvel, contacts=None, status=None, M=None, bias=None, a0=None, qacc=None,
@@ -318,7 +324,7 @@ class Batch:
         import torch
         n, pc, pq, pv, ps = self._common(ctrl, qpos, qvel, status)
         nv = self.model.nv
-        cs = C.byref(contacts._struct(n)) if contacts is not None else None
+        cs = C.byref(contacts._struct(n, self.ncap)) if contacts is not None else None
         _check(lib().rb_step_taps(self._h, int(n), pc, pq, pv, cs, ps,
                                   _ptr(M, torch.float32, (n, nv, nv), "M"), _ptr(bias, torch.float32, (n, nv), "bias"),
                                   _ptr(a0, torch.float32, (n, nv), "a0"), _ptr(qacc, torch.float32, (n, nv), "qacc"),
@@ -352,7 +358,7 @@ class Multi:
     def bind(self, i, ctrl, qpos, qvel, contacts: Contacts | None = None, status=None) -> None:
         """Step inputs of batch i (kept alive by the plan until rebound)."""
         n, pc, pq, pv, ps = self.batches[i]._common(ctrl, qpos, qvel, status)
-        cs = C.byref(contacts._struct(n)) if contacts is not None else None
+        cs = C.byref(contacts._struct(n, self.batches[i].ncap)) if contacts is not None else None
         _check(lib().rb_multi_bind(self._h, int(i), int(n), pc, pq, pv, cs, ps))
         self.bound[i] = (ctrl, qpos, qvel, contacts, status)
 

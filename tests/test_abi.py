@@ -183,3 +183,37 @@ def test_size_limits_rejected(rb):
     assert rc == -1 and "64 collision pairs" in msg, msg
     rc, msg = _create_error(robots.chain(65, "chain65"))
     assert rc == -1 and "64 dofs" in msg, msg
+    # contact ids carry geom indices in 8-bit fields: more than 256 geoms are refused even when
+    # they make no collision pair
+    m = robots.chain3()
+    for i in range(260):
+        m["geoms"].append(dict(m["geoms"][1], contype=0, conaffinity=0))
+    rc, msg = _create_error(m)
+    assert rc == -1 and "256 geoms" in msg, msg
+
+
+def test_every_declaration_cites_its_passage():
+    """Each function of include/rbstep.h carries a comment that cites the paper passage that
+    defines the operation (or states that no passage does)."""
+    src = open(os.path.join(ROOT, "include", "rbstep.h")).read()
+    names = _declared()
+    for n in names:
+        m = re.search(r"^[A-Za-z_][\w\s\*]*\b" + n + r"\s*\(", src, flags=re.M)
+        assert m, n
+        head = src[:m.start()]
+        comment_end = head.rstrip().endswith("*/")
+        assert comment_end, f"{n}: no comment right before the declaration"
+        comment = re.sub(r"\s*\n\s*\*?\s*", " ", head[head.rstrip().rfind("/*"):])
+        assert "Cites:" in comment and ("section" in comment or "no passage" in comment or "as rb_" in comment), n
+
+
+def test_contacts_capacity_checked():
+    """Contact buffers whose slots per world differ from the batch's capacity are refused before
+    any launch (the kernel writes world w's contacts at w * capacity)."""
+    from paper_2601_22074_amd import rbstep
+    c = rbstep.Contacts(4, 8, device="cpu")
+    c._struct(4, 8)
+    with pytest.raises(ValueError):
+        c._struct(4, 16)
+    with pytest.raises(ValueError):
+        c._struct(5, 8)
