@@ -51,8 +51,10 @@ def gpu_run(model, qpos, qvel, ctrl=None, qacc_ws=None, friction=None, mass_scal
             Mt = torch.zeros(n, nv, nv, device=dev); bias = torch.zeros(n, nv, device=dev)
             a0 = torch.zeros(n, nv, device=dev); qacc = torch.zeros(n, nv, device=dev)
             efc = torch.zeros(n, B.ncap, 4, 3, device=dev)
-            B.step_taps(u, q, v, con, st, M=Mt, bias=bias, a0=a0, qacc=qacc, efc=efc)
-            out.update(M=Mt, bias=bias, a0=a0, qacc=qacc, efc=efc)
+            from paper_2601_22074_amd.rbstep import NSTATS
+            stats = torch.zeros(n, NSTATS, dtype=torch.int32, device=dev)
+            B.step_taps(u, q, v, con, st, M=Mt, bias=bias, a0=a0, qacc=qacc, efc=efc, stats=stats)
+            out.update(M=Mt, bias=bias, a0=a0, qacc=qacc, efc=efc, stats=stats)
         else:
             B.step(u, q, v, con, st)
     torch.cuda.synchronize()
@@ -121,18 +123,13 @@ def by_name(name):
     return robots.by_name(name)
 
 
-BAND_SPEED = 1e-4     # normal speed above which a contact on its threshold matters (m/s)
-
-
-def margin_band_worlds(oracle_mod, model, qpos, qvel, ctrl, qacc_ws, friction, mass_scale):
-    """Per world: whether one env step from this FP32 state passes a contact within
-    MARGIN_BAND of its inclusion threshold, moving along its normal faster than BAND_SPEED, at
-    the start of some substep.  The two paths may then include the contact on one side only,
-    and its reference acceleration, which damps the normal speed (about b |v_n| with
-    b = 2 / (dmax tc) ~ 105 / s), changes the velocity by about dt b |v_n|: past the step
-    tolerance above ~2e-4 m/s.  Found with the oracle alone: its substeps are replayed one at a
-    time, each starting state listed by a copy of the model whose margins are widened by the
-    band."""
+def band_worlds(oracle_mod, model, qpos, qvel, ctrl, qacc_ws, friction, mass_scale):
+    """Per world: whether one env step from this FP32 state passes a contact within MARGIN_BAND
+    of its inclusion threshold at the start of some substep.  Such a contact may be included by
+    one path only, and a contact row that acts in one path and not in the other changes the
+    step by far more than rounding.  Found with the oracle alone: its substeps are replayed one
+    at a time and each starting state's contacts are listed by a copy of the model whose
+    margins are widened by the band."""
     import copy
     m1 = substeps1(model)
     wide = copy.deepcopy(m1)
@@ -149,10 +146,233 @@ def margin_band_worlds(oracle_mod, model, qpos, qvel, ctrl, qacc_ws, friction, m
         for w in range(n):
             t = ow.forward(q[w], v[w], u[w] if o1.nu else None, ws[w],
                            None if friction is None else friction[w], None if mass_scale is None else mass_scale[w])
-            for i, ((g1, g2), d) in enumerate(zip(t["geom"], t["dist"])):
-                if abs(d - max(gm[g1], gm[g2])) <= MARGIN_BAND:
-                    vn = 0.5 * (t["J"][4 * i] + t["J"][4 * i + 1]) @ v[w]
-                    band[w] |= abs(vn) > BAND_SPEED
+            band[w] |= any(abs(d - max(gm[g1], gm[g2])) <= MARGIN_BAND for (g1, g2), d in zip(t["geom"], t["dist"]))
         o1.step(u, q, v, ws, None if friction is None else np.asarray(friction, np.float64),
                 None if mass_scale is None else np.asarray(mass_scale, np.float64))
     return band
+
+
+# per-substep work record columns compared between the two paths: contacts, rows, Newton
+# updates, rows active at the solution, and the active-set fingerprints of the first updates
+# (line-search segment counts are left out: equal breakpoints may be swept as one or two)
+REC_COLS = [0, 1, 2, 3, 5, 6, 7, 8]
+CON_COLS = [0, 1]
+
+
+def gpu_step_records(model, q32, v32, u32, w32, fr, ms):
+    """One env step of every world on the GPU from FP32 inputs: the plain launch (results and
+    contacts) and the diagnostic launch (per-substep work records), which must compute the same
+    bits."""
+    import torch
+    import paper_2601_22074_amd as rb
+    from paper_2601_22074_amd.rbstep import NSTATS
+    dev = torch.device("cuda:0")
+    n = q32.shape[0]
+    M = rb.Model(model)
+    B = rb.Batch(M, n)
+    res = {}
+    try:
+        if fr is not None:
+            B.set_params(rb.PARAM_FRICTION, torch.tensor(np.asarray(fr, np.float32), device=dev))
+        if ms is not None:
+            B.set_params(rb.PARAM_MASS_SCALE, torch.tensor(np.asarray(ms, np.float32), device=dev))
+        ids = torch.arange(n, dtype=torch.int32, device=dev)
+        u = u32 if M.nu else np.zeros((n, 0), np.float32)
+        for diag in (False, True):
+            qt, vt = torch.tensor(q32, device=dev), torch.tensor(v32, device=dev)
+            ut = torch.tensor(np.asarray(u, np.float32), device=dev)
+            B.reset(ids, torch.tensor(w32, device=dev))
+            sta = torch.zeros(n, dtype=torch.int32, device=dev)
+            if diag:
+                stats = torch.zeros(n, NSTATS, dtype=torch.int32, device=dev)
+                B.step_taps(ut, qt, vt, None, sta, stats=stats)
+                torch.cuda.synchronize()
+                res["stats"] = stats.cpu().numpy()
+                np.testing.assert_array_equal(qt.cpu().numpy(), res["qpos"])
+                np.testing.assert_array_equal(vt.cpu().numpy(), res["qvel"])
+            else:
+                con = B.contacts(n)
+                B.step(ut, qt, vt, con, sta)
+                torch.cuda.synchronize()
+                res.update(qpos=qt.cpu().numpy(), qvel=vt.cpu().numpy(), status=sta.cpu().numpy(),
+                           contacts={k: getattr(con, k).cpu().numpy() for k in
+                                     ("ncon", "geom", "feature", "dist", "pos", "frame", "force")})
+    finally:
+        B.close()
+        M.close()
+    K = model["opt"]["nsubsteps"] if isinstance(model, dict) else None
+    res["sub"] = res["stats"][:, 14:14 + 36].reshape(n, 4, 9)[:, :K]
+    return res
+
+
+def oracle_step_records(o, q32, v32, u32, w32, fr, ms):
+    """The oracle's env step (mirror mode, with contacts and per-substep work records) and the
+    converged-mode step from the same FP32 inputs."""
+    n = q32.shape[0]
+    f64 = lambda a: None if a is None else np.asarray(a, np.float64)
+    u = np.zeros((n, o.nu)) if u32 is None else np.asarray(u32, np.float64)
+    rq, rv, rw = (np.array(x, np.float64) for x in (q32, v32, w32))
+    work = {}
+    _, con = o.step(u, rq, rv, rw, f64(fr), f64(ms), contacts=True, work=work)
+    o.set_mode("converged")
+    cq, cv, cw = (np.array(x, np.float64) for x in (q32, v32, w32))
+    o.step(u, cq, cv, cw, f64(fr), f64(ms))
+    o.set_mode("mirror")
+    return dict(qpos=rq, qvel=rv, qacc_ws=rw, contacts=con, sub=work["sub"], cq=cq, cv=cv)
+
+
+def classify(gsub, osub):
+    """'match': the two paths made the same contacts, rows, Newton updates and active sets in
+    every substep; 'contacts': they listed different contacts or rows in some substep; 'path':
+    same contacts and rows, different Newton updates or active sets."""
+    if np.array_equal(gsub[:, REC_COLS], osub[:, REC_COLS]):
+        return "match"
+    if not np.array_equal(gsub[:, CON_COLS], osub[:, CON_COLS]):
+        return "contacts"
+    return "path"
+
+
+DEPTH_TOL = 3e-7      # FP32 contact-depth error of the GPU's kinematics (asserted on the stage taps)
+
+
+def free_lift(model, q, dz):
+    """Copy of q [n, nq] (float64) with every free joint raised by dz along z."""
+    q = np.array(q, np.float64)
+    for (t, qa, _), j in zip(_layout(model), model["joints"]):
+        if t == "free":
+            q[:, qa + 2] += dz
+    return q
+
+
+def depth_floor(o, model, q32, v32, u32, w32, fr, ms, j):
+    """The FP32 floor of world j's env step: how far the FP64 step moves (R23 metric, qpos and
+    qvel) when the floating bases are displaced by +-DEPTH_TOL along z, i.e. when every contact
+    depth moves by the FP32 error the GPU's kinematics may carry.  Contact rows are stiff within
+    the impedance width (1 mm), so some states resolve only to this floor in single precision."""
+    sl = slice(j, j + 1)
+    f64 = lambda a: None if a is None else np.asarray(a[sl], np.float64)
+    u = np.zeros((1, o.nu)) if u32 is None else np.asarray(u32[sl], np.float64)
+
+    def step(dz):
+        q = free_lift(model, q32[sl], dz)
+        v, w = np.array(v32[sl], np.float64), np.array(w32[sl], np.float64)
+        o.step(u, q, v, w, f64(fr), f64(ms))
+        return free_lift(model, q, -dz), v
+
+    q0, v0 = step(0.0)
+    out = 0.0
+    for dz in (DEPTH_TOL, -DEPTH_TOL):
+        q, v = step(dz)
+        out = max(out, rel_err(q, q0), rel_err(v, v0))
+    return out
+
+
+class StepTally:
+    """Single-step parity of one workload over many (world, state) samples.
+
+    Per sample (R23 metric, tolerance RTOL_STEP):
+      * same work records on both paths ('match'): qpos and qvel within RTOL_STEP (or, where the
+        oracle's own step moves by more than that when every contact depth moves by DEPTH_TOL,
+        within that FP32 floor: depth_floor), and the
+        last substep's contacts (keys exactly; dist and pos within RTOL_STEP m, frame within
+        RTOL_STEP, the qpos bar carried to the contact geometry; force within RTOL_STEP of the
+        world's largest contact force, the accelerations' bar carried to the multipliers);
+      * different contacts or rows in some substep ('contacts'): allowed only where the oracle
+        finds a contact within MARGIN_BAND of its inclusion threshold at the start of a substep
+        (the contact pair-set rule); qpos and qvel are then not compared;
+      * same contacts and rows, different Newton updates or active sets ('path'): the truncated
+        Newton iterate depends on its path, and the bar is RTOL_STEP plus a tenth of the FP64
+        distance between the 4-iteration and the converged step.
+    Over the workload: 'path' samples at most 5 %, iteration counts equal in at least 98 % of
+    the compared samples, 'contacts' samples at most a sixth."""
+
+    def __init__(self, name):
+        self.name = name
+        self.n = self.nmatch = self.npath = self.ncon = self.nband = self.iteq = self.ncmp = self.nfloor = 0
+        self.worst = self.worst_path = 0.0
+        self.cworst = dict(dist=0.0, pos=0.0, frame=0.0, force=0.0)
+
+    def add(self, g, r, gw, rw, band, where, floor=None):
+        """floor: callable giving the sample's FP32 floor (depth_floor), asked only where the
+        error exceeds RTOL_STEP."""
+        gs, os_ = g["sub"][gw], r["sub"][rw]
+        kind = classify(gs, os_)
+        self.n += 1
+        err = max(rel_err(g[k][gw], r[k][rw]) for k in ("qpos", "qvel"))
+        if kind == "contacts":
+            assert band, (where, "contact records differ with no contact on its threshold", gs.tolist(), os_.tolist())
+            self.ncon += 1
+            return
+        self.ncmp += 1
+        self.iteq += bool(np.array_equal(gs[:, 2], os_[:, 2]))
+        if kind == "match":
+            self.nmatch += 1
+            if err > RTOL_STEP:
+                fl = floor() if floor is not None else 0.0
+                assert err <= fl, (where, err, fl)
+                self.nfloor += 1
+            else:
+                self.worst = max(self.worst, err)
+            if not band:
+                self._contacts(g["contacts"], r["contacts"], gw, rw, where)
+        else:
+            self.npath += 1
+            trunc = max(rel_err(r["cq"][rw], r["qpos"][rw]), rel_err(r["cv"][rw], r["qvel"][rw]))
+            assert err <= RTOL_STEP + 0.1 * trunc, (where, err, trunc, gs.tolist(), os_.tolist())
+            self.worst_path = max(self.worst_path, err)
+
+    def _contacts(self, gc, rc, gw, rw, where):
+        nc = int(rc["ncon"][rw])
+        assert int(gc["ncon"][gw]) == nc, where
+        if nc == 0:
+            return
+        assert [tuple(x) for x in gc["geom"][gw, :nc]] == [tuple(x) for x in rc["geom"][rw, :nc]], where
+        assert list(gc["feature"][gw, :nc]) == list(rc["feature"][rw, :nc]), where
+        e = dict(dist=np.abs(gc["dist"][gw, :nc] - rc["dist"][rw, :nc]).max(),
+                 pos=rel_err(gc["pos"][gw, :nc], rc["pos"][rw, :nc]),
+                 frame=np.abs(gc["frame"][gw, :nc].reshape(nc, 9) - rc["frame"][rw, :nc].reshape(nc, 9)).max(),
+                 force=vec_err(gc["force"][gw, :nc], rc["force"][rw, :nc]))
+        for k, x in e.items():
+            assert x <= RTOL_STEP, (where, k, x)
+            self.cworst[k] = max(self.cworst[k], float(x))
+
+    def finish(self):
+        print(f"{self.name}: {self.n} samples: {self.nmatch} same path (max err {self.worst:.2e}, "
+              f"{self.nfloor} above RTOL_STEP within their FP32 floor), "
+              f"{self.npath} path differences (max err {self.worst_path:.2e}), {self.ncon} contact-threshold "
+              f"samples not compared; iteration counts equal in {self.iteq}/{self.ncmp}; contact outputs max "
+              + ", ".join(f"{k} {v:.1e}" for k, v in self.cworst.items()), flush=True)
+        assert self.npath <= 0.05 * self.n, (self.npath, self.n)
+        assert self.iteq >= 0.98 * self.ncmp, (self.iteq, self.ncmp)
+        assert self.ncon <= self.n / 6, (self.ncon, self.n)
+        assert self.nfloor <= 0.01 * self.n, (self.nfloor, self.n)
+
+
+def teacher_forced(oracle_mod, name, horizon, every=25, n=32):
+    """Along the oracle's own trajectory of n worlds, hand its state (rounded to FP32) to the GPU
+    every ``every`` env steps and compare one env step of every world (StepTally)."""
+    from workloads import inputs
+    m = by_name(name)
+    worlds = list(range(n))
+    q, v = inputs.initial_state(m, name, worlds)
+    fr, ms = inputs.world_params(m, name, worlds)
+    o = oracle_mod.Oracle(m)
+    ctab = inputs.ctrl_table(m, name, worlds, horizon // 20 + 1)
+    qq = q.astype(np.float64); vv = v.astype(np.float64); ws = np.zeros((n, o.nv)); st = np.zeros(n, np.uint32)
+    frd = None if fr is None else fr.astype(np.float64)
+    msd = None if ms is None else ms.astype(np.float64)
+    T = StepTally(name)
+    for s in range(horizon):
+        uu = ctab[s // 20].astype(np.float64)
+        if s % every == every - 1:
+            q32, v32, w32, u32 = (x.astype(np.float32) for x in (qq, vv, ws, uu))
+            g = gpu_step_records(m, q32, v32, u32, w32, fr, ms)
+            r = oracle_step_records(o, q32, v32, u32, w32, fr, ms)
+            band = band_worlds(oracle_mod, m, q32, v32, u32, w32, fr, ms)
+            assert np.all(g["status"] & 1 == 0)
+            for w in range(n):
+                T.add(g, r, w, w, band[w], (name, s, w),
+                      floor=lambda w=w: depth_floor(o, m, q32, v32, u32, w32, fr, ms, w))
+        o.step(uu, qq, vv, ws, frd, msd, st)
+    T.finish()
+    return T

@@ -3,29 +3,11 @@ launch, contacts returned), on a sample of worlds the oracle computes one by one
 import numpy as np
 import pytest
 
-from gpu_common import RTOL_ROLLOUT, RTOL_STEP, gpu_run, oracle_run, rel_err
+from gpu_common import (RTOL_ROLLOUT, StepTally, band_worlds, depth_floor, gpu_run, gpu_step_records, oracle_run,
+                        oracle_step_records, rel_err)
 from workloads import inputs
 
 pytestmark = pytest.mark.gpu
-
-
-def _sample_check(o, g, qs, vs, ws, u, fr, ms, idx, tol_trunc=True):
-    """Oracle on the sampled worlds from the same FP32 state; per-world tolerance as in the
-    teacher-forced test (1e-4, plus a tenth of the truncation distance where the 4-iteration
-    Newton has not converged)."""
-    sub = lambda a: None if a is None else a[idx]
-    r = oracle_run(o, qs[idx], vs[idx], u[idx], ws[idx], sub(fr), sub(ms))
-    o.set_mode("converged")
-    rc = oracle_run(o, qs[idx], vs[idx], u[idx], ws[idx], sub(fr), sub(ms))
-    o.set_mode("mirror")
-    strict = 0
-    for j, w in enumerate(idx):
-        trunc = max(rel_err(rc[k][j], r[k][j]) for k in ("qpos", "qvel"))
-        tol = RTOL_STEP + 0.1 * trunc
-        strict += trunc <= RTOL_STEP
-        err = max(rel_err(g[k][w], r[k][j]) for k in ("qpos", "qvel"))
-        assert err <= tol, (int(w), err, trunc)
-    return strict
 
 
 @pytest.mark.parametrize("name,n,start", [("humanoid", 8192, 0), ("humanoid", 8192, 20), ("quadruped", 4096, 20)])
@@ -51,10 +33,17 @@ def test_full_size_sampled_worlds(oracle_mod, name, n, start):
                    None if W["mass_scale"] is None else W["mass_scale"][idx].astype(np.float64), st)
         q[idx], v[idx], ws[idx] = qq.astype(np.float32), vv.astype(np.float32), wd.astype(np.float32)
     u = W["ctrl"][start // inputs.CTRL_PERIOD]
-    g = gpu_run(m, q, v, u, ws, W["friction"], W["mass_scale"], contacts=True)
+    fr, ms = W["friction"], W["mass_scale"]
+    g = gpu_step_records(m, q, v, u, ws, fr, ms)
     assert np.all(g["status"] & 1 == 0)
-    strict = _sample_check(o, g, q, v, ws, u, W["friction"], W["mass_scale"], idx)
-    assert strict >= len(idx) // 2
+    sub = lambda a: None if a is None else a[idx]
+    r = oracle_step_records(o, q[idx], v[idx], u[idx], ws[idx], sub(fr), sub(ms))
+    band = band_worlds(oracle_mod, m, q[idx], v[idx], u[idx], ws[idx], sub(fr), sub(ms))
+    T = StepTally(f"{name} x{n} from step {start}")
+    for j, w in enumerate(idx):
+        T.add(g, r, w, j, band[j], (name, n, start, int(w)),
+              floor=lambda j=j: depth_floor(o, m, q[idx], v[idx], u[idx], ws[idx], sub(fr), sub(ms), j))
+    T.finish()
 
 
 def test_chain_rollout_500_steps(oracle_mod):

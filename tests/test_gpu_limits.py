@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_common import RTOL_STEP, by_name, gpu_run, oracle_run, rel_err
+from gpu_common import StepTally, band_worlds, by_name, depth_floor, gpu_step_records, oracle_step_records
 from helpers import lever, lever_rest_angle
 from workloads import inputs
 
@@ -25,8 +25,7 @@ def _hinge_qadr(m):
 @pytest.mark.parametrize("name", LIMITED)
 def test_single_step_outside_limits(oracle_mod, name):
     """States with hinges up to 0.1 rad past their bounds (and moving): one env step against
-    the oracle, at the step tolerance conditioned, as for contacts, on how far the truncated
-    Newton iterate is from the converged one."""
+    the oracle (StepTally: the step tolerance wherever the work records of both paths agree)."""
     m = by_name(name)
     n = 64
     worlds = range(n)
@@ -40,18 +39,14 @@ def test_single_step_outside_limits(oracle_mod, name):
     q[:, hq] = rng.uniform(lo - 0.1, hi + 0.1, (n, len(hq))).astype(np.float32)
     v = (v + rng.normal(0, 0.5, v.shape)).astype(np.float32)
     o = oracle_mod.Oracle(m)
-    g = gpu_run(m, q, v, u, friction=fr, mass_scale=ms)
-    r = oracle_run(o, q, v, u, None, fr, ms)
-    o.set_mode("converged")
-    rc = oracle_run(o, q, v, u, None, fr, ms)
-    o.set_mode("mirror")
-    ntrunc = 0
+    ws = np.zeros((n, o.nv), np.float32)
+    g = gpu_step_records(m, q, v, u, ws, fr, ms)
+    r = oracle_step_records(o, q, v, u, ws, fr, ms)
+    band = band_worlds(oracle_mod, m, q, v, u, ws, fr, ms)
+    T = StepTally(f"{name} outside its limits")
     for w in range(n):
-        trunc = max(rel_err(rc[k][w], r[k][w]) for k in ("qpos", "qvel"))
-        ntrunc += trunc > RTOL_STEP
-        err = max(rel_err(g[k][w], r[k][w]) for k in ("qpos", "qvel"))
-        assert err <= RTOL_STEP + 0.1 * trunc, (w, err, trunc)
-    assert ntrunc <= n // 2
+        T.add(g, r, w, w, band[w], (name, w), floor=lambda w=w: depth_floor(o, m, q, v, u, ws, fr, ms, w))
+    T.finish()
     assert np.all(g["status"] & 1 == 0)
 
 

@@ -2,8 +2,8 @@
 import numpy as np
 import pytest
 
-from gpu_common import (MARGIN_BAND, RTOL_ROLLOUT, RTOL_STEP, by_name, contact_keys, gpu_run, lifted,
-                        margin_band_worlds, oracle_run, rel_err, substeps1, vec_err)
+from gpu_common import (DEPTH_TOL, MARGIN_BAND, RTOL_ROLLOUT, RTOL_STEP, by_name, contact_keys, free_lift, gpu_run,
+                        lifted, oracle_run, rel_err, substeps1, teacher_forced, vec_err)
 from helpers import rot
 from workloads import inputs, robots
 
@@ -51,7 +51,7 @@ def test_stage_taps_contact_rows(oracle_mod, name):
     r = oracle_run(o, q, v, u, None, fr, ms, nsteps=60)
     q1, v1, ws1 = r["qpos"].astype(np.float32), r["qvel"].astype(np.float32), r["qacc_ws"].astype(np.float32)
     g = gpu_run(m, q1, v1, u, ws1, fr, ms, taps=True, contacts=True)
-    ncmp = 0
+    ncmp = nsame = nfloor = 0
     for w in range(q1.shape[0]):
         t = o.forward(q1[w], v1[w], u[w], ws1[w], None if fr is None else fr[w], None if ms is None else ms[w])
         nc = t["ncon"]
@@ -64,15 +64,31 @@ def test_stage_taps_contact_rows(oracle_mod, name):
         efc = g["efc"][w, :nc]
         # penetration depths agree to FP32 rounding of body positions (~1 m scale)
         ddist = np.abs(g["contacts"]["dist"][w, :nc] - t["dist"]).max()
-        assert ddist <= 3e-7
+        assert ddist <= DEPTH_TOL
         np.testing.assert_allclose(efc[:, :, 2].reshape(-1), t["Ahat"], rtol=1e-4)
         np.testing.assert_allclose(efc[:, :, 1].reshape(-1), t["D"], rtol=2e-4)
         # aref = -b v - k imp r carries the stiffness k (~2770 / s^2) times the depth error
         kref = 1.0 / (0.95 ** 2 * 0.02 ** 2)
-        np.testing.assert_allclose(efc[:, :, 0].reshape(-1), t["aref"], rtol=1e-4, atol=2 * kref * 3e-7 + 1e-5)
-        assert vec_err(g["qacc"][w], t["qacc"]) <= 1e-3, f"qacc world {w}"
+        np.testing.assert_allclose(efc[:, :, 0].reshape(-1), t["aref"], rtol=1e-4, atol=2 * kref * DEPTH_TOL + 1e-5)
+        # the first substep's Newton updates and active rows (work record) against the oracle's:
+        # where they agree the accelerations match at the step tolerance, or, where the oracle's
+        # own accelerations move by more than that when every contact depth moves by DEPTH_TOL
+        # (the FP32 depth error asserted above), within that floor
+        grec = g["stats"][w, 14:14 + 9]
+        if grec[2] == t["niter"] and int(grec[3]) == int(np.sum(t["efc_force"] > 0)):
+            err = vec_err(g["qacc"][w], t["qacc"])
+            if err > RTOL_STEP:
+                args = (v1[w], u[w], ws1[w], None if fr is None else fr[w], None if ms is None else ms[w])
+                fl = max(vec_err(o.forward(free_lift(m, q1[w:w + 1], dz)[0], *args)["qacc"], t["qacc"])
+                         for dz in (DEPTH_TOL, -DEPTH_TOL))
+                assert err <= fl, (f"qacc world {w}", err, fl)
+                nfloor += 1
+            nsame += 1
         ncmp += 1
+    print(f"{name}: {ncmp} worlds compared, {nsame} on the same Newton path, {nfloor} of those above "
+          f"RTOL_STEP within their FP32 floor")
     assert ncmp >= q1.shape[0] // 2
+    assert nsame >= 0.9 * ncmp
 
 
 # ------------------------------------------------------------------ single env step
@@ -86,58 +102,18 @@ def test_single_step_from_initial_states(oracle_mod, name):
     assert np.all(g["status"] & 1 == 0)
 
 
-@pytest.mark.parametrize("name,horizon", [("quadruped", 200), ("humanoid", 150), ("arm_box", 150),
-                                          ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 150),
-                                          ("quadruped_terrain", 200), ("humanoid_terrain", 100),
-                                          ("humanoid_damp", 150), ("quadruped_slip", 200)])
+@pytest.mark.parametrize("name,horizon", [("quadruped", 1000), ("humanoid", 1000), ("arm_box", 200),
+                                          ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 200),
+                                          ("quadruped_terrain", 200), ("humanoid_terrain", 200),
+                                          ("humanoid_damp", 200), ("quadruped_slip", 200)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
-    """Along the oracle's own trajectory, hand its state (rounded to FP32) to the GPU at
-    sampled steps and compare one env step.  Samples where a moving contact starts a substep
-    on its inclusion threshold (found by the oracle, see margin_band_worlds) are left out."""
-    m, q, v, u, fr, ms = _wl(name, 32)
-    o = oracle_mod.Oracle(m)
-    worlds = list(range(32))
-    ctab = inputs.ctrl_table(m, name, worlds, horizon // 20 + 1)
-    qq = q.astype(np.float64); vv = v.astype(np.float64); ws = np.zeros((32, o.nv)); st = np.zeros(32, np.uint32)
-    frd = None if fr is None else fr.astype(np.float64)
-    msd = None if ms is None else ms.astype(np.float64)
-    worst = 0.0
-    ntrunc = 0
-    nover = nsamp = nband = 0
-    # joint limits put stiff rows on light distal dofs: a rare sample then carries FP32 solve
-    # error a little past the step tolerance with the same iterations and active set as the
-    # oracle; those may reach twice the tolerance, at most 1 % of the samples
-    slack = 2.0 if name.endswith("_lim") else 1.0
-    for s in range(horizon):
-        uu = ctab[s // 20].astype(np.float64)
-        if s % 25 == 24:
-            q32, v32, w32 = qq.astype(np.float32), vv.astype(np.float32), ws.astype(np.float32)
-            g = gpu_run(m, q32, v32, uu.astype(np.float32), w32, fr, ms)
-            r = oracle_run(o, q32, v32, uu.astype(np.float32), w32, fr, ms)
-            o.set_mode("converged")
-            rc = oracle_run(o, q32, v32, uu.astype(np.float32), w32, fr, ms)
-            o.set_mode("mirror")
-            band = margin_band_worlds(oracle_mod, m, q32, v32, uu.astype(np.float32), w32, fr, ms)
-            nband += int(band.sum())
-            for w in range(32):
-                if band[w]:
-                    continue
-                # distance of the truncated (4-iteration) FP64 step from the converged one: where
-                # the truncated Newton has not reached the solution its iterate depends on the
-                # rounding along the way, and the comparison is conditioned by that distance
-                trunc = max(rel_err(rc[k][w], r[k][w]) for k in ("qpos", "qvel"))
-                ntrunc += trunc > RTOL_STEP
-                tol = RTOL_STEP + 0.1 * trunc
-                err = max(rel_err(g[k][w], r[k][w]) for k in ("qpos", "qvel"))
-                assert err <= slack * tol, (s, w, err, trunc)
-                nover += err > tol
-                nsamp += 1
-                worst = max(worst, err / tol)
-        o.step(uu, qq, vv, ws, frd, msd, st)
-    # most sampled worlds are compared at the plain step tolerance
-    assert worst <= slack and nover <= nsamp // 100 and ntrunc <= 32 * (horizon // 25) // 2, (worst, nover, ntrunc)
-    # samples with a moving contact on its inclusion threshold (feet landing) stay a minority
-    assert nband <= 32 * (horizon // 25) // 6, nband
+    """Along the oracle's own trajectory (up to env step 1000 for the quadruped and humanoid
+    workloads), hand its state (rounded to FP32) to the GPU every 25 env steps and compare one
+    env step of 32 worlds: qpos, qvel and the last substep's contacts at the step tolerance
+    wherever both paths made the same contacts, rows, Newton updates and active sets (checked
+    from the per-substep work records of both); see StepTally for the other two cases."""
+    T = teacher_forced(oracle_mod, name, horizon)
+    assert T.nmatch >= 0.8 * T.n
 
 
 # ------------------------------------------------------------------ contact-free rollouts
@@ -364,7 +340,7 @@ def test_sphere_box_contacts_random_poses(oracle_mod):
 def test_newton_iterations_match_oracle(oracle_mod, name):
     """The GPU ends Newton when no row changed sides since the last Hessian; the oracle ends
     it by its FP64 gradient test.  On the same states both take the same number of
-    iterations, except where a row sits on its breakpoint to rounding."""
+    iterations, except where a row sits on its breakpoint to rounding (at most 2 %)."""
     import torch
     import paper_2601_22074_amd as rb
     m = substeps1(by_name(name))
@@ -387,8 +363,7 @@ def test_newton_iterations_match_oracle(oracle_mod, name):
     M.close()
     oi = np.array([o.forward(q1[w], v1[w], u[w], ws1[w], None if fr is None else fr[w],
                              None if ms is None else ms[w])["niter"] for w in range(64)])
-    assert np.mean(gi == oi) >= 0.85, (gi, oi)
-    assert abs(gi.mean() - oi.mean()) <= 0.25
+    assert np.mean(gi == oi) >= 0.98, (gi, oi)
 
 
 # ------------------------------------------------------------------ system properties
