@@ -212,10 +212,12 @@ def run_mix(args):
 # ------------------------------------------------------------------ serving
 def run_serve(args):
     """The serving form: (a) the offered load (Poisson rate --rate for --seconds), stopped at
-    that time with whatever is still queued counted as backlog; (b) a rate the measured
-    throughput sustains (80 % of it), run to completion, for steady-state latency."""
+    that time with whatever is still queued counted as backlog, served by the fused server and,
+    on the same trace, by the plain-launch baseline (one rb_step launch per live request per
+    tick); (b) a rate the fused server's measured throughput sustains (80 % of it), run to
+    completion, for steady-state latency."""
     import torch
-    from paper_2601_22074_amd.serve import Server
+    from paper_2601_22074_amd.serve import PlainServer, Server
     from workloads import robots
     from workloads.requests import NAMES, DeviceSource, mean_request_work, poisson_requests
 
@@ -223,24 +225,33 @@ def run_serve(args):
         print(msg, file=sys.stderr, flush=True)
 
     src = DeviceSource({k: robots.by_name(k) for k in NAMES})
-    budget = int(args.budget_mb) << 20
+    # admission by the device's free memory, or by a configured budget as well
+    budget = (int(args.budget_mb) << 20) if args.budget_mb > 0 else None
 
-    srv = Server(src, budget=budget)
-    # warm-up: compile and first launches outside the timed runs
-    srv.run_script(poisson_requests(50.0, 0.2, seed=99, wmax=64, hmax=50))
-    srv.close()
+    for cls in (Server, PlainServer):
+        srv = cls(src, budget=budget)
+        # warm-up: compile and first launches outside the timed runs
+        srv.run_script(poisson_requests(50.0, 0.2, seed=99, wmax=64, hmax=50))
+        srv.close()
 
-    srv = Server(src, budget=budget)
     reqs = poisson_requests(args.rate, args.seconds, seed=1)
-    log(f"serve: offered {len(reqs)} requests over {args.seconds} s")
-    a = srv.run_timed(reqs, stop_after=args.seconds, progress=log)
-    srv.close()
+    runs = {}
+    for key, cls in (("fused", Server), ("plain", PlainServer)):
+        srv = cls(src, budget=budget)
+        log(f"serve ({key}): offered {len(reqs)} requests over {args.seconds} s")
+        runs[key] = srv.run_timed(reqs, stop_after=args.seconds, progress=log)
+        srv.close()
+    a = runs["fused"]
     offered = args.rate * mean_request_work()
     lam = 0.8 * a["env_steps_per_s"] / mean_request_work()
     srv = Server(src, budget=budget)
     reqs_b = poisson_requests(lam, args.sustain_seconds, seed=2)
     log(f"serve: sustainable-rate run at {lam:.2f}/s, {len(reqs_b)} requests")
     b = srv.run_timed(reqs_b, stop_after=3 * args.sustain_seconds, progress=log)
+    srv.close()
+    srv = PlainServer(src, budget=budget)
+    log(f"serve (plain): the same sustainable-rate trace")
+    bp = srv.run_timed(reqs_b, stop_after=3 * args.sustain_seconds, progress=log)
     srv.close()
     out = {
         "metric": f"env-steps/sec served at Poisson {args.rate:g} requests/s; p50/p99 request latency",
@@ -251,11 +262,13 @@ def run_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT["serve"], "rate_per_s": args.rate, "seconds": args.seconds,
-                   "budget_bytes": budget},
+                   "budget_bytes": a["budget_bytes"]},
         "offered_env_steps_per_s": offered,
         "offered_load": a,
+        "offered_load_plain_launches": runs["plain"],
         "sustainable_rate_per_s": lam,
         "sustainable": b,
+        "sustainable_plain_launches": bp,
     }
     print(json.dumps(out), flush=True)
 
@@ -289,7 +302,9 @@ def tree_info(model):
 
 
 def flops_per_env_step(model, stats_mean):
-    """Algorithmic FP32 operations of one env step of the tree-sparse method (multiply-add = 2).
+    """A cross-check of the roofline numerator (which comes from the oracle's operation counts):
+    a per-stage hand count of the tree-sparse method's FP32 operations (multiply-add = 2) fed
+    with the kernel's own work per substep.
 
     stats_mean: per-substep means of (contacts, active rows, Newton iterations, line-search
     segments), measured by the kernel's stats tap on a subset of the same worlds."""
@@ -353,38 +368,90 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(W, budget_s=12.0, single_budget_s=3.0):
-    """The FP64 oracle on the host cores (OpenMP over worlds) over a bounded sample, and the
-    same sample on one thread."""
+CPU_PHASE = 20        # env steps the CPU baseline's sample starts into the workload
+CPU_STEPS = 10        # env steps the CPU baseline times
+CPU_WORLDS = 4096     # worlds of the OpenMP run (the workload's own count if smaller)
+CPU_WORLDS_1T = 256   # worlds of the single-thread run
+
+
+def _oracle_inputs(W, nw, s):
+    f = lambda a: None if a is None else a[:nw].astype(np.float64)
+    return W["ctrl"][min(s // 20, len(W["ctrl"]) - 1)][:nw].astype(np.float64), f(W["friction"]), f(W["mass_scale"])
+
+
+def cpu_baseline(W):
+    """The FP64 oracle on the host cores (OpenMP over worlds) over a fixed sample of the same
+    workload: min(CPU_WORLDS, worlds) worlds advanced untimed by the oracle to env step
+    CPU_PHASE (the robots are down and in contact, as in the timed GPU run), then CPU_STEPS env
+    steps timed; and the first CPU_WORLDS_1T of those worlds on one thread.  The sample does not
+    depend on the bench's step count."""
     from oracle import Oracle
-    m = W["model"]
-    o = Oracle(m)
+    o = Oracle(W["model"])
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     if os.environ.get("OMP_NUM_THREADS", "").isdigit():
         cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
-    nw = min(len(W["worlds"]), 512 if W["name"].startswith("humanoid") else 2048)
+    nw = min(len(W["worlds"]), CPU_WORLDS)
+    q = W["qpos"][:nw].astype(np.float64)
+    v = W["qvel"][:nw].astype(np.float64)
+    ws = np.zeros_like(v)
+    st = np.zeros(nw, np.uint32)
+    for s in range(CPU_PHASE):
+        u, fr, ms = _oracle_inputs(W, nw, s)
+        o.step(u, q, v, ws, fr, ms, st, nthreads=cores)
 
-    def run(threads, budget):
-        q = W["qpos"][:nw].astype(np.float64)
-        v = W["qvel"][:nw].astype(np.float64)
-        ws = np.zeros_like(v)
-        fr = None if W["friction"] is None else W["friction"][:nw].astype(np.float64)
-        ms = None if W["mass_scale"] is None else W["mass_scale"][:nw].astype(np.float64)
-        st = np.zeros(nw, np.uint32)
-        done = 0
+    def run(n, threads):
+        qq, vv, ww, ss = q[:n].copy(), v[:n].copy(), ws[:n].copy(), st[:n].copy()
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < budget and done < W["nsteps"]:
-            u = W["ctrl"][done // 20][:nw].astype(np.float64)
-            o.step(u, q, v, ws, fr, ms, st, nthreads=threads)
-            done += 1
-        return done, time.perf_counter() - t0
+        for s in range(CPU_PHASE, CPU_PHASE + CPU_STEPS):
+            u, fr, ms = _oracle_inputs(W, n, s)
+            o.step(u, qq, vv, ww, fr, ms, ss, nthreads=threads)
+        return time.perf_counter() - t0
 
-    done, dt = run(cores, budget_s)
-    done1, dt1 = run(1, single_budget_s)
-    return {"value": nw * done / dt, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nw} worlds x {done} env steps of the same workload from the same initial states, "
-                      f"FP64, OpenMP over worlds, {dt:.1f} s",
-            "single_thread_value": nw * done1 / dt1, "cpu_model": _cpu_model(), "cpu_count": os.cpu_count()}
+    dt = run(nw, cores)
+    n1 = min(nw, CPU_WORLDS_1T)
+    dt1 = run(n1, 1)
+    return {"value": nw * CPU_STEPS / dt, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nw} worlds x env steps {CPU_PHASE}-{CPU_PHASE + CPU_STEPS - 1} of the same workload "
+                      f"(advanced to step {CPU_PHASE} by the oracle, untimed), FP64, OpenMP over worlds, {dt:.1f} s",
+            "single_thread_value": n1 * CPU_STEPS / dt1,
+            "single_thread_sample": f"{n1} of those worlds, same steps, one thread, {dt1:.1f} s",
+            "cpu_model": _cpu_model(), "cpu_count": os.cpu_count()}
+
+
+ORACLE_STAGES = ("kinematics", "inertia+bias", "factorisation+a0", "collision", "constraint rows", "newton",
+                 "integration")
+
+
+def oracle_work(W, nworlds, first, nsteps):
+    """Algorithmic work per env step from the oracle: its per-stage operation counts of the
+    tree-sparse formulation (a multiply-add counts 2), evaluated on its own contacts, rows,
+    active sets, Newton updates and line-search segments, and its per-substep work record means,
+    over nworlds worlds of the workload, env steps [first, first + nsteps) of the oracle's own
+    trajectory from the same initial states and controls."""
+    from oracle import Oracle
+    o = Oracle(W["model"])
+    nw = min(nworlds, len(W["worlds"]))
+    q = W["qpos"][:nw].astype(np.float64)
+    v = W["qvel"][:nw].astype(np.float64)
+    ws = np.zeros_like(v)
+    st = np.zeros(nw, np.uint32)
+    ops = np.zeros(7)
+    sub = np.zeros(5)
+    for s in range(first + nsteps):
+        u, fr, ms = _oracle_inputs(W, nw, s)
+        work = {} if s >= first else None
+        o.step(u, q, v, ws, fr, ms, st, work=work)
+        if work is not None:
+            ops += work["ops"][:, 1, :].sum(0)
+            sub += work["sub"][:, :, :5].reshape(-1, 5).sum(0)
+    K = W["model"]["opt"]["nsubsteps"]
+    per = ops / (nw * nsteps)
+    rec = sub / (nw * nsteps * K)
+    return {"flops_per_env_step": float(per.sum()),
+            "stage_flops_per_env_step": {k: float(x) for k, x in zip(ORACLE_STAGES, per)},
+            "per_substep": {"contacts": rec[0], "rows": rec[1], "newton_updates": rec[2], "active_rows": rec[3],
+                            "line_search_segments": rec[4]},
+            "sample": f"{nw} worlds x env steps {first}-{first + nsteps - 1}, the oracle's own trajectory"}
 
 
 def kernel_source_hash():
@@ -522,6 +589,9 @@ def main():
                     help="resident waves per SIMD of the plain launch (0: automatic)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--stats-worlds", type=int, default=512)
+    ap.add_argument("--flop-worlds", type=int, default=64,
+                    help="worlds of the oracle run whose operation counts give the roofline numerator")
+    ap.add_argument("--flop-steps", type=int, default=1000, help="at most this many env steps of that run")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     ap.add_argument("--resident", type=int, default=2048,
@@ -529,7 +599,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: request arrival rate (1/s)")
     ap.add_argument("--seconds", type=float, default=60.0, help="serve: arrival window of the offered-load run")
     ap.add_argument("--sustain-seconds", type=float, default=20.0, help="serve: arrival window at the sustained rate")
-    ap.add_argument("--budget-mb", type=int, default=1024, help="serve: HBM budget for admitted requests (MiB)")
+    ap.add_argument("--budget-mb", type=int, default=0,
+                    help="serve: HBM budget for admitted requests (MiB); 0: the device's free memory")
     ap.add_argument("--summarize-trace", nargs=4, metavar=("DB", "TITLE", "OUT", "COMMAND"),
                     help="write a profiles/ table of the top kernels of a trace database and exit")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("DB", "TITLE", "OUT", "COMMAND"),
@@ -634,9 +705,12 @@ def main():
             acc += stats.double().sum(0).cpu().numpy()
     Ksub = m["opt"]["nsubsteps"]
     stats_mean = acc[:4] / (ns * K * Ksub)      # per substep per world
-    cyc = acc[4:]
+    cyc = acc[4:4 + rb.rbstep.NSTAGE]
     stage_share = {n: float(c / cyc.sum()) for n, c in zip(rb.rbstep.STAGES, cyc)} if cyc.sum() > 0 else {}
-    fl = flops_per_env_step(m, stats_mean)
+    fl_kernel = flops_per_env_step(m, stats_mean)
+    # the numerator: the oracle's operation counts on its own trajectory of the same workload
+    ow = oracle_work(W, args.flop_worlds, warm, min(K, args.flop_steps))
+    fl = ow["flops_per_env_step"]
     hb = hbm_bytes_per_env_step(m, ncon_last if con is not None else 0, con is not None)
     launch_s = float(np.mean(per)) / 1e3
     achieved_tf = fl * nw / launch_s / 1e12
@@ -663,7 +737,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_TFLOPS,
                      "traffic": None if traffic is None else traffic,
-                     "flops_per_env_step": fl, "launch_ms": launch_s * 1e3},
+                     "flops_per_env_step": fl, "flops_source": "oracle operation counts (tree-sparse formulation)",
+                     "oracle_work": ow, "flops_per_env_step_kernel_stats_estimate": fl_kernel,
+                     "launch_ms": launch_s * 1e3},
         "hbm": {"algorithmic_bytes_per_env_step": hb, "achieved_GBs": hb * nw / launch_s / 1e9,
                 "peak_GBs": PEAK_HBM_GBS, "frac": hb * nw / launch_s / 1e9 / PEAK_HBM_GBS},
         "work_per_substep": {"contacts": stats_mean[0], "active_rows": stats_mean[1],

@@ -63,18 +63,22 @@ class SlotPool:
 
 
 class Scheduler:
-    """FIFO admission against an HBM budget: a request is admitted when the bytes its worlds
-    occupy (``bytes_per_world[name] * n``) fit in what the budget has left and its model's
-    pool has a contiguous range of n slots.  The head of the queue blocks later requests, so
-    large requests are not starved."""
+    """FIFO admission against HBM: a request is admitted when the bytes its worlds occupy
+    (``bytes_per_world[name] * n``) fit in what the budget has left, in what the device reports
+    free (``free_probe()``, bytes, less ``reserve``) when a probe is given, and its model's pool
+    has a contiguous range of n slots.  The head of the queue blocks later requests, so large
+    requests are not starved."""
 
-    def __init__(self, capacity: dict, bytes_per_world: dict, budget: int):
+    def __init__(self, capacity: dict, bytes_per_world: dict, budget: int, free_probe=None, reserve: int = 0):
         self.pools = {k: SlotPool(c) for k, c in capacity.items()}
         self.bpw = dict(bytes_per_world)
         self.budget = int(budget)
+        self.free_probe = free_probe
+        self.reserve = int(reserve)
         self.used = 0
         self.queue = collections.deque()
         self.peak = 0
+        self.blocked_by_device = 0   # admissions deferred because the device had too little free
 
     def need(self, req) -> int:
         return self.bpw[req.name] * req.n
@@ -94,6 +98,9 @@ class Scheduler:
             r = self.queue[0]
             need = self.need(r)
             if self.used + need > self.budget:
+                break
+            if self.free_probe is not None and need > self.free_probe() - self.reserve:
+                self.blocked_by_device += 1
                 break
             s = self.pools[r.name].alloc(r.n)
             if s is None:
@@ -138,15 +145,26 @@ def bytes_per_world(model: "rbstep.Model", ncap: int) -> int:
     return model.bytes_per_world + 4 * (2 * model.nq + 2 * model.nv + max(model.nu, 1) + 2)
 
 
+DEVICE_RESERVE = 512 << 20   # device bytes admission leaves free for everything else
+
+
+def device_free_bytes() -> int:
+    """Free device memory as the runtime reports it (hipMemGetInfo through torch)."""
+    import torch
+    return int(torch.cuda.mem_get_info()[0])
+
+
 class Server:
     """Continuous-batching server over the models in ``source.models`` (name -> model dict).
 
-    budget: HBM bytes that admitted requests may hold; capacity: slots per model pool
+    budget: HBM bytes that admitted requests may hold (default: the device's free memory at
+    start, less DEVICE_RESERVE); admission also re-reads the device's free memory before each
+    request (``free_probe``, default ``device_free_bytes``).  capacity: slots per model pool
     (default: what the budget could hold of that model alone, at most ``max_pool``).
     inflight: ticks the host may run ahead of the device."""
 
-    def __init__(self, source, budget: int = 1 << 30, capacity: dict | None = None, max_pool: int = 1 << 17,
-                 inflight: int = 3, grid: int = 0):
+    def __init__(self, source, budget: int | None = None, capacity: dict | None = None, max_pool: int = 1 << 17,
+                 inflight: int = 3, grid: int = 0, free_probe=device_free_bytes, reserve: int = DEVICE_RESERVE):
         import torch
         self.torch = torch
         self.src = source
@@ -154,8 +172,28 @@ class Server:
         self.names = list(source.models)
         self.models = {k: rbstep.Model(m) for k, m in source.models.items()}
         bpw = {k: bytes_per_world(self.models[k], 0) for k in self.names}
+        if budget is None:
+            budget = max(0, (free_probe() if free_probe is not None else 1 << 30) - reserve)
         cap = capacity or {k: max(1, min(max_pool, budget // bpw[k])) for k in self.names}
-        self.sched = Scheduler(cap, bpw, budget)
+        self.sched = Scheduler(cap, bpw, budget, free_probe, reserve)
+        self.live: list[_Live] = []
+        self.dirty = True
+        self.inflight = inflight
+        self.grid = grid
+        self.ticks = collections.deque()
+        self.pending: list[Result] = []
+        self.results: dict[int, Result] = {}
+        self.env_steps = 0
+        self.nticks = 0
+        self.launches = 0
+        self.stream = torch.cuda.current_stream()
+        self.t0 = None
+        self.ev0 = None
+        self._init_device(cap)
+
+    def _init_device(self, cap):
+        """One slot pool per model and one fused launch plan over the pools."""
+        torch = self.torch
         self.pools = []
         for k in self.names:
             M, c = self.models[k], cap[k]
@@ -172,18 +210,6 @@ class Server:
         # heaviest models first in the work list (rough per-world cost of one env step)
         self.cost = {k: self.models[k].nv ** 2 + 8 * self.pools[i]["batch"].ncap + 4 * self.models[k].nbody
                      for i, k in enumerate(self.names)}
-        self.live: list[_Live] = []
-        self.dirty = True
-        self.inflight = inflight
-        self.grid = grid
-        self.ticks = collections.deque()
-        self.pending: list[Result] = []
-        self.results: dict[int, Result] = {}
-        self.env_steps = 0
-        self.nticks = 0
-        self.stream = torch.cuda.current_stream()
-        self.t0 = None
-        self.ev0 = None
 
     def close(self):
         self.torch.cuda.synchronize()
@@ -237,6 +263,7 @@ class Server:
         if len(self.ticks) >= self.inflight:
             self.ticks.popleft().synchronize()
         self.plan.step()
+        self.launches += 1
         ev = self.torch.cuda.Event()
         ev.record(self.stream)
         self.ticks.append(ev)
@@ -334,4 +361,91 @@ class Server:
             "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_latency_s": float(lat.mean()) if lat.size else None,
             "peak_budget_bytes": self.sched.peak, "budget_bytes": self.sched.budget,
+            "launches": self.launches, "admissions_blocked_by_device_memory": self.sched.blocked_by_device,
         }
+
+
+class PlainServer(Server):
+    """The same request loop served by plain launches, the baseline of the fused server: each
+    live request owns a batch of its model (batches are reused across requests of the model:
+    the smallest idle one that holds the request, else a new one of the next power-of-two
+    capacity) and every tick makes one plain ``rb_step`` launch per live request."""
+
+    def _init_device(self, cap):
+        self.idle = {k: [] for k in self.names}   # name -> [(capacity, state dict)]
+        self.all_batches = []
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        for d in self.all_batches:
+            d["batch"].close()
+        for M in self.models.values():
+            M.close()
+
+    def _take(self, name, n):
+        t = self.torch
+        free = self.idle[name]
+        fit = [i for i, (c, _) in enumerate(free) if c >= n]
+        if fit:
+            i = min(fit, key=lambda i: free[i][0])
+            return free.pop(i)[1]
+        M = self.models[name]
+        c = 1 << max(0, (n - 1).bit_length())
+        d = dict(name=name, cap=c, batch=rbstep.Batch(M, c), q=t.zeros(c, M.nq, device=self.dev),
+                 v=t.zeros(c, M.nv, device=self.dev), u=t.zeros(c, max(M.nu, 1), device=self.dev),
+                 st=t.zeros(c, dtype=t.int32, device=self.dev))
+        self.all_batches.append(d)
+        return d
+
+    def _admit(self, req, start: int) -> None:
+        t = self.torch
+        n = req.n
+        d = self._take(req.name, n)
+        M = self.models[req.name]
+        gen = self.src.generator(req.seed)
+        self.src.initial(req.name, n, gen, d["q"][:n], d["v"][:n])
+        fr, ms = self.src.params(req.name, n, gen)
+        if fr is not None:
+            d["batch"].set_params_at(rbstep.PARAM_FRICTION, 0, fr.contiguous())
+        if ms is not None:
+            d["batch"].set_params_at(rbstep.PARAM_MASS_SCALE, 0, ms.contiguous())
+        d["batch"].reset(t.arange(n, dtype=t.int32, device=self.dev))
+        if M.nu:
+            self.src.ctrl(req.name, gen, d["u"][:n])
+        L = _Live(req, -1, start, gen)
+        L.state = d
+        self.live.append(L)
+
+    def _complete(self, L: _Live) -> None:
+        d, n = L.state, L.req.n
+        r = Result(L.req.rid, d["q"][:n].clone(), d["v"][:n].clone(), d["st"][:n].clone(), L.req.arrival)
+        r.event = self.torch.cuda.Event(enable_timing=True)
+        r.event.record(self.stream)
+        self.pending.append(r)
+        self.sched.release(L.req, L.start)
+        # stream order keeps the batch's next user behind the copies above
+        self.idle[L.req.name].append((d["cap"], d))
+
+    def _tick(self) -> None:
+        if len(self.ticks) >= self.inflight:
+            self.ticks.popleft().synchronize()
+        for L in self.live:
+            d, n = L.state, L.req.n
+            M = self.models[L.req.name]
+            d["batch"].step(d["u"][:n] if M.nu else None, d["q"][:n], d["v"][:n], None, d["st"][:n])
+            self.launches += 1
+        ev = self.torch.cuda.Event()
+        ev.record(self.stream)
+        self.ticks.append(ev)
+        self.nticks += 1
+        still = []
+        for L in self.live:
+            self.env_steps += L.req.n
+            L.done += 1
+            if L.done >= L.req.horizon:
+                self._complete(L)
+            else:
+                if L.done % 20 == 0 and self.models[L.req.name].nu:
+                    self.src.ctrl(L.req.name, L.gen, L.state["u"][:L.req.n])
+                still.append(L)
+        self.live = still

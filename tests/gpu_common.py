@@ -235,36 +235,60 @@ def classify(gsub, osub):
 DEPTH_TOL = 3e-7      # FP32 contact-depth error of the GPU's kinematics (asserted on the stage taps)
 
 
-def free_lift(model, q, dz):
-    """Copy of q [n, nq] (float64) with every free joint raised by dz along z."""
-    q = np.array(q, np.float64)
-    for (t, qa, _), j in zip(_layout(model), model["joints"]):
-        if t == "free":
-            q[:, qa + 2] += dz
-    return q
+FP32_U = 2.0 ** -24    # unit roundoff of FP32
+FLOOR_ULPS = 4         # input perturbation of the FP32 floor, in unit roundoffs
+FD_REL = 1e-9          # finite-difference step, relative to max(|x|, 1)
 
 
-def depth_floor(o, model, q32, v32, u32, w32, fr, ms, j):
-    """The FP32 floor of world j's env step: how far the FP64 step moves (R23 metric, qpos and
-    qvel) when the floating bases are displaced by +-DEPTH_TOL along z, i.e. when every contact
-    depth moves by the FP32 error the GPU's kinematics may carry.  Contact rows are stiff within
-    the impedance width (1 mm), so some states resolve only to this floor in single precision."""
+def _floor(f, xs, scale):
+    """First-order worst case of |f(xs + d) - f(xs)| over perturbations |d_i| <= FLOOR_ULPS *
+    FP32_U * max(|x_i|, 1) of every element of the arrays xs, divided elementwise by
+    scale(f(xs)): the componentwise condition of f at single-precision inputs on R23's scale.
+    Derivatives by forward differences of FD_REL * max(|x_i|, 1), small enough that no contact
+    flips its inclusion."""
+    y0 = f(*xs)
+    bound = np.zeros_like(y0)
+    for k, x in enumerate(xs):
+        for i in range(x.size):
+            h = FD_REL * max(abs(x.flat[i]), 1.0)
+            xp = [a.copy() for a in xs]
+            xp[k].flat[i] += h
+            bound += np.abs(f(*xp) - y0) / h * (FLOOR_ULPS * FP32_U * max(abs(x.flat[i]), 1.0))
+    return float(np.max(bound / scale(y0)))
+
+
+def fp32_floor(o, model, q32, v32, u32, w32, fr, ms, j):
+    """The FP32 floor of world j's env step (R23 metric over qpos and qvel): how far the FP64
+    step can move when its inputs (qpos, qvel, warm start) carry the rounding of a few units of
+    single precision (_floor).  A single-precision step that rounds backward-stably resolves the
+    step only to about this; it is large where stiff contact rows (aref moves by k imp ~ 2600 /
+    s^2 per metre of depth) act on light dofs, and where the 4-update Newton iterate is
+    truncated.  Computed by the oracle alone."""
     sl = slice(j, j + 1)
     f64 = lambda a: None if a is None else np.asarray(a[sl], np.float64)
     u = np.zeros((1, o.nu)) if u32 is None else np.asarray(u32[sl], np.float64)
 
-    def step(dz):
-        q = free_lift(model, q32[sl], dz)
-        v, w = np.array(v32[sl], np.float64), np.array(w32[sl], np.float64)
+    def step(q, v, w):
+        q, v, w = q[None].copy(), v[None].copy(), w[None].copy()
         o.step(u, q, v, w, f64(fr), f64(ms))
-        return free_lift(model, q, -dz), v
+        return np.concatenate([q[0], v[0]])
 
-    q0, v0 = step(0.0)
-    out = 0.0
-    for dz in (DEPTH_TOL, -DEPTH_TOL):
-        q, v = step(dz)
-        out = max(out, rel_err(q, q0), rel_err(v, v0))
-    return out
+    xs = [np.asarray(x[j], np.float64) for x in (q32, v32, w32)]
+    return _floor(step, xs, lambda y: np.maximum(np.abs(y), 1.0))
+
+
+def qacc_floor(oracle_mod, model, q, v, u, ws, fr, ms):
+    """fp32_floor's counterpart for one substep's constrained acceleration at one world's state
+    (vec_err metric)."""
+    o = oracle_mod.Oracle(model)
+    acc = lambda qq, vv, ww: o.forward(qq, vv, u, ww, fr, ms)["qacc"]
+    xs = [np.asarray(x, np.float64) for x in (q, v, ws)]
+    return _floor(acc, xs, lambda y: max(np.max(np.abs(y)), 1.0))
+
+
+def _memo(f):
+    box = []
+    return lambda: box[0] if box else (box.append(f()) or box[0])
 
 
 class StepTally:
@@ -272,11 +296,12 @@ class StepTally:
 
     Per sample (R23 metric, tolerance RTOL_STEP):
       * same work records on both paths ('match'): qpos and qvel within RTOL_STEP (or, where the
-        oracle's own step moves by more than that when every contact depth moves by DEPTH_TOL,
-        within that FP32 floor: depth_floor), and the
-        last substep's contacts (keys exactly; dist and pos within RTOL_STEP m, frame within
-        RTOL_STEP, the qpos bar carried to the contact geometry; force within RTOL_STEP of the
-        world's largest contact force, the accelerations' bar carried to the multipliers);
+        oracle's own step moves by more than that when its inputs carry single-precision rounding,
+        within that FP32 floor: fp32_floor), and the last substep's contacts (keys exactly;
+        dist and pos within RTOL_STEP m, frame within RTOL_STEP, the qpos bar carried to the
+        contact geometry; force within RTOL_STEP of the world's largest contact force plus
+        RTOL_STEP of the contact's own: the accelerations' bar carried to the multipliers, and
+        the stage taps' bar on A-hat carried through the rows' D);
       * different contacts or rows in some substep ('contacts'): allowed only where the oracle
         finds a contact within MARGIN_BAND of its inclusion threshold at the start of a substep
         (the contact pair-set rule); qpos and qvel are then not compared;
@@ -284,7 +309,8 @@ class StepTally:
         Newton iterate depends on its path, and the bar is RTOL_STEP plus a tenth of the FP64
         distance between the 4-iteration and the converged step.
     Over the workload: 'path' samples at most 5 %, iteration counts equal in at least 98 % of
-    the compared samples, 'contacts' samples at most a sixth."""
+    the compared samples, 'contacts' samples at most a sixth, samples on their FP32 floor at
+    most 1 %."""
 
     def __init__(self, name):
         self.name = name
@@ -293,8 +319,9 @@ class StepTally:
         self.cworst = dict(dist=0.0, pos=0.0, frame=0.0, force=0.0)
 
     def add(self, g, r, gw, rw, band, where, floor=None):
-        """floor: callable giving the sample's FP32 floor (depth_floor), asked only where the
+        """floor: callable giving the sample's FP32 floors (fp32_floor), asked only where an
         error exceeds RTOL_STEP."""
+        floor = _memo(floor) if floor is not None else (lambda: 0.0)
         gs, os_ = g["sub"][gw], r["sub"][rw]
         kind = classify(gs, os_)
         self.n += 1
@@ -308,7 +335,7 @@ class StepTally:
         if kind == "match":
             self.nmatch += 1
             if err > RTOL_STEP:
-                fl = floor() if floor is not None else 0.0
+                fl = floor()
                 assert err <= fl, (where, err, fl)
                 self.nfloor += 1
             else:
@@ -328,10 +355,16 @@ class StepTally:
             return
         assert [tuple(x) for x in gc["geom"][gw, :nc]] == [tuple(x) for x in rc["geom"][rw, :nc]], where
         assert list(gc["feature"][gw, :nc]) == list(rc["feature"][rw, :nc]), where
+        fg, fr_ = gc["force"][gw, :nc].astype(np.float64), rc["force"][rw, :nc]
         e = dict(dist=np.abs(gc["dist"][gw, :nc] - rc["dist"][rw, :nc]).max(),
                  pos=rel_err(gc["pos"][gw, :nc], rc["pos"][rw, :nc]),
                  frame=np.abs(gc["frame"][gw, :nc].reshape(nc, 9) - rc["frame"][rw, :nc].reshape(nc, 9)).max(),
-                 force=vec_err(gc["force"][gw, :nc], rc["force"][rw, :nc]))
+                 # per element: RTOL_STEP of the world's largest contact force (the accelerations'
+                 # bar carried to the multipliers) plus RTOL_STEP of the contact's own force (A-hat's
+                 # bar on the stage taps carried through D = imp / ((1 - imp) A-hat) into each of
+                 # its pyramid rows, whose forces make up all three components)
+                 force=np.max(np.abs(fg - fr_) / (max(np.abs(fr_).max(), 1.0)
+                                                   + np.linalg.norm(fr_, axis=1, keepdims=True))))
         for k, x in e.items():
             assert x <= RTOL_STEP, (where, k, x)
             self.cworst[k] = max(self.cworst[k], float(x))
@@ -372,7 +405,7 @@ def teacher_forced(oracle_mod, name, horizon, every=25, n=32):
             assert np.all(g["status"] & 1 == 0)
             for w in range(n):
                 T.add(g, r, w, w, band[w], (name, s, w),
-                      floor=lambda w=w: depth_floor(o, m, q32, v32, u32, w32, fr, ms, w))
+                      floor=lambda w=w: fp32_floor(o, m, q32, v32, u32, w32, fr, ms, w))
         o.step(uu, qq, vv, ws, frd, msd, st)
     T.finish()
     return T

@@ -3,8 +3,7 @@ launch, contacts returned), on a sample of worlds the oracle computes one by one
 import numpy as np
 import pytest
 
-from gpu_common import (RTOL_ROLLOUT, StepTally, band_worlds, depth_floor, gpu_run, gpu_step_records, oracle_run,
-                        oracle_step_records, rel_err)
+from gpu_common import StepTally, band_worlds, fp32_floor, gpu_step_records, oracle_step_records
 from workloads import inputs
 
 pytestmark = pytest.mark.gpu
@@ -42,22 +41,5 @@ def test_full_size_sampled_worlds(oracle_mod, name, n, start):
     T = StepTally(f"{name} x{n} from step {start}")
     for j, w in enumerate(idx):
         T.add(g, r, w, j, band[j], (name, n, start, int(w)),
-              floor=lambda j=j: depth_floor(o, m, q[idx], v[idx], u[idx], ws[idx], sub(fr), sub(ms), j))
+              floor=lambda j=j: fp32_floor(o, m, q[idx], v[idx], u[idx], ws[idx], sub(fr), sub(ms), j))
     T.finish()
-
-
-def test_chain_rollout_500_steps(oracle_mod):
-    """The 3-link chain workload (64 worlds, 500 steps, dt 2 ms): along the GPU's own 500-step
-    rollout, every 50 steps the oracle takes the GPU's state and both advance 10 steps."""
-    W = inputs.workload("chain3", 64, 500)
-    m = W["model"]
-    o = oracle_mod.Oracle(m)
-    q, v = W["qpos"].copy(), W["qvel"].copy()
-    for start in range(0, 500, 50):
-        g10 = gpu_run(m, q, v, nsteps=10)
-        r10 = oracle_run(o, q, v, nsteps=10)
-        assert rel_err(g10["qpos"], r10["qpos"]) <= RTOL_ROLLOUT
-        assert rel_err(g10["qvel"], r10["qvel"]) <= RTOL_ROLLOUT
-        g50 = gpu_run(m, q, v, nsteps=50)
-        q, v = g50["qpos"], g50["qvel"]
-    assert np.all(np.isfinite(q))

@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_common import StepTally, band_worlds, by_name, depth_floor, gpu_step_records, oracle_step_records
+from gpu_common import StepTally, band_worlds, by_name, fp32_floor, gpu_step_records, oracle_step_records
 from helpers import lever, lever_rest_angle
 from workloads import inputs
 
@@ -45,7 +45,7 @@ def test_single_step_outside_limits(oracle_mod, name):
     band = band_worlds(oracle_mod, m, q, v, u, ws, fr, ms)
     T = StepTally(f"{name} outside its limits")
     for w in range(n):
-        T.add(g, r, w, w, band[w], (name, w), floor=lambda w=w: depth_floor(o, m, q, v, u, ws, fr, ms, w))
+        T.add(g, r, w, w, band[w], (name, w), floor=lambda w=w: fp32_floor(o, m, q, v, u, ws, fr, ms, w))
     T.finish()
     assert np.all(g["status"] & 1 == 0)
 

@@ -95,3 +95,41 @@ def test_timed_run_reports_latency():
     assert out["finished"] == len(reqs) and out["queued_at_end"] == 0
     assert 0 < out["p50_latency_s"] <= out["p99_latency_s"] < out["wall_s"]
     assert out["env_steps"] == sum(r.n * r.horizon for r in reqs)
+
+
+def test_plain_launch_server_same_results():
+    """The plain-launch baseline (one rb_step launch per live request per tick) serves the same
+    trace to the same bits as the fused server, with one launch per request-tick."""
+    from paper_2601_22074_amd.serve import PlainServer
+    fused, _, _ = _run(MIXED)
+    src = DeviceSource({k: robots.by_name(k) for k in NAMES})
+    s = PlainServer(src, capacity={k: 256 for k in NAMES})
+    res = s.run_script(MIXED)
+    launches = s.launches
+    plain = {rid: (r.qpos.cpu().numpy(), r.qvel.cpu().numpy(), r.status.cpu().numpy()) for rid, r in res.items()}
+    s.close()
+    assert launches == sum(r.horizon for r in MIXED)
+    for rid in fused:
+        for a, b in zip(fused[rid], plain[rid]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_default_budget_is_free_device_memory():
+    """Without a configured budget the server admits against the device's free memory (less a
+    reserve), read through hipMemGetInfo, and re-reads it at each admission."""
+    import torch
+    from paper_2601_22074_amd.serve import DEVICE_RESERVE, Server
+    src = DeviceSource({k: robots.by_name(k) for k in NAMES})
+    free0 = torch.cuda.mem_get_info()[0]
+    calls = []
+
+    def probe():
+        calls.append(1)
+        return torch.cuda.mem_get_info()[0]
+
+    s = Server(src, capacity={k: 256 for k in NAMES}, free_probe=probe)
+    assert abs(s.sched.budget - (free0 - DEVICE_RESERVE)) <= 64 << 20
+    n0 = len(calls)
+    s.run_script(MIXED[:3])
+    s.close()
+    assert len(calls) - n0 >= 3

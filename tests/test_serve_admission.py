@@ -111,3 +111,26 @@ def test_poisson_request_stream():
     assert {r.name for r in rs} == {"chain3", "quadruped", "humanoid", "arm_box"}
     assert abs(mean_request_work() / (n * h).mean() - 1) < 0.05
     assert poisson_requests(200.0, 1.0, seed=1)[:5] == rs[:5]
+
+
+def test_admission_bounded_by_device_free_memory():
+    """With a free-memory probe, a request waits while the device reports less free memory
+    (less the reserve) than its worlds need, even when the budget has room; it is admitted
+    once the device frees memory, in FIFO order."""
+    free = {"bytes": 10_000}
+    s = Scheduler({"a": 100}, {"a": 100}, budget=1 << 30, free_probe=lambda: free["bytes"], reserve=1_000)
+    s.submit(Request(0, "a", 50, 10, 0))     # needs 5000 <= 10000 - 1000
+    s.submit(Request(1, "a", 40, 10, 1))     # needs 4000
+    got = s.admit()
+    assert [r.rid for r, _ in got] == [0, 1]
+    free["bytes"] = 4_000                     # the device filled up
+    s.submit(Request(2, "a", 5, 10, 2))       # needs 500 > 4000 - 1000? no: 500 <= 3000
+    s.submit(Request(3, "a", 40, 10, 3))      # needs 4000 > 3000: waits (and blocks the queue)
+    got = s.admit()
+    assert [r.rid for r, _ in got] == [2]
+    assert s.admit() == [] and s.blocked_by_device >= 1
+    for r, st in [(Request(0, "a", 50, 10, 0), 0), (Request(1, "a", 40, 10, 1), 50)]:
+        s.release(r, st)
+    free["bytes"] = 20_000
+    got = s.admit()
+    assert [r.rid for r, _ in got] == [3]
