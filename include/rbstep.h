@@ -243,6 +243,29 @@ int rb_step_taps(rb_batch* batch, int32_t n, const float* dev_ctrl, float* dev_q
                  const rb_contacts* contacts, uint32_t* dev_status, float* dev_M, float* dev_bias,
                  float* dev_a0, float* dev_qacc, float* dev_efc, int32_t* dev_stats, void* hip_stream);
 
+/* Floats of the library's fixed per-device array that rb_step_noalloc works in (16 MiB). */
+#define RB_NOALLOC_MAX_FLOATS (4 << 20)
+
+/* One env step of n worlds, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It computes what rb_step
+ * computes on a batch of n slots that was just created or reset (zero warm start, status 0)
+ * with the given per-world parameters, and allocates nothing: the per-world working state the
+ * kernel keeps (warm start, status word, default parameters) lives in a fixed array of
+ * RB_NOALLOC_MAX_FLOATS floats that the library holds on each device it runs on until the
+ * process ends, cleared by a fill kernel at the start of every call (no memset, so the call can
+ * be captured in a graph).  Consequently the warm start does not carry from one call to the
+ * next.  Arguments as rb_step, with the model in place of a batch: dev_ctrl [n, nu] (NULL when
+ * nu = 0), dev_qpos [n, nq] and dev_qvel [n, nv] read and overwritten; dev_friction [n] and
+ * dev_mass_scale [n, nbody] (nullable, read only) for models with those per-world fields (NULL
+ * means 1.0); contacts (nullable) with capacity min(maxcon, 64) per world, as a batch created
+ * with contact_capacity 0; dev_status [n] (nullable).  Returns RB_EINVAL, before any launch,
+ * when n * (nv + 2 + nbody) exceeds RB_NOALLOC_MAX_FLOATS.  Every call on a GPU uses that GPU's
+ * one array: calls that overlap on one GPU (concurrent streams or host threads) race and must
+ * be serialised by the caller. */
+int rb_step_noalloc(const rb_model* model, int32_t n, const float* dev_ctrl, float* dev_qpos, float* dev_qvel,
+                    const float* dev_friction, const float* dev_mass_scale, const rb_contacts* contacts,
+                    uint32_t* dev_status, void* hip_stream);
+
 /* ---------------------------------------------------------------------------------------
  * Mixed-model batching: one fused launch steps several batches (of the same or different
  * models) together.  Every world runs the same per-world code as rb_step, so its results do

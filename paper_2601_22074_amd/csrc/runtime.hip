@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -627,6 +628,38 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
 int rb_record_error(int code, const char* msg) { return fail(code, msg); }
 
 // ====================================================================================== ABI
+// ---------------------------------------------------------------------------------------
+// the fixed per-device array of rb_step_noalloc
+// ---------------------------------------------------------------------------------------
+// One array per device, held until the process ends.  In host code its name stands for a
+// host-side symbol, not a device address: the device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is used.
+static __device__ __align__(256) float scratch[RB_NOALLOC_MAX_FLOATS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's scratch array, looked up on first use on the device.
+int scratch_address(float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(RB_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RB_OK;
+}
+}  // namespace
+
+
 extern "C" {
 
 const char* rb_last_error(void) { return g_err.c_str(); }
@@ -757,10 +790,9 @@ int rb_get_state(const rb_batch* b, int32_t n, float* ws, uint32_t* st, void* st
 // Resident waves per SIMD for a plain launch of n worlds: the batch's setting, or
 // automatically 4 when the model's LDS lets 16 worlds share a compute unit, its chain bound is
 // at most 16 and n is more than one round of the 3-wave kernel; otherwise 3.
-static int plain_waves(const rb_batch* b, int n) {
-    const DevModel& m = b->dm;
-    if (b->waves == 3 || m.maxd > 16) return 3;
-    if (b->waves == 4) return 4;
+static int auto_waves(const DevModel& m, int setting, int n) {
+    if (setting == 3 || m.maxd > 16) return 3;
+    if (setting == 4) return 4;
     static int ncu = 0, lds_cu = 0;
     if (ncu == 0) {
         int dev = 0;
@@ -772,6 +804,7 @@ static int plain_waves(const rb_batch* b, int n) {
     const bool lds_ok = (long)m.lds_floats * 4 * 16 <= (long)lds_cu;
     return lds_ok && n > 12 * ncu ? 4 : 3;
 }
+static int plain_waves(const rb_batch* b, int n) { return auto_waves(b->dm, b->waves, n); }
 
 static int step_impl(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* qvel, const rb_contacts* c,
                      uint32_t* status, const DevTaps* taps, void* stream) {
@@ -802,6 +835,53 @@ int rb_step_taps(rb_batch* b, int32_t n, const float* ctrl, float* qpos, float* 
                  void* stream) {
     DevTaps t{M, bias, a0, qacc, efc, stats};
     return step_impl(b, n, ctrl, qpos, qvel, c, status, &t, stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// the step without allocation: per-world working state in a fixed device array
+// ---------------------------------------------------------------------------------------
+int rb_step_noalloc(const rb_model* model, int32_t n, const float* ctrl, float* qpos, float* qvel,
+                    const float* friction, const float* mass_scale, const rb_contacts* c, uint32_t* status,
+                    void* stream) {
+    if (!model) return fail(RB_EINVAL, "null model");
+    if (n < 0) return fail(RB_EINVAL, "negative world count");
+    if (n == 0) return RB_OK;
+    if (!qpos || !qvel) return fail(RB_EINVAL, "qpos and qvel are required");
+    if (model->dm.nu > 0 && !ctrl) return fail(RB_EINVAL, "ctrl is required for a model with actuators");
+    const size_t nv = (size_t)model->nv_, nb = (size_t)model->nbody_;
+    const size_t need = (size_t)n * (nv + 2 + nb);
+    if (need > (size_t)RB_NOALLOC_MAX_FLOATS)
+        return fail(RB_EINVAL, "rb_step_noalloc: n * (nv + 2 + nbody) = " + std::to_string(need) +
+                                   " floats exceeds RB_NOALLOC_MAX_FLOATS (" + std::to_string(RB_NOALLOC_MAX_FLOATS) +
+                                   "); use a batch (rb_batch_create) or fewer worlds per call");
+    hipError_t pending = hipGetLastError();
+    if (pending != hipSuccess) return hip_fail(pending, "earlier asynchronous error");
+    float* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc != RB_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // every call starts as a freshly reset batch: zero warm start and status, per-world
+    // friction and mass scale 1 unless the caller passes them
+    DevWorlds W;
+    W.qacc_ws = base;
+    W.status = reinterpret_cast<uint32_t*>(base + (size_t)n * nv);
+    float* fr = base + (size_t)n * (nv + 1);
+    float* ms = base + (size_t)n * (nv + 2);
+    hipError_t e = rb_launch_fill(base, 0.0f, (size_t)n * (nv + 1), s);   // 0.0f is the zero status word too
+    W.friction = friction ? const_cast<float*>(friction) : fr;
+    W.mass_scale = mass_scale ? const_cast<float*>(mass_scale) : ms;
+    if (e == hipSuccess && !friction && model->dm.fr_pw) e = rb_launch_fill(fr, 1.0f, (size_t)n, s);
+    if (e == hipSuccess && !mass_scale && model->dm.ms_pw) e = rb_launch_fill(ms, 1.0f, (size_t)n * nb, s);
+    if (e != hipSuccess) return hip_fail(e, "rb_step_noalloc: clearing the scratch array");
+    DevModel dm = model->dm;
+    dm.ncap = std::max(std::min(model->maxcon_static, RB_MAX_CON), 1);   // a batch's default capacity
+    DevContactsOut co{};
+    if (c) {
+        co.ncon = c->ncon; co.geom = c->geom; co.feature = c->feature; co.dist = c->dist;
+        co.pos = c->pos; co.frame = c->frame; co.force = c->force;
+    }
+    e = rb_launch_step(dm, n, ctrl, qpos, qvel, W, c ? &co : nullptr, status, nullptr, auto_waves(dm, 0, n), s);
+    return e == hipSuccess ? RB_OK : hip_fail(e, "rb_step_noalloc launch");
 }
 
 // ---------------------------------------------------------------------------------------

@@ -36,9 +36,10 @@ _f64p = C.POINTER(C.c_double)
 EXPORTED = ["rb_last_error", "rb_model_create", "rb_model_create_json", "rb_model_destroy", "rb_model_info_get", "rb_batch_create",
             "rb_batch_destroy", "rb_batch_contact_capacity", "rb_batch_set_params", "rb_batch_set_params_at", "rb_batch_set_waves",
             "rb_world_reset",
-            "rb_get_state", "rb_step", "rb_step_taps", "rb_multi_create", "rb_multi_destroy", "rb_multi_bind",
+            "rb_get_state", "rb_step", "rb_step_taps", "rb_step_noalloc", "rb_multi_create", "rb_multi_destroy", "rb_multi_bind",
             "rb_multi_set_schedule", "rb_multi_set_items", "rb_multi_set_occupancy", "rb_multi_step", "rb_multi_graph_capture", "rb_multi_graph_launch"]
 ORDER_BATCH, ORDER_HEAVY_FIRST, ORDER_INTERLEAVE = 0, 1, 2
+NOALLOC_MAX_FLOATS = 4 << 20   # RB_NOALLOC_MAX_FLOATS
 
 
 class RbError(RuntimeError):
@@ -103,6 +104,7 @@ def lib():
         L.rb_get_state.argtypes = [vp, C.c_int32, vp, vp, vp]
         L.rb_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp]
         L.rb_step_taps.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rb_step_noalloc.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.POINTER(_Contacts), vp, vp]
         L.rb_multi_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
         L.rb_multi_destroy.argtypes = [vp]
         L.rb_multi_bind.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.POINTER(_Contacts), vp]
@@ -211,6 +213,25 @@ class Model:
         self.npair, self.maxcon, self.max_depth, self.lds_bytes = info.npair, info.maxcon, info.max_depth, info.lds_bytes
         self.meaninertia = info.meaninertia
         self.bytes_per_world = info.bytes_per_world
+
+    @property
+    def contact_capacity(self) -> int:
+        """Contact slots per world of a batch created with the default capacity."""
+        return max(1, min(self.maxcon, 64))
+
+    def step_noalloc(self, ctrl, qpos, qvel, friction=None, mass_scale=None, contacts=None, status=None,
+                     stream=None) -> None:
+        """rb_step_noalloc: one env step of worlds [0, n) without any device allocation, as a
+        freshly reset batch would step them (the warm start does not carry between calls)."""
+        import torch
+        n = qpos.shape[0]
+        pc = _ptr(ctrl, torch.float32, (n, self.nu), "ctrl") if self.nu else None
+        cs = C.byref(contacts._struct(n, self.contact_capacity)) if contacts is not None else None
+        _check(lib().rb_step_noalloc(self._h, int(n), pc, _ptr(qpos, torch.float32, (n, self.nq), "qpos"),
+                                     _ptr(qvel, torch.float32, (n, self.nv), "qvel"),
+                                     _ptr(friction, torch.float32, (n,), "friction"),
+                                     _ptr(mass_scale, torch.float32, (n, self.nbody), "mass_scale"), cs,
+                                     _ptr(status, torch.int32, (n,), "status"), _stream(stream)))
 
     def close(self):
         if getattr(self, "_h", None):
