@@ -73,6 +73,13 @@ def build_if_missing() -> None:
         _build.build()
 
 
+class _Fields(C.Structure):
+    _fields_ = [("geom_size", _f64p), ("body_pos", _f64p), ("act_kp", _f64p), ("act_kd", _f64p)]
+
+
+FIELDS = ("geom_size", "body_pos", "act_kp", "act_kd")
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -88,6 +95,9 @@ def lib():
                                C.POINTER(C.c_uint32), C.POINTER(_Contacts), C.c_int32]
         L.rbo_step_work.argtypes = [C.c_void_p, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
                                     C.POINTER(C.c_uint32), C.POINTER(_Contacts), _i32p, _f64p, C.c_int32]
+        L.rbo_step_fields.argtypes = [C.c_void_p, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
+                                      C.POINTER(_Fields), C.POINTER(C.c_uint32), C.POINTER(_Contacts), _i32p, _f64p,
+                                      C.c_int32]
         L.rbo_line_search.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p,
                                       _f64p, _f64p]
         L.rbo_energy.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p]
@@ -212,9 +222,11 @@ class Oracle:
         return out
 
     def step(self, ctrl, qpos, qvel, qacc_ws, friction=None, mass_scale=None, status=None, contacts=False,
-             nthreads=0, work=None):
+             nthreads=0, work=None, fields=None):
         """One env step (K substeps) for n worlds, in place on float64 arrays; returns (status, contacts).
 
+        fields: an optional dict of per-world model fields (``geom_size`` [n, ngeom, 3], ``body_pos``
+        [n, nbody, 3], ``act_kp`` / ``act_kd`` [n, nu]); world w steps as the model with its values.
         work: an optional dict that receives ``sub`` [n, K, SUBCOLS] int32 (per substep: contacts,
         rows, Newton updates, active rows at the solution, line-search segments, active-set
         fingerprints of the first FPITER updates) and ``ops`` [n, 2, NSTAGE] float64 (operation
@@ -228,6 +240,7 @@ class Oracle:
         st = np.zeros(n, np.uint32) if status is None else status
         cs = None
         out = None
+        keep = []
         if contacts:
             mc = max(1, self.maxcon)
             out = dict(ncon=np.zeros(n, np.int32), geom=np.zeros((n, mc, 2), np.int32),
@@ -236,18 +249,34 @@ class Oracle:
             cs = _Contacts()
             for k, v in out.items():
                 setattr(cs, k, v.ctypes.data_as(_i32p if v.dtype == np.int32 else _f64p))
-        if work is None:
+        fs = None
+        if fields:
+            shapes = dict(geom_size=(n, self.ngeom, 3), body_pos=(n, self.nbody, 3), act_kp=(n, self.nu),
+                          act_kd=(n, self.nu))
+            fs = _Fields()
+            for k, a in fields.items():
+                if k not in FIELDS:
+                    raise KeyError(k)
+                arr = _d(a, shapes[k])
+                keep.append(arr)
+                setattr(fs, k, _f(arr))
+        if work is None and fs is None:
             _check(lib().rbo_step(self._h, n, _f(u), _f(qpos), _f(qvel), _f(qacc_ws), _f(fr), _f(ms),
                                   st.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(cs) if cs is not None else None,
                                   int(nthreads)))
+        elif work is None:
+            _check(lib().rbo_step_fields(self._h, n, _f(u), _f(qpos), _f(qvel), _f(qacc_ws), _f(fr), _f(ms),
+                                         C.byref(fs), st.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                         C.byref(cs) if cs is not None else None, None, None, int(nthreads)))
         else:
             K = self.model["opt"]["nsubsteps"]
             sub = np.zeros((n, K, SUBCOLS), np.int32)
             ops = np.zeros((n, 2, NSTAGE), np.float64)
-            _check(lib().rbo_step_work(self._h, n, _f(u), _f(qpos), _f(qvel), _f(qacc_ws), _f(fr), _f(ms),
-                                       st.ctypes.data_as(C.POINTER(C.c_uint32)),
-                                       C.byref(cs) if cs is not None else None, sub.ctypes.data_as(_i32p),
-                                       ops.ctypes.data_as(_f64p), int(nthreads)))
+            _check(lib().rbo_step_fields(self._h, n, _f(u), _f(qpos), _f(qvel), _f(qacc_ws), _f(fr), _f(ms),
+                                         C.byref(fs) if fs is not None else None,
+                                         st.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                         C.byref(cs) if cs is not None else None, sub.ctypes.data_as(_i32p),
+                                         ops.ctypes.data_as(_f64p), int(nthreads)))
             work["sub"] = sub
             work["ops"] = ops
         return st, out

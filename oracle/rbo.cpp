@@ -1407,20 +1407,45 @@ int rbo_step(const void* mp, int32_t n, const double* ctrl, double* qpos, double
 int rbo_step_work(const void* mp, int32_t n, const double* ctrl, double* qpos, double* qvel, double* qacc_ws,
                   const double* friction, const double* mass_scale, uint32_t* status, rbo_contacts* out, int32_t* sub,
                   double* ops, int32_t nthreads) {
+    return rbo_step_fields(mp, n, ctrl, qpos, qvel, qacc_ws, friction, mass_scale, nullptr, status, out, sub, ops,
+                           nthreads);
+}
+
+int rbo_step_fields(const void* mp, int32_t n, const double* ctrl, double* qpos, double* qvel, double* qacc_ws,
+                    const double* friction, const double* mass_scale, const rbo_fields* fields, uint32_t* status,
+                    rbo_contacts* out, int32_t* sub, double* ops, int32_t nthreads) {
     if (!mp || n < 0 || !qpos || !qvel || !qacc_ws || !status) return fail("null argument");
-    const Model& m = *static_cast<const Model*>(mp);
-    if (m.nu && !ctrl) return fail("ctrl required");
+    const Model& m0 = *static_cast<const Model*>(mp);
+    if (m0.nu && !ctrl) return fail("ctrl required");
+    const bool expanded = fields && (fields->geom_size || fields->body_pos || fields->act_kp || fields->act_kd);
 #ifdef _OPENMP
     int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #pragma omp parallel num_threads(nt)
 #endif
     {
+        // a world with expanded fields runs a copy of the model with those fields replaced by its
+        // own values (the paper's per-world model fields: section "Architecture", paragraph on the
+        // GPU physics backend, and section "Manager-Based API", paragraph "Event manager")
+        Model mw = expanded ? m0 : Model();
+        const Model& m = expanded ? mw : m0;
         Data d(&m);
         std::vector<double> q1(m.nq), v1(m.nv);
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 4)
 #endif
         for (int w = 0; w < n; w++) {
+            if (expanded) {
+                if (fields->geom_size)
+                    std::copy(fields->geom_size + (size_t)w * 3 * m0.ngeom, fields->geom_size + (size_t)(w + 1) * 3 * m0.ngeom,
+                              mw.gsize.begin());
+                if (fields->body_pos)
+                    std::copy(fields->body_pos + (size_t)w * 3 * m0.nbody, fields->body_pos + (size_t)(w + 1) * 3 * m0.nbody,
+                              mw.bpos.begin());
+                if (fields->act_kp)
+                    std::copy(fields->act_kp + (size_t)w * m0.nu, fields->act_kp + (size_t)(w + 1) * m0.nu, mw.akp.begin());
+                if (fields->act_kd)
+                    std::copy(fields->act_kd + (size_t)w * m0.nu, fields->act_kd + (size_t)(w + 1) * m0.nu, mw.akd.begin());
+            }
             double* q = qpos + (size_t)w * m.nq;
             double* v = qvel + (size_t)w * m.nv;
             double* aws = qacc_ws + (size_t)w * m.nv;

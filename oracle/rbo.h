@@ -144,6 +144,19 @@ int rbo_step_work(const void* m, int32_t n, const double* ctrl, double* qpos, do
                   double* qacc_ws, const double* friction, const double* mass_scale, uint32_t* status,
                   rbo_contacts* contacts, int32_t* sub, double* ops, int32_t nthreads);
 
+/* Per-world values of model fields (any pointer may be NULL: every world uses the model's own
+ * values): geom_size [n, ngeom, 3], body_pos [n, nbody, 3] (position in the parent's frame),
+ * act_kp [n, nu] and act_kd [n, nu] (position-actuator gains).  World w steps exactly as a
+ * model whose description carries world w's values would. */
+typedef struct rbo_fields {
+    const double *geom_size, *body_pos, *act_kp, *act_kd;
+} rbo_fields;
+
+/* rbo_step_work with per-world model fields (fields may be NULL). */
+int rbo_step_fields(const void* m, int32_t n, const double* ctrl, double* qpos, double* qvel, double* qacc_ws,
+                    const double* friction, const double* mass_scale, const rbo_fields* fields, uint32_t* status,
+                    rbo_contacts* contacts, int32_t* sub, double* ops, int32_t nthreads);
+
 /* The constraint cost f(a) of one substep's state (rows built as in rbo_forward) and the exact
  * line search of the Newton method from acceleration a along direction p:
  * alpha = argmin over alpha >= 0 of f(a + alpha p) (cost_out, alpha_out nullable). */
