@@ -49,7 +49,14 @@ extern "C" {
 enum { RB_GEOM_PLANE = 0, RB_GEOM_SPHERE = 1, RB_GEOM_CAPSULE = 2, RB_GEOM_BOX = 3 };
 enum { RB_JNT_FREE = 0, RB_JNT_HINGE = 1 };
 enum { RB_ACT_POSITION = 0, RB_ACT_MOTOR = 1 };
-enum { RB_PARAM_FRICTION = 0, RB_PARAM_MASS_SCALE = 1 };
+enum {
+    RB_PARAM_FRICTION = 0,   /* [n]: friction of every contact of the world (model flag) */
+    RB_PARAM_MASS_SCALE = 1, /* [n, nbody]: body mass and rotational inertia scale (model flag) */
+    RB_PARAM_GEOM_SIZE = 2,  /* [n, ngeom, 3]: geom sizes (any model; expanded on first use) */
+    RB_PARAM_BODY_POS = 3,   /* [n, nbody, 3]: body position in its parent's frame (ditto) */
+    RB_PARAM_ACT_KP = 4,     /* [n, nu]: position-actuator stiffness kp (ditto) */
+    RB_PARAM_ACT_KD = 5      /* [n, nu]: position-actuator damping kd (ditto) */
+};
 
 /* Host-side model description, float64, owned by the caller (copied by rb_model_create).
  * Bodies [nbody] (body 0 = world), joints [njnt] (listed in body order, at most one per
@@ -181,8 +188,17 @@ int32_t rb_batch_contact_capacity(const rb_batch* batch);
 /* Per-world parameters for slots [0, n): RB_PARAM_FRICTION takes [n] floats (friction of
  * every contact in the world; the model must have friction_per_world), RB_PARAM_MASS_SCALE
  * [n, nbody] floats (scales each body's mass and rotational inertia; the model must have
- * mass_scale_per_world).  Device pointer; copied on the stream.  RB_EINVAL for another field,
- * a model without that per-world field, or n outside [0, capacity].  Cites: paper, section
+ * mass_scale_per_world).  RB_PARAM_GEOM_SIZE [n, ngeom, 3], RB_PARAM_BODY_POS [n, nbody, 3],
+ * RB_PARAM_ACT_KP and RB_PARAM_ACT_KD [n, nu] expand that model field to one value per world
+ * slot on first use: the batch allocates a [capacity, ...] array (synchronously) holding the
+ * model's values in every slot, then takes the given slots' values; every world then runs with
+ * its own values (a world steps as a model whose description carried them; inertias, static
+ * contact bounds and the tolerance scale stay the model's).  Fused plans that bound the batch
+ * pick the new arrays up at their next step or graph replay (their argument blocks are
+ * rewritten; a captured graph needs no new capture).  Values are not validated.  Device
+ * pointer; copied on the stream.  RB_EINVAL for another field, a model without that per-world
+ * field (friction, mass scale) or without actuators (gains), or n outside [0, capacity];
+ * RB_ENOMEM when the expansion cannot allocate.  Cites: paper, section
  * "Architecture", paragraph on the GPU physics backend (model fields expanded to vary per
  * world), and section "Manager-Based API", paragraph "Event manager" (domain randomisation
  * writing per-world values). */

@@ -23,6 +23,7 @@
 struct DevModel {
     // sizes
     int nbody, nv, nq, nu, njnt, npair, ncap, maxd;
+    int ngeom;
     int nbb;       // box-box pairs (each has an LDS block)
     int nblevel;   // body levels 1..nblevel (level 0 = world)
     int ndlevel;   // dof depth levels 1..ndlevel
@@ -120,6 +121,11 @@ struct DevWorlds {
     uint32_t* status;       // [cap]
     float* friction;        // [cap]
     float* mass_scale;      // [cap, nbody]
+    // model fields expanded to one value per world (null: every world uses the model's)
+    float* geom_size;       // [cap, ngeom, 3]
+    float* body_pos;        // [cap, nbody, 3]
+    float* act_kp;          // [cap, nu]
+    float* act_kd;          // [cap, nu]
 };
 
 struct DevContactsOut {

@@ -23,6 +23,7 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
 hipError_t rb_launch_reset(int nv, const int32_t* ids, int n, const float* qacc_ws, DevWorlds W, int capacity,
                            hipStream_t stream);
 hipError_t rb_launch_fill(float* dst, float value, size_t count, hipStream_t stream);
+hipError_t rb_launch_tile(float* dst, const float* src, size_t k, size_t copies, hipStream_t stream);
 size_t rb_step_args_size();
 void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
                        const DevContactsOut* co, uint32_t* status_out);
@@ -120,6 +121,8 @@ struct rb_batch {
     DevWorlds W{};
     DevModel dm;   // model copy with this batch's contact capacity
     void* mem = nullptr;
+    void* field_mem[4] = {};   // model fields expanded per world (geom size, body pos, kp, kd)
+    int version = 0;           // bumped when W changes (an expansion): plans re-bind
 };
 
 namespace {
@@ -579,7 +582,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.body_chainmask = (const uint64_t*)(base + 4 * off_mask);
     m.dof_descmask = (const uint64_t*)(base + 4 * off_dmask);
     // sizes and options
-    m.nbody = nb; m.nv = nv; m.nq = nq; m.nu = nu; m.njnt = nj; m.npair = npair; m.nbb = nbb;
+    m.nbody = nb; m.nv = nv; m.nq = nq; m.nu = nu; m.njnt = nj; m.npair = npair; m.nbb = nbb; m.ngeom = ng;
     m.maxd = tmaxd; m.nblevel = nblevel; m.ndlevel = maxd; m.nhlevel = nhlevel; m.maxpiv = maxpiv; m.K = d->nsubsteps; m.maxiter = d->iterations;
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.nlim = nlim;
@@ -736,16 +739,54 @@ void rb_batch_destroy(rb_batch* b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
     if (b->mem) (void)hipFree(b->mem);
+    for (void* f : b->field_mem)
+        if (f) (void)hipFree(f);
     delete b;
 }
 
 int32_t rb_batch_contact_capacity(const rb_batch* b) { return b ? b->dm.ncap : 0; }
 
+// Expand a model field to one value per world slot: a [capacity, k] array initialised with the
+// model's values in every slot.  Returns the array (already expanded: the same one).
+static int expand_field(rb_batch* b, int field, float** out) {
+    const DevModel& m = b->dm;
+    const int idx = field - RB_PARAM_GEOM_SIZE;
+    float** slot = idx == 0 ? &b->W.geom_size : idx == 1 ? &b->W.body_pos : idx == 2 ? &b->W.act_kp : &b->W.act_kd;
+    const float* src = idx == 0 ? m.geom_size : idx == 1 ? m.body_pos : idx == 2 ? m.act_kp : m.act_kd;
+    const size_t k = idx == 0 ? 3 * (size_t)m.ngeom : idx == 1 ? 3 * (size_t)m.nbody : (size_t)m.nu;
+    if (!*slot) {
+        if (k == 0) return fail(RB_EINVAL, "the model has no values of this field");
+        void* mem = nullptr;
+        hipError_t e = hipMalloc(&mem, k * b->capacity * sizeof(float));
+        if (e != hipSuccess) return fail(RB_ENOMEM, std::string("hipMalloc(field): ") + hipGetErrorString(e));
+        e = rb_launch_tile(static_cast<float*>(mem), src, k, (size_t)b->capacity, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipFree(mem);
+            return hip_fail(e, "expanding a model field");
+        }
+        b->field_mem[idx] = mem;
+        *slot = static_cast<float*>(mem);
+        b->version++;
+    }
+    *out = *slot;
+    return RB_OK;
+}
+
 int rb_batch_set_params_at(rb_batch* b, int32_t field, int32_t first, int32_t n, const float* vals, void* stream) {
     if (!b || n < 0 || first < 0 || first > b->capacity || n > b->capacity - first || (n > 0 && !vals))
         return fail(RB_EINVAL, "bad arguments to rb_batch_set_params");
     hipError_t e = hipSuccess;
-    if (field == RB_PARAM_FRICTION) {
+    if (field >= RB_PARAM_GEOM_SIZE && field <= RB_PARAM_ACT_KD) {
+        float* dst = nullptr;
+        int rc = expand_field(b, field, &dst);
+        if (rc != RB_OK) return rc;
+        const DevModel& m = b->dm;
+        const size_t k = field == RB_PARAM_GEOM_SIZE ? 3 * (size_t)m.ngeom
+                         : field == RB_PARAM_BODY_POS ? 3 * (size_t)m.nbody : (size_t)m.nu;
+        if (n) e = hipMemcpyAsync(dst + (size_t)first * k, vals, (size_t)n * k * 4, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream);
+    } else if (field == RB_PARAM_FRICTION) {
         if (!b->dm.fr_pw) return fail(RB_EINVAL, "model does not have per-world friction");
         if (n) e = hipMemcpyAsync(b->W.friction + first, vals, (size_t)n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream);
     } else if (field == RB_PARAM_MASS_SCALE) {
@@ -862,7 +903,7 @@ int rb_step_noalloc(const rb_model* model, int32_t n, const float* ctrl, float* 
     hipStream_t s = (hipStream_t)stream;
     // every call starts as a freshly reset batch: zero warm start and status, per-world
     // friction and mass scale 1 unless the caller passes them
-    DevWorlds W;
+    DevWorlds W{};
     W.qacc_ws = base;
     W.status = reinterpret_cast<uint32_t*>(base + (size_t)n * nv);
     float* fr = base + (size_t)n * (nv + 1);
@@ -887,9 +928,20 @@ int rb_step_noalloc(const rb_model* model, int32_t n, const float* ctrl, float* 
 // ---------------------------------------------------------------------------------------
 // mixed-model batching
 // ---------------------------------------------------------------------------------------
+struct BindRec {
+    int n = -1;
+    const float* ctrl = nullptr;
+    float *qpos = nullptr, *qvel = nullptr;
+    DevContactsOut co{};
+    bool has_co = false;
+    uint32_t* status = nullptr;
+    int version = 0;          // the batch's version the argument block was written from
+};
+
 struct rb_multi {
     std::vector<rb_batch*> batches;
     std::vector<int> bound_n;
+    std::vector<BindRec> bind;
     std::vector<char> args_host;   // nbatch step-argument blocks
     DevModel* d_models = nullptr;
     void* d_args = nullptr;
@@ -935,6 +987,7 @@ int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out) {
     // every batch runs in its own model's instantiation, with its own LDS layout
     for (int i = 0; i < nbatch; i++) p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);
     p->bound_n.assign(nbatch, -1);
+    p->bind.assign(nbatch, BindRec{});
     p->args_host.assign(rb_step_args_size() * nbatch, 0);
     hipError_t e = hipMalloc((void**)&p->d_models, sizeof(DevModel) * nbatch);
     if (e == hipSuccess) e = hipMalloc(&p->d_args, rb_step_args_size() * nbatch);
@@ -980,7 +1033,31 @@ int rb_multi_bind(rb_multi* p, int32_t i, int32_t n, const float* ctrl, float* q
     hipError_t e = hipMemcpy((char*)p->d_args + sz * i, p->args_host.data() + sz * i, sz, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "rb_multi_bind");
     p->bound_n[i] = n;
+    BindRec& r = p->bind[i];
+    r.n = n; r.ctrl = ctrl; r.qpos = qpos; r.qvel = qvel; r.co = co; r.has_co = c != nullptr; r.status = status;
+    r.version = b->version;
     multi_free_graph(p);
+    return RB_OK;
+}
+
+// A batch that expanded a model field since it was bound has new per-world arrays: rewrite its
+// argument block (on the stream, before the launch that reads it).  The blocks live in device
+// memory and launches (captured graphs included) read them at run time, so a captured graph
+// picks up the new arrays without being captured again.
+static int multi_refresh(rb_multi* p, hipStream_t stream) {
+    const size_t sz = rb_step_args_size();
+    for (size_t i = 0; i < p->batches.size(); i++) {
+        BindRec& r = p->bind[i];
+        rb_batch* b = p->batches[i];
+        if (r.n < 0 || r.version == b->version) continue;
+        rb_fill_step_args(p->args_host.data() + sz * i, r.n, r.ctrl, r.qpos, r.qvel, b->W, r.has_co ? &r.co : nullptr,
+                          r.status);
+        hipError_t e = hipMemcpyAsync((char*)p->d_args + sz * i, p->args_host.data() + sz * i, sz,
+                                      hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);   // the host block is rewritten on the next refresh
+        if (e != hipSuccess) return hip_fail(e, "re-binding a batch with expanded fields");
+        r.version = b->version;
+    }
     return RB_OK;
 }
 
@@ -1150,6 +1227,8 @@ int rb_multi_step(rb_multi* p, void* stream) {
     if (!p) return fail(RB_EINVAL, "null plan");
     if (!p->scheduled) return fail(RB_ESTATE, "no schedule: set one (rb_multi_set_schedule or rb_multi_set_items) after binding");
     if (p->nitems == 0) return RB_OK;
+    int rc = multi_refresh(p, (hipStream_t)stream);
+    if (rc != RB_OK) return rc;
     hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid, multi_waves(p),
                                    (hipStream_t)stream);
     return e == hipSuccess ? RB_OK : hip_fail(e, "rb_multi_step");
@@ -1183,6 +1262,8 @@ int rb_multi_graph_capture(rb_multi* p, int32_t nsteps, void* stream) {
 int rb_multi_graph_launch(rb_multi* p, void* stream) {
     if (!p) return fail(RB_EINVAL, "null plan");
     if (!p->exec) return fail(RB_ESTATE, "nothing captured");
+    int rc = multi_refresh(p, (hipStream_t)stream);
+    if (rc != RB_OK) return rc;
     hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
     return e == hipSuccess ? RB_OK : hip_fail(e, "hipGraphLaunch");
 }

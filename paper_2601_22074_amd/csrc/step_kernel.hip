@@ -487,14 +487,15 @@ DEV int pair_ncand(int type) {
 // depth, lowest axis on ties, + side at 0); distance |c - closest| - r outside, -(depth + r)
 // inside; normal from the sphere towards the box.
 template <bool EXT>
-DEV void pair_candidate(const DevModel& m, const float* L, int p, int k, float* dist, float* pos, float* nrm) {
+DEV void pair_candidate(const DevModel& m, const float* L, const float* gsize, int p, int k, float* dist, float* pos,
+                        float* nrm) {
     float xp[3], Rp[9], x[3], R[9];
     geom_pose(m, L, m.pair_g1[p], xp, Rp);
     geom_pose(m, L, m.pair_g2[p], x, R);
-    const float* sz = m.geom_size + 3 * m.pair_g2[p];
+    const float* sz = gsize + 3 * m.pair_g2[p];
     const int type = m.pair_type[p];
     if (EXT && type == RB_PAIR_SPHEREBOX) {
-        const float rad = m.geom_size[3 * m.pair_g1[p]];
+        const float rad = gsize[3 * m.pair_g1[p]];
         const float rel[3] = {xp[0] - x[0], xp[1] - x[1], xp[2] - x[2]};
         float pl[3], ql[3];
         bool inside = true;
@@ -554,13 +555,13 @@ DEV void pair_candidate(const DevModel& m, const float* L, int p, int k, float* 
 // contact lanes then pick their candidate from these bits, so membership never depends on
 // re-evaluating a distance that sits on the margin.
 template <bool EXT>
-DEV uint32_t pair_mask(const DevModel& m, const float* L, int p) {
+DEV uint32_t pair_mask(const DevModel& m, const float* L, const float* gsize, int p) {
     const int nc = pair_ncand(m.pair_type[p]);
     const float margin = m.pair_margin[p];
     uint32_t mask = 0;
     for (int k = 0; k < nc; k++) {
         float d, pos[3], nrm[3];
-        pair_candidate<EXT>(m, L, p, k, &d, pos, nrm);
+        pair_candidate<EXT>(m, L, gsize, p, k, &d, pos, nrm);
         if (d < margin) mask |= 1u << k;
     }
     return mask;
@@ -584,13 +585,13 @@ DEV void pick_axis(const float (&a)[3][3], int i, float* o) {
 // contact, placed halfway between the point and the face, numbered by its position in the
 // clipped polygon.  An edge axis gives one contact halfway between the closest points of
 // the two supporting edges, at depth minus the overlap.  Returns the number of contacts.
-DEV int box_box(const DevModel& m, const float* L, int p, float* S) {
+DEV int box_box(const DevModel& m, const float* L, const float* gsize, int p, float* S) {
     float cA[3], RA[9], cB[3], RB[9];
     const int g1 = m.pair_g1[p], g2 = m.pair_g2[p];
     geom_pose(m, L, g1, cA, RA);
     geom_pose(m, L, g2, cB, RB);
-    const float hA[3] = {m.geom_size[3 * g1], m.geom_size[3 * g1 + 1], m.geom_size[3 * g1 + 2]};
-    const float hB[3] = {m.geom_size[3 * g2], m.geom_size[3 * g2 + 1], m.geom_size[3 * g2 + 2]};
+    const float hA[3] = {gsize[3 * g1], gsize[3 * g1 + 1], gsize[3 * g1 + 2]};
+    const float hB[3] = {gsize[3 * g2], gsize[3 * g2 + 1], gsize[3 * g2 + 2]};
     const float margin = m.pair_margin[p];
     float aA[3][3], aB[3][3];
 #pragma unroll
@@ -879,10 +880,14 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             float t = 0.f;
             for (int c = m.act_start[i]; c < m.act_start[i + 1]; c++) {
                 int u = m.act_list[c];
-                if (m.act_type[u] == RB_ACT_POSITION)
-                    t += m.act_kp[u] * (ctrl[u] - q[m.act_qadr[u]]) - m.act_kd[u] * v[i];
-                else
+                if (m.act_type[u] == RB_ACT_POSITION) {
+                    // gains: the world's own where the fields are expanded per world
+                    const float kp = A.W.act_kp ? A.W.act_kp[(size_t)w * nu + u] : m.act_kp[u];
+                    const float kd = A.W.act_kd ? A.W.act_kd[(size_t)w * nu + u] : m.act_kd[u];
+                    t += kp * (ctrl[u] - q[m.act_qadr[u]]) - kd * v[i];
+                } else {
                     t += m.act_gear[u] * ctrl[u];
+                }
             }
             // passive joint damping (its implicit integration follows the solve)
             if (EXT && m.ndamp > 0) t -= m.dof_damping[i] * v[i];
@@ -910,7 +915,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 ql[0] = q[a + 3] * inv; ql[1] = q[a + 4] * inv; ql[2] = q[a + 5] * inv; ql[3] = q[a + 6] * inv;
             } else {
                 const float* qb = m.body_quat + 4 * b;
-                const float* pb = m.body_pos + 3 * b;
+                // position in the parent: the world's own where the field is expanded per world
+                const float* pb = A.W.body_pos ? A.W.body_pos + ((size_t)w * nb + b) * 3 : m.body_pos + 3 * b;
                 ql[0] = qb[0]; ql[1] = qb[1]; ql[2] = qb[2]; ql[3] = qb[3];
                 tl[0] = pb[0]; tl[1] = pb[1]; tl[2] = pb[2];
                 if (BK.jtype == RB_JNT_HINGE) {
@@ -1120,11 +1126,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         int cnt = 0;
         uint32_t cmask = 0;    // plane pairs: candidates below the margin
         float pos_[3];
+        // geom sizes: the world's own where the field is expanded per world
+        const float* gsize = A.W.geom_size ? A.W.geom_size + (size_t)w * 3 * m.ngeom : m.geom_size;
         if (lane < m.npair) {
             if (EXT && m.pair_type[lane] == RB_PAIR_BOXBOX) {
-                cnt = box_box(m, L, lane, L + m.o_bb + RB_BB_FLOATS * m.pair_slot[lane]);
+                cnt = box_box(m, L, gsize, lane, L + m.o_bb + RB_BB_FLOATS * m.pair_slot[lane]);
             } else {
-                cmask = pair_mask<EXT>(m, L, lane);
+                cmask = pair_mask<EXT>(m, L, gsize, lane);
                 cnt = __builtin_popcount(cmask);
             }
         }
@@ -1162,7 +1170,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 // the j-th set bit of the pair's candidate mask
                 for (int t = 0; t < j; t++) smask &= smask - 1u;
                 feat = __builtin_ctz(smask);
-                pair_candidate<EXT>(m, L, src, feat, &C.dist, pos_, C.n);
+                pair_candidate<EXT>(m, L, gsize, src, feat, &C.dist, pos_, C.n);
             }
             C.r[0] = pos_[0] - O[0]; C.r[1] = pos_[1] - O[1]; C.r[2] = pos_[2] - O[2];
             contact_frame(C.n, C.t1);

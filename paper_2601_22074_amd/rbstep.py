@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "librbstep.so")
 
 RB_OK, RB_EINVAL, RB_ENOMEM, RB_EHIP, RB_EBUDGET, RB_ESTATE = 0, -1, -2, -3, -4, -5
 STATUS_NONFINITE, STATUS_ITERCAP, STATUS_CONOVERFLOW = 1, 2, 4
-PARAM_FRICTION, PARAM_MASS_SCALE = 0, 1
+PARAM_FRICTION, PARAM_MASS_SCALE, PARAM_GEOM_SIZE, PARAM_BODY_POS, PARAM_ACT_KP, PARAM_ACT_KD = 0, 1, 2, 3, 4, 5
 NSTAGE = 10             # timed stages in the stats tap
 STATS_SUB = 4           # substeps with a per-substep record in the stats tap
 STATS_FP = 4            # Newton updates with an active-set fingerprint per substep
@@ -299,17 +299,21 @@ class Batch:
     def set_params(self, field: int, vals, stream=None) -> None:
         import torch
         n = vals.shape[0]
-        shape = (n,) if field == PARAM_FRICTION else (n, self.model.nbody)
-        _check(lib().rb_batch_set_params(self._h, int(field), int(n), _ptr(vals, torch.float32, shape, "vals"),
-                                         _stream(stream)))
+        _check(lib().rb_batch_set_params(self._h, int(field), int(n),
+                                         _ptr(vals, torch.float32, self._param_shape(field, n), "vals"), _stream(stream)))
 
     def set_params_at(self, field: int, first: int, vals, stream=None) -> None:
         """Per-world parameters of slots [first, first + n), n = vals.shape[0]."""
         import torch
         n = vals.shape[0]
-        shape = (n,) if field == PARAM_FRICTION else (n, self.model.nbody)
         _check(lib().rb_batch_set_params_at(self._h, int(field), int(first), int(n),
-                                            _ptr(vals, torch.float32, shape, "vals"), _stream(stream)))
+                                            _ptr(vals, torch.float32, self._param_shape(field, n), "vals"),
+                                            _stream(stream)))
+
+    def _param_shape(self, field: int, n: int):
+        M = self.model
+        return {PARAM_FRICTION: (n,), PARAM_MASS_SCALE: (n, M.nbody), PARAM_GEOM_SIZE: (n, M.ngeom, 3),
+                PARAM_BODY_POS: (n, M.nbody, 3), PARAM_ACT_KP: (n, M.nu), PARAM_ACT_KD: (n, M.nu)}.get(field, (n,))
 
     def set_waves(self, waves: int) -> None:
         """Resident waves per SIMD of plain launches: 3, 4, or 0 (automatic)."""
