@@ -423,6 +423,7 @@ int pair_capacity(int t1, int t2) {
     if (t1 == RBO_GEOM_PLANE && t2 == RBO_GEOM_BOX) return 8;
     if (t1 == RBO_GEOM_BOX && t2 == RBO_GEOM_BOX) return 8;
     if (t1 == RBO_GEOM_SPHERE && t2 == RBO_GEOM_BOX) return 1;
+    if (t1 == RBO_GEOM_CAPSULE && t2 == RBO_GEOM_BOX) return 2;
     return -1;
 }
 
@@ -610,14 +611,12 @@ void box_box(const Model& m, Data& d, int g1, int g2, double margin) {
     }
 }
 
-// Sphere g1 against box g2: the closest point of the box to the sphere's centre c (the centre
+// A sphere (centre c, radius r) of geom g1 against box g2: the closest point of the box to c (the centre
 // clamped to the box in the box frame); when c lies inside the box, the nearest face instead
 // (least depth h_i - |p_i|, lowest axis on ties, towards the side of p_i, + at 0).  Signed
 // distance = |c - closest| - r outside, -(depth + r) inside; normal from the sphere towards
 // the box; the contact point lies halfway between the sphere's surface and the box's.
-void sphere_box(const Model& m, Data& d, int g1, int g2, double margin) {
-    const double* c = &d.gx[3 * g1];
-    const double r = m.gsize[3 * g1];
+void sphere_at_box(const Model& m, Data& d, int g1, int g2, int feature, const double* c, double r, double margin) {
     const double* x = &d.gx[3 * g2];
     const double* R = &d.gR[9 * g2];
     const double* h = &m.gsize[3 * g2];
@@ -647,7 +646,26 @@ void sphere_box(const Model& m, Data& d, int g1, int g2, double margin) {
     matvec3(R, nl, nw);
     double n[3] = {-nw[0], -nw[1], -nw[2]}, pos[3];
     for (int i = 0; i < 3; i++) pos[i] = c[i] - nw[i] * (r + dist / 2);
-    add_contact(m, d, g1, g2, 0, dist, pos, n);
+    add_contact(m, d, g1, g2, feature, dist, pos, n);
+}
+
+void sphere_box(const Model& m, Data& d, int g1, int g2, double margin) {
+    sphere_at_box(m, d, g1, g2, 0, &d.gx[3 * g1], m.gsize[3 * g1], margin);
+}
+
+// Capsule g1 against box g2, as against a plane: the spheres of radius r at the capsule's two
+// segment ends (feature 0 at -z, 1 at +z of the capsule frame), each against the box by the
+// sphere rule above.
+void capsule_box(const Model& m, Data& d, int g1, int g2, double margin) {
+    const double* x = &d.gx[3 * g1];
+    const double* R = &d.gR[9 * g1];
+    const double r = m.gsize[3 * g1], h = m.gsize[3 * g1 + 1];
+    for (int f = 0; f < 2; f++) {
+        const double sgn = f == 0 ? -1.0 : 1.0;
+        double e[3];
+        for (int i = 0; i < 3; i++) e[i] = x[i] + sgn * h * R[3 * i + 2];
+        sphere_at_box(m, d, g1, g2, f, e, r, margin);
+    }
 }
 
 void collide(const Model& m, Data& d) {
@@ -665,6 +683,10 @@ void collide(const Model& m, Data& d) {
             }
             if (t1 == RBO_GEOM_SPHERE && t2 == RBO_GEOM_BOX) {
                 sphere_box(m, d, g1, g2, margin);
+                continue;
+            }
+            if (t1 == RBO_GEOM_CAPSULE && t2 == RBO_GEOM_BOX) {
+                capsule_box(m, d, g1, g2, margin);
                 continue;
             }
             if (t1 != RBO_GEOM_PLANE) continue;  // other pairs were rejected at creation
@@ -976,6 +998,7 @@ double collision_ops(const Model& m, const Data& d) {
             int t1 = std::min(m.gtype[a], m.gtype[b]), t2 = std::max(m.gtype[a], m.gtype[b]);
             if (t1 == RBO_GEOM_PLANE) f += t2 == RBO_GEOM_SPHERE ? 20 : (t2 == RBO_GEOM_CAPSULE ? 60 : 8 * 25);
             else if (t1 == RBO_GEOM_SPHERE) f += 80;
+            else if (t1 == RBO_GEOM_CAPSULE) f += 2 * 80 + 12;
             else f += 15 * 40 + 300;
         }
     return f + 25.0 * d.con.size();

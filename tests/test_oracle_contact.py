@@ -673,3 +673,91 @@ def test_invalid_condim_rejected(oracle_mod):
     m, q, R = _incline_box(0.3, 2)
     with pytest.raises(Exception):
         oracle_mod.Oracle(m)
+
+
+# ---------------------------------------------------------------- capsule against box
+def _box_capsule(pos, quat=(1.0, 0, 0, 0), r=0.04, half_len=0.15, margin=0.0, box_quat=(1.0, 0, 0, 0)):
+    """A static box (half sizes 0.3, 0.2, 0.1, top at z = 0.2) and a free capsule (radius r,
+    segment half-length half_len along its z) at pos / quat."""
+    mb = robots.ModelBuilder("box_capsule", timestep=0.002, nsubsteps=1)
+    mb.geom(0, "box", [0.3, 0.2, 0.1], pos=(0.0, 0.0, 0.1), quat=box_quat, contype=0, conaffinity=1)
+    b = mb.body("capsule", 0, (0, 0, 1), 0.8, robots.capsule_inertia(0.8, r, 2 * half_len))
+    mb.joint(b, "free")
+    mb.geom(b, "capsule", [r, half_len], contype=1, conaffinity=0, margin=margin)
+    return mb.build(), np.concatenate([pos, quat])
+
+
+def test_capsule_lying_on_box_face(oracle_mod):
+    """A capsule lying along x, 1e-4 into the top face: two contacts (its ends, features 0 and
+    1), each normal from the capsule down into the box, points halfway between the surfaces."""
+    dz, r, hl = 1e-4, 0.04, 0.15
+    quat = robots.quat_axis_angle([0, 1, 0], np.pi / 2)      # capsule z along world x
+    m, q = _box_capsule([0.05, 0.02, 0.2 + r - dz], quat, r, hl)
+    t = oracle_mod.Oracle(m).forward(q, np.zeros(6))
+    assert t["ncon"] == 2 and list(t["feature"]) == [0, 1]
+    ends = [np.array([0.05, 0.02, 0.2 + r - dz]) + s * hl * rot(quat)[:, 2] for s in (-1, 1)]
+    for i in range(2):
+        np.testing.assert_allclose(t["frame"][i, 0], [0, 0, -1.0], atol=1e-12)
+        assert abs(t["dist"][i] + dz) < 1e-12
+        np.testing.assert_allclose(t["pos"][i], ends[i] - [0, 0, r - dz / 2], atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_capsule_box_ends_brute_force(oracle_mod, seed):
+    """A capsule at a random pose near a rotated box: each end listed exactly when its sphere's
+    signed distance to the box (brute force over a dense sampling of the box surface) is within
+    the margin, with that distance and normal."""
+    rng = np.random.default_rng(100 + seed)
+    ax = rng.normal(size=3)
+    box_quat = robots.quat_axis_angle(ax / np.linalg.norm(ax), rng.uniform(0, np.pi))
+    half, box_pos, r, hl, margin = (0.3, 0.2, 0.1), np.array([0.0, 0.0, 0.1]), 0.04, 0.15, 0.05
+    cq = rng.normal(size=4)
+    cq /= np.linalg.norm(cq)
+    P = _box_surface_points(box_pos, box_quat, half)
+    Rb = rot(box_quat)
+    while True:
+        d = rng.normal(size=3)
+        c = box_pos + d / np.linalg.norm(d) * rng.uniform(0.15, 0.5)
+        ends = [c + s * hl * rot(cq)[:, 2] for s in (-1, 1)]
+        sd = []
+        for e in ends:
+            dist = np.linalg.norm(P - e, axis=1)
+            k = np.argmin(dist)
+            inside = np.all(np.abs(Rb.T @ (e - box_pos)) <= np.asarray(half))
+            sd.append(((-1.0 if inside else 1.0) * dist[k] - r, P[k], inside, dist[k]))
+        if any(x[0] < margin - 0.01 for x in sd) and all(abs(x[0] - margin) > 0.01 for x in sd):
+            break
+    mb = robots.ModelBuilder("box_capsule", timestep=0.005, nsubsteps=1)
+    mb.geom(0, "box", list(half), pos=box_pos, quat=box_quat, contype=0, conaffinity=1)
+    b = mb.body("capsule", 0, (0, 0, 1), 0.8, robots.capsule_inertia(0.8, r, 2 * hl))
+    mb.joint(b, "free")
+    mb.geom(b, "capsule", [r, hl], contype=1, conaffinity=0, margin=margin)
+    t = oracle_mod.Oracle(mb.build()).forward(np.concatenate([c, cq]), np.zeros(6))
+    spacing = 2 * max(half) / 120
+    listed = [f for f in range(2) if sd[f][0] < margin]
+    assert list(t["feature"]) == listed
+    for i, f in enumerate(listed):
+        dist_bf, Pk, inside, dk = sd[f]
+        assert abs(t["dist"][i] - dist_bf) <= spacing
+        n_bf = (-1.0 if inside else 1.0) * (Pk - ends[f]) / dk
+        assert np.dot(t["frame"][i, 0], n_bf) > 1 - 5 * spacing / dk
+        np.testing.assert_allclose(t["pos"][i], ends[f] + t["frame"][i, 0] * (r + t["dist"][i] / 2), atol=1e-12)
+
+
+def test_capsule_rests_on_box(oracle_mod):
+    """Dropped flat onto the box, the capsule comes to rest on its two ends, whose normal forces
+    carry its weight (each half, by symmetry); their tangential forces cancel in total (as the
+    corners of a resting box's do, not each one: R31)."""
+    r, hl, mass = 0.04, 0.15, 0.8
+    quat = robots.quat_axis_angle([0, 1, 0], np.pi / 2)
+    m, q0 = _box_capsule([0.0, 0.0, 0.2 + r + 0.01], quat, r, hl)
+    o = oracle_mod.Oracle(m)
+    q = q0[None].copy(); v = np.zeros((1, 6)); ws = np.zeros((1, 6))
+    for _ in range(1500):
+        o.step(np.zeros((1, 0)), q, v, ws)
+    t = o.forward(q[0], v[0], None, ws[0])
+    assert t["ncon"] == 2
+    np.testing.assert_allclose(t["cforce"][:, 0], [mass * 9.81 / 2] * 2, rtol=1e-5)
+    np.testing.assert_allclose(t["frame"][0], t["frame"][1], atol=1e-9)
+    assert np.abs(t["cforce"][:, 1:].sum(0)).max() < 1e-6
+    assert np.abs(v).max() < 1e-6
