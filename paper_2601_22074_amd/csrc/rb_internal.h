@@ -8,7 +8,7 @@
 
 #define RB_WAVE 64
 #define RB_MAX_DOF 64
-#define RB_MAX_PAIR 64
+#define RB_MAX_PAIR 128          // pairs are lanes, in two rounds past 64 (extended code only)
 #define RB_MAX_CON 64
 #define RB_MAX_GEOM 256           // contact ids pack geom indices into 8-bit fields
 #define RB_NSTAGE 10              // timed kernel stages in the stats tap
@@ -18,6 +18,7 @@
 #define RB_NSTATS (4 + RB_NSTAGE + RB_STATS_SUB * RB_SUBSTAT)   // stats tap columns per world
 #define RB_PAIR_BOXBOX 16         // pair_type of a box-box pair (plane pairs hold g2's geom type)
 #define RB_PAIR_SPHEREBOX 17      // pair_type of a sphere (g1) - box (g2) pair
+#define RB_PAIR_CAPSULEBOX 18     // pair_type of a capsule (g1) - box (g2) pair: its two end spheres
 #define RB_BB_FLOATS 96           // LDS floats per box-box pair: clip buffers, contacts, normal
 
 struct DevModel {
@@ -92,10 +93,10 @@ struct DevModel {
     const int* jnt_qadr;
     const int* jnt_dadr;
     // collision pairs [npair], in (g1, g2) order; g1 is the plane, the sphere of a sphere-box
-    // pair, or the lower-numbered box
+    // pair, the capsule of a capsule-box pair, or the lower-numbered box
     const int* pair_g1;
     const int* pair_g2;
-    const int* pair_type;      // geom type of g2 (plane pairs), RB_PAIR_BOXBOX or RB_PAIR_SPHEREBOX
+    const int* pair_type;      // geom type of g2 (plane pairs), RB_PAIR_BOXBOX, RB_PAIR_SPHEREBOX or RB_PAIR_CAPSULEBOX
     const int* pair_slot;      // box-box pairs: index of the pair's LDS block; -1 otherwise
     const int* pair_body;      // the body that can move
     const int* pair_cap;       // contacts the pair can produce

@@ -377,16 +377,17 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             bool plane_pair = d->geom_type[g1] == RB_GEOM_PLANE && d->geom_type[g2] != RB_GEOM_PLANE;
             bool box_pair = d->geom_type[g1] == RB_GEOM_BOX && d->geom_type[g2] == RB_GEOM_BOX;
             bool sphere_box = d->geom_type[g1] == RB_GEOM_SPHERE && d->geom_type[g2] == RB_GEOM_BOX;
-            if (!plane_pair && !box_pair && !sphere_box)
-                return fail(RB_EINVAL,
-                            "unsupported collision pair (only plane vs sphere, capsule, box; box vs box; sphere vs box)");
+            bool capsule_box = d->geom_type[g1] == RB_GEOM_CAPSULE && d->geom_type[g2] == RB_GEOM_BOX;
+            if (!plane_pair && !box_pair && !sphere_box && !capsule_box)
+                return fail(RB_EINVAL, "unsupported collision pair (only plane vs sphere, capsule, box; box vs box; "
+                                       "sphere or capsule vs box)");
             pairs.push_back({g1, g2});
         }
     std::sort(pairs.begin(), pairs.end(), [](const Pair& x, const Pair& y) {
         return x.g1 != y.g1 ? x.g1 < y.g1 : x.g2 < y.g2;
     });
     int npair = (int)pairs.size();
-    if (npair > RB_MAX_PAIR) return fail(RB_EINVAL, "more than 64 collision pairs");
+    if (npair > RB_MAX_PAIR) return fail(RB_EINVAL, "more than 128 collision pairs");
     std::vector<int> pg1(npair), pg2(npair), ptype(npair), pbody(npair), pcap(npair), pslot(npair, -1);
     int nbb = 0;
     std::vector<double> psig(npair), pmu(npair), pmar(npair);
@@ -396,9 +397,10 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         int g1 = pairs[k].g1, g2 = pairs[k].g2;
         pg1[k] = g1;
         pg2[k] = g2;
-        ptype[k] = d->geom_type[g1] == RB_GEOM_BOX      ? RB_PAIR_BOXBOX
-                   : d->geom_type[g1] == RB_GEOM_SPHERE ? RB_PAIR_SPHEREBOX
-                                                        : d->geom_type[g2];
+        ptype[k] = d->geom_type[g1] == RB_GEOM_BOX       ? RB_PAIR_BOXBOX
+                   : d->geom_type[g1] == RB_GEOM_SPHERE  ? RB_PAIR_SPHEREBOX
+                   : d->geom_type[g1] == RB_GEOM_CAPSULE ? RB_PAIR_CAPSULEBOX
+                                                         : d->geom_type[g2];
         if (ptype[k] == RB_PAIR_BOXBOX) pslot[k] = nbb++;
         bool mov2 = movable[d->geom_body[g2]];
         pbody[k] = mov2 ? d->geom_body[g2] : d->geom_body[g1];
@@ -406,7 +408,9 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         pmu[k] = std::max(d->geom_friction[g1], d->geom_friction[g2]);
         pmar[k] = std::max(d->geom_margin[g1], d->geom_margin[g2]);
         if (d->geom_condim) pfric0[k] = std::max(d->geom_condim[g1], d->geom_condim[g2]) == 1;
-        pcap[k] = (ptype[k] == RB_GEOM_SPHERE || ptype[k] == RB_PAIR_SPHEREBOX) ? 1 : (ptype[k] == RB_GEOM_CAPSULE ? 2 : 8);
+        pcap[k] = (ptype[k] == RB_GEOM_SPHERE || ptype[k] == RB_PAIR_SPHEREBOX)      ? 1
+                  : (ptype[k] == RB_GEOM_CAPSULE || ptype[k] == RB_PAIR_CAPSULEBOX) ? 2
+                                                                                    : 8;
         maxcon += pcap[k];
     }
     // options
@@ -587,7 +591,9 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.nlim = nlim;
     m.ndamp = ndamp;
-    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
+    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE ||
+             std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
+             std::count(ptype.begin(), ptype.end(), RB_PAIR_CAPSULEBOX) > 0 ||
              std::count(pfric0.begin(), pfric0.end(), 1) > 0) ? 1 : 0;
     m.dt = (float)d->timestep;
     for (int i = 0; i < 3; i++) m.grav[i] = (float)d->gravity[i];

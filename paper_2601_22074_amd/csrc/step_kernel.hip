@@ -478,14 +478,17 @@ DEV float pick3(const float* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] :
 // Candidate contacts of a plane pair, in feature order: sphere 0; capsule ends 0 (-z), 1 (+z);
 // box vertices k = 4x + 2y + z by sign bits.  A sphere-box pair has the one candidate 0.
 DEV int pair_ncand(int type) {
-    return (type == RB_GEOM_SPHERE || type == RB_PAIR_SPHEREBOX) ? 1 : (type == RB_GEOM_CAPSULE ? 2 : 8);
+    return (type == RB_GEOM_SPHERE || type == RB_PAIR_SPHEREBOX)      ? 1
+           : (type == RB_GEOM_CAPSULE || type == RB_PAIR_CAPSULEBOX) ? 2
+                                                                     : 8;
 }
 
 // Candidate k of plane pair p: distance to the plane, contact point (halfway between the
 // surfaces) and the plane normal.  Sphere-box pair: the box's point closest to the sphere's
 // centre c (c clamped to the box in its frame), or the nearest face when c is inside (least
 // depth, lowest axis on ties, + side at 0); distance |c - closest| - r outside, -(depth + r)
-// inside; normal from the sphere towards the box.
+// inside; normal from the sphere towards the box.  Capsule-box pair: candidate k is the sphere
+// at the capsule's segment end k (0 at -z, 1 at +z) against the box by the same rule.
 template <bool EXT>
 DEV void pair_candidate(const DevModel& m, const float* L, const float* gsize, int p, int k, float* dist, float* pos,
                         float* nrm) {
@@ -494,8 +497,13 @@ DEV void pair_candidate(const DevModel& m, const float* L, const float* gsize, i
     geom_pose(m, L, m.pair_g2[p], x, R);
     const float* sz = gsize + 3 * m.pair_g2[p];
     const int type = m.pair_type[p];
-    if (EXT && type == RB_PAIR_SPHEREBOX) {
+    if (EXT && (type == RB_PAIR_SPHEREBOX || type == RB_PAIR_CAPSULEBOX)) {
         const float rad = gsize[3 * m.pair_g1[p]];
+        if (type == RB_PAIR_CAPSULEBOX) {
+            // the segment end: the sphere's centre
+            const float hl = k == 0 ? -gsize[3 * m.pair_g1[p] + 1] : gsize[3 * m.pair_g1[p] + 1];
+            xp[0] += hl * Rp[2]; xp[1] += hl * Rp[5]; xp[2] += hl * Rp[8];
+        }
         const float rel[3] = {xp[0] - x[0], xp[1] - x[1], xp[2] - x[2]};
         float pl[3], ql[3];
         bool inside = true;
@@ -794,8 +802,8 @@ struct StepArgs {
 // MAXD: longest dof chain the instantiation supports; TIMED: the diagnostic instantiation that
 // serves rb_step_taps (stage taps, work totals and per-stage shader-clock cycles); the plain
 // instantiation carries none of that code.  EXT: the extended instantiation, with the code of
-// box-box and sphere-box pairs, frictionless pairs, joint limits and joint damping, used for
-// models that have any.
+// box-box, sphere-box and capsule-box pairs, more than 64 pairs, frictionless pairs, joint
+// limits and joint damping, used for models that have any.
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
@@ -1123,26 +1131,38 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         RB_STAGE(2);
 
         // ---- collision: count per pair, scan, then each contact lane rebuilds its contact
-        int cnt = 0;
-        uint32_t cmask = 0;    // plane pairs: candidates below the margin
+        int cnt = 0, cnt2 = 0;
+        uint32_t cmask = 0, cmask2 = 0;    // plane-like pairs: candidates below the margin
         float pos_[3];
         // geom sizes: the world's own where the field is expanded per world
         const float* gsize = A.W.geom_size ? A.W.geom_size + (size_t)w * 3 * m.ngeom : m.geom_size;
-        if (lane < m.npair) {
-            if (EXT && m.pair_type[lane] == RB_PAIR_BOXBOX) {
-                cnt = box_box(m, L, gsize, lane, L + m.o_bb + RB_BB_FLOATS * m.pair_slot[lane]);
+        auto pair_count = [&](int p, int& c, uint32_t& mk) {
+            if (EXT && m.pair_type[p] == RB_PAIR_BOXBOX) {
+                c = box_box(m, L, gsize, p, L + m.o_bb + RB_BB_FLOATS * m.pair_slot[p]);
             } else {
-                cmask = pair_mask<EXT>(m, L, gsize, lane);
-                cnt = __builtin_popcount(cmask);
+                mk = pair_mask<EXT>(m, L, gsize, p);
+                c = __builtin_popcount(mk);
             }
-        }
+        };
+        if (lane < m.npair) pair_count(lane, cnt, cmask);
+        // more pairs than lanes (extended code): a second round, pair lane + 64
+        const bool two = EXT && m.npair > RB_WAVE;
+        if (two && lane + RB_WAVE < m.npair) pair_count(lane + RB_WAVE, cnt2, cmask2);
         if (EXT) wave_sync();   // box-box blocks written by their pair lanes are read by contact lanes
         int incl = wscan_incl(cnt, lane);
-        int total = __shfl(incl, RB_WAVE - 1);
+        const int total1 = __shfl(incl, RB_WAVE - 1);
+        int incl2 = 0, total = total1;
+        if (two) {
+            incl2 = wscan_incl(cnt2, lane);
+            total += __shfl(incl2, RB_WAVE - 1);
+        }
         ncon = total < m.ncap ? total : m.ncap;
         if (total > m.ncap) status |= RB_STATUS_CONOVERFLOW;
         ncon = __builtin_amdgcn_readfirstlane(ncon);
         bool has = lane < ncon;
+        // this lane's contact comes from the first round's pairs, or the second's past total1
+        const bool second = two && lane >= total1;
+        const int key = second ? lane - total1 : lane;
         int src = 0;
         {
             // smallest pair whose inclusive count exceeds this lane's contact index
@@ -1151,12 +1171,25 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             for (int it = 0; it < 6; it++) {
                 int mid = (lo + hi) >> 1;
                 int vmid = __shfl(incl, mid);
-                if (vmid > lane) hi = mid; else lo = mid + 1;
+                if (two) {
+                    const int v2 = __shfl(incl2, mid);
+                    if (second) vmid = v2;
+                }
+                if (vmid > key) hi = mid; else lo = mid + 1;
             }
             src = lo;
         }
         int before = __shfl(incl - cnt, src);
         uint32_t smask = (uint32_t)__shfl((int)cmask, src);
+        if (two) {
+            const int before2 = __shfl(incl2 - cnt2, src) + total1;
+            const uint32_t smask2 = (uint32_t)__shfl((int)cmask2, src);
+            if (second) {
+                before = before2;
+                smask = smask2;
+                src += RB_WAVE;
+            }
+        }
         float margin_c = 0.f;
         if (has) {
             int j = lane - before, feat;

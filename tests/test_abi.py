@@ -178,9 +178,9 @@ def test_model_files_match_generators(name):
 
 def test_size_limits_rejected(rb):
     """Models past the kernel's static bounds are refused before any device call: more than
-    64 collision pairs (the humanoid on a 3x3 tile grid has 76), more than 64 dofs."""
+    128 collision pairs (the humanoid on a 3x3 tile grid has 220), more than 64 dofs."""
     rc, msg = _create_error(robots.humanoid_terrain(n=3))
-    assert rc == -1 and "64 collision pairs" in msg, msg
+    assert rc == -1 and "128 collision pairs" in msg, msg
     rc, msg = _create_error(robots.chain(65, "chain65"))
     assert rc == -1 and "64 dofs" in msg, msg
     # contact ids carry geom indices in 8-bit fields: more than 256 geoms are refused even when

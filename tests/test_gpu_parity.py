@@ -461,3 +461,112 @@ def test_contact_overflow_flag():
     g = gpu_run(m, q, v, u, friction=fr, mass_scale=ms, contacts=True, contact_capacity=4)
     assert np.all(g["status"] & 4)
     assert np.all(g["contacts"]["ncon"] == 4)
+
+
+def test_capsule_box_contacts_random_poses(oracle_mod):
+    """A capsule at random poses around a rotated static box, its ends within a 2 cm margin band
+    or penetrating (centres outside or inside): contact keys, depths, points and normals
+    against the oracle on the same FP32 state."""
+    n = 64
+    r, hl = 0.04, 0.15
+    quat = robots.quat_axis_angle([0.3, -0.5, 0.8], 0.7)
+    mb = robots.ModelBuilder("box_capsule", timestep=0.005, nsubsteps=1)
+    mb.geom(0, "box", [0.3, 0.2, 0.1], pos=(0.0, 0.0, 0.5), quat=quat, contype=0, conaffinity=1)
+    b = mb.body("capsule", 0, (0, 0, 1), 0.8, robots.capsule_inertia(0.8, r, 2 * hl))
+    mb.joint(b, "free")
+    mb.geom(b, "capsule", [r, hl], contype=1, conaffinity=0, margin=0.02)
+    m = mb.build()
+    rng = np.random.default_rng(15)
+    R = rot(quat)
+    q = np.zeros((n, 7))
+    for w in range(n):
+        # one end near a point of a random face, the capsule at a random orientation
+        ax = rng.integers(3)
+        loc = rng.uniform(-1, 1, 3) * np.array([0.3, 0.2, 0.1])
+        sg = rng.choice([-1.0, 1.0])
+        loc[ax] = sg * ([0.3, 0.2, 0.1][ax] + rng.uniform(-0.06, 0.09))
+        end = np.array([0.0, 0.0, 0.5]) + R @ loc
+        cq = rng.normal(size=4)
+        cq /= np.linalg.norm(cq)
+        q[w, :3] = end + hl * rot(cq)[:, 2]          # the -z end sits at `end`
+        q[w, 3:] = cq
+    q = q.astype(np.float32)
+    v = np.zeros((n, 6), np.float32)
+    g = gpu_run(m, q, v, contacts=True)
+    c = g["contacts"]
+    o = oracle_mod.Oracle(m)
+    kinds = set()
+    for w in range(n):
+        t = o.forward(q[w], v[w])
+        if any(abs(d - 0.02) <= MARGIN_BAND for d in t["dist"]):
+            continue
+        nc = t["ncon"]
+        assert c["ncon"][w] == nc, f"world {w}"
+        kinds.add(nc)
+        if nc == 0:
+            continue
+        assert [tuple(x) for x in c["geom"][w, :nc]] == [tuple(x) for x in t["geom"]]
+        assert list(c["feature"][w, :nc]) == list(t["feature"])
+        assert np.abs(c["dist"][w, :nc] - t["dist"]).max() <= 2e-6, f"world {w}"
+        assert np.abs(c["pos"][w, :nc] - t["pos"]).max() <= 2e-6, f"world {w}"
+        assert np.abs(c["frame"][w, :nc].reshape(nc, 9) - t["frame"].reshape(nc, 9)).max() <= 2e-5, f"world {w}"
+    assert {0, 1} <= kinds
+
+
+def test_capsule_rests_on_box_gpu():
+    """A capsule dropped flat onto a box comes to rest on its two ends, each carrying half its
+    weight (HIP path, 3 s)."""
+    import torch
+    import paper_2601_22074_amd as rb
+    r, hl, mass = 0.04, 0.15, 0.8
+    mb = robots.ModelBuilder("box_capsule", timestep=0.002, nsubsteps=1)
+    mb.geom(0, "box", [0.3, 0.2, 0.1], pos=(0.0, 0.0, 0.1), contype=0, conaffinity=1)
+    b = mb.body("capsule", 0, (0, 0, 1), mass, robots.capsule_inertia(mass, r, 2 * hl))
+    mb.joint(b, "free")
+    mb.geom(b, "capsule", [r, hl], contype=1, conaffinity=0)
+    m = mb.build()
+    quat = robots.quat_axis_angle([0, 1, 0], np.pi / 2)
+    M = rb.Model(m)
+    B = rb.Batch(M, 4)
+    q = torch.tensor(np.tile(np.concatenate([[0.0, 0.0, 0.2 + r + 0.01], quat]), (4, 1)), dtype=torch.float32,
+                     device="cuda")
+    v = torch.zeros(4, 6, device="cuda")
+    con = B.contacts(4)
+    for _ in range(1500):
+        B.step(torch.zeros(4, 0, device="cuda"), q, v, con)
+    f = con.force[0, :int(con.ncon[0].item())].cpu().numpy()
+    vmax = float(v.abs().max().item())
+    B.close()
+    M.close()
+    assert f.shape[0] == 2
+    np.testing.assert_allclose(f[:, 0], [mass * 9.81 / 2] * 2, rtol=1e-4)
+    assert vmax < 1e-4
+
+
+def test_humanoid_limbs_touch_the_tiles():
+    """On the tile grid the humanoid's limbs come down on the tiles: along a 200-step rollout of
+    64 worlds, capsule-tile contacts appear in the contacts output (their parity with the
+    oracle is the teacher-forced humanoid_terrain test's)."""
+    m, q, v, u, fr, ms = _wl("humanoid_terrain", 64)
+    ctab = inputs.ctrl_table(m, "humanoid_terrain", range(64), 10)
+    import torch
+    import paper_2601_22074_amd as rb
+    dev = torch.device("cuda:0")
+    M = rb.Model(m)
+    B = rb.Batch(M, 64)
+    B.set_params(rb.PARAM_FRICTION, torch.tensor(fr, device=dev))
+    B.set_params(rb.PARAM_MASS_SCALE, torch.tensor(ms, device=dev))
+    qt, vt = torch.tensor(q, device=dev), torch.tensor(v, device=dev)
+    con = B.contacts(64)
+    tiles = [i for i, g in enumerate(m["geoms"]) if g["body"] == 0 and g["type"] == "box"]
+    caps = {i for i, g in enumerate(m["geoms"]) if g["type"] == "capsule"}
+    hits = 0
+    for s in range(200):
+        B.step(torch.tensor(ctab[s // 20], device=dev), qt, vt, con)
+        if s % 10 == 9:
+            n_ = con.ncon.cpu().numpy()
+            gg = con.geom.cpu().numpy()
+            hits += sum(1 for w in range(64) for i in range(n_[w]) if gg[w, i, 0] in caps and gg[w, i, 1] in tiles)
+    B.close()
+    M.close()
+    assert hits > 0

@@ -401,10 +401,14 @@ def quadruped_terrain(tile=0.4, n=3, max_height=0.04, seed=2601) -> dict:
     return m
 
 
+LIMB_BODIES = ("hip_yaw", "knee", "shoulder_yaw", "elbow")   # thighs, shins, upper arms, forearms
+
+
 def humanoid_terrain(tile=0.6, n=2, max_height=0.03, seed=2602) -> dict:
     """The humanoid on a random-height grid: n x n static box tiles of side ``tile`` centred
     under the robot, tops at heights U[0, max_height] from a fixed seed; the four foot boxes
-    touch the tiles (box against box), every other geom only the plane.  The pelvis starts
+    touch the tiles (box against box) and so do the limb capsules (thighs, shins, upper arms,
+    forearms: capsule against box), every other geom only the plane.  The pelvis starts
     ``max_height`` higher."""
     m = humanoid()
     m["name"] = "humanoid_terrain"
@@ -418,7 +422,10 @@ def humanoid_terrain(tile=0.6, n=2, max_height=0.03, seed=2602) -> dict:
                                    quat=[1.0, 0.0, 0.0, 0.0], size=[half, half, 0.05], friction=1.0,
                                    margin=0.0, **TERRAIN_GEOM))
     for g in m["geoms"]:
-        if g["type"] == "box" and m["bodies"][g["body"]]["name"].endswith("ankle_roll"):
+        bname = m["bodies"][g["body"]]["name"]
+        if g["type"] == "box" and bname.endswith("ankle_roll"):
+            g["contype"] = 3
+        if g["type"] == "capsule" and bname.endswith(LIMB_BODIES):
             g["contype"] = 3
     m["bodies"][1]["pos"][2] += max_height
     return m
