@@ -97,6 +97,8 @@ struct Model {
     std::vector<double> jdamp;    // hinge damping
     int ndamp = 0;
     std::vector<int> gtype, gbody, gcontype, gconaff, gcondim;
+    int hf_nrow = 0, hf_ncol = 0;
+    std::vector<double> hf;   // height grid [hf_nrow, hf_ncol]
     std::vector<double> gpos, gquat, gsize, gfric, gmargin;
     std::vector<int> atype, ajoint;
     std::vector<double> akp, akd, agear;
@@ -424,6 +426,7 @@ int pair_capacity(int t1, int t2) {
     if (t1 == RBO_GEOM_BOX && t2 == RBO_GEOM_BOX) return 8;
     if (t1 == RBO_GEOM_SPHERE && t2 == RBO_GEOM_BOX) return 1;
     if (t1 == RBO_GEOM_CAPSULE && t2 == RBO_GEOM_BOX) return 2;
+    if (t2 == RBO_GEOM_HFIELD) return t1 == RBO_GEOM_SPHERE ? 1 : t1 == RBO_GEOM_CAPSULE ? 2 : t1 == RBO_GEOM_BOX ? 8 : -1;
     return -1;
 }
 
@@ -668,6 +671,82 @@ void capsule_box(const Model& m, Data& d, int g1, int g2, double margin) {
     }
 }
 
+// The plane of the height-field triangle under world point e (by its local x, y): outward
+// (local +z side) unit normal n and vertex p0, world frame; false when e lies outside the grid.
+bool hfield_plane(const Model& m, const Data& d, int g, const double* e, double* n, double* p0) {
+    const double* x = &d.gx[3 * g];
+    const double* R = &d.gR[9 * g];
+    const double sx = m.gsize[3 * g], sy = m.gsize[3 * g + 1];
+    const double rel[3] = {e[0] - x[0], e[1] - x[1], e[2] - x[2]};
+    const double lx = R[0] * rel[0] + R[3] * rel[1] + R[6] * rel[2];
+    const double ly = R[1] * rel[0] + R[4] * rel[1] + R[7] * rel[2];
+    const int nr = m.hf_nrow, nc = m.hf_ncol;
+    const double u = (lx + sx) / (2 * sx) * (nc - 1), v = (ly + sy) / (2 * sy) * (nr - 1);
+    if (!(u >= 0 && u <= nc - 1 && v >= 0 && v <= nr - 1)) return false;
+    const int j = std::min((int)std::floor(u), nc - 2), i = std::min((int)std::floor(v), nr - 2);
+    auto vert = [&](int a, int b, double* P) {
+        P[0] = -sx + 2 * sx * b / (nc - 1);
+        P[1] = -sy + 2 * sy * a / (nr - 1);
+        P[2] = m.hf[(size_t)a * nc + b];
+    };
+    double P0[3], P1[3], P2[3];
+    vert(i, j, P0);
+    if (u - j >= v - i) {
+        vert(i, j + 1, P1);
+        vert(i + 1, j + 1, P2);
+    } else {
+        vert(i + 1, j + 1, P1);
+        vert(i + 1, j, P2);
+    }
+    const double a[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
+    const double b[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
+    double nl[3];
+    cross3(a, b, nl);
+    const double len = std::sqrt(dot3(nl, nl));
+    for (int k = 0; k < 3; k++) nl[k] /= len;
+    matvec3(R, nl, n);
+    double pw[3];
+    matvec3(R, P0, pw);
+    for (int k = 0; k < 3; k++) p0[k] = x[k] + pw[k];
+    return true;
+}
+
+// Height field g1 against sphere, capsule or box g2, as against a plane candidate by candidate
+// (sphere centre, capsule ends 0 / 1, box vertices by sign bits): each candidate point is
+// tested against the plane of the triangle under it (hfield_plane); candidates outside the
+// grid make no contact.  Normal from the height field towards g2.
+void hfield_pair(const Model& m, Data& d, int g1, int g2, double margin) {
+    const double* x = &d.gx[3 * g2];
+    const double* R = &d.gR[9 * g2];
+    const double* sz = &m.gsize[3 * g2];
+    const int t2 = m.gtype[g2];
+    const int ncand = t2 == RBO_GEOM_SPHERE ? 1 : t2 == RBO_GEOM_CAPSULE ? 2 : 8;
+    for (int k = 0; k < ncand; k++) {
+        double e[3], rad = 0;
+        if (t2 == RBO_GEOM_SPHERE) {
+            for (int i = 0; i < 3; i++) e[i] = x[i];
+            rad = sz[0];
+        } else if (t2 == RBO_GEOM_CAPSULE) {
+            const double sgn = k == 0 ? -1.0 : 1.0;
+            for (int i = 0; i < 3; i++) e[i] = x[i] + sgn * sz[1] * R[3 * i + 2];
+            rad = sz[0];
+        } else {
+            const double loc[3] = {(k & 4) ? sz[0] : -sz[0], (k & 2) ? sz[1] : -sz[1], (k & 1) ? sz[2] : -sz[2]};
+            matvec3(R, loc, e);
+            for (int i = 0; i < 3; i++) e[i] += x[i];
+        }
+        double n[3], p0[3];
+        if (!hfield_plane(m, d, g1, e, n, p0)) continue;
+        const double r[3] = {e[0] - p0[0], e[1] - p0[1], e[2] - p0[2]};
+        const double dist = dot3(n, r) - rad;
+        if (dist < margin) {
+            double pos[3];
+            for (int i = 0; i < 3; i++) pos[i] = e[i] - n[i] * (rad + dist / 2);
+            add_contact(m, d, g1, g2, k, dist, pos, n);
+        }
+    }
+}
+
 void collide(const Model& m, Data& d) {
     d.con.clear();
     for (int ga = 0; ga < m.ngeom; ga++)
@@ -687,6 +766,10 @@ void collide(const Model& m, Data& d) {
             }
             if (t1 == RBO_GEOM_CAPSULE && t2 == RBO_GEOM_BOX) {
                 capsule_box(m, d, g1, g2, margin);
+                continue;
+            }
+            if (t2 == RBO_GEOM_HFIELD) {
+                hfield_pair(m, d, g2, g1, margin);   // the height field first, as a plane
                 continue;
             }
             if (t1 != RBO_GEOM_PLANE) continue;  // other pairs were rejected at creation
@@ -996,7 +1079,8 @@ double collision_ops(const Model& m, const Data& d) {
         for (int b = a + 1; b < m.ngeom; b++) {
             if (!pair_allowed(m, a, b)) continue;
             int t1 = std::min(m.gtype[a], m.gtype[b]), t2 = std::max(m.gtype[a], m.gtype[b]);
-            if (t1 == RBO_GEOM_PLANE) f += t2 == RBO_GEOM_SPHERE ? 20 : (t2 == RBO_GEOM_CAPSULE ? 60 : 8 * 25);
+            if (t2 == RBO_GEOM_HFIELD) f += (t1 == RBO_GEOM_SPHERE ? 1 : t1 == RBO_GEOM_CAPSULE ? 2 : 8) * 90;
+            else if (t1 == RBO_GEOM_PLANE) f += t2 == RBO_GEOM_SPHERE ? 20 : (t2 == RBO_GEOM_CAPSULE ? 60 : 8 * 25);
             else if (t1 == RBO_GEOM_SPHERE) f += 80;
             else if (t1 == RBO_GEOM_CAPSULE) f += 2 * 80 + 12;
             else f += 15 * 40 + 300;
@@ -1313,10 +1397,24 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
     if (dsc->geom_condim) M.gcondim.assign(dsc->geom_condim, dsc->geom_condim + ng);
     for (int g = 0; g < ng; g++)
         if (M.gcondim[g] != 1 && M.gcondim[g] != 3) return bad("geom condim must be 1 or 3");
+    bool any_hf = false;
     for (int g = 0; g < ng; g++) {
-        if (M.gtype[g] < 0 || M.gtype[g] > 3) return bad("unknown geom type");
+        if (M.gtype[g] < 0 || M.gtype[g] > 4) return bad("unknown geom type");
         if (M.gbody[g] < 0 || M.gbody[g] >= nb) return bad("geom on invalid body");
         if (M.gtype[g] == RBO_GEOM_PLANE && M.movable[M.gbody[g]]) return bad("planes must be static");
+        if (M.gtype[g] == RBO_GEOM_HFIELD) {
+            if (M.movable[M.gbody[g]]) return bad("height fields must be static");
+            if (!(M.gsize[3 * g] > 0 && M.gsize[3 * g + 1] > 0)) return bad("height field extents must be positive");
+            any_hf = true;
+        }
+    }
+    if (any_hf) {
+        if (dsc->hfield_nrow < 2 || dsc->hfield_ncol < 2 || !dsc->hfield_data) return bad("height field grid missing");
+        M.hf_nrow = dsc->hfield_nrow;
+        M.hf_ncol = dsc->hfield_ncol;
+        M.hf.assign(dsc->hfield_data, dsc->hfield_data + (size_t)M.hf_nrow * M.hf_ncol);
+        for (double h : M.hf)
+            if (!std::isfinite(h)) return bad("height field heights must be finite");
     }
     M.maxcon = 0; M.npair = 0;
     for (int a = 0; a < ng; a++)

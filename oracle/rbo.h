@@ -26,7 +26,7 @@
 extern "C" {
 #endif
 
-enum { RBO_GEOM_PLANE = 0, RBO_GEOM_SPHERE = 1, RBO_GEOM_CAPSULE = 2, RBO_GEOM_BOX = 3 };
+enum { RBO_GEOM_PLANE = 0, RBO_GEOM_SPHERE = 1, RBO_GEOM_CAPSULE = 2, RBO_GEOM_BOX = 3, RBO_GEOM_HFIELD = 4 };
 enum { RBO_JNT_FREE = 0, RBO_JNT_HINGE = 1 };
 enum { RBO_ACT_POSITION = 0, RBO_ACT_MOTOR = 1 };
 
@@ -62,6 +62,15 @@ typedef struct rbo_desc {
     /* geom contact dimensionality [ngeom] (1 frictionless, 3 pyramidal friction), or NULL for
        3 everywhere; a pair takes the larger of its two geoms' */
     const int32_t* geom_condim;
+    /* height grid of the model's height-field geoms (type RBO_GEOM_HFIELD, static; a geom's
+       size[0], size[1] are the grid's half extents along its local x and y): hfield_nrow rows
+       along y by hfield_ncol columns along x (both >= 2), heights [nrow, ncol] along local z;
+       sample (i, j) sits at x = -sx + 2 sx j / (ncol - 1), y = -sy + 2 sy i / (nrow - 1).  Each
+       cell is split along its diagonal from sample (i, j) to (i + 1, j + 1) into the triangles
+       {(i, j), (i, j + 1), (i + 1, j + 1)} and {(i, j), (i + 1, j + 1), (i + 1, j)}.  NULL with
+       0 rows when the model has no height field. */
+    int32_t hfield_nrow, hfield_ncol;
+    const double* hfield_data;
 } rbo_desc;
 
 typedef struct rbo_info {

@@ -105,6 +105,7 @@ class ModelBuilder:
         self.geoms: list[dict] = []
         self.actuators: list[dict] = []
         self.per_world = {"friction": False, "mass_scale": False}
+        self.hfield_grid = None
 
     def body(self, name, parent, pos, mass, inertia, ipos=(0, 0, 0), iquat=(1, 0, 0, 0), quat=(1, 0, 0, 0)) -> int:
         pid = parent if isinstance(parent, int) else self.body_id(parent)
@@ -153,14 +154,23 @@ class ModelBuilder:
         half = float(np.linalg.norm(b - a)) / 2.0
         return self.geom(body, "capsule", [radius, half], pos=(a + b) / 2.0, quat=quat_z_to(b - a), **kw)
 
+    def hfield(self, heights) -> None:
+        """The model's height grid [nrow, ncol] (rows along y, columns along x) used by its
+        "hfield" geoms, whose size[0], size[1] are the grid's half extents."""
+        h = np.asarray(heights, float)
+        self.hfield_grid = dict(nrow=int(h.shape[0]), ncol=int(h.shape[1]), data=[float(x) for x in h.ravel()])
+
     def actuator(self, joint, type_="position", kp=0.0, kd=0.0, gear=1.0) -> int:
         self.actuators.append(dict(type=type_, joint=int(joint), kp=float(kp), kd=float(kd), gear=float(gear)))
         return len(self.actuators) - 1
 
     def build(self) -> dict:
-        return dict(name=self.name, opt=copy.deepcopy(self.opt), bodies=copy.deepcopy(self.bodies),
-                    joints=copy.deepcopy(self.joints), geoms=copy.deepcopy(self.geoms),
-                    actuators=copy.deepcopy(self.actuators), per_world=dict(self.per_world))
+        m = dict(name=self.name, opt=copy.deepcopy(self.opt), bodies=copy.deepcopy(self.bodies),
+                 joints=copy.deepcopy(self.joints), geoms=copy.deepcopy(self.geoms),
+                 actuators=copy.deepcopy(self.actuators), per_world=dict(self.per_world))
+        if self.hfield_grid is not None:
+            m["hfield"] = copy.deepcopy(self.hfield_grid)
+        return m
 
 
 # --------------------------------------------------------------------------------------
