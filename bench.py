@@ -43,14 +43,17 @@ WORKLOAD_TEXT = {
     "quadruped_terrain": "quadruped on a 3x3 random-height grid of 0.4 m box tiles (tops U[0, 4 cm]): "
                          "sphere feet vs static boxes, otherwise as quadruped",
     "humanoid_terrain": "humanoid on a 2x2 random-height grid of 0.6 m box tiles (tops U[0, 3 cm]): foot boxes vs "
-                        "static boxes (16 box-box pairs), otherwise as humanoid",
+                        "static boxes (16 box-box pairs), limb capsules vs static boxes (64 capsule-box pairs), "
+                        "otherwise as humanoid",
     "humanoid_damp": "humanoid with joint damping 0.5 N m s/rad on every hinge (implicit in the step), "
                      "otherwise as humanoid",
+    "quadruped_hfield": "quadruped on smooth height-field terrain (41x41 grid over 4 m x 4 m, +-3 cm) instead of the "
+                        "plane: feet and torso vs the triangle under each candidate point, otherwise as quadruped",
 }
 MIX = [("chain3", 512), ("quadruped", 4096), ("humanoid", 2048), ("arm_box", 1024)]
 DEFAULT_WORLDS = {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 1024, "humanoid_lim": 8192,
                   "quadruped_lim": 4096, "quadruped_terrain": 4096, "humanoid_terrain": 8192,
-                  "humanoid_damp": 8192}
+                  "humanoid_damp": 8192, "quadruped_hfield": 4096}
 WORKLOAD_TEXT["serve"] = ("serving: Poisson arrivals of rollout requests, model uniform over chain3/quadruped/humanoid/"
                           "arm_box, worlds log-uniform 16-4096, horizon uniform 50-500 env steps, device-side seeded "
                           "inputs, HBM-budget admission, continuous batching in one fused launch per tick")

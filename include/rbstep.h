@@ -46,7 +46,7 @@ extern "C" {
 #define RB_STATUS_CONOVERFLOW 4u /* more contacts than the per-world capacity; the extra ones
                                     (last in pair order) were dropped for this substep */
 
-enum { RB_GEOM_PLANE = 0, RB_GEOM_SPHERE = 1, RB_GEOM_CAPSULE = 2, RB_GEOM_BOX = 3 };
+enum { RB_GEOM_PLANE = 0, RB_GEOM_SPHERE = 1, RB_GEOM_CAPSULE = 2, RB_GEOM_BOX = 3, RB_GEOM_HFIELD = 4 };
 enum { RB_JNT_FREE = 0, RB_JNT_HINGE = 1 };
 enum { RB_ACT_POSITION = 0, RB_ACT_MOTOR = 1 };
 enum {
@@ -94,6 +94,17 @@ typedef struct rb_model_desc {
      * everywhere; a pair takes the larger of its two geoms' (a condim-1 pair keeps the normal
      * row only and reports zero tangential force) */
     const int32_t* geom_condim;
+    /* height grid of the model's height-field geoms (type RB_GEOM_HFIELD, static; a geom's
+     * size[0], size[1] are the grid's half extents along its local x and y): hfield_nrow rows
+     * along y by hfield_ncol columns along x (both >= 2), heights [nrow, ncol] along local z,
+     * sample (i, j) at x = -sx + 2 sx j / (ncol - 1), y = -sy + 2 sy i / (nrow - 1).  A cell is
+     * split along its diagonal from sample (i, j) to (i + 1, j + 1); a sphere's centre, a
+     * capsule's segment ends and a box's vertices are each tested, as against a plane, against
+     * the plane of the triangle under them (none off the grid), the height field taking the
+     * place of g1.  0 rows and NULL when the model has none.  Cites: paper, section
+     * "Components", paragraph "Terrain" (height-field terrains). */
+    int32_t hfield_nrow, hfield_ncol;
+    const double* hfield_data;
 } rb_model_desc;
 
 typedef struct rb_model rb_model;
@@ -148,11 +159,12 @@ int rb_model_create(const rb_model_desc* desc, rb_model** out);
  *               "inertia": [3]}, ...]   (body 0 = world),
  *   "joints": [{"type": "free" | "hinge", "body", "pos": [3], "axis": [3], "armature",
  *               "range": [2], "damping" (both optional, hinges only)}, ...],
- *   "geoms": [{"type": "plane" | "sphere" | "capsule" | "box", "body", "pos": [3],
+ *   "geoms": [{"type": "plane" | "sphere" | "capsule" | "box" | "hfield", "body", "pos": [3],
  *              "quat": [4], "size": [3], "friction", "contype", "conaffinity", "margin",
  *              "condim" (optional, 1 or 3)}, ...],
  *   "actuators": [{"type": "position" | "motor", "joint", "kp", "kd", "gear"}, ...],
- *   "per_world": {"friction": bool, "mass_scale": bool}   (optional, default false);
+ *   "per_world": {"friction": bool, "mass_scale": bool}   (optional, default false),
+ *   "hfield": {"nrow", "ncol", "data": [nrow * ncol]}    (required with hfield geoms);
  * other keys are ignored.  Each entry maps to the rb_model_desc field of the same name, in
  * list order.  Malformed JSON or a missing or mistyped field is RB_EINVAL (with the field
  * named in rb_last_error) before any device call; the parsed description then goes through

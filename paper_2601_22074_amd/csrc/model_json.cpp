@@ -7,10 +7,11 @@
 //              "inertia": [3]}, ...],                    body 0 is the world
 //  "joints": [{"type": "free"|"hinge", "body", "pos": [3], "axis": [3], "armature",
 //              "range": [2], "damping" (both optional)}, ...],
-//  "geoms": [{"type": "plane"|"sphere"|"capsule"|"box", "body", "pos": [3], "quat": [4],
+//  "geoms": [{"type": "plane"|"sphere"|"capsule"|"box"|"hfield", "body", "pos": [3], "quat": [4],
 //             "size": [3], "friction", "contype", "conaffinity", "margin", "condim" (optional)}, ...],
 //  "actuators": [{"type": "position"|"motor", "joint", "kp", "kd", "gear"}, ...],
-//  "per_world": {"friction": bool, "mass_scale": bool}}      optional, default false
+//  "per_world": {"friction": bool, "mass_scale": bool},      optional, default false
+//  "hfield": {"nrow", "ncol", "data": [nrow * ncol]}}        required with hfield geoms
 //
 // Other keys (names, comments) are ignored.  Every listed field is required except a joint's
 // range and damping, a geom's condim and per_world; a missing or mistyped field is RB_EINVAL with
@@ -244,11 +245,11 @@ int rb_model_create_json(const char* json, rb_model** out) {
         if (ok && o.obj.count("range")) ok = R.vec(o, "range", w, 2, &jrange[2 * j]);
         if (ok && o.obj.count("damping")) ok = R.num(o, "damping", w, &jdamp[j]);
     }
-    static const char* const gnames[] = {"plane", "sphere", "capsule", "box"};
+    static const char* const gnames[] = {"plane", "sphere", "capsule", "box", "hfield"};
     for (int g = 0; g < ng && ok; g++) {
         const JVal& o = (*geoms)[g];
         const std::string w = "geom " + std::to_string(g);
-        ok = R.choice(o, "type", w, gnames, 4, &gtype[g]) && R.integer(o, "body", w, &gbody[g]) &&
+        ok = R.choice(o, "type", w, gnames, 5, &gtype[g]) && R.integer(o, "body", w, &gbody[g]) &&
              R.vec(o, "pos", w, 3, &gpos[3 * g]) && R.vec(o, "quat", w, 4, &gquat[4 * g]) &&
              R.vec(o, "size", w, 3, &gsize[3 * g]) && R.num(o, "friction", w, &gfric[g]) &&
              R.integer(o, "contype", w, &gct[g]) && R.integer(o, "conaffinity", w, &gca[g]) &&
@@ -280,6 +281,22 @@ int rb_model_create_json(const char* json, rb_model** out) {
         auto s = pw->second.obj.find("mass_scale");
         d.friction_per_world = f != pw->second.obj.end() && f->second.kind == JVal::BOOL && f->second.b;
         d.mass_scale_per_world = s != pw->second.obj.end() && s->second.kind == JVal::BOOL && s->second.b;
+    }
+    std::vector<double> hfdata;
+    auto hf = root.obj.find("hfield");
+    if (hf != root.obj.end()) {
+        double nr = 0, nc = 0;
+        ok = R.num(hf->second, "nrow", "hfield", &nr) && R.num(hf->second, "ncol", "hfield", &nc);
+        if (ok && (nr != std::floor(nr) || nc != std::floor(nc) || nr < 2 || nc < 2 || nr * nc > 1e7))
+            return rb_record_error(RB_EINVAL, "model JSON: hfield nrow and ncol must be integers >= 2");
+        if (ok) {
+            hfdata.assign((size_t)(nr * nc), 0.0);
+            ok = R.vec(hf->second, "data", "hfield", (int)(nr * nc), hfdata.data());
+        }
+        if (!ok) return rb_record_error(RB_EINVAL, ("model JSON: " + R.err).c_str());
+        d.hfield_nrow = (int32_t)nr;
+        d.hfield_ncol = (int32_t)nc;
+        d.hfield_data = hfdata.data();
     }
     d.nbody = nb; d.njnt = nj; d.ngeom = ng; d.nu = nu;
     d.body_parent = bpar.data(); d.body_pos = bpos.data(); d.body_quat = bquat.data();

@@ -19,6 +19,7 @@
 #define RB_PAIR_BOXBOX 16         // pair_type of a box-box pair (plane pairs hold g2's geom type)
 #define RB_PAIR_SPHEREBOX 17      // pair_type of a sphere (g1) - box (g2) pair
 #define RB_PAIR_CAPSULEBOX 18     // pair_type of a capsule (g1) - box (g2) pair: its two end spheres
+#define RB_PAIR_HFIELD 32         // pair_type of a height field (g1) - geom (g2) pair: this + g2's geom type
 #define RB_BB_FLOATS 96           // LDS floats per box-box pair: clip buffers, contacts, normal
 
 struct DevModel {
@@ -108,6 +109,8 @@ struct DevModel {
     const float* geom_pos;     // [3]
     const float* geom_quat;    // [4]
     const float* geom_size;    // [3]
+    const float* hf_data;      // height grid [hf_nrow, hf_ncol] of the height-field geoms (or null)
+    int hf_nrow, hf_ncol;
     // LDS layout (offsets in floats from the world's base)
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
     int o_xpos, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;

@@ -352,7 +352,16 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     for (int b = 1; b < nb; b++) movable[b] = movable[P(b)] || bjnt[b] >= 0;
     for (int g = 0; g < ng; g++) {
         int t = d->geom_type[g], b = d->geom_body[g];
-        if (t < RB_GEOM_PLANE || t > RB_GEOM_BOX) return fail(RB_EINVAL, "unknown geom type");
+        if (t < RB_GEOM_PLANE || t > RB_GEOM_HFIELD) return fail(RB_EINVAL, "unknown geom type");
+        if (t == RB_GEOM_HFIELD) {
+            if (movable[b]) return fail(RB_EINVAL, "a height field must be on a static body");
+            if (!(d->geom_size[3 * g] > 0 && d->geom_size[3 * g + 1] > 0))
+                return fail(RB_EINVAL, "height field extents must be positive");
+            if (d->hfield_nrow < 2 || d->hfield_ncol < 2 || !d->hfield_data)
+                return fail(RB_EINVAL, "height field geom without a grid (hfield_nrow, hfield_ncol >= 2, data)");
+            for (long k = 0; k < (long)d->hfield_nrow * d->hfield_ncol; k++)
+                if (!std::isfinite(d->hfield_data[k])) return fail(RB_EINVAL, "height field heights must be finite");
+        }
         if (d->geom_condim && d->geom_condim[g] != 1 && d->geom_condim[g] != 3)
             return fail(RB_EINVAL, "geom condim must be 1 or 3");
         if (b < 0 || b >= nb) return fail(RB_EINVAL, "geom on an invalid body");
@@ -374,13 +383,18 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             if (movable[ba] && movable[bb]) return fail(RB_EINVAL, "contacts between two moving bodies are not supported");
             int g1 = a, g2 = b;
             if (d->geom_type[g2] < d->geom_type[g1]) std::swap(g1, g2);
-            bool plane_pair = d->geom_type[g1] == RB_GEOM_PLANE && d->geom_type[g2] != RB_GEOM_PLANE;
+            // a height field takes the place of g1, as a plane does
+            if (d->geom_type[g2] == RB_GEOM_HFIELD) std::swap(g1, g2);
+            bool hfield_pair = d->geom_type[g1] == RB_GEOM_HFIELD && d->geom_type[g2] >= RB_GEOM_SPHERE &&
+                               d->geom_type[g2] <= RB_GEOM_BOX;
+            bool plane_pair = d->geom_type[g1] == RB_GEOM_PLANE && d->geom_type[g2] != RB_GEOM_PLANE &&
+                              d->geom_type[g2] != RB_GEOM_HFIELD;
             bool box_pair = d->geom_type[g1] == RB_GEOM_BOX && d->geom_type[g2] == RB_GEOM_BOX;
             bool sphere_box = d->geom_type[g1] == RB_GEOM_SPHERE && d->geom_type[g2] == RB_GEOM_BOX;
             bool capsule_box = d->geom_type[g1] == RB_GEOM_CAPSULE && d->geom_type[g2] == RB_GEOM_BOX;
-            if (!plane_pair && !box_pair && !sphere_box && !capsule_box)
-                return fail(RB_EINVAL, "unsupported collision pair (only plane vs sphere, capsule, box; box vs box; "
-                                       "sphere or capsule vs box)");
+            if (!plane_pair && !box_pair && !sphere_box && !capsule_box && !hfield_pair)
+                return fail(RB_EINVAL, "unsupported collision pair (only plane or height field vs sphere, capsule, "
+                                       "box; box vs box; sphere or capsule vs box)");
             pairs.push_back({g1, g2});
         }
     std::sort(pairs.begin(), pairs.end(), [](const Pair& x, const Pair& y) {
@@ -400,6 +414,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         ptype[k] = d->geom_type[g1] == RB_GEOM_BOX       ? RB_PAIR_BOXBOX
                    : d->geom_type[g1] == RB_GEOM_SPHERE  ? RB_PAIR_SPHEREBOX
                    : d->geom_type[g1] == RB_GEOM_CAPSULE ? RB_PAIR_CAPSULEBOX
+                   : d->geom_type[g1] == RB_GEOM_HFIELD  ? RB_PAIR_HFIELD + d->geom_type[g2]
                                                          : d->geom_type[g2];
         if (ptype[k] == RB_PAIR_BOXBOX) pslot[k] = nbb++;
         bool mov2 = movable[d->geom_body[g2]];
@@ -408,9 +423,10 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         pmu[k] = std::max(d->geom_friction[g1], d->geom_friction[g2]);
         pmar[k] = std::max(d->geom_margin[g1], d->geom_margin[g2]);
         if (d->geom_condim) pfric0[k] = std::max(d->geom_condim[g1], d->geom_condim[g2]) == 1;
-        pcap[k] = (ptype[k] == RB_GEOM_SPHERE || ptype[k] == RB_PAIR_SPHEREBOX)      ? 1
-                  : (ptype[k] == RB_GEOM_CAPSULE || ptype[k] == RB_PAIR_CAPSULEBOX) ? 2
-                                                                                    : 8;
+        const int shape = ptype[k] >= RB_PAIR_HFIELD ? ptype[k] - RB_PAIR_HFIELD : ptype[k];
+        pcap[k] = (shape == RB_GEOM_SPHERE || shape == RB_PAIR_SPHEREBOX)      ? 1
+                  : (shape == RB_GEOM_CAPSULE || shape == RB_PAIR_CAPSULEBOX) ? 2
+                                                                               : 8;
         maxcon += pcap[k];
     }
     // options
@@ -572,6 +588,12 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     F(std::vector<double>(d->geom_pos, d->geom_pos + 3 * ng), &m.geom_pos);
     F(std::vector<double>(d->geom_quat, d->geom_quat + 4 * ng), &m.geom_quat);
     F(std::vector<double>(d->geom_size, d->geom_size + 3 * ng), &m.geom_size);
+    const bool has_hf = std::count(d->geom_type, d->geom_type + ng, RB_GEOM_HFIELD) > 0;
+    if (has_hf) {
+        F(std::vector<double>(d->hfield_data, d->hfield_data + (size_t)d->hfield_nrow * d->hfield_ncol), &m.hf_data);
+        m.hf_nrow = d->hfield_nrow;
+        m.hf_ncol = d->hfield_ncol;
+    }
     void* dev = nullptr;
     size_t bytes = B.words.size() * 4;
     hipError_t e = hipMalloc(&dev, bytes);
@@ -594,6 +616,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_CAPSULEBOX) > 0 ||
+             std::count_if(ptype.begin(), ptype.end(), [](int t) { return t >= RB_PAIR_HFIELD; }) > 0 ||
              std::count(pfric0.begin(), pfric0.end(), 1) > 0) ? 1 : 0;
     m.dt = (float)d->timestep;
     for (int i = 0; i < 3; i++) m.grav[i] = (float)d->gravity[i];

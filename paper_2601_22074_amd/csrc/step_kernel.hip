@@ -478,9 +478,51 @@ DEV float pick3(const float* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] :
 // Candidate contacts of a plane pair, in feature order: sphere 0; capsule ends 0 (-z), 1 (+z);
 // box vertices k = 4x + 2y + z by sign bits.  A sphere-box pair has the one candidate 0.
 DEV int pair_ncand(int type) {
+    if (type >= RB_PAIR_HFIELD) type -= RB_PAIR_HFIELD;   // a height field: as the plane
     return (type == RB_GEOM_SPHERE || type == RB_PAIR_SPHEREBOX)      ? 1
            : (type == RB_GEOM_CAPSULE || type == RB_PAIR_CAPSULEBOX) ? 2
                                                                      : 8;
+}
+
+// The plane of the height-field triangle under world point e (by its local x and y): outward
+// (local +z side) unit normal n and vertex p0; false when e lies outside the grid.  Rows run
+// along local y, columns along x; a cell is split along its diagonal from sample (i, j) to
+// (i + 1, j + 1).
+DEV bool hfield_plane(const DevModel& m, const float* gsize, int g, const float* xg, const float* Rg, const float* e,
+                      float* n, float* p0) {
+    const float sx = gsize[3 * g], sy = gsize[3 * g + 1];
+    const float rel[3] = {e[0] - xg[0], e[1] - xg[1], e[2] - xg[2]};
+    const float lx = Rg[0] * rel[0] + Rg[3] * rel[1] + Rg[6] * rel[2];
+    const float ly = Rg[1] * rel[0] + Rg[4] * rel[1] + Rg[7] * rel[2];
+    const int nr = m.hf_nrow, nc = m.hf_ncol;
+    const float u = (lx + sx) / (2.f * sx) * (float)(nc - 1), v = (ly + sy) / (2.f * sy) * (float)(nr - 1);
+    if (!(u >= 0.f && u <= (float)(nc - 1) && v >= 0.f && v <= (float)(nr - 1))) return false;
+    const int j = min((int)floorf(u), nc - 2), i = min((int)floorf(v), nr - 2);
+    auto vert = [&](int a, int b, float* P) {
+        P[0] = -sx + 2.f * sx * (float)b / (float)(nc - 1);
+        P[1] = -sy + 2.f * sy * (float)a / (float)(nr - 1);
+        P[2] = m.hf_data[a * nc + b];
+    };
+    float P0[3], P1[3], P2[3];
+    vert(i, j, P0);
+    if (u - (float)j >= v - (float)i) {
+        vert(i, j + 1, P1);
+        vert(i + 1, j + 1, P2);
+    } else {
+        vert(i + 1, j + 1, P1);
+        vert(i + 1, j, P2);
+    }
+    const float a[3] = {P1[0] - P0[0], P1[1] - P0[1], P1[2] - P0[2]};
+    const float b[3] = {P2[0] - P0[0], P2[1] - P0[1], P2[2] - P0[2]};
+    float nl[3];
+    cross(a, b, nl);
+    const float il = 1.0f / sqrtf(dot(nl, nl));
+    nl[0] *= il; nl[1] *= il; nl[2] *= il;
+    mv(Rg, nl, n);
+    float pw[3];
+    mv(Rg, P0, pw);
+    p0[0] = xg[0] + pw[0]; p0[1] = xg[1] + pw[1]; p0[2] = xg[2] + pw[2];
+    return true;
 }
 
 // Candidate k of plane pair p: distance to the plane, contact point (halfway between the
@@ -537,13 +579,15 @@ DEV void pair_candidate(const DevModel& m, const float* L, const float* gsize, i
         pos[0] = xp[0] - nw[0] * h; pos[1] = xp[1] - nw[1] * h; pos[2] = xp[2] - nw[2] * h;
         return;
     }
-    const float n[3] = {Rp[2], Rp[5], Rp[8]};
-    nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2];
+    // a plane, or a height field: the plane of the triangle under the candidate point
+    const bool hf = EXT && type >= RB_PAIR_HFIELD;
+    const int shape = hf ? type - RB_PAIR_HFIELD : type;
+    float n[3] = {Rp[2], Rp[5], Rp[8]};
     float e[3], rad = 0.f;
-    if (type == RB_GEOM_SPHERE) {
+    if (shape == RB_GEOM_SPHERE) {
         e[0] = x[0]; e[1] = x[1]; e[2] = x[2];
         rad = sz[0];
-    } else if (type == RB_GEOM_CAPSULE) {
+    } else if (shape == RB_GEOM_CAPSULE) {
         const float sgn = k == 0 ? -sz[1] : sz[1];
         e[0] = x[0] + sgn * R[2]; e[1] = x[1] + sgn * R[5]; e[2] = x[2] + sgn * R[8];
         rad = sz[0];
@@ -552,7 +596,15 @@ DEV void pair_candidate(const DevModel& m, const float* L, const float* gsize, i
         mv(R, loc, e);
         e[0] += x[0]; e[1] += x[1]; e[2] += x[2];
     }
-    const float r[3] = {e[0] - xp[0], e[1] - xp[1], e[2] - xp[2]};
+    float p0[3] = {xp[0], xp[1], xp[2]};
+    if (hf && !hfield_plane(m, gsize, m.pair_g1[p], xp, Rp, e, n, p0)) {
+        *dist = INFINITY;   // off the grid: no contact
+        nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2];
+        pos[0] = e[0]; pos[1] = e[1]; pos[2] = e[2];
+        return;
+    }
+    nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2];
+    const float r[3] = {e[0] - p0[0], e[1] - p0[1], e[2] - p0[2]};
     const float d = dot(n, r) - rad;
     *dist = d;
     const float h = rad + 0.5f * d;

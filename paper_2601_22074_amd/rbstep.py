@@ -26,7 +26,7 @@ NSTATS = 4 + NSTAGE + STATS_SUB * SUBSTAT
 STAGES = ["kinematics", "inertia+bias+M", "factor M + a0", "collision", "constraint rows", "newton start",
           "gradient+hessian", "hessian factor+solve", "line search+update", "integrate"]
 
-_GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3}
+_GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3, "hfield": 4}
 _JNT = {"free": 0, "hinge": 1}
 _ACT = {"position": 0, "motor": 1}
 
@@ -63,7 +63,8 @@ class _Desc(C.Structure):
                 ("timestep", C.c_double), ("nsubsteps", C.c_int32), ("gravity", C.c_double * 3),
                 ("iterations", C.c_int32), ("tolerance", C.c_double), ("solref", C.c_double * 2),
                 ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32),
-                ("jnt_range", _f64p), ("jnt_damping", _f64p), ("geom_condim", _i32p)]
+                ("jnt_range", _f64p), ("jnt_damping", _f64p), ("geom_condim", _i32p),
+                ("hfield_nrow", C.c_int32), ("hfield_ncol", C.c_int32), ("hfield_data", _f64p)]
 
 
 class _Info(C.Structure):
@@ -188,6 +189,10 @@ def marshal_desc(model: dict):
     d.jnt_range = f64([j.get("range", [0.0, 0.0]) for j in Jt] or [0.0, 0.0])
     d.jnt_damping = f64([j.get("damping", 0.0) for j in Jt] or [0.0])
     d.geom_condim = i32([g.get("condim", 3) for g in G] or [3])
+    hf = model.get("hfield")
+    if hf:
+        d.hfield_nrow, d.hfield_ncol = int(hf["nrow"]), int(hf["ncol"])
+        d.hfield_data = f64(hf["data"])
     return d, keep
 
 

@@ -199,7 +199,7 @@ def test_chain3_500_steps(oracle_mod):
 
 # ------------------------------------------------------------------ contact sets
 @pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain", "humanoid_terrain",
-                                  "quadruped_slip"])
+                                  "quadruped_slip", "quadruped_hfield"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -404,7 +404,7 @@ def test_run_twice_bitwise(oracle_mod):
 
 
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim", "quadruped_terrain",
-                                  "humanoid_terrain", "humanoid_damp"])
+                                  "humanoid_terrain", "humanoid_damp", "quadruped_hfield"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""

@@ -1,6 +1,6 @@
 """Write the workload models (chain3, quadruped, humanoid, arm_box and the joint-limited
 chain3_lim, quadruped_lim, humanoid_lim, the quadruped and humanoid on random-height grids of box tiles, the damped chain3_damp and
-humanoid_damp, and quadruped_slip with frictionless feet)
+humanoid_damp, quadruped_slip with frictionless feet, and quadruped_hfield on height-field terrain)
 as JSON files in the form rb_model_create_json reads.  The generators in workloads/robots.py are the source; the
 files are for callers that load a model without Python."""
 import json
@@ -13,7 +13,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from workloads import robots  # noqa: E402
 
 NAMES = ("chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim", "humanoid_lim",
-         "quadruped_terrain", "humanoid_terrain", "chain3_damp", "humanoid_damp", "quadruped_slip")
+         "quadruped_terrain", "humanoid_terrain", "chain3_damp", "humanoid_damp", "quadruped_slip", "quadruped_hfield")
 
 
 def main():

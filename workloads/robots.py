@@ -411,6 +411,30 @@ def quadruped_terrain(tile=0.4, n=3, max_height=0.04, seed=2601) -> dict:
     return m
 
 
+def quadruped_hfield(nrow=41, half=2.0, amp=0.03, seed=2603) -> dict:
+    """The quadruped on smooth height-field terrain instead of the plane: a 41 x 41 grid over
+    4 m x 4 m, heights a sum of three sinusoids of wavelength 0.6-1.5 m and random phase from a
+    fixed seed, scaled to +-``amp``, shifted to zero under the robot's start; feet and torso
+    collide with it (5 height-field pairs)."""
+    m = quadruped()
+    m["name"] = "quadruped_hfield"
+    rng = np.random.default_rng(seed)
+    xs = np.linspace(-half, half, nrow)
+    X, Y = np.meshgrid(xs, xs)          # rows along y, columns along x
+    H = np.zeros_like(X)
+    for _ in range(3):
+        lam = rng.uniform(0.6, 1.5)
+        th = rng.uniform(0, np.pi)
+        H += np.sin(2 * np.pi * (np.cos(th) * X + np.sin(th) * Y) / lam + rng.uniform(0, 2 * np.pi))
+    H *= amp / np.abs(H).max()
+    H -= H[nrow // 2, nrow // 2]
+    planes = [g for g in m["geoms"] if g["type"] == "plane"]
+    for g in planes:
+        g.update(type="hfield", size=[half, half, 0.0])
+    m["hfield"] = dict(nrow=nrow, ncol=nrow, data=[float(x) for x in H.ravel()])
+    return m
+
+
 LIMB_BODIES = ("hip_yaw", "knee", "shoulder_yaw", "elbow")   # thighs, shins, upper arms, forearms
 
 
@@ -501,7 +525,8 @@ def humanoid_lim() -> dict:
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
                 "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
-                "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp, "quadruped_slip": quadruped_slip}
+                "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp, "quadruped_slip": quadruped_slip,
+                "quadruped_hfield": quadruped_hfield}
 
 
 def by_name(name: str) -> dict:
