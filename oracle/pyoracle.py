@@ -9,6 +9,7 @@ import numpy as np
 from . import build as _build
 
 _GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3, "hfield": 4}
+_EQ = {"connect": 0, "weld": 1}
 _JNT = {"free": 0, "hinge": 1}
 _ACT = {"position": 0, "motor": 1}
 
@@ -32,7 +33,8 @@ class _Desc(C.Structure):
                 ("iterations", C.c_int32), ("tolerance", C.c_double), ("solref", C.c_double * 2),
                 ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32),
                 ("jnt_range", _f64p), ("jnt_damping", _f64p), ("geom_condim", _i32p),
-                ("hfield_nrow", C.c_int32), ("hfield_ncol", C.c_int32), ("hfield_data", _f64p)]
+                ("hfield_nrow", C.c_int32), ("hfield_ncol", C.c_int32), ("hfield_data", _f64p),
+                ("neq", C.c_int32), ("eq_type", _i32p), ("eq_body", _i32p), ("eq_anchor", _f64p), ("eq_target", _f64p)]
 
 
 class _Info(C.Structure):
@@ -172,6 +174,12 @@ class Oracle:
         if hf:
             d.hfield_nrow, d.hfield_ncol = int(hf["nrow"]), int(hf["ncol"])
             d.hfield_data = f64(hf["data"])
+        E = model.get("equality", [])
+        if E:
+            d.neq = len(E)
+            d.eq_type = i32([_EQ[e["type"]] for e in E]); d.eq_body = i32([e["body"] for e in E])
+            d.eq_anchor = f64([e["anchor"] for e in E])
+            d.eq_target = f64([list(e["target"]) + list(e.get("quat", [1.0, 0.0, 0.0, 0.0])) for e in E])
         h = C.c_void_p()
         _check(L.rbo_model_create(C.byref(d), C.byref(h)))
         self._h = h

@@ -77,6 +77,15 @@ inline void quat2mat(const double* q, double* R) {
     R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
     R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
 }
+// rotation vector (axis times angle, angle in [0, pi)) of a rotation matrix E: the angle from the
+// trace, the axis from the skew part E - E' = 2 sin(angle) [axis]x
+inline void rotvec(const double* E, double* th) {
+    double c = std::min(std::max((E[0] + E[4] + E[8] - 1) / 2, -1.0), 1.0);
+    double ang = std::acos(c);
+    double w[3] = {E[7] - E[5], E[2] - E[6], E[3] - E[1]};
+    double f = ang < 1e-6 ? 0.5 + ang * ang / 12 : ang / (2 * std::sin(ang));
+    for (int i = 0; i < 3; i++) th[i] = f * w[i];
+}
 inline void axisangle2quat(const double* u, double theta, double* q) {
     double s = std::sin(theta / 2);
     q[0] = std::cos(theta / 2); q[1] = s * u[0]; q[2] = s * u[1]; q[3] = s * u[2];
@@ -99,6 +108,9 @@ struct Model {
     std::vector<int> gtype, gbody, gcontype, gconaff, gcondim;
     int hf_nrow = 0, hf_ncol = 0;
     std::vector<double> hf;   // height grid [hf_nrow, hf_ncol]
+    int neq = 0;
+    std::vector<int> eqtype, eqbody;           // equality constraints: connect / weld, the moving body
+    std::vector<double> eqanchor, eqtarget;    // [neq, 3] anchor (body frame), [neq, 7] world point + quat
     std::vector<double> gpos, gquat, gsize, gfric, gmargin;
     std::vector<int> atype, ajoint;
     std::vector<double> akp, akd, agear;
@@ -143,7 +155,9 @@ struct Data {
     bool itercap = false;   // the Newton loop used every iteration without meeting a tolerance
     double cost = 0;
     // work record of the substep (for the work and operation-count outputs)
-    std::vector<int> row_id;        // per row: 4 c + e (pyramid row e of contact c), 256 + dof (limit)
+    std::vector<int> row_id;        // per row: 4 c + e (pyramid row e of contact c), 256 + dof (limit),
+                                    // 512 + 6 q + k (row k of equality q)
+    std::vector<char> bilat;        // per row: bilateral (equality rows: active on both sides)
     std::vector<int> row_nnz;       // per row: non-zero Jacobian entries (the dofs it touches)
     int segments = 0;               // quadratic pieces the line searches examined
     int active_final = 0;           // rows active at the solution
@@ -862,7 +876,10 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
         d.crow[ci] = nr;
         nr += d.con[ci].dim == 1 ? 1 : 4;
     }
-    d.nrows = nr + nl;
+    int ne = 0;
+    for (int q = 0; q < m.neq; q++) ne += m.eqtype[q] == RBO_EQ_WELD ? 6 : 3;
+    d.nrows = nr + nl + ne;
+    d.bilat.assign(d.nrows, 0);
     d.J.assign((size_t)d.nrows * nv, 0.0);
     d.row_id.assign(d.nrows, 0);
     d.row_nnz.assign(d.nrows, 0);
@@ -916,6 +933,37 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
         d.row_id[row] = 256 + ldof[l];
         finish_row(row, ldist[l]);
     }
+    // equality rows: the anchor's world offset from its target (x, y, z), then for a weld the
+    // rotation vector of R_body R_target' (x, y, z), each against the point or angular Jacobian
+    int row = nr + nl;
+    for (int q = 0; q < m.neq; q++) {
+        const int b = m.eqbody[q];
+        const double* R = &d.xmat[9 * b];
+        double c[3];
+        matvec3(R, &m.eqanchor[3 * q], c);
+        for (int i = 0; i < 3; i++) c[i] += d.xpos[3 * b + i];
+        jacobian(m, d, b, c, jp1.data(), jr1.data());
+        const double* tgt = &m.eqtarget[7 * q];
+        for (int k = 0; k < 3; k++, row++) {
+            std::copy(&jp1[k * nv], &jp1[k * nv] + nv, &d.J[(size_t)row * nv]);
+            d.row_id[row] = 512 + 6 * q + k;
+            d.bilat[row] = 1;
+            finish_row(row, c[k] - tgt[k]);
+        }
+        if (m.eqtype[q] != RBO_EQ_WELD) continue;
+        double Rt[9], E[9];
+        quat2mat(&tgt[3], Rt);
+        for (int i = 0; i < 3; i++)   // E = R Rt'
+            for (int j = 0; j < 3; j++) E[3 * i + j] = R[3 * i] * Rt[3 * j] + R[3 * i + 1] * Rt[3 * j + 1] + R[3 * i + 2] * Rt[3 * j + 2];
+        double th[3];
+        rotvec(E, th);
+        for (int k = 0; k < 3; k++, row++) {
+            std::copy(&jr1[k * nv], &jr1[k * nv] + nv, &d.J[(size_t)row * nv]);
+            d.row_id[row] = 512 + 6 * q + 3 + k;
+            d.bilat[row] = 1;
+            finish_row(row, th[k]);
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -929,7 +977,7 @@ double cost(const Model& m, const Data& d, const double* a) {
     for (int e = 0; e < d.nrows; e++) {
         double jar = -d.aref[e];
         for (int k = 0; k < nv; k++) jar += d.J[(size_t)e * nv + k] * a[k];
-        if (jar < 0) f += 0.5 * d.D[e] * jar * jar;
+        if (jar < 0 || d.bilat[e]) f += 0.5 * d.D[e] * jar * jar;
     }
     return f;
 }
@@ -954,14 +1002,14 @@ double line_search(const Model& m, const Data& d, const std::vector<double>& jar
     // breakpoints where a row switches on or off, in ascending order
     std::vector<std::pair<double, int>> bp;
     for (int e = 0; e < nr; e++)
-        if (s[e] != 0) {
+        if (s[e] != 0 && !d.bilat[e]) {
             double al = -jar[e] / s[e];
             if (al > 0) bp.push_back({al, e});
         }
     std::sort(bp.begin(), bp.end());
     // rows active just to the right of alpha = 0
     std::vector<char> act(nr);
-    for (int e = 0; e < nr; e++) act[e] = (jar[e] < 0) || (jar[e] == 0 && s[e] < 0);
+    for (int e = 0; e < nr; e++) act[e] = d.bilat[e] || (jar[e] < 0) || (jar[e] == 0 && s[e] < 0);
     size_t i = 0;
     while (true) {
         if (nseg) ++*nseg;
@@ -1014,7 +1062,7 @@ void newton(const Model& m, Data& d) {
         }
         H = d.M;
         for (int e = 0; e < nr; e++) {
-            if (!(jar[e] < 0)) continue;
+            if (!(jar[e] < 0) && !d.bilat[e]) continue;
             const double* Je = &d.J[(size_t)e * nv];
             for (int r = 0; r < nv; r++) {
                 g[r] += d.D[e] * jar[e] * Je[r];
@@ -1028,7 +1076,7 @@ void newton(const Model& m, Data& d) {
         std::vector<int> act;
         uint32_t fp = 0;
         for (int e = 0; e < nr; e++)
-            if (jar[e] < 0) {
+            if (jar[e] < 0 || d.bilat[e]) {
                 act.push_back(e);
                 fp += ((uint32_t)d.row_id[e] + 1u) * 2654435761u;
             }
@@ -1052,8 +1100,8 @@ void newton(const Model& m, Data& d) {
     for (int e = 0; e < nr; e++) {
         double t = -d.aref[e];
         for (int k = 0; k < nv; k++) t += d.J[(size_t)e * nv + k] * d.a[k];
-        d.efc_force[e] = -d.D[e] * std::min(t, 0.0);
-        d.active_final += t < 0;
+        d.efc_force[e] = -d.D[e] * (d.bilat[e] ? t : std::min(t, 0.0));
+        d.active_final += t < 0 || d.bilat[e];
     }
 }
 
@@ -1416,6 +1464,24 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
         for (double h : M.hf)
             if (!std::isfinite(h)) return bad("height field heights must be finite");
     }
+    M.neq = dsc->neq;
+    if (M.neq < 0 || (M.neq > 0 && (!dsc->eq_type || !dsc->eq_body || !dsc->eq_anchor || !dsc->eq_target)))
+        return bad("equality constraints missing");
+    for (int q = 0; q < M.neq; q++) {
+        const int t = dsc->eq_type[q], b = dsc->eq_body[q];
+        if (t != RBO_EQ_CONNECT && t != RBO_EQ_WELD) return bad("unknown equality type");
+        if (b <= 0 || b >= nb || !M.movable[b]) return bad("an equality constraint needs a moving body");
+        const double* tq = dsc->eq_target + 7 * q + 3;
+        if (t == RBO_EQ_WELD && std::fabs(std::sqrt(tq[0] * tq[0] + tq[1] * tq[1] + tq[2] * tq[2] + tq[3] * tq[3]) - 1) > 1e-6)
+            return bad("weld target quaternion not unit");
+        for (int i = 0; i < 10; i++)
+            if (!std::isfinite(i < 3 ? dsc->eq_anchor[3 * q + i] : dsc->eq_target[7 * q + i - 3]))
+                return bad("equality constraint values must be finite");
+    }
+    M.eqtype.assign(dsc->eq_type, dsc->eq_type + M.neq);
+    M.eqbody.assign(dsc->eq_body, dsc->eq_body + M.neq);
+    M.eqanchor.assign(dsc->eq_anchor, dsc->eq_anchor + 3 * M.neq);
+    M.eqtarget.assign(dsc->eq_target, dsc->eq_target + 7 * M.neq);
     M.maxcon = 0; M.npair = 0;
     for (int a = 0; a < ng; a++)
         for (int b = a + 1; b < ng; b++) {
@@ -1472,7 +1538,9 @@ int rbo_model_info(const void* mp, rbo_info* out) {
     if (!mp || !out) return fail("null argument");
     const Model& m = *static_cast<const Model*>(mp);
     out->nq = m.nq; out->nv = m.nv; out->nu = m.nu; out->nbody = m.nbody; out->ngeom = m.ngeom;
-    out->maxcon = m.maxcon; out->maxrows = 4 * m.maxcon + m.nlim; out->npair = m.npair;
+    int neqrows = 0;
+    for (int q = 0; q < m.neq; q++) neqrows += m.eqtype[q] == RBO_EQ_WELD ? 6 : 3;
+    out->maxcon = m.maxcon; out->maxrows = 4 * m.maxcon + m.nlim + neqrows; out->npair = m.npair;
     out->meaninertia = m.meaninertia;
     return 0;
 }

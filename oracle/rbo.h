@@ -29,6 +29,7 @@ extern "C" {
 enum { RBO_GEOM_PLANE = 0, RBO_GEOM_SPHERE = 1, RBO_GEOM_CAPSULE = 2, RBO_GEOM_BOX = 3, RBO_GEOM_HFIELD = 4 };
 enum { RBO_JNT_FREE = 0, RBO_JNT_HINGE = 1 };
 enum { RBO_ACT_POSITION = 0, RBO_ACT_MOTOR = 1 };
+enum { RBO_EQ_CONNECT = 0, RBO_EQ_WELD = 1 };
 
 typedef struct rbo_desc {
     int32_t nbody, njnt, ngeom, nu;
@@ -71,6 +72,16 @@ typedef struct rbo_desc {
        0 rows when the model has no height field. */
     int32_t hfield_nrow, hfield_ncol;
     const double* hfield_data;
+    /* equality constraints [neq] between a moving body and the world: eq_type 0 = connect (the
+       point eq_anchor [neq, 3] of body eq_body, in its frame, held at the world point
+       eq_target[0..3)), 1 = weld (that, and the body's orientation held at the unit quaternion
+       eq_target[3..7)); eq_target [neq, 7].  Each gives 3 (connect) or 6 (weld) bilateral soft
+       rows after the contact and limit rows: world x, y, z components of the anchor's offset
+       from the target, then of the rotation vector of R_body R_target', each with its own
+       impedance, the contacts' solref / solimp and exact A-hat. */
+    int32_t neq;
+    const int32_t *eq_type, *eq_body;
+    const double *eq_anchor, *eq_target;
 } rbo_desc;
 
 typedef struct rbo_info {
@@ -101,7 +112,7 @@ typedef struct rbo_taps {
     double *qacc, *cforce;                      /* [nv] [maxcon,3] */
     int32_t* niter;                             /* [1] Newton iterations run */
     double* cost;                               /* [1] final cost f(qacc) */
-    int32_t* nrows;                             /* [1] constraint rows: 4 per contact, then limits */
+    int32_t* nrows;                             /* [1] constraint rows: 4 per contact, limits, equalities */
 } rbo_taps;
 
 /* Work outputs of rbo_step_work.
@@ -112,7 +123,8 @@ typedef struct rbo_taps {
  *   5 .. 5 + RBO_FPITER - 1: fingerprint of the active set each of the first RBO_FPITER Newton
  *   updates was built from (0 past the last update).  The fingerprint of a set A of rows is
  *   sum over e in A of (id_e + 1) * 2654435761 mod 2^32, with id = 4 c + e for pyramid row e of
- *   contact c (a frictionless contact's one row has e = 0) and 256 + dof for a joint-limit row.
+ *   contact c (a frictionless contact's one row has e = 0), 256 + dof for a joint-limit row and
+ *   512 + 6 q + k for row k of equality q (bilateral rows are always active).
  *
  * Per world, 2 x RBO_NSTAGE doubles ([n, 2, RBO_NSTAGE]), summed over the K substeps: arithmetic
  * operations (a multiply-add counts 2) of the stages kinematics, inertia and bias forces,

@@ -106,6 +106,7 @@ class ModelBuilder:
         self.actuators: list[dict] = []
         self.per_world = {"friction": False, "mass_scale": False}
         self.hfield_grid = None
+        self.equalities: list[dict] = []
 
     def body(self, name, parent, pos, mass, inertia, ipos=(0, 0, 0), iquat=(1, 0, 0, 0), quat=(1, 0, 0, 0)) -> int:
         pid = parent if isinstance(parent, int) else self.body_id(parent)
@@ -160,6 +161,17 @@ class ModelBuilder:
         h = np.asarray(heights, float)
         self.hfield_grid = dict(nrow=int(h.shape[0]), ncol=int(h.shape[1]), data=[float(x) for x in h.ravel()])
 
+    def equality(self, type_, body, anchor, target, quat=None) -> int:
+        """An equality constraint of a moving body with the world: "connect" holds the body point
+        ``anchor`` (body frame) at the world point ``target``; "weld" also holds the body's
+        orientation at the unit quaternion ``quat``."""
+        bid = body if isinstance(body, int) else self.body_id(body)
+        e = dict(type=type_, body=bid, anchor=list(map(float, anchor)), target=list(map(float, target)))
+        if type_ == "weld":
+            e["quat"] = list(map(float, quat if quat is not None else (1, 0, 0, 0)))
+        self.equalities.append(e)
+        return len(self.equalities) - 1
+
     def actuator(self, joint, type_="position", kp=0.0, kd=0.0, gear=1.0) -> int:
         self.actuators.append(dict(type=type_, joint=int(joint), kp=float(kp), kd=float(kd), gear=float(gear)))
         return len(self.actuators) - 1
@@ -170,6 +182,8 @@ class ModelBuilder:
                  actuators=copy.deepcopy(self.actuators), per_world=dict(self.per_world))
         if self.hfield_grid is not None:
             m["hfield"] = copy.deepcopy(self.hfield_grid)
+        if self.equalities:
+            m["equality"] = copy.deepcopy(self.equalities)
         return m
 
 
