@@ -1608,7 +1608,8 @@ int rbo_step_fields(const void* mp, int32_t n, const double* ctrl, double* qpos,
     if (m0.nu && !ctrl) return fail("ctrl required");
     const bool expanded = fields && (fields->geom_size || fields->body_pos || fields->act_kp || fields->act_kd);
 #ifdef _OPENMP
-    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+    // no more threads than chunks of worlds: a one-world call runs on the calling thread
+    int nt = std::max(1, std::min(nthreads > 0 ? nthreads : omp_get_max_threads(), (n + 3) / 4));
 #pragma omp parallel num_threads(nt)
 #endif
     {
