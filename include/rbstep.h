@@ -49,6 +49,7 @@ extern "C" {
 enum { RB_GEOM_PLANE = 0, RB_GEOM_SPHERE = 1, RB_GEOM_CAPSULE = 2, RB_GEOM_BOX = 3, RB_GEOM_HFIELD = 4 };
 enum { RB_JNT_FREE = 0, RB_JNT_HINGE = 1 };
 enum { RB_ACT_POSITION = 0, RB_ACT_MOTOR = 1 };
+enum { RB_EQ_CONNECT = 0, RB_EQ_WELD = 1 };
 enum {
     RB_PARAM_FRICTION = 0,   /* [n]: friction of every contact of the world (model flag) */
     RB_PARAM_MASS_SCALE = 1, /* [n, nbody]: body mass and rotational inertia scale (model flag) */
@@ -105,6 +106,17 @@ typedef struct rb_model_desc {
      * "Components", paragraph "Terrain" (height-field terrains). */
     int32_t hfield_nrow, hfield_ncol;
     const double* hfield_data;
+    /* equality constraints [neq] between a moving body and the world (0 and NULLs for none; the
+     * rows of all of them together at most 64): eq_type RB_EQ_CONNECT holds the body point
+     * eq_anchor [neq, 3] (body frame) at the world point eq_target[0..2] ([neq, 7]); RB_EQ_WELD
+     * also holds the body's orientation at the unit quaternion eq_target[3..6].  Each gives soft
+     * bilateral rows (connect 3: the anchor's world offset from its target along x, y, z; weld 3
+     * more: the rotation vector of R_body R_target') solved with the contacts, always active,
+     * with the contacts' solref/solimp.  Cites: paper, section "Architecture", paragraph on the
+     * GPU physics backend (the constraint model of the simulator it builds on). */
+    int32_t neq;
+    const int32_t *eq_type, *eq_body;
+    const double *eq_anchor, *eq_target;
 } rb_model_desc;
 
 typedef struct rb_model rb_model;
@@ -164,7 +176,9 @@ int rb_model_create(const rb_model_desc* desc, rb_model** out);
  *              "condim" (optional, 1 or 3)}, ...],
  *   "actuators": [{"type": "position" | "motor", "joint", "kp", "kd", "gear"}, ...],
  *   "per_world": {"friction": bool, "mass_scale": bool}   (optional, default false),
- *   "hfield": {"nrow", "ncol", "data": [nrow * ncol]}    (required with hfield geoms);
+ *   "hfield": {"nrow", "ncol", "data": [nrow * ncol]}    (required with hfield geoms),
+ *   "equality": [{"type": "connect" | "weld", "body", "anchor": [3], "target": [3],
+ *                 "quat": [4] (welds only)}, ...]   (optional);
  * other keys are ignored.  Each entry maps to the rb_model_desc field of the same name, in
  * list order.  Malformed JSON or a missing or mistyped field is RB_EINVAL (with the field
  * named in rb_last_error) before any device call; the parsed description then goes through

@@ -11,11 +11,13 @@
 //             "size": [3], "friction", "contype", "conaffinity", "margin", "condim" (optional)}, ...],
 //  "actuators": [{"type": "position"|"motor", "joint", "kp", "kd", "gear"}, ...],
 //  "per_world": {"friction": bool, "mass_scale": bool},      optional, default false
-//  "hfield": {"nrow", "ncol", "data": [nrow * ncol]}}        required with hfield geoms
+//  "hfield": {"nrow", "ncol", "data": [nrow * ncol]},         required with hfield geoms
+//  "equality": [{"type": "connect"|"weld", "body", "anchor": [3], "target": [3],
+//                "quat": [4] (welds)}, ...]}                  optional
 //
 // Other keys (names, comments) are ignored.  Every listed field is required except a joint's
-// range and damping, a geom's condim and per_world; a missing or mistyped field is RB_EINVAL with
-// the field named.
+// range and damping, a geom's condim, per_world, hfield and equality; a missing or mistyped
+// field is RB_EINVAL with the field named.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -297,6 +299,29 @@ int rb_model_create_json(const char* json, rb_model** out) {
         d.hfield_nrow = (int32_t)nr;
         d.hfield_ncol = (int32_t)nc;
         d.hfield_data = hfdata.data();
+    }
+    std::vector<int32_t> etype, ebody;
+    std::vector<double> eanchor, etarget;
+    auto eq = root.obj.find("equality");
+    if (eq != root.obj.end()) {
+        if (eq->second.kind != JVal::ARR) return rb_record_error(RB_EINVAL, "model JSON: \"equality\" is not an array");
+        static const char* const enames[] = {"connect", "weld"};
+        const int ne = (int)eq->second.arr.size();
+        etype.assign(ne, 0); ebody.assign(ne, 0); eanchor.assign(3 * ne, 0.0); etarget.assign(7 * ne, 0.0);
+        for (int q = 0; q < ne && ok; q++) {
+            const JVal& o = eq->second.arr[q];
+            const std::string w = "equality " + std::to_string(q);
+            ok = R.choice(o, "type", w, enames, 2, &etype[q]) && R.integer(o, "body", w, &ebody[q]) &&
+                 R.vec(o, "anchor", w, 3, &eanchor[3 * q]) && R.vec(o, "target", w, 3, &etarget[7 * q]);
+            etarget[7 * q + 3] = 1.0;
+            if (ok && etype[q] == RB_EQ_WELD) ok = R.vec(o, "quat", w, 4, &etarget[7 * q + 3]);
+        }
+        if (!ok) return rb_record_error(RB_EINVAL, ("model JSON: " + R.err).c_str());
+        d.neq = ne;
+        if (ne > 0) {
+            d.eq_type = etype.data(); d.eq_body = ebody.data();
+            d.eq_anchor = eanchor.data(); d.eq_target = etarget.data();
+        }
     }
     d.nbody = nb; d.njnt = nj; d.ngeom = ng; d.nu = nu;
     d.body_parent = bpar.data(); d.body_pos = bpos.data(); d.body_quat = bquat.data();

@@ -21,6 +21,8 @@
 #define RB_PAIR_CAPSULEBOX 18     // pair_type of a capsule (g1) - box (g2) pair: its two end spheres
 #define RB_PAIR_HFIELD 32         // pair_type of a height field (g1) - geom (g2) pair: this + g2's geom type
 #define RB_BB_FLOATS 96           // LDS floats per box-box pair: clip buffers, contacts, normal
+#define RB_MAX_EQROW 64           // equality-constraint rows (one lane each; extended code only)
+#define RB_EQF 10                 // LDS floats per equality row: psi[6], D, residual, direction, body
 
 struct DevModel {
     // sizes
@@ -81,7 +83,8 @@ struct DevModel {
     int nlim;                  // limited hinges
     const float* dof_damping;  // hinge damping (0 when undamped)
     int ndamp;                 // damped hinges
-    int ext;                   // needs the extended code: box-box or sphere-box pairs, joint limits, damping
+    int ext;                   // needs the extended code: box-box or sphere-box pairs, joint limits, damping,
+                               // equality constraints
     const int* act_start;      // [nv + 1] CSR of actuators driving each dof
     const int* act_list;
     const int* act_type;
@@ -111,11 +114,19 @@ struct DevModel {
     const float* geom_size;    // [3]
     const float* hf_data;      // height grid [hf_nrow, hf_ncol] of the height-field geoms (or null)
     int hf_nrow, hf_ncol;
+    // equality constraints with the world [neq]; their rows [neqrow] (connect 3, weld 6)
+    int neq, neqrow;
+    const int* eq_body;
+    const float* eq_anchor;    // [3] body frame
+    const float* eq_tpos;      // [3] world target point
+    const float* eq_tmat;      // [9] world target orientation (welds)
+    const int* eqrow_eq;       // the row's constraint
+    const int* eqrow_k;        // 0..2 translational axis, 3..5 rotational axis
     // LDS layout (offsets in floats from the world's base)
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
     int o_xpos, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
     int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp, o_lD, o_ljar;
-    int o_M, o_H, o_piv, o_rowadr, o_bb;
+    int o_M, o_H, o_piv, o_rowadr, o_bb, o_eq;
     int lds_floats;
 };
 

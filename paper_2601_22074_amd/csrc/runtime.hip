@@ -138,6 +138,8 @@ void layout_tail(DevModel& m, int kernel_maxd) {
     o += r4(m.nv);
     m.o_bb = o;
     o += r4(RB_BB_FLOATS * m.nbb);
+    m.o_eq = o;
+    o += r4(RB_EQF * m.neqrow);
     m.lds_floats = o;
 }
 
@@ -551,6 +553,36 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             limhi[jd[j]] = d->jnt_range[2 * j + 1];
             nlim++;
         }
+    // equality constraints: per constraint body, anchor, target point and orientation; per row
+    // its constraint and axis (k < 3 translational, 3..5 rotational)
+    if (d->neq < 0 || (d->neq > 0 && (!d->eq_type || !d->eq_body || !d->eq_anchor || !d->eq_target)))
+        return fail(RB_EINVAL, "equality constraints missing");
+    std::vector<int> eqb, eqr_q, eqr_k;
+    std::vector<double> eqa, eqp, eqm;
+    for (int q = 0; q < d->neq; q++) {
+        const int t = d->eq_type[q], b = d->eq_body[q];
+        if (t != RB_EQ_CONNECT && t != RB_EQ_WELD) return fail(RB_EINVAL, "unknown equality type");
+        if (b <= 0 || b >= nb || !movable[b]) return fail(RB_EINVAL, "an equality constraint needs a moving body");
+        if (!finite(d->eq_anchor + 3 * q, 3) || !finite(d->eq_target + 7 * q, 7))
+            return fail(RB_EINVAL, "equality constraint values must be finite");
+        const double* tq = d->eq_target + 7 * q + 3;
+        const double qn = std::sqrt(tq[0] * tq[0] + tq[1] * tq[1] + tq[2] * tq[2] + tq[3] * tq[3]);
+        if (t == RB_EQ_WELD && std::fabs(qn - 1) > 1e-6) return fail(RB_EINVAL, "weld target quaternion is not unit");
+        eqb.push_back(b);
+        for (int i = 0; i < 3; i++) {
+            eqa.push_back(d->eq_anchor[3 * q + i]);
+            eqp.push_back(d->eq_target[7 * q + i]);
+        }
+        double Rt[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        if (t == RB_EQ_WELD) qmat_d(tq, Rt);
+        eqm.insert(eqm.end(), Rt, Rt + 9);
+        for (int k = 0; k < (t == RB_EQ_WELD ? 6 : 3); k++) {
+            eqr_q.push_back(q);
+            eqr_k.push_back(k);
+        }
+    }
+    const int neqrow = (int)eqr_q.size();
+    if (neqrow > RB_MAX_EQROW) return fail(RB_EINVAL, "more than 64 equality-constraint rows");
     // ---- upload
     Blob B;
     DevModel& m = M->dm;
@@ -588,6 +620,10 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     F(std::vector<double>(d->geom_pos, d->geom_pos + 3 * ng), &m.geom_pos);
     F(std::vector<double>(d->geom_quat, d->geom_quat + 4 * ng), &m.geom_quat);
     F(std::vector<double>(d->geom_size, d->geom_size + 3 * ng), &m.geom_size);
+    if (neqrow > 0) {
+        I(eqb, &m.eq_body); F(eqa, &m.eq_anchor); F(eqp, &m.eq_tpos); F(eqm, &m.eq_tmat);
+        I(eqr_q, &m.eqrow_eq); I(eqr_k, &m.eqrow_k);
+    }
     const bool has_hf = std::count(d->geom_type, d->geom_type + ng, RB_GEOM_HFIELD) > 0;
     if (has_hf) {
         F(std::vector<double>(d->hfield_data, d->hfield_data + (size_t)d->hfield_nrow * d->hfield_ncol), &m.hf_data);
@@ -613,7 +649,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.nlim = nlim;
     m.ndamp = ndamp;
-    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE ||
+    m.neq = d->neq; m.neqrow = neqrow;
+    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE || neqrow > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_CAPSULEBOX) > 0 ||
              std::count_if(ptype.begin(), ptype.end(), [](int t) { return t >= RB_PAIR_HFIELD; }) > 0 ||

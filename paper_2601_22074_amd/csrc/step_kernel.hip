@@ -1367,6 +1367,85 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         }
         }
 
+        // ---- equality constraints with the world (extended code): lane r < neqrow builds row r.
+        // A row is a spatial force direction psi at O on its body's chain: translational row k of
+        // a connect or weld is the unit axis e_k applied at the anchor's world point c,
+        // psi = (r x e_k, e_k) with r = c - O, against the offset c_k - target_k; rotational row
+        // k is e_k as a pure torque, psi = (e_k, 0), against component k of the rotation vector of
+        // E = R_body R_target'.  LDS keeps psi, D, the residual J a - aref (aref until the Newton
+        // start), the line-search direction J p and the body.  Bilateral: always active.
+        float* EQ = L + m.o_eq;
+        const bool eqact = EXT && m.neqrow > 0;
+        if (eqact) {
+            const bool own = lane < m.neqrow;
+            const int qe = own ? m.eqrow_eq[lane] : 0;
+            const int k = own ? m.eqrow_k[lane] : 0;
+            const int body = own ? m.eq_body[qe] : 0;
+            float psi[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float rdist = 0.f;
+            if (own) {
+                const float* Rb = xmat + 9 * body;
+                float c[3];
+                mv(Rb, m.eq_anchor + 3 * qe, c);
+                for (int i = 0; i < 3; i++) c[i] += xpos[3 * body + i];
+                if (k < 3) {
+                    const float r[3] = {c[0] - O[0], c[1] - O[1], c[2] - O[2]};
+                    const float e[3] = {k == 0 ? 1.f : 0.f, k == 1 ? 1.f : 0.f, k == 2 ? 1.f : 0.f};
+                    cross(r, e, psi);
+                    psi[3 + k] = 1.f;
+                    rdist = c[k] - m.eq_tpos[3 * qe + k];
+                } else {
+                    // E = R_b R_t'; rotation vector = angle * axis from the skew part
+                    // E - E' = 2 sin(angle) [axis]x and the trace, the angle by atan2 (well
+                    // conditioned at small angles, where acos of the trace is not in FP32)
+                    const float* Rt = m.eq_tmat + 9 * qe;
+                    float E[9];
+                    for (int i = 0; i < 3; i++)
+                        for (int j = 0; j < 3; j++)
+                            E[3 * i + j] = Rb[3 * i] * Rt[3 * j] + Rb[3 * i + 1] * Rt[3 * j + 1] + Rb[3 * i + 2] * Rt[3 * j + 2];
+                    const float wv[3] = {E[7] - E[5], E[2] - E[6], E[3] - E[1]};
+                    const float s2 = sqrtf(dot(wv, wv));          // 2 sin(angle)
+                    const float ang = atan2f(0.5f * s2, 0.5f * (E[0] + E[4] + E[8] - 1.f));
+                    const float f = s2 > 1e-4f ? ang / s2 : 0.5f + ang * ang * (1.f / 12.f);
+                    psi[k - 3] = 1.f;
+                    rdist = f * pick3(wv, k - 3);
+                }
+            }
+            // A-hat = J M^-1 J' from Y = L'^-1 J' on the body's chain, as for a contact row
+            const int d = __shfl(BL.depth, body);
+            const int csrc = __shfl(BL.src, body);
+            uint32_t cw[MAXD / 4];
+#pragma unroll
+            for (int w2 = 0; w2 < MAXD / 4; w2++) cw[w2] = (uint32_t)__shfl((int)DL.anc[w2], csrc);
+            auto eq_anc = [&](int t) { return (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu); };
+            if (own) {
+                float Y[MAXD];
+#pragma unroll
+                for (int t = 0; t < MAXD; t++) Y[t] = t < d ? sdot(cdof + 6 * eq_anc(t), psi) : 0.f;
+#pragma unroll
+                for (int tp = MAXD - 1; tp >= 1; tp--) {
+                    if (tp < d) {
+                        const int row = rowadr_l[eq_anc(tp)];
+#pragma unroll
+                        for (int t = 0; t < tp; t++) Y[t] -= H[row + t] * Y[tp];
+                    }
+                }
+                float Ah = 0.f;
+#pragma unroll
+                for (int t = 0; t < MAXD; t++)
+                    if (t < d) Ah += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[rowadr_l[eq_anc(t)] + t]);
+                const float jvel = sdot(cvel + 6 * body, psi);
+                const float imp = impedance(m, rdist);
+                float* Er = EQ + RB_EQF * lane;
+                for (int c6 = 0; c6 < 6; c6++) Er[c6] = psi[c6];
+                Er[6] = 1.0f / fmaxf(1e-15f, (1.0f - imp) / imp * Ah);
+                Er[7] = -m.bref * jvel - m.kref * imp * rdist;
+                Er[8] = 0.f;
+                Er[9] = __int_as_float(body);
+            }
+            wave_sync();   // xmat's space is reused by the limit rows and the Newton vectors
+        }
+
         // ---- joint limits: a hinge outside its range gets one row J = s e_i (s = +1 below the
         // lower bound, -1 above the upper one), held in LDS by the dof's lane: lD = s D (0 when
         // the hinge is inside its range) and ljar, the residual J a - aref (-aref until the
@@ -1416,7 +1495,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         RB_STAGE(4);
         // ---- primal Newton solve
         bool itercap = false;
-        if (ncon == 0 && !limact) {
+        if (ncon == 0 && !limact && !eqact) {
             for (int i = lane; i < nv; i += RB_WAVE) acc[i] = a0[i];
             wave_sync();
         } else {
@@ -1444,6 +1523,14 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 const float mn = fminf(lim_res(false), 0.f);
                 f0 += 0.5f * fabsf(lD[lane]) * mn * mn;
             }
+            // equality rows at a0 (bilateral: the whole residual counts)
+            const bool eqown = eqact && lane < m.neqrow;
+            float* Er = EQ + RB_EQF * (eqown ? lane : 0);
+            float ej0 = 0.f;
+            if (eqown) {
+                ej0 = sdot(bvec + 6 * __float_as_int(Er[9]), Er) - Er[7];
+                f0 += 0.5f * Er[6] * ej0 * ej0;
+            }
             f0 = wsum(f0);
             for (int i = lane; i < nv; i += RB_WAVE) tmp[i] = aws[i] - a0[i];
             wave_sync();
@@ -1467,9 +1554,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 const float mn = fminf(lim_res(true), 0.f);
                 fw += 0.5f * fabsf(lD[lane]) * mn * mn;
             }
+            float ejw = 0.f;
+            if (eqown) {
+                ejw = ej0 + sdot(bvec + 6 * __float_as_int(Er[9]), Er);
+                fw += 0.5f * Er[6] * ejw * ejw;
+            }
             fw = wsum(fw) + 0.5f * wsum(qf);
             bool use_ws = fw < f0;
             if (limact && lane < nv) ljar[lane] = lim_res(use_ws);
+            if (eqown) Er[7] = use_ws ? ejw : ej0;
             float fcur = use_ws ? fw : f0;
             for (int i = lane; i < nv; i += RB_WAVE) {
                 acc[i] = use_ws ? aws[i] : a0[i];
@@ -1541,6 +1634,22 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         }
                     }
                 }
+                // equality rows: every row is active; psi, D and the residual from LDS
+                if (eqact) {
+                    for (int rr = 0; rr < m.neqrow; rr++) {
+                        const float* Eo = EQ + RB_EQF * rr;
+                        const int body = __builtin_amdgcn_readfirstlane(__float_as_int(Eo[9]));
+                        const uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)BL.chainmask, body);
+                        const uint32_t mhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(BL.chainmask >> 32), body);
+                        const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
+                        if (dof_lane && ((mask >> lane) & 1ull)) {
+                            const float Dj = Eo[6] * sdot(S, Eo);
+                            gc += Dj * Eo[7];
+#pragma unroll
+                            for (int c6 = 0; c6 < 6; c6++) F[c6] += Dj * Eo[c6];
+                        }
+                    }
+                }
                 float gi = 0.f;
                 if (dof_lane) {
                     gi = Ma[lane] - (tau[lane] - bias[lane]) + gc;
@@ -1565,6 +1674,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     }
                     if (limact && dof_lane && lD[lane] != 0.f && ljar[lane] < 0.f)
                         fpl += (uint32_t)(256 + lane + 1) * 2654435761u;
+                    // equality row k of constraint q: 512 + 6 q + k, always active
+                    if (eqown) fpl += (uint32_t)(512 + 6 * m.eqrow_eq[lane] + m.eqrow_k[lane] + 1) * 2654435761u;
                     fpl = wsum_u32(fpl);
                     if (lane == 0) SUBREC[RB_SUBSTAT * sub + 5 + it] = (int32_t)fpl;
                 }
@@ -1601,6 +1712,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 if (dof_lane) {
                     pa = p[lane] * Mp[lane];
                     pb = p[lane] * (Ma[lane] - (tau[lane] - bias[lane]));
+                }
+                if (eqown) {
+                    // the equality rows are quadratic along p: constant terms of every segment
+                    const float sre = sdot(bvec + 6 * __float_as_int(Er[9]), Er);
+                    Er[8] = sre;
+                    pa += Er[6] * sre * sre;
+                    pb += Er[6] * sre * Er[7];
                 }
                 float A0 = wsum(pa), B0 = wsum(pb);
                 float alpha = 0.f;
@@ -1675,6 +1793,11 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     const float mn = fminf(lj, 0.f);
                     fc += 0.5f * fabsf(lD[lane]) * mn * mn;
                 }
+                if (eqown) {
+                    const float ej = Er[7] + alpha * Er[8];
+                    Er[7] = ej;
+                    fc += 0.5f * Er[6] * ej * ej;
+                }
                 float fnew = 0.5f * wsum(qf2) + wsum(fc);
                 wave_sync();
                 float improvement = fcur - fnew;
@@ -1693,6 +1816,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f && (e == 0 || !fl);
                 if (limact && lane < nv && lD[lane] != 0.f) {
                     act += ljar[lane] < 0.f;
+                    nrow += 1;
+                }
+                if (eqown) {
+                    act += 1;
                     nrow += 1;
                 }
                 const int actw = (int)wsum_u32((uint32_t)act);
@@ -1749,7 +1876,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 #pragma unroll
             for (int t = 0; t < MAXD; t++)
                 if (t == DL.depth - 1) Hr[t] += bd;
-            const bool solved = ncon > 0 || limact;
+            const bool solved = ncon > 0 || limact || eqact;
             const float rhs = lane < nv ? (solved ? Ma[lane] : tau[lane] - bias[lane]) : 0.f;
             float invd;
             const float x = factor_solve<MAXD>(m, DL, Hr, rhs, lane, piv, &invd);

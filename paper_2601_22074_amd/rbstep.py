@@ -27,6 +27,7 @@ STAGES = ["kinematics", "inertia+bias+M", "factor M + a0", "collision", "constra
           "gradient+hessian", "hessian factor+solve", "line search+update", "integrate"]
 
 _GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3, "hfield": 4}
+_EQTYPE = {"connect": 0, "weld": 1}
 _JNT = {"free": 0, "hinge": 1}
 _ACT = {"position": 0, "motor": 1}
 
@@ -64,7 +65,9 @@ class _Desc(C.Structure):
                 ("iterations", C.c_int32), ("tolerance", C.c_double), ("solref", C.c_double * 2),
                 ("solimp", C.c_double * 5), ("friction_per_world", C.c_int32), ("mass_scale_per_world", C.c_int32),
                 ("jnt_range", _f64p), ("jnt_damping", _f64p), ("geom_condim", _i32p),
-                ("hfield_nrow", C.c_int32), ("hfield_ncol", C.c_int32), ("hfield_data", _f64p)]
+                ("hfield_nrow", C.c_int32), ("hfield_ncol", C.c_int32), ("hfield_data", _f64p),
+                ("neq", C.c_int32), ("eq_type", _i32p), ("eq_body", _i32p), ("eq_anchor", _f64p),
+                ("eq_target", _f64p)]
 
 
 class _Info(C.Structure):
@@ -193,6 +196,14 @@ def marshal_desc(model: dict):
     if hf:
         d.hfield_nrow, d.hfield_ncol = int(hf["nrow"]), int(hf["ncol"])
         d.hfield_data = f64(hf["data"])
+    eqs = model.get("equality") or []
+    if eqs:
+        # target: the world point, then the orientation quaternion (identity for a connect)
+        d.neq = len(eqs)
+        d.eq_type = i32([_EQTYPE[e["type"]] for e in eqs])
+        d.eq_body = i32([e["body"] for e in eqs])
+        d.eq_anchor = f64([e["anchor"] for e in eqs])
+        d.eq_target = f64([[*e["target"], *(e["quat"] if e["type"] == "weld" else (1.0, 0.0, 0.0, 0.0))] for e in eqs])
     return d, keep
 
 

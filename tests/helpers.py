@@ -104,3 +104,21 @@ def lever_rest_angle(l, mass, r, g=9.81, solref=(0.02, 1.0), dmax=0.95):
         mid = 0.5 * (lo + hi)
         lo, hi = (mid, hi) if resid(mid) < 0 else (lo, mid)
     return lo
+
+
+def soft_sag(mass, g=9.81, ahat=None, tc=0.02, dmax=0.95):
+    """Closed-form sag r < 0 of a bilateral row holding a weight m g at rest: the row's force
+    -D jar, jar = k imp(r) r, balances m g with D = imp / ((1 - imp) A-hat) and A-hat = 1/m for a
+    point held at its body's centre of mass; solved by bisection."""
+    k = 1.0 / (dmax * dmax * tc * tc)
+    A = ahat if ahat is not None else 1.0 / mass
+
+    def resid(d):
+        imp = impedance(-d)
+        return imp * imp * k * d / ((1 - imp) * A) - mass * g
+
+    lo, hi = 0.0, 0.1
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if resid(mid) < 0 else (lo, mid)
+    return -lo

@@ -6,7 +6,7 @@ import math
 
 import numpy as np
 
-from helpers import impedance, rot
+from helpers import rot, soft_sag
 from workloads import robots
 
 DT = 0.002
@@ -58,23 +58,6 @@ def test_weld_rows_add_the_angular_velocity(oracle_mod):
     np.testing.assert_allclose(t["J"][3:] @ v, rot(qq) @ v[3:], atol=1e-12)
 
 
-def _sag(mass, g=9.81, Ahat=None, tc=0.02, dmax=0.95):
-    """Closed-form soft sag r < 0 of a bilateral row holding a weight m g at rest: the row's
-    force -D jar with jar = k imp r balances m g, D = imp / ((1 - imp) A-hat); by bisection."""
-    k = 1.0 / (dmax * dmax * tc * tc)
-    A = Ahat if Ahat is not None else 1.0 / mass
-
-    def resid(d):
-        imp = impedance(-d)
-        return imp * imp * k * d / ((1 - imp) * A) - mass * g
-
-    lo, hi = 0.0, 0.1
-    for _ in range(200):
-        mid = 0.5 * (lo + hi)
-        lo, hi = (mid, hi) if resid(mid) < 0 else (lo, mid)
-    return -lo
-
-
 def test_connect_at_the_centre_of_mass_sags_by_the_closed_form(oracle_mod):
     """A ball connected at its centre to a world point settles below it by the soft sag, the
     three rows' forces summing to (0, 0, m g)."""
@@ -82,7 +65,7 @@ def test_connect_at_the_centre_of_mass_sags_by_the_closed_form(oracle_mod):
     m = _hanging("connect", mass=mass)
     o, q, v, ws = _settle(oracle_mod, m, [0.0, 0.0, 1.0, 1.0, 0, 0, 0])
     t = o.forward(q[0], v[0], None, ws[0])
-    assert abs(q[0, 2] - 1.0 - _sag(mass)) < 1e-6 * abs(_sag(mass))
+    assert abs(q[0, 2] - 1.0 - soft_sag(mass)) < 1e-6 * abs(soft_sag(mass))
     np.testing.assert_allclose(t["efc_force"], [0.0, 0.0, mass * 9.81], atol=1e-6)
     assert np.abs(v).max() < 1e-8
 

@@ -13,7 +13,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from workloads import robots  # noqa: E402
 
 NAMES = ("chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim", "humanoid_lim",
-         "quadruped_terrain", "humanoid_terrain", "chain3_damp", "humanoid_damp", "quadruped_slip", "quadruped_hfield")
+         "quadruped_terrain", "humanoid_terrain", "chain3_damp", "humanoid_damp", "quadruped_slip", "quadruped_hfield",
+         "chain3_loop", "humanoid_weld")
 
 
 def main():

@@ -536,11 +536,32 @@ def humanoid_lim() -> dict:
     return with_limits(humanoid(), -0.15, 0.15, "humanoid_lim")
 
 
+LOOP_POINT = (0.5, 0.0, -1.1)   # world point holding chain3_loop's tip
+
+
+def chain3_loop() -> dict:
+    """chain3 whose tip (the end of link 3) is connected to the world point LOOP_POINT: a closed
+    planar loop with one degree of freedom, swinging under gravity."""
+    m = chain(3, "chain3_loop")
+    m["equality"] = [dict(type="connect", body=3, anchor=[0.0, 0.0, -0.5], target=list(LOOP_POINT))]
+    return m
+
+
+def humanoid_weld() -> dict:
+    """humanoid whose pelvis is welded to the world at its reference pose (a fixed-base humanoid:
+    the limbs move under position control, the feet reach the ground)."""
+    m = humanoid()
+    m["name"] = "humanoid_weld"
+    m["equality"] = [dict(type="weld", body=1, anchor=[0.0, 0.0, 0.0], target=list(m["bodies"][1]["pos"]),
+                          quat=[1.0, 0.0, 0.0, 0.0])]
+    return m
+
+
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
                 "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
                 "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp, "quadruped_slip": quadruped_slip,
-                "quadruped_hfield": quadruped_hfield}
+                "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld}
 
 
 def by_name(name: str) -> dict:
