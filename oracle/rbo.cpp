@@ -112,6 +112,7 @@ struct Model {
     std::vector<int> eqtype, eqbody;           // equality constraints: connect / weld, the moving body
     std::vector<double> eqanchor, eqtarget;    // [neq, 3] anchor (body frame), [neq, 7] world point + quat
     std::vector<double> gpos, gquat, gsize, gfric, gmargin;
+    std::vector<double> gfric_spin, gfric_roll;   // torsional, rolling friction (condim 4, 6)
     std::vector<int> atype, ajoint;
     std::vector<double> akp, akd, agear;
     std::vector<int> movable;  // body has a joint on its path to the world
@@ -126,14 +127,15 @@ struct Model {
     double solimp[5] = {0.9, 0.95, 0.001, 0.5, 2.0};
     bool fr_pw = false, ms_pw = false;
     int maxcon = 0, npair = 0;
+    int maxconrows = 0;   // rows of maxcon contacts: 1 (condim 1) or 2 (condim - 1) per contact
     double meaninertia = 1.0;
     int mode = 0;
 };
 
 struct Contact {
     int g1, g2, feature, b1, b2;
-    int dim;   // 1: frictionless (one normal row), 3: pyramidal friction (four rows)
-    double dist, pos[3], frame[9], mu;
+    int dim;   // 1: frictionless (one normal row), 3, 4, 6: pyramidal friction, 2 (dim - 1) rows
+    double dist, pos[3], frame[9], mu, mu_spin, mu_roll;
 };
 
 struct Data {
@@ -473,6 +475,8 @@ void add_contact(const Model& m, Data& d, int g1, int g2, int feature, double di
     contact_frame(n, c.frame);
     c.dim = std::max(m.gcondim[g1], m.gcondim[g2]);
     c.mu = c.dim == 1 ? 0.0 : (m.fr_pw ? d.fr : std::max(m.gfric[g1], m.gfric[g2]));
+    c.mu_spin = c.dim >= 4 ? std::max(m.gfric_spin[g1], m.gfric_spin[g2]) : 0.0;
+    c.mu_roll = c.dim >= 6 ? std::max(m.gfric_roll[g1], m.gfric_roll[g2]) : 0.0;
     d.con.push_back(c);
 }
 
@@ -874,7 +878,7 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
     int nr = 0;
     for (int ci = 0; ci < nc; ci++) {
         d.crow[ci] = nr;
-        nr += d.con[ci].dim == 1 ? 1 : 4;
+        nr += d.con[ci].dim == 1 ? 1 : 2 * (d.con[ci].dim - 1);
     }
     int ne = 0;
     for (int q = 0; q < m.neq; q++) ne += m.eqtype[q] == RBO_EQ_WELD ? 6 : 3;
@@ -890,7 +894,7 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
     double tc = std::max(m.solref[0], 2 * m.dt), zeta = m.solref[1];
     double bcoef = 2.0 / (dmax * tc);
     double kcoef = 1.0 / (dmax * dmax * tc * tc * zeta * zeta);
-    std::vector<double> jp1(3 * nv), jr1(3 * nv), jp2(3 * nv), jr2(3 * nv), Jc(3 * nv), x(nv);
+    std::vector<double> jp1(3 * nv), jr1(3 * nv), jp2(3 * nv), jr2(3 * nv), Jc(6 * nv), x(nv);
     // reference acceleration and regulariser of row `row` (Jacobian already in place)
     auto finish_row = [&](int row, double rdist) {
         const double* Je = &d.J[(size_t)row * nv];
@@ -916,14 +920,28 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
                 for (int i = 0; i < 3; i++) acc += c.frame[3 * r + i] * (jp2[i * nv + k] - jp1[i * nv + k]);
                 Jc[r * nv + k] = acc;
             }
+        // torsional (about the normal) and rolling (about the tangents) rows: the frame's
+        // components of the relative angular velocity, rows 3..5 of Jc
+        if (c.dim >= 4)
+            for (int r = 0; r < 3; r++)
+                for (int k = 0; k < nv; k++) {
+                    double acc = 0;
+                    for (int i = 0; i < 3; i++) acc += c.frame[3 * r + i] * (jr2[i * nv + k] - jr1[i * nv + k]);
+                    Jc[(3 + r) * nv + k] = acc;
+                }
         double rdist = c.dist - std::max(m.gmargin[c.g1], m.gmargin[c.g2]);
-        for (int e = 0; e < (c.dim == 1 ? 1 : 4); e++) {
+        // pyramid row pairs J_n +- mu_d J_d over the friction directions d: sliding t1, t2
+        // (mu), then spin about n (mu_spin), then rolling about t1, t2 (mu_roll)
+        const int nrow_c = c.dim == 1 ? 1 : 2 * (c.dim - 1);
+        for (int e = 0; e < nrow_c; e++) {
             int row = d.crow[ci] + e;
-            int t = 1 + e / 2;
+            int dir = e / 2;   // 0 t1, 1 t2, 2 spin, 3 roll t1, 4 roll t2
+            int t = dir < 2 ? 1 + dir : dir + 1;
+            double mu = dir < 2 ? c.mu : (dir == 2 ? c.mu_spin : c.mu_roll);
             double sgn = (e % 2 == 0) ? 1.0 : -1.0;
             double* Je = &d.J[(size_t)row * nv];
-            for (int k = 0; k < nv; k++) Je[k] = Jc[k] + sgn * c.mu * Jc[t * nv + k];
-            d.row_id[row] = 4 * ci + e;
+            for (int k = 0; k < nv; k++) Je[k] = Jc[k] + sgn * mu * Jc[t * nv + k];
+            d.row_id[row] = e < 4 ? 4 * ci + e : 1024 + 6 * ci + (e - 4);
             finish_row(row, rdist);
         }
     }
@@ -1262,7 +1280,10 @@ void forward(const Model& m, Data& d) {
             d.cforce[3 * ci] = f[0];
             continue;
         }
-        d.cforce[3 * ci] = f[0] + f[1] + f[2] + f[3];
+        // every pyramid row carries the normal direction once
+        double fn = 0;
+        for (int e = 0; e < 2 * (d.con[ci].dim - 1); e++) fn += f[e];
+        d.cforce[3 * ci] = fn;
         d.cforce[3 * ci + 1] = mu * (f[0] - f[1]);
         d.cforce[3 * ci + 2] = mu * (f[2] - f[3]);
     }
@@ -1444,7 +1465,16 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
     M.gcondim.assign(ng, 3);
     if (dsc->geom_condim) M.gcondim.assign(dsc->geom_condim, dsc->geom_condim + ng);
     for (int g = 0; g < ng; g++)
-        if (M.gcondim[g] != 1 && M.gcondim[g] != 3) return bad("geom condim must be 1 or 3");
+        if (M.gcondim[g] != 1 && M.gcondim[g] != 3 && M.gcondim[g] != 4 && M.gcondim[g] != 6)
+            return bad("geom condim must be 1, 3, 4 or 6");
+    M.gfric_spin.assign(ng, 0.005);
+    M.gfric_roll.assign(ng, 0.0001);
+    if (dsc->geom_friction_spin) M.gfric_spin.assign(dsc->geom_friction_spin, dsc->geom_friction_spin + ng);
+    if (dsc->geom_friction_roll) M.gfric_roll.assign(dsc->geom_friction_roll, dsc->geom_friction_roll + ng);
+    for (int g = 0; g < ng; g++)
+        if (!(M.gfric_spin[g] >= 0 && M.gfric_roll[g] >= 0 && std::isfinite(M.gfric_spin[g]) &&
+              std::isfinite(M.gfric_roll[g])))
+            return bad("torsional and rolling friction must be finite and >= 0");
     bool any_hf = false;
     for (int g = 0; g < ng; g++) {
         if (M.gtype[g] < 0 || M.gtype[g] > 4) return bad("unknown geom type");
@@ -1482,7 +1512,7 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
     M.eqbody.assign(dsc->eq_body, dsc->eq_body + M.neq);
     M.eqanchor.assign(dsc->eq_anchor, dsc->eq_anchor + 3 * M.neq);
     M.eqtarget.assign(dsc->eq_target, dsc->eq_target + 7 * M.neq);
-    M.maxcon = 0; M.npair = 0;
+    M.maxcon = 0; M.npair = 0; M.maxconrows = 0;
     for (int a = 0; a < ng; a++)
         for (int b = a + 1; b < ng; b++) {
             if (!pair_allowed(M, a, b)) continue;
@@ -1490,6 +1520,8 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
             int cap = pair_capacity(t1, t2);
             if (cap < 0) return bad("unsupported collision pair type");
             M.maxcon += cap;
+            const int dim = std::max(M.gcondim[a], M.gcondim[b]);
+            M.maxconrows += cap * (dim == 1 ? 1 : 2 * (dim - 1));
             M.npair++;
         }
     if (nu) {
@@ -1540,7 +1572,7 @@ int rbo_model_info(const void* mp, rbo_info* out) {
     out->nq = m.nq; out->nv = m.nv; out->nu = m.nu; out->nbody = m.nbody; out->ngeom = m.ngeom;
     int neqrows = 0;
     for (int q = 0; q < m.neq; q++) neqrows += m.eqtype[q] == RBO_EQ_WELD ? 6 : 3;
-    out->maxcon = m.maxcon; out->maxrows = 4 * m.maxcon + m.nlim + neqrows; out->npair = m.npair;
+    out->maxcon = m.maxcon; out->maxrows = m.maxconrows + m.nlim + neqrows; out->npair = m.npair;
     out->meaninertia = m.meaninertia;
     return 0;
 }

@@ -60,8 +60,9 @@ typedef struct rbo_desc {
     /* joint damping [njnt] (>= 0, hinges only), or NULL: a passive torque -damping * qvel,
        integrated implicitly (see rbo_step) */
     const double* jnt_damping;
-    /* geom contact dimensionality [ngeom] (1 frictionless, 3 pyramidal friction), or NULL for
-       3 everywhere; a pair takes the larger of its two geoms' */
+    /* geom contact dimensionality [ngeom] (1 frictionless, 3 pyramidal sliding friction, 4 with
+       torsional friction, 6 with torsional and rolling friction), or NULL for 3 everywhere; a
+       pair takes the larger of its two geoms' */
     const int32_t* geom_condim;
     /* height grid of the model's height-field geoms (type RBO_GEOM_HFIELD, static; a geom's
        size[0], size[1] are the grid's half extents along its local x and y): hfield_nrow rows
@@ -82,6 +83,9 @@ typedef struct rbo_desc {
     int32_t neq;
     const int32_t *eq_type, *eq_body;
     const double *eq_anchor, *eq_target;
+    /* torsional and rolling friction coefficients [ngeom] (>= 0), or NULL for 0.005 and 0.0001;
+       a pair takes the larger of its two geoms' and uses them when its condim is 4 or 6 */
+    const double *geom_friction_spin, *geom_friction_roll;
 } rbo_desc;
 
 typedef struct rbo_info {
