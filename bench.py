@@ -49,11 +49,20 @@ WORKLOAD_TEXT = {
                      "otherwise as humanoid",
     "quadruped_hfield": "quadruped on smooth height-field terrain (41x41 grid over 4 m x 4 m, +-3 cm) instead of the "
                         "plane: feet and torso vs the triangle under each candidate point, otherwise as quadruped",
+    "humanoid_weld": "humanoid with its pelvis welded to the world at the reference pose (6 equality rows solved "
+                     "with the contacts): limbs under position control, feet reaching the floor, otherwise as humanoid",
+    "chain3_loop": "chain3 with its tip connected to a world point (3 equality rows): a closed one-degree-of-freedom "
+                   "loop swinging under gravity, dt 2 ms, K = 1",
+    "quadruped_condim6": "quadruped whose sphere feet have torsional and rolling friction (condim 6, mu_spin 0.02, "
+                         "mu_roll 0.002: 10 pyramid rows per foot contact), otherwise as quadruped",
+    "humanoid_condim4": "humanoid whose four foot boxes have torsional friction (condim 4, mu_spin 0.02: 6 pyramid "
+                        "rows per foot contact), otherwise as humanoid",
 }
 MIX = [("chain3", 512), ("quadruped", 4096), ("humanoid", 2048), ("arm_box", 1024)]
 DEFAULT_WORLDS = {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 1024, "humanoid_lim": 8192,
                   "quadruped_lim": 4096, "quadruped_terrain": 4096, "humanoid_terrain": 8192,
-                  "humanoid_damp": 8192, "quadruped_hfield": 4096}
+                  "humanoid_damp": 8192, "quadruped_hfield": 4096, "humanoid_weld": 8192, "chain3_loop": 8192,
+                  "quadruped_condim6": 4096, "humanoid_condim4": 8192}
 WORKLOAD_TEXT["serve"] = ("serving: Poisson arrivals of rollout requests, model uniform over chain3/quadruped/humanoid/"
                           "arm_box, worlds log-uniform 16-4096, horizon uniform 50-500 env steps, device-side seeded "
                           "inputs, HBM-budget admission, continuous batching in one fused launch per tick")

@@ -91,9 +91,14 @@ typedef struct rb_model_desc {
      * -damping * qvel, integrated implicitly -- the step applies (M + dt B)^-1 M qacc, B the
      * diagonal of dampings, instead of the solved qacc (which stays the warm start). */
     const double* jnt_damping;
-    /* geom contact dimensionality [ngeom] (1 frictionless, 3 pyramidal friction), or NULL for 3
-     * everywhere; a pair takes the larger of its two geoms' (a condim-1 pair keeps the normal
-     * row only and reports zero tangential force) */
+    /* geom contact dimensionality [ngeom] (1 frictionless, 3 pyramidal sliding friction, 4 with
+     * torsional friction, 6 with torsional and rolling friction), or NULL for 3 everywhere; a
+     * pair takes the larger of its two geoms' (a condim-1 pair keeps the normal row only and
+     * reports zero tangential force).  Condim 4 and 6 add the row pairs J_n +- mu_spin J_spin
+     * and J_n +- mu_roll J_roll (J_spin, J_roll the contact frame's n and t1, t2 components of
+     * the body's angular velocity); their forces add to the reported normal force, and the
+     * torsional and rolling torques are not reported.  A model's equality rows and the rows
+     * its condim-4/6 pairs can produce (2 or 6 per contact) number at most 64. */
     const int32_t* geom_condim;
     /* height grid of the model's height-field geoms (type RB_GEOM_HFIELD, static; a geom's
      * size[0], size[1] are the grid's half extents along its local x and y): hfield_nrow rows
@@ -117,6 +122,11 @@ typedef struct rb_model_desc {
     int32_t neq;
     const int32_t *eq_type, *eq_body;
     const double *eq_anchor, *eq_target;
+    /* torsional and rolling friction coefficients [ngeom] (>= 0), or NULL for 0.005 and 0.0001;
+     * a pair takes the larger of its two geoms' and uses them when its condim is 4 or 6.  Cites:
+     * paper, section "Architecture", paragraph on the GPU physics backend (the contact model of
+     * the simulator it builds on). */
+    const double *geom_friction_spin, *geom_friction_roll;
 } rb_model_desc;
 
 typedef struct rb_model rb_model;
@@ -173,7 +183,7 @@ int rb_model_create(const rb_model_desc* desc, rb_model** out);
  *               "range": [2], "damping" (both optional, hinges only)}, ...],
  *   "geoms": [{"type": "plane" | "sphere" | "capsule" | "box" | "hfield", "body", "pos": [3],
  *              "quat": [4], "size": [3], "friction", "contype", "conaffinity", "margin",
- *              "condim" (optional, 1 or 3)}, ...],
+ *              "condim" (optional, 1, 3, 4 or 6), "friction_spin", "friction_roll" (optional)}, ...],
  *   "actuators": [{"type": "position" | "motor", "joint", "kp", "kd", "gear"}, ...],
  *   "per_world": {"friction": bool, "mass_scale": bool}   (optional, default false),
  *   "hfield": {"nrow", "ncol", "data": [nrow * ncol]}    (required with hfield geoms),

@@ -8,7 +8,8 @@
 //  "joints": [{"type": "free"|"hinge", "body", "pos": [3], "axis": [3], "armature",
 //              "range": [2], "damping" (both optional)}, ...],
 //  "geoms": [{"type": "plane"|"sphere"|"capsule"|"box"|"hfield", "body", "pos": [3], "quat": [4],
-//             "size": [3], "friction", "contype", "conaffinity", "margin", "condim" (optional)}, ...],
+//             "size": [3], "friction", "contype", "conaffinity", "margin", "condim", "friction_spin",
+//             "friction_roll" (the last three optional)}, ...],
 //  "actuators": [{"type": "position"|"motor", "joint", "kp", "kd", "gear"}, ...],
 //  "per_world": {"friction": bool, "mass_scale": bool},      optional, default false
 //  "hfield": {"nrow", "ncol", "data": [nrow * ncol]},         required with hfield geoms
@@ -16,8 +17,8 @@
 //                "quat": [4] (welds)}, ...]}                  optional
 //
 // Other keys (names, comments) are ignored.  Every listed field is required except a joint's
-// range and damping, a geom's condim, per_world, hfield and equality; a missing or mistyped
-// field is RB_EINVAL with the field named.
+// range and damping, a geom's condim, friction_spin and friction_roll, per_world, hfield and
+// equality; a missing or mistyped field is RB_EINVAL with the field named.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -226,7 +227,8 @@ int rb_model_create_json(const char* json, rb_model** out) {
         gdim(g1, 3);
     std::vector<double> bpos(3 * b1), bquat(4 * b1), bipos(3 * b1), biquat(4 * b1), bmass(b1), binert(3 * b1);
     std::vector<double> jpos(3 * j1), jaxis(3 * j1), jarm(j1), jrange(2 * j1, 0.0), jdamp(j1, 0.0);
-    std::vector<double> gpos(3 * g1), gquat(4 * g1), gsize(3 * g1), gfric(g1), gmarg(g1);
+    std::vector<double> gpos(3 * g1), gquat(4 * g1), gsize(3 * g1), gfric(g1), gmarg(g1), gspin(g1, 0.005),
+        groll(g1, 0.0001);
     std::vector<double> akp(u1), akd(u1), agear(u1);
     bool ok = true;
     for (int b = 0; b < nb && ok; b++) {
@@ -257,6 +259,8 @@ int rb_model_create_json(const char* json, rb_model** out) {
              R.integer(o, "contype", w, &gct[g]) && R.integer(o, "conaffinity", w, &gca[g]) &&
              R.num(o, "margin", w, &gmarg[g]);
         if (ok && o.obj.count("condim")) ok = R.integer(o, "condim", w, &gdim[g]);
+        if (ok && o.obj.count("friction_spin")) ok = R.num(o, "friction_spin", w, &gspin[g]);
+        if (ok && o.obj.count("friction_roll")) ok = R.num(o, "friction_roll", w, &groll[g]);
     }
     static const char* const anames[] = {"position", "motor"};
     for (int u = 0; u < nu && ok; u++) {
@@ -331,6 +335,8 @@ int rb_model_create_json(const char* json, rb_model** out) {
     d.jnt_range = jrange.data();
     d.jnt_damping = jdamp.data();
     d.geom_condim = gdim.data();
+    d.geom_friction_spin = gspin.data();
+    d.geom_friction_roll = groll.data();
     d.geom_type = gtype.data(); d.geom_body = gbody.data(); d.geom_contype = gct.data(); d.geom_conaffinity = gca.data();
     d.geom_pos = gpos.data(); d.geom_quat = gquat.data(); d.geom_size = gsize.data(); d.geom_friction = gfric.data();
     d.geom_margin = gmarg.data();

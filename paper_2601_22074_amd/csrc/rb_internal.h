@@ -21,8 +21,9 @@
 #define RB_PAIR_CAPSULEBOX 18     // pair_type of a capsule (g1) - box (g2) pair: its two end spheres
 #define RB_PAIR_HFIELD 32         // pair_type of a height field (g1) - geom (g2) pair: this + g2's geom type
 #define RB_BB_FLOATS 96           // LDS floats per box-box pair: clip buffers, contacts, normal
-#define RB_MAX_EQROW 64           // equality-constraint rows (one lane each; extended code only)
-#define RB_EQF 10                 // LDS floats per equality row: psi[6], D, residual, direction, body
+#define RB_MAX_GROW 64            // generic rows: equality rows and contacts' torsional / rolling rows
+                                  // (one lane each; extended code only)
+#define RB_GRF 12                 // LDS floats per generic row: psi[6], D, residual, J p, body, id, pad
 
 struct DevModel {
     // sizes
@@ -116,6 +117,10 @@ struct DevModel {
     int hf_nrow, hf_ncol;
     // equality constraints with the world [neq]; their rows [neqrow] (connect 3, weld 6)
     int neq, neqrow;
+    int nxmax;                 // bound on the contacts' torsional / rolling rows (condim 4, 6 pairs)
+    const int* pair_xrows;     // per pair: 0, 2 (condim 4) or 6 (condim 6) rows per contact
+    const float* pair_mu_spin;
+    const float* pair_mu_roll;
     const int* eq_body;
     const float* eq_anchor;    // [3] body frame
     const float* eq_tpos;      // [3] world target point
@@ -126,7 +131,7 @@ struct DevModel {
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
     int o_xpos, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
     int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp, o_lD, o_ljar;
-    int o_M, o_H, o_piv, o_rowadr, o_bb, o_eq;
+    int o_M, o_H, o_piv, o_rowadr, o_bb, o_gr;
     int lds_floats;
 };
 

@@ -138,8 +138,8 @@ void layout_tail(DevModel& m, int kernel_maxd) {
     o += r4(m.nv);
     m.o_bb = o;
     o += r4(RB_BB_FLOATS * m.nbb);
-    m.o_eq = o;
-    o += r4(RB_EQF * m.neqrow);
+    m.o_gr = o;
+    o += r4(RB_GRF * (m.neqrow + m.nxmax));
     m.lds_floats = o;
 }
 
@@ -364,8 +364,13 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             for (long k = 0; k < (long)d->hfield_nrow * d->hfield_ncol; k++)
                 if (!std::isfinite(d->hfield_data[k])) return fail(RB_EINVAL, "height field heights must be finite");
         }
-        if (d->geom_condim && d->geom_condim[g] != 1 && d->geom_condim[g] != 3)
-            return fail(RB_EINVAL, "geom condim must be 1 or 3");
+        if (d->geom_condim && d->geom_condim[g] != 1 && d->geom_condim[g] != 3 && d->geom_condim[g] != 4 &&
+            d->geom_condim[g] != 6)
+            return fail(RB_EINVAL, "geom condim must be 1, 3, 4 or 6");
+        const double fs = d->geom_friction_spin ? d->geom_friction_spin[g] : 0.0;
+        const double fr = d->geom_friction_roll ? d->geom_friction_roll[g] : 0.0;
+        if (!(fs >= 0 && fr >= 0 && std::isfinite(fs) && std::isfinite(fr)))
+            return fail(RB_EINVAL, "torsional and rolling friction must be finite and >= 0");
         if (b < 0 || b >= nb) return fail(RB_EINVAL, "geom on an invalid body");
         if (t == RB_GEOM_PLANE && movable[b]) return fail(RB_EINVAL, "a plane must be on a static body");
         const double* q = d->geom_quat + 4 * g;
@@ -407,7 +412,9 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     std::vector<int> pg1(npair), pg2(npair), ptype(npair), pbody(npair), pcap(npair), pslot(npair, -1);
     int nbb = 0;
     std::vector<double> psig(npair), pmu(npair), pmar(npair);
-    std::vector<int> pfric0(npair, 0);
+    std::vector<int> pfric0(npair, 0), pxr(npair, 0);
+    std::vector<double> pmus(npair, 0.0), pmur(npair, 0.0);
+    int nxmax = 0;
     int maxcon = 0;
     for (int k = 0; k < npair; k++) {
         int g1 = pairs[k].g1, g2 = pairs[k].g2;
@@ -424,12 +431,21 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         psig[k] = mov2 ? 1.0 : -1.0;
         pmu[k] = std::max(d->geom_friction[g1], d->geom_friction[g2]);
         pmar[k] = std::max(d->geom_margin[g1], d->geom_margin[g2]);
-        if (d->geom_condim) pfric0[k] = std::max(d->geom_condim[g1], d->geom_condim[g2]) == 1;
+        if (d->geom_condim) {
+            // condim 4 adds the torsional row pair, 6 the two rolling pairs too
+            const int cd = std::max(d->geom_condim[g1], d->geom_condim[g2]);
+            pfric0[k] = cd == 1;
+            pxr[k] = cd == 4 ? 2 : (cd == 6 ? 6 : 0);
+            auto fmax = [&](const double* f, double dflt) { return f ? std::max(f[g1], f[g2]) : dflt; };
+            pmus[k] = fmax(d->geom_friction_spin, 0.005);
+            pmur[k] = fmax(d->geom_friction_roll, 0.0001);
+        }
         const int shape = ptype[k] >= RB_PAIR_HFIELD ? ptype[k] - RB_PAIR_HFIELD : ptype[k];
         pcap[k] = (shape == RB_GEOM_SPHERE || shape == RB_PAIR_SPHEREBOX)      ? 1
                   : (shape == RB_GEOM_CAPSULE || shape == RB_PAIR_CAPSULEBOX) ? 2
                                                                                : 8;
         maxcon += pcap[k];
+        nxmax += pcap[k] * pxr[k];
     }
     // options
     if (!(d->timestep > 0) || d->nsubsteps < 1 || d->iterations < 0) return fail(RB_EINVAL, "bad options");
@@ -582,7 +598,13 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         }
     }
     const int neqrow = (int)eqr_q.size();
-    if (neqrow > RB_MAX_EQROW) return fail(RB_EINVAL, "more than 64 equality-constraint rows");
+    // generic rows, one lane each: equality rows and the torsional / rolling rows that the
+    // contacts can produce
+    nxmax = std::min(nxmax, 6 * RB_MAX_CON);
+    if (neqrow + nxmax > RB_MAX_GROW)
+        return fail(RB_EINVAL, "more than 64 equality and torsional / rolling friction rows (condim 4 and 6 "
+                               "pairs count 2 and 6 rows for every contact they can produce)");
+
     // ---- upload
     Blob B;
     DevModel& m = M->dm;
@@ -620,6 +642,9 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     F(std::vector<double>(d->geom_pos, d->geom_pos + 3 * ng), &m.geom_pos);
     F(std::vector<double>(d->geom_quat, d->geom_quat + 4 * ng), &m.geom_quat);
     F(std::vector<double>(d->geom_size, d->geom_size + 3 * ng), &m.geom_size);
+    if (nxmax > 0) {
+        I(pxr, &m.pair_xrows); F(pmus, &m.pair_mu_spin); F(pmur, &m.pair_mu_roll);
+    }
     if (neqrow > 0) {
         I(eqb, &m.eq_body); F(eqa, &m.eq_anchor); F(eqp, &m.eq_tpos); F(eqm, &m.eq_tmat);
         I(eqr_q, &m.eqrow_eq); I(eqr_k, &m.eqrow_k);
@@ -649,8 +674,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.fr_pw = d->friction_per_world != 0; m.ms_pw = d->mass_scale_per_world != 0; m.nM = nM;
     m.nlim = nlim;
     m.ndamp = ndamp;
-    m.neq = d->neq; m.neqrow = neqrow;
-    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE || neqrow > 0 ||
+    m.neq = d->neq; m.neqrow = neqrow; m.nxmax = nxmax;
+    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE || neqrow > 0 || nxmax > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_CAPSULEBOX) > 0 ||
              std::count_if(ptype.begin(), ptype.end(), [](int t) { return t >= RB_PAIR_HFIELD; }) > 0 ||

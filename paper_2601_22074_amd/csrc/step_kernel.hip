@@ -917,6 +917,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 
     Con C;
     int ncon = 0;
+    // torsional / rolling pyramid rows of the lane's contact (condim 4: 2, condim 6: 6), kept in
+    // LDS as generic rows after the equality rows at slot xbase; nx of them in the world
+    int xr = 0, xbase = 0, nx = 0;
     int st_con = 0, st_rows = 0, st_iter = 0, st_seg = 0;   // work totals for the stats tap
     uint64_t stage_cyc[RB_NSTAGE] = {};                          // cycles per stage (stats tap)
     uint64_t t_mark = TIMED ? clock64() : 0;
@@ -1243,6 +1246,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             }
         }
         float margin_c = 0.f;
+        xr = 0;
+        float mu_spin = 0.f, mu_roll = 0.f;
         if (has) {
             int j = lane - before, feat;
             if (EXT && m.pair_type[src] == RB_PAIR_BOXBOX) {
@@ -1270,10 +1275,24 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 C.ids |= 1 << 24;
             }
             margin_c = m.pair_margin[src];
+            if (EXT && m.nxmax > 0) {
+                xr = m.pair_xrows[src];
+                mu_spin = m.pair_mu_spin[src];
+                mu_roll = m.pair_mu_roll[src];
+            }
         } else {
             C.body = 0;
         }
         RB_STAGE(3);
+        // generic-row slots of the contacts' extra rows: after the equality rows, in contact order
+        float* GR = L + m.o_gr;
+        xbase = 0;
+        nx = 0;
+        if (EXT && m.nxmax > 0) {
+            const int xi = wscan_incl(xr, lane);
+            xbase = m.neqrow + xi - xr;
+            nx = __builtin_amdgcn_readfirstlane(__shfl(xi, RB_WAVE - 1));
+        }
         // ---- constraint rows: exact A-hat from the chain half-solve with M's factor
         {
             // the contact body's chain, from the body lane
@@ -1364,6 +1383,58 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     E[3 * e + 2] = ah[e];
                 }
             }
+            if (EXT && xr > 0) {
+                // torsional (about n) and rolling (about t1, t2) pyramid rows J_n +- mu_d J_d,
+                // J_d the frame component of the body's angular velocity: as spatial forces at O,
+                // psi = sigma (r x n +- mu_d k_d, n); A-hat from one more half-solve per axis
+                // (Y = L'^-1 J_d' for the pure torque k_d) and the normal column's Z0
+                float rxn[3];
+                cross(C.r, C.n, rxn);
+                const float vn = 0.5f * (vrow[0] + vrow[1]);
+                const float* wb = cvel + 6 * C.body;
+                for (int dir = 0; 2 * dir < xr; dir++) {
+                    const float* k = dir == 0 ? C.n : (dir == 1 ? C.t1 : t2c);
+                    float Y[MAXD];
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++) {
+                        const float* S = cdof + 6 * (int)((cw[t >> 2] >> (8 * (t & 3))) & 0xffu);
+                        Y[t] = t < d ? C.sigma * dot(k, S) : 0.f;
+                    }
+#pragma unroll
+                    for (int tp = MAXD - 1; tp >= 1; tp--) {
+                        if (tp < d) {
+                            const int row = CROW(tp);
+#pragma unroll
+                            for (int t = 0; t < tp; t++) Y[t] -= H[row + t] * Y[tp];
+                        }
+                    }
+                    float Akk = 0.f, Ank = 0.f;
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++)
+                        if (t < d) {
+                            Akk += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[CROW(t) + t]);
+                            Ank += Z0[t] * Y[t];
+                        }
+                    const float mud = dir == 0 ? mu_spin : mu_roll;
+                    const float wk = C.sigma * dot(k, wb);
+                    for (int sg = 0; sg < 2; sg++) {
+                        const float sm = sg ? -mud : mud;
+                        const float ahx = A00 + mud * mud * Akk + 2.f * sm * Ank;
+                        float* G = GR + RB_GRF * (xbase + 2 * dir + sg);
+                        G[0] = C.sigma * (rxn[0] + sm * k[0]);
+                        G[1] = C.sigma * (rxn[1] + sm * k[1]);
+                        G[2] = C.sigma * (rxn[2] + sm * k[2]);
+                        G[3] = C.sigma * C.n[0];
+                        G[4] = C.sigma * C.n[1];
+                        G[5] = C.sigma * C.n[2];
+                        G[6] = 1.0f / fmaxf(1e-15f, (1.0f - imp) / imp * ahx);
+                        G[7] = -m.bref * (vn + sm * wk) - m.kref * imp * rd;
+                        G[8] = 0.f;
+                        G[9] = __int_as_float(C.body);
+                        G[10] = __int_as_float(1024 + 6 * lane + 2 * dir + sg);
+                    }
+                }
+            }
         }
         }
 
@@ -1374,9 +1445,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         // k is e_k as a pure torque, psi = (e_k, 0), against component k of the rotation vector of
         // E = R_body R_target'.  LDS keeps psi, D, the residual J a - aref (aref until the Newton
         // start), the line-search direction J p and the body.  Bilateral: always active.
-        float* EQ = L + m.o_eq;
-        const bool eqact = EXT && m.neqrow > 0;
-        if (eqact) {
+        const int ngr = m.neqrow + nx;            // generic rows: equality, then contact extras
+        const bool gract = EXT && ngr > 0;
+        if (EXT && m.neqrow > 0) {
             const bool own = lane < m.neqrow;
             const int qe = own ? m.eqrow_eq[lane] : 0;
             const int k = own ? m.eqrow_k[lane] : 0;
@@ -1436,15 +1507,16 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     if (t < d) Ah += Y[t] * Y[t] * __builtin_amdgcn_rcpf(H[rowadr_l[eq_anc(t)] + t]);
                 const float jvel = sdot(cvel + 6 * body, psi);
                 const float imp = impedance(m, rdist);
-                float* Er = EQ + RB_EQF * lane;
+                float* Er = GR + RB_GRF * lane;
                 for (int c6 = 0; c6 < 6; c6++) Er[c6] = psi[c6];
                 Er[6] = 1.0f / fmaxf(1e-15f, (1.0f - imp) / imp * Ah);
                 Er[7] = -m.bref * jvel - m.kref * imp * rdist;
                 Er[8] = 0.f;
                 Er[9] = __int_as_float(body);
+                Er[10] = __int_as_float(512 + 6 * qe + k);
             }
-            wave_sync();   // xmat's space is reused by the limit rows and the Newton vectors
         }
+        if (gract) wave_sync();   // rows read by every lane; xmat's space is reused next
 
         // ---- joint limits: a hinge outside its range gets one row J = s e_i (s = +1 below the
         // lower bound, -1 above the upper one), held in LDS by the dof's lane: lD = s D (0 when
@@ -1495,7 +1567,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         RB_STAGE(4);
         // ---- primal Newton solve
         bool itercap = false;
-        if (ncon == 0 && !limact && !eqact) {
+        if (ncon == 0 && !limact && !gract) {
             for (int i = lane; i < nv; i += RB_WAVE) acc[i] = a0[i];
             wave_sync();
         } else {
@@ -1523,13 +1595,16 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 const float mn = fminf(lim_res(false), 0.f);
                 f0 += 0.5f * fabsf(lD[lane]) * mn * mn;
             }
-            // equality rows at a0 (bilateral: the whole residual counts)
-            const bool eqown = eqact && lane < m.neqrow;
-            float* Er = EQ + RB_EQF * (eqown ? lane : 0);
+            // generic rows at a0: lane r holds row r; equality rows are bilateral (the whole
+            // residual counts), the contacts' extra rows unilateral
+            const bool grown = gract && lane < ngr;
+            const bool grbil = lane < m.neqrow;
+            float* Er = GR + RB_GRF * (grown ? lane : 0);
+            auto gr_cost = [&](float j) { const float mn = grbil ? j : fminf(j, 0.f); return 0.5f * Er[6] * mn * mn; };
             float ej0 = 0.f;
-            if (eqown) {
+            if (grown) {
                 ej0 = sdot(bvec + 6 * __float_as_int(Er[9]), Er) - Er[7];
-                f0 += 0.5f * Er[6] * ej0 * ej0;
+                f0 += gr_cost(ej0);
             }
             f0 = wsum(f0);
             for (int i = lane; i < nv; i += RB_WAVE) tmp[i] = aws[i] - a0[i];
@@ -1555,14 +1630,14 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 fw += 0.5f * fabsf(lD[lane]) * mn * mn;
             }
             float ejw = 0.f;
-            if (eqown) {
+            if (grown) {
                 ejw = ej0 + sdot(bvec + 6 * __float_as_int(Er[9]), Er);
-                fw += 0.5f * Er[6] * ejw * ejw;
+                fw += gr_cost(ejw);
             }
             fw = wsum(fw) + 0.5f * wsum(qf);
             bool use_ws = fw < f0;
             if (limact && lane < nv) ljar[lane] = lim_res(use_ws);
-            if (eqown) Er[7] = use_ws ? ejw : ej0;
+            if (grown) Er[7] = use_ws ? ejw : ej0;
             float fcur = use_ws ? fw : f0;
             for (int i = lane; i < nv; i += RB_WAVE) {
                 acc[i] = use_ws ? aws[i] : a0[i];
@@ -1588,6 +1663,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     for (int e = 0; e < 4; e++) bits |= (C.jar[e] < 0.f ? 1u : 0u) << e;
                 }
                 if (limact && lane < nv) bits |= (ljar[lane] < 0.f ? 1u : 0u) << 4;
+                if (grown && !grbil) bits |= (Er[7] < 0.f ? 1u : 0u) << 5;
                 if (it > 0 && __ballot(bits != prev_bits) == 0) break;
                 prev_bits = bits;
                 // gradient and the contact part of the Hessian, one contact at a time
@@ -1634,10 +1710,11 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         }
                     }
                 }
-                // equality rows: every row is active; psi, D and the residual from LDS
-                if (eqact) {
-                    for (int rr = 0; rr < m.neqrow; rr++) {
-                        const float* Eo = EQ + RB_EQF * rr;
+                // generic rows: psi, D and the residual from LDS; equality rows always active
+                if (gract) {
+                    for (int rr = 0; rr < ngr; rr++) {
+                        const float* Eo = GR + RB_GRF * rr;
+                        if (rr >= m.neqrow && !(Eo[7] < 0.f)) continue;
                         const int body = __builtin_amdgcn_readfirstlane(__float_as_int(Eo[9]));
                         const uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)BL.chainmask, body);
                         const uint32_t mhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(BL.chainmask >> 32), body);
@@ -1674,8 +1751,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     }
                     if (limact && dof_lane && lD[lane] != 0.f && ljar[lane] < 0.f)
                         fpl += (uint32_t)(256 + lane + 1) * 2654435761u;
-                    // equality row k of constraint q: 512 + 6 q + k, always active
-                    if (eqown) fpl += (uint32_t)(512 + 6 * m.eqrow_eq[lane] + m.eqrow_k[lane] + 1) * 2654435761u;
+                    // generic rows: equality row k of constraint q 512 + 6 q + k (always active),
+                    // extra row e of contact c 1024 + 6 c + e
+                    if (grown && (grbil || Er[7] < 0.f))
+                        fpl += (uint32_t)(__float_as_int(Er[10]) + 1) * 2654435761u;
                     fpl = wsum_u32(fpl);
                     if (lane == 0) SUBREC[RB_SUBSTAT * sub + 5 + it] = (int32_t)fpl;
                 }
@@ -1713,12 +1792,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     pa = p[lane] * Mp[lane];
                     pb = p[lane] * (Ma[lane] - (tau[lane] - bias[lane]));
                 }
-                if (eqown) {
-                    // the equality rows are quadratic along p: constant terms of every segment
-                    const float sre = sdot(bvec + 6 * __float_as_int(Er[9]), Er);
-                    Er[8] = sre;
-                    pa += Er[6] * sre * sre;
-                    pb += Er[6] * sre * Er[7];
+                float gsr = 0.f;   // J p of the lane's generic row
+                if (grown) {
+                    gsr = sdot(bvec + 6 * __float_as_int(Er[9]), Er);
+                    Er[8] = gsr;
+                    if (grbil) {
+                        // bilateral rows are quadratic along p: constant terms of every segment
+                        pa += Er[6] * gsr * gsr;
+                        pb += Er[6] * gsr * Er[7];
+                    }
                 }
                 float A0 = wsum(pa), B0 = wsum(pb);
                 float alpha = 0.f;
@@ -1733,8 +1815,12 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     for (int e = 0; e < 4; e++) {
                         bp[e] = (has && sr[e] != 0.f) ? -C.jar[e] * __builtin_amdgcn_rcpf(sr[e]) : INFINITY;
                     }
+                    // the lane's unilateral generic row: residual, D and breakpoint
+                    const bool gu = grown && !grbil;
+                    const float gj = gu ? Er[7] : 0.f, gD = gu ? Er[6] : 0.f;
+                    const float gbp = (gu && gsr != 0.f) ? -gj * __builtin_amdgcn_rcpf(gsr) : INFINITY;
                     float at = 0.f;
-                    int guard = 4 * ncon + 2 + (limact ? nv : 0);
+                    int guard = 4 * ncon + 2 + (limact ? nv : 0) + nx;
                     for (int k = 0; k < guard; k++) {
                         if (TIMED) seg_sub++;
                         float sa = 0.f, sb = 0.f, nxt = INFINITY;
@@ -1759,6 +1845,14 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                                 sb += Dl * sl * lj;
                             }
                             if (bpl > at) nxt = fminf(nxt, bpl);
+                        }
+                        if (gu) {
+                            const bool act = gsr > 0.f ? (at < gbp) : (gsr < 0.f ? (at >= gbp) : (gj < 0.f));
+                            if (act) {
+                                sa += gD * gsr * gsr;
+                                sb += gD * gsr * gj;
+                            }
+                            if (gbp > at) nxt = fminf(nxt, gbp);
                         }
                         float Aseg = A0 + wsum(sa), Bseg = B0 + wsum(sb);
                         nxt = wmin(nxt);
@@ -1793,10 +1887,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     const float mn = fminf(lj, 0.f);
                     fc += 0.5f * fabsf(lD[lane]) * mn * mn;
                 }
-                if (eqown) {
+                if (grown) {
                     const float ej = Er[7] + alpha * Er[8];
                     Er[7] = ej;
-                    fc += 0.5f * Er[6] * ej * ej;
+                    fc += gr_cost(ej);
                 }
                 float fnew = 0.5f * wsum(qf2) + wsum(fc);
                 wave_sync();
@@ -1818,8 +1912,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     act += ljar[lane] < 0.f;
                     nrow += 1;
                 }
-                if (eqown) {
-                    act += 1;
+                if (grown) {
+                    act += grbil || Er[7] < 0.f;
                     nrow += 1;
                 }
                 const int actw = (int)wsum_u32((uint32_t)act);
@@ -1876,7 +1970,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 #pragma unroll
             for (int t = 0; t < MAXD; t++)
                 if (t == DL.depth - 1) Hr[t] += bd;
-            const bool solved = ncon > 0 || limact || eqact;
+            const bool solved = ncon > 0 || limact || gract;
             const float rhs = lane < nv ? (solved ? Ma[lane] : tau[lane] - bias[lane]) : 0.f;
             float invd;
             const float x = factor_solve<MAXD>(m, DL, Hr, rhs, lane, piv, &invd);
@@ -1975,7 +2069,14 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         if (A.co.force) {
             float f[4];
             for (int e = 0; e < 4; e++) f[e] = -C.D[e] * fminf(C.jar[e], 0.f);
-            A.co.force[3 * slot] = f[0] + f[1] + f[2] + f[3];
+            // every pyramid row, the torsional and rolling ones included, carries the normal once
+            float fx = 0.f;
+            if (EXT)
+                for (int e = 0; e < xr; e++) {
+                    const float* G = L + m.o_gr + RB_GRF * (xbase + e);
+                    fx += -G[6] * fminf(G[7], 0.f);
+                }
+            A.co.force[3 * slot] = f[0] + f[1] + f[2] + f[3] + fx;
             A.co.force[3 * slot + 1] = C.mu * (f[0] - f[1]);
             A.co.force[3 * slot + 2] = C.mu * (f[2] - f[3]);
         }

@@ -43,7 +43,8 @@ def _create_error(m):
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
                                   "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
-                                  "negative_damping", "condim", "nan_pos", "inf_size"])
+                                  "negative_damping", "condim", "nan_pos", "inf_size", "negative_spin",
+                                  "generic_rows"])
 def test_invalid_models_rejected(rb, case):
     m = robots.quadruped()
     if case == "parent":
@@ -73,7 +74,13 @@ def test_invalid_models_rejected(rb, case):
     elif case == "negative_damping":
         m["joints"][2]["damping"] = -1.0
     elif case == "condim":
-        m["geoms"][1]["condim"] = 4
+        m["geoms"][1]["condim"] = 5
+    elif case == "negative_spin":
+        m["geoms"][1].update(condim=4, friction_spin=-0.1)
+    elif case == "generic_rows":
+        # condim 6 on the torso box (8 contacts) and the four feet: 6 x 12 = 72 rows > 64
+        for g in m["geoms"]:
+            g["condim"] = 6
     elif case == "nan_pos":
         m["bodies"][2]["pos"][0] = float("nan")
     elif case == "inf_size":
@@ -93,7 +100,8 @@ def _create_json_error(text):
 
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
                                   "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
-                                  "negative_damping", "condim", "nan_pos", "inf_size"])
+                                  "negative_damping", "condim", "nan_pos", "inf_size", "negative_spin",
+                                  "generic_rows"])
 def test_json_models_validated_like_descriptions(rb, case):
     """The JSON entry point hands the same description to the same validation: every invalid
     model above is rejected with the message the struct entry point gives."""
@@ -126,7 +134,13 @@ def test_json_models_validated_like_descriptions(rb, case):
     elif case == "negative_damping":
         m["joints"][2]["damping"] = -1.0
     elif case == "condim":
-        m["geoms"][1]["condim"] = 4
+        m["geoms"][1]["condim"] = 5
+    elif case == "negative_spin":
+        m["geoms"][1].update(condim=4, friction_spin=-0.1)
+    elif case == "generic_rows":
+        # condim 6 on the torso box (8 contacts) and the four feet: 6 x 12 = 72 rows > 64
+        for g in m["geoms"]:
+            g["condim"] = 6
     elif case == "nan_pos":
         m["bodies"][2]["pos"][0] = float("nan")
     elif case == "inf_size":

@@ -105,7 +105,8 @@ def test_single_step_from_initial_states(oracle_mod, name):
                                           ("chain3_lim", 200), ("quadruped_lim", 200), ("humanoid_lim", 200),
                                           ("quadruped_terrain", 200), ("humanoid_terrain", 200),
                                           ("humanoid_damp", 200), ("quadruped_slip", 200),
-                                          ("chain3_loop", 200), ("humanoid_weld", 200)])
+                                          ("chain3_loop", 200), ("humanoid_weld", 200),
+                                          ("quadruped_condim6", 200), ("humanoid_condim4", 200)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory (up to env step 1000 for the quadruped and humanoid
     workloads), hand its state (rounded to FP32) to the GPU every 25 env steps and compare one
@@ -200,7 +201,8 @@ def test_chain3_500_steps(oracle_mod):
 
 # ------------------------------------------------------------------ contact sets
 @pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain", "humanoid_terrain",
-                                  "quadruped_slip", "quadruped_hfield", "humanoid_weld"])
+                                  "quadruped_slip", "quadruped_hfield", "humanoid_weld", "quadruped_condim6",
+                                  "humanoid_condim4"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -336,7 +338,8 @@ def test_sphere_box_contacts_random_poses(oracle_mod):
     assert {"none", "band", "touch", "inside"} <= kinds
 
 
-@pytest.mark.parametrize("name", ["quadruped", "humanoid", "quadruped_lim", "humanoid_lim", "humanoid_weld"])
+@pytest.mark.parametrize("name", ["quadruped", "humanoid", "quadruped_lim", "humanoid_lim", "humanoid_weld",
+                                  "quadruped_condim6", "humanoid_condim4"])
 def test_newton_iterations_match_oracle(oracle_mod, name):
     """The GPU ends Newton when no row changed sides since the last Hessian; the oracle ends
     it by its FP64 gradient test.  On the same states both take the same number of
@@ -367,7 +370,7 @@ def test_newton_iterations_match_oracle(oracle_mod, name):
 
 
 # ------------------------------------------------------------------ system properties
-@pytest.mark.parametrize("name", ["quadruped", "arm_box", "humanoid_lim", "humanoid_weld"])
+@pytest.mark.parametrize("name", ["quadruped", "arm_box", "humanoid_lim", "humanoid_weld", "humanoid_condim4"])
 def test_plain_launch_occupancy_bitwise(name):
     """The 3- and 4-wave instantiations of the plain step (plain and extended code) compute the
     same bits."""
@@ -406,7 +409,7 @@ def test_run_twice_bitwise(oracle_mod):
 
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim", "quadruped_terrain",
                                   "humanoid_terrain", "humanoid_damp", "quadruped_hfield", "chain3_loop",
-                                  "humanoid_weld"])
+                                  "humanoid_weld", "quadruped_condim6", "humanoid_condim4"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""

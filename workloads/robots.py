@@ -557,11 +557,34 @@ def humanoid_weld() -> dict:
     return m
 
 
+def quadruped_condim6() -> dict:
+    """quadruped whose sphere feet have torsional and rolling friction (condim 6: mu_spin 0.02,
+    mu_roll 0.002 against the ground)."""
+    m = quadruped()
+    m["name"] = "quadruped_condim6"
+    for g in m["geoms"]:
+        if g["type"] == "sphere":
+            g.update(condim=6, friction_spin=0.02, friction_roll=0.002)
+    return m
+
+
+def humanoid_condim4() -> dict:
+    """humanoid whose four foot boxes have torsional friction (condim 4, mu_spin 0.02)."""
+    m = humanoid()
+    m["name"] = "humanoid_condim4"
+    feet = {i for i, b in enumerate(m["bodies"]) if b.get("name", "").endswith("ankle_roll")}
+    for g in m["geoms"]:
+        if g["type"] == "box" and g["body"] in feet:
+            g.update(condim=4, friction_spin=0.02)
+    return m
+
+
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
                 "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
                 "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp, "quadruped_slip": quadruped_slip,
-                "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld}
+                "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld,
+                "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4}
 
 
 def by_name(name: str) -> dict:
