@@ -123,6 +123,8 @@ struct Model {
     double grav[3] = {0, 0, -9.81};
     int iters = 4;
     double tol = 1e-8;
+    int cone = 0;             // 0 pyramidal, 1 elliptic friction cones
+    double impratio = 1.0;    // elliptic cones: ratio of frictional to normal impedance
     double solref[2] = {0.02, 1.0};
     double solimp[5] = {0.9, 0.95, 0.001, 0.5, 2.0};
     bool fr_pw = false, ms_pw = false;
@@ -160,6 +162,9 @@ struct Data {
     std::vector<int> row_id;        // per row: 4 c + e (pyramid row e of contact c), 256 + dof (limit),
                                     // 512 + 6 q + k (row k of equality q)
     std::vector<char> bilat;        // per row: bilateral (equality rows: active on both sides)
+    std::vector<char> ell;          // per row: one of an elliptic contact's rows (costed per contact)
+    std::vector<int> ell_row0;      // per elliptic contact: its first row (normal, then t1, t2)
+    std::vector<double> ell_mu;     // per elliptic contact: cone slope mu / sqrt(impratio)
     std::vector<int> row_nnz;       // per row: non-zero Jacobian entries (the dofs it touches)
     int segments = 0;               // quadratic pieces the line searches examined
     int active_final = 0;           // rows active at the solution
@@ -878,12 +883,15 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
     int nr = 0;
     for (int ci = 0; ci < nc; ci++) {
         d.crow[ci] = nr;
-        nr += d.con[ci].dim == 1 ? 1 : 2 * (d.con[ci].dim - 1);
+        nr += d.con[ci].dim == 1 ? 1 : (m.cone == 1 ? d.con[ci].dim : 2 * (d.con[ci].dim - 1));
     }
     int ne = 0;
     for (int q = 0; q < m.neq; q++) ne += m.eqtype[q] == RBO_EQ_WELD ? 6 : 3;
     d.nrows = nr + nl + ne;
     d.bilat.assign(d.nrows, 0);
+    d.ell.assign(d.nrows, 0);
+    d.ell_row0.clear();
+    d.ell_mu.clear();
     d.J.assign((size_t)d.nrows * nv, 0.0);
     d.row_id.assign(d.nrows, 0);
     d.row_nnz.assign(d.nrows, 0);
@@ -930,6 +938,23 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
                     Jc[(3 + r) * nv + k] = acc;
                 }
         double rdist = c.dist - std::max(m.gmargin[c.g1], m.gmargin[c.g2]);
+        if (m.cone == 1 && c.dim == 3) {
+            // elliptic cone: the frame rows themselves; the normal row takes the distance
+            // reference, the tangential rows none, and their regulariser is the normal row's
+            // divided by impratio (which makes the cone circular in the rows' D-scaled
+            // coordinates: slope mu / sqrt(impratio))
+            for (int e = 0; e < 3; e++) {
+                int row = d.crow[ci] + e;
+                std::copy(&Jc[e * nv], &Jc[e * nv] + nv, &d.J[(size_t)row * nv]);
+                d.row_id[row] = 4 * ci + e;
+                d.ell[row] = 1;
+                finish_row(row, e == 0 ? rdist : 0.0);
+                if (e > 0) d.D[row] = d.D[d.crow[ci]] * m.impratio;
+            }
+            d.ell_row0.push_back(d.crow[ci]);
+            d.ell_mu.push_back(c.mu / std::sqrt(m.impratio));
+            continue;
+        }
         // pyramid row pairs J_n +- mu_d J_d over the friction directions d: sliding t1, t2
         // (mu), then spin about n (mu_spin), then rolling about t1, t2 (mu_roll)
         const int nrow_c = c.dim == 1 ? 1 : 2 * (c.dim - 1);
@@ -985,19 +1010,83 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
 }
 
 // ------------------------------------------------------------------------------------
-// primal Newton solver on f(a) = 0.5 (a-a0)'M(a-a0) + sum_e 0.5 D_e min(J_e a - aref_e, 0)^2
+// Soft elliptic cone of one contact.  The contact's force is the projection of -D jar onto the
+// friction cone in the metric of the regulariser R = D^-1; with x = sqrt(D) jar the cone is the
+// circular one of slope mu (mu the contact's scaled slope), and the cost is half the squared
+// norm of the projection of -x onto it:
+//   top zone, mu |x_t| <= x_n (separating): 0;
+//   bottom zone, |x_t| <= -mu x_n (inside the cone): |x|^2 / 2 (every row active);
+//   middle zone: (mu |x_t| - x_n)^2 / (2 (1 + mu^2)) (the force on the cone's surface).
+// Returns the zone (0 top, 1 middle, 2 bottom); g = ds/djar, h = d2s/djar2 (3x3, row-major).
 // ------------------------------------------------------------------------------------
+int ell_eval(const double* jar, const double* D, double mu, double* s, double* g, double* h) {
+    double sq[3], x[3];
+    for (int a = 0; a < 3; a++) {
+        sq[a] = std::sqrt(D[a]);
+        x[a] = sq[a] * jar[a];
+    }
+    const double N = x[0], T = std::sqrt(x[1] * x[1] + x[2] * x[2]);
+    std::fill(g, g + 3, 0.0);
+    std::fill(h, h + 9, 0.0);
+    *s = 0;
+    if (mu * T <= N) return 0;
+    if (T <= -mu * N) {
+        *s = 0.5 * (x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        for (int a = 0; a < 3; a++) {
+            g[a] = D[a] * jar[a];
+            h[4 * a] = D[a];
+        }
+        return 2;
+    }
+    const double c = 1.0 / (1.0 + mu * mu), hh = mu * T - N;
+    const double u[3] = {0.0, x[1] / T, x[2] / T};
+    const double w[3] = {-1.0, mu * u[1], mu * u[2]};   // gradient of hh in x
+    *s = 0.5 * c * hh * hh;
+    for (int a = 0; a < 3; a++) {
+        g[a] = sq[a] * c * hh * w[a];
+        for (int b = 0; b < 3; b++) {
+            // c (w w' + hh mu / T (I - u u') on the tangential block)
+            double hx = w[a] * w[b];
+            if (a > 0 && b > 0) hx += hh * mu / T * ((a == b ? 1.0 : 0.0) - u[a] * u[b]);
+            h[3 * a + b] = sq[a] * sq[b] * c * hx;
+        }
+    }
+    return 1;
+}
+
+// ------------------------------------------------------------------------------------
+// primal Newton solver on f(a) = 0.5 (a-a0)'M(a-a0) + sum_e 0.5 D_e min(J_e a - aref_e, 0)^2
+// (bilateral rows: the whole residual; elliptic contacts: their cone cost above)
+// ------------------------------------------------------------------------------------
+double constraint_cost(const Data& d, const std::vector<double>& jar) {
+    double f = 0;
+    for (int e = 0; e < d.nrows; e++)
+        if (!d.ell[e] && (jar[e] < 0 || d.bilat[e])) f += 0.5 * d.D[e] * jar[e] * jar[e];
+    for (size_t k = 0; k < d.ell_row0.size(); k++) {
+        const int r0 = d.ell_row0[k];
+        double sc, g[3], h[9];
+        ell_eval(&jar[r0], &d.D[r0], d.ell_mu[k], &sc, g, h);
+        f += sc;
+    }
+    return f;
+}
+
+std::vector<double> residuals(const Model& m, const Data& d, const double* a) {
+    std::vector<double> jar(d.nrows);
+    for (int e = 0; e < d.nrows; e++) {
+        double t = -d.aref[e];
+        for (int k = 0; k < m.nv; k++) t += d.J[(size_t)e * m.nv + k] * a[k];
+        jar[e] = t;
+    }
+    return jar;
+}
+
 double cost(const Model& m, const Data& d, const double* a) {
     int nv = m.nv;
     double f = 0;
     for (int r = 0; r < nv; r++)
         for (int s = 0; s < nv; s++) f += 0.5 * (a[r] - d.a0[r]) * d.M[r * nv + s] * (a[s] - d.a0[s]);
-    for (int e = 0; e < d.nrows; e++) {
-        double jar = -d.aref[e];
-        for (int k = 0; k < nv; k++) jar += d.J[(size_t)e * nv + k] * a[k];
-        if (jar < 0 || d.bilat[e]) f += 0.5 * d.D[e] * jar * jar;
-    }
-    return f;
+    return f + constraint_cost(d, residuals(m, d, a));
 }
 
 // exact minimiser over alpha >= 0 of the convex piecewise quadratic phi(alpha) = f(a + alpha p)
@@ -1047,6 +1136,65 @@ double line_search(const Model& m, const Data& d, const std::vector<double>& jar
     }
 }
 
+// Minimiser over alpha >= 0 of phi(alpha) = f(a + alpha p) when elliptic contacts make phi
+// convex and continuously differentiable but not piecewise quadratic: Newton's method on
+// phi'(alpha) = 0 safeguarded by the bracket [lo, hi] of a sign change (bisection when a Newton
+// step leaves it), from alpha = 0, until |phi'| <= 1e-13 |phi'(0)| or the bracket closes.
+double line_search_smooth(const Model& m, const Data& d, const std::vector<double>& jar,
+                          const std::vector<double>& p, int* nseg) {
+    int nv = m.nv, nr = d.nrows;
+    std::vector<double> s(nr, 0.0), Mp(nv, 0.0);
+    for (int e = 0; e < nr; e++)
+        for (int k = 0; k < nv; k++) s[e] += d.J[(size_t)e * nv + k] * p[k];
+    for (int r = 0; r < nv; r++)
+        for (int k = 0; k < nv; k++) Mp[r] += d.M[r * nv + k] * p[k];
+    double A0 = 0, B0 = 0;
+    for (int k = 0; k < nv; k++) {
+        A0 += p[k] * Mp[k];
+        B0 += (d.a[k] - d.a0[k]) * Mp[k];
+    }
+    if (!(A0 > 0)) return 0.0;
+    // phi'(alpha) and phi''(alpha) (the right derivative at zone changes)
+    auto dphi = [&](double al, double* d2) {
+        double d1 = al * A0 + B0;
+        *d2 = A0;
+        for (int e = 0; e < nr; e++) {
+            if (d.ell[e]) continue;
+            const double j = jar[e] + al * s[e];
+            if (j < 0 || (j == 0 && s[e] < 0) || d.bilat[e]) {
+                d1 += d.D[e] * s[e] * j;
+                *d2 += d.D[e] * s[e] * s[e];
+            }
+        }
+        for (size_t k = 0; k < d.ell_row0.size(); k++) {
+            const int r0 = d.ell_row0[k];
+            double j[3], sc, g[3], h[9];
+            for (int a = 0; a < 3; a++) j[a] = jar[r0 + a] + al * s[r0 + a];
+            ell_eval(j, &d.D[r0], d.ell_mu[k], &sc, g, h);
+            for (int a = 0; a < 3; a++) {
+                d1 += g[a] * s[r0 + a];
+                for (int b = 0; b < 3; b++) *d2 += s[r0 + a] * h[3 * a + b] * s[r0 + b];
+            }
+        }
+        return d1;
+    };
+    double d2, d1 = dphi(0.0, &d2);
+    if (!(d1 < 0)) return 0.0;
+    const double tolg = 1e-13 * std::fabs(d1);
+    double lo = 0, hi = INFINITY, al = 0;
+    for (int k = 0; k < 100; k++) {
+        if (nseg) ++*nseg;
+        if (std::fabs(d1) <= tolg) break;
+        if (d1 < 0) lo = al; else hi = al;
+        if (std::isfinite(hi) && hi - lo <= 1e-15 * hi) break;
+        double nxt = al - d1 / d2;
+        if (!(nxt > lo && nxt < hi)) nxt = std::isfinite(hi) ? 0.5 * (lo + hi) : 2 * std::max(lo, 1.0);
+        al = nxt;
+        d1 = dphi(al, &d2);
+    }
+    return al;
+}
+
 void newton(const Model& m, Data& d) {
     int nv = m.nv, nr = d.nrows;
     int maxiter = m.mode == 1 ? 100 : m.iters;
@@ -1080,21 +1228,44 @@ void newton(const Model& m, Data& d) {
         }
         H = d.M;
         for (int e = 0; e < nr; e++) {
-            if (!(jar[e] < 0) && !d.bilat[e]) continue;
+            if (d.ell[e] || (!(jar[e] < 0) && !d.bilat[e])) continue;
             const double* Je = &d.J[(size_t)e * nv];
             for (int r = 0; r < nv; r++) {
                 g[r] += d.D[e] * jar[e] * Je[r];
                 for (int k = 0; k < nv; k++) H[r * nv + k] += d.D[e] * Je[r] * Je[k];
             }
         }
+        // elliptic contacts: J_c' ds/djar and J_c' h J_c over their three rows
+        std::vector<int> ell_zone(d.ell_row0.size());
+        for (size_t c = 0; c < d.ell_row0.size(); c++) {
+            const int r0 = d.ell_row0[c];
+            double sc, ge[3], he[9];
+            ell_zone[c] = ell_eval(&jar[r0], &d.D[r0], d.ell_mu[c], &sc, ge, he);
+            for (int a = 0; a < 3; a++) {
+                const double* Ja = &d.J[(size_t)(r0 + a) * nv];
+                for (int r = 0; r < nv; r++) g[r] += ge[a] * Ja[r];
+                for (int b = 0; b < 3; b++) {
+                    const double* Jb = &d.J[(size_t)(r0 + b) * nv];
+                    if (he[3 * a + b] == 0) continue;
+                    for (int r = 0; r < nv; r++)
+                        for (int k = 0; k < nv; k++) H[r * nv + k] += he[3 * a + b] * Ja[r] * Jb[k];
+                }
+            }
+        }
         double gn = 0;
         for (int k = 0; k < nv; k++) gn += g[k] * g[k];
         if (std::sqrt(gn) / scale < tol) { stopped = true; break; }
         // record the active set this update is built from
+        // (an elliptic contact's three rows are active unless it is in its top zone)
         std::vector<int> act;
         uint32_t fp = 0;
+        auto ell_active = [&](int e) {
+            for (size_t c = 0; c < d.ell_row0.size(); c++)
+                if (e >= d.ell_row0[c] && e < d.ell_row0[c] + 3) return ell_zone[c] != 0;
+            return false;
+        };
         for (int e = 0; e < nr; e++)
-            if (jar[e] < 0 || d.bilat[e]) {
+            if (d.ell[e] ? ell_active(e) : (jar[e] < 0 || d.bilat[e])) {
                 act.push_back(e);
                 fp += ((uint32_t)d.row_id[e] + 1u) * 2654435761u;
             }
@@ -1104,22 +1275,33 @@ void newton(const Model& m, Data& d) {
         std::vector<double> ng(nv);
         for (int k = 0; k < nv; k++) ng[k] = -g[k];
         chol_solve(LH, nv, ng.data(), p.data());
-        double alpha = line_search(m, d, jar, p, &d.segments);
+        double alpha = d.ell_row0.empty() ? line_search(m, d, jar, p, &d.segments)
+                                          : line_search_smooth(m, d, jar, p, &d.segments);
         double fold = cost(m, d, d.a.data());
         for (int k = 0; k < nv; k++) anew[k] = d.a[k] + alpha * p[k];
         double fnew = cost(m, d, anew.data());
         d.a = anew;
         d.niter = it + 1;
-        if ((fold - fnew) / scale < tol) { stopped = true; break; }
+        // (the converged mode stops on the gradient alone: with elliptic cones the cost is not
+        // piecewise quadratic, and a small improvement does not yet mean a small gradient)
+        if (m.mode != 1 && (fold - fnew) / scale < tol) { stopped = true; break; }
     }
     d.itercap = !stopped && maxiter > 0;
     d.cost = cost(m, d, d.a.data());
     d.efc_force.assign(nr, 0.0);
+    const std::vector<double> jf = residuals(m, d, d.a.data());
     for (int e = 0; e < nr; e++) {
-        double t = -d.aref[e];
-        for (int k = 0; k < nv; k++) t += d.J[(size_t)e * nv + k] * d.a[k];
+        if (d.ell[e]) continue;
+        const double t = jf[e];
         d.efc_force[e] = -d.D[e] * (d.bilat[e] ? t : std::min(t, 0.0));
         d.active_final += t < 0 || d.bilat[e];
+    }
+    for (size_t c = 0; c < d.ell_row0.size(); c++) {
+        const int r0 = d.ell_row0[c];
+        double sc, ge[3], he[9];
+        const int zone = ell_eval(&jf[r0], &d.D[r0], d.ell_mu[c], &sc, ge, he);
+        for (int a = 0; a < 3; a++) d.efc_force[r0 + a] = -ge[a];
+        d.active_final += zone != 0 ? 3 : 0;
     }
 }
 
@@ -1278,6 +1460,10 @@ void forward(const Model& m, Data& d) {
         double mu = d.con[ci].mu;
         if (d.con[ci].dim == 1) {
             d.cforce[3 * ci] = f[0];
+            continue;
+        }
+        if (m.cone == 1) {   // elliptic: the rows' forces are the frame components
+            for (int a = 0; a < 3; a++) d.cforce[3 * ci + a] = f[a];
             continue;
         }
         // every pyramid row carries the normal direction once
@@ -1544,6 +1730,13 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
     M.fr_pw = dsc->friction_per_world != 0;
     M.ms_pw = dsc->mass_scale_per_world != 0;
     if (!(M.dt > 0) || M.K < 1 || M.iters < 0) return bad("bad options");
+    M.cone = dsc->cone;
+    M.impratio = dsc->impratio;
+    if (M.cone != 0 && M.cone != 1) return bad("cone must be pyramidal (0) or elliptic (1)");
+    if (!(M.impratio > 0) || !std::isfinite(M.impratio)) return bad("impratio must be positive");
+    if (M.cone == 1)
+        for (int g = 0; g < ng; g++)
+            if (M.gcondim[g] != 1 && M.gcondim[g] != 3) return bad("elliptic cones take condim 1 or 3");
     // mean diagonal inertia at the reference configuration (free joints at their body pose)
     if (M.nv > 0) {
         Data d(&M);

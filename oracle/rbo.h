@@ -86,6 +86,11 @@ typedef struct rbo_desc {
     /* torsional and rolling friction coefficients [ngeom] (>= 0), or NULL for 0.005 and 0.0001;
        a pair takes the larger of its two geoms' and uses them when its condim is 4 or 6 */
     const double *geom_friction_spin, *geom_friction_roll;
+    /* friction cones: 0 pyramidal (2 (condim - 1) rows per contact), 1 elliptic (condim 1 or 3:
+       the frame rows themselves, costed per contact by the soft elliptic cone, the tangential
+       rows' regulariser the normal row's divided by impratio > 0) */
+    int32_t cone;
+    double impratio;
 } rbo_desc;
 
 typedef struct rbo_info {
