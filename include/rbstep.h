@@ -50,6 +50,7 @@ enum { RB_GEOM_PLANE = 0, RB_GEOM_SPHERE = 1, RB_GEOM_CAPSULE = 2, RB_GEOM_BOX =
 enum { RB_JNT_FREE = 0, RB_JNT_HINGE = 1 };
 enum { RB_ACT_POSITION = 0, RB_ACT_MOTOR = 1 };
 enum { RB_EQ_CONNECT = 0, RB_EQ_WELD = 1 };
+enum { RB_CONE_PYRAMIDAL = 0, RB_CONE_ELLIPTIC = 1 };
 enum {
     RB_PARAM_FRICTION = 0,   /* [n]: friction of every contact of the world (model flag) */
     RB_PARAM_MASS_SCALE = 1, /* [n, nbody]: body mass and rotational inertia scale (model flag) */
@@ -127,6 +128,15 @@ typedef struct rb_model_desc {
      * paper, section "Architecture", paragraph on the GPU physics backend (the contact model of
      * the simulator it builds on). */
     const double *geom_friction_spin, *geom_friction_roll;
+    /* friction cones: RB_CONE_PYRAMIDAL (2 (condim - 1) pyramid rows per contact) or
+     * RB_CONE_ELLIPTIC (condim 1 or 3 only): a contact's frame rows (normal, t1, t2) costed
+     * together by the soft elliptic cone, its force the projection of -D jar onto the friction
+     * cone {|f_t| <= mu f_n} in the metric of D^-1; the tangential rows have no distance
+     * reference and the normal row's D times impratio (> 0; 1 when 0 is given).  Cites: paper,
+     * section "Architecture", paragraph on the GPU physics backend (the constraint model of the
+     * simulator it builds on). */
+    int32_t cone;
+    double impratio;
 } rb_model_desc;
 
 typedef struct rb_model rb_model;
@@ -176,7 +186,8 @@ int rb_model_create(const rb_model_desc* desc, rb_model** out);
  * "Architecture", paragraph "Scene pipeline" (a scene description compiled into a model).
  * The text is an object with
  *   "opt": {"timestep", "nsubsteps", "gravity": [3], "iterations", "tolerance",
- *           "solref": [2], "solimp": [5]},
+ *           "solref": [2], "solimp": [5], "cone": "pyramidal" | "elliptic", "impratio"
+ *           (the last two optional)},
  *   "bodies": [{"parent", "pos": [3], "quat": [4], "ipos": [3], "iquat": [4], "mass",
  *               "inertia": [3]}, ...]   (body 0 = world),
  *   "joints": [{"type": "free" | "hinge", "body", "pos": [3], "axis": [3], "armature",

@@ -1256,19 +1256,22 @@ void newton(const Model& m, Data& d) {
         for (int k = 0; k < nv; k++) gn += g[k] * g[k];
         if (std::sqrt(gn) / scale < tol) { stopped = true; break; }
         // record the active set this update is built from
-        // (an elliptic contact's three rows are active unless it is in its top zone)
+        // (an elliptic contact's three rows are active unless it is in its top zone; inside the
+        // cone they enter the fingerprint as 2048 + id, so that its zone is recorded too)
         std::vector<int> act;
         uint32_t fp = 0;
-        auto ell_active = [&](int e) {
+        auto ell_zone_of = [&](int e) {
             for (size_t c = 0; c < d.ell_row0.size(); c++)
-                if (e >= d.ell_row0[c] && e < d.ell_row0[c] + 3) return ell_zone[c] != 0;
-            return false;
+                if (e >= d.ell_row0[c] && e < d.ell_row0[c] + 3) return ell_zone[c];
+            return 0;
         };
-        for (int e = 0; e < nr; e++)
-            if (d.ell[e] ? ell_active(e) : (jar[e] < 0 || d.bilat[e])) {
+        for (int e = 0; e < nr; e++) {
+            const int zone = d.ell[e] ? ell_zone_of(e) : 0;
+            if (d.ell[e] ? zone != 0 : (jar[e] < 0 || d.bilat[e])) {
                 act.push_back(e);
-                fp += ((uint32_t)d.row_id[e] + 1u) * 2654435761u;
+                fp += ((uint32_t)d.row_id[e] + (zone == 2 ? 2048u : 0u) + 1u) * 2654435761u;
             }
+        }
         if (it < RBO_FPITER) d.fp[it] = fp;
         d.act_iter.push_back(act);
         if (!cholesky(H, nv, LH)) { stopped = true; break; }

@@ -2,7 +2,7 @@
 // grouped per body / joint / geom / actuator), parsed on the host into an rb_model_desc.
 //
 // {"opt": {"timestep", "nsubsteps", "gravity": [3], "iterations", "tolerance",
-//          "solref": [2], "solimp": [5]},
+//          "solref": [2], "solimp": [5], "cone": "pyramidal"|"elliptic", "impratio" (optional)},
 //  "bodies": [{"parent", "pos": [3], "quat": [4], "ipos": [3], "iquat": [4], "mass",
 //              "inertia": [3]}, ...],                    body 0 is the world
 //  "joints": [{"type": "free"|"hinge", "body", "pos": [3], "axis": [3], "armature",
@@ -281,6 +281,14 @@ int rb_model_create_json(const char* json, rb_model** out) {
         return rb_record_error(RB_EINVAL, "model JSON: opt nsubsteps and iterations must be integers");
     d.nsubsteps = (int32_t)nsub;
     d.iterations = (int32_t)iters;
+    d.impratio = 1.0;
+    if (opt->obj.count("cone")) {
+        static const char* const cnames[] = {"pyramidal", "elliptic"};
+        if (!R.choice(*opt, "cone", "opt", cnames, 2, &d.cone))
+            return rb_record_error(RB_EINVAL, ("model JSON: " + R.err).c_str());
+    }
+    if (opt->obj.count("impratio") && !R.num(*opt, "impratio", "opt", &d.impratio))
+        return rb_record_error(RB_EINVAL, ("model JSON: " + R.err).c_str());
     auto pw = root.obj.find("per_world");
     if (pw != root.obj.end() && pw->second.kind == JVal::OBJ) {
         auto f = pw->second.obj.find("friction");

@@ -118,6 +118,8 @@ struct DevModel {
     // equality constraints with the world [neq]; their rows [neqrow] (connect 3, weld 6)
     int neq, neqrow;
     int nxmax;                 // bound on the contacts' torsional / rolling rows (condim 4, 6 pairs)
+    int cone;                  // 0 pyramidal, 1 elliptic friction cones (extended code)
+    float impratio, rsqrt_impratio;
     const int* pair_xrows;     // per pair: 0, 2 (condim 4) or 6 (condim 6) rows per contact
     const float* pair_mu_spin;
     const float* pair_mu_roll;

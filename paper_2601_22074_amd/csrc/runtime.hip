@@ -449,6 +449,12 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     }
     // options
     if (!(d->timestep > 0) || d->nsubsteps < 1 || d->iterations < 0) return fail(RB_EINVAL, "bad options");
+    if (d->cone != RB_CONE_PYRAMIDAL && d->cone != RB_CONE_ELLIPTIC)
+        return fail(RB_EINVAL, "cone must be RB_CONE_PYRAMIDAL or RB_CONE_ELLIPTIC");
+    const double impratio = d->impratio == 0 ? 1.0 : d->impratio;
+    if (!(impratio > 0) || !std::isfinite(impratio)) return fail(RB_EINVAL, "impratio must be positive");
+    if (d->cone == RB_CONE_ELLIPTIC && nxmax > 0)
+        return fail(RB_EINVAL, "elliptic cones take condim 1 or 3");
     double dmax = std::min(std::max(d->solimp[1], 1e-4), 0.9999);
     double tc = std::max(d->solref[0], 2 * d->timestep), zeta = d->solref[1];
     // mean diagonal inertia at the reference configuration: composite inertias in double
@@ -675,7 +681,10 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.nlim = nlim;
     m.ndamp = ndamp;
     m.neq = d->neq; m.neqrow = neqrow; m.nxmax = nxmax;
-    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE || neqrow > 0 || nxmax > 0 ||
+    m.cone = d->cone == RB_CONE_ELLIPTIC && npair > 0 ? 1 : 0;
+    m.impratio = (float)impratio;
+    m.rsqrt_impratio = (float)(1.0 / std::sqrt(impratio));
+    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE || neqrow > 0 || nxmax > 0 || m.cone ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_CAPSULEBOX) > 0 ||
              std::count_if(ptype.begin(), ptype.end(), [](int t) { return t >= RB_PAIR_HFIELD; }) > 0 ||

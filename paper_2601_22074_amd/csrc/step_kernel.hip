@@ -433,18 +433,58 @@ struct Con {
     float D[4], aref[4], jar[4];
 };
 
-// velocity of the contact's pyramid rows for body spatial motions `bm` (already includes sign)
-DEV void rows_of(const Con& c, const float* bm, float* out) {
+// velocity of the contact's pyramid rows for body spatial motions `bm` (already includes sign);
+// of its frame rows (normal, t1, t2, then 0) for an elliptic-cone contact
+DEV void rows_of(const Con& c, const float* bm, float* out, bool ell = false) {
     const float* sv = bm + 6 * c.body;
     float wr[3], t2[3];
     cross(sv, c.r, wr);
     cross(c.n, c.t1, t2);
     float vp[3] = {sv[3] + wr[0], sv[4] + wr[1], sv[5] + wr[2]};
     float vn = c.sigma * dot(c.n, vp), v1 = c.sigma * dot(c.t1, vp), v2 = c.sigma * dot(t2, vp);
+    if (ell) {
+        out[0] = vn; out[1] = v1; out[2] = v2; out[3] = 0.f;
+        return;
+    }
     out[0] = vn + c.mu * v1;
     out[1] = vn - c.mu * v1;
     out[2] = vn + c.mu * v2;
     out[3] = vn - c.mu * v2;
+}
+
+// Soft elliptic cone of one contact at the frame-row residuals jar (normal, t1, t2), with
+// regulariser inverses D0 (normal) and Dt (tangential) and cone slope mu: with x = sqrt(D) jar,
+// cost 0 when mu |x_t| <= x_n (separating), |x|^2 / 2 when |x_t| <= -mu x_n (inside the cone),
+// else (mu |x_t| - x_n)^2 / (2 (1 + mu^2)) (the force on the cone's surface).  Returns the zone
+// (0, 1 surface, 2 inside) and the cost; g = d cost / d jar, h its Hessian (h00 h01 h02 h11 h12
+// h22).
+DEV int ell_eval(const float* jar, float D0, float Dt, float mu, float* cost, float* g, float* h) {
+    const float s0 = sqrtf(D0), st = sqrtf(Dt);
+    const float N = s0 * jar[0], x1 = st * jar[1], x2 = st * jar[2];
+    const float T = sqrtf(x1 * x1 + x2 * x2);
+    for (int k = 0; k < 3; k++) g[k] = 0.f;
+    for (int k = 0; k < 6; k++) h[k] = 0.f;
+    *cost = 0.f;
+    if (mu * T <= N) return 0;
+    if (T <= -mu * N) {
+        *cost = 0.5f * (N * N + x1 * x1 + x2 * x2);
+        g[0] = D0 * jar[0]; g[1] = Dt * jar[1]; g[2] = Dt * jar[2];
+        h[0] = D0; h[3] = Dt; h[5] = Dt;
+        return 2;
+    }
+    const float c = 1.f / (1.f + mu * mu), hh = mu * T - N, iT = 1.f / T;
+    const float u1 = x1 * iT, u2 = x2 * iT;
+    const float w0 = -1.f, w1 = mu * u1, w2 = mu * u2;      // gradient of hh in x
+    const float k = hh * mu * iT;                            // curvature of |x_t| across the cone
+    *cost = 0.5f * c * hh * hh;
+    g[0] = s0 * c * hh * w0; g[1] = st * c * hh * w1; g[2] = st * c * hh * w2;
+    h[0] = D0 * c * w0 * w0;
+    h[1] = s0 * st * c * w0 * w1;
+    h[2] = s0 * st * c * w0 * w2;
+    h[3] = Dt * c * (w1 * w1 + k * (1.f - u1 * u1));
+    h[4] = Dt * c * (w1 * w2 - k * u1 * u2);
+    h[5] = Dt * c * (w2 * w2 + k * (1.f - u2 * u2));
+    return 1;
 }
 
 DEV void contact_frame(const float* n, float* t1) {
@@ -1283,6 +1323,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         } else {
             C.body = 0;
         }
+        // an elliptic-cone contact (extended code): frame rows costed by the soft elliptic cone;
+        // frictionless contacts keep their one normal row
+        const bool cell = EXT && m.cone && has && !(C.ids >> 24);
         RB_STAGE(3);
         // generic-row slots of the contacts' extra rows: after the equality rows, in contact order
         float* GR = L + m.o_gr;
@@ -1362,7 +1405,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     }
             }
             float vrow[4];
-            rows_of(C, cvel, vrow);
+            rows_of(C, cvel, vrow, cell);
             float rd = C.dist - margin_c;
             float imp = impedance(m, rd);
             float mu = C.mu, mu2 = mu * mu;
@@ -1375,6 +1418,19 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 C.D[e] = 1.0f / R;
             }
             if (EXT && (C.ids >> 24)) C.D[1] = C.D[2] = C.D[3] = 0.f;
+            if (cell) {
+                // elliptic cone: the frame rows, the distance reference on the normal only, the
+                // tangential regulariser the normal's divided by impratio
+                const float D0 = 1.0f / fmaxf(1e-15f, (1.0f - imp) / imp * A00);
+                C.aref[0] = -m.bref * vrow[0] - m.kref * imp * rd;
+                C.aref[1] = -m.bref * vrow[1];
+                C.aref[2] = -m.bref * vrow[2];
+                C.aref[3] = 0.f;
+                C.D[0] = D0;
+                C.D[1] = C.D[2] = m.impratio * D0;
+                C.D[3] = 0.f;
+                ah[0] = A00; ah[1] = A11; ah[2] = A22; ah[3] = 0.f;
+            }
             if (TIMED && A.want_taps && sub == 0 && A.taps.efc) {
                 float* E = A.taps.efc + ((size_t)w * m.ncap + lane) * 12;
                 for (int e = 0; e < 4; e++) {
@@ -1575,14 +1631,26 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             body_motion(m, BL, DL, cdof, a0, bvec, lane);
             float j0[4] = {0, 0, 0, 0};
             float f0 = 0.f;
-            if (has) {
-                rows_of(C, bvec, j0);
+            // the lane's contact cost at residuals j: pyramid rows, or the elliptic cone
+            auto con_cost = [&](const float* j) {
+                if (cell) {
+                    float cst, ge[3], he[6];
+                    ell_eval(j, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he);
+                    return cst;
+                }
+                float cst = 0.f;
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    j0[e] -= C.aref[e];
-                    float mn = fminf(j0[e], 0.f);
-                    f0 += 0.5f * C.D[e] * mn * mn;
+                    const float mn = fminf(j[e], 0.f);
+                    cst += 0.5f * C.D[e] * mn * mn;
                 }
+                return cst;
+            };
+            if (has) {
+                rows_of(C, bvec, j0, cell);
+#pragma unroll
+                for (int e = 0; e < 4; e++) j0[e] -= C.aref[e];
+                f0 += con_cost(j0);
             }
             // limit rows at a0 and at the warm start (their residuals are linear in a too);
             // recomputed from LDS where needed rather than held across the tree passes
@@ -1615,13 +1683,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             float jw[4] = {0, 0, 0, 0};
             float fw = 0.f;
             if (has) {
-                rows_of(C, bvec, jw);
+                rows_of(C, bvec, jw, cell);
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    jw[e] += j0[e];
-                    float mn = fminf(jw[e], 0.f);
-                    fw += 0.5f * C.D[e] * mn * mn;
-                }
+                for (int e = 0; e < 4; e++) jw[e] += j0[e];
+                fw += con_cost(jw);
             }
             float qf = 0.f;
             for (int i = lane; i < nv; i += RB_WAVE) qf += tmp[i] * g[i];
@@ -1658,13 +1723,21 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 // the gradient vanishes (in exact arithmetic; the FP32 gradient does not reach
                 // the tolerance, so this is the test that ends the iteration).
                 uint32_t bits = 0;
-                if (has) {
+                bool mid = false;   // an elliptic contact on its cone's surface: cost not quadratic
+                if (cell) {
+                    float cst, ge[3], he[6];
+                    const int zone = ell_eval(C.jar, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he);
+                    bits = (uint32_t)zone;
+                    mid = zone == 1;
+                } else if (has) {
 #pragma unroll
                     for (int e = 0; e < 4; e++) bits |= (C.jar[e] < 0.f ? 1u : 0u) << e;
                 }
                 if (limact && lane < nv) bits |= (ljar[lane] < 0.f ? 1u : 0u) << 4;
                 if (grown && !grbil) bits |= (Er[7] < 0.f ? 1u : 0u) << 5;
-                if (it > 0 && __ballot(bits != prev_bits) == 0) break;
+                // (with a contact on its cone's surface the cost is not piecewise quadratic, and
+                // an unchanged active set does not mean the minimum was reached)
+                if (it > 0 && __ballot(bits != prev_bits) == 0 && __ballot(mid) == 0) break;
                 prev_bits = bits;
                 // gradient and the contact part of the Hessian, one contact at a time
                 float gc = 0.f;
@@ -1686,7 +1759,29 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     cross(n, t1, t2);
                     for (int e = 0; e < 4; e++) { D[e] = rl(C.D[e], c); jar[e] = rl(C.jar[e], c); }
                     float mu = rl(C.mu, c), sg = rl(C.sigma, c);
-                    if (dof_lane && ((mask >> lane) & 1ull)) {
+                    // an elliptic contact: its cost's gradient and Hessian in its frame rows
+                    const bool ellc = EXT && m.cone && !(__builtin_amdgcn_readlane(C.ids, c) >> 24);
+                    float ge[3], he[6];
+                    if (ellc) {
+                        float cst;
+                        ell_eval(jar, D[0], D[1], mu * m.rsqrt_impratio, &cst, ge, he);
+                    }
+                    if (ellc && dof_lane && ((mask >> lane) & 1ull)) {
+                        float wr[3];
+                        cross(S, r, wr);
+                        const float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                        const float jn = sg * dot(n, vp), j1 = sg * dot(t1, vp), j2 = sg * dot(t2, vp);
+                        gc += ge[0] * jn + ge[1] * j1 + ge[2] * j2;
+                        // Hessian term: the rows' directions weighted by h je, as a spatial force
+                        const float u0 = he[0] * jn + he[1] * j1 + he[2] * j2;
+                        const float u1 = he[1] * jn + he[3] * j1 + he[4] * j2;
+                        const float u2 = he[2] * jn + he[4] * j1 + he[5] * j2;
+                        float a[3], ra[3];
+                        for (int k = 0; k < 3; k++) a[k] = sg * (u0 * n[k] + u1 * t1[k] + u2 * t2[k]);
+                        cross(r, a, ra);
+                        F[0] += ra[0]; F[1] += ra[1]; F[2] += ra[2];
+                        F[3] += a[0]; F[4] += a[1]; F[5] += a[2];
+                    } else if (!ellc && dof_lane && ((mask >> lane) & 1ull)) {
                         float wr[3];
                         cross(S, r, wr);
                         float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
@@ -1743,7 +1838,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     // of (id + 1) * 2654435761 mod 2^32, id = 4 c + e for pyramid row e of contact c
                     // (a frictionless contact's one row is e = 0), 256 + dof for a limit row
                     uint32_t fpl = 0;
-                    if (has) {
+                    if (cell) {
+                        // an elliptic contact's three rows count unless it separates (zone 0),
+                        // as 2048 + id inside the cone (zone 2)
+                        if (bits != 0)
+                            for (int e = 0; e < 3; e++)
+                                fpl += (uint32_t)(4 * lane + e + (bits == 2 ? 2048 : 0) + 1) * 2654435761u;
+                    } else if (has) {
 #pragma unroll
                         for (int e = 0; e < 4; e++)
                             if (C.jar[e] < 0.f && (e == 0 || !(EXT && (C.ids >> 24))))
@@ -1786,7 +1887,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 // directional quantities for the line search
                 spatial_mul(m, BL, DL, cdof, cinert, p, bvec, cvel, Mp, lane);
                 float sr[4] = {0, 0, 0, 0};
-                if (has) rows_of(C, bvec, sr);
+                if (has) rows_of(C, bvec, sr, cell);
                 float pa = 0.f, pb = 0.f;
                 if (dof_lane) {
                     pa = p[lane] * Mp[lane];
@@ -1819,6 +1920,64 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     const bool gu = grown && !grbil;
                     const float gj = gu ? Er[7] : 0.f, gD = gu ? Er[6] : 0.f;
                     const float gbp = (gu && gsr != 0.f) ? -gj * __builtin_amdgcn_rcpf(gsr) : INFINITY;
+                    if (EXT && m.cone && ncon > 0) {
+                        // elliptic contacts make phi(alpha) convex and C1 but not piecewise
+                        // quadratic: Newton's method on phi'(alpha) = 0 from alpha = 0, kept inside
+                        // the bracket of a sign change (bisection when a step leaves it)
+                        const float mue = C.mu * m.rsqrt_impratio;
+                        auto dphi = [&](float al, float* d2) {
+                            float d1l = 0.f, d2l = 0.f;
+                            if (cell) {
+                                const float jj[3] = {C.jar[0] + al * sr[0], C.jar[1] + al * sr[1], C.jar[2] + al * sr[2]};
+                                float cst, ge[3], he[6];
+                                ell_eval(jj, C.D[0], C.D[1], mue, &cst, ge, he);
+                                d1l += ge[0] * sr[0] + ge[1] * sr[1] + ge[2] * sr[2];
+                                d2l += he[0] * sr[0] * sr[0] + he[3] * sr[1] * sr[1] + he[5] * sr[2] * sr[2] +
+                                       2.f * (he[1] * sr[0] * sr[1] + he[2] * sr[0] * sr[2] + he[4] * sr[1] * sr[2]);
+                            } else if (has) {
+#pragma unroll
+                                for (int e = 0; e < 4; e++) {
+                                    const float j = C.jar[e] + al * sr[e];
+                                    if (j < 0.f || (j == 0.f && sr[e] < 0.f)) {
+                                        d1l += C.D[e] * sr[e] * j;
+                                        d2l += C.D[e] * sr[e] * sr[e];
+                                    }
+                                }
+                            }
+                            if (limact && dof_lane) {
+                                const float sl = lim_dir(), lj = ljar[lane] + al * sl, Dl = fabsf(lD[lane]);
+                                if (lj < 0.f || (lj == 0.f && sl < 0.f)) {
+                                    d1l += Dl * sl * lj;
+                                    d2l += Dl * sl * sl;
+                                }
+                            }
+                            if (gu) {
+                                const float j = gj + al * gsr;
+                                if (j < 0.f || (j == 0.f && gsr < 0.f)) {
+                                    d1l += gD * gsr * j;
+                                    d2l += gD * gsr * gsr;
+                                }
+                            }
+                            *d2 = A0 + wsum(d2l);
+                            return al * A0 + B0 + wsum(d1l);
+                        };
+                        float d2, d1 = dphi(0.f, &d2);
+                        if (d1 < 0.f) {
+                            const float tolg = 1e-6f * fabsf(d1);
+                            float lo = 0.f, hi = INFINITY, al = 0.f;
+                            for (int k = 0; k < 24; k++) {
+                                if (TIMED) seg_sub++;
+                                if (fabsf(d1) <= tolg) break;
+                                if (d1 < 0.f) lo = al; else hi = al;
+                                if (hi < INFINITY && hi - lo <= 1e-7f * hi) break;
+                                float nxt = al - d1 / d2;
+                                if (!(nxt > lo && nxt < hi)) nxt = hi < INFINITY ? 0.5f * (lo + hi) : 2.f * fmaxf(lo, 1.f);
+                                al = nxt;
+                                d1 = dphi(al, &d2);
+                            }
+                            alpha = al;
+                        }
+                    } else {
                     float at = 0.f;
                     int guard = 4 * ncon + 2 + (limact ? nv : 0) + nx;
                     for (int k = 0; k < guard; k++) {
@@ -1864,6 +2023,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         at = nxt;
                         alpha = at;
                     }
+                    }
                 }
                 // update a, M a and the row residuals along p
                 float qf2 = 0.f;
@@ -1875,11 +2035,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 float fc = 0.f;
                 if (has) {
 #pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        C.jar[e] += alpha * sr[e];
-                        float mn = fminf(C.jar[e], 0.f);
-                        fc += 0.5f * C.D[e] * mn * mn;
-                    }
+                    for (int e = 0; e < 4; e++) C.jar[e] += alpha * sr[e];
+                    fc += con_cost(C.jar);
                 }
                 if (limact && dof_lane) {
                     const float lj = ljar[lane] + alpha * lim_dir();
@@ -1905,9 +2062,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 st_seg += seg_sub;
                 // rows, and rows active at the solution (a frictionless contact has one row)
                 const bool fl = has && EXT && (C.ids >> 24);
-                int act = 0, nrow = has ? (fl ? 1 : 4) : 0;
-                if (has)
+                int act = 0, nrow = has ? (fl ? 1 : (cell ? 3 : 4)) : 0;
+                if (cell) {
+                    float cst, ge[3], he[6];
+                    act += ell_eval(C.jar, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he) != 0 ? 3 : 0;
+                } else if (has) {
                     for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f && (e == 0 || !fl);
+                }
                 if (limact && lane < nv && lD[lane] != 0.f) {
                     act += ljar[lane] < 0.f;
                     nrow += 1;
@@ -2066,7 +2227,14 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             cross(C.n, C.t1, t2o);
             for (int k = 0; k < 3; k++) { F[k] = C.n[k]; F[3 + k] = C.t1[k]; F[6 + k] = t2o[k]; }
         }
-        if (A.co.force) {
+        if (A.co.force && EXT && m.cone && !(C.ids >> 24)) {
+            // elliptic cone: the frame rows' forces, minus the cost's gradient
+            float cst, ge[3], he[6];
+            ell_eval(C.jar, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he);
+            A.co.force[3 * slot] = -ge[0];
+            A.co.force[3 * slot + 1] = -ge[1];
+            A.co.force[3 * slot + 2] = -ge[2];
+        } else if (A.co.force) {
             float f[4];
             for (int e = 0; e < 4; e++) f[e] = -C.D[e] * fminf(C.jar[e], 0.f);
             // every pyramid row, the torsional and rolling ones included, carries the normal once

@@ -67,7 +67,8 @@ class _Desc(C.Structure):
                 ("jnt_range", _f64p), ("jnt_damping", _f64p), ("geom_condim", _i32p),
                 ("hfield_nrow", C.c_int32), ("hfield_ncol", C.c_int32), ("hfield_data", _f64p),
                 ("neq", C.c_int32), ("eq_type", _i32p), ("eq_body", _i32p), ("eq_anchor", _f64p),
-                ("eq_target", _f64p), ("geom_friction_spin", _f64p), ("geom_friction_roll", _f64p)]
+                ("eq_target", _f64p), ("geom_friction_spin", _f64p), ("geom_friction_roll", _f64p),
+                ("cone", C.c_int32), ("impratio", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -194,6 +195,8 @@ def marshal_desc(model: dict):
     d.geom_condim = i32([g.get("condim", 3) for g in G] or [3])
     d.geom_friction_spin = f64([g.get("friction_spin", 0.005) for g in G] or [0.0])
     d.geom_friction_roll = f64([g.get("friction_roll", 0.0001) for g in G] or [0.0])
+    d.cone = {"pyramidal": 0, "elliptic": 1}[o.get("cone", "pyramidal")]
+    d.impratio = float(o.get("impratio", 1.0))
     hf = model.get("hfield")
     if hf:
         d.hfield_nrow, d.hfield_ncol = int(hf["nrow"]), int(hf["ncol"])

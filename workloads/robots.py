@@ -579,12 +579,31 @@ def humanoid_condim4() -> dict:
     return m
 
 
+def with_elliptic(model: dict, impratio: float, name: str) -> dict:
+    out = copy.deepcopy(model)
+    out["opt"]["cone"] = "elliptic"
+    out["opt"]["impratio"] = float(impratio)
+    out["name"] = name
+    return out
+
+
+def quadruped_elliptic() -> dict:
+    """quadruped with elliptic friction cones (impratio 1)."""
+    return with_elliptic(quadruped(), 1.0, "quadruped_elliptic")
+
+
+def humanoid_elliptic() -> dict:
+    """humanoid with elliptic friction cones (impratio 1)."""
+    return with_elliptic(humanoid(), 1.0, "humanoid_elliptic")
+
+
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
                 "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
                 "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp, "quadruped_slip": quadruped_slip,
                 "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld,
-                "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4}
+                "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4,
+                "quadruped_elliptic": quadruped_elliptic, "humanoid_elliptic": humanoid_elliptic}
 
 
 def by_name(name: str) -> dict:
