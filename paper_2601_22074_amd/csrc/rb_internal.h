@@ -84,8 +84,9 @@ struct DevModel {
     int nlim;                  // limited hinges
     const float* dof_damping;  // hinge damping (0 when undamped)
     int ndamp;                 // damped hinges
-    int ext;                   // needs the extended code: box-box or sphere-box pairs, joint limits, damping,
-                               // equality constraints
+    int ext;                   // level of extended code: 1 box-box and primitive-box pairs, height fields,
+                               // joint limits, damping, condim 1; 2 also equality constraints, condim 4/6,
+                               // elliptic cones
     const int* act_start;      // [nv + 1] CSR of actuators driving each dof
     const int* act_list;
     const int* act_type;

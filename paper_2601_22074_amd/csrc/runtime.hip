@@ -28,7 +28,7 @@ size_t rb_step_args_size();
 void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
                        const DevContactsOut* co, uint32_t* status_out);
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
-                           bool boxbox, int lds_floats, int grid, int waves, hipStream_t stream);
+                           int ext, int lds_floats, int grid, int waves, hipStream_t stream);
 
 namespace {
 
@@ -684,7 +684,9 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.cone = d->cone == RB_CONE_ELLIPTIC && npair > 0 ? 1 : 0;
     m.impratio = (float)impratio;
     m.rsqrt_impratio = (float)(1.0 / std::sqrt(impratio));
-    m.ext = (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE || neqrow > 0 || nxmax > 0 || m.cone ||
+    // level 2: equality rows, torsional / rolling rows, elliptic cones; level 1: the rest
+    const int ext2 = (neqrow > 0 || nxmax > 0 || m.cone) ? 2 : 0;
+    m.ext = ext2 ? ext2 : (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_CAPSULEBOX) > 0 ||
              std::count_if(ptype.begin(), ptype.end(), [](int t) { return t >= RB_PAIR_HFIELD; }) > 0 ||
@@ -1047,7 +1049,7 @@ struct rb_multi {
     void* d_args = nullptr;
     int* d_items = nullptr;
     int nitems = 0, grid = 0, maxd = 0, lds_floats = 0;
-    bool boxbox = false;                       // some model needs the extended instantiation
+    int boxbox = 0;                            // highest level of extended code a model needs
     bool scheduled = false;                    // a work list was set (possibly empty)
     int items_cap = 0;                         // capacity of d_items
     int lds_pad = 0;                           // extra LDS floats per workgroup (occupancy cap)
@@ -1082,7 +1084,7 @@ int rb_multi_create(rb_batch* const* batches, int32_t nbatch, rb_multi** out) {
         p->batches.push_back(batches[i]);
         models[i] = batches[i]->dm;
         p->maxd = std::max(p->maxd, models[i].maxd);
-        p->boxbox = p->boxbox || models[i].ext;   // some model needs the extended code
+        p->boxbox = std::max(p->boxbox, models[i].ext);   // the extended code the models need
     }
     // every batch runs in its own model's instantiation, with its own LDS layout
     for (int i = 0; i < nbatch; i++) p->lds_floats = std::max(p->lds_floats, models[i].lds_floats);

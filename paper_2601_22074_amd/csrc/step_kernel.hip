@@ -571,7 +571,7 @@ DEV bool hfield_plane(const DevModel& m, const float* gsize, int g, const float*
 // depth, lowest axis on ties, + side at 0); distance |c - closest| - r outside, -(depth + r)
 // inside; normal from the sphere towards the box.  Capsule-box pair: candidate k is the sphere
 // at the capsule's segment end k (0 at -z, 1 at +z) against the box by the same rule.
-template <bool EXT>
+template <int EXT>
 DEV void pair_candidate(const DevModel& m, const float* L, const float* gsize, int p, int k, float* dist, float* pos,
                         float* nrm) {
     float xp[3], Rp[9], x[3], R[9];
@@ -654,7 +654,7 @@ DEV void pair_candidate(const DevModel& m, const float* L, const float* gsize, i
 // Bit k set iff candidate k of plane pair p is below the margin.  Computed once per pair; the
 // contact lanes then pick their candidate from these bits, so membership never depends on
 // re-evaluating a distance that sits on the margin.
-template <bool EXT>
+template <int EXT>
 DEV uint32_t pair_mask(const DevModel& m, const float* L, const float* gsize, int p) {
     const int nc = pair_ncand(m.pair_type[p]);
     const float margin = m.pair_margin[p];
@@ -899,7 +899,7 @@ struct StepArgs {
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
-template <int MAXD, bool TIMED, bool EXT>
+template <int MAXD, bool TIMED, int EXT>
 DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* lds) {
     const int lane = threadIdx.x;
     float* L = lds;
@@ -1315,7 +1315,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 C.ids |= 1 << 24;
             }
             margin_c = m.pair_margin[src];
-            if (EXT && m.nxmax > 0) {
+            if (EXT >= 2 && m.nxmax > 0) {
                 xr = m.pair_xrows[src];
                 mu_spin = m.pair_mu_spin[src];
                 mu_roll = m.pair_mu_roll[src];
@@ -1325,13 +1325,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         }
         // an elliptic-cone contact (extended code): frame rows costed by the soft elliptic cone;
         // frictionless contacts keep their one normal row
-        const bool cell = EXT && m.cone && has && !(C.ids >> 24);
+        const bool cell = EXT >= 2 && m.cone && has && !(C.ids >> 24);
         RB_STAGE(3);
         // generic-row slots of the contacts' extra rows: after the equality rows, in contact order
         float* GR = L + m.o_gr;
         xbase = 0;
         nx = 0;
-        if (EXT && m.nxmax > 0) {
+        if (EXT >= 2 && m.nxmax > 0) {
             const int xi = wscan_incl(xr, lane);
             xbase = m.neqrow + xi - xr;
             nx = __builtin_amdgcn_readfirstlane(__shfl(xi, RB_WAVE - 1));
@@ -1439,7 +1439,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     E[3 * e + 2] = ah[e];
                 }
             }
-            if (EXT && xr > 0) {
+            if (EXT >= 2 && xr > 0) {
                 // torsional (about n) and rolling (about t1, t2) pyramid rows J_n +- mu_d J_d,
                 // J_d the frame component of the body's angular velocity: as spatial forces at O,
                 // psi = sigma (r x n +- mu_d k_d, n); A-hat from one more half-solve per axis
@@ -1502,8 +1502,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         // E = R_body R_target'.  LDS keeps psi, D, the residual J a - aref (aref until the Newton
         // start), the line-search direction J p and the body.  Bilateral: always active.
         const int ngr = m.neqrow + nx;            // generic rows: equality, then contact extras
-        const bool gract = EXT && ngr > 0;
-        if (EXT && m.neqrow > 0) {
+        const bool gract = EXT >= 2 && ngr > 0;
+        if (EXT >= 2 && m.neqrow > 0) {
             const bool own = lane < m.neqrow;
             const int qe = own ? m.eqrow_eq[lane] : 0;
             const int k = own ? m.eqrow_k[lane] : 0;
@@ -1760,7 +1760,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     for (int e = 0; e < 4; e++) { D[e] = rl(C.D[e], c); jar[e] = rl(C.jar[e], c); }
                     float mu = rl(C.mu, c), sg = rl(C.sigma, c);
                     // an elliptic contact: its cost's gradient and Hessian in its frame rows
-                    const bool ellc = EXT && m.cone && !(__builtin_amdgcn_readlane(C.ids, c) >> 24);
+                    const bool ellc = EXT >= 2 && m.cone && !(__builtin_amdgcn_readlane(C.ids, c) >> 24);
                     float ge[3], he[6];
                     if (ellc) {
                         float cst;
@@ -1920,7 +1920,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     const bool gu = grown && !grbil;
                     const float gj = gu ? Er[7] : 0.f, gD = gu ? Er[6] : 0.f;
                     const float gbp = (gu && gsr != 0.f) ? -gj * __builtin_amdgcn_rcpf(gsr) : INFINITY;
-                    if (EXT && m.cone && ncon > 0) {
+                    if (EXT >= 2 && m.cone && ncon > 0) {
                         // elliptic contacts make phi(alpha) convex and C1 but not piecewise
                         // quadratic: Newton's method on phi'(alpha) = 0 from alpha = 0, kept inside
                         // the bracket of a sign change (bisection when a step leaves it)
@@ -2227,7 +2227,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             cross(C.n, C.t1, t2o);
             for (int k = 0; k < 3; k++) { F[k] = C.n[k]; F[3 + k] = C.t1[k]; F[6 + k] = t2o[k]; }
         }
-        if (A.co.force && EXT && m.cone && !(C.ids >> 24)) {
+        if (A.co.force && EXT >= 2 && m.cone && !(C.ids >> 24)) {
             // elliptic cone: the frame rows' forces, minus the cost's gradient
             float cst, ge[3], he[6];
             ell_eval(C.jar, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he);
@@ -2239,7 +2239,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             for (int e = 0; e < 4; e++) f[e] = -C.D[e] * fminf(C.jar[e], 0.f);
             // every pyramid row, the torsional and rolling ones included, carries the normal once
             float fx = 0.f;
-            if (EXT)
+            if (EXT >= 2)
                 for (int e = 0; e < xr; e++) {
                     const float* G = L + m.o_gr + RB_GRF * (xbase + e);
                     fx += -G[6] * fminf(G[7], 0.f);
@@ -2251,10 +2251,12 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     }
 }
 
-// One world per 64-lane workgroup.  EXT: the model has box-box or sphere-box pairs or joint
-// limits (that code is kept out of the other instantiations so their register allocation is not
+// One world per 64-lane workgroup.  EXT: the level of extended code -- 1 for box-box,
+// sphere-box, capsule-box and height-field pairs, more than 64 pairs, joint limits, damping and
+// frictionless contacts; 2 adds equality constraints, torsional / rolling friction and elliptic
+// cones (each level kept out of the lower instantiations so their register allocation is not
 // shaped by it).
-template <int MAXD, bool TIMED, bool EXT>
+template <int MAXD, bool TIMED, int EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void step_kernel(
     DevModel m, StepArgs A) {
     extern __shared__ float lds[];
@@ -2266,7 +2268,7 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVE
 // The same step compiled for 4 resident waves per SIMD (at most 128 registers, more spills):
 // worth it when the model's LDS lets 16 worlds share a CU and the batch is more than one
 // round of the 3-wave kernel -- the last round then has fewer worlds waiting on it.
-template <int MAXD, bool EXT>
+template <int MAXD, int EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void step_kernel_w4(
     DevModel m, StepArgs A) {
     extern __shared__ float lds[];
@@ -2288,22 +2290,23 @@ struct MultiArgs {
 // Each item runs the instantiation the plain launch would use for its model (chain bound and
 // box-box code), so a world computes exactly as in rb_step and small models keep lean code;
 // MAXD and EXT bound what the plan's models need.
-template <int MAXD, bool EXT>
-DEV void world_step_as_plain(const DevModel& m, const StepArgs& A, int w, float* lds) {
-    const bool bb = EXT && m.ext;
-    if (MAXD >= 32 && m.maxd > 16) {
-        if (bb) world_step<(MAXD >= 32 ? 32 : MAXD), false, EXT>(m, A, w, lds);
-        else world_step<(MAXD >= 32 ? 32 : MAXD), false, false>(m, A, w, lds);
-    } else if (MAXD >= 16 && m.maxd > 8) {
-        if (bb) world_step<(MAXD >= 16 ? 16 : MAXD), false, EXT>(m, A, w, lds);
-        else world_step<(MAXD >= 16 ? 16 : MAXD), false, false>(m, A, w, lds);
-    } else {
-        if (bb) world_step<8, false, EXT>(m, A, w, lds);
-        else world_step<8, false, false>(m, A, w, lds);
-    }
+template <int MAXD, int EXT>
+DEV void world_step_level(const DevModel& m, const StepArgs& A, int w, float* lds) {
+    // the model's own level of extended code, at most the plan's
+    const int lv = m.ext < EXT ? m.ext : EXT;
+    if (EXT >= 2 && lv == 2) world_step<MAXD, false, (EXT >= 2 ? 2 : 0)>(m, A, w, lds);
+    else if (EXT >= 1 && lv == 1) world_step<MAXD, false, (EXT >= 1 ? 1 : 0)>(m, A, w, lds);
+    else world_step<MAXD, false, 0>(m, A, w, lds);
 }
 
-template <int MAXD, bool EXT>
+template <int MAXD, int EXT>
+DEV void world_step_as_plain(const DevModel& m, const StepArgs& A, int w, float* lds) {
+    if (MAXD >= 32 && m.maxd > 16) world_step_level<(MAXD >= 32 ? 32 : MAXD), EXT>(m, A, w, lds);
+    else if (MAXD >= 16 && m.maxd > 8) world_step_level<(MAXD >= 16 ? 16 : MAXD), EXT>(m, A, w, lds);
+    else world_step_level<8, EXT>(m, A, w, lds);
+}
+
+template <int MAXD, int EXT>
 DEV void multi_items(const MultiArgs& M, float* lds) {
     for (int it = blockIdx.x; it < M.nitems; it += gridDim.x) {
         const int item = __builtin_amdgcn_readfirstlane(M.items[it]);
@@ -2314,7 +2317,7 @@ DEV void multi_items(const MultiArgs& M, float* lds) {
     }
 }
 
-template <int MAXD, bool EXT>
+template <int MAXD, int EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
     MultiArgs M) {
     extern __shared__ float lds[];
@@ -2323,7 +2326,7 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVE
 
 // 4 resident waves per SIMD, for plans whose models all fit that (chain bound <= 16 and LDS
 // small enough for 16 worlds per CU)
-template <int MAXD, bool EXT>
+template <int MAXD, int EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void multi_kernel_w4(
     MultiArgs M) {
     extern __shared__ float lds[];
@@ -2357,14 +2360,14 @@ void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* 
     *(rbk::StepArgs*)dst = A;
 }
 
-template <int MAXD, bool EXT>
+template <int MAXD, int EXT>
 static void launch_multi_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, bool w4, hipStream_t stream) {
     if (w4 && MAXD <= 16)
         hipLaunchKernelGGL((rbk::multi_kernel_w4<(MAXD <= 16 ? MAXD : 16), EXT>), g, dim3(RB_WAVE), shmem, stream, M);
     else
         hipLaunchKernelGGL((rbk::multi_kernel<MAXD, EXT>), g, dim3(RB_WAVE), shmem, stream, M);
 }
-template <bool EXT>
+template <int EXT>
 static void launch_multi_b(int maxd, const rbk::MultiArgs& M, dim3 g, size_t shmem, bool w4, hipStream_t stream) {
     if (maxd <= 8) launch_multi_t<8, EXT>(M, g, shmem, w4, stream);
     else if (maxd <= 16) launch_multi_t<16, EXT>(M, g, shmem, w4, stream);
@@ -2372,7 +2375,7 @@ static void launch_multi_b(int maxd, const rbk::MultiArgs& M, dim3 g, size_t shm
 }
 
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
-                           bool boxbox, int lds_floats, int grid, int waves, hipStream_t stream) {
+                           int ext, int lds_floats, int grid, int waves, hipStream_t stream) {
     rbk::MultiArgs M;
     M.models = models;
     M.args = (const rbk::StepArgs*)args;
@@ -2380,16 +2383,17 @@ hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* 
     M.nitems = nitems;
     size_t shmem = (size_t)lds_floats * sizeof(float);
     dim3 g(grid);
-    if (boxbox) launch_multi_b<true>(maxd, M, g, shmem, waves == 4, stream);
-    else launch_multi_b<false>(maxd, M, g, shmem, waves == 4, stream);
+    if (ext >= 2) launch_multi_b<2>(maxd, M, g, shmem, waves == 4, stream);
+    else if (ext == 1) launch_multi_b<1>(maxd, M, g, shmem, waves == 4, stream);
+    else launch_multi_b<0>(maxd, M, g, shmem, waves == 4, stream);
     return hipGetLastError();
 }
 
-template <int MAXD, bool TIMED, bool EXT>
+template <int MAXD, bool TIMED, int EXT>
 static void launch_step_t(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
     hipLaunchKernelGGL((rbk::step_kernel<MAXD, TIMED, EXT>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
 }
-template <bool TIMED, bool EXT>
+template <bool TIMED, int EXT>
 static void launch_step_d(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
     if (m.maxd <= 8) launch_step_t<8, TIMED, EXT>(m, A, n, shmem, stream);
     else if (m.maxd <= 16) launch_step_t<16, TIMED, EXT>(m, A, n, shmem, stream);
@@ -2412,21 +2416,25 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     if (taps) A.taps = *taps; else A.taps = DevTaps{};
     size_t shmem = (size_t)m.lds_floats * sizeof(float);
     const bool timed = taps != nullptr;   // every tap is served by the diagnostic instantiation
-    const bool bb = m.ext != 0;   // the extended instantiation
+    const int lv = m.ext;   // the level of extended code the model needs
     if (timed) {
-        if (bb) launch_step_d<true, true>(m, A, n, shmem, stream);
-        else launch_step_d<true, false>(m, A, n, shmem, stream);
+        if (lv >= 2) launch_step_d<true, 2>(m, A, n, shmem, stream);
+        else if (lv == 1) launch_step_d<true, 1>(m, A, n, shmem, stream);
+        else launch_step_d<true, 0>(m, A, n, shmem, stream);
     } else if (waves == 4 && m.maxd <= 16) {
         if (m.maxd <= 8) {
-            if (bb) hipLaunchKernelGGL((rbk::step_kernel_w4<8, true>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-            else hipLaunchKernelGGL((rbk::step_kernel_w4<8, false>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            if (lv >= 2) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 2>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            else if (lv == 1) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 1>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            else hipLaunchKernelGGL((rbk::step_kernel_w4<8, 0>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
         } else {
-            if (bb) hipLaunchKernelGGL((rbk::step_kernel_w4<16, true>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-            else hipLaunchKernelGGL((rbk::step_kernel_w4<16, false>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            if (lv >= 2) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 2>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            else if (lv == 1) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 1>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            else hipLaunchKernelGGL((rbk::step_kernel_w4<16, 0>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
         }
     } else {
-        if (bb) launch_step_d<false, true>(m, A, n, shmem, stream);
-        else launch_step_d<false, false>(m, A, n, shmem, stream);
+        if (lv >= 2) launch_step_d<false, 2>(m, A, n, shmem, stream);
+        else if (lv == 1) launch_step_d<false, 1>(m, A, n, shmem, stream);
+        else launch_step_d<false, 0>(m, A, n, shmem, stream);
     }
     return hipGetLastError();
 }
