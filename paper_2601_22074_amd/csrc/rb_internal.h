@@ -86,7 +86,7 @@ struct DevModel {
     int ndamp;                 // damped hinges
     int ext;                   // level of extended code: 1 box-box and primitive-box pairs, height fields,
                                // joint limits, damping, condim 1; 2 also equality constraints, condim 4/6,
-                               // elliptic cones
+                               // elliptic cones; 3 also contacts between two moving bodies
     const int* act_start;      // [nv + 1] CSR of actuators driving each dof
     const int* act_list;
     const int* act_type;
@@ -120,6 +120,8 @@ struct DevModel {
     int neq, neqrow;
     int nxmax;                 // bound on the contacts' torsional / rolling rows (condim 4, 6 pairs)
     int cone;                  // 0 pyramidal, 1 elliptic friction cones (extended code)
+    int nmm;                   // pairs of two moving bodies (level-3 code: dense Newton Hessian)
+    const int* pair_body1;     // per pair: the second moving body (g1's), 0 when g1's body is static
     float impratio, rsqrt_impratio;
     const int* pair_xrows;     // per pair: 0, 2 (condim 4) or 6 (condim 6) rows per contact
     const float* pair_mu_spin;
@@ -134,7 +136,7 @@ struct DevModel {
     int o_q, o_v, o_ctrl, o_aws, o_mscale;
     int o_xpos, o_xmat, o_cinert, o_crb, o_cdof, o_cvel, o_bvec, o_bvec2;
     int o_tau, o_bias, o_a0, o_a, o_Ma, o_g, o_p, o_Mp, o_tmp, o_lD, o_ljar;
-    int o_M, o_H, o_piv, o_rowadr, o_bb, o_gr;
+    int o_M, o_H, o_piv, o_rowadr, o_bb, o_gr, o_hd;
     int lds_floats;
 };
 

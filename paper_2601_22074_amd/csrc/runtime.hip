@@ -140,6 +140,9 @@ void layout_tail(DevModel& m, int kernel_maxd) {
     o += r4(RB_BB_FLOATS * m.nbb);
     m.o_gr = o;
     o += r4(RB_GRF * (m.neqrow + m.nxmax));
+    // dense Newton Hessian [nv, nv] and three direction vectors [3, nv] (two-body contacts)
+    m.o_hd = o;
+    if (m.nmm > 0) o += r4(m.nv * m.nv) + r4(3 * m.nv);
     m.lds_floats = o;
 }
 
@@ -387,7 +390,6 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             if (((d->geom_contype[a] & d->geom_conaffinity[b]) | (d->geom_contype[b] & d->geom_conaffinity[a])) == 0)
                 continue;
             if (!movable[ba] && !movable[bb]) continue;
-            if (movable[ba] && movable[bb]) return fail(RB_EINVAL, "contacts between two moving bodies are not supported");
             int g1 = a, g2 = b;
             if (d->geom_type[g2] < d->geom_type[g1]) std::swap(g1, g2);
             // a height field takes the place of g1, as a plane does
@@ -410,6 +412,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     int npair = (int)pairs.size();
     if (npair > RB_MAX_PAIR) return fail(RB_EINVAL, "more than 128 collision pairs");
     std::vector<int> pg1(npair), pg2(npair), ptype(npair), pbody(npair), pcap(npair), pslot(npair, -1);
+    std::vector<int> pbody1(npair, 0);   // the second moving body of a pair (0: the other is static)
+    int nmm = 0;                         // pairs of two moving bodies
     int nbb = 0;
     std::vector<double> psig(npair), pmu(npair), pmar(npair);
     std::vector<int> pfric0(npair, 0), pxr(npair, 0);
@@ -429,6 +433,12 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         bool mov2 = movable[d->geom_body[g2]];
         pbody[k] = mov2 ? d->geom_body[g2] : d->geom_body[g1];
         psig[k] = mov2 ? 1.0 : -1.0;
+        if (mov2 && movable[d->geom_body[g1]]) {
+            // both bodies move (box-box, sphere or capsule against box: planes and height
+            // fields are static): rows of the relative velocity, g2's body minus g1's
+            pbody1[k] = d->geom_body[g1];
+            nmm++;
+        }
         pmu[k] = std::max(d->geom_friction[g1], d->geom_friction[g2]);
         pmar[k] = std::max(d->geom_margin[g1], d->geom_margin[g2]);
         if (d->geom_condim) {
@@ -455,6 +465,13 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     if (!(impratio > 0) || !std::isfinite(impratio)) return fail(RB_EINVAL, "impratio must be positive");
     if (d->cone == RB_CONE_ELLIPTIC && nxmax > 0)
         return fail(RB_EINVAL, "elliptic cones take condim 1 or 3");
+    if (nmm > 0) {
+        if (d->cone == RB_CONE_ELLIPTIC)
+            return fail(RB_EINVAL, "contacts between two moving bodies take pyramidal cones");
+        for (int k = 0; k < npair; k++)
+            if (pbody1[k] > 0 && pxr[k] > 0)
+                return fail(RB_EINVAL, "contacts between two moving bodies take condim 1 or 3");
+    }
     double dmax = std::min(std::max(d->solimp[1], 1e-4), 0.9999);
     double tc = std::max(d->solref[0], 2 * d->timestep), zeta = d->solref[1];
     // mean diagonal inertia at the reference configuration: composite inertias in double
@@ -642,6 +659,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     F(akp, &m.act_kp); F(akd, &m.act_kd); F(agear, &m.act_gear);
     I(jtype, &m.jnt_type); I(jq, &m.jnt_qadr); I(jd, &m.jnt_dadr);
     I(pg1, &m.pair_g1); I(pg2, &m.pair_g2); I(ptype, &m.pair_type); I(pbody, &m.pair_body); I(pcap, &m.pair_cap);
+    if (nmm > 0) I(pbody1, &m.pair_body1);
     I(pslot, &m.pair_slot);
     F(psig, &m.pair_sigma); F(pmu, &m.pair_mu); F(pmar, &m.pair_margin); I(pfric0, &m.pair_frictionless);
     I(std::vector<int>(d->geom_body, d->geom_body + ng), &m.geom_body);
@@ -685,7 +703,9 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.impratio = (float)impratio;
     m.rsqrt_impratio = (float)(1.0 / std::sqrt(impratio));
     // level 2: equality rows, torsional / rolling rows, elliptic cones; level 1: the rest
-    const int ext2 = (neqrow > 0 || nxmax > 0 || m.cone) ? 2 : 0;
+    // level 3: pairs of two moving bodies (a dense Newton Hessian)
+    const int ext2 = nmm > 0 ? 3 : (neqrow > 0 || nxmax > 0 || m.cone) ? 2 : 0;
+    m.nmm = nmm;
     m.ext = ext2 ? ext2 : (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_CAPSULEBOX) > 0 ||

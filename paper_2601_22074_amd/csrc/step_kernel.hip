@@ -429,18 +429,26 @@ struct Con {
     float n[3], t1[3];     // normal and first tangent (t2 = n x t1)
     float mu, sigma, dist;
     int body;
+    int body1;             // g1's body when both bodies move (rows of g2's minus g1's motion), else 0
     int ids;               // g1 | g2 << 8 | feature << 16
     float D[4], aref[4], jar[4];
 };
 
 // velocity of the contact's pyramid rows for body spatial motions `bm` (already includes sign);
-// of its frame rows (normal, t1, t2, then 0) for an elliptic-cone contact
-DEV void rows_of(const Con& c, const float* bm, float* out, bool ell = false) {
+// of its frame rows (normal, t1, t2, then 0) for an elliptic-cone contact; b1 > 0: the
+// contact's second moving body, whose point motion is subtracted
+DEV void rows_of(const Con& c, const float* bm, float* out, bool ell = false, int b1 = 0) {
     const float* sv = bm + 6 * c.body;
     float wr[3], t2[3];
     cross(sv, c.r, wr);
     cross(c.n, c.t1, t2);
     float vp[3] = {sv[3] + wr[0], sv[4] + wr[1], sv[5] + wr[2]};
+    if (b1 > 0) {
+        const float* s1 = bm + 6 * b1;
+        float w1[3];
+        cross(s1, c.r, w1);
+        vp[0] -= s1[3] + w1[0]; vp[1] -= s1[4] + w1[1]; vp[2] -= s1[5] + w1[2];
+    }
     float vn = c.sigma * dot(c.n, vp), v1 = c.sigma * dot(c.t1, vp), v2 = c.sigma * dot(t2, vp);
     if (ell) {
         out[0] = vn; out[1] = v1; out[2] = v2; out[3] = 0.f;
@@ -1306,6 +1314,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             contact_frame(C.n, C.t1);
             C.ids = m.pair_g1[src] | (m.pair_g2[src] << 8) | (feat << 16);
             C.body = m.pair_body[src];
+            C.body1 = (EXT >= 3 && m.nmm > 0) ? m.pair_body1[src] : 0;
             C.sigma = m.pair_sigma[src];
             C.mu = m.fr_pw ? mu_world : m.pair_mu[src];
             if (EXT && m.pair_frictionless[src]) {
@@ -1322,6 +1331,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             }
         } else {
             C.body = 0;
+            C.body1 = 0;
         }
         // an elliptic-cone contact (extended code): frame rows costed by the soft elliptic cone;
         // frictionless contacts keep their one normal row
@@ -1345,6 +1355,17 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 #pragma unroll
             for (int w2 = 0; w2 < MAXD / 4; w2++) cw[w2] = (uint32_t)__shfl((int)DL.anc[w2], csrc);
 #define CROW(t) rowadr_l[(int)((cw[(t) >> 2] >> (8 * ((t) & 3))) & 0xffu)]
+            // the second moving body's chain (contacts between two moving bodies)
+            int d1 = 0;
+            uint32_t cw1[MAXD / 4];
+#pragma unroll
+            for (int w2 = 0; w2 < MAXD / 4; w2++) cw1[w2] = 0u;
+            if (EXT >= 3 && m.nmm > 0) {
+                d1 = __shfl(BL.depth, C.body1);
+                const int csrc1 = __shfl(BL.src, C.body1);
+#pragma unroll
+                for (int w2 = 0; w2 < MAXD / 4; w2++) cw1[w2] = (uint32_t)__shfl((int)DL.anc[w2], csrc1);
+            }
         if (has) {
             // A_c = J_c M^-1 J_c' from Y = L'^-1 J_c' on the body's chain (positions t < d): one
             // column (normal, t1, t2) at a time, keeping only the normal column (fewer values live
@@ -1404,8 +1425,75 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         A02 += Z0[t] * Y[t];
                     }
             }
+            if (EXT >= 3 && C.body1 > 0) {
+                // both bodies move: J = J(b2) - J(b1), and Y = L'^-1 J' is the sum of the half-solves
+                // along each chain (+dir on b2's, -dir on b1's), the two adding on their common
+                // prefix; A-hat sums Y^2 / D over the union of the two chains
+                auto byte_of = [](const uint32_t* cwx, int t) { return (int)((cwx[t >> 2] >> (8 * (t & 3))) & 0xffu); };
+                int cpl = 0;
+#pragma unroll
+                for (int t = 0; t < MAXD; t++)
+                    if (t == cpl && t < d && t < d1 && byte_of(cw, t) == byte_of(cw1, t)) cpl = t + 1;
+                auto solve_on = [&](const uint32_t* cwx, int dx, const float* dir, float sg, float (&Y)[MAXD]) {
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++) {
+                        const float* S = cdof + 6 * byte_of(cwx, t);
+                        float wr[3];
+                        cross(S, C.r, wr);
+                        const float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                        Y[t] = t < dx ? sg * dot(dir, vp) : 0.f;
+                    }
+#pragma unroll
+                    for (int tp = MAXD - 1; tp >= 1; tp--) {
+                        if (tp < dx) {
+                            const int row = rowadr_l[byte_of(cwx, tp)];
+#pragma unroll
+                            for (int t = 0; t < tp; t++) Y[t] -= H[row + t] * Y[tp];
+                        }
+                    }
+                };
+                // a direction's column on the union: U2 over b2's chain (the common prefix
+                // summed), U1 over b1's positions past the prefix
+                auto column = [&](const float* dir, float (&U2)[MAXD], float (&U1)[MAXD]) {
+                    float Y1[MAXD];
+                    solve_on(cw, d, dir, 1.f, U2);
+                    solve_on(cw1, d1, dir, -1.f, Y1);
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++) {
+                        if (t < cpl) U2[t] += Y1[t];
+                        U1[t] = (t >= cpl && t < d1) ? Y1[t] : 0.f;
+                    }
+                };
+                auto dinv2 = [&](int t) { return __builtin_amdgcn_rcpf(H[rowadr_l[byte_of(cw, t)] + t]); };
+                auto dinv1 = [&](int t) { return __builtin_amdgcn_rcpf(H[rowadr_l[byte_of(cw1, t)] + t]); };
+                float Zn2[MAXD], Zn1[MAXD];
+                A00 = A11 = A22 = A01 = A02 = 0.f;
+                {
+                    float U2[MAXD], U1[MAXD];
+                    column(C.n, U2, U1);
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++) {
+                        Zn2[t] = t < d ? U2[t] * dinv2(t) : 0.f;
+                        Zn1[t] = (t >= cpl && t < d1) ? U1[t] * dinv1(t) : 0.f;
+                        A00 += U2[t] * Zn2[t] + U1[t] * Zn1[t];
+                    }
+                }
+                for (int k = 0; k < 2; k++) {
+                    float U2[MAXD], U1[MAXD];
+                    column(k == 0 ? C.t1 : t2c, U2, U1);
+                    float Akk = 0.f, A0k = 0.f;
+#pragma unroll
+                    for (int t = 0; t < MAXD; t++) {
+                        const float z2 = t < d ? U2[t] * dinv2(t) : 0.f;
+                        const float z1 = (t >= cpl && t < d1) ? U1[t] * dinv1(t) : 0.f;
+                        Akk += U2[t] * z2 + U1[t] * z1;
+                        A0k += Zn2[t] * U2[t] + Zn1[t] * U1[t];
+                    }
+                    if (k == 0) { A11 = Akk; A01 = A0k; } else { A22 = Akk; A02 = A0k; }
+                }
+            }
             float vrow[4];
-            rows_of(C, cvel, vrow, cell);
+            rows_of(C, cvel, vrow, cell, EXT >= 3 ? C.body1 : 0);
             float rd = C.dist - margin_c;
             float imp = impedance(m, rd);
             float mu = C.mu, mu2 = mu * mu;
@@ -1647,7 +1735,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 return cst;
             };
             if (has) {
-                rows_of(C, bvec, j0, cell);
+                rows_of(C, bvec, j0, cell, EXT >= 3 ? C.body1 : 0);
 #pragma unroll
                 for (int e = 0; e < 4; e++) j0[e] -= C.aref[e];
                 f0 += con_cost(j0);
@@ -1683,7 +1771,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             float jw[4] = {0, 0, 0, 0};
             float fw = 0.f;
             if (has) {
-                rows_of(C, bvec, jw, cell);
+                rows_of(C, bvec, jw, cell, EXT >= 3 ? C.body1 : 0);
 #pragma unroll
                 for (int e = 0; e < 4; e++) jw[e] += j0[e];
                 fw += con_cost(jw);
@@ -1781,14 +1869,35 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         cross(r, a, ra);
                         F[0] += ra[0]; F[1] += ra[1]; F[2] += ra[2];
                         F[3] += a[0]; F[4] += a[1]; F[5] += a[2];
-                    } else if (!ellc && dof_lane && ((mask >> lane) & 1ull)) {
+                    }
+                    // a contact between two moving bodies (level-3 code): a dof on b2's chain
+                    // only takes the rows with +, on b1's only with -, on both (the common
+                    // ancestors) not at all; its Hessian terms go to the dense Hessian instead
+                    int b1c = 0;
+                    uint64_t mask1 = 0ull;
+                    if (EXT >= 3 && m.nmm > 0) {
+                        b1c = __builtin_amdgcn_readlane(C.body1, c);
+                        if (b1c > 0) {
+                            const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)BL.chainmask, b1c);
+                            const uint32_t khi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(BL.chainmask >> 32), b1c);
+                            mask1 = ((uint64_t)khi << 32) | klo;
+                        }
+                    }
+                    const float cf = EXT >= 3 ? (float)((mask >> lane) & 1ull) - (float)((mask1 >> lane) & 1ull) : 1.f;
+                    const bool onrow = EXT >= 3 ? cf != 0.f : (bool)((mask >> lane) & 1ull);
+                    if (!ellc && dof_lane && onrow) {
                         float wr[3];
                         cross(S, r, wr);
                         float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                        if (EXT >= 3) sg *= cf;
                         float jn = sg * dot(n, vp), j1 = sg * dot(t1, vp), j2 = sg * dot(t2, vp);
                         float je[4] = {jn + mu * j1, jn - mu * j1, jn + mu * j2, jn - mu * j2};
 #pragma unroll
                         for (int e = 0; e < 4; e++) {
+                            if (EXT >= 3 && b1c > 0) {
+                                if (jar[e] < 0.f) gc += D[e] * jar[e] * je[e];
+                                continue;
+                            }
                             if (jar[e] < 0.f) {
                                 gc += D[e] * jar[e] * je[e];
                                 // row direction as a spatial force at O: sg * (r x a, a)
@@ -1877,7 +1986,86 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         if (t == DL.depth - 1) Hr[t] += hl;
                 }
                 RB_STAGE(6);
-                {
+                if (EXT >= 3 && m.nmm > 0) {
+                    // Dense Newton Hessian: a contact between two moving bodies couples the two
+                    // branches below their common ancestor, beyond M's tree sparsity.  The tree
+                    // part is the row above; each such contact adds U' W U (U: its frame rows'
+                    // Jacobian, W: the sum over its active pyramid rows of D a a', a = (1, +-mu, 0)
+                    // or (1, 0, +-mu)); then a right-looking L D L' of the lower triangle in LDS,
+                    // row i on lane i, and the two triangular solves by lane broadcasts.
+                    float* HD = L + m.o_hd;
+                    float* UD = HD + ((nv * nv + 3) & ~3);
+                    if (dof_lane) {
+                        for (int j = 0; j <= lane; j++) HD[lane * nv + j] = 0.f;
+#pragma unroll
+                        for (int t = 0; t < MAXD; t++)
+                            if (t < DL.depth) HD[lane * nv + DL.ancestor(t)] = Hr[t];
+                    }
+                    for (int c = 0; c < ncon; c++) {
+                        const int b1c = __builtin_amdgcn_readlane(C.body1, c);
+                        if (b1c == 0) continue;
+                        const int b2c = __builtin_amdgcn_readlane(C.body, c);
+                        const uint64_t m2 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(BL.chainmask >> 32), b2c) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)BL.chainmask, b2c);
+                        const uint64_t m1 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(BL.chainmask >> 32), b1c) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)BL.chainmask, b1c);
+                        float r[3], n[3], t1[3], t2[3];
+                        for (int k = 0; k < 3; k++) {
+                            r[k] = rl(C.r[k], c); n[k] = rl(C.n[k], c); t1[k] = rl(C.t1[k], c);
+                        }
+                        cross(n, t1, t2);
+                        const float mu = rl(C.mu, c);
+                        float W00 = 0.f, W01 = 0.f, W02 = 0.f, W11 = 0.f, W22 = 0.f;
+                        for (int e = 0; e < 4; e++) {
+                            const float De = rl(C.D[e], c), je = rl(C.jar[e], c);
+                            if (je < 0.f) {
+                                const float sm = (e & 1) ? -mu : mu;
+                                W00 += De;
+                                if (e < 2) { W01 += De * sm; W11 += De * sm * sm; }
+                                else { W02 += De * sm; W22 += De * sm * sm; }
+                            }
+                        }
+                        float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+                        if (dof_lane) {
+                            const float cf = (float)((m2 >> lane) & 1ull) - (float)((m1 >> lane) & 1ull);
+                            float wr[3];
+                            cross(S, r, wr);
+                            const float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
+                            u0 = cf * dot(n, vp); u1 = cf * dot(t1, vp); u2 = cf * dot(t2, vp);
+                            UD[lane] = u0; UD[nv + lane] = u1; UD[2 * nv + lane] = u2;
+                        }
+                        wave_sync();
+                        if (dof_lane) {
+                            const float v0 = W00 * u0 + W01 * u1 + W02 * u2;
+                            const float v1 = W01 * u0 + W11 * u1;
+                            const float v2 = W02 * u0 + W22 * u2;
+                            for (int j = 0; j <= lane; j++)
+                                HD[lane * nv + j] += v0 * UD[j] + v1 * UD[nv + j] + v2 * UD[2 * nv + j];
+                        }
+                        wave_sync();
+                    }
+                    for (int k = 0; k < nv; k++) {
+                        wave_sync();
+                        const float ik = 1.f / HD[k * nv + k];
+                        if (lane > k && lane < nv) {
+                            const float l = HD[lane * nv + k] * ik;
+                            for (int j = k + 1; j <= lane; j++) HD[lane * nv + j] -= l * HD[j * nv + k];
+                        }
+                    }
+                    wave_sync();
+                    float y = dof_lane ? -gi : 0.f;
+                    for (int k = 0; k < nv; k++) {
+                        const float yk = rl(y, k);
+                        if (lane > k && lane < nv) y -= HD[lane * nv + k] / HD[k * nv + k] * yk;
+                    }
+                    if (dof_lane) y /= HD[lane * nv + lane];
+                    for (int k = nv - 1; k >= 0; k--) {
+                        const float xk = rl(y, k);
+                        if (lane < k) y -= HD[k * nv + lane] / HD[lane * nv + lane] * xk;
+                    }
+                    if (dof_lane) p[lane] = y;
+                    wave_sync();
+                } else {
                     float invd;
                     float x = factor_solve<MAXD>(m, DL, Hr, -gi, lane, piv, &invd);
                     if (dof_lane) p[lane] = x;
@@ -1887,7 +2075,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 // directional quantities for the line search
                 spatial_mul(m, BL, DL, cdof, cinert, p, bvec, cvel, Mp, lane);
                 float sr[4] = {0, 0, 0, 0};
-                if (has) rows_of(C, bvec, sr, cell);
+                if (has) rows_of(C, bvec, sr, cell, EXT >= 3 ? C.body1 : 0);
                 float pa = 0.f, pb = 0.f;
                 if (dof_lane) {
                     pa = p[lane] * Mp[lane];
@@ -2294,7 +2482,8 @@ template <int MAXD, int EXT>
 DEV void world_step_level(const DevModel& m, const StepArgs& A, int w, float* lds) {
     // the model's own level of extended code, at most the plan's
     const int lv = m.ext < EXT ? m.ext : EXT;
-    if (EXT >= 2 && lv == 2) world_step<MAXD, false, (EXT >= 2 ? 2 : 0)>(m, A, w, lds);
+    if (EXT >= 3 && lv == 3) world_step<MAXD, false, (EXT >= 3 ? 3 : 0)>(m, A, w, lds);
+    else if (EXT >= 2 && lv == 2) world_step<MAXD, false, (EXT >= 2 ? 2 : 0)>(m, A, w, lds);
     else if (EXT >= 1 && lv == 1) world_step<MAXD, false, (EXT >= 1 ? 1 : 0)>(m, A, w, lds);
     else world_step<MAXD, false, 0>(m, A, w, lds);
 }
@@ -2383,7 +2572,8 @@ hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* 
     M.nitems = nitems;
     size_t shmem = (size_t)lds_floats * sizeof(float);
     dim3 g(grid);
-    if (ext >= 2) launch_multi_b<2>(maxd, M, g, shmem, waves == 4, stream);
+    if (ext >= 3) launch_multi_b<3>(maxd, M, g, shmem, waves == 4, stream);
+    else if (ext == 2) launch_multi_b<2>(maxd, M, g, shmem, waves == 4, stream);
     else if (ext == 1) launch_multi_b<1>(maxd, M, g, shmem, waves == 4, stream);
     else launch_multi_b<0>(maxd, M, g, shmem, waves == 4, stream);
     return hipGetLastError();
@@ -2418,21 +2608,25 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     const bool timed = taps != nullptr;   // every tap is served by the diagnostic instantiation
     const int lv = m.ext;   // the level of extended code the model needs
     if (timed) {
-        if (lv >= 2) launch_step_d<true, 2>(m, A, n, shmem, stream);
+        if (lv >= 3) launch_step_d<true, 3>(m, A, n, shmem, stream);
+        else if (lv == 2) launch_step_d<true, 2>(m, A, n, shmem, stream);
         else if (lv == 1) launch_step_d<true, 1>(m, A, n, shmem, stream);
         else launch_step_d<true, 0>(m, A, n, shmem, stream);
     } else if (waves == 4 && m.maxd <= 16) {
         if (m.maxd <= 8) {
-            if (lv >= 2) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 2>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            if (lv >= 3) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 3>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            else if (lv == 2) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 2>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
             else if (lv == 1) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 1>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
             else hipLaunchKernelGGL((rbk::step_kernel_w4<8, 0>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
         } else {
-            if (lv >= 2) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 2>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            if (lv >= 3) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 3>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+            else if (lv == 2) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 2>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
             else if (lv == 1) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 1>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
             else hipLaunchKernelGGL((rbk::step_kernel_w4<16, 0>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
         }
     } else {
-        if (lv >= 2) launch_step_d<false, 2>(m, A, n, shmem, stream);
+        if (lv >= 3) launch_step_d<false, 3>(m, A, n, shmem, stream);
+        else if (lv == 2) launch_step_d<false, 2>(m, A, n, shmem, stream);
         else if (lv == 1) launch_step_d<false, 1>(m, A, n, shmem, stream);
         else launch_step_d<false, 0>(m, A, n, shmem, stream);
     }

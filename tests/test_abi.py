@@ -62,7 +62,9 @@ def test_invalid_models_rejected(rb, case):
     elif case == "pair":
         m["geoms"][0]["type"] = "sphere"; m["geoms"][0]["size"] = [0.1, 0, 0]
     elif case == "moving_pair":
-        m["geoms"][1]["conaffinity"] = 1          # torso box would collide with the feet
+        # the torso box would collide with the feet: two moving bodies, which take pyramidal cones
+        m["geoms"][1]["conaffinity"] = 1
+        m["opt"]["cone"] = "elliptic"
     elif case == "actuator_free":
         m["actuators"][0]["joint"] = 0
     elif case == "free_range":
@@ -122,7 +124,9 @@ def test_json_models_validated_like_descriptions(rb, case):
     elif case == "pair":
         m["geoms"][0]["type"] = "sphere"; m["geoms"][0]["size"] = [0.1, 0, 0]
     elif case == "moving_pair":
+        # the torso box would collide with the feet: two moving bodies, which take pyramidal cones
         m["geoms"][1]["conaffinity"] = 1
+        m["opt"]["cone"] = "elliptic"
     elif case == "actuator_free":
         m["actuators"][0]["joint"] = 0
     elif case == "free_range":

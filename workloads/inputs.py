@@ -19,14 +19,14 @@ WORKLOAD_IDS = {"chain3": 1, "quadruped": 2, "humanoid": 3, "arm_box": 4,
                 "humanoid_terrain": 10, "chain3_damp": 11, "humanoid_damp": 12,
                 "quadruped_slip": 13, "quadruped_hfield": 14, "chain3_loop": 15, "humanoid_weld": 16,
                 "quadruped_condim6": 17, "humanoid_condim4": 18, "quadruped_elliptic": 19,
-                "humanoid_elliptic": 20}
+                "humanoid_elliptic": 20, "cube_stack": 21}
 CTRL_PERIOD = 20          # env steps between control resamples
 CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3,
             "chain3_lim": 0.0, "quadruped_lim": 0.3, "humanoid_lim": 0.2, "quadruped_terrain": 0.3,
             "humanoid_terrain": 0.2, "chain3_damp": 0.0, "humanoid_damp": 0.2,
             "quadruped_slip": 0.3, "quadruped_hfield": 0.3, "chain3_loop": 0.0, "humanoid_weld": 0.2,
             "quadruped_condim6": 0.3, "humanoid_condim4": 0.2, "quadruped_elliptic": 0.3,
-            "humanoid_elliptic": 0.2}
+            "humanoid_elliptic": 0.2, "cube_stack": 0.0}
 
 
 def rng(workload_id: int, world: int, stream: int) -> np.random.Generator:
@@ -66,6 +66,20 @@ def initial_state(model: dict, name: str, worlds, workload_id: int | None = None
         elif name in ("quadruped_lim", "quadruped_terrain", "quadruped_slip", "quadruped_hfield", "quadruped_condim6",
                       "quadruped_elliptic"):
             qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))
+        elif name == "cube_stack":
+            # each cube over the one below with a horizontal offset U[+-1.5 cm], yaw U[+-0.3],
+            # a tilt U[0, 0.02] rad about a random horizontal axis, lifted 1 mm per level, at rest
+            h = robots.CUBE_HALF
+            for k in range(len(model["bodies"]) - 1):
+                yaw, tilt, ax = g.uniform(-0.3, 0.3), g.uniform(0.0, 0.02), g.uniform(0, 2 * math.pi)
+                qy = np.array([math.cos(yaw / 2), 0, 0, math.sin(yaw / 2)])
+                s = math.sin(tilt / 2)
+                qt = np.array([math.cos(tilt / 2), s * math.cos(ax), s * math.sin(ax), 0])
+                qq = np.array([qt[0] * qy[0] - qt[3] * qy[3], qt[1] * qy[0] + qt[2] * qy[3],
+                               qt[2] * qy[0] - qt[1] * qy[3], qt[0] * qy[3] + qt[3] * qy[0]])
+                qpos[i, 7 * k:7 * k + 3] = [g.uniform(-0.015, 0.015), g.uniform(-0.015, 0.015),
+                                            h + 2 * h * k + 0.001 * (k + 1)]
+                qpos[i, 7 * k + 3:7 * k + 7] = qq / np.linalg.norm(qq)
         elif name == "chain3_loop":
             # on the loop: link 1's angle uniform around the direction of the held point, links 2
             # and 3 closing the loop (elbow bent either way, the knee's sign drawn), at rest

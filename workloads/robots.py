@@ -597,13 +597,31 @@ def humanoid_elliptic() -> dict:
     return with_elliptic(humanoid(), 1.0, "humanoid_elliptic")
 
 
+CUBE_HALF = 0.05   # cube_stack: cube half size (m)
+
+
+def cube_stack(ncube: int = 3) -> dict:
+    """Free 10 cm cubes (0.3, 0.2, 0.1 kg from the bottom) stacked on a plane: box-box contacts
+    between two moving bodies (each pair of cubes) and box-plane contacts."""
+    mb = ModelBuilder("cube_stack", timestep=0.002, nsubsteps=4)
+    mb.geom(0, "plane", [0, 0, 0], friction=1.0, contype=0, conaffinity=1)
+    h = CUBE_HALF
+    for k in range(ncube):
+        m = 0.3 - 0.1 * k
+        b = mb.body(f"cube{k}", 0, (0, 0, h + 2 * h * k), m, box_inertia(m, h, h, h))
+        mb.joint(b, "free")
+        mb.geom(b, "box", [h, h, h], friction=0.8, contype=1, conaffinity=1)
+    return mb.build()
+
+
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
                 "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
                 "chain3_damp": chain3_damp, "humanoid_damp": humanoid_damp, "quadruped_slip": quadruped_slip,
                 "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld,
                 "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4,
-                "quadruped_elliptic": quadruped_elliptic, "humanoid_elliptic": humanoid_elliptic}
+                "quadruped_elliptic": quadruped_elliptic, "humanoid_elliptic": humanoid_elliptic,
+                "cube_stack": cube_stack}
 
 
 def by_name(name: str) -> dict:
