@@ -19,14 +19,16 @@ WORKLOAD_IDS = {"chain3": 1, "quadruped": 2, "humanoid": 3, "arm_box": 4,
                 "humanoid_terrain": 10, "chain3_damp": 11, "humanoid_damp": 12,
                 "quadruped_slip": 13, "quadruped_hfield": 14, "chain3_loop": 15, "humanoid_weld": 16,
                 "quadruped_condim6": 17, "humanoid_condim4": 18, "quadruped_elliptic": 19,
-                "humanoid_elliptic": 20, "cube_stack": 21}
+                "humanoid_elliptic": 20, "cube_stack": 21, "pincer": 22}
 CTRL_PERIOD = 20          # env steps between control resamples
 CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3,
             "chain3_lim": 0.0, "quadruped_lim": 0.3, "humanoid_lim": 0.2, "quadruped_terrain": 0.3,
             "humanoid_terrain": 0.2, "chain3_damp": 0.0, "humanoid_damp": 0.2,
             "quadruped_slip": 0.3, "quadruped_hfield": 0.3, "chain3_loop": 0.0, "humanoid_weld": 0.2,
             "quadruped_condim6": 0.3, "humanoid_condim4": 0.2, "quadruped_elliptic": 0.3,
-            "humanoid_elliptic": 0.2, "cube_stack": 0.0}
+            "humanoid_elliptic": 0.2, "cube_stack": 0.0, "pincer": 0.1}
+# mean control target per actuator where it is not 0: the pincer's fingers close past each other
+CTRL_MEAN = {"pincer": [0.0, -0.4, 0.4]}
 
 
 def rng(workload_id: int, world: int, stream: int) -> np.random.Generator:
@@ -66,6 +68,9 @@ def initial_state(model: dict, name: str, worlds, workload_id: int | None = None
         elif name in ("quadruped_lim", "quadruped_terrain", "quadruped_slip", "quadruped_hfield", "quadruped_condim6",
                       "quadruped_elliptic"):
             qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))
+        elif name == "pincer":
+            # palm angle U[+-0.2], fingers open U[0, 0.3] / U[-0.3, 0] (tips apart), at rest
+            qpos[i, :] = [g.uniform(-0.2, 0.2), g.uniform(0.0, 0.3), g.uniform(-0.3, 0.0)]
         elif name == "cube_stack":
             # each cube over the one below with a horizontal offset U[+-1.5 cm], yaw U[+-0.3],
             # a tilt U[0, 0.02] rad about a random horizontal axis, lifted 1 mm per level, at rest
@@ -122,6 +127,8 @@ def ctrl_table(model: dict, name: str, worlds, nseg: int, workload_id: int | Non
     if nu and std > 0:
         for i, w in enumerate(worlds):
             out[:, i, :] = rng(wid, w, 1).normal(0.0, std, (nseg, nu))
+    if name in CTRL_MEAN:
+        out += np.asarray(CTRL_MEAN[name], np.float64)
     return out.astype(np.float32)
 
 

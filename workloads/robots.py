@@ -614,6 +614,28 @@ def cube_stack(ncube: int = 3) -> dict:
     return mb.build()
 
 
+def pincer() -> dict:
+    """A palm on a hinge about x under a fixed mount, with two box fingers (4 and 3 cm deep) on
+    hinges about y at x = -+4 cm hanging 10 cm below it; position actuators close the fingers until their tips
+    press on each other: box-box contacts between two moving bodies whose chains share the palm's
+    dof (and a ground plane under them)."""
+    mb = ModelBuilder("pincer", timestep=0.002, nsubsteps=4)
+    mb.geom(0, "plane", [0, 0, 0], friction=1.0, **GROUND_GEOM)
+    palm = mb.body("palm", 0, (0, 0, 0.3), 0.5, box_inertia(0.5, 0.06, 0.03, 0.01))
+    jp = mb.joint(palm, "hinge", (1, 0, 0), armature=0.01)
+    mb.geom(palm, "box", [0.06, 0.03, 0.01], **GHOST_GEOM)
+    mb.actuator(jp, "position", kp=5.0, kd=0.2)
+    # the right finger is narrower along y, so that no edge of one finger's face lies exactly on a
+    # side plane of the other's (a clipping tie)
+    for side, sx, hy in (("L", -1, 0.02), ("R", 1, 0.015)):
+        f = mb.body(f"finger{side}", palm, (0.04 * sx, 0, 0), 0.05, box_inertia(0.05, 0.015, hy, 0.05),
+                    ipos=(0, 0, -0.05))
+        jf = mb.joint(f, "hinge", (0, 1, 0), armature=0.001)
+        mb.geom(f, "box", [0.015, hy, 0.05], pos=(0, 0, -0.05), friction=0.8, contype=1, conaffinity=1)
+        mb.actuator(jf, "position", kp=2.0, kd=0.05)
+    return mb.build()
+
+
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
                 "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
@@ -621,7 +643,7 @@ BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, 
                 "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld,
                 "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4,
                 "quadruped_elliptic": quadruped_elliptic, "humanoid_elliptic": humanoid_elliptic,
-                "cube_stack": cube_stack}
+                "cube_stack": cube_stack, "pincer": pincer}
 
 
 def by_name(name: str) -> dict:
