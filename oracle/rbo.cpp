@@ -447,6 +447,7 @@ int pair_capacity(int t1, int t2) {
     if (t1 == RBO_GEOM_BOX && t2 == RBO_GEOM_BOX) return 8;
     if (t1 == RBO_GEOM_SPHERE && t2 == RBO_GEOM_BOX) return 1;
     if (t1 == RBO_GEOM_CAPSULE && t2 == RBO_GEOM_BOX) return 2;
+    if ((t1 == RBO_GEOM_SPHERE || t1 == RBO_GEOM_CAPSULE) && (t2 == RBO_GEOM_SPHERE || t2 == RBO_GEOM_CAPSULE)) return 1;
     if (t2 == RBO_GEOM_HFIELD) return t1 == RBO_GEOM_SPHERE ? 1 : t1 == RBO_GEOM_CAPSULE ? 2 : t1 == RBO_GEOM_BOX ? 8 : -1;
     return -1;
 }
@@ -682,6 +683,80 @@ void sphere_box(const Model& m, Data& d, int g1, int g2, double margin) {
 // Capsule g1 against box g2, as against a plane: the spheres of radius r at the capsule's two
 // segment ends (feature 0 at -z, 1 at +z of the capsule frame), each against the box by the
 // sphere rule above.
+// Closest points of segments [p1, q1] and [p2, q2] (Ericson, Real-Time Collision Detection,
+// section 5.1.9): the parameters s, t in [0, 1] minimising the distance, with nearly parallel
+// segments (a e - b^2 <= 1e-6 a e) taking s = 0.
+void closest_segments(const double* p1, const double* q1, const double* p2, const double* q2, double* c1,
+                      double* c2) {
+    double d1[3], d2[3], r[3];
+    for (int i = 0; i < 3; i++) {
+        d1[i] = q1[i] - p1[i];
+        d2[i] = q2[i] - p2[i];
+        r[i] = p1[i] - p2[i];
+    }
+    const double a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
+    auto clamp01 = [](double x) { return std::min(std::max(x, 0.0), 1.0); };
+    double s = 0, t = 0;
+    if (a <= 1e-12 && e <= 1e-12) {
+        s = t = 0;
+    } else if (a <= 1e-12) {
+        t = clamp01(f / e);
+    } else {
+        const double c = dot3(d1, r);
+        if (e <= 1e-12) {
+            s = clamp01(-c / a);
+        } else {
+            const double b = dot3(d1, d2), den = a * e - b * b;
+            s = den > 1e-6 * a * e ? clamp01((b * f - c * e) / den) : 0.0;
+            t = (b * s + f) / e;
+            if (t < 0) {
+                t = 0;
+                s = clamp01(-c / a);
+            } else if (t > 1) {
+                t = 1;
+                s = clamp01((b - c) / a);
+            }
+        }
+    }
+    for (int i = 0; i < 3; i++) {
+        c1[i] = p1[i] + d1[i] * s;
+        c2[i] = p2[i] + d2[i] * t;
+    }
+}
+
+// Spheres and capsules against each other: a capsule is its segment (local z, half-length
+// size[1]) swept by its radius, a sphere a point swept by its radius; the contact joins the
+// closest points c1 (on g1) and c2 (on g2): distance |c2 - c1| - r1 - r2, normal from c1 to c2
+// (+z when they coincide), point halfway between the surfaces, feature 0.
+void round_pair(const Model& m, Data& d, int g1, int g2, double margin) {
+    double p[2][3], q[2][3];
+    for (int k = 0; k < 2; k++) {
+        const int g = k == 0 ? g1 : g2;
+        const double* x = &d.gx[3 * g];
+        const double* R = &d.gR[9 * g];
+        const double h = m.gtype[g] == RBO_GEOM_CAPSULE ? m.gsize[3 * g + 1] : 0.0;
+        for (int i = 0; i < 3; i++) {
+            p[k][i] = x[i] - h * R[3 * i + 2];
+            q[k][i] = x[i] + h * R[3 * i + 2];
+        }
+    }
+    double c1[3], c2[3];
+    closest_segments(p[0], q[0], p[1], q[1], c1, c2);
+    const double r1 = m.gsize[3 * g1], r2 = m.gsize[3 * g2];
+    double n[3] = {c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2]};
+    const double len = std::sqrt(dot3(n, n));
+    if (len > 0) {
+        for (int i = 0; i < 3; i++) n[i] /= len;
+    } else {
+        n[0] = 0; n[1] = 0; n[2] = 1;
+    }
+    const double dist = len - r1 - r2;
+    if (dist >= margin) return;
+    double pos[3];
+    for (int i = 0; i < 3; i++) pos[i] = c1[i] + n[i] * (r1 + 0.5 * dist);
+    add_contact(m, d, g1, g2, 0, dist, pos, n);
+}
+
 void capsule_box(const Model& m, Data& d, int g1, int g2, double margin) {
     const double* x = &d.gx[3 * g1];
     const double* R = &d.gR[9 * g1];
@@ -789,6 +864,10 @@ void collide(const Model& m, Data& d) {
             }
             if (t1 == RBO_GEOM_CAPSULE && t2 == RBO_GEOM_BOX) {
                 capsule_box(m, d, g1, g2, margin);
+                continue;
+            }
+            if ((t1 == RBO_GEOM_SPHERE || t1 == RBO_GEOM_CAPSULE) && (t2 == RBO_GEOM_SPHERE || t2 == RBO_GEOM_CAPSULE)) {
+                round_pair(m, d, g1, g2, margin);
                 continue;
             }
             if (t2 == RBO_GEOM_HFIELD) {
