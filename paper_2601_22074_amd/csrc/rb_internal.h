@@ -19,6 +19,7 @@
 #define RB_PAIR_BOXBOX 16         // pair_type of a box-box pair (plane pairs hold g2's geom type)
 #define RB_PAIR_SPHEREBOX 17      // pair_type of a sphere (g1) - box (g2) pair
 #define RB_PAIR_CAPSULEBOX 18     // pair_type of a capsule (g1) - box (g2) pair: its two end spheres
+#define RB_PAIR_ROUND 19          // pair_type of a sphere or capsule (g1) - sphere or capsule (g2) pair
 #define RB_PAIR_HFIELD 32         // pair_type of a height field (g1) - geom (g2) pair: this + g2's geom type
 #define RB_BB_FLOATS 96           // LDS floats per box-box pair: clip buffers, contacts, normal
 #define RB_MAX_GROW 64            // generic rows: equality rows and contacts' torsional / rolling rows
@@ -102,7 +103,8 @@ struct DevModel {
     // pair, the capsule of a capsule-box pair, or the lower-numbered box
     const int* pair_g1;
     const int* pair_g2;
-    const int* pair_type;      // geom type of g2 (plane pairs), RB_PAIR_BOXBOX, RB_PAIR_SPHEREBOX or RB_PAIR_CAPSULEBOX
+    const int* pair_type;      // geom type of g2 (plane pairs), RB_PAIR_BOXBOX, RB_PAIR_SPHEREBOX, RB_PAIR_CAPSULEBOX,
+                               // RB_PAIR_ROUND, or RB_PAIR_HFIELD + g2's type
     const int* pair_slot;      // box-box pairs: index of the pair's LDS block; -1 otherwise
     const int* pair_body;      // the body that can move
     const int* pair_cap;       // contacts the pair can produce
@@ -111,6 +113,7 @@ struct DevModel {
     const float* pair_margin;
     const int* pair_frictionless;  // 1 when the pair's larger geom condim is 1 (normal row only)
     const int* geom_body;
+    const int* geom_type;      // RB_GEOM_* per geom
     const float* geom_pos;     // [3]
     const float* geom_quat;    // [4]
     const float* geom_size;    // [3]

@@ -401,9 +401,11 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             bool box_pair = d->geom_type[g1] == RB_GEOM_BOX && d->geom_type[g2] == RB_GEOM_BOX;
             bool sphere_box = d->geom_type[g1] == RB_GEOM_SPHERE && d->geom_type[g2] == RB_GEOM_BOX;
             bool capsule_box = d->geom_type[g1] == RB_GEOM_CAPSULE && d->geom_type[g2] == RB_GEOM_BOX;
-            if (!plane_pair && !box_pair && !sphere_box && !capsule_box && !hfield_pair)
+            auto round = [&](int g) { return d->geom_type[g] == RB_GEOM_SPHERE || d->geom_type[g] == RB_GEOM_CAPSULE; };
+            bool round_pair = round(g1) && round(g2);
+            if (!plane_pair && !box_pair && !sphere_box && !capsule_box && !hfield_pair && !round_pair)
                 return fail(RB_EINVAL, "unsupported collision pair (only plane or height field vs sphere, capsule, "
-                                       "box; box vs box; sphere or capsule vs box)");
+                                       "box; box vs box; sphere or capsule vs box; sphere or capsule vs sphere or capsule)");
             pairs.push_back({g1, g2});
         }
     std::sort(pairs.begin(), pairs.end(), [](const Pair& x, const Pair& y) {
@@ -424,9 +426,11 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         int g1 = pairs[k].g1, g2 = pairs[k].g2;
         pg1[k] = g1;
         pg2[k] = g2;
-        ptype[k] = d->geom_type[g1] == RB_GEOM_BOX       ? RB_PAIR_BOXBOX
-                   : d->geom_type[g1] == RB_GEOM_SPHERE  ? RB_PAIR_SPHEREBOX
-                   : d->geom_type[g1] == RB_GEOM_CAPSULE ? RB_PAIR_CAPSULEBOX
+        const bool g2box = d->geom_type[g2] == RB_GEOM_BOX;
+        ptype[k] = d->geom_type[g1] == RB_GEOM_BOX                ? RB_PAIR_BOXBOX
+                   : (d->geom_type[g1] == RB_GEOM_SPHERE && g2box)  ? RB_PAIR_SPHEREBOX
+                   : (d->geom_type[g1] == RB_GEOM_CAPSULE && g2box) ? RB_PAIR_CAPSULEBOX
+                   : (d->geom_type[g1] == RB_GEOM_SPHERE || d->geom_type[g1] == RB_GEOM_CAPSULE) ? RB_PAIR_ROUND
                    : d->geom_type[g1] == RB_GEOM_HFIELD  ? RB_PAIR_HFIELD + d->geom_type[g2]
                                                          : d->geom_type[g2];
         if (ptype[k] == RB_PAIR_BOXBOX) pslot[k] = nbb++;
@@ -451,7 +455,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             pmur[k] = fmax(d->geom_friction_roll, 0.0001);
         }
         const int shape = ptype[k] >= RB_PAIR_HFIELD ? ptype[k] - RB_PAIR_HFIELD : ptype[k];
-        pcap[k] = (shape == RB_GEOM_SPHERE || shape == RB_PAIR_SPHEREBOX)      ? 1
+        pcap[k] = (shape == RB_GEOM_SPHERE || shape == RB_PAIR_SPHEREBOX || shape == RB_PAIR_ROUND) ? 1
                   : (shape == RB_GEOM_CAPSULE || shape == RB_PAIR_CAPSULEBOX) ? 2
                                                                                : 8;
         maxcon += pcap[k];
@@ -663,6 +667,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     I(pslot, &m.pair_slot);
     F(psig, &m.pair_sigma); F(pmu, &m.pair_mu); F(pmar, &m.pair_margin); I(pfric0, &m.pair_frictionless);
     I(std::vector<int>(d->geom_body, d->geom_body + ng), &m.geom_body);
+    I(std::vector<int>(d->geom_type, d->geom_type + ng), &m.geom_type);
     F(std::vector<double>(d->geom_pos, d->geom_pos + 3 * ng), &m.geom_pos);
     F(std::vector<double>(d->geom_quat, d->geom_quat + 4 * ng), &m.geom_quat);
     F(std::vector<double>(d->geom_size, d->geom_size + 3 * ng), &m.geom_size);
@@ -709,6 +714,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.ext = ext2 ? ext2 : (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_CAPSULEBOX) > 0 ||
+             std::count(ptype.begin(), ptype.end(), RB_PAIR_ROUND) > 0 ||
              std::count_if(ptype.begin(), ptype.end(), [](int t) { return t >= RB_PAIR_HFIELD; }) > 0 ||
              std::count(pfric0.begin(), pfric0.end(), 1) > 0) ? 1 : 0;
     m.dt = (float)d->timestep;

@@ -527,7 +527,7 @@ DEV float pick3(const float* a, int i) { return i == 0 ? a[0] : (i == 1 ? a[1] :
 // box vertices k = 4x + 2y + z by sign bits.  A sphere-box pair has the one candidate 0.
 DEV int pair_ncand(int type) {
     if (type >= RB_PAIR_HFIELD) type -= RB_PAIR_HFIELD;   // a height field: as the plane
-    return (type == RB_GEOM_SPHERE || type == RB_PAIR_SPHEREBOX)      ? 1
+    return (type == RB_GEOM_SPHERE || type == RB_PAIR_SPHEREBOX || type == RB_PAIR_ROUND) ? 1
            : (type == RB_GEOM_CAPSULE || type == RB_PAIR_CAPSULEBOX) ? 2
                                                                      : 8;
 }
@@ -587,6 +587,60 @@ DEV void pair_candidate(const DevModel& m, const float* L, const float* gsize, i
     geom_pose(m, L, m.pair_g2[p], x, R);
     const float* sz = gsize + 3 * m.pair_g2[p];
     const int type = m.pair_type[p];
+    if (EXT && type == RB_PAIR_ROUND) {
+        // spheres and capsules: segments (a sphere's of length 0) swept by their radii; the
+        // closest points of the two segments (Ericson, Real-Time Collision Detection, section
+        // 5.1.9; nearly parallel segments, a e - b^2 <= 1e-6 a e, take s = 0), the contact
+        // joining them from g1 to g2 (+z when they coincide), halfway between the surfaces
+        const int g1 = m.pair_g1[p], g2 = m.pair_g2[p];
+        const float h1 = m.geom_type[g1] == RB_GEOM_CAPSULE ? gsize[3 * g1 + 1] : 0.f;
+        const float h2 = m.geom_type[g2] == RB_GEOM_CAPSULE ? gsize[3 * g2 + 1] : 0.f;
+        const float d1[3] = {2.f * h1 * Rp[2], 2.f * h1 * Rp[5], 2.f * h1 * Rp[8]};
+        const float d2[3] = {2.f * h2 * R[2], 2.f * h2 * R[5], 2.f * h2 * R[8]};
+        const float p1[3] = {xp[0] - h1 * Rp[2], xp[1] - h1 * Rp[5], xp[2] - h1 * Rp[8]};
+        const float p2[3] = {x[0] - h2 * R[2], x[1] - h2 * R[5], x[2] - h2 * R[8]};
+        const float rr[3] = {p1[0] - p2[0], p1[1] - p2[1], p1[2] - p2[2]};
+        const float a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, rr);
+        auto clamp01 = [](float v) { return fminf(fmaxf(v, 0.f), 1.f); };
+        float s = 0.f, t = 0.f;
+        if (a <= 1e-12f && e <= 1e-12f) {
+        } else if (a <= 1e-12f) {
+            t = clamp01(f / e);
+        } else {
+            const float c = dot(d1, rr);
+            if (e <= 1e-12f) {
+                s = clamp01(-c / a);
+            } else {
+                const float b = dot(d1, d2), den = a * e - b * b;
+                s = den > 1e-6f * a * e ? clamp01((b * f - c * e) / den) : 0.f;
+                t = (b * s + f) / e;
+                if (t < 0.f) {
+                    t = 0.f;
+                    s = clamp01(-c / a);
+                } else if (t > 1.f) {
+                    t = 1.f;
+                    s = clamp01((b - c) / a);
+                }
+            }
+        }
+        const float c1[3] = {p1[0] + d1[0] * s, p1[1] + d1[1] * s, p1[2] + d1[2] * s};
+        const float c2[3] = {p2[0] + d2[0] * t, p2[1] + d2[1] * t, p2[2] + d2[2] * t};
+        float n[3] = {c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2]};
+        const float len = sqrtf(dot(n, n));
+        if (len > 0.f) {
+            const float il = 1.0f / len;
+            n[0] *= il; n[1] *= il; n[2] *= il;
+        } else {
+            n[0] = 0.f; n[1] = 0.f; n[2] = 1.f;
+        }
+        const float r1 = gsize[3 * g1], r2 = gsize[3 * g2];
+        const float dd = len - r1 - r2;
+        *dist = dd;
+        nrm[0] = n[0]; nrm[1] = n[1]; nrm[2] = n[2];
+        const float hh = r1 + 0.5f * dd;
+        pos[0] = c1[0] + n[0] * hh; pos[1] = c1[1] + n[1] * hh; pos[2] = c1[2] + n[2] * hh;
+        return;
+    }
     if (EXT && (type == RB_PAIR_SPHEREBOX || type == RB_PAIR_CAPSULEBOX)) {
         const float rad = gsize[3 * m.pair_g1[p]];
         if (type == RB_PAIR_CAPSULEBOX) {

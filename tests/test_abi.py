@@ -60,7 +60,7 @@ def test_invalid_models_rejected(rb, case):
     elif case == "two_joints":
         m["joints"].insert(2, dict(m["joints"][1]))
     elif case == "pair":
-        m["geoms"][0]["type"] = "sphere"; m["geoms"][0]["size"] = [0.1, 0, 0]
+        m["geoms"][0]["body"] = 1                 # a plane on a moving body
     elif case == "moving_pair":
         # the torso box would collide with the feet: two moving bodies, which take pyramidal cones
         m["geoms"][1]["conaffinity"] = 1
@@ -122,7 +122,7 @@ def test_json_models_validated_like_descriptions(rb, case):
     elif case == "two_joints":
         m["joints"].insert(2, dict(m["joints"][1]))
     elif case == "pair":
-        m["geoms"][0]["type"] = "sphere"; m["geoms"][0]["size"] = [0.1, 0, 0]
+        m["geoms"][0]["body"] = 1                 # a plane on a moving body
     elif case == "moving_pair":
         # the torso box would collide with the feet: two moving bodies, which take pyramidal cones
         m["geoms"][1]["conaffinity"] = 1

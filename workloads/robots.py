@@ -636,6 +636,25 @@ def pincer() -> dict:
     return mb.build()
 
 
+def humanoid_self() -> dict:
+    """humanoid whose left and right leg capsules (thighs and shins) collide with each other:
+    self-collision between two branches of the tree below the pelvis (16 capsule pairs), with a
+    Newton budget of 8 updates for the extra rows."""
+    m = humanoid()
+    m["name"] = "humanoid_self"
+    m["opt"]["iterations"] = 8
+    names = [b.get("name", "") for b in m["bodies"]]
+    for g in m["geoms"]:
+        if g["type"] != "capsule":
+            continue
+        bn = names[g["body"]]
+        if bn in ("L_hip_yaw", "L_knee"):
+            g["contype"] = g["contype"] | 4
+        elif bn in ("R_hip_yaw", "R_knee"):
+            g["conaffinity"] = g["conaffinity"] | 4
+    return m
+
+
 BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, "arm_box": arm_box,
                 "chain3_lim": chain3_lim, "quadruped_lim": quadruped_lim, "humanoid_lim": humanoid_lim,
                 "quadruped_terrain": quadruped_terrain, "humanoid_terrain": humanoid_terrain,
@@ -643,7 +662,7 @@ BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, 
                 "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld,
                 "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4,
                 "quadruped_elliptic": quadruped_elliptic, "humanoid_elliptic": humanoid_elliptic,
-                "cube_stack": cube_stack, "pincer": pincer}
+                "cube_stack": cube_stack, "pincer": pincer, "humanoid_self": humanoid_self}
 
 
 def by_name(name: str) -> dict:
