@@ -64,6 +64,8 @@ WORKLOAD_TEXT = {
                   "box-box contacts between moving bodies (dense Newton Hessian), dt 2 ms x 4 substeps",
     "pincer": "a hinged palm with two hinged box fingers closed onto each other by position actuators: box-box "
               "contacts between bodies whose chains share the palm's dof, dt 2 ms x 4 substeps",
+    "pincer_cube": "the pincer holding a free 4 cm cube between its fingertips while the palm swings (finger-cube "
+                   "contacts between moving bodies, friction carrying the cube), dt 2 ms x 4 substeps",
     "humanoid_self": "humanoid whose left and right thigh and shin capsules collide with each other (16 capsule "
                      "pairs, hips adducted so the legs meet; dense Newton Hessian), otherwise as humanoid",
 }
@@ -72,7 +74,8 @@ DEFAULT_WORLDS = {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 
                   "quadruped_lim": 4096, "quadruped_terrain": 4096, "humanoid_terrain": 8192,
                   "humanoid_damp": 8192, "quadruped_hfield": 4096, "humanoid_weld": 8192, "chain3_loop": 8192,
                   "quadruped_condim6": 4096, "humanoid_condim4": 8192, "quadruped_elliptic": 4096,
-                  "humanoid_elliptic": 8192, "cube_stack": 8192, "pincer": 8192, "humanoid_self": 8192}
+                  "humanoid_elliptic": 8192, "cube_stack": 8192, "pincer": 8192, "humanoid_self": 8192,
+                  "pincer_cube": 8192}
 WORKLOAD_TEXT["serve"] = ("serving: Poisson arrivals of rollout requests, model uniform over chain3/quadruped/humanoid/"
                           "arm_box, worlds log-uniform 16-4096, horizon uniform 50-500 env steps, device-side seeded "
                           "inputs, HBM-budget admission, continuous batching in one fused launch per tick")

@@ -108,7 +108,8 @@ def test_single_step_from_initial_states(oracle_mod, name):
                                           ("chain3_loop", 200), ("humanoid_weld", 200),
                                           ("quadruped_condim6", 200), ("humanoid_condim4", 200),
                                           ("quadruped_elliptic", 200), ("humanoid_elliptic", 200),
-                                          ("cube_stack", 200), ("pincer", 200), ("humanoid_self", 200)])
+                                          ("cube_stack", 200), ("pincer", 200), ("humanoid_self", 200),
+                                          ("pincer_cube", 400)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory (up to env step 1000 for the quadruped and humanoid
     workloads), hand its state (rounded to FP32) to the GPU every 25 env steps and compare one
@@ -205,7 +206,7 @@ def test_chain3_500_steps(oracle_mod):
 @pytest.mark.parametrize("name", ["quadruped", "humanoid", "arm_box", "quadruped_terrain", "humanoid_terrain",
                                   "quadruped_slip", "quadruped_hfield", "humanoid_weld", "quadruped_condim6",
                                   "humanoid_condim4", "quadruped_elliptic", "humanoid_elliptic", "cube_stack",
-                                  "pincer", "humanoid_self"])
+                                  "pincer", "humanoid_self", "pincer_cube"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -426,7 +427,8 @@ def test_run_twice_bitwise(oracle_mod):
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "humanoid_lim", "quadruped_terrain",
                                   "humanoid_terrain", "humanoid_damp", "quadruped_hfield", "chain3_loop",
                                   "humanoid_weld", "quadruped_condim6", "humanoid_condim4", "quadruped_elliptic",
-                                  "humanoid_elliptic", "cube_stack", "pincer", "humanoid_self"])
+                                  "humanoid_elliptic", "cube_stack", "pincer", "humanoid_self",
+                                  "pincer_cube"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""

@@ -110,6 +110,18 @@ def test_stack_forces_carry_the_weights(oracle_mod):
     assert rest >= 6
 
 
+def test_pincer_holds_the_cube():
+    """pincer_cube with the palm held still (targets 0) for 2 s: the fingers' friction carries the
+    cube, which stays between the fingertips (above 0.2 m), on both paths."""
+    import copy
+    m = robots.pincer_cube()
+    W = inputs.workload("pincer_cube", 16, 1)
+    u = np.tile(np.array([[0.0, -0.2, 0.2]], np.float32), (16, 1))
+    g = gpu_run(m, W["qpos"], W["qvel"], u, nsteps=250)
+    assert np.all(g["status"] & 1 == 0)
+    assert g["qpos"][:, 5].min() > 0.2, g["qpos"][:, 5]
+
+
 def test_fused_equals_plain():
     """cube_stack in a fused launch beside the quadruped computes the same bits as its own plain
     launch."""

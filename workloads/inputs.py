@@ -20,7 +20,7 @@ WORKLOAD_IDS = {"chain3": 1, "quadruped": 2, "humanoid": 3, "arm_box": 4,
                 "quadruped_slip": 13, "quadruped_hfield": 14, "chain3_loop": 15, "humanoid_weld": 16,
                 "quadruped_condim6": 17, "humanoid_condim4": 18, "quadruped_elliptic": 19,
                 "humanoid_elliptic": 20, "cube_stack": 21, "pincer": 22,
-                "humanoid_self": 23}
+                "humanoid_self": 23, "pincer_cube": 24}
 CTRL_PERIOD = 20          # env steps between control resamples
 CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3,
             "chain3_lim": 0.0, "quadruped_lim": 0.3, "humanoid_lim": 0.2, "quadruped_terrain": 0.3,
@@ -28,9 +28,9 @@ CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3,
             "quadruped_slip": 0.3, "quadruped_hfield": 0.3, "chain3_loop": 0.0, "humanoid_weld": 0.2,
             "quadruped_condim6": 0.3, "humanoid_condim4": 0.2, "quadruped_elliptic": 0.3,
             "humanoid_elliptic": 0.2, "cube_stack": 0.0, "pincer": 0.1,
-            "humanoid_self": 0.2}
+            "humanoid_self": 0.2, "pincer_cube": 0.1}
 # mean control target per actuator where it is not 0: the pincer's fingers close past each other
-CTRL_MEAN = {"pincer": [0.0, -0.4, 0.4],
+CTRL_MEAN = {"pincer": [0.0, -0.4, 0.4], "pincer_cube": [0.0, -0.2, 0.2],
              # the humanoid's hips adducted (left roll -, right roll +) so that its legs meet
              "humanoid_self": [0.0, -0.25] + [0.0] * 5 + [0.25] + [0.0] * 21}
 
@@ -75,6 +75,10 @@ def initial_state(model: dict, name: str, worlds, workload_id: int | None = None
         elif name == "pincer":
             # palm angle U[+-0.2], fingers open U[0, 0.3] / U[-0.3, 0] (tips apart), at rest
             qpos[i, :] = [g.uniform(-0.2, 0.2), g.uniform(0.0, 0.3), g.uniform(-0.3, 0.0)]
+        elif name == "pincer_cube":
+            # palm angle U[+-0.05], fingertips just touching the cube (U[0, 0.01] rad past contact),
+            # the cube between them at rest
+            qpos[i, :3] = [g.uniform(-0.05, 0.05), -0.0625 - g.uniform(0, 0.01), 0.0625 + g.uniform(0, 0.01)]
         elif name == "cube_stack":
             # each cube over the one below with a horizontal offset U[+-1.5 cm], yaw U[+-0.3],
             # a tilt U[0, 0.02] rad about a random horizontal axis, lifted 1 mm per level, at rest

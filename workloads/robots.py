@@ -636,6 +636,24 @@ def pincer() -> dict:
     return mb.build()
 
 
+def pincer_cube() -> dict:
+    """The pincer holding a free 4 cm cube (50 g) between its fingertips: the fingers squeeze it
+    and friction carries its weight while the palm swings (finger-cube contacts between moving
+    bodies, the analogue of the paper's cube lifting)."""
+    m = pincer()
+    m["name"] = "pincer_cube"
+    mb_cube = {"name": "cube", "parent": 0, "pos": [0.0, 0.0, 0.3 - 0.08], "quat": [1.0, 0.0, 0.0, 0.0],
+               "ipos": [0.0, 0.0, 0.0], "iquat": [1.0, 0.0, 0.0, 0.0], "mass": 0.05,
+               "inertia": box_inertia(0.05, 0.02, 0.02, 0.02)}
+    m["bodies"].append(mb_cube)
+    cb = len(m["bodies"]) - 1
+    m["joints"].append({"type": "free", "body": cb, "pos": [0.0, 0.0, 0.0], "axis": [0.0, 0.0, 1.0],
+                        "armature": 0.0})
+    m["geoms"].append({"type": "box", "body": cb, "pos": [0.0, 0.0, 0.0], "quat": [1.0, 0.0, 0.0, 0.0],
+                       "size": [0.02, 0.02, 0.02], "friction": 1.0, "contype": 1, "conaffinity": 1, "margin": 0.0})
+    return m
+
+
 def humanoid_self() -> dict:
     """humanoid whose left and right leg capsules (thighs and shins) collide with each other:
     self-collision between two branches of the tree below the pelvis (16 capsule pairs), with a
@@ -662,7 +680,8 @@ BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, 
                 "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld,
                 "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4,
                 "quadruped_elliptic": quadruped_elliptic, "humanoid_elliptic": humanoid_elliptic,
-                "cube_stack": cube_stack, "pincer": pincer, "humanoid_self": humanoid_self}
+                "cube_stack": cube_stack, "pincer": pincer, "humanoid_self": humanoid_self,
+                "pincer_cube": pincer_cube}
 
 
 def by_name(name: str) -> dict:
