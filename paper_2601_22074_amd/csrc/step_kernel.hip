@@ -2579,6 +2579,83 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)))
 }  // namespace rbk
 
 // ------------------------------------------------------------------ launch
+// The instantiations are many (chain bound x level of extended code x plain, diagnostic, 4-wave
+// and fused forms) and each carries a whole inlined step, so the library compiles this file in
+// parts, in parallel: with RB_PART = k a translation unit defines only the launchers of part k
+// (the explicit instantiations below), and part 0 also holds the dispatchers, which reach every
+// launcher through explicit instantiation declarations.  Without RB_PART one unit holds all.
+#ifndef RB_PART
+#define RB_PART -1
+#endif
+#define RB_IN_PART(k) (RB_PART < 0 || RB_PART == (k))
+
+template <int MAXD, bool TIMED, int EXT>
+void launch_step_t(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
+    hipLaunchKernelGGL((rbk::step_kernel<MAXD, TIMED, EXT>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+}
+template <int MAXD, int EXT>
+void launch_step_w4_t(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
+    hipLaunchKernelGGL((rbk::step_kernel_w4<MAXD, EXT>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
+}
+template <int MAXD, int EXT>
+void launch_multi_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_t stream) {
+    hipLaunchKernelGGL((rbk::multi_kernel<MAXD, EXT>), g, dim3(RB_WAVE), shmem, stream, M);
+}
+template <int MAXD, int EXT>
+void launch_multi_w4_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_t stream) {
+    hipLaunchKernelGGL((rbk::multi_kernel_w4<MAXD, EXT>), g, dim3(RB_WAVE), shmem, stream, M);
+}
+
+// X is empty (an explicit instantiation definition) or `extern` (a declaration)
+#define RB_STEP_I(X, D, T, E) \
+    X template void launch_step_t<D, T, E>(const DevModel&, const rbk::StepArgs&, int, size_t, hipStream_t);
+#define RB_W4_I(X, D, E) \
+    X template void launch_step_w4_t<D, E>(const DevModel&, const rbk::StepArgs&, int, size_t, hipStream_t);
+#define RB_MULTI_I(X, D, E) X template void launch_multi_t<D, E>(const rbk::MultiArgs&, dim3, size_t, hipStream_t);
+#define RB_MULTI_W4_I(X, D, E) \
+    X template void launch_multi_w4_t<D, E>(const rbk::MultiArgs&, dim3, size_t, hipStream_t);
+#define RB_LEVELS(F, X, ...) F(X, __VA_ARGS__, 0) F(X, __VA_ARGS__, 1) F(X, __VA_ARGS__, 2) F(X, __VA_ARGS__, 3)
+
+// every launcher the dispatchers use
+RB_LEVELS(RB_STEP_I, extern, 8, false) RB_LEVELS(RB_STEP_I, extern, 16, false) RB_LEVELS(RB_STEP_I, extern, 32, false)
+RB_LEVELS(RB_STEP_I, extern, 8, true) RB_LEVELS(RB_STEP_I, extern, 16, true) RB_LEVELS(RB_STEP_I, extern, 32, true)
+RB_LEVELS(RB_W4_I, extern, 8) RB_LEVELS(RB_W4_I, extern, 16)
+RB_LEVELS(RB_MULTI_I, extern, 8) RB_LEVELS(RB_MULTI_I, extern, 16) RB_LEVELS(RB_MULTI_I, extern, 32)
+RB_LEVELS(RB_MULTI_W4_I, extern, 8) RB_LEVELS(RB_MULTI_W4_I, extern, 16)
+
+// The parts, each defining launchers that inline 12 to 15 steps in all (a fused launcher inlines
+// one step per chain bound and level at or below its own).  RB_NPARTS must match the list.
+#define RB_NPARTS 9
+#if RB_IN_PART(0)
+RB_LEVELS(RB_STEP_I, , 8, false) RB_LEVELS(RB_STEP_I, , 16, false) RB_LEVELS(RB_STEP_I, , 32, false)
+#endif
+#if RB_IN_PART(1)
+RB_LEVELS(RB_STEP_I, , 8, true) RB_LEVELS(RB_STEP_I, , 16, true) RB_LEVELS(RB_STEP_I, , 32, true)
+#endif
+#if RB_IN_PART(2)
+RB_LEVELS(RB_W4_I, , 8) RB_LEVELS(RB_W4_I, , 16)
+RB_MULTI_I(, 8, 0) RB_MULTI_I(, 8, 1) RB_MULTI_I(, 8, 2)
+#endif
+#if RB_IN_PART(3)
+RB_MULTI_I(, 8, 3) RB_LEVELS(RB_MULTI_W4_I, , 8)
+#endif
+#if RB_IN_PART(4)
+RB_MULTI_I(, 16, 0) RB_MULTI_I(, 16, 1) RB_MULTI_I(, 16, 3)
+#endif
+#if RB_IN_PART(5)
+RB_MULTI_I(, 16, 2) RB_MULTI_W4_I(, 16, 3)
+#endif
+#if RB_IN_PART(6)
+RB_MULTI_W4_I(, 16, 0) RB_MULTI_W4_I(, 16, 1) RB_MULTI_W4_I(, 16, 2)
+#endif
+#if RB_IN_PART(7)
+RB_MULTI_I(, 32, 0) RB_MULTI_I(, 32, 3)
+#endif
+#if RB_IN_PART(8)
+RB_MULTI_I(, 32, 1) RB_MULTI_I(, 32, 2)
+#endif
+
+#if RB_IN_PART(0)
 rbk::StepArgs rb_make_args(int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
                            const DevContactsOut* co, uint32_t* status_out) {
     rbk::StepArgs A;
@@ -2603,18 +2680,17 @@ void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* 
     *(rbk::StepArgs*)dst = A;
 }
 
-template <int MAXD, int EXT>
-static void launch_multi_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, bool w4, hipStream_t stream) {
-    if (w4 && MAXD <= 16)
-        hipLaunchKernelGGL((rbk::multi_kernel_w4<(MAXD <= 16 ? MAXD : 16), EXT>), g, dim3(RB_WAVE), shmem, stream, M);
-    else
-        hipLaunchKernelGGL((rbk::multi_kernel<MAXD, EXT>), g, dim3(RB_WAVE), shmem, stream, M);
-}
 template <int EXT>
 static void launch_multi_b(int maxd, const rbk::MultiArgs& M, dim3 g, size_t shmem, bool w4, hipStream_t stream) {
-    if (maxd <= 8) launch_multi_t<8, EXT>(M, g, shmem, w4, stream);
-    else if (maxd <= 16) launch_multi_t<16, EXT>(M, g, shmem, w4, stream);
-    else launch_multi_t<32, EXT>(M, g, shmem, false, stream);
+    if (maxd <= 8) {
+        if (w4) launch_multi_w4_t<8, EXT>(M, g, shmem, stream);
+        else launch_multi_t<8, EXT>(M, g, shmem, stream);
+    } else if (maxd <= 16) {
+        if (w4) launch_multi_w4_t<16, EXT>(M, g, shmem, stream);
+        else launch_multi_t<16, EXT>(M, g, shmem, stream);
+    } else {
+        launch_multi_t<32, EXT>(M, g, shmem, stream);
+    }
 }
 
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
@@ -2633,15 +2709,17 @@ hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* 
     return hipGetLastError();
 }
 
-template <int MAXD, bool TIMED, int EXT>
-static void launch_step_t(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
-    hipLaunchKernelGGL((rbk::step_kernel<MAXD, TIMED, EXT>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-}
 template <bool TIMED, int EXT>
 static void launch_step_d(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
     if (m.maxd <= 8) launch_step_t<8, TIMED, EXT>(m, A, n, shmem, stream);
     else if (m.maxd <= 16) launch_step_t<16, TIMED, EXT>(m, A, n, shmem, stream);
     else launch_step_t<32, TIMED, EXT>(m, A, n, shmem, stream);
+}
+
+template <int EXT>
+static void launch_step_w4_d(const DevModel& m, const rbk::StepArgs& A, int n, size_t shmem, hipStream_t stream) {
+    if (m.maxd <= 8) launch_step_w4_t<8, EXT>(m, A, n, shmem, stream);
+    else launch_step_w4_t<16, EXT>(m, A, n, shmem, stream);
 }
 
 hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
@@ -2667,17 +2745,10 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
         else if (lv == 1) launch_step_d<true, 1>(m, A, n, shmem, stream);
         else launch_step_d<true, 0>(m, A, n, shmem, stream);
     } else if (waves == 4 && m.maxd <= 16) {
-        if (m.maxd <= 8) {
-            if (lv >= 3) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 3>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-            else if (lv == 2) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 2>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-            else if (lv == 1) hipLaunchKernelGGL((rbk::step_kernel_w4<8, 1>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-            else hipLaunchKernelGGL((rbk::step_kernel_w4<8, 0>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-        } else {
-            if (lv >= 3) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 3>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-            else if (lv == 2) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 2>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-            else if (lv == 1) hipLaunchKernelGGL((rbk::step_kernel_w4<16, 1>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-            else hipLaunchKernelGGL((rbk::step_kernel_w4<16, 0>), dim3(n), dim3(RB_WAVE), shmem, stream, m, A);
-        }
+        if (lv >= 3) launch_step_w4_d<3>(m, A, n, shmem, stream);
+        else if (lv == 2) launch_step_w4_d<2>(m, A, n, shmem, stream);
+        else if (lv == 1) launch_step_w4_d<1>(m, A, n, shmem, stream);
+        else launch_step_w4_d<0>(m, A, n, shmem, stream);
     } else {
         if (lv >= 3) launch_step_d<false, 3>(m, A, n, shmem, stream);
         else if (lv == 2) launch_step_d<false, 2>(m, A, n, shmem, stream);
@@ -2686,3 +2757,4 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     }
     return hipGetLastError();
 }
+#endif  // RB_IN_PART(0)
