@@ -175,13 +175,15 @@ def run_mix(args):
     plan = rb.Multi([x["batch"] for x in S])
     for i, x in enumerate(S):
         plan.bind(i, x["u"], x["q"], x["v"], x["con"], x["st"])
-    choice, timings = autotune.tune(plan, [(x["u"], x["q"], x["v"]) for x in S], reps=3, resident=args.resident)
+    choice, timings = autotune.tune(plan, [(x["u"], x["q"], x["v"]) for x in S], reps=10, resident=args.resident,
+                                    advance=warm)
     for i, x in enumerate(S):
         plan.bind(i, x["u"], x["q"], x["v"], x["con"], x["st"])
     if choice[0] != "fused":
-        choice = ("fused", rb.ORDER_HEAVY_FIRST, 0, 0)
+        choice = ("fused", rb.ORDER_HEAVY_FIRST, 0, 0, 1)
     plan.set_schedule(choice[1], choice[2])
     plan.set_occupancy(choice[3])
+    plan.set_group(choice[4])
 
     def load_ctrl(S, s):
         for x, u in zip(S, seg(S, s)):
@@ -198,6 +200,7 @@ def run_mix(args):
         plan.bind(i, x["u"], x["q"], x["v"], x["con"], x["st"])
     plan.set_schedule(choice[1], choice[2])
     plan.set_occupancy(choice[3])
+    plan.set_group(choice[4])
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
     plan.graph_capture(P, side)
@@ -223,7 +226,8 @@ def run_mix(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT["mix"], "worlds": nworlds, "env_steps": K, "form": best,
-                   "schedule": {"order": choice[1], "grid": choice[2], "waves_per_simd_cap": choice[3]},
+                   "schedule": {"order": choice[1], "grid": choice[2], "waves_per_simd_cap": choice[3],
+                                "worlds_per_workgroup": choice[4]},
                    "graph_steps": P},
         "forms_env_steps_per_s": rates,
         "forms_ms_per_step": res,

@@ -381,6 +381,15 @@ int rb_multi_set_items(rb_multi* plan, const int32_t* host_items, int32_t n, int
  * not depend on it.  Cites: no passage. */
 int rb_multi_set_occupancy(rb_multi* plan, int32_t waves_per_simd);
 
+/* Worlds per workgroup of the fused launch: 1 (the default), 2 or 4 worlds, one 64-lane wave
+ * each, share a workgroup and its LDS allocation (each world keeps its own LDS section; the
+ * waves never wait for each other).  The schedule's grid still counts worlds in flight.
+ * RB_EINVAL for another count or when the worlds of one workgroup would need more LDS than a
+ * workgroup may use.  Composes with rb_multi_set_occupancy (a cap of w waves per SIMD then
+ * allows 4 w / count workgroups per compute unit).  A schedule knob for the autotuner; results
+ * do not depend on it.  Cites: no passage (the batching form's launch shape). */
+int rb_multi_set_group(rb_multi* plan, int32_t worlds_per_workgroup);
+
 /* One env step of every scheduled world in one launch on the stream.  RB_ESTATE until a work
  * list has been set (rb_multi_set_schedule or rb_multi_set_items); an empty one is a no-op.
  * Cites: paper, section "Manager-Based API", pipeline step "Simulate". */

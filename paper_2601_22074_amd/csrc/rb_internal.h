@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #define RB_WAVE 64
+#define RB_MAX_WPG 4   // worlds (waves) per workgroup of the fused launch, at most
 #define RB_MAX_DOF 64
 #define RB_MAX_PAIR 128          // pairs are lanes, in two rounds past 64 (extended code only)
 #define RB_MAX_CON 64

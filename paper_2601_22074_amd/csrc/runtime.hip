@@ -28,7 +28,7 @@ size_t rb_step_args_size();
 void rb_fill_step_args(void* dst, int n, const float* ctrl, float* qpos, float* qvel, const DevWorlds& W,
                        const DevContactsOut* co, uint32_t* status_out);
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
-                           int ext, int lds_floats, int grid, int waves, hipStream_t stream);
+                           int ext, int lds_floats, int lds_pad, int grid, int wpg, int waves, hipStream_t stream);
 
 namespace {
 
@@ -1080,6 +1080,7 @@ struct rb_multi {
     int items_cap = 0;                         // capacity of d_items
     int lds_pad = 0;                           // extra LDS floats per workgroup (occupancy cap)
     int occ = 0;                               // requested waves per SIMD (0 automatic)
+    int wpg = 1;                               // worlds (waves) per workgroup
     // pinned staging ring for rb_multi_set_items (a slot is reused once its copy is done)
     static constexpr int RING = 4;
     int32_t* stage[RING] = {};
@@ -1329,26 +1330,43 @@ static int multi_waves(const rb_multi* p) {
     return multi_fits_w4(p) && p->nitems > 12 * ncu ? 4 : 3;
 }
 
+// The LDS of one fused workgroup: wpg world sections, plus the padding that enforces an
+// occupancy cap of w < 3 waves per SIMD.  Four SIMDs per CU and wpg waves per workgroup: the CU
+// is capped at 4 w / wpg workgroups by making each one need more than 1 / (4 w / wpg + 1) of
+// the CU's LDS.
+static int multi_layout(rb_multi* p, int occ, int wpg, const char* who) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, who);
+    const long sections = (long)wpg * p->lds_floats;   // floats
+    if (sections * 4 > (long)prop.sharedMemPerBlock)
+        return fail(RB_EINVAL, "the worlds of one workgroup need more LDS than a workgroup may use");
+    int pad = 0;
+    if (occ > 0 && occ < 3) {
+        const long per_cu = (long)prop.maxSharedMemoryPerMultiProcessor;
+        const long need = per_cu / (4 * occ / wpg + 1) / 4 + 1;   // floats
+        if (need * 4 > (long)prop.sharedMemPerBlock) return fail(RB_EINVAL, "occupancy cap needs more LDS than a workgroup may use");
+        pad = (int)std::max(0L, need - sections);
+    }
+    p->occ = occ;
+    p->wpg = wpg;
+    p->lds_pad = pad;
+    multi_free_graph(p);
+    return RB_OK;
+}
+
 int rb_multi_set_occupancy(rb_multi* p, int32_t waves_per_simd) {
     if (!p || waves_per_simd < 0 || waves_per_simd > 4) return fail(RB_EINVAL, "bad arguments to rb_multi_set_occupancy");
     if (waves_per_simd == 4 && !multi_fits_w4(p)) return fail(RB_EINVAL, "the plan's models do not fit 4 waves per SIMD");
-    p->occ = waves_per_simd;
-    p->lds_pad = 0;
-    if (waves_per_simd > 0 && waves_per_simd < 3) {
-        // one wave per workgroup, four SIMDs per CU: cap the CU at 4 w workgroups by making
-        // each one need more than 1 / (4 w + 1) of the CU's LDS
-        int dev = 0;
-        hipDeviceProp_t prop;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-        if (e != hipSuccess) return hip_fail(e, "rb_multi_set_occupancy");
-        const size_t per_cu = prop.maxSharedMemoryPerMultiProcessor;
-        const int need = (int)(per_cu / (4 * waves_per_simd + 1) / 4) + 1;   // floats
-        if ((size_t)need * 4 > prop.sharedMemPerBlock) return fail(RB_EINVAL, "occupancy cap needs more LDS than a workgroup may use");
-        p->lds_pad = std::max(0, need - p->lds_floats);
-    }
-    multi_free_graph(p);
-    return RB_OK;
+    return multi_layout(p, waves_per_simd, p->wpg, "rb_multi_set_occupancy");
+}
+
+int rb_multi_set_group(rb_multi* p, int32_t worlds_per_workgroup) {
+    const int g = worlds_per_workgroup;
+    if (!p || (g != 1 && g != 2 && g != 4)) return fail(RB_EINVAL, "bad arguments to rb_multi_set_group (1, 2 or 4 worlds)");
+    return multi_layout(p, p->occ, g, "rb_multi_set_group");
 }
 
 int rb_multi_step(rb_multi* p, void* stream) {
@@ -1357,8 +1375,8 @@ int rb_multi_step(rb_multi* p, void* stream) {
     if (p->nitems == 0) return RB_OK;
     int rc = multi_refresh(p, (hipStream_t)stream);
     if (rc != RB_OK) return rc;
-    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid, multi_waves(p),
-                                   (hipStream_t)stream);
+    hipError_t e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats,
+                                   p->lds_pad, p->grid, p->wpg, multi_waves(p), (hipStream_t)stream);
     return e == hipSuccess ? RB_OK : hip_fail(e, "rb_multi_step");
 }
 
@@ -1371,7 +1389,8 @@ int rb_multi_graph_capture(rb_multi* p, int32_t nsteps, void* stream) {
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     for (int k = 0; k < nsteps && e == hipSuccess; k++)
-        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats + p->lds_pad, p->grid, multi_waves(p), s);
+        e = rb_launch_multi(p->d_models, p->d_args, p->d_items, p->nitems, p->maxd, p->boxbox, p->lds_floats,
+                            p->lds_pad, p->grid, p->wpg, multi_waves(p), s);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

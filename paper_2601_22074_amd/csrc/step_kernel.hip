@@ -963,7 +963,7 @@ struct StepArgs {
 #endif
 template <int MAXD, bool TIMED, int EXT>
 DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* lds) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (RB_WAVE - 1);   // a fused workgroup may hold several worlds
     float* L = lds;
     float* q = L + m.o_q;
     float* v = L + m.o_v;
@@ -1039,7 +1039,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
     for (int sub = 0; sub < m.K && !frozen; sub++) {
         // the lane index, opaque at the top of each substep: per-lane addresses are recomputed
         // in the substep rather than hoisted out of the loop and spilled
-        const int lane = (int)opaque((uint32_t)threadIdx.x);
+        const int lane = (int)opaque((uint32_t)threadIdx.x & (RB_WAVE - 1));
         // ---- actuation: tau = kp (ctrl - q) - kd v  (position) or gear * ctrl (motor)
         for (int i = lane; i < nv; i += RB_WAVE) {
             float t = 0.f;
@@ -2527,6 +2527,8 @@ struct MultiArgs {
     const StepArgs* args;     // [nbatch]
     const int* items;         // [nitems] batch << 24 | world
     int nitems;
+    int wpg;                  // worlds per workgroup (one wave each, 1 .. RB_MAX_WPG)
+    int lds_stride;           // LDS floats of one world's section of the workgroup's LDS
 };
 
 // Each item runs the instantiation the plain launch would use for its model (chain bound and
@@ -2549,19 +2551,24 @@ DEV void world_step_as_plain(const DevModel& m, const StepArgs& A, int w, float*
     else world_step_level<8, EXT>(m, A, w, lds);
 }
 
+// The waves of a workgroup are independent worlds: wave k of workgroup g takes items g wpg + k,
+// then every (grid size x wpg)-th after it, in its own LDS section.  No workgroup barrier is
+// ever taken, so a wave that runs out of items simply ends.
 template <int MAXD, int EXT>
 DEV void multi_items(const MultiArgs& M, float* lds) {
-    for (int it = blockIdx.x; it < M.nitems; it += gridDim.x) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / RB_WAVE));
+    float* L = lds + wave * M.lds_stride;
+    for (int it = blockIdx.x * M.wpg + wave; it < M.nitems; it += gridDim.x * M.wpg) {
         const int item = __builtin_amdgcn_readfirstlane(M.items[it]);
         const int b = item >> 24, w = item & 0xffffff;
         const DevModel& m = M.models[b];
         const StepArgs& A = M.args[b];
-        if (w < A.n) world_step_as_plain<MAXD, EXT>(m, A, w, lds);
+        if (w < A.n) world_step_as_plain<MAXD, EXT>(m, A, w, L);
     }
 }
 
 template <int MAXD, int EXT>
-__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
+__global__ __launch_bounds__(RB_WAVE * RB_MAX_WPG) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void multi_kernel(
     MultiArgs M) {
     extern __shared__ float lds[];
     multi_items<MAXD, EXT>(M, lds);
@@ -2570,7 +2577,7 @@ __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVE
 // 4 resident waves per SIMD, for plans whose models all fit that (chain bound <= 16 and LDS
 // small enough for 16 worlds per CU)
 template <int MAXD, int EXT>
-__global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void multi_kernel_w4(
+__global__ __launch_bounds__(RB_WAVE * RB_MAX_WPG) __attribute__((amdgpu_waves_per_eu(4, 8))) void multi_kernel_w4(
     MultiArgs M) {
     extern __shared__ float lds[];
     multi_items<MAXD, EXT>(M, lds);
@@ -2599,11 +2606,11 @@ void launch_step_w4_t(const DevModel& m, const rbk::StepArgs& A, int n, size_t s
 }
 template <int MAXD, int EXT>
 void launch_multi_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_t stream) {
-    hipLaunchKernelGGL((rbk::multi_kernel<MAXD, EXT>), g, dim3(RB_WAVE), shmem, stream, M);
+    hipLaunchKernelGGL((rbk::multi_kernel<MAXD, EXT>), g, dim3(RB_WAVE * M.wpg), shmem, stream, M);
 }
 template <int MAXD, int EXT>
 void launch_multi_w4_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_t stream) {
-    hipLaunchKernelGGL((rbk::multi_kernel_w4<MAXD, EXT>), g, dim3(RB_WAVE), shmem, stream, M);
+    hipLaunchKernelGGL((rbk::multi_kernel_w4<MAXD, EXT>), g, dim3(RB_WAVE * M.wpg), shmem, stream, M);
 }
 
 // X is empty (an explicit instantiation definition) or `extern` (a declaration)
@@ -2694,14 +2701,17 @@ static void launch_multi_b(int maxd, const rbk::MultiArgs& M, dim3 g, size_t shm
 }
 
 hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* items, int nitems, int maxd,
-                           int ext, int lds_floats, int grid, int waves, hipStream_t stream) {
+                           int ext, int lds_floats, int lds_pad, int grid, int wpg, int waves, hipStream_t stream) {
+    if (wpg < 1 || wpg > RB_MAX_WPG || grid < 1) return hipErrorInvalidValue;
     rbk::MultiArgs M;
     M.models = models;
     M.args = (const rbk::StepArgs*)args;
     M.items = items;
     M.nitems = nitems;
-    size_t shmem = (size_t)lds_floats * sizeof(float);
-    dim3 g(grid);
+    M.wpg = wpg;
+    M.lds_stride = lds_floats;
+    size_t shmem = ((size_t)wpg * lds_floats + lds_pad) * sizeof(float);
+    dim3 g((grid + wpg - 1) / wpg);   // grid counts worlds in flight, one wave each
     if (ext >= 3) launch_multi_b<3>(maxd, M, g, shmem, waves == 4, stream);
     else if (ext == 2) launch_multi_b<2>(maxd, M, g, shmem, waves == 4, stream);
     else if (ext == 1) launch_multi_b<1>(maxd, M, g, shmem, waves == 4, stream);

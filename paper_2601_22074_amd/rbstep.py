@@ -38,7 +38,7 @@ EXPORTED = ["rb_last_error", "rb_model_create", "rb_model_create_json", "rb_mode
             "rb_batch_destroy", "rb_batch_contact_capacity", "rb_batch_set_params", "rb_batch_set_params_at", "rb_batch_set_waves",
             "rb_world_reset",
             "rb_get_state", "rb_step", "rb_step_taps", "rb_step_noalloc", "rb_multi_create", "rb_multi_destroy", "rb_multi_bind",
-            "rb_multi_set_schedule", "rb_multi_set_items", "rb_multi_set_occupancy", "rb_multi_step", "rb_multi_graph_capture", "rb_multi_graph_launch"]
+            "rb_multi_set_schedule", "rb_multi_set_items", "rb_multi_set_occupancy", "rb_multi_set_group", "rb_multi_step", "rb_multi_graph_capture", "rb_multi_graph_launch"]
 ORDER_BATCH, ORDER_HEAVY_FIRST, ORDER_INTERLEAVE = 0, 1, 2
 NOALLOC_MAX_FLOATS = 4 << 20   # RB_NOALLOC_MAX_FLOATS
 
@@ -116,6 +116,7 @@ def lib():
         L.rb_multi_set_schedule.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_float)]
         L.rb_multi_set_items.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32, C.c_int32, vp]
         L.rb_multi_set_occupancy.argtypes = [vp, C.c_int32]
+        L.rb_multi_set_group.argtypes = [vp, C.c_int32]
         L.rb_multi_step.argtypes = [vp, vp]
         L.rb_multi_graph_capture.argtypes = [vp, C.c_int32, vp]
         L.rb_multi_graph_launch.argtypes = [vp, vp]
@@ -423,6 +424,10 @@ class Multi:
     def set_occupancy(self, waves_per_simd: int) -> None:
         """Cap resident waves per SIMD of the fused launch (0 = no cap)."""
         _check(lib().rb_multi_set_occupancy(self._h, int(waves_per_simd)))
+
+    def set_group(self, worlds_per_workgroup: int) -> None:
+        """Worlds (one wave each) per workgroup of the fused launch: 1, 2 or 4."""
+        _check(lib().rb_multi_set_group(self._h, int(worlds_per_workgroup)))
 
     def step(self, stream=None) -> None:
         _check(lib().rb_multi_step(self._h, _stream(stream)))

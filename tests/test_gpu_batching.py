@@ -74,6 +74,41 @@ def test_fused_with_occupancy_cap_equals_separate(occ):
         np.testing.assert_array_equal(s["v"].cpu().numpy(), v)
 
 
+ODD_MIX = [("chain3", 47), ("quadruped", 95), ("humanoid", 63), ("arm_box", 41)]
+LEVEL_MIX = [("pincer_cube", 21), ("humanoid_weld", 19), ("quadruped_elliptic", 30), ("quadruped_lim", 33)]
+
+
+@pytest.mark.parametrize("mix,wpg,order,grid,occ", [
+    ("odd", 2, 0, 0, 0), ("odd", 4, 1, 0, 0), ("odd", 4, 2, 100, 0), ("odd", 2, 1, 62, 2), ("odd", 4, 0, 0, 2),
+    ("odd", 4, 1, 0, 4), ("levels", 2, 1, 0, 0), ("levels", 4, 0, 0, 0), ("levels", 4, 2, 30, 0)])
+def test_fused_worlds_per_workgroup_equals_separate(mix, wpg, order, grid, occ):
+    """2 or 4 worlds per workgroup (one wave each, a partial last workgroup, persistent grids that
+    are not a multiple of the group, occupancy caps, models of every level of extended code):
+    every world ends bitwise where its plain launch puts it."""
+    import torch
+    import paper_2601_22074_amd as rb
+    mx = ODD_MIX if mix == "odd" else LEVEL_MIX
+    ref = _run_separate(rb, torch, 3, mx)
+    S = _setup(rb, torch, mx)
+    plan = rb.Multi([s["batch"] for s in S])
+    for i, s in enumerate(S):
+        plan.bind(i, s["u"], s["q"], s["v"])
+    plan.set_schedule(order, grid)
+    if occ == 4 and mix == "levels":
+        pytest.skip("the level mix does not fit 4 waves per SIMD")
+    plan.set_occupancy(occ)
+    plan.set_group(wpg)
+    for _ in range(3):
+        plan.step()
+    torch.cuda.synchronize()
+    for (q, v), s in zip(ref, S):
+        np.testing.assert_array_equal(s["q"].cpu().numpy(), q)
+        np.testing.assert_array_equal(s["v"].cpu().numpy(), v)
+    with pytest.raises(rb.RbError):
+        plan.set_group(3)
+    plan.close()
+
+
 def test_fused_equals_separate_long_rollout():
     """300 env steps of contact-rich worlds: any rounding difference between the fused and the
     plain instantiations would have grown into visible divergence by then."""
@@ -127,8 +162,11 @@ def test_autotune_leaves_state_untouched(tmp_path, monkeypatch):
     ref = _run_separate(rb, torch, 2)
     S = _setup(rb, torch)
     plan = rb.Multi([s["batch"] for s in S])
-    choice, timings = autotune.tune(plan, [(s["u"], s["q"], s["v"]) for s in S], reps=1, resident=64)
+    choice, timings = autotune.tune(plan, [(s["u"], s["q"], s["v"]) for s in S], reps=1, resident=64, advance=3)
     assert choice[0] in ("separate", "fused") and len(timings) >= 4
+    # dimensions: dispatch order, grid, occupancy cap and worlds per workgroup
+    assert all(len(k.split("/")) == 5 for k in timings)
+    assert {k.split("/")[4] for k in timings if k.startswith("fused")} == {"1", "2", "4"}
     for _ in range(2):
         if choice[0] == "fused":
             plan.step()
