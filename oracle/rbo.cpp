@@ -163,7 +163,8 @@ struct Data {
                                     // 512 + 6 q + k (row k of equality q)
     std::vector<char> bilat;        // per row: bilateral (equality rows: active on both sides)
     std::vector<char> ell;          // per row: one of an elliptic contact's rows (costed per contact)
-    std::vector<int> ell_row0;      // per elliptic contact: its first row (normal, then t1, t2)
+    std::vector<int> ell_row0;      // per elliptic contact: its first row (normal, then t1, t2, spin)
+    std::vector<int> ell_dim;       // per elliptic contact: its rows (3, or 4 with spin about n)
     std::vector<double> ell_mu;     // per elliptic contact: cone slope mu / sqrt(impratio)
     std::vector<int> row_nnz;       // per row: non-zero Jacobian entries (the dofs it touches)
     int segments = 0;               // quadratic pieces the line searches examined
@@ -970,6 +971,7 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
     d.bilat.assign(d.nrows, 0);
     d.ell.assign(d.nrows, 0);
     d.ell_row0.clear();
+    d.ell_dim.clear();
     d.ell_mu.clear();
     d.J.assign((size_t)d.nrows * nv, 0.0);
     d.row_id.assign(d.nrows, 0);
@@ -1017,20 +1019,25 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
                     Jc[(3 + r) * nv + k] = acc;
                 }
         double rdist = c.dist - std::max(m.gmargin[c.g1], m.gmargin[c.g2]);
-        if (m.cone == 1 && c.dim == 3) {
-            // elliptic cone: the frame rows themselves; the normal row takes the distance
-            // reference, the tangential rows none, and their regulariser is the normal row's
-            // divided by impratio (which makes the cone circular in the rows' D-scaled
-            // coordinates: slope mu / sqrt(impratio))
-            for (int e = 0; e < 3; e++) {
+        if (m.cone == 1 && (c.dim == 3 || c.dim == 4)) {
+            // elliptic cone: the frame rows themselves (normal, t1, t2, and with condim 4 the
+            // spin about n); the normal row takes the distance reference, the others none.
+            // The cone is {f : sum_i (f_i / mu_i)^2 <= f_n^2} with mu_i = mu on the tangents and
+            // mu_spin on the spin; friction row i's regulariser is R_n mu^2 / (mu_i^2 impratio),
+            // which makes the cone circular in the rows' D-scaled coordinates, of slope
+            // mu / sqrt(impratio) (for the tangents R_n / impratio)
+            for (int e = 0; e < c.dim; e++) {
                 int row = d.crow[ci] + e;
                 std::copy(&Jc[e * nv], &Jc[e * nv] + nv, &d.J[(size_t)row * nv]);
                 d.row_id[row] = 4 * ci + e;
                 d.ell[row] = 1;
                 finish_row(row, e == 0 ? rdist : 0.0);
-                if (e > 0) d.D[row] = d.D[d.crow[ci]] * m.impratio;
+                if (e == 1 || e == 2) d.D[row] = d.D[d.crow[ci]] * m.impratio;
+                if (e == 3)
+                    d.D[row] = c.mu > 0 ? d.D[d.crow[ci]] * m.impratio * (c.mu_spin / c.mu) * (c.mu_spin / c.mu) : 0.0;
             }
             d.ell_row0.push_back(d.crow[ci]);
+            d.ell_dim.push_back(c.dim);
             d.ell_mu.push_back(c.mu / std::sqrt(m.impratio));
             continue;
         }
@@ -1096,38 +1103,44 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
 //   top zone, mu |x_t| <= x_n (separating): 0;
 //   bottom zone, |x_t| <= -mu x_n (inside the cone): |x|^2 / 2 (every row active);
 //   middle zone: (mu |x_t| - x_n)^2 / (2 (1 + mu^2)) (the force on the cone's surface).
-// Returns the zone (0 top, 1 middle, 2 bottom); g = ds/djar, h = d2s/djar2 (3x3, row-major).
+// The contact has n = 3 or 4 rows (normal first, x_t the rest).  Returns the zone (0 top, 1
+// middle, 2 bottom); g = ds/djar [n], h = d2s/djar2 (n x n, row-major).
 // ------------------------------------------------------------------------------------
-int ell_eval(const double* jar, const double* D, double mu, double* s, double* g, double* h) {
-    double sq[3], x[3];
-    for (int a = 0; a < 3; a++) {
+int ell_eval(const double* jar, const double* D, double mu, int n, double* s, double* g, double* h) {
+    double sq[4] = {0, 0, 0, 0}, x[4] = {0, 0, 0, 0};
+    for (int a = 0; a < n; a++) {
         sq[a] = std::sqrt(D[a]);
         x[a] = sq[a] * jar[a];
     }
-    const double N = x[0], T = std::sqrt(x[1] * x[1] + x[2] * x[2]);
-    std::fill(g, g + 3, 0.0);
-    std::fill(h, h + 9, 0.0);
+    double T2 = 0;
+    for (int a = 1; a < n; a++) T2 += x[a] * x[a];
+    const double N = x[0], T = std::sqrt(T2);
+    std::fill(g, g + n, 0.0);
+    std::fill(h, h + n * n, 0.0);
     *s = 0;
     if (mu * T <= N) return 0;
     if (T <= -mu * N) {
-        *s = 0.5 * (x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-        for (int a = 0; a < 3; a++) {
+        *s = 0.5 * (N * N + T2);
+        for (int a = 0; a < n; a++) {
             g[a] = D[a] * jar[a];
-            h[4 * a] = D[a];
+            h[(n + 1) * a] = D[a];
         }
         return 2;
     }
     const double c = 1.0 / (1.0 + mu * mu), hh = mu * T - N;
-    const double u[3] = {0.0, x[1] / T, x[2] / T};
-    const double w[3] = {-1.0, mu * u[1], mu * u[2]};   // gradient of hh in x
+    double u[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {-1.0, 0.0, 0.0, 0.0};   // w: gradient of hh in x
+    for (int a = 1; a < n; a++) {
+        u[a] = x[a] / T;
+        w[a] = mu * u[a];
+    }
     *s = 0.5 * c * hh * hh;
-    for (int a = 0; a < 3; a++) {
+    for (int a = 0; a < n; a++) {
         g[a] = sq[a] * c * hh * w[a];
-        for (int b = 0; b < 3; b++) {
+        for (int b = 0; b < n; b++) {
             // c (w w' + hh mu / T (I - u u') on the tangential block)
             double hx = w[a] * w[b];
             if (a > 0 && b > 0) hx += hh * mu / T * ((a == b ? 1.0 : 0.0) - u[a] * u[b]);
-            h[3 * a + b] = sq[a] * sq[b] * c * hx;
+            h[n * a + b] = sq[a] * sq[b] * c * hx;
         }
     }
     return 1;
@@ -1143,8 +1156,8 @@ double constraint_cost(const Data& d, const std::vector<double>& jar) {
         if (!d.ell[e] && (jar[e] < 0 || d.bilat[e])) f += 0.5 * d.D[e] * jar[e] * jar[e];
     for (size_t k = 0; k < d.ell_row0.size(); k++) {
         const int r0 = d.ell_row0[k];
-        double sc, g[3], h[9];
-        ell_eval(&jar[r0], &d.D[r0], d.ell_mu[k], &sc, g, h);
+        double sc, g[4], h[16];
+        ell_eval(&jar[r0], &d.D[r0], d.ell_mu[k], d.ell_dim[k], &sc, g, h);
         f += sc;
     }
     return f;
@@ -1246,13 +1259,13 @@ double line_search_smooth(const Model& m, const Data& d, const std::vector<doubl
             }
         }
         for (size_t k = 0; k < d.ell_row0.size(); k++) {
-            const int r0 = d.ell_row0[k];
-            double j[3], sc, g[3], h[9];
-            for (int a = 0; a < 3; a++) j[a] = jar[r0 + a] + al * s[r0 + a];
-            ell_eval(j, &d.D[r0], d.ell_mu[k], &sc, g, h);
-            for (int a = 0; a < 3; a++) {
+            const int r0 = d.ell_row0[k], n = d.ell_dim[k];
+            double j[4], sc, g[4], h[16];
+            for (int a = 0; a < n; a++) j[a] = jar[r0 + a] + al * s[r0 + a];
+            ell_eval(j, &d.D[r0], d.ell_mu[k], n, &sc, g, h);
+            for (int a = 0; a < n; a++) {
                 d1 += g[a] * s[r0 + a];
-                for (int b = 0; b < 3; b++) *d2 += s[r0 + a] * h[3 * a + b] * s[r0 + b];
+                for (int b = 0; b < n; b++) *d2 += s[r0 + a] * h[n * a + b] * s[r0 + b];
             }
         }
         return d1;
@@ -1314,20 +1327,20 @@ void newton(const Model& m, Data& d) {
                 for (int k = 0; k < nv; k++) H[r * nv + k] += d.D[e] * Je[r] * Je[k];
             }
         }
-        // elliptic contacts: J_c' ds/djar and J_c' h J_c over their three rows
+        // elliptic contacts: J_c' ds/djar and J_c' h J_c over their rows
         std::vector<int> ell_zone(d.ell_row0.size());
         for (size_t c = 0; c < d.ell_row0.size(); c++) {
-            const int r0 = d.ell_row0[c];
-            double sc, ge[3], he[9];
-            ell_zone[c] = ell_eval(&jar[r0], &d.D[r0], d.ell_mu[c], &sc, ge, he);
-            for (int a = 0; a < 3; a++) {
+            const int r0 = d.ell_row0[c], n = d.ell_dim[c];
+            double sc, ge[4], he[16];
+            ell_zone[c] = ell_eval(&jar[r0], &d.D[r0], d.ell_mu[c], n, &sc, ge, he);
+            for (int a = 0; a < n; a++) {
                 const double* Ja = &d.J[(size_t)(r0 + a) * nv];
                 for (int r = 0; r < nv; r++) g[r] += ge[a] * Ja[r];
-                for (int b = 0; b < 3; b++) {
+                for (int b = 0; b < n; b++) {
                     const double* Jb = &d.J[(size_t)(r0 + b) * nv];
-                    if (he[3 * a + b] == 0) continue;
+                    if (he[n * a + b] == 0) continue;
                     for (int r = 0; r < nv; r++)
-                        for (int k = 0; k < nv; k++) H[r * nv + k] += he[3 * a + b] * Ja[r] * Jb[k];
+                        for (int k = 0; k < nv; k++) H[r * nv + k] += he[n * a + b] * Ja[r] * Jb[k];
                 }
             }
         }
@@ -1335,13 +1348,13 @@ void newton(const Model& m, Data& d) {
         for (int k = 0; k < nv; k++) gn += g[k] * g[k];
         if (std::sqrt(gn) / scale < tol) { stopped = true; break; }
         // record the active set this update is built from
-        // (an elliptic contact's three rows are active unless it is in its top zone; inside the
-        // cone they enter the fingerprint as 2048 + id, so that its zone is recorded too)
+        // (an elliptic contact's rows are active unless it is in its top zone; inside the cone
+        // they enter the fingerprint as 2048 + id, so that its zone is recorded too)
         std::vector<int> act;
         uint32_t fp = 0;
         auto ell_zone_of = [&](int e) {
             for (size_t c = 0; c < d.ell_row0.size(); c++)
-                if (e >= d.ell_row0[c] && e < d.ell_row0[c] + 3) return ell_zone[c];
+                if (e >= d.ell_row0[c] && e < d.ell_row0[c] + d.ell_dim[c]) return ell_zone[c];
             return 0;
         };
         for (int e = 0; e < nr; e++) {
@@ -1379,11 +1392,11 @@ void newton(const Model& m, Data& d) {
         d.active_final += t < 0 || d.bilat[e];
     }
     for (size_t c = 0; c < d.ell_row0.size(); c++) {
-        const int r0 = d.ell_row0[c];
-        double sc, ge[3], he[9];
-        const int zone = ell_eval(&jf[r0], &d.D[r0], d.ell_mu[c], &sc, ge, he);
-        for (int a = 0; a < 3; a++) d.efc_force[r0 + a] = -ge[a];
-        d.active_final += zone != 0 ? 3 : 0;
+        const int r0 = d.ell_row0[c], n = d.ell_dim[c];
+        double sc, ge[4], he[16];
+        const int zone = ell_eval(&jf[r0], &d.D[r0], d.ell_mu[c], n, &sc, ge, he);
+        for (int a = 0; a < n; a++) d.efc_force[r0 + a] = -ge[a];
+        d.active_final += zone != 0 ? n : 0;
     }
 }
 
@@ -1818,7 +1831,8 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
     if (!(M.impratio > 0) || !std::isfinite(M.impratio)) return bad("impratio must be positive");
     if (M.cone == 1)
         for (int g = 0; g < ng; g++)
-            if (M.gcondim[g] != 1 && M.gcondim[g] != 3) return bad("elliptic cones take condim 1 or 3");
+            if (M.gcondim[g] != 1 && M.gcondim[g] != 3 && M.gcondim[g] != 4)
+                return bad("elliptic cones take condim 1, 3 or 4");
     // mean diagonal inertia at the reference configuration (free joints at their body pose)
     if (M.nv > 0) {
         Data d(&M);
