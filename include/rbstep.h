@@ -129,11 +129,13 @@ typedef struct rb_model_desc {
      * the simulator it builds on). */
     const double *geom_friction_spin, *geom_friction_roll;
     /* friction cones: RB_CONE_PYRAMIDAL (2 (condim - 1) pyramid rows per contact) or
-     * RB_CONE_ELLIPTIC (condim 1 or 3 only): a contact's frame rows (normal, t1, t2) costed
-     * together by the soft elliptic cone, its force the projection of -D jar onto the friction
-     * cone {|f_t| <= mu f_n} in the metric of D^-1; the tangential rows have no distance
-     * reference and the normal row's D times impratio (> 0; 1 when 0 is given).  Cites: paper,
-     * section "Architecture", paragraph on the GPU physics backend (the constraint model of the
+     * RB_CONE_ELLIPTIC (condim 1, 3 or 4; 6 is refused): a contact's frame rows (normal, t1, t2,
+     * and with condim 4 the spin about the normal) costed together by the soft elliptic cone,
+     * its force the projection of -D jar onto the friction cone {(f_1/mu)^2 + (f_2/mu)^2 +
+     * (f_spin/mu_spin)^2 <= f_n^2} in the metric of D^-1; the friction rows have no distance
+     * reference, the tangential rows take the normal row's D times impratio (> 0; 1 when 0 is
+     * given) and the spin row that times (mu_spin / mu)^2.  Cites: paper, section
+     * "Architecture", paragraph on the GPU physics backend (the constraint model of the
      * simulator it builds on). */
     int32_t cone;
     double impratio;

@@ -435,9 +435,9 @@ struct Con {
 };
 
 // velocity of the contact's pyramid rows for body spatial motions `bm` (already includes sign);
-// of its frame rows (normal, t1, t2, then 0) for an elliptic-cone contact; b1 > 0: the
-// contact's second moving body, whose point motion is subtracted
-DEV void rows_of(const Con& c, const float* bm, float* out, bool ell = false, int b1 = 0) {
+// of its frame rows (normal, t1, t2, then the spin about n when ell is 2, else 0) for an
+// elliptic-cone contact; b1 > 0: the contact's second moving body, whose motion is subtracted
+DEV void rows_of(const Con& c, const float* bm, float* out, int ell = 0, int b1 = 0) {
     const float* sv = bm + 6 * c.body;
     float wr[3], t2[3];
     cross(sv, c.r, wr);
@@ -451,7 +451,12 @@ DEV void rows_of(const Con& c, const float* bm, float* out, bool ell = false, in
     }
     float vn = c.sigma * dot(c.n, vp), v1 = c.sigma * dot(c.t1, vp), v2 = c.sigma * dot(t2, vp);
     if (ell) {
-        out[0] = vn; out[1] = v1; out[2] = v2; out[3] = 0.f;
+        float ws = 0.f;
+        if (ell == 2) {
+            ws = dot(c.n, sv);
+            if (b1 > 0) ws -= dot(c.n, bm + 6 * b1);
+        }
+        out[0] = vn; out[1] = v1; out[2] = v2; out[3] = c.sigma * ws;
         return;
     }
     out[0] = vn + c.mu * v1;
@@ -460,38 +465,43 @@ DEV void rows_of(const Con& c, const float* bm, float* out, bool ell = false, in
     out[3] = vn - c.mu * v2;
 }
 
-// Soft elliptic cone of one contact at the frame-row residuals jar (normal, t1, t2), with
-// regulariser inverses D0 (normal) and Dt (tangential) and cone slope mu: with x = sqrt(D) jar,
-// cost 0 when mu |x_t| <= x_n (separating), |x|^2 / 2 when |x_t| <= -mu x_n (inside the cone),
-// else (mu |x_t| - x_n)^2 / (2 (1 + mu^2)) (the force on the cone's surface).  Returns the zone
-// (0, 1 surface, 2 inside) and the cost; g = d cost / d jar, h its Hessian (h00 h01 h02 h11 h12
-// h22).
-DEV int ell_eval(const float* jar, float D0, float Dt, float mu, float* cost, float* g, float* h) {
-    const float s0 = sqrtf(D0), st = sqrtf(Dt);
-    const float N = s0 * jar[0], x1 = st * jar[1], x2 = st * jar[2];
-    const float T = sqrtf(x1 * x1 + x2 * x2);
-    for (int k = 0; k < 3; k++) g[k] = 0.f;
-    for (int k = 0; k < 6; k++) h[k] = 0.f;
+// Soft elliptic cone of one contact at the frame-row residuals jar (normal, t1, t2, spin about
+// n), with regulariser inverses D0 (normal), Dt (tangential) and Ds (spin; 0 without torsional
+// friction, which leaves the three-row cone) and cone slope mu: with x = sqrt(D) jar, cost 0
+// when mu |x_t| <= x_n (separating), |x|^2 / 2 when |x_t| <= -mu x_n (inside the cone), else
+// (mu |x_t| - x_n)^2 / (2 (1 + mu^2)) (the force on the cone's surface).  Returns the zone (0,
+// 1 surface, 2 inside) and the cost; g = d cost / d jar [4], h its Hessian (h00 h01 h02 h11 h12
+// h22, then h03 h13 h23 h33).
+DEV int ell_eval(const float* jar, float D0, float Dt, float Ds, float mu, float* cost, float* g, float* h) {
+    const float s0 = sqrtf(D0), st = sqrtf(Dt), ss = sqrtf(Ds);
+    const float N = s0 * jar[0], x1 = st * jar[1], x2 = st * jar[2], x3 = ss * jar[3];
+    const float T = sqrtf(x1 * x1 + x2 * x2 + x3 * x3);
+    for (int k = 0; k < 4; k++) g[k] = 0.f;
+    for (int k = 0; k < 10; k++) h[k] = 0.f;
     *cost = 0.f;
     if (mu * T <= N) return 0;
     if (T <= -mu * N) {
-        *cost = 0.5f * (N * N + x1 * x1 + x2 * x2);
-        g[0] = D0 * jar[0]; g[1] = Dt * jar[1]; g[2] = Dt * jar[2];
-        h[0] = D0; h[3] = Dt; h[5] = Dt;
+        *cost = 0.5f * (N * N + x1 * x1 + x2 * x2 + x3 * x3);
+        g[0] = D0 * jar[0]; g[1] = Dt * jar[1]; g[2] = Dt * jar[2]; g[3] = Ds * jar[3];
+        h[0] = D0; h[3] = Dt; h[5] = Dt; h[9] = Ds;
         return 2;
     }
     const float c = 1.f / (1.f + mu * mu), hh = mu * T - N, iT = 1.f / T;
-    const float u1 = x1 * iT, u2 = x2 * iT;
-    const float w0 = -1.f, w1 = mu * u1, w2 = mu * u2;      // gradient of hh in x
-    const float k = hh * mu * iT;                            // curvature of |x_t| across the cone
+    const float u1 = x1 * iT, u2 = x2 * iT, u3 = x3 * iT;
+    const float w0 = -1.f, w1 = mu * u1, w2 = mu * u2, w3 = mu * u3;   // gradient of hh in x
+    const float k = hh * mu * iT;                                      // curvature of |x_t| across the cone
     *cost = 0.5f * c * hh * hh;
-    g[0] = s0 * c * hh * w0; g[1] = st * c * hh * w1; g[2] = st * c * hh * w2;
+    g[0] = s0 * c * hh * w0; g[1] = st * c * hh * w1; g[2] = st * c * hh * w2; g[3] = ss * c * hh * w3;
     h[0] = D0 * c * w0 * w0;
     h[1] = s0 * st * c * w0 * w1;
     h[2] = s0 * st * c * w0 * w2;
     h[3] = Dt * c * (w1 * w1 + k * (1.f - u1 * u1));
     h[4] = Dt * c * (w1 * w2 - k * u1 * u2);
     h[5] = Dt * c * (w2 * w2 + k * (1.f - u2 * u2));
+    h[6] = s0 * ss * c * w0 * w3;
+    h[7] = st * ss * c * (w1 * w3 - k * u1 * u3);
+    h[8] = st * ss * c * (w2 * w3 - k * u2 * u3);
+    h[9] = Ds * c * (w3 * w3 + k * (1.f - u3 * u3));
     return 1;
 }
 
@@ -1350,6 +1360,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         float margin_c = 0.f;
         xr = 0;
         float mu_spin = 0.f, mu_roll = 0.f;
+        bool spin4 = false;   // an elliptic contact with the spin row (condim 4)
         if (has) {
             int j = lane - before, feat;
             if (EXT && m.pair_type[src] == RB_PAIR_BOXBOX) {
@@ -1378,10 +1389,11 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 C.ids |= 1 << 24;
             }
             margin_c = m.pair_margin[src];
-            if (EXT >= 2 && m.nxmax > 0) {
+            if (EXT >= 2 && (m.nxmax > 0 || m.cone)) {
                 xr = m.pair_xrows[src];
                 mu_spin = m.pair_mu_spin[src];
                 mu_roll = m.pair_mu_roll[src];
+                spin4 = m.pair_spin4[src] != 0;
             }
         } else {
             C.body = 0;
@@ -1390,6 +1402,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         // an elliptic-cone contact (extended code): frame rows costed by the soft elliptic cone;
         // frictionless contacts keep their one normal row
         const bool cell = EXT >= 2 && m.cone && has && !(C.ids >> 24);
+        const bool cspin = cell && spin4;
+        const int cellm = cell ? (cspin ? 2 : 1) : 0;   // rows_of's frame rows (with the spin: 2)
         RB_STAGE(3);
         // generic-row slots of the contacts' extra rows: after the equality rows, in contact order
         float* GR = L + m.o_gr;
@@ -1547,7 +1561,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 }
             }
             float vrow[4];
-            rows_of(C, cvel, vrow, cell, EXT >= 3 ? C.body1 : 0);
+            rows_of(C, cvel, vrow, cellm, EXT >= 3 ? C.body1 : 0);
             float rd = C.dist - margin_c;
             float imp = impedance(m, rd);
             float mu = C.mu, mu2 = mu * mu;
@@ -1567,10 +1581,13 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 C.aref[0] = -m.bref * vrow[0] - m.kref * imp * rd;
                 C.aref[1] = -m.bref * vrow[1];
                 C.aref[2] = -m.bref * vrow[2];
-                C.aref[3] = 0.f;
+                C.aref[3] = -m.bref * vrow[3];
                 C.D[0] = D0;
                 C.D[1] = C.D[2] = m.impratio * D0;
-                C.D[3] = 0.f;
+                // the spin row (condim 4): regulariser the normal's times mu^2 / (mu_spin^2
+                // impratio), which keeps the cone circular in the D-scaled rows
+                const float rs = (cspin && C.mu > 0.f) ? mu_spin / C.mu : 0.f;
+                C.D[3] = m.impratio * D0 * rs * rs;
                 ah[0] = A00; ah[1] = A11; ah[2] = A22; ah[3] = 0.f;
             }
             if (TIMED && A.want_taps && sub == 0 && A.taps.efc) {
@@ -1776,8 +1793,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             // the lane's contact cost at residuals j: pyramid rows, or the elliptic cone
             auto con_cost = [&](const float* j) {
                 if (cell) {
-                    float cst, ge[3], he[6];
-                    ell_eval(j, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he);
+                    float cst, ge[4], he[10];
+                    ell_eval(j, C.D[0], C.D[1], C.D[3], C.mu * m.rsqrt_impratio, &cst, ge, he);
                     return cst;
                 }
                 float cst = 0.f;
@@ -1789,7 +1806,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 return cst;
             };
             if (has) {
-                rows_of(C, bvec, j0, cell, EXT >= 3 ? C.body1 : 0);
+                rows_of(C, bvec, j0, cellm, EXT >= 3 ? C.body1 : 0);
 #pragma unroll
                 for (int e = 0; e < 4; e++) j0[e] -= C.aref[e];
                 f0 += con_cost(j0);
@@ -1825,7 +1842,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             float jw[4] = {0, 0, 0, 0};
             float fw = 0.f;
             if (has) {
-                rows_of(C, bvec, jw, cell, EXT >= 3 ? C.body1 : 0);
+                rows_of(C, bvec, jw, cellm, EXT >= 3 ? C.body1 : 0);
 #pragma unroll
                 for (int e = 0; e < 4; e++) jw[e] += j0[e];
                 fw += con_cost(jw);
@@ -1867,8 +1884,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 uint32_t bits = 0;
                 bool mid = false;   // an elliptic contact on its cone's surface: cost not quadratic
                 if (cell) {
-                    float cst, ge[3], he[6];
-                    const int zone = ell_eval(C.jar, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he);
+                    float cst, ge[4], he[10];
+                    const int zone = ell_eval(C.jar, C.D[0], C.D[1], C.D[3], C.mu * m.rsqrt_impratio, &cst, ge, he);
                     bits = (uint32_t)zone;
                     mid = zone == 1;
                 } else if (has) {
@@ -1903,25 +1920,29 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     float mu = rl(C.mu, c), sg = rl(C.sigma, c);
                     // an elliptic contact: its cost's gradient and Hessian in its frame rows
                     const bool ellc = EXT >= 2 && m.cone && !(__builtin_amdgcn_readlane(C.ids, c) >> 24);
-                    float ge[3], he[6];
+                    float ge[4], he[10];
                     if (ellc) {
                         float cst;
-                        ell_eval(jar, D[0], D[1], mu * m.rsqrt_impratio, &cst, ge, he);
+                        ell_eval(jar, D[0], D[1], D[3], mu * m.rsqrt_impratio, &cst, ge, he);
                     }
                     if (ellc && dof_lane && ((mask >> lane) & 1ull)) {
                         float wr[3];
                         cross(S, r, wr);
                         const float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
                         const float jn = sg * dot(n, vp), j1 = sg * dot(t1, vp), j2 = sg * dot(t2, vp);
-                        gc += ge[0] * jn + ge[1] * j1 + ge[2] * j2;
+                        const float js = sg * dot(n, S);   // the spin row (D = 0 without it)
+                        gc += ge[0] * jn + ge[1] * j1 + ge[2] * j2 + ge[3] * js;
                         // Hessian term: the rows' directions weighted by h je, as a spatial force
-                        const float u0 = he[0] * jn + he[1] * j1 + he[2] * j2;
-                        const float u1 = he[1] * jn + he[3] * j1 + he[4] * j2;
-                        const float u2 = he[2] * jn + he[4] * j1 + he[5] * j2;
+                        // (the spin row's direction is the pure torque n)
+                        const float u0 = he[0] * jn + he[1] * j1 + he[2] * j2 + he[6] * js;
+                        const float u1 = he[1] * jn + he[3] * j1 + he[4] * j2 + he[7] * js;
+                        const float u2 = he[2] * jn + he[4] * j1 + he[5] * j2 + he[8] * js;
+                        const float u3 = he[6] * jn + he[7] * j1 + he[8] * j2 + he[9] * js;
                         float a[3], ra[3];
                         for (int k = 0; k < 3; k++) a[k] = sg * (u0 * n[k] + u1 * t1[k] + u2 * t2[k]);
                         cross(r, a, ra);
-                        F[0] += ra[0]; F[1] += ra[1]; F[2] += ra[2];
+                        const float su3 = sg * u3;
+                        F[0] += ra[0] + su3 * n[0]; F[1] += ra[1] + su3 * n[1]; F[2] += ra[2] + su3 * n[2];
                         F[3] += a[0]; F[4] += a[1]; F[5] += a[2];
                     }
                     // a contact between two moving bodies (level-3 code): a dof on b2's chain
@@ -2005,7 +2026,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         // an elliptic contact's three rows count unless it separates (zone 0),
                         // as 2048 + id inside the cone (zone 2)
                         if (bits != 0)
-                            for (int e = 0; e < 3; e++)
+                            for (int e = 0; e < (cspin ? 4 : 3); e++)
                                 fpl += (uint32_t)(4 * lane + e + (bits == 2 ? 2048 : 0) + 1) * 2654435761u;
                     } else if (has) {
 #pragma unroll
@@ -2129,7 +2150,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 // directional quantities for the line search
                 spatial_mul(m, BL, DL, cdof, cinert, p, bvec, cvel, Mp, lane);
                 float sr[4] = {0, 0, 0, 0};
-                if (has) rows_of(C, bvec, sr, cell, EXT >= 3 ? C.body1 : 0);
+                if (has) rows_of(C, bvec, sr, cellm, EXT >= 3 ? C.body1 : 0);
                 float pa = 0.f, pb = 0.f;
                 if (dof_lane) {
                     pa = p[lane] * Mp[lane];
@@ -2170,12 +2191,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         auto dphi = [&](float al, float* d2) {
                             float d1l = 0.f, d2l = 0.f;
                             if (cell) {
-                                const float jj[3] = {C.jar[0] + al * sr[0], C.jar[1] + al * sr[1], C.jar[2] + al * sr[2]};
-                                float cst, ge[3], he[6];
-                                ell_eval(jj, C.D[0], C.D[1], mue, &cst, ge, he);
-                                d1l += ge[0] * sr[0] + ge[1] * sr[1] + ge[2] * sr[2];
+                                const float jj[4] = {C.jar[0] + al * sr[0], C.jar[1] + al * sr[1], C.jar[2] + al * sr[2],
+                                                     C.jar[3] + al * sr[3]};
+                                float cst, ge[4], he[10];
+                                ell_eval(jj, C.D[0], C.D[1], C.D[3], mue, &cst, ge, he);
+                                d1l += ge[0] * sr[0] + ge[1] * sr[1] + ge[2] * sr[2] + ge[3] * sr[3];
                                 d2l += he[0] * sr[0] * sr[0] + he[3] * sr[1] * sr[1] + he[5] * sr[2] * sr[2] +
-                                       2.f * (he[1] * sr[0] * sr[1] + he[2] * sr[0] * sr[2] + he[4] * sr[1] * sr[2]);
+                                       he[9] * sr[3] * sr[3] +
+                                       2.f * (he[1] * sr[0] * sr[1] + he[2] * sr[0] * sr[2] + he[4] * sr[1] * sr[2] +
+                                              he[6] * sr[0] * sr[3] + he[7] * sr[1] * sr[3] + he[8] * sr[2] * sr[3]);
                             } else if (has) {
 #pragma unroll
                                 for (int e = 0; e < 4; e++) {
@@ -2304,10 +2328,11 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 st_seg += seg_sub;
                 // rows, and rows active at the solution (a frictionless contact has one row)
                 const bool fl = has && EXT && (C.ids >> 24);
-                int act = 0, nrow = has ? (fl ? 1 : (cell ? 3 : 4)) : 0;
+                int act = 0, nrow = has ? (fl ? 1 : (cell ? (cspin ? 4 : 3) : 4)) : 0;
                 if (cell) {
-                    float cst, ge[3], he[6];
-                    act += ell_eval(C.jar, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he) != 0 ? 3 : 0;
+                    float cst, ge[4], he[10];
+                    act += ell_eval(C.jar, C.D[0], C.D[1], C.D[3], C.mu * m.rsqrt_impratio, &cst, ge, he) != 0
+                               ? (cspin ? 4 : 3) : 0;
                 } else if (has) {
                     for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f && (e == 0 || !fl);
                 }
@@ -2471,8 +2496,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         }
         if (A.co.force && EXT >= 2 && m.cone && !(C.ids >> 24)) {
             // elliptic cone: the frame rows' forces, minus the cost's gradient
-            float cst, ge[3], he[6];
-            ell_eval(C.jar, C.D[0], C.D[1], C.mu * m.rsqrt_impratio, &cst, ge, he);
+            float cst, ge[4], he[10];
+            ell_eval(C.jar, C.D[0], C.D[1], C.D[3], C.mu * m.rsqrt_impratio, &cst, ge, he);
             A.co.force[3 * slot] = -ge[0];
             A.co.force[3 * slot + 1] = -ge[1];
             A.co.force[3 * slot + 2] = -ge[2];

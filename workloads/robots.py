@@ -597,6 +597,26 @@ def humanoid_elliptic() -> dict:
     return with_elliptic(humanoid(), 1.0, "humanoid_elliptic")
 
 
+def quadruped_elliptic4() -> dict:
+    """quadruped with elliptic friction cones (impratio 1) whose sphere feet have torsional
+    friction (condim 4, mu_spin 0.02): four rows per foot contact in one cone."""
+    m = with_elliptic(quadruped(), 1.0, "quadruped_elliptic4")
+    for g in m["geoms"]:
+        if g["type"] == "sphere":
+            g.update(condim=4, friction_spin=0.02)
+    return m
+
+
+def humanoid_elliptic4() -> dict:
+    """humanoid with elliptic friction cones (impratio 1) whose four foot boxes have torsional
+    friction (condim 4, mu_spin 0.02), with up to 8 Newton updates per substep: a spin row in
+    each foot corner's cone puts more contacts on their cones' surfaces, where the cost is not
+    quadratic, and 4 updates leave about a tenth of the steps short of convergence."""
+    m = with_elliptic(humanoid_condim4(), 1.0, "humanoid_elliptic4")
+    m["opt"]["iterations"] = 8
+    return m
+
+
 CUBE_HALF = 0.05   # cube_stack: cube half size (m)
 
 
@@ -680,6 +700,7 @@ BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, 
                 "quadruped_hfield": quadruped_hfield, "chain3_loop": chain3_loop, "humanoid_weld": humanoid_weld,
                 "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4,
                 "quadruped_elliptic": quadruped_elliptic, "humanoid_elliptic": humanoid_elliptic,
+                "quadruped_elliptic4": quadruped_elliptic4, "humanoid_elliptic4": humanoid_elliptic4,
                 "cube_stack": cube_stack, "pincer": pincer, "humanoid_self": humanoid_self,
                 "pincer_cube": pincer_cube}
 
