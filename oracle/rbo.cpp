@@ -163,8 +163,8 @@ struct Data {
                                     // 512 + 6 q + k (row k of equality q)
     std::vector<char> bilat;        // per row: bilateral (equality rows: active on both sides)
     std::vector<char> ell;          // per row: one of an elliptic contact's rows (costed per contact)
-    std::vector<int> ell_row0;      // per elliptic contact: its first row (normal, then t1, t2, spin)
-    std::vector<int> ell_dim;       // per elliptic contact: its rows (3, or 4 with spin about n)
+    std::vector<int> ell_row0;      // per elliptic contact: its first row (normal, t1, t2, spin, roll)
+    std::vector<int> ell_dim;       // per elliptic contact: its rows (its condim: 3, 4 or 6)
     std::vector<double> ell_mu;     // per elliptic contact: cone slope mu / sqrt(impratio)
     std::vector<int> row_nnz;       // per row: non-zero Jacobian entries (the dofs it touches)
     int segments = 0;               // quadratic pieces the line searches examined
@@ -1019,22 +1019,25 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
                     Jc[(3 + r) * nv + k] = acc;
                 }
         double rdist = c.dist - std::max(m.gmargin[c.g1], m.gmargin[c.g2]);
-        if (m.cone == 1 && (c.dim == 3 || c.dim == 4)) {
-            // elliptic cone: the frame rows themselves (normal, t1, t2, and with condim 4 the
-            // spin about n); the normal row takes the distance reference, the others none.
-            // The cone is {f : sum_i (f_i / mu_i)^2 <= f_n^2} with mu_i = mu on the tangents and
-            // mu_spin on the spin; friction row i's regulariser is R_n mu^2 / (mu_i^2 impratio),
-            // which makes the cone circular in the rows' D-scaled coordinates, of slope
-            // mu / sqrt(impratio) (for the tangents R_n / impratio)
+        if (m.cone == 1 && c.dim >= 3) {
+            // elliptic cone: the frame rows themselves (normal, t1, t2, then with condim 4 the
+            // spin about n, with condim 6 also the rolling about t1 and t2); the normal row takes
+            // the distance reference, the others none.  The cone is
+            // {f : sum_i (f_i / mu_i)^2 <= f_n^2} with mu_i = mu on the tangents, mu_spin on the
+            // spin and mu_roll on the rolling rows; friction row i's regulariser is
+            // R_n mu^2 / (mu_i^2 impratio), which makes the cone circular in the rows' D-scaled
+            // coordinates, of slope mu / sqrt(impratio) (for the tangents R_n / impratio)
             for (int e = 0; e < c.dim; e++) {
                 int row = d.crow[ci] + e;
                 std::copy(&Jc[e * nv], &Jc[e * nv] + nv, &d.J[(size_t)row * nv]);
-                d.row_id[row] = 4 * ci + e;
+                d.row_id[row] = e < 4 ? 4 * ci + e : 1024 + 6 * ci + (e - 4);
                 d.ell[row] = 1;
                 finish_row(row, e == 0 ? rdist : 0.0);
                 if (e == 1 || e == 2) d.D[row] = d.D[d.crow[ci]] * m.impratio;
-                if (e == 3)
-                    d.D[row] = c.mu > 0 ? d.D[d.crow[ci]] * m.impratio * (c.mu_spin / c.mu) * (c.mu_spin / c.mu) : 0.0;
+                if (e >= 3) {
+                    const double r = c.mu > 0 ? (e == 3 ? c.mu_spin : c.mu_roll) / c.mu : 0.0;
+                    d.D[row] = d.D[d.crow[ci]] * m.impratio * r * r;
+                }
             }
             d.ell_row0.push_back(d.crow[ci]);
             d.ell_dim.push_back(c.dim);
@@ -1103,11 +1106,11 @@ void make_rows(const Model& m, Data& d, const std::vector<double>& LM) {
 //   top zone, mu |x_t| <= x_n (separating): 0;
 //   bottom zone, |x_t| <= -mu x_n (inside the cone): |x|^2 / 2 (every row active);
 //   middle zone: (mu |x_t| - x_n)^2 / (2 (1 + mu^2)) (the force on the cone's surface).
-// The contact has n = 3 or 4 rows (normal first, x_t the rest).  Returns the zone (0 top, 1
+// The contact has n = 3, 4 or 6 rows (normal first, x_t the rest).  Returns the zone (0 top, 1
 // middle, 2 bottom); g = ds/djar [n], h = d2s/djar2 (n x n, row-major).
 // ------------------------------------------------------------------------------------
 int ell_eval(const double* jar, const double* D, double mu, int n, double* s, double* g, double* h) {
-    double sq[4] = {0, 0, 0, 0}, x[4] = {0, 0, 0, 0};
+    double sq[6] = {0, 0, 0, 0, 0, 0}, x[6] = {0, 0, 0, 0, 0, 0};
     for (int a = 0; a < n; a++) {
         sq[a] = std::sqrt(D[a]);
         x[a] = sq[a] * jar[a];
@@ -1128,7 +1131,7 @@ int ell_eval(const double* jar, const double* D, double mu, int n, double* s, do
         return 2;
     }
     const double c = 1.0 / (1.0 + mu * mu), hh = mu * T - N;
-    double u[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {-1.0, 0.0, 0.0, 0.0};   // w: gradient of hh in x
+    double u[6] = {0, 0, 0, 0, 0, 0}, w[6] = {-1.0, 0, 0, 0, 0, 0};   // w: gradient of hh in x
     for (int a = 1; a < n; a++) {
         u[a] = x[a] / T;
         w[a] = mu * u[a];
@@ -1156,7 +1159,7 @@ double constraint_cost(const Data& d, const std::vector<double>& jar) {
         if (!d.ell[e] && (jar[e] < 0 || d.bilat[e])) f += 0.5 * d.D[e] * jar[e] * jar[e];
     for (size_t k = 0; k < d.ell_row0.size(); k++) {
         const int r0 = d.ell_row0[k];
-        double sc, g[4], h[16];
+        double sc, g[6], h[36];
         ell_eval(&jar[r0], &d.D[r0], d.ell_mu[k], d.ell_dim[k], &sc, g, h);
         f += sc;
     }
@@ -1260,7 +1263,7 @@ double line_search_smooth(const Model& m, const Data& d, const std::vector<doubl
         }
         for (size_t k = 0; k < d.ell_row0.size(); k++) {
             const int r0 = d.ell_row0[k], n = d.ell_dim[k];
-            double j[4], sc, g[4], h[16];
+            double j[6], sc, g[6], h[36];
             for (int a = 0; a < n; a++) j[a] = jar[r0 + a] + al * s[r0 + a];
             ell_eval(j, &d.D[r0], d.ell_mu[k], n, &sc, g, h);
             for (int a = 0; a < n; a++) {
@@ -1331,7 +1334,7 @@ void newton(const Model& m, Data& d) {
         std::vector<int> ell_zone(d.ell_row0.size());
         for (size_t c = 0; c < d.ell_row0.size(); c++) {
             const int r0 = d.ell_row0[c], n = d.ell_dim[c];
-            double sc, ge[4], he[16];
+            double sc, ge[6], he[36];
             ell_zone[c] = ell_eval(&jar[r0], &d.D[r0], d.ell_mu[c], n, &sc, ge, he);
             for (int a = 0; a < n; a++) {
                 const double* Ja = &d.J[(size_t)(r0 + a) * nv];
@@ -1393,7 +1396,7 @@ void newton(const Model& m, Data& d) {
     }
     for (size_t c = 0; c < d.ell_row0.size(); c++) {
         const int r0 = d.ell_row0[c], n = d.ell_dim[c];
-        double sc, ge[4], he[16];
+        double sc, ge[6], he[36];
         const int zone = ell_eval(&jf[r0], &d.D[r0], d.ell_mu[c], n, &sc, ge, he);
         for (int a = 0; a < n; a++) d.efc_force[r0 + a] = -ge[a];
         d.active_final += zone != 0 ? n : 0;
@@ -1831,8 +1834,8 @@ int rbo_model_create(const rbo_desc* dsc, void** out) {
     if (!(M.impratio > 0) || !std::isfinite(M.impratio)) return bad("impratio must be positive");
     if (M.cone == 1)
         for (int g = 0; g < ng; g++)
-            if (M.gcondim[g] != 1 && M.gcondim[g] != 3 && M.gcondim[g] != 4)
-                return bad("elliptic cones take condim 1, 3 or 4");
+            if (M.gcondim[g] != 1 && M.gcondim[g] != 3 && M.gcondim[g] != 4 && M.gcondim[g] != 6)
+                return bad("elliptic cones take condim 1, 3, 4 or 6");
     // mean diagonal inertia at the reference configuration (free joints at their body pose)
     if (M.nv > 0) {
         Data d(&M);

@@ -158,11 +158,12 @@ def test_frictionless_contacts_ignore_the_cone(oracle_mod):
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
 
 
-def test_elliptic_takes_condim_1_3_and_4(oracle_mod):
+def test_elliptic_takes_condim_1_3_4_and_6(oracle_mod):
     m = _elliptic(robots.free_body("sphere", size=(0.1,)))
-    m["geoms"][1]["condim"] = 4
-    oracle_mod.Oracle(m)
-    m["geoms"][1]["condim"] = 6
+    for cd in (1, 3, 4, 6):
+        m["geoms"][1]["condim"] = cd
+        oracle_mod.Oracle(m)
+    m["geoms"][1]["condim"] = 5
     with pytest.raises(Exception):
         oracle_mod.Oracle(m)
     m = robots.free_body("sphere", size=(0.1,))

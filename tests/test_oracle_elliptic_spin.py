@@ -1,9 +1,10 @@
-"""Pins of the oracle's elliptic cones with torsional friction (condim 4): the contact's four
-row forces (normal, two tangents, spin about the normal) are the projection of -D jar onto the
-cone {sum_i (f_i / mu_i)^2 <= f_n^2} in the metric of R = D^-1 (checked by the conditions that
-define a projection onto a closed convex cone), friction row i's regulariser is the normal's
-times mu^2 / (mu_i^2 impratio), a contact without torsional friction steps exactly as its
-condim-3 cone, a slowly spinning ball loses its spin at the rate the cone's quadratic zone fixes
+"""Pins of the oracle's elliptic cones with torsional and rolling friction (condim 4 and 6):
+the contact's row forces (normal, two tangents, spin about the normal, rolling about the
+tangents) are the projection of -D jar onto the cone {sum_i (f_i / mu_i)^2 <= f_n^2} in the
+metric of R = D^-1 (checked by the conditions that define a projection onto a closed convex
+cone), friction row i's regulariser is the normal's times mu^2 / (mu_i^2 impratio), a contact
+without torsional (rolling) friction steps exactly as its condim-3 (condim-4) cone, a rolling
+ball keeps its speed with condim 4 and loses it with condim 6, a slowly spinning ball loses its spin at the rate the cone's quadratic zone fixes
 in closed form, and a fast-spinning one has its spin force on the cone's surface."""
 import numpy as np
 import pytest
@@ -31,37 +32,40 @@ def _states(n, seed, height):
     return out
 
 
-@pytest.mark.parametrize("impratio", [1.0, 4.0])
-def test_forces_are_the_anisotropic_cone_projection(oracle_mod, impratio):
+@pytest.mark.parametrize("condim,impratio", [(4, 1.0), (4, 4.0), (6, 1.0), (6, 4.0)])
+def test_forces_are_the_anisotropic_cone_projection(oracle_mod, condim, impratio):
     """Tilted boxes touching the plane at random velocities, Newton run to convergence: per
-    contact, D of the tangents is impratio D_n and of the spin impratio D_n (mu_spin / mu)^2;
-    the four forces f lie in K = {f_n >= |(f_1 / mu, f_2 / mu, f_s / mu_spin)|}, the residual
-    w = R (y - f) (y = -D jar) lies in K's polar cone {w_n <= -|(mu w_1, mu w_2, mu_spin w_s)|},
-    w . f = 0, all three zones occur, and M (a - a0) = J' f."""
-    mu, mus = 0.6, 0.05
-    m = _elliptic4(robots.free_body("box", size=(0.1, 0.07, 0.05), mass=1.3, friction=mu), mus, impratio)
+    contact, D of the tangents is impratio D_n, of the spin impratio D_n (mu_spin / mu)^2 and of
+    the rolling rows (condim 6) impratio D_n (mu_roll / mu)^2; the forces f lie in
+    K = {f_n >= |(f_1 / mu, f_2 / mu, f_s / mu_spin, f_r1 / mu_roll, f_r2 / mu_roll)|}, the
+    residual w = R (y - f) (y = -D jar) lies in K's polar cone
+    {w_n <= -|(mu w_1, mu w_2, mu_spin w_s, mu_roll w_r1, mu_roll w_r2)|}, w . f = 0, all three
+    zones occur, and M (a - a0) = J' f."""
+    mu, mus, mur = 0.6, 0.05, 0.01
+    m = _elliptic4(robots.free_body("box", size=(0.1, 0.07, 0.05), mass=1.3, friction=mu), mus, impratio, condim)
+    for g in m["geoms"]:
+        g["friction_roll"] = mur
     o = oracle_mod.Oracle(m)
     o.set_mode("converged")
-    scale = np.array([1.0, mu, mu, mus])
+    scale = np.array([1.0, mu, mu, mus, mur, mur])[:condim]
     zones = set()
-    for q, v in _states(24, 37, 0.06):
+    for q, v in _states(64, 37, 0.06):
         t = o.forward(q, v)
         if t["ncon"] == 0:
             continue
         J, D, f = t["J"], t["D"], t["efc_force"]
-        assert J.shape[0] == 4 * t["ncon"]
+        assert J.shape[0] == condim * t["ncon"]
         jar = J @ t["qacc"] - t["aref"]
         for c in range(t["ncon"]):
-            r = slice(4 * c, 4 * c + 4)
-            Dn = D[4 * c]
-            np.testing.assert_allclose(D[4 * c + 1:4 * c + 3], impratio * Dn, rtol=1e-12)
-            np.testing.assert_allclose(D[4 * c + 3], impratio * Dn * (mus / mu) ** 2, rtol=1e-12)
+            r = slice(condim * c, condim * c + condim)
+            Dn = D[condim * c]
+            np.testing.assert_allclose(D[r][1:], impratio * Dn * (scale[1:] / mu) ** 2, rtol=1e-12)
             y = -D[r] * jar[r]
             fc = f[r]
             w = (y - fc) / D[r]
             sf = max(np.abs(y).max(), 1e-12)
             sw = max(np.abs(y / D[r]).max(), 1e-12)
-            assert np.linalg.norm(fc[1:] / scale[1:]) <= fc[0] + 1e-10 * sf / mus
+            assert np.linalg.norm(fc[1:] / scale[1:]) <= fc[0] + 1e-10 * sf / scale.min()
             assert w[0] + np.linalg.norm(w[1:] * scale[1:]) <= 1e-10 * sw
             assert abs(w @ fc) <= 1e-10 * sf * sw
             fz, wz = np.abs(fc).max() <= 1e-12 * sf, np.abs(w).max() <= 1e-12 * sw
@@ -86,6 +90,40 @@ def test_no_torsional_friction_steps_as_condim3(oracle_mod):
         res.append((q.copy(), v.copy()))
     np.testing.assert_allclose(res[0][0], res[1][0], rtol=0, atol=1e-12)
     np.testing.assert_allclose(res[0][1], res[1][1], rtol=0, atol=1e-12)
+
+
+def test_no_rolling_friction_steps_as_condim4(oracle_mod):
+    """condim 6 with mu_roll = 0 gives the rolling rows D = 0, so its cone is the condim-4 cone: 30
+    steps of a tumbling box agree with the condim-4 steps to 1e-12."""
+    res = []
+    for condim in (4, 6):
+        m = _elliptic4(robots.free_body("box", size=(0.1, 0.07, 0.05), friction=0.5), 0.03, 2.0, condim)
+        for g in m["geoms"]:
+            g["friction_roll"] = 0.0
+        o = oracle_mod.Oracle(m)
+        q = np.concatenate([[0, 0, 0.06], robots.quat_axis_angle((1, 1, 0), 0.4)])[None]
+        v = np.full((1, 6), 0.3)
+        ws = np.zeros((1, 6))
+        for _ in range(30):
+            o.step(np.zeros((1, 0)), q, v, ws)
+        res.append((q.copy(), v.copy()))
+    np.testing.assert_allclose(res[0][0], res[1][0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(res[0][1], res[1][1], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("condim,keeps_roll", [(4, True), (6, False)])
+def test_rolling_kept_or_lost_by_condim(oracle_mod, condim, keeps_roll):
+    """A ball rolling at 0.5 m/s on a plane with elliptic cones keeps its speed over 4 s to 0.1 %
+    with condim 4 (no rolling friction) and loses at least 10 % of it with condim 6 (mu_roll
+    0.002)."""
+    m = _elliptic4(robots.free_body("sphere", size=(0.1,), pos=(0, 0, 0.1), timestep=0.002), 0.002, 1.0, condim)
+    for g in m["geoms"]:
+        g["friction_roll"] = 0.002
+    o, q, v, ws = _rest_sphere(oracle_mod, m, 500)
+    v[0, 0], v[0, 4] = 0.5, 5.0
+    for _ in range(2000):
+        o.step(np.zeros((1, 0)), q, v, ws)
+    assert (abs(v[0, 0] - 0.5) < 5e-4) == keeps_roll and (v[0, 0] < 0.45) != keeps_roll
 
 
 def _rest_sphere(oracle_mod, m, steps):
