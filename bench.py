@@ -64,6 +64,9 @@ WORKLOAD_TEXT = {
                            "sphere feet (condim 4, mu_spin 0.02): 4 rows per foot contact in one cone",
     "humanoid_elliptic4": "humanoid with elliptic friction cones (impratio 1) and torsional friction on the "
                           "foot boxes (condim 4, mu_spin 0.02)",
+    "quadruped_elliptic6": "quadruped with elliptic friction cones (impratio 1) and torsional and rolling friction "
+                           "on the sphere feet (condim 6, mu_spin 0.02, mu_roll 0.002): 6 rows per foot contact "
+                           "in one cone",
     "cube_stack": "three free 10 cm cubes (0.3/0.2/0.1 kg) stacked on a plane with random offsets, yaws and tilts: "
                   "box-box contacts between moving bodies (dense Newton Hessian), dt 2 ms x 4 substeps",
     "pincer": "a hinged palm with two hinged box fingers closed onto each other by position actuators: box-box "
@@ -78,7 +81,7 @@ DEFAULT_WORLDS = {"humanoid": 8192, "quadruped": 4096, "chain3": 64, "arm_box": 
                   "quadruped_lim": 4096, "quadruped_terrain": 4096, "humanoid_terrain": 8192,
                   "humanoid_damp": 8192, "quadruped_hfield": 4096, "humanoid_weld": 8192, "chain3_loop": 8192,
                   "quadruped_condim6": 4096, "humanoid_condim4": 8192, "quadruped_elliptic": 4096,
-                  "humanoid_elliptic": 8192, "quadruped_elliptic4": 4096, "humanoid_elliptic4": 8192, "cube_stack": 8192, "pincer": 8192, "humanoid_self": 8192,
+                  "humanoid_elliptic": 8192, "quadruped_elliptic4": 4096, "humanoid_elliptic4": 8192, "quadruped_elliptic6": 4096, "cube_stack": 8192, "pincer": 8192, "humanoid_self": 8192,
                   "pincer_cube": 8192}
 WORKLOAD_TEXT["serve"] = ("serving: Poisson arrivals of rollout requests, model uniform over chain3/quadruped/humanoid/"
                           "arm_box, worlds log-uniform 16-4096, horizon uniform 50-500 env steps, device-side seeded "

@@ -129,14 +129,14 @@ typedef struct rb_model_desc {
      * the simulator it builds on). */
     const double *geom_friction_spin, *geom_friction_roll;
     /* friction cones: RB_CONE_PYRAMIDAL (2 (condim - 1) pyramid rows per contact) or
-     * RB_CONE_ELLIPTIC (condim 1, 3 or 4; 6 is refused): a contact's frame rows (normal, t1, t2,
-     * and with condim 4 the spin about the normal) costed together by the soft elliptic cone,
-     * its force the projection of -D jar onto the friction cone {(f_1/mu)^2 + (f_2/mu)^2 +
-     * (f_spin/mu_spin)^2 <= f_n^2} in the metric of D^-1; the friction rows have no distance
-     * reference, the tangential rows take the normal row's D times impratio (> 0; 1 when 0 is
-     * given) and the spin row that times (mu_spin / mu)^2.  Cites: paper, section
-     * "Architecture", paragraph on the GPU physics backend (the constraint model of the
-     * simulator it builds on). */
+     * RB_CONE_ELLIPTIC: a contact's condim frame rows (normal, t1, t2, then the spin about the
+     * normal with condim 4 and 6, and the rolling about t1, t2 with condim 6) costed together by
+     * the soft elliptic cone, its force the projection of -D jar onto the friction cone
+     * {sum_i (f_i / mu_i)^2 <= f_n^2} (mu_i: mu, mu_spin or mu_roll) in the metric of D^-1; the
+     * friction rows have no distance reference, the tangential rows take the normal row's D
+     * times impratio (> 0; 1 when 0 is given), the spin and rolling rows that times
+     * (mu_i / mu)^2.  Cites: paper, section "Architecture", paragraph on the GPU physics
+     * backend (the constraint model of the simulator it builds on). */
     int32_t cone;
     double impratio;
 } rb_model_desc;

@@ -49,7 +49,8 @@ def _jobs() -> int:
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     os.makedirs(OBJ_DIR, exist_ok=True)
-    units = [(PARTED, [f"-DRB_PART={k}"], f"step_kernel.part{k}.o") for k in range(nparts())]
+    # the last parts hold the fused launchers, which inline the most steps: started first
+    units = [(PARTED, [f"-DRB_PART={k}"], f"step_kernel.part{k}.o") for k in reversed(range(nparts()))]
     units += [(s, [], os.path.splitext(s)[0] + ".o") for s in SOURCES if s != PARTED]
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     cmds = []

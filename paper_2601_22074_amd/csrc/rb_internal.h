@@ -128,7 +128,7 @@ struct DevModel {
     const int* pair_body1;     // per pair: the second moving body (g1's), 0 when g1's body is static
     float impratio, rsqrt_impratio;
     const int* pair_xrows;     // per pair: 0, 2 (condim 4) or 6 (condim 6) rows per contact
-    const int* pair_spin4;     // per pair: 1 when an elliptic contact carries the spin row (condim 4)
+    const int* pair_ellrows;   // per pair, elliptic cones: frame rows beyond three (1 spin: condim 4; 3 spin, rolling: 6)
     const float* pair_mu_spin;
     const float* pair_mu_roll;
     const int* eq_body;

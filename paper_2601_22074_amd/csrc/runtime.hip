@@ -418,9 +418,8 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     int nmm = 0;                         // pairs of two moving bodies
     int nbb = 0;
     std::vector<double> psig(npair), pmu(npair), pmar(npair);
-    std::vector<int> pfric0(npair, 0), pxr(npair, 0), pspin4(npair, 0);
+    std::vector<int> pfric0(npair, 0), pxr(npair, 0), pellx(npair, 0);
     const bool elliptic = d->cone == RB_CONE_ELLIPTIC;
-    bool ell6 = false;   // condim 6 under elliptic cones (refused below)
     std::vector<double> pmus(npair, 0.0), pmur(npair, 0.0);
     int nxmax = 0;
     int maxcon = 0;
@@ -451,11 +450,10 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
             // condim 4 adds the torsional row pair, 6 the two rolling pairs too
             const int cd = std::max(d->geom_condim[g1], d->geom_condim[g2]);
             pfric0[k] = cd == 1;
-            // pyramidal: extra generic rows; elliptic: condim 4's spin row joins the contact's
-            // cone in its own lane
+            // pyramidal: extra generic rows; elliptic: the spin row (condim 4) and the rolling
+            // rows (6) join the contact's cone in its own lane
             pxr[k] = elliptic ? 0 : (cd == 4 ? 2 : (cd == 6 ? 6 : 0));
-            pspin4[k] = elliptic && cd == 4;
-            ell6 = ell6 || (elliptic && cd == 6);
+            pellx[k] = elliptic ? (cd == 4 ? 1 : (cd == 6 ? 3 : 0)) : 0;
             auto fmax = [&](const double* f, double dflt) { return f ? std::max(f[g1], f[g2]) : dflt; };
             pmus[k] = fmax(d->geom_friction_spin, 0.005);
             pmur[k] = fmax(d->geom_friction_roll, 0.0001);
@@ -473,7 +471,6 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
         return fail(RB_EINVAL, "cone must be RB_CONE_PYRAMIDAL or RB_CONE_ELLIPTIC");
     const double impratio = d->impratio == 0 ? 1.0 : d->impratio;
     if (!(impratio > 0) || !std::isfinite(impratio)) return fail(RB_EINVAL, "impratio must be positive");
-    if (ell6) return fail(RB_EINVAL, "elliptic cones take condim 1, 3 or 4");
     if (nmm > 0) {
         if (d->cone == RB_CONE_ELLIPTIC)
             return fail(RB_EINVAL, "contacts between two moving bodies take pyramidal cones");
@@ -677,7 +674,7 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     F(std::vector<double>(d->geom_quat, d->geom_quat + 4 * ng), &m.geom_quat);
     F(std::vector<double>(d->geom_size, d->geom_size + 3 * ng), &m.geom_size);
     if (nxmax > 0 || elliptic) {
-        I(pxr, &m.pair_xrows); F(pmus, &m.pair_mu_spin); F(pmur, &m.pair_mu_roll); I(pspin4, &m.pair_spin4);
+        I(pxr, &m.pair_xrows); F(pmus, &m.pair_mu_spin); F(pmur, &m.pair_mu_roll); I(pellx, &m.pair_ellrows);
     }
     if (neqrow > 0) {
         I(eqb, &m.eq_body); F(eqa, &m.eq_anchor); F(eqp, &m.eq_tpos); F(eqm, &m.eq_tmat);
@@ -712,9 +709,12 @@ int compile_model(const rb_model_desc* d, rb_model* M) {
     m.cone = d->cone == RB_CONE_ELLIPTIC && npair > 0 ? 1 : 0;
     m.impratio = (float)impratio;
     m.rsqrt_impratio = (float)(1.0 / std::sqrt(impratio));
-    // level 2: equality rows, torsional / rolling rows, elliptic cones; level 1: the rest
-    // level 3: pairs of two moving bodies (a dense Newton Hessian)
-    const int ext2 = nmm > 0 ? 3 : (neqrow > 0 || nxmax > 0 || m.cone) ? 2 : 0;
+    // level 2: equality rows, torsional / rolling rows, elliptic cones up to condim 4; level 1:
+    // the rest; level 3: pairs of two moving bodies (a dense Newton Hessian); level 4: elliptic
+    // cones with condim 6 (the rolling rows)
+    bool ell6 = false;
+    for (int k = 0; k < npair; k++) ell6 = ell6 || pellx[k] == 3;
+    const int ext2 = nmm > 0 ? 3 : (ell6 ? 4 : ((neqrow > 0 || nxmax > 0 || m.cone) ? 2 : 0));
     m.nmm = nmm;
     m.ext = ext2 ? ext2 : (nbb > 0 || nlim > 0 || ndamp > 0 || npair > RB_WAVE ||
              std::count(ptype.begin(), ptype.end(), RB_PAIR_SPHEREBOX) > 0 ||

@@ -431,12 +431,15 @@ struct Con {
     int body;
     int body1;             // g1's body when both bodies move (rows of g2's minus g1's motion), else 0
     int ids;               // g1 | g2 << 8 | feature << 16
-    float D[4], aref[4], jar[4];
+    // rows: the pyramid's four, or an elliptic contact's frame rows (normal, t1, t2, spin, and
+    // the two rolling rows, used only by the extended instantiations)
+    float D[6], aref[6], jar[6];
 };
 
 // velocity of the contact's pyramid rows for body spatial motions `bm` (already includes sign);
-// of its frame rows (normal, t1, t2, then the spin about n when ell is 2, else 0) for an
-// elliptic-cone contact; b1 > 0: the contact's second moving body, whose motion is subtracted
+// of its frame rows for an elliptic-cone contact: normal, t1, t2, then the spin about n (ell 2
+// or 3, else 0) and the rolling about t1 and t2 (ell 3; out [6]); b1 > 0: the contact's second
+// moving body, whose motion is subtracted
 DEV void rows_of(const Con& c, const float* bm, float* out, int ell = 0, int b1 = 0) {
     const float* sv = bm + 6 * c.body;
     float wr[3], t2[3];
@@ -451,12 +454,16 @@ DEV void rows_of(const Con& c, const float* bm, float* out, int ell = 0, int b1 
     }
     float vn = c.sigma * dot(c.n, vp), v1 = c.sigma * dot(c.t1, vp), v2 = c.sigma * dot(t2, vp);
     if (ell) {
-        float ws = 0.f;
-        if (ell == 2) {
-            ws = dot(c.n, sv);
-            if (b1 > 0) ws -= dot(c.n, bm + 6 * b1);
+        float wa[3] = {sv[0], sv[1], sv[2]};   // angular motion, relative to b1's
+        if (b1 > 0) {
+            wa[0] -= bm[6 * b1]; wa[1] -= bm[6 * b1 + 1]; wa[2] -= bm[6 * b1 + 2];
         }
-        out[0] = vn; out[1] = v1; out[2] = v2; out[3] = c.sigma * ws;
+        out[0] = vn; out[1] = v1; out[2] = v2;
+        out[3] = ell >= 2 ? c.sigma * dot(c.n, wa) : 0.f;
+        if (ell == 3) {
+            out[4] = c.sigma * dot(c.t1, wa);
+            out[5] = c.sigma * dot(t2, wa);
+        }
         return;
     }
     out[0] = vn + c.mu * v1;
@@ -465,44 +472,106 @@ DEV void rows_of(const Con& c, const float* bm, float* out, int ell = 0, int b1 
     out[3] = vn - c.mu * v2;
 }
 
-// Soft elliptic cone of one contact at the frame-row residuals jar (normal, t1, t2, spin about
-// n), with regulariser inverses D0 (normal), Dt (tangential) and Ds (spin; 0 without torsional
-// friction, which leaves the three-row cone) and cone slope mu: with x = sqrt(D) jar, cost 0
-// when mu |x_t| <= x_n (separating), |x|^2 / 2 when |x_t| <= -mu x_n (inside the cone), else
-// (mu |x_t| - x_n)^2 / (2 (1 + mu^2)) (the force on the cone's surface).  Returns the zone (0,
-// 1 surface, 2 inside) and the cost; g = d cost / d jar [4], h its Hessian (h00 h01 h02 h11 h12
-// h22, then h03 h13 h23 h33).
-DEV int ell_eval(const float* jar, float D0, float Dt, float Ds, float mu, float* cost, float* g, float* h) {
-    const float s0 = sqrtf(D0), st = sqrtf(Dt), ss = sqrtf(Ds);
-    const float N = s0 * jar[0], x1 = st * jar[1], x2 = st * jar[2], x3 = ss * jar[3];
-    const float T = sqrtf(x1 * x1 + x2 * x2 + x3 * x3);
-    for (int k = 0; k < 4; k++) g[k] = 0.f;
-    for (int k = 0; k < 10; k++) h[k] = 0.f;
+// Soft elliptic cone of one contact at its frame-row residuals jar [6] (normal, t1, t2, spin about
+// n, rolling about t1 and t2), with regulariser inverses D0 (normal), Dt (tangents), Ds (spin)
+// and Dr (rolling; 0 for the rows a contact does not have, which leaves the smaller cone) and
+// cone slope mu: with x = sqrt(D) jar, cost 0 when mu |x_t| <= x_n (separating), |x|^2 / 2 when
+// |x_t| <= -mu x_n (inside the cone), else (mu |x_t| - x_n)^2 / (2 (1 + mu^2)) (the force on the
+// cone's surface).  ell_eval returns the zone (0, 1 surface, 2 inside), the cost and
+// g = d cost / d jar [6], and keeps what the Hessian's products need: on the surface the Hessian
+// is diag(sqrt D) c (w w' + k (I - u u') on the friction block) diag(sqrt D), w the gradient of
+// mu |x_t| - x_n in x, u = x_t / |x_t|, c = 1 / (1 + mu^2), k = (mu |x_t| - x_n) mu / |x_t|;
+// inside the cone it is diag(D).  The products are formed from these in O(rows), never the
+// 6 x 6 matrix.
+struct EllCone {
+    int zone;
+    float c, k, mu;
+    float sq[6];   // sqrt(D) per row
+    float u[6];    // u[0] unused
+};
+
+// NE: the rows the instantiation carries (4: normal, tangents, spin; 6: also rolling); jar, g and
+// the products' vectors have NE entries.
+template <int NE>
+DEV int ell_eval(const float* jar, float D0, float Dt, float Ds, float Dr, float mu, float* cost, float* g,
+                 EllCone* E) {
+    const float st = sqrtf(Dt);
+    E->sq[0] = sqrtf(D0); E->sq[1] = st; E->sq[2] = st; E->sq[3] = sqrtf(Ds);
+    if (NE > 4) E->sq[4] = E->sq[5] = sqrtf(Dr);
+    E->mu = mu;
+    float x[NE], T2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < NE; a++) x[a] = E->sq[a] * jar[a];
+#pragma unroll
+    for (int a = 1; a < NE; a++) T2 += x[a] * x[a];
+    const float N = x[0], T = sqrtf(T2);
+#pragma unroll
+    for (int k = 0; k < NE; k++) g[k] = 0.f;
     *cost = 0.f;
-    if (mu * T <= N) return 0;
+    E->c = E->k = 0.f;
+#pragma unroll
+    for (int a = 0; a < NE; a++) E->u[a] = 0.f;
+    if (mu * T <= N) return E->zone = 0;
     if (T <= -mu * N) {
-        *cost = 0.5f * (N * N + x1 * x1 + x2 * x2 + x3 * x3);
-        g[0] = D0 * jar[0]; g[1] = Dt * jar[1]; g[2] = Dt * jar[2]; g[3] = Ds * jar[3];
-        h[0] = D0; h[3] = Dt; h[5] = Dt; h[9] = Ds;
-        return 2;
+        const float Dd[6] = {D0, Dt, Dt, Ds, Dr, Dr};
+        float cs = N * N;
+#pragma unroll
+        for (int a = 1; a < NE; a++) cs += x[a] * x[a];
+        *cost = 0.5f * cs;
+#pragma unroll
+        for (int a = 0; a < NE; a++) g[a] = Dd[a] * jar[a];
+        return E->zone = 2;
     }
     const float c = 1.f / (1.f + mu * mu), hh = mu * T - N, iT = 1.f / T;
-    const float u1 = x1 * iT, u2 = x2 * iT, u3 = x3 * iT;
-    const float w0 = -1.f, w1 = mu * u1, w2 = mu * u2, w3 = mu * u3;   // gradient of hh in x
-    const float k = hh * mu * iT;                                      // curvature of |x_t| across the cone
+    E->c = c;
+    E->k = hh * mu * iT;
+#pragma unroll
+    for (int a = 1; a < NE; a++) E->u[a] = x[a] * iT;
     *cost = 0.5f * c * hh * hh;
-    g[0] = s0 * c * hh * w0; g[1] = st * c * hh * w1; g[2] = st * c * hh * w2; g[3] = ss * c * hh * w3;
-    h[0] = D0 * c * w0 * w0;
-    h[1] = s0 * st * c * w0 * w1;
-    h[2] = s0 * st * c * w0 * w2;
-    h[3] = Dt * c * (w1 * w1 + k * (1.f - u1 * u1));
-    h[4] = Dt * c * (w1 * w2 - k * u1 * u2);
-    h[5] = Dt * c * (w2 * w2 + k * (1.f - u2 * u2));
-    h[6] = s0 * ss * c * w0 * w3;
-    h[7] = st * ss * c * (w1 * w3 - k * u1 * u3);
-    h[8] = st * ss * c * (w2 * w3 - k * u2 * u3);
-    h[9] = Ds * c * (w3 * w3 + k * (1.f - u3 * u3));
-    return 1;
+    g[0] = E->sq[0] * c * hh * -1.f;
+#pragma unroll
+    for (int a = 1; a < NE; a++) {
+        const float wa = mu * E->u[a];   // the gradient of mu |x_t| - x_n in x
+        g[a] = E->sq[a] * c * hh * wa;
+    }
+    return E->zone = 1;
+}
+
+// out = H v for the cone's Hessian H (zone 0: 0)
+template <int NE>
+DEV void ell_hv(const EllCone& E, const float* v, float* out) {
+    float y[NE];
+#pragma unroll
+    for (int a = 0; a < NE; a++) y[a] = E.sq[a] * v[a];
+    if (E.zone == 2) {
+#pragma unroll
+        for (int a = 0; a < NE; a++) out[a] = E.sq[a] * y[a];
+        return;
+    }
+    float uy = 0.f;
+#pragma unroll
+    for (int a = 1; a < NE; a++) uy += E.u[a] * y[a];
+    const float wy = E.mu * uy - y[0];
+    out[0] = -E.sq[0] * E.c * wy;
+#pragma unroll
+    for (int a = 1; a < NE; a++) out[a] = E.sq[a] * E.c * (E.mu * E.u[a] * wy + E.k * (y[a] - E.u[a] * uy));
+}
+
+// v' H v
+template <int NE>
+DEV float ell_vhv(const EllCone& E, const float* v) {
+    float y[NE];
+#pragma unroll
+    for (int a = 0; a < NE; a++) y[a] = E.sq[a] * v[a];
+    float yy = 0.f, uy = 0.f;
+#pragma unroll
+    for (int a = 1; a < NE; a++) {
+        yy += y[a] * y[a];
+        uy += E.u[a] * y[a];
+    }
+    if (E.zone == 2) return y[0] * y[0] + yy;
+    const float wy = E.mu * uy - y[0];
+    return E.c * (wy * wy + E.k * (yy - uy * uy));
 }
 
 DEV void contact_frame(const float* n, float* t1) {
@@ -965,14 +1034,20 @@ struct StepArgs {
 
 // MAXD: longest dof chain the instantiation supports; TIMED: the diagnostic instantiation that
 // serves rb_step_taps (stage taps, work totals and per-stage shader-clock cycles); the plain
-// instantiation carries none of that code.  EXT: the extended instantiation, with the code of
-// box-box, sphere-box and capsule-box pairs, more than 64 pairs, frictionless pairs, joint
-// limits and joint damping, used for models that have any.
+// instantiation carries none of that code.  EXT: the level of extended code -- 1: box-box,
+// sphere-box and capsule-box pairs, more than 64 pairs, frictionless pairs, joint limits and
+// joint damping; 2: also generic rows (equality constraints, pyramidal torsional / rolling rows)
+// and elliptic cones up to condim 4; 3: level 2 and contacts between two moving bodies; 4: level
+// 2 with elliptic cones up to condim 6 (two more rows per contact lane).  Each model runs the
+// lowest level that has its features.
 #ifndef RB_WAVES_PER_EU
 #define RB_WAVES_PER_EU 3
 #endif
 template <int MAXD, bool TIMED, int EXT>
 DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* lds) {
+    // an elliptic contact's frame rows: normal, tangents and spin; with the rolling rows too in the
+    // level-4 instantiation (elliptic cones with condim 6)
+    constexpr int NE = EXT == 4 ? 6 : 4;
     const int lane = threadIdx.x & (RB_WAVE - 1);   // a fused workgroup may hold several worlds
     float* L = lds;
     float* q = L + m.o_q;
@@ -1360,7 +1435,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         float margin_c = 0.f;
         xr = 0;
         float mu_spin = 0.f, mu_roll = 0.f;
-        bool spin4 = false;   // an elliptic contact with the spin row (condim 4)
+        int ellx = 0;   // an elliptic contact's rows beyond the three: 1 spin (condim 4), 3 spin and rolling (6)
         if (has) {
             int j = lane - before, feat;
             if (EXT && m.pair_type[src] == RB_PAIR_BOXBOX) {
@@ -1379,7 +1454,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             contact_frame(C.n, C.t1);
             C.ids = m.pair_g1[src] | (m.pair_g2[src] << 8) | (feat << 16);
             C.body = m.pair_body[src];
-            C.body1 = (EXT >= 3 && m.nmm > 0) ? m.pair_body1[src] : 0;
+            C.body1 = (EXT == 3 && m.nmm > 0) ? m.pair_body1[src] : 0;
             C.sigma = m.pair_sigma[src];
             C.mu = m.fr_pw ? mu_world : m.pair_mu[src];
             if (EXT && m.pair_frictionless[src]) {
@@ -1393,7 +1468,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 xr = m.pair_xrows[src];
                 mu_spin = m.pair_mu_spin[src];
                 mu_roll = m.pair_mu_roll[src];
-                spin4 = m.pair_spin4[src] != 0;
+                ellx = m.pair_ellrows[src];
             }
         } else {
             C.body = 0;
@@ -1402,8 +1477,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         // an elliptic-cone contact (extended code): frame rows costed by the soft elliptic cone;
         // frictionless contacts keep their one normal row
         const bool cell = EXT >= 2 && m.cone && has && !(C.ids >> 24);
-        const bool cspin = cell && spin4;
-        const int cellm = cell ? (cspin ? 2 : 1) : 0;   // rows_of's frame rows (with the spin: 2)
+        const bool cspin = cell && ellx >= 1, croll = EXT == 4 && cell && ellx == 3;
+        const int cellm = cell ? (croll ? 3 : (cspin ? 2 : 1)) : 0;   // rows_of's elliptic frame rows
+        const int celld = croll ? 6 : (cspin ? 4 : 3);                 // and their number
         RB_STAGE(3);
         // generic-row slots of the contacts' extra rows: after the equality rows, in contact order
         float* GR = L + m.o_gr;
@@ -1428,7 +1504,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             uint32_t cw1[MAXD / 4];
 #pragma unroll
             for (int w2 = 0; w2 < MAXD / 4; w2++) cw1[w2] = 0u;
-            if (EXT >= 3 && m.nmm > 0) {
+            if (EXT == 3 && m.nmm > 0) {
                 d1 = __shfl(BL.depth, C.body1);
                 const int csrc1 = __shfl(BL.src, C.body1);
 #pragma unroll
@@ -1493,7 +1569,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         A02 += Z0[t] * Y[t];
                     }
             }
-            if (EXT >= 3 && C.body1 > 0) {
+            if (EXT == 3 && C.body1 > 0) {
                 // both bodies move: J = J(b2) - J(b1), and Y = L'^-1 J' is the sum of the half-solves
                 // along each chain (+dir on b2's, -dir on b1's), the two adding on their common
                 // prefix; A-hat sums Y^2 / D over the union of the two chains
@@ -1560,8 +1636,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     if (k == 0) { A11 = Akk; A01 = A0k; } else { A22 = Akk; A02 = A0k; }
                 }
             }
-            float vrow[4];
-            rows_of(C, cvel, vrow, cellm, EXT >= 3 ? C.body1 : 0);
+            float vrow[6] = {0, 0, 0, 0, 0, 0};
+            rows_of(C, cvel, vrow, cellm, EXT == 3 ? C.body1 : 0);
             float rd = C.dist - margin_c;
             float imp = impedance(m, rd);
             float mu = C.mu, mu2 = mu * mu;
@@ -1582,13 +1658,22 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 C.aref[1] = -m.bref * vrow[1];
                 C.aref[2] = -m.bref * vrow[2];
                 C.aref[3] = -m.bref * vrow[3];
+                if (EXT == 4) {
+                    C.aref[4] = -m.bref * vrow[4];
+                    C.aref[5] = -m.bref * vrow[5];
+                }
                 C.D[0] = D0;
                 C.D[1] = C.D[2] = m.impratio * D0;
-                // the spin row (condim 4): regulariser the normal's times mu^2 / (mu_spin^2
-                // impratio), which keeps the cone circular in the D-scaled rows
+                // the spin row (condim 4, 6) and the rolling rows (6): regulariser the normal's
+                // times mu^2 / (mu_d^2 impratio), which keeps the cone circular in the D-scaled rows
                 const float rs = (cspin && C.mu > 0.f) ? mu_spin / C.mu : 0.f;
+                const float rr = (croll && C.mu > 0.f) ? mu_roll / C.mu : 0.f;
                 C.D[3] = m.impratio * D0 * rs * rs;
+                if (EXT == 4) C.D[4] = C.D[5] = m.impratio * D0 * rr * rr;
                 ah[0] = A00; ah[1] = A11; ah[2] = A22; ah[3] = 0.f;
+            } else if (EXT == 4) {
+                C.aref[4] = C.aref[5] = 0.f;
+                C.D[4] = C.D[5] = 0.f;
             }
             if (TIMED && A.want_taps && sub == 0 && A.taps.efc) {
                 float* E = A.taps.efc + ((size_t)w * m.ncap + lane) * 12;
@@ -1788,13 +1873,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         } else {
             // cost at a0 and at the warm start; keep the better (ties go to a0)
             body_motion(m, BL, DL, cdof, a0, bvec, lane);
-            float j0[4] = {0, 0, 0, 0};
+            constexpr int NR = EXT == 4 ? 6 : 4;   // rows per contact lane in this instantiation
+            float j0[6] = {0, 0, 0, 0, 0, 0};
             float f0 = 0.f;
             // the lane's contact cost at residuals j: pyramid rows, or the elliptic cone
             auto con_cost = [&](const float* j) {
                 if (cell) {
-                    float cst, ge[4], he[10];
-                    ell_eval(j, C.D[0], C.D[1], C.D[3], C.mu * m.rsqrt_impratio, &cst, ge, he);
+                    float cst, ge[6];
+                    EllCone E;
+                    ell_eval<NE>(j, C.D[0], C.D[1], C.D[3], NE > 4 ? C.D[4] : 0.f, C.mu * m.rsqrt_impratio, &cst, ge, &E);
                     return cst;
                 }
                 float cst = 0.f;
@@ -1806,9 +1893,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 return cst;
             };
             if (has) {
-                rows_of(C, bvec, j0, cellm, EXT >= 3 ? C.body1 : 0);
+                rows_of(C, bvec, j0, cellm, EXT == 3 ? C.body1 : 0);
 #pragma unroll
-                for (int e = 0; e < 4; e++) j0[e] -= C.aref[e];
+                for (int e = 0; e < NR; e++) j0[e] -= C.aref[e];
                 f0 += con_cost(j0);
             }
             // limit rows at a0 and at the warm start (their residuals are linear in a too);
@@ -1839,12 +1926,12 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
             // g <- M (aws - a0); bvec keeps the body motions of (aws - a0), and the rows are
             // linear in the motion, so the residuals at aws are those at a0 plus these
             spatial_mul(m, BL, DL, cdof, cinert, tmp, bvec, cvel, g, lane);
-            float jw[4] = {0, 0, 0, 0};
+            float jw[6] = {0, 0, 0, 0, 0, 0};
             float fw = 0.f;
             if (has) {
-                rows_of(C, bvec, jw, cellm, EXT >= 3 ? C.body1 : 0);
+                rows_of(C, bvec, jw, cellm, EXT == 3 ? C.body1 : 0);
 #pragma unroll
-                for (int e = 0; e < 4; e++) jw[e] += j0[e];
+                for (int e = 0; e < NR; e++) jw[e] += j0[e];
                 fw += con_cost(jw);
             }
             float qf = 0.f;
@@ -1868,7 +1955,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 Ma[i] = use_ws ? (tau[i] - bias[i]) + g[i] : (tau[i] - bias[i]);
             }
 #pragma unroll
-            for (int e = 0; e < 4; e++) C.jar[e] = use_ws ? jw[e] : j0[e];
+            for (int e = 0; e < NR; e++) C.jar[e] = use_ws ? jw[e] : j0[e];
             wave_sync();
             RB_STAGE(5);
 
@@ -1884,8 +1971,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 uint32_t bits = 0;
                 bool mid = false;   // an elliptic contact on its cone's surface: cost not quadratic
                 if (cell) {
-                    float cst, ge[4], he[10];
-                    const int zone = ell_eval(C.jar, C.D[0], C.D[1], C.D[3], C.mu * m.rsqrt_impratio, &cst, ge, he);
+                    float cst, ge[6];
+                    EllCone E;
+                    const int zone = ell_eval<NE>(C.jar, C.D[0], C.D[1], C.D[3], NE > 4 ? C.D[4] : 0.f, C.mu * m.rsqrt_impratio, &cst, ge, &E);
                     bits = (uint32_t)zone;
                     mid = zone == 1;
                 } else if (has) {
@@ -1910,39 +1998,49 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     const uint32_t mlo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)BL.chainmask, body);
                     const uint32_t mhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(BL.chainmask >> 32), body);
                     const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
-                    float r[3], n[3], t1[3], t2[3], D[4], jar[4];
+                    float r[3], n[3], t1[3], t2[3], D[6], jar[6];
                     for (int k = 0; k < 3; k++) {
                         r[k] = rl(C.r[k], c); n[k] = rl(C.n[k], c);
                         t1[k] = rl(C.t1[k], c);
                     }
                     cross(n, t1, t2);
                     for (int e = 0; e < 4; e++) { D[e] = rl(C.D[e], c); jar[e] = rl(C.jar[e], c); }
+                    D[4] = D[5] = jar[4] = jar[5] = 0.f;
+                    if (EXT == 4) {
+                        // an elliptic contact's rolling rows
+                        D[4] = D[5] = rl(C.D[4], c);
+                        jar[4] = rl(C.jar[4], c); jar[5] = rl(C.jar[5], c);
+                    }
                     float mu = rl(C.mu, c), sg = rl(C.sigma, c);
                     // an elliptic contact: its cost's gradient and Hessian in its frame rows
                     const bool ellc = EXT >= 2 && m.cone && !(__builtin_amdgcn_readlane(C.ids, c) >> 24);
-                    float ge[4], he[10];
+                    float ge[6];
+                    EllCone E;
                     if (ellc) {
                         float cst;
-                        ell_eval(jar, D[0], D[1], D[3], mu * m.rsqrt_impratio, &cst, ge, he);
+                        ell_eval<NE>(jar, D[0], D[1], D[3], NE > 4 ? D[4] : 0.f, mu * m.rsqrt_impratio, &cst, ge, &E);
                     }
                     if (ellc && dof_lane && ((mask >> lane) & 1ull)) {
                         float wr[3];
                         cross(S, r, wr);
                         const float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
-                        const float jn = sg * dot(n, vp), j1 = sg * dot(t1, vp), j2 = sg * dot(t2, vp);
-                        const float js = sg * dot(n, S);   // the spin row (D = 0 without it)
-                        gc += ge[0] * jn + ge[1] * j1 + ge[2] * j2 + ge[3] * js;
+                        // the rows' Jacobian entries: sliding from the point's velocity, spin and
+                        // rolling from the angular one (rows a contact lacks have D = 0)
+                        const float je[6] = {sg * dot(n, vp), sg * dot(t1, vp), sg * dot(t2, vp),
+                                             sg * dot(n, S), sg * dot(t1, S), sg * dot(t2, S)};
+                        float u[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+                        for (int a = 0; a < NE; a++) gc += ge[a] * je[a];
+                        ell_hv<NE>(E, je, u);
                         // Hessian term: the rows' directions weighted by h je, as a spatial force
-                        // (the spin row's direction is the pure torque n)
-                        const float u0 = he[0] * jn + he[1] * j1 + he[2] * j2 + he[6] * js;
-                        const float u1 = he[1] * jn + he[3] * j1 + he[4] * j2 + he[7] * js;
-                        const float u2 = he[2] * jn + he[4] * j1 + he[5] * j2 + he[8] * js;
-                        const float u3 = he[6] * jn + he[7] * j1 + he[8] * j2 + he[9] * js;
-                        float a[3], ra[3];
-                        for (int k = 0; k < 3; k++) a[k] = sg * (u0 * n[k] + u1 * t1[k] + u2 * t2[k]);
+                        // (the spin and rolling rows' directions are the pure torques n, t1, t2)
+                        float a[3], ra[3], tq[3];
+                        for (int k = 0; k < 3; k++) {
+                            a[k] = sg * (u[0] * n[k] + u[1] * t1[k] + u[2] * t2[k]);
+                            tq[k] = sg * (u[3] * n[k] + u[4] * t1[k] + u[5] * t2[k]);
+                        }
                         cross(r, a, ra);
-                        const float su3 = sg * u3;
-                        F[0] += ra[0] + su3 * n[0]; F[1] += ra[1] + su3 * n[1]; F[2] += ra[2] + su3 * n[2];
+                        F[0] += ra[0] + tq[0]; F[1] += ra[1] + tq[1]; F[2] += ra[2] + tq[2];
                         F[3] += a[0]; F[4] += a[1]; F[5] += a[2];
                     }
                     // a contact between two moving bodies (level-3 code): a dof on b2's chain
@@ -1950,7 +2048,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                     // ancestors) not at all; its Hessian terms go to the dense Hessian instead
                     int b1c = 0;
                     uint64_t mask1 = 0ull;
-                    if (EXT >= 3 && m.nmm > 0) {
+                    if (EXT == 3 && m.nmm > 0) {
                         b1c = __builtin_amdgcn_readlane(C.body1, c);
                         if (b1c > 0) {
                             const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)BL.chainmask, b1c);
@@ -1958,18 +2056,18 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                             mask1 = ((uint64_t)khi << 32) | klo;
                         }
                     }
-                    const float cf = EXT >= 3 ? (float)((mask >> lane) & 1ull) - (float)((mask1 >> lane) & 1ull) : 1.f;
-                    const bool onrow = EXT >= 3 ? cf != 0.f : (bool)((mask >> lane) & 1ull);
+                    const float cf = EXT == 3 ? (float)((mask >> lane) & 1ull) - (float)((mask1 >> lane) & 1ull) : 1.f;
+                    const bool onrow = EXT == 3 ? cf != 0.f : (bool)((mask >> lane) & 1ull);
                     if (!ellc && dof_lane && onrow) {
                         float wr[3];
                         cross(S, r, wr);
                         float vp[3] = {S[3] + wr[0], S[4] + wr[1], S[5] + wr[2]};
-                        if (EXT >= 3) sg *= cf;
+                        if (EXT == 3) sg *= cf;
                         float jn = sg * dot(n, vp), j1 = sg * dot(t1, vp), j2 = sg * dot(t2, vp);
                         float je[4] = {jn + mu * j1, jn - mu * j1, jn + mu * j2, jn - mu * j2};
 #pragma unroll
                         for (int e = 0; e < 4; e++) {
-                            if (EXT >= 3 && b1c > 0) {
+                            if (EXT == 3 && b1c > 0) {
                                 if (jar[e] < 0.f) gc += D[e] * jar[e] * je[e];
                                 continue;
                             }
@@ -2026,8 +2124,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         // an elliptic contact's three rows count unless it separates (zone 0),
                         // as 2048 + id inside the cone (zone 2)
                         if (bits != 0)
-                            for (int e = 0; e < (cspin ? 4 : 3); e++)
-                                fpl += (uint32_t)(4 * lane + e + (bits == 2 ? 2048 : 0) + 1) * 2654435761u;
+                            for (int e = 0; e < celld; e++)
+                                fpl += (uint32_t)((e < 4 ? 4 * lane + e : 1024 + 6 * lane + e - 4) + (bits == 2 ? 2048 : 0) + 1) *
+                                       2654435761u;
                     } else if (has) {
 #pragma unroll
                         for (int e = 0; e < 4; e++)
@@ -2061,7 +2160,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         if (t == DL.depth - 1) Hr[t] += hl;
                 }
                 RB_STAGE(6);
-                if (EXT >= 3 && m.nmm > 0) {
+                if (EXT == 3 && m.nmm > 0) {
                     // Dense Newton Hessian: a contact between two moving bodies couples the two
                     // branches below their common ancestor, beyond M's tree sparsity.  The tree
                     // part is the row above; each such contact adds U' W U (U: its frame rows'
@@ -2149,8 +2248,8 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 RB_STAGE(7);
                 // directional quantities for the line search
                 spatial_mul(m, BL, DL, cdof, cinert, p, bvec, cvel, Mp, lane);
-                float sr[4] = {0, 0, 0, 0};
-                if (has) rows_of(C, bvec, sr, cellm, EXT >= 3 ? C.body1 : 0);
+                float sr[6] = {0, 0, 0, 0, 0, 0};
+                if (has) rows_of(C, bvec, sr, cellm, EXT == 3 ? C.body1 : 0);
                 float pa = 0.f, pb = 0.f;
                 if (dof_lane) {
                     pa = p[lane] * Mp[lane];
@@ -2191,15 +2290,15 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         auto dphi = [&](float al, float* d2) {
                             float d1l = 0.f, d2l = 0.f;
                             if (cell) {
-                                const float jj[4] = {C.jar[0] + al * sr[0], C.jar[1] + al * sr[1], C.jar[2] + al * sr[2],
-                                                     C.jar[3] + al * sr[3]};
-                                float cst, ge[4], he[10];
-                                ell_eval(jj, C.D[0], C.D[1], C.D[3], mue, &cst, ge, he);
-                                d1l += ge[0] * sr[0] + ge[1] * sr[1] + ge[2] * sr[2] + ge[3] * sr[3];
-                                d2l += he[0] * sr[0] * sr[0] + he[3] * sr[1] * sr[1] + he[5] * sr[2] * sr[2] +
-                                       he[9] * sr[3] * sr[3] +
-                                       2.f * (he[1] * sr[0] * sr[1] + he[2] * sr[0] * sr[2] + he[4] * sr[1] * sr[2] +
-                                              he[6] * sr[0] * sr[3] + he[7] * sr[1] * sr[3] + he[8] * sr[2] * sr[3]);
+                                float jj[NE];
+#pragma unroll
+                                for (int a = 0; a < NE; a++) jj[a] = C.jar[a] + al * sr[a];
+                                float cst, ge[6];
+                                EllCone E;
+                                ell_eval<NE>(jj, C.D[0], C.D[1], C.D[3], NE > 4 ? C.D[4] : 0.f, mue, &cst, ge, &E);
+#pragma unroll
+                                for (int a = 0; a < NE; a++) d1l += ge[a] * sr[a];
+                                d2l += ell_vhv<NE>(E, sr);
                             } else if (has) {
 #pragma unroll
                                 for (int e = 0; e < 4; e++) {
@@ -2301,7 +2400,7 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 float fc = 0.f;
                 if (has) {
 #pragma unroll
-                    for (int e = 0; e < 4; e++) C.jar[e] += alpha * sr[e];
+                    for (int e = 0; e < (EXT == 4 ? 6 : 4); e++) C.jar[e] += alpha * sr[e];
                     fc += con_cost(C.jar);
                 }
                 if (limact && dof_lane) {
@@ -2328,11 +2427,12 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                 st_seg += seg_sub;
                 // rows, and rows active at the solution (a frictionless contact has one row)
                 const bool fl = has && EXT && (C.ids >> 24);
-                int act = 0, nrow = has ? (fl ? 1 : (cell ? (cspin ? 4 : 3) : 4)) : 0;
+                int act = 0, nrow = has ? (fl ? 1 : (cell ? celld : 4)) : 0;
                 if (cell) {
-                    float cst, ge[4], he[10];
-                    act += ell_eval(C.jar, C.D[0], C.D[1], C.D[3], C.mu * m.rsqrt_impratio, &cst, ge, he) != 0
-                               ? (cspin ? 4 : 3) : 0;
+                    float cst, ge[6];
+                    EllCone E;
+                    act += ell_eval<NE>(C.jar, C.D[0], C.D[1], C.D[3], NE > 4 ? C.D[4] : 0.f, C.mu * m.rsqrt_impratio, &cst, ge, &E) != 0
+                               ? celld : 0;
                 } else if (has) {
                     for (int e = 0; e < 4; e++) act += C.jar[e] < 0.f && (e == 0 || !fl);
                 }
@@ -2496,8 +2596,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
         }
         if (A.co.force && EXT >= 2 && m.cone && !(C.ids >> 24)) {
             // elliptic cone: the frame rows' forces, minus the cost's gradient
-            float cst, ge[4], he[10];
-            ell_eval(C.jar, C.D[0], C.D[1], C.D[3], C.mu * m.rsqrt_impratio, &cst, ge, he);
+            float cst, ge[6];
+            EllCone E;
+            ell_eval<NE>(C.jar, C.D[0], C.D[1], C.D[3], NE > 4 ? C.D[4] : 0.f, C.mu * m.rsqrt_impratio, &cst, ge, &E);
             A.co.force[3 * slot] = -ge[0];
             A.co.force[3 * slot + 1] = -ge[1];
             A.co.force[3 * slot + 2] = -ge[2];
@@ -2563,7 +2664,8 @@ template <int MAXD, int EXT>
 DEV void world_step_level(const DevModel& m, const StepArgs& A, int w, float* lds) {
     // the model's own level of extended code, at most the plan's
     const int lv = m.ext < EXT ? m.ext : EXT;
-    if (EXT >= 3 && lv == 3) world_step<MAXD, false, (EXT >= 3 ? 3 : 0)>(m, A, w, lds);
+    if (EXT >= 4 && lv == 4) world_step<MAXD, false, (EXT >= 4 ? 4 : 0)>(m, A, w, lds);
+    else if (EXT >= 3 && lv == 3) world_step<MAXD, false, (EXT >= 3 ? 3 : 0)>(m, A, w, lds);
     else if (EXT >= 2 && lv == 2) world_step<MAXD, false, (EXT >= 2 ? 2 : 0)>(m, A, w, lds);
     else if (EXT >= 1 && lv == 1) world_step<MAXD, false, (EXT >= 1 ? 1 : 0)>(m, A, w, lds);
     else world_step<MAXD, false, 0>(m, A, w, lds);
@@ -2646,7 +2748,8 @@ void launch_multi_w4_t(const rbk::MultiArgs& M, dim3 g, size_t shmem, hipStream_
 #define RB_MULTI_I(X, D, E) X template void launch_multi_t<D, E>(const rbk::MultiArgs&, dim3, size_t, hipStream_t);
 #define RB_MULTI_W4_I(X, D, E) \
     X template void launch_multi_w4_t<D, E>(const rbk::MultiArgs&, dim3, size_t, hipStream_t);
-#define RB_LEVELS(F, X, ...) F(X, __VA_ARGS__, 0) F(X, __VA_ARGS__, 1) F(X, __VA_ARGS__, 2) F(X, __VA_ARGS__, 3)
+#define RB_LEVELS(F, X, ...) \
+    F(X, __VA_ARGS__, 0) F(X, __VA_ARGS__, 1) F(X, __VA_ARGS__, 2) F(X, __VA_ARGS__, 3) F(X, __VA_ARGS__, 4)
 
 // every launcher the dispatchers use
 RB_LEVELS(RB_STEP_I, extern, 8, false) RB_LEVELS(RB_STEP_I, extern, 16, false) RB_LEVELS(RB_STEP_I, extern, 32, false)
@@ -2655,9 +2758,9 @@ RB_LEVELS(RB_W4_I, extern, 8) RB_LEVELS(RB_W4_I, extern, 16)
 RB_LEVELS(RB_MULTI_I, extern, 8) RB_LEVELS(RB_MULTI_I, extern, 16) RB_LEVELS(RB_MULTI_I, extern, 32)
 RB_LEVELS(RB_MULTI_W4_I, extern, 8) RB_LEVELS(RB_MULTI_W4_I, extern, 16)
 
-// The parts, each defining launchers that inline 12 to 15 steps in all (a fused launcher inlines
+// The parts, each defining launchers that inline 10 to 19 steps in all (a fused launcher inlines
 // one step per chain bound and level at or below its own).  RB_NPARTS must match the list.
-#define RB_NPARTS 9
+#define RB_NPARTS 12
 #if RB_IN_PART(0)
 RB_LEVELS(RB_STEP_I, , 8, false) RB_LEVELS(RB_STEP_I, , 16, false) RB_LEVELS(RB_STEP_I, , 32, false)
 #endif
@@ -2685,6 +2788,15 @@ RB_MULTI_I(, 32, 0) RB_MULTI_I(, 32, 3)
 #endif
 #if RB_IN_PART(8)
 RB_MULTI_I(, 32, 1) RB_MULTI_I(, 32, 2)
+#endif
+#if RB_IN_PART(9)
+RB_MULTI_I(, 8, 4) RB_MULTI_I(, 16, 4)
+#endif
+#if RB_IN_PART(10)
+RB_MULTI_I(, 32, 4)
+#endif
+#if RB_IN_PART(11)
+RB_MULTI_W4_I(, 16, 4)
 #endif
 
 #if RB_IN_PART(0)
@@ -2737,7 +2849,8 @@ hipError_t rb_launch_multi(const DevModel* models, const void* args, const int* 
     M.lds_stride = lds_floats;
     size_t shmem = ((size_t)wpg * lds_floats + lds_pad) * sizeof(float);
     dim3 g((grid + wpg - 1) / wpg);   // grid counts worlds in flight, one wave each
-    if (ext >= 3) launch_multi_b<3>(maxd, M, g, shmem, waves == 4, stream);
+    if (ext >= 4) launch_multi_b<4>(maxd, M, g, shmem, waves == 4, stream);
+    else if (ext == 3) launch_multi_b<3>(maxd, M, g, shmem, waves == 4, stream);
     else if (ext == 2) launch_multi_b<2>(maxd, M, g, shmem, waves == 4, stream);
     else if (ext == 1) launch_multi_b<1>(maxd, M, g, shmem, waves == 4, stream);
     else launch_multi_b<0>(maxd, M, g, shmem, waves == 4, stream);
@@ -2775,17 +2888,20 @@ hipError_t rb_launch_step(const DevModel& m, int n, const float* ctrl, float* qp
     const bool timed = taps != nullptr;   // every tap is served by the diagnostic instantiation
     const int lv = m.ext;   // the level of extended code the model needs
     if (timed) {
-        if (lv >= 3) launch_step_d<true, 3>(m, A, n, shmem, stream);
+        if (lv >= 4) launch_step_d<true, 4>(m, A, n, shmem, stream);
+        else if (lv == 3) launch_step_d<true, 3>(m, A, n, shmem, stream);
         else if (lv == 2) launch_step_d<true, 2>(m, A, n, shmem, stream);
         else if (lv == 1) launch_step_d<true, 1>(m, A, n, shmem, stream);
         else launch_step_d<true, 0>(m, A, n, shmem, stream);
     } else if (waves == 4 && m.maxd <= 16) {
-        if (lv >= 3) launch_step_w4_d<3>(m, A, n, shmem, stream);
+        if (lv >= 4) launch_step_w4_d<4>(m, A, n, shmem, stream);
+        else if (lv == 3) launch_step_w4_d<3>(m, A, n, shmem, stream);
         else if (lv == 2) launch_step_w4_d<2>(m, A, n, shmem, stream);
         else if (lv == 1) launch_step_w4_d<1>(m, A, n, shmem, stream);
         else launch_step_w4_d<0>(m, A, n, shmem, stream);
     } else {
-        if (lv >= 3) launch_step_d<false, 3>(m, A, n, shmem, stream);
+        if (lv >= 4) launch_step_d<false, 4>(m, A, n, shmem, stream);
+        else if (lv == 3) launch_step_d<false, 3>(m, A, n, shmem, stream);
         else if (lv == 2) launch_step_d<false, 2>(m, A, n, shmem, stream);
         else if (lv == 1) launch_step_d<false, 1>(m, A, n, shmem, stream);
         else launch_step_d<false, 0>(m, A, n, shmem, stream);

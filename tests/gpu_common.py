@@ -381,6 +381,11 @@ class StepTally:
         floor = _memo(floor) if floor is not None else (lambda: 0.0)
         gs, os_ = g["sub"][gw], r["sub"][rw]
         kind = classify(gs, os_, self.smooth)
+        if kind == "path" and band and not np.array_equal(gs[:, CON_COLS], os_[:, CON_COLS]):
+            # (smooth mode) contact sets that differ after a solve that differed: where the world
+            # also has a contact on its inclusion threshold, that contact decided the later
+            # substep's set, so the sample is a threshold sample like any other
+            kind = "contacts"
         self.n += 1
         err = max(rel_err(g[k][gw], r[k][rw]) for k in ("qpos", "qvel"))
         if kind == "contacts":

@@ -44,7 +44,7 @@ def _create_error(m):
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
                                   "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
                                   "negative_damping", "condim", "nan_pos", "inf_size", "negative_spin",
-                                  "generic_rows", "elliptic_condim6"])
+                                  "generic_rows"])
 def test_invalid_models_rejected(rb, case):
     m = robots.quadruped()
     if case == "parent":
@@ -83,10 +83,6 @@ def test_invalid_models_rejected(rb, case):
         # condim 6 on the torso box (8 contacts) and the four feet: 6 x 12 = 72 rows > 64
         for g in m["geoms"]:
             g["condim"] = 6
-    elif case == "elliptic_condim6":
-        # elliptic cones take condim 1, 3 or 4
-        m["geoms"][1]["condim"] = 6
-        m["opt"]["cone"] = "elliptic"
     elif case == "nan_pos":
         m["bodies"][2]["pos"][0] = float("nan")
     elif case == "inf_size":
@@ -107,7 +103,7 @@ def _create_json_error(text):
 @pytest.mark.parametrize("case", ["parent", "mass", "triangle", "quat", "free_not_root", "two_joints", "pair",
                                   "moving_pair", "actuator_free", "free_range", "inverted_range", "free_damping",
                                   "negative_damping", "condim", "nan_pos", "inf_size", "negative_spin",
-                                  "generic_rows", "elliptic_condim6"])
+                                  "generic_rows"])
 def test_json_models_validated_like_descriptions(rb, case):
     """The JSON entry point hands the same description to the same validation: every invalid
     model above is rejected with the message the struct entry point gives."""
@@ -149,10 +145,6 @@ def test_json_models_validated_like_descriptions(rb, case):
         # condim 6 on the torso box (8 contacts) and the four feet: 6 x 12 = 72 rows > 64
         for g in m["geoms"]:
             g["condim"] = 6
-    elif case == "elliptic_condim6":
-        # elliptic cones take condim 1, 3 or 4
-        m["geoms"][1]["condim"] = 6
-        m["opt"]["cone"] = "elliptic"
     elif case == "nan_pos":
         m["bodies"][2]["pos"][0] = float("nan")
     elif case == "inf_size":
@@ -193,7 +185,8 @@ def test_malformed_json_rejected(rb, mutate, needle):
 
 @pytest.mark.parametrize("name", ["chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_lim",
                                   "humanoid_lim", "quadruped_terrain", "humanoid_terrain", "chain3_damp",
-                                  "humanoid_damp", "quadruped_slip", "quadruped_elliptic4", "humanoid_elliptic4"])
+                                  "humanoid_damp", "quadruped_slip", "quadruped_elliptic4", "humanoid_elliptic4",
+                                  "quadruped_elliptic6"])
 def test_model_files_match_generators(name):
     """workloads/models/<name>.json holds exactly what the generator builds (float values
     round-trip through JSON unchanged)."""

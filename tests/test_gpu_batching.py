@@ -75,7 +75,8 @@ def test_fused_with_occupancy_cap_equals_separate(occ):
 
 
 ODD_MIX = [("chain3", 47), ("quadruped", 95), ("humanoid", 63), ("arm_box", 41)]
-LEVEL_MIX = [("pincer_cube", 21), ("humanoid_weld", 19), ("quadruped_elliptic", 30), ("quadruped_lim", 33)]
+LEVEL_MIX = [("pincer_cube", 21), ("humanoid_weld", 19), ("quadruped_elliptic", 30), ("quadruped_lim", 33),
+             ("quadruped_elliptic6", 17)]
 
 
 @pytest.mark.parametrize("mix,wpg,order,grid,occ", [

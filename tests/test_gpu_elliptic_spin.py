@@ -1,9 +1,10 @@
-"""Elliptic cones with torsional friction (condim 4) on the HIP path: a spinning ball's step
-against the oracle's from the same settled states (spins from well inside the cone to far on
-its surface), a slow spin's decay over 50 steps against the oracle and the closed form, the
-workloads' returned contact forces inside the cone, and the fused launch equal to the plain one.
-Teacher-forced parity of quadruped_elliptic4 and humanoid_elliptic4 runs with the other
-workloads in the parity tests."""
+"""Elliptic cones with torsional and rolling friction (condim 4 and 6) on the HIP path: a
+spinning ball's step against the oracle's from the same settled states (spins from well inside
+the cone to far on its surface), a spinning and rolling ball's step under condim 6, a slow
+spin's decay over 50 steps against the oracle and the closed form, rolling kept by condim 4 and
+lost by condim 6, the workloads' returned contact forces inside the cone, and the fused launch
+equal to the plain one.  Teacher-forced parity of quadruped_elliptic4, humanoid_elliptic4 and
+quadruped_elliptic6 runs with the other workloads in the parity tests."""
 import math
 
 import numpy as np
@@ -16,12 +17,12 @@ from workloads import inputs, robots
 pytestmark = pytest.mark.gpu
 
 
-def _ball(mus=0.02, impratio=1.0):
+def _ball(mus=0.02, impratio=1.0, condim=4, mur=0.002):
     m = robots.free_body("sphere", size=(0.1,), mass=1.0, pos=(0, 0, 0.1), friction=0.8, timestep=0.002)
     m["opt"]["cone"] = "elliptic"
     m["opt"]["impratio"] = impratio
     for g in m["geoms"]:
-        g.update(condim=4, friction_spin=mus)
+        g.update(condim=condim, friction_spin=mus, friction_roll=mur)
     return m
 
 
@@ -55,6 +56,36 @@ def test_spinning_ball_step_against_oracle(oracle_mod, impratio):
         assert g["qvel"][w, 5] < spins[w]
 
 
+@pytest.mark.parametrize("impratio", [1.0, 4.0])
+def test_spinning_rolling_ball_step_against_oracle(oracle_mod, impratio):
+    """condim 6: 32 balls spinning (0.01 to 20 rad/s about the vertical) and rolling (0.02 to 2 m/s
+    along x, with the matching spin about y): one env step of the HIP path equals the oracle's
+    from the same FP32 state at the step tolerance."""
+    m = _ball(impratio=impratio, condim=6)
+    spins = np.geomspace(0.01, 20.0, 32)
+    o, q, v, ws = _settled(oracle_mod, m, spins)
+    roll = np.geomspace(0.02, 2.0, 32)[::-1]
+    v[:, 0] = roll
+    v[:, 4] = roll / 0.1
+    g = gpu_run(m, q, v, None, ws)
+    r = oracle_run(o, q, v, None, ws)
+    for w in range(len(spins)):
+        assert rel_err(g["qpos"][w], r["qpos"][w]) <= RTOL_STEP, (w, spins[w], roll[w])
+        assert rel_err(g["qvel"][w], r["qvel"][w]) <= RTOL_STEP, (w, spins[w], roll[w])
+
+
+@pytest.mark.parametrize("condim,keeps_roll", [(4, True), (6, False)])
+def test_rolling_kept_or_lost_by_condim(oracle_mod, condim, keeps_roll):
+    """A ball rolling at 0.5 m/s for 4 s on the HIP path keeps its speed to 0.1 % with condim 4 and
+    loses at least 10 % of it with condim 6 (mu_roll 0.002), as the oracle's does."""
+    m = _ball(mus=0.002, condim=condim)
+    o, q, v, ws = _settled(oracle_mod, m, [0.0])
+    v[0, 0], v[0, 4] = 0.5, 5.0
+    g = gpu_run(m, q, v, None, ws, nsteps=2000)
+    vx = float(g["qvel"][0, 0])
+    assert (abs(vx - 0.5) < 5e-4) == keeps_roll and (vx < 0.45) != keeps_roll, vx
+
+
 def test_slow_spin_decay_against_oracle(oracle_mod):
     """A slow spin (0.05 rad/s, inside the cone) over 50 steps: the HIP path's spin follows the
     oracle's to 1e-4 of the initial spin and both follow the closed-form geometric decay of the
@@ -72,7 +103,7 @@ def test_slow_spin_decay_against_oracle(oracle_mod):
     assert abs((w0 - g["qvel"][0, 5]) / lost - 1) < 1e-2
 
 
-@pytest.mark.parametrize("name", ["quadruped_elliptic4", "humanoid_elliptic4"])
+@pytest.mark.parametrize("name", ["quadruped_elliptic4", "humanoid_elliptic4", "quadruped_elliptic6"])
 def test_forces_inside_the_cone(name):
     """After 40 steps every returned contact force lies in its cone (the spin force takes its
     share, so |f_t| <= mu f_n a fortiori), to FP32 rounding, and some lie on the cone's surface
@@ -93,7 +124,7 @@ def test_forces_inside_the_cone(name):
     assert loaded > 0
 
 
-@pytest.mark.parametrize("name", ["quadruped_elliptic4", "humanoid_elliptic4"])
+@pytest.mark.parametrize("name", ["quadruped_elliptic4", "humanoid_elliptic4", "quadruped_elliptic6"])
 def test_fused_equals_plain(name):
     """The fused launch of a condim-4 elliptic model beside a pyramidal one computes the same bits
     as the model's own plain launch."""

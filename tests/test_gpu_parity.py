@@ -110,7 +110,7 @@ def test_single_step_from_initial_states(oracle_mod, name):
                                           ("quadruped_elliptic", 200), ("humanoid_elliptic", 200),
                                           ("cube_stack", 200), ("pincer", 200), ("humanoid_self", 200),
                                           ("pincer_cube", 400), ("quadruped_elliptic4", 200),
-                                          ("humanoid_elliptic4", 200)])
+                                          ("humanoid_elliptic4", 200), ("quadruped_elliptic6", 200)])
 def test_single_step_teacher_forced(oracle_mod, name, horizon):
     """Along the oracle's own trajectory (up to env step 1000 for the quadruped and humanoid
     workloads), hand its state (rounded to FP32) to the GPU every 25 env steps and compare one
@@ -208,7 +208,7 @@ def test_chain3_500_steps(oracle_mod):
                                   "quadruped_slip", "quadruped_hfield", "humanoid_weld", "quadruped_condim6",
                                   "humanoid_condim4", "quadruped_elliptic", "humanoid_elliptic", "cube_stack",
                                   "pincer", "humanoid_self", "pincer_cube", "quadruped_elliptic4",
-                                  "humanoid_elliptic4"])
+                                  "humanoid_elliptic4", "quadruped_elliptic6"])
 def test_contact_sets(oracle_mod, name):
     m, q, v, u, fr, ms = _wl(name, 32)
     o = oracle_mod.Oracle(m)
@@ -346,7 +346,7 @@ def test_sphere_box_contacts_random_poses(oracle_mod):
 
 @pytest.mark.parametrize("name", ["quadruped", "humanoid", "quadruped_lim", "humanoid_lim", "humanoid_weld",
                                   "quadruped_condim6", "humanoid_condim4", "quadruped_elliptic", "humanoid_elliptic",
-                                  "quadruped_elliptic4", "humanoid_elliptic4"])
+                                  "quadruped_elliptic4", "humanoid_elliptic4", "quadruped_elliptic6"])
 def test_newton_iterations_match_oracle(oracle_mod, name):
     """The GPU ends Newton when no row changed sides since the last Hessian; the oracle ends
     it by its FP64 gradient test.  On the same states both take the same number of
@@ -432,7 +432,7 @@ def test_run_twice_bitwise(oracle_mod):
                                   "humanoid_terrain", "humanoid_damp", "quadruped_hfield", "chain3_loop",
                                   "humanoid_weld", "quadruped_condim6", "humanoid_condim4", "quadruped_elliptic",
                                   "humanoid_elliptic", "cube_stack", "pincer", "humanoid_self",
-                                  "pincer_cube", "quadruped_elliptic4", "humanoid_elliptic4"])
+                                  "pincer_cube", "quadruped_elliptic4", "humanoid_elliptic4", "quadruped_elliptic6"])
 def test_json_model_bitwise(name):
     """A model created from its JSON file (rb_model_create_json) steps exactly like the same
     model created from the description struct."""

@@ -20,7 +20,8 @@ WORKLOAD_IDS = {"chain3": 1, "quadruped": 2, "humanoid": 3, "arm_box": 4,
                 "quadruped_slip": 13, "quadruped_hfield": 14, "chain3_loop": 15, "humanoid_weld": 16,
                 "quadruped_condim6": 17, "humanoid_condim4": 18, "quadruped_elliptic": 19,
                 "humanoid_elliptic": 20, "cube_stack": 21, "pincer": 22,
-                "humanoid_self": 23, "pincer_cube": 24, "quadruped_elliptic4": 25, "humanoid_elliptic4": 26}
+                "humanoid_self": 23, "pincer_cube": 24, "quadruped_elliptic4": 25, "humanoid_elliptic4": 26,
+                "quadruped_elliptic6": 27}
 CTRL_PERIOD = 20          # env steps between control resamples
 CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3,
             "chain3_lim": 0.0, "quadruped_lim": 0.3, "humanoid_lim": 0.2, "quadruped_terrain": 0.3,
@@ -28,7 +29,8 @@ CTRL_STD = {"chain3": 0.0, "quadruped": 0.3, "humanoid": 0.2, "arm_box": 0.3,
             "quadruped_slip": 0.3, "quadruped_hfield": 0.3, "chain3_loop": 0.0, "humanoid_weld": 0.2,
             "quadruped_condim6": 0.3, "humanoid_condim4": 0.2, "quadruped_elliptic": 0.3,
             "humanoid_elliptic": 0.2, "cube_stack": 0.0, "pincer": 0.1,
-            "humanoid_self": 0.2, "pincer_cube": 0.1, "quadruped_elliptic4": 0.3, "humanoid_elliptic4": 0.2}
+            "humanoid_self": 0.2, "pincer_cube": 0.1, "quadruped_elliptic4": 0.3, "humanoid_elliptic4": 0.2,
+            "quadruped_elliptic6": 0.3}
 # mean control target per actuator where it is not 0: the pincer's fingers close past each other
 CTRL_MEAN = {"pincer": [0.0, -0.4, 0.4], "pincer_cube": [0.0, -0.2, 0.2],
              # the humanoid's hips adducted (left roll -, right roll +) so that its legs meet
@@ -70,7 +72,7 @@ def initial_state(model: dict, name: str, worlds, workload_id: int | None = None
             qpos[i, :] = g.uniform(-0.5, 0.5, d["nq"])
             qvel[i, :] = g.normal(0.0, 2.0, d["nv"])
         elif name in ("quadruped_lim", "quadruped_terrain", "quadruped_slip", "quadruped_hfield", "quadruped_condim6",
-                      "quadruped_elliptic", "quadruped_elliptic4"):
+                      "quadruped_elliptic", "quadruped_elliptic4", "quadruped_elliptic6"):
             qpos[i, hq] = g.uniform(-0.1, 0.1, len(hq))
         elif name == "pincer":
             # palm angle U[+-0.2], fingers open U[0, 0.3] / U[-0.3, 0] (tips apart), at rest

@@ -16,7 +16,7 @@ NAMES = ("chain3", "quadruped", "humanoid", "arm_box", "chain3_lim", "quadruped_
          "quadruped_terrain", "humanoid_terrain", "chain3_damp", "humanoid_damp", "quadruped_slip", "quadruped_hfield",
          "chain3_loop", "humanoid_weld", "quadruped_condim6", "humanoid_condim4",
          "quadruped_elliptic", "humanoid_elliptic", "cube_stack", "pincer", "humanoid_self", "pincer_cube",
-         "quadruped_elliptic4", "humanoid_elliptic4")
+         "quadruped_elliptic4", "humanoid_elliptic4", "quadruped_elliptic6")
 
 
 def main():

@@ -607,6 +607,17 @@ def quadruped_elliptic4() -> dict:
     return m
 
 
+def quadruped_elliptic6() -> dict:
+    """quadruped with elliptic friction cones (impratio 1) whose sphere feet have torsional and
+    rolling friction (condim 6: mu_spin 0.02, mu_roll 0.002): six rows per foot contact in one
+    cone."""
+    m = with_elliptic(quadruped(), 1.0, "quadruped_elliptic6")
+    for g in m["geoms"]:
+        if g["type"] == "sphere":
+            g.update(condim=6, friction_spin=0.02, friction_roll=0.002)
+    return m
+
+
 def humanoid_elliptic4() -> dict:
     """humanoid with elliptic friction cones (impratio 1) whose four foot boxes have torsional
     friction (condim 4, mu_spin 0.02), with up to 8 Newton updates per substep: a spin row in
@@ -701,6 +712,7 @@ BENCH_MODELS = {"chain3": chain3, "quadruped": quadruped, "humanoid": humanoid, 
                 "quadruped_condim6": quadruped_condim6, "humanoid_condim4": humanoid_condim4,
                 "quadruped_elliptic": quadruped_elliptic, "humanoid_elliptic": humanoid_elliptic,
                 "quadruped_elliptic4": quadruped_elliptic4, "humanoid_elliptic4": humanoid_elliptic4,
+                "quadruped_elliptic6": quadruped_elliptic6,
                 "cube_stack": cube_stack, "pincer": pincer, "humanoid_self": humanoid_self,
                 "pincer_cube": pincer_cube}
 
