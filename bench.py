@@ -781,6 +781,8 @@ def main():
         "work_per_substep": {"contacts": stats_mean[0], "active_rows": stats_mean[1],
                              "newton_iters": stats_mean[2], "line_search_segments": stats_mean[3]},
         "stage_cycle_share": stage_share,
+        "stage_cycle_share_source": "the diagnostic instantiation's shader-clock taps (compiled for 3 resident "
+                                    "waves per SIMD, not the timed kernel) on the stats sample of worlds",
         "nonfinite_worlds": int(np.sum(st & 1)),
         "wall_s": wall,
         "kernel_source_hash": kernel_source_hash(),
