@@ -241,3 +241,12 @@ def test_contacts_capacity_checked():
         c._struct(4, 16)
     with pytest.raises(ValueError):
         c._struct(5, 8)
+
+
+def test_c_caller_builds(tmp_path):
+    """include/rbstep.h is a C99 header: a C caller (tests/c_abi_step.c) compiles with -Wall
+    -Wextra -Werror and links against the library and the HIP runtime (it runs in the GPU
+    tests)."""
+    from c_abi_build import build_c_caller
+    exe = build_c_caller(str(tmp_path / "c_abi_step"))
+    assert os.path.exists(exe)

@@ -130,7 +130,10 @@ def test_fused_equals_separate_long_rollout():
         np.testing.assert_array_equal(s["v"].cpu().numpy(), v)
 
 
-def test_graph_replay_equals_eager():
+@pytest.mark.parametrize("wpg", [1, 2])
+def test_graph_replay_equals_eager(wpg):
+    """Three replays of a captured control period (2 fused steps each, with eager work between
+    them), one or two worlds per workgroup: every world ends where 6 plain steps put it."""
     import torch
     import paper_2601_22074_amd as rb
     ref = _run_separate(rb, torch, 6)
@@ -139,6 +142,7 @@ def test_graph_replay_equals_eager():
     for i, s in enumerate(S):
         plan.bind(i, s["u"], s["q"], s["v"])
     plan.set_schedule(1, 0)
+    plan.set_group(wpg)
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
     plan.graph_capture(2, side)
