@@ -2622,8 +2622,9 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
 // One world per 64-lane workgroup.  EXT: the level of extended code -- 1 for box-box,
 // sphere-box, capsule-box and height-field pairs, more than 64 pairs, joint limits, damping and
 // frictionless contacts; 2 adds equality constraints, torsional / rolling friction and elliptic
-// cones (each level kept out of the lower instantiations so their register allocation is not
-// shaped by it).
+// cones up to condim 4; 3 is level 2 with contacts between two moving bodies, 4 level 2 with
+// elliptic cones up to condim 6 (each level kept out of the other instantiations so their
+// register allocation is not shaped by it).
 template <int MAXD, bool TIMED, int EXT>
 __global__ __launch_bounds__(RB_WAVE) __attribute__((amdgpu_waves_per_eu(RB_WAVES_PER_EU, 8))) void step_kernel(
     DevModel m, StepArgs A) {
