@@ -653,16 +653,21 @@ def main():
     if args.summarize:
         wl = args.workload
         nwd = args.worlds or DEFAULT_WORLDS[wl]
-        cmds = {"trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace -- "
+        # the commands that wrote the three databases, each into the directory it was read from
+        def out_dir(db):
+            d = os.path.dirname(os.path.abspath(db))
+            return os.path.relpath(d, os.getcwd()) if d.startswith(os.getcwd()) else d
+        tdb, fdb, wdb = args.summarize
+        cmds = {"trace": f"rocprofv3 --kernel-trace --stats -d {out_dir(tdb)} -o trace -- "
                          "python bench.py --steps 50 --warmup 5 --no-cpu --stats-worlds 64",
-                "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch -- "
+                "fetch": f"rocprofv3 --pmc FETCH_SIZE -d {out_dir(fdb)} -o fetch -- "
                          "python bench.py --steps 10 --warmup 2 --no-cpu --stats-worlds 16 --copy-calib-mb 256",
-                "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write -- "
+                "write": f"rocprofv3 --pmc WRITE_SIZE -d {out_dir(wdb)} -o write -- "
                          "python bench.py --steps 10 --warmup 2 --no-cpu --stats-worlds 16 --copy-calib-mb 256"}
         summarize_profiles(*args.summarize, wl, nwd, args.copy_calib_mb or 256, cmds)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: worlds are independent and this build runs on a single MI355X; "
+        print("bench.py measures one GPU: worlds are independent and the step runs on a single MI355X; "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
