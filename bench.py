@@ -89,12 +89,12 @@ WORKLOAD_TEXT["serve"] = ("serving: Poisson arrivals of rollout requests, model 
 
 
 # ------------------------------------------------------------------ mixed-model batching
-def run_mix(args):
+def run_mix(args, emit=True):
     """The batching form on the mixed batch: one env step of every world per call, timed for
     (a) separate plain launches back to back on one stream, (b) the same on one stream per
     model, (c) the fused launch under the autotuned schedule and (d) that launch replayed from
     a captured hipGraph of one control period.  Every form starts from the same state; its
-    final state is compared bit for bit with (a)."""
+    final state is compared bit for bit with (a).  Returns the result (printed when emit)."""
     import torch
     import paper_2601_22074_amd as rb
     from paper_2601_22074_amd import autotune
@@ -242,7 +242,9 @@ def run_mix(args):
         "bitwise_equal_to_separate": equal,
         "autotune_timings_ms": timings,
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 # ------------------------------------------------------------------ serving
@@ -624,6 +626,8 @@ def main():
     ap.add_argument("--waves", type=int, default=0, choices=(0, 3, 4),
                     help="resident waves per SIMD of the plain launch (0: automatic)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-mix", action="store_true",
+                    help="humanoid: skip the mixed-batch batching figures reported beside the headline")
     ap.add_argument("--stats-worlds", type=int, default=512)
     ap.add_argument("--flop-worlds", type=int, default=64,
                     help="worlds of the oracle run whose operation counts give the roofline numerator")
@@ -659,11 +663,11 @@ def main():
             return os.path.relpath(d, os.getcwd()) if d.startswith(os.getcwd()) else d
         tdb, fdb, wdb = args.summarize
         cmds = {"trace": f"rocprofv3 --kernel-trace --stats -d {out_dir(tdb)} -o trace -- "
-                         "python bench.py --steps 50 --warmup 5 --no-cpu --stats-worlds 64",
+                         "python bench.py --steps 50 --warmup 5 --no-cpu --no-mix --stats-worlds 64",
                 "fetch": f"rocprofv3 --pmc FETCH_SIZE -d {out_dir(fdb)} -o fetch -- "
-                         "python bench.py --steps 10 --warmup 2 --no-cpu --stats-worlds 16 --copy-calib-mb 256",
+                         "python bench.py --steps 10 --warmup 2 --no-cpu --no-mix --stats-worlds 16 --copy-calib-mb 256",
                 "write": f"rocprofv3 --pmc WRITE_SIZE -d {out_dir(wdb)} -o write -- "
-                         "python bench.py --steps 10 --warmup 2 --no-cpu --stats-worlds 16 --copy-calib-mb 256"}
+                         "python bench.py --steps 10 --warmup 2 --no-cpu --no-mix --stats-worlds 16 --copy-calib-mb 256"}
         summarize_profiles(*args.summarize, wl, nwd, args.copy_calib_mb or 256, cmds)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -797,6 +801,18 @@ def main():
                                    "the launch is latency-bound and its roofline fraction is not meaningful")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W)
+    if args.workload == "humanoid" and not args.no_mix:
+        # the batching form beside the headline figure, after its timed region: the mixed batch
+        # at its counts, fused launch against the separate plain launches (200 env steps)
+        margs = argparse.Namespace(**vars(args))
+        margs.steps, margs.warmup = 200, 20
+        mx = run_mix(margs, emit=False)
+        out["batching"] = {"workload": mx["config"]["workload"], "worlds": mx["config"]["worlds"],
+                           "env_steps": mx["steps"], "form": mx["config"]["form"],
+                           "schedule": mx["config"]["schedule"],
+                           "env_steps_per_s": mx["forms_env_steps_per_s"],
+                           "speedup_vs_separate": mx["speedup_vs_separate"],
+                           "bitwise_equal_to_separate": mx["bitwise_equal_to_separate"]}
     print(json.dumps(out), flush=True)
 
 
