@@ -2065,6 +2065,10 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                         if (EXT == 3) sg *= cf;
                         float jn = sg * dot(n, vp), j1 = sg * dot(t1, vp), j2 = sg * dot(t2, vp);
                         float je[4] = {jn + mu * j1, jn - mu * j1, jn + mu * j2, jn - mu * j2};
+                        // active row e's direction is n +- mu t_k; their weighted sum is kept as
+                        // the coefficients of n, t1 and t2 and turned into one spatial force at O,
+                        // sg (r x a, a), after the rows
+                        float wn = 0.f, w1 = 0.f, w2 = 0.f;
 #pragma unroll
                         for (int e = 0; e < 4; e++) {
                             if (EXT == 3 && b1c > 0) {
@@ -2073,17 +2077,18 @@ DEV void world_step(const DevModel& m, const StepArgs& A, const int w, float* ld
                             }
                             if (jar[e] < 0.f) {
                                 gc += D[e] * jar[e] * je[e];
-                                // row direction as a spatial force at O: sg * (r x a, a)
-                                float a[3];
-                                const float* tk = e < 2 ? t1 : t2;
-                                float sm = (e & 1) ? -mu : mu;
-                                a[0] = n[0] + sm * tk[0]; a[1] = n[1] + sm * tk[1]; a[2] = n[2] + sm * tk[2];
-                                float ra[3];
-                                cross(r, a, ra);
-                                float wgt = D[e] * je[e] * sg;
-                                F[0] += wgt * ra[0]; F[1] += wgt * ra[1]; F[2] += wgt * ra[2];
-                                F[3] += wgt * a[0]; F[4] += wgt * a[1]; F[5] += wgt * a[2];
+                                const float wgt = D[e] * je[e] * sg;
+                                const float mw = (e & 1) ? -mu * wgt : mu * wgt;
+                                wn += wgt;
+                                if (e < 2) w1 += mw; else w2 += mw;
                             }
+                        }
+                        if (!(EXT == 3 && b1c > 0)) {
+                            float a[3], ra[3];
+                            for (int k = 0; k < 3; k++) a[k] = wn * n[k] + w1 * t1[k] + w2 * t2[k];
+                            cross(r, a, ra);
+                            F[0] += ra[0]; F[1] += ra[1]; F[2] += ra[2];
+                            F[3] += a[0]; F[4] += a[1]; F[5] += a[2];
                         }
                     }
                 }
