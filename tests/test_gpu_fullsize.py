@@ -9,7 +9,8 @@ from workloads import inputs
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name,n,start", [("humanoid", 8192, 0), ("humanoid", 8192, 20), ("quadruped", 4096, 20)])
+@pytest.mark.parametrize("name,n,start", [("humanoid", 8192, 0), ("humanoid", 8192, 20), ("quadruped", 4096, 20),
+                                          ("humanoid_elliptic4", 8192, 20)])
 def test_full_size_sampled_worlds(oracle_mod, name, n, start):
     W = inputs.workload(name, n, start + 1)
     m = W["model"]
@@ -38,7 +39,9 @@ def test_full_size_sampled_worlds(oracle_mod, name, n, start):
     sub = lambda a: None if a is None else a[idx]
     r = oracle_step_records(o, q[idx], v[idx], u[idx], ws[idx], sub(fr), sub(ms))
     band = band_worlds(oracle_mod, m, q[idx], v[idx], u[idx], ws[idx], sub(fr), sub(ms))
-    T = StepTally(f"{name} x{n} from step {start}")
+    ell = m["opt"].get("cone") == "elliptic"   # elliptic cones: the smooth-cost rules of the tally
+    T = StepTally(f"{name} x{n} from step {start}", smooth=ell,
+                  force_scale=max(1.0, m["opt"].get("impratio", 1.0)) if ell else 1.0)
     for j, w in enumerate(idx):
         T.add(g, r, w, j, band[j], (name, n, start, int(w)),
               floor=lambda j=j: fp32_floor(o, m, q[idx], v[idx], u[idx], ws[idx], sub(fr), sub(ms), j))
