@@ -134,9 +134,12 @@ def tune(multi: "rbstep.Multi", inputs, reps: int = 3, resident: int = 2048, use
         choice = tuple(None if x == "None" else (x if i == 0 else int(x)) for i, x in enumerate(best.split("/")))
         cache[sig] = {"choice": list(choice), "timings_ms": timings}
         if use_cache:
-            os.makedirs(os.path.dirname(CACHE), exist_ok=True)
-            with open(CACHE, "w") as f:
-                json.dump(cache, f, indent=1)
+            try:
+                os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+                with open(CACHE, "w") as f:
+                    json.dump(cache, f, indent=1)
+            except OSError:
+                pass   # an unwritable cache only means the next run tunes again
     # restore the warm starts and bind the real inputs
     for b, n, ws in zip(batches, ns, saved_ws):
         b.reset(torch.arange(n, dtype=torch.int32, device="cuda"), ws)
